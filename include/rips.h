@@ -1,0 +1,168 @@
+/*
+ * rips.h -- C ABI of the MI355X (gfx950) Vietoris-Rips persistence library.
+ *
+ * The library computes persistence barcodes of the lexicographically refined
+ * Vietoris-Rips filtration of a finite metric space over the prime field Z/p,
+ * following U. Bauer, "Ripser: efficient computation of Vietoris-Rips
+ * persistence barcodes" (arXiv:1908.02518):
+ *   - simplices are indexed in the combinatorial number system (section
+ *     "Indexing simplices in the combinatorial number system");
+ *   - the filtration is refined by diameter, then dimension, then reverse
+ *     colexicographic order (section "Lexicographic refinement");
+ *   - persistence is computed as relative cohomology with clearing, in
+ *     increasing dimension (Algorithm 2 applied to coboundary matrices,
+ *     section "Persistent cohomology"), with implicit coboundary columns
+ *     (section "Implicit matrix reduction"), columns in zero-persistence
+ *     apparent pairs skipped (section "Apparent pairs", Proposition on zero
+ *     apparent pairs; "Assembling column indices") and the emergent-pair
+ *     shortcut (Proposition on emergent pairs);
+ *   - with no threshold the enclosing radius min_x max_y d(x, y) is used
+ *     ("Input" paragraph); a finite threshold is also clamped to it, which
+ *     changes no bar of nonzero persistence.
+ * Every step runs in hand-written HIP kernels on the GPU; there is no CPU
+ * fallback. All entry points return a rips_status; no exception crosses the
+ * ABI. Error details for the calling thread: rips_last_error().
+ *
+ * Conventions shared by all entry points
+ *   - Distances are float32, d(i, j) = sqrt(sum_c (x_ic - x_jc)^2) with the
+ *     sum taken over c in increasing order, each product and sum rounded to
+ *     float32 (no fused multiply-add) and a correctly rounded square root.
+ *   - A simplex is reported by its CNS index within its dimension; a vertex
+ *     v has index v. For a bar of dimension d the birth simplex is a
+ *     d-simplex, the death simplex a (d+1)-simplex (-1 for an infinite bar).
+ *   - Bars of zero persistence (death == birth in float32) are not reported.
+ *   - Within a dimension bars are ordered by the refined order of their birth
+ *     simplex: birth ascending, then birth simplex index descending.
+ *   - H0 birth simplices follow the elder rule of the reduction: when two
+ *     components merge, the one whose oldest vertex (largest index) is
+ *     younger dies.
+ *   - Limits: 1 <= n <= RIPS_MAX_POINTS, 0 <= max_dim <= RIPS_MAX_DIM,
+ *     2 <= p < 65536 prime, and C(n, max_dim + 2) < 2^63 (simplex indices are
+ *     64-bit, "Vertices and simplices" paragraph).
+ */
+#ifndef RIPS_H
+#define RIPS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RIPS_MAX_DIM 3
+#define RIPS_MAX_POINTS 65535
+
+typedef enum {
+    RIPS_OK = 0,
+    RIPS_E_INVALID_ARG = -1,    /* bad size, dimension, pointer or layout */
+    RIPS_E_NOT_PRIME = -2,      /* p is not a prime in [2, 65536) */
+    RIPS_E_INDEX_OVERFLOW = -3, /* C(n, max_dim + 2) does not fit in int64 */
+    RIPS_E_NONFINITE = -4,      /* NaN/Inf coordinate or distance, or a negative distance */
+    RIPS_E_OOM = -5,            /* device or host allocation failed */
+    RIPS_E_CAPACITY = -6,       /* a caller-provided output buffer is too small; see `needed` */
+    RIPS_E_HIP = -7             /* a HIP runtime call failed */
+} rips_status;
+
+/* Bars of one dimension (host memory owned by the rips_result). */
+typedef struct {
+    int64_t count;
+    float *birth;
+    float *death;           /* +INFINITY for an essential class */
+    int64_t *birth_simplex; /* CNS index of a d-simplex */
+    int64_t *death_simplex; /* CNS index of a (d+1)-simplex, -1 if essential */
+} rips_bars;
+
+/* Per-dimension counters (Table "counts of pairs" of the paper is of this kind). */
+typedef struct {
+    int64_t candidates;     /* d-simplices of diameter <= threshold */
+    int64_t cleared;        /* candidates that were pivots in dimension d-1 (clearing) */
+    int64_t apparent_col;   /* candidates sigma in a zero apparent pair (sigma, tau) */
+    int64_t apparent_pivot; /* candidates sigma in a zero apparent pair (rho, sigma), d >= 2 */
+    int64_t columns;        /* columns left for the reduction */
+    int64_t emergent;       /* columns resolved by the emergent shortcut */
+    int64_t reduced;        /* columns that needed at least one column addition */
+    int64_t additions;      /* column additions in total */
+    int64_t bars_nonzero;   /* finite bars of nonzero persistence */
+    int64_t essential;      /* infinite bars */
+} rips_dim_stats;
+
+typedef struct {
+    int32_t n;
+    int32_t max_dim;
+    uint32_t p;
+    int32_t sparse;          /* 1 if neighbour lists were used for cofacets */
+    float threshold_used;    /* min(threshold, enclosing radius) */
+    float enclosing_radius;
+    rips_bars *dims;         /* max_dim + 1 entries */
+    rips_dim_stats *stats;   /* max_dim + 1 entries */
+    int64_t *simplex_count;  /* max_dim + 1 entries: |K_d| at threshold_used */
+    /* columns left for the reduction in each dimension, in reduction order
+       (diameter descending, then CNS index ascending) */
+    int64_t *column_count;   /* max_dim + 1 entries */
+    int64_t **column_index;  /* max_dim + 1 arrays */
+    float **column_diam;     /* max_dim + 1 arrays */
+} rips_result;
+
+/*
+ * rips_barcode -- barcode of one point cloud or distance matrix (host memory).
+ *   data      dim > 0: n x dim float32 points, row-major;
+ *             dim == 0: n x n float32 distance matrix, row-major; only the
+ *             entries (i, j) with i > j are read.
+ *   threshold +INFINITY for none; simplices with diameter <= threshold.
+ *   p         prime coefficient field Z/p, 2 <= p < 65536.
+ *   out       receives a library-allocated result (free with
+ *             rips_result_free); *out = NULL on error.
+ * Inputs are copied; no caller pointer is kept. Runs on the current HIP device.
+ */
+rips_status rips_barcode(const float *data, int64_t n, int32_t dim, int32_t max_dim,
+                         float threshold, uint32_t p, rips_result **out);
+
+void rips_result_free(rips_result *r);
+const char *rips_status_string(rips_status s);
+const char *rips_last_error(void);
+
+/*
+ * rips_barcode_device -- one cloud, device-resident input and output.
+ * Same computation and arguments as rips_barcode, but `d_data` is device
+ * memory and the bars are written to caller-owned device buffers:
+ *   birth/death/birth_simplex/death_simplex hold (max_dim + 1) * cap entries;
+ *   dimension d uses entries [d * cap, d * cap + count[d]).
+ * Host-side results: count[d], stats[d], simplex_count[d], threshold_used.
+ * On RIPS_E_CAPACITY nothing is written to the bar buffers and needed_cap
+ * holds the capacity that suffices. All work is queued on `hip_stream`
+ * (a hipStream_t, NULL = default stream); the call returns after the stream
+ * has finished. Scratch memory is owned by a per-device context that grows
+ * on demand and is reused by later calls.
+ */
+typedef struct {
+    int64_t cap;
+    float *birth;
+    float *death;
+    int64_t *birth_simplex;
+    int64_t *death_simplex;
+    int64_t count[RIPS_MAX_DIM + 1];
+    rips_dim_stats stats[RIPS_MAX_DIM + 1];
+    int64_t simplex_count[RIPS_MAX_DIM + 1];
+    float threshold_used;
+    int32_t sparse;
+    int64_t needed_cap;
+} rips_device_out;
+
+rips_status rips_barcode_device(const float *d_data, int64_t n, int32_t dim, int32_t max_dim,
+                                float threshold, uint32_t p, rips_device_out *out,
+                                void *hip_stream);
+
+/*
+ * rips_simplex_counts_device -- |K_d| for d = 0 .. top (top <= RIPS_MAX_DIM + 1)
+ * at threshold min(threshold, enclosing radius), counted on the GPU without
+ * storing the top dimension. Used for throughput accounting
+ * (simplices of the explicit filtration). counts: host array of top + 1.
+ */
+rips_status rips_simplex_counts_device(const float *d_data, int64_t n, int32_t dim, int32_t top,
+                                       float threshold, int64_t *counts, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIPS_H */

@@ -1,0 +1,288 @@
+"""MI355X (gfx950) Vietoris-Rips persistence barcodes -- Python binding.
+
+A thin ctypes binding of the C ABI declared in include/rips.h (librips.so,
+built in-tree by ``paper_1908_02518_amd.build``). It only marshals
+arguments: every step of the method runs in the library's HIP kernels. If
+the library is missing this module raises at import; there is no other
+implementation behind it.
+
+Functions take and return torch tensors (device-resident inputs) or numpy
+arrays (host inputs):
+
+* ``barcode(points, ...)``        host arrays in, host results out (C ABI rips_barcode)
+* ``barcode_device(x, ...)``      torch.cuda tensor in, torch.cuda bars out
+* ``simplex_counts(x, top, ...)`` |K_d| for d <= top on the GPU
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librips.so")
+
+RIPS_MAX_DIM = 3
+RIPS_MAX_POINTS = 65535
+
+STATUS = {
+    0: "RIPS_OK",
+    -1: "RIPS_E_INVALID_ARG",
+    -2: "RIPS_E_NOT_PRIME",
+    -3: "RIPS_E_INDEX_OVERFLOW",
+    -4: "RIPS_E_NONFINITE",
+    -5: "RIPS_E_OOM",
+    -6: "RIPS_E_CAPACITY",
+    -7: "RIPS_E_HIP",
+}
+
+# exported symbols, in include/rips.h order
+EXPORTS = (
+    "rips_barcode",
+    "rips_result_free",
+    "rips_status_string",
+    "rips_last_error",
+    "rips_barcode_device",
+    "rips_simplex_counts_device",
+)
+
+
+class RipsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class rips_bars(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64),
+                ("birth", ctypes.POINTER(ctypes.c_float)),
+                ("death", ctypes.POINTER(ctypes.c_float)),
+                ("birth_simplex", ctypes.POINTER(ctypes.c_int64)),
+                ("death_simplex", ctypes.POINTER(ctypes.c_int64))]
+
+
+STAT_FIELDS = ("candidates", "cleared", "apparent_col", "apparent_pivot", "columns", "emergent",
+               "reduced", "additions", "bars_nonzero", "essential")
+
+
+class rips_dim_stats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in STAT_FIELDS]
+
+
+class rips_result(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32),
+                ("max_dim", ctypes.c_int32),
+                ("p", ctypes.c_uint32),
+                ("sparse", ctypes.c_int32),
+                ("threshold_used", ctypes.c_float),
+                ("enclosing_radius", ctypes.c_float),
+                ("dims", ctypes.POINTER(rips_bars)),
+                ("stats", ctypes.POINTER(rips_dim_stats)),
+                ("simplex_count", ctypes.POINTER(ctypes.c_int64)),
+                ("column_count", ctypes.POINTER(ctypes.c_int64)),
+                ("column_index", ctypes.POINTER(ctypes.POINTER(ctypes.c_int64))),
+                ("column_diam", ctypes.POINTER(ctypes.POINTER(ctypes.c_float)))]
+
+
+_D1 = RIPS_MAX_DIM + 1
+
+
+class rips_device_out(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int64),
+                ("birth", ctypes.c_void_p),
+                ("death", ctypes.c_void_p),
+                ("birth_simplex", ctypes.c_void_p),
+                ("death_simplex", ctypes.c_void_p),
+                ("count", ctypes.c_int64 * _D1),
+                ("stats", rips_dim_stats * _D1),
+                ("simplex_count", ctypes.c_int64 * _D1),
+                ("threshold_used", ctypes.c_float),
+                ("sparse", ctypes.c_int32),
+                ("needed_cap", ctypes.c_int64)]
+
+
+def _load():
+    # One HIP runtime per process: torch ships its own libamdhip64 (SONAME
+    # libamdhip64.so.7) and resolves it through its RPATH. Importing torch
+    # first lets librips.so bind to that same, already loaded runtime instead
+    # of a second copy from /opt/rocm, which would make torch see no GPU.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1908_02518_amd.build` "
+            "(hipcc, gfx950). There is no fallback implementation.")
+    lib = ctypes.CDLL(LIB_PATH)
+    f32p = ctypes.POINTER(ctypes.c_float)
+    lib.rips_barcode.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_float, ctypes.c_uint32,
+                                 ctypes.POINTER(ctypes.POINTER(rips_result))]
+    lib.rips_barcode.restype = ctypes.c_int
+    lib.rips_result_free.argtypes = [ctypes.POINTER(rips_result)]
+    lib.rips_result_free.restype = None
+    lib.rips_status_string.argtypes = [ctypes.c_int]
+    lib.rips_status_string.restype = ctypes.c_char_p
+    lib.rips_last_error.argtypes = []
+    lib.rips_last_error.restype = ctypes.c_char_p
+    lib.rips_barcode_device.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_float, ctypes.c_uint32,
+                                        ctypes.POINTER(rips_device_out), ctypes.c_void_p]
+    lib.rips_barcode_device.restype = ctypes.c_int
+    lib.rips_simplex_counts_device.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.c_float,
+                                               ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
+    lib.rips_simplex_counts_device.restype = ctypes.c_int
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def _check(status: int):
+    if status != 0:
+        raise RipsError(status, _lib.rips_last_error().decode())
+
+
+@dataclass
+class Bars:
+    birth: np.ndarray
+    death: np.ndarray
+    birth_simplex: np.ndarray
+    death_simplex: np.ndarray
+
+    def __len__(self):
+        return int(self.birth.shape[0])
+
+
+@dataclass
+class Result:
+    n: int
+    max_dim: int
+    p: int
+    sparse: bool
+    threshold: float
+    enclosing_radius: float
+    bars: list
+    stats: list
+    simplex_count: list
+    columns: list = field(default_factory=list)
+
+
+def _stats_dict(s) -> dict:
+    return {f: int(getattr(s, f)) for f in STAT_FIELDS}
+
+
+def barcode(points: np.ndarray | None = None, *, dist: np.ndarray | None = None,
+            max_dim: int = 1, threshold: float = float("inf"), p: int = 2) -> Result:
+    """Barcode of a host point cloud (float32 (n, m)) or full distance matrix
+    (float32 (n, n), entries i > j read) via the C ABI rips_barcode."""
+    if (points is None) == (dist is None):
+        raise ValueError("give exactly one of points, dist")
+    if points is not None:
+        x = np.ascontiguousarray(points, dtype=np.float32)
+        if x.ndim != 2:
+            raise ValueError("points must be (n, m)")
+        n, m = x.shape
+    else:
+        x = np.ascontiguousarray(dist, dtype=np.float32)
+        if x.ndim != 2 or x.shape[0] != x.shape[1]:
+            raise ValueError("dist must be (n, n)")
+        n, m = x.shape[0], 0
+    out = ctypes.POINTER(rips_result)()
+    _check(_lib.rips_barcode(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, m, max_dim,
+                             ctypes.c_float(threshold), p, ctypes.byref(out)))
+    try:
+        r = out.contents
+        bars, stats, counts, cols = [], [], [], []
+        for d in range(r.max_dim + 1):
+            b = r.dims[d]
+            c = int(b.count)
+
+            def arr(ptr, dt):
+                return np.ctypeslib.as_array(ptr, shape=(c,)).astype(dt, copy=True) if c else \
+                    np.empty(0, dt)
+            bars.append(Bars(arr(b.birth, np.float32), arr(b.death, np.float32),
+                             arr(b.birth_simplex, np.int64), arr(b.death_simplex, np.int64)))
+            stats.append(_stats_dict(r.stats[d]))
+            counts.append(int(r.simplex_count[d]))
+            nc = int(r.column_count[d])
+            if nc:
+                ci = np.ctypeslib.as_array(r.column_index[d], shape=(nc,)).copy()
+                cd = np.ctypeslib.as_array(r.column_diam[d], shape=(nc,)).copy()
+            else:
+                ci, cd = np.empty(0, np.int64), np.empty(0, np.float32)
+            cols.append((ci, cd))
+        return Result(n=int(r.n), max_dim=int(r.max_dim), p=int(r.p), sparse=bool(r.sparse),
+                      threshold=float(r.threshold_used),
+                      enclosing_radius=float(r.enclosing_radius), bars=bars, stats=stats,
+                      simplex_count=counts, columns=cols)
+    finally:
+        _lib.rips_result_free(out)
+
+
+def _stream_ptr(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def barcode_device(x, *, max_dim: int = 1, threshold: float = float("inf"), p: int = 2,
+                   is_distance: bool = False, cap: int | None = None):
+    """Barcode of a device-resident float32 tensor (points (n, m), or a full
+    (n, n) distance matrix with is_distance=True). Returns (bars, info):
+    bars[d] = (birth, death, birth_simplex, death_simplex) torch.cuda tensors;
+    info holds stats, simplex counts and the threshold used."""
+    import torch
+    if not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 2:
+        raise ValueError("x must be a contiguous float32 CUDA tensor of rank 2")
+    n = x.shape[0]
+    m = 0 if is_distance else x.shape[1]
+    dev = x.device
+    cap = cap if cap is not None else max(64, n)
+    while True:
+        birth = torch.empty((max_dim + 1) * cap, dtype=torch.float32, device=dev)
+        death = torch.empty_like(birth)
+        bs = torch.empty((max_dim + 1) * cap, dtype=torch.int64, device=dev)
+        ds = torch.empty_like(bs)
+        o = rips_device_out()
+        o.cap = cap
+        o.birth, o.death = birth.data_ptr(), death.data_ptr()
+        o.birth_simplex, o.death_simplex = bs.data_ptr(), ds.data_ptr()
+        st = _lib.rips_barcode_device(ctypes.c_void_p(x.data_ptr()), n, m, max_dim,
+                                      ctypes.c_float(threshold), p, ctypes.byref(o),
+                                      _stream_ptr(torch, dev))
+        if st == -6 and o.needed_cap > cap:
+            cap = int(o.needed_cap)
+            continue
+        _check(st)
+        break
+    bars = []
+    for d in range(max_dim + 1):
+        c = int(o.count[d])
+        sl = slice(d * cap, d * cap + c)
+        bars.append((birth[sl], death[sl], bs[sl], ds[sl]))
+    info = dict(stats=[_stats_dict(o.stats[d]) for d in range(max_dim + 1)],
+                simplex_count=[int(o.simplex_count[d]) for d in range(max_dim + 1)],
+                threshold=float(o.threshold_used), sparse=bool(o.sparse))
+    return bars, info
+
+
+def simplex_counts(x, top: int, *, threshold: float = float("inf"), is_distance: bool = False):
+    """|K_d| for d = 0..top at min(threshold, enclosing radius), on the GPU."""
+    import torch
+    if not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous():
+        raise ValueError("x must be a contiguous float32 CUDA tensor")
+    n = x.shape[0]
+    m = 0 if is_distance else x.shape[1]
+    counts = (ctypes.c_int64 * (top + 1))()
+    _check(_lib.rips_simplex_counts_device(ctypes.c_void_p(x.data_ptr()), n, m, top,
+                                           ctypes.c_float(threshold), counts,
+                                           _stream_ptr(torch, x.device)))
+    return [int(c) for c in counts]

@@ -1,0 +1,522 @@
+// rips_device.hpp -- device building blocks of the gfx950 Vietoris-Rips
+// persistence path (wave64, CDNA4). Written from U. Bauer, "Ripser: efficient
+// computation of Vietoris-Rips persistence barcodes" (arXiv:1908.02518).
+//
+// Everything here is integer and comparison work: combinatorial-number-system
+// (CNS) encoding and decoding, cofacet and facet enumeration, the zero
+// apparent pair tests, open-addressing hash tables, and a block-wide LSD
+// radix sort. No floating point arithmetic beyond comparisons happens on
+// distances here; distances are computed once (rips_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rips {
+
+typedef unsigned long long u64;
+typedef uint32_t u32;
+
+constexpr int kWave = 64;
+constexpr int kMaxDim = 3;             // largest homology dimension
+constexpr int kMaxVerts = kMaxDim + 2; // vertices of a cofacet of a top-dimension column
+constexpr int64_t kEmpty = -1;         // empty hash slot / "no simplex"
+
+// ---------------------------------------------------------------------------
+// Binomial coefficient table, C(i, j) at t[j * stride + i], 0 <= i <= n,
+// 0 <= j <= kMaxDim + 2 (the table of the "Vertices and simplices" paragraph).
+// ---------------------------------------------------------------------------
+struct Binom {
+    const u64 *t;
+    int stride;
+    __host__ __device__ __forceinline__ u64 operator()(int i, int j) const {
+        return t[(int64_t)j * stride + i];
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Distance access.
+// ---------------------------------------------------------------------------
+
+// Full n x n row-major float32 matrix in global memory (HBM, L2/MALL
+// resident for the sizes of one cloud). Row v is contiguous, so a wave that
+// scans candidate vertices j for a fixed simplex vertex v reads coalesced.
+struct DistFull {
+    const float *D;
+    int n;
+    __device__ __forceinline__ float operator()(int a, int b) const {
+        return D[(int64_t)a * n + b];
+    }
+};
+
+// Packed lower triangle (entry (a, b), a > b, at a(a-1)/2 + b, which is the
+// CNS index of the edge {a, b}), used when one cloud's matrix lives in LDS.
+struct DistPacked {
+    const float *D;
+    int n;
+    __device__ __forceinline__ float operator()(int a, int b) const {
+        if (a == b) return 0.0f;
+        int hi = a > b ? a : b, lo = a > b ? b : a;
+        return D[hi * (hi - 1) / 2 + lo];
+    }
+};
+
+// Neighbour lists within the threshold, ascending by neighbour index (the
+// adjacency lists of the "sparse distance matrix"); off == nullptr means
+// dense enumeration over all vertices.
+struct Nbrs {
+    const int *off;
+    const int *idx;
+};
+
+template <class Dist>
+struct Ctx {
+    Dist d;
+    Binom B;
+    Nbrs nb;
+    int n;
+    float t;
+};
+
+// ---------------------------------------------------------------------------
+// Combinatorial number system.
+// A k-simplex is the decreasing tuple v[0] > v[1] > ... > v[k]; with i_l the
+// l-th smallest vertex its index is sum_l C(i_l, l + 1).
+// ---------------------------------------------------------------------------
+
+__host__ __device__ __forceinline__ int64_t simplex_index(const int *v, int k, Binom B) {
+    int64_t s = 0;
+    for (int m = 0; m <= k; ++m) s += (int64_t)B(v[m], k - m + 1);
+    return s;
+}
+
+// Vertices of the k-simplex with index idx on n vertices: the largest vertex
+// is the largest i with C(i, k+1) <= idx (Lemma of the "Vertices and
+// simplices" paragraph), found by binary search; then recurse on the rest.
+__host__ __device__ __forceinline__ void decode(int64_t idx, int k, int n, Binom B, int *v) {
+    int hi = n - 1;
+    for (int l = k; l >= 1; --l) {
+        int lo = l;
+        int h = hi;
+        while (lo < h) {
+            int mid = (lo + h + 1) >> 1;
+            if (B(mid, l + 1) <= (u64)idx) lo = mid;
+            else h = mid - 1;
+        }
+        v[k - l] = lo;
+        idx -= (int64_t)B(lo, l + 1);
+        hi = lo - 1;
+    }
+    // valid indices leave 0 <= idx <= hi; the clamp only keeps a corrupted
+    // index from addressing outside the distance matrix
+    v[k] = (int)(idx < 0 ? 0 : (idx > hi ? hi : idx));
+}
+
+// Index of the cofacet sigma u {j}, j not in sigma (section "Enumerating
+// cofacets and facets"): vertices above j move up one binomial order. The
+// number of vertices of sigma below j is returned in *below; the coefficient
+// of the cofacet in the coboundary is (-1)^below (standard orientation).
+__host__ __device__ __forceinline__ int64_t cofacet_index(const int *v, int k, int j, Binom B,
+                                                         int *below) {
+    int64_t s = 0;
+    int nb = 0;
+    for (int m = 0; m <= k; ++m) {
+        int l = k - m;
+        if (v[m] > j) s += (int64_t)B(v[m], l + 2);
+        else {
+            s += (int64_t)B(v[m], l + 1);
+            ++nb;
+        }
+    }
+    s += (int64_t)B(j, nb + 1);
+    *below = nb;
+    return s;
+}
+
+// Insert j into the decreasing tuple v[0..k]; returns the position of j.
+__host__ __device__ __forceinline__ int insert_vertex(const int *v, int k, int j, int *out) {
+    int q = 0, pos = -1;
+    for (int m = 0; m <= k; ++m) {
+        if (pos < 0 && j > v[m]) {
+            pos = q;
+            out[q++] = j;
+        }
+        out[q++] = v[m];
+    }
+    if (pos < 0) {
+        pos = q;
+        out[q] = j;
+    }
+    return pos;
+}
+
+__host__ __device__ __forceinline__ void remove_vertex(const int *v, int k, int m, int *out) {
+    int q = 0;
+    for (int u = 0; u <= k; ++u)
+        if (u != m) out[q++] = v[u];
+}
+
+__host__ __device__ __forceinline__ u32 coeff_sign(int below, u32 p) {
+    return (below & 1) ? (p - 1) : 1u;
+}
+
+template <class Dist>
+__device__ __forceinline__ float diam_of(const Ctx<Dist> &c, const int *v, int k) {
+    float m = 0.0f;
+    for (int a = 0; a < k + 1; ++a)
+        for (int b = a + 1; b < k + 1; ++b) m = fmaxf(m, c.d(v[a], v[b]));
+    return m;
+}
+
+// Zero pivot facet: the first facet in forward colexicographic order (i.e.
+// removing v[0], then v[1], ...) whose diameter equals the simplex's. Returns
+// the position of the removed vertex or -1.
+template <class Dist>
+__device__ __forceinline__ int zero_pivot_facet(const Ctx<Dist> &c, const int *v, int k, float dm) {
+    float pd[kMaxVerts][kMaxVerts];
+    for (int a = 0; a <= k; ++a)
+        for (int b = a + 1; b <= k; ++b) pd[a][b] = c.d(v[a], v[b]);
+    for (int m = 0; m <= k; ++m) {
+        float mx = 0.0f;
+        for (int a = 0; a <= k; ++a)
+            for (int b = a + 1; b <= k; ++b)
+                if (a != m && b != m) mx = fmaxf(mx, pd[a][b]);
+        if (mx == dm) return m;
+    }
+    return -1;
+}
+
+// ---------------------------------------------------------------------------
+// Wave / group helpers. A "group" is G consecutive lanes of one wave64 that
+// cooperate on one simplex; every lane of a group follows the same control
+// flow, different groups of a wave may diverge.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Barrier for phases that hand data between waves through global memory:
+// an agent-scope fence first, so that every store and atomic of this wave
+// has completed in L2 and later loads do not hit stale L1 lines (atomics
+// execute in L2, plain accesses go through the per-CU L1).
+__device__ __forceinline__ void gsync() {
+    __threadfence();
+    __syncthreads();
+}
+
+template <class T>
+__device__ __forceinline__ T ld(const T *p) {
+    return __atomic_load_n(p, __ATOMIC_RELAXED);
+}
+
+template <class T>
+__device__ __forceinline__ void st(T *p, T v) {
+    __atomic_store_n(p, v, __ATOMIC_RELAXED);
+}
+
+template <int G>
+__device__ __forceinline__ u64 group_mask() {
+    if (G == 64) return ~0ull;
+    const int base = lane_id() & ~(G - 1);
+    return ((1ull << G) - 1) << base;
+}
+
+// Largest candidate vertex j > jmin, j not in v[0..k], with d(j, v_m) <= bound
+// for every vertex v_m; -1 if none. Candidates are scanned in decreasing
+// order, G at a time, which is decreasing CNS order of the cofacets
+// sigma u {j}; the scan stops at the first chunk holding a hit (the
+// early exit of the apparent-pair shortcut). Dense: all vertices; sparse:
+// the neighbour list of the vertex of v with the fewest neighbours.
+template <int G, class Dist>
+__device__ int group_find_max(const Ctx<Dist> &c, const int *v, int k, float bound, int jmin) {
+    const int lg = lane_id() & (G - 1);
+    const u64 gm = group_mask<G>();
+    if (c.nb.off == nullptr) {
+        for (int top = c.n - 1; top > jmin; top -= G) {
+            const int j = top - lg;
+            bool ok = j > jmin;
+            if (ok)
+                for (int m = 0; m <= k; ++m) ok = ok && (j != v[m]);
+            if (ok)
+                for (int m = 0; m <= k; ++m) ok = ok && (c.d(v[m], j) <= bound);
+            const u64 mask = __ballot(ok) & gm;
+            if (mask) return __shfl(j, __ffsll((unsigned long long)mask) - 1, kWave);
+        }
+        return -1;
+    }
+    int u = v[0];
+    int du = c.nb.off[u + 1] - c.nb.off[u];
+    for (int m = 1; m <= k; ++m) {
+        const int dm = c.nb.off[v[m] + 1] - c.nb.off[v[m]];
+        if (dm < du) {
+            du = dm;
+            u = v[m];
+        }
+    }
+    const int *L = c.nb.idx + c.nb.off[u];
+    for (int top = du - 1; top >= 0; top -= G) {
+        if (L[top] <= jmin) break; // the rest of the list is smaller still
+        const int q = top - lg;
+        const int j = q >= 0 ? L[q] : -1;
+        bool ok = j > jmin;
+        if (ok)
+            for (int m = 0; m <= k; ++m) ok = ok && (j != v[m]);
+        if (ok)
+            for (int m = 0; m <= k; ++m) ok = ok && (c.d(v[m], j) <= bound);
+        const u64 mask = __ballot(ok) & gm;
+        if (mask) return __shfl(j, __ffsll((unsigned long long)mask) - 1, kWave);
+    }
+    return -1;
+}
+
+// (sigma, sigma u {j}) is a zero apparent pair iff sigma u {j} is the
+// lexicographically largest same-diameter cofacet of sigma (j = the result of
+// group_find_max with bound = diam sigma) and sigma is its lexicographically
+// smallest same-diameter facet (Proposition on zero apparent pairs).
+template <class Dist>
+__device__ __forceinline__ bool is_zero_apparent_cofacet(const Ctx<Dist> &c, const int *v, int k,
+                                                        float dm, int j) {
+    int tv[kMaxVerts];
+    const int pos = insert_vertex(v, k, j, tv);
+    return zero_pivot_facet(c, tv, k + 1, dm) == pos;
+}
+
+// Does the k-simplex v (diameter dm) lie in a zero apparent pair (rho, v)
+// with rho a facet? rho is v's zero pivot facet; the pair is apparent iff no
+// vertex j above the removed vertex w extends rho at the same diameter, i.e.
+// v is rho's lexicographically largest same-diameter cofacet. Returns the
+// position of w in v, or -1.
+template <int G, class Dist>
+__device__ int zero_apparent_facet(const Ctx<Dist> &c, const int *v, int k, float dm) {
+    if (k == 0) return -1;
+    const int m = zero_pivot_facet(c, v, k, dm);
+    if (m < 0) return -1;
+    int rv[kMaxVerts];
+    remove_vertex(v, k, m, rv);
+    const int j = group_find_max<G>(c, rv, k - 1, dm, v[m]);
+    return j < 0 ? m : -1;
+}
+
+// ---------------------------------------------------------------------------
+// Hashing.
+// ---------------------------------------------------------------------------
+__host__ __device__ __forceinline__ u32 mix64(u64 x) {
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdULL;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ULL;
+    x ^= x >> 33;
+    return (u32)x;
+}
+
+// Pivot table of one dimension: pivot (a (k+1)-simplex) -> column position.
+// Apparent pairs are never stored (section "Implementation", persistence
+// pairs paragraph); the table only holds pivots found by the reduction.
+struct PivotHash {
+    int64_t *keys; // kEmpty when free
+    int32_t *vals;
+    u32 mask;      // capacity - 1, capacity a power of two
+};
+
+__device__ __forceinline__ int32_t ph_find(const PivotHash &h, int64_t key) {
+    u32 s = mix64((u64)key) & h.mask;
+    for (u32 probe = 0; probe <= h.mask; ++probe) {
+        const int64_t cur = __atomic_load_n(&h.keys[s], __ATOMIC_RELAXED);
+        if (cur == key) return __atomic_load_n(&h.vals[s], __ATOMIC_RELAXED);
+        if (cur == kEmpty) return -1;
+        s = (s + 1) & h.mask;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ bool ph_insert(const PivotHash &h, int64_t key, int32_t val) {
+    u32 s = mix64((u64)key) & h.mask;
+    for (u32 probe = 0; probe <= h.mask; ++probe) {
+        const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
+        if (prev == (u64)kEmpty || prev == (u64)key) {
+            __atomic_store_n(&h.vals[s], val, __ATOMIC_RELAXED);
+            return true;
+        }
+        s = (s + 1) & h.mask;
+    }
+    return false;
+}
+
+// Working column R_j (or V_j) of the reduction: a sparse vector over Z/p
+// keyed by simplex index, in LDS when it fits. Coefficients accumulate with
+// 32-bit atomics and are reduced mod p when read (XOR for p = 2).
+struct WorkHash {
+    int64_t *keys;
+    u32 *coef;
+    float *diam;
+    u32 mask;
+};
+
+// Add c * e_key (c in [0, p)); false on overflow.
+__device__ __forceinline__ bool wh_add(const WorkHash &h, int64_t key, float dm, u32 c, u32 p) {
+    u32 s = mix64((u64)key) & h.mask;
+    for (u32 probe = 0; probe <= h.mask; ++probe) {
+        const int64_t cur = __atomic_load_n(&h.keys[s], __ATOMIC_RELAXED);
+        bool mine = cur == key;
+        if (!mine && cur == kEmpty) {
+            const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
+            if (prev == (u64)kEmpty) {
+                h.diam[s] = dm;
+                mine = true;
+            } else mine = prev == (u64)key;
+        }
+        if (mine) {
+            if (p == 2) atomicXor(&h.coef[s], c & 1u);
+            else atomicAdd(&h.coef[s], c);
+            return true;
+        }
+        s = (s + 1) & h.mask;
+    }
+    return false;
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide reductions of a (diameter, index) pivot candidate: the oldest
+// entry of a coboundary column is the one of smallest diameter, then largest
+// CNS index (refined order).
+// ---------------------------------------------------------------------------
+struct PivotCand {
+    float diam;
+    int64_t idx; // kEmpty = none
+    u32 coef;
+};
+
+__device__ __forceinline__ bool older(const PivotCand &a, const PivotCand &b) {
+    if (a.idx == kEmpty) return false;
+    if (b.idx == kEmpty) return true;
+    if (a.diam != b.diam) return a.diam < b.diam;
+    return a.idx > b.idx;
+}
+
+__device__ __forceinline__ PivotCand wave_oldest(PivotCand x) {
+    for (int off = 32; off >= 1; off >>= 1) {
+        PivotCand y;
+        y.diam = __shfl_xor(x.diam, off, kWave);
+        y.idx = __shfl_xor(x.idx, off, kWave);
+        y.coef = __shfl_xor(x.coef, off, kWave);
+        if (older(y, x)) x = y;
+    }
+    return x;
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide stable LSD radix sort (8-bit digits) of up to 2^31 records with
+// 96-bit keys (hi: 32 bits, lo: 64 bits), ascending by (hi, lo), carrying a
+// 32-bit payload. Runs in one workgroup of BT threads over global ping-pong
+// buffers; histograms and per-wave digit counts live in LDS. Within a tile of
+// BT records, ranks of equal digits come from 8 ballots per wave (a
+// match-any on the digit), which keeps the scatter stable.
+// ---------------------------------------------------------------------------
+struct SortBufs {
+    u64 *lo[2];
+    u32 *hi[2];
+    u32 *val[2];
+};
+
+template <int BT>
+struct SortShared {
+    u32 hist[256];
+    u32 off[256];
+    u32 wcnt[BT / kWave][256];
+};
+
+template <int BT>
+__device__ int block_radix_sort(SortBufs b, int N, int lo_bytes, int hi_bytes, SortShared<BT> &S) {
+    const int tid = threadIdx.x;
+    const int w = tid / kWave;
+    const int lane = lane_id();
+    const u64 lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int cur = 0;
+    for (int pass = 0; pass < lo_bytes + hi_bytes; ++pass) {
+        const bool on_lo = pass < lo_bytes;
+        const int sh = 8 * (on_lo ? pass : pass - lo_bytes);
+        for (int d = tid; d < 256; d += BT) S.hist[d] = 0;
+        gsync();
+        for (int e = tid; e < N; e += BT) {
+            const u32 dg = on_lo ? (u32)((b.lo[cur][e] >> sh) & 255) : ((b.hi[cur][e] >> sh) & 255);
+            atomicAdd(&S.hist[dg], 1u);
+        }
+        __syncthreads();
+        if (tid < kWave) {
+            // exclusive scan of 256 bins by one wave, 4 bins per lane
+            u32 v0 = S.hist[4 * lane], v1 = S.hist[4 * lane + 1], v2 = S.hist[4 * lane + 2],
+                v3 = S.hist[4 * lane + 3];
+            u32 sum = v0 + v1 + v2 + v3, inc = sum;
+            for (int o = 1; o < kWave; o <<= 1) {
+                u32 t = __shfl_up(inc, o, kWave);
+                if (lane >= o) inc += t;
+            }
+            u32 ex = inc - sum;
+            S.off[4 * lane] = ex;
+            S.off[4 * lane + 1] = ex + v0;
+            S.off[4 * lane + 2] = ex + v0 + v1;
+            S.off[4 * lane + 3] = ex + v0 + v1 + v2;
+        }
+        __syncthreads();
+        const int nxt = cur ^ 1;
+        for (int base = 0; base < N; base += BT) {
+            const int e = base + tid;
+            const bool valid = e < N;
+            u32 dg = 0;
+            u64 klo = 0;
+            u32 khi = 0, kv = 0;
+            if (valid) {
+                klo = b.lo[cur][e];
+                khi = b.hi[cur][e];
+                kv = b.val[cur][e];
+                dg = on_lo ? (u32)((klo >> sh) & 255) : ((khi >> sh) & 255);
+            }
+            u64 same = __ballot(valid);
+            for (int bit = 0; bit < 8; ++bit) {
+                const u64 bb = __ballot(valid && ((dg >> bit) & 1));
+                same &= ((dg >> bit) & 1) ? bb : ~bb;
+            }
+            for (int d = tid; d < (BT / kWave) * 256; d += BT) (&S.wcnt[0][0])[d] = 0;
+            __syncthreads();
+            const u32 rank_w = __popcll(same & lt);
+            if (valid && rank_w == 0) S.wcnt[w][dg] = __popcll(same);
+            __syncthreads();
+            if (valid) {
+                u32 r = rank_w;
+                for (int ww = 0; ww < w; ++ww) r += S.wcnt[ww][dg];
+                const u32 dst = S.off[dg] + r;
+                if (dst < (u32)N) {
+                    b.lo[nxt][dst] = klo;
+                    b.hi[nxt][dst] = khi;
+                    b.val[nxt][dst] = kv;
+                }
+            }
+            __syncthreads();
+            for (int d = tid; d < 256; d += BT) {
+                u32 s = 0;
+                for (int ww = 0; ww < BT / kWave; ++ww) s += S.wcnt[ww][d];
+                S.off[d] += s;
+            }
+            __syncthreads();
+        }
+        gsync();
+        cur = nxt;
+    }
+    gsync();
+    return cur; // buffer index holding the sorted data
+}
+
+// Wave-aggregated append: lanes with pred get consecutive slots of *counter
+// (one atomic per wave). Returns the slot or -1.
+__device__ __forceinline__ int64_t wave_append(unsigned long long *counter, bool pred) {
+    const u64 m = __ballot(pred);
+    if (!m) return -1;
+    const int lane = lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+    base = __shfl(base, leader, kWave);
+    const u64 lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    return pred ? (int64_t)(base + __popcll(m & lt)) : -1;
+}
+
+} // namespace rips

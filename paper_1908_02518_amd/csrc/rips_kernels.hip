@@ -1,0 +1,1154 @@
+// rips_kernels.hip -- gfx950 kernels of the single-cloud Vietoris-Rips path.
+//
+// Data layout in HBM (one cloud):
+//   D        n x n float32, row-major (rows contiguous: coalesced scans of
+//            candidate vertices for a fixed simplex vertex)
+//   B        binomial table, (kMaxDim + 3) x (n + 1) uint64
+//   edges    SoA (idx int64, diam f32, a i32, b i32) of the edges <= t
+//   nbr      CSR neighbour lists <= t, ascending (sparse path only)
+//   lists    SoA (idx int64, diam f32) of all k-simplices <= t, k >= 2
+//   columns  SoA (idx, diam, j*, tau-apparent flag) of the surviving columns
+//   pivots   open-addressing table pivot -> column per dimension
+//   V        death columns of the reduction matrix, CSR-like append buffer
+#include "rips_kernels.hpp"
+
+namespace rips {
+
+// ---------------------------------------------------------------------------
+// tables
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ u64 gcd64(u64 a, u64 b) {
+    while (b) {
+        u64 t = a % b;
+        a = b;
+        b = t;
+    }
+    return a;
+}
+
+// C(i, j) for 0 <= i <= n, 0 <= j <= jmax, by C(i, j) = C(i, j-1) (i-j+1) / j
+// with the gcd split so that no intermediate exceeds the result.
+__global__ void k_binom(u64 *B, int stride, int n, int jmax) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    u64 r = 1;
+    B[i] = 1;
+    for (int j = 1; j <= jmax; ++j) {
+        if (j > i) r = 0;
+        else {
+            const u64 g = gcd64(r, (u64)j);
+            r = (r / g) * ((u64)(i - j + 1) / ((u64)j / g));
+        }
+        B[(int64_t)j * stride + i] = r;
+    }
+}
+
+// multiplicative inverses mod p (the paper's multiplicative_inverse_vector)
+__global__ void k_inverse(u32 *inv, u32 p) {
+    const u32 a = blockIdx.x * blockDim.x + threadIdx.x;
+    if (a >= p) return;
+    if (a == 0) {
+        inv[0] = 0;
+        return;
+    }
+    u64 r = 1, b = a, e = p - 2;
+    while (e) {
+        if (e & 1) r = r * b % p;
+        b = b * b % p;
+        e >>= 1;
+    }
+    inv[a] = (u32)r;
+}
+
+// ---------------------------------------------------------------------------
+// distances
+// ---------------------------------------------------------------------------
+
+// d(i, j) = sqrt(sum_c (x_ic - x_jc)^2): coordinates in increasing order,
+// every product and sum rounded to float32 (built with -ffp-contract=off),
+// correctly rounded square root. Full square matrix; (x_i - x_j)^2 equals
+// (x_j - x_i)^2 exactly, so D is bitwise symmetric.
+__global__ void k_dist_points(const float *__restrict__ X, int n, int m, float *__restrict__ D,
+                              int *bad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n) return;
+    const float *xi = X + (int64_t)i * m;
+    const float *xj = X + (int64_t)j * m;
+    float s = 0.0f;
+    bool fin = true;
+    for (int c = 0; c < m; ++c) {
+        const float a = xi[c], b = xj[c];
+        fin = fin && isfinite(a) && isfinite(b);
+        const float t = a - b;
+        const float sq = t * t;
+        s = s + sq;
+    }
+    if (!fin) atomicOr(bad, 1);
+    D[(int64_t)i * n + j] = __builtin_sqrtf(s);
+}
+
+// Distance-matrix input: entries (i, j), i > j, of a row-major n x n matrix.
+__global__ void k_dist_matrix(const float *__restrict__ M, int n, float *__restrict__ D, int *bad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (j >= n) return;
+    float v;
+    if (i > j) v = M[(int64_t)i * n + j];
+    else if (i < j) v = M[(int64_t)j * n + i];
+    else v = 0.0f;
+    if (!(v >= 0.0f) || isinf(v)) atomicOr(bad, 1);
+    D[(int64_t)i * n + j] = v;
+}
+
+// ---------------------------------------------------------------------------
+// threshold: enclosing radius min_x max_y d(x, y); t_eff = min(t, r_enc)
+// ---------------------------------------------------------------------------
+__global__ void k_init_scalars(Scalars *s) {
+    s->renc_bits = 0x7f800000u; // +inf
+    s->bad = 0;
+    s->status = 0;
+    s->edges = 0;
+    s->list = 0;
+    s->survivors = 0;
+    s->vcount = 0;
+    s->mst = 0;
+    s->nbars = 0;
+    s->maxdeg = 0;
+    for (int q = 0; q < kNumStats; ++q) s->stat[q] = 0;
+}
+
+// per-dimension counters back to zero (the host has read them)
+__global__ void k_reset_dim(Scalars *s) {
+    s->status = 0;
+    s->list = 0;
+    s->survivors = 0;
+    s->vcount = 0;
+    s->nbars = 0;
+    for (int q = 0; q < kNumStats; ++q) s->stat[q] = 0;
+}
+
+__global__ void k_rowmax(const float *__restrict__ D, int n, Scalars *s) {
+    const int wpb = blockDim.x / kWave;
+    const int i = blockIdx.x * wpb + threadIdx.x / kWave;
+    if (i >= n) return;
+    const int lane = lane_id();
+    const float *row = D + (int64_t)i * n;
+    float mx = 0.0f;
+    for (int j = lane; j < n; j += kWave) mx = fmaxf(mx, row[j]);
+    for (int off = 32; off >= 1; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, kWave));
+    if (lane == 0) atomicMin(&s->renc_bits, __float_as_uint(mx));
+}
+
+__global__ void k_set_teff(Scalars *s, float t) {
+    const float r = __uint_as_float(s->renc_bits);
+    s->r_enc = r;
+    s->t_eff = fminf(t, r);
+}
+
+// ---------------------------------------------------------------------------
+// edges <= t_eff (k = 1 candidates; Kruskal/Boruvka input), degrees
+// ---------------------------------------------------------------------------
+__global__ void k_edges(const float *__restrict__ D, int n, Scalars *s, EdgeList E, int64_t cap,
+                        int *deg) {
+    const int wpb = blockDim.x / kWave;
+    const int i = blockIdx.x * wpb + threadIdx.x / kWave;
+    if (i >= n) return;
+    const float t = s->t_eff;
+    const int lane = lane_id();
+    const float *row = D + (int64_t)i * n;
+    int mine = 0;
+    for (int j0 = 0; j0 < i; j0 += kWave) {
+        const int j = j0 + lane;
+        const float d = j < i ? row[j] : INFINITY;
+        const bool ok = d <= t;
+        const int64_t slot = wave_append(&s->edges, ok);
+        if (ok) {
+            if (slot < cap) {
+                E.idx[slot] = (int64_t)i * (i - 1) / 2 + j;
+                E.diam[slot] = d;
+                E.a[slot] = i;
+                E.b[slot] = j;
+            }
+            atomicAdd(&deg[j], 1);
+            ++mine;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) mine += __shfl_xor(mine, off, kWave);
+    if (lane == 0 && mine) atomicAdd(&deg[i], mine);
+}
+
+__global__ void k_zero_int(int *a, int64_t n) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        a[q] = 0;
+}
+
+__global__ void k_fill_i64(int64_t *a, int64_t n, int64_t v) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        a[q] = v;
+}
+
+// ---------------------------------------------------------------------------
+// block-wide exclusive scan helper (BT threads, one value each)
+// ---------------------------------------------------------------------------
+template <int BT>
+__device__ __forceinline__ int block_exclusive_scan(int x, int *s_w, int *total) {
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    int inc = x;
+    for (int o = 1; o < kWave; o <<= 1) {
+        int t = __shfl_up(inc, o, kWave);
+        if (lane >= o) inc += t;
+    }
+    if (lane == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int q = 0; q < BT / kWave; ++q) {
+            int t = s_w[q];
+            s_w[q] = acc;
+            acc += t;
+        }
+        s_w[BT / kWave] = acc;
+    }
+    __syncthreads();
+    const int r = s_w[w] + inc - x;
+    *total = s_w[BT / kWave];
+    __syncthreads();
+    return r;
+}
+
+// exclusive scan of deg[0..n) into off[0..n], single block
+__global__ void __launch_bounds__(1024) k_scan_deg(const int *deg, int n, int *off) {
+    __shared__ int s_w[1024 / kWave + 1];
+    int carry = 0;
+    for (int base = 0; base < n; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int x = i < n ? deg[i] : 0;
+        int tot;
+        const int ex = block_exclusive_scan<1024>(x, s_w, &tot);
+        if (i < n) off[i] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) off[n] = carry;
+}
+
+// neighbour lists: one block per vertex, ascending neighbour order
+__global__ void __launch_bounds__(256) k_csr_fill(const float *__restrict__ D, int n, Scalars *s,
+                                                  const int *off, int *nbr) {
+    __shared__ int s_w[256 / kWave + 1];
+    const int i = blockIdx.x;
+    const float t = s->t_eff;
+    const float *row = D + (int64_t)i * n;
+    int at = off[i];
+    const int end = off[i + 1];
+    for (int base = 0; base < n; base += 256) {
+        const int j = base + threadIdx.x;
+        const bool ok = j < n && j != i && row[j] <= t;
+        int tot;
+        const int ex = block_exclusive_scan<256>(ok ? 1 : 0, s_w, &tot);
+        if (ok && at + ex < end) nbr[at + ex] = j;
+        at += tot;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// H0: minimum spanning forest by Boruvka rounds on the refined edge order
+// (diameter, then larger CNS index = older first), then the elder rule on the
+// forest's edges in that order (Kruskal with union-find, "Persistence pairs"
+// paragraph). One block.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 edge_key(float d, u32 idx) {
+    return ((u64)__float_as_uint(d) << 32) | (u64)(0xffffffffu - idx);
+}
+
+__device__ __forceinline__ void edge_vertices(u32 idx, int *a, int *b) {
+    // largest a with a(a-1)/2 <= idx
+    int x = (int)((1.0 + sqrt(1.0 + 8.0 * (double)idx)) * 0.5);
+    while ((int64_t)x * (x - 1) / 2 > (int64_t)idx) --x;
+    while ((int64_t)(x + 1) * x / 2 <= (int64_t)idx) ++x;
+    *a = x;
+    *b = (int)((int64_t)idx - (int64_t)x * (x - 1) / 2);
+}
+
+__device__ __forceinline__ int uf_find(int *parent, int v, int n) {
+    int p = __atomic_load_n(&parent[v], __ATOMIC_RELAXED);
+    for (int guard = 0; p != v && guard < n; ++guard) {
+        v = p;
+        p = __atomic_load_n(&parent[v], __ATOMIC_RELAXED);
+    }
+    return v;
+}
+
+constexpr int kH0Threads = 1024;
+constexpr int kH0LdsMax = 2048; // union-find state of up to this many vertices lives in LDS
+
+__global__ void __launch_bounds__(kH0Threads) k_h0(EdgeList E, Scalars *s, int n, H0Scratch W,
+                                                    BarBuf out) {
+    __shared__ SortShared<kH0Threads> S;
+    __shared__ int s_flag;
+    __shared__ int s_w[kH0Threads / kWave + 1];
+    __shared__ int l_comp[kH0LdsMax];
+    __shared__ int l_hook[kH0LdsMax];
+    __shared__ u64 l_best[kH0LdsMax];
+    const bool in_lds = n <= kH0LdsMax;
+    // every word below that is touched by an atomic is only ever accessed
+    // atomically; phases are separated by gsync()
+    int *comp = in_lds ? l_comp : W.comp;
+    int *hook = in_lds ? l_hook : W.hook;
+    u64 *best = in_lds ? l_best : W.best;
+    const int tid = threadIdx.x;
+    const int64_t ne = s->edges;
+    const int64_t all_edges = (int64_t)n * (n - 1) / 2;
+    for (int v = tid; v < n; v += kH0Threads) st(&comp[v], v);
+    gsync();
+    // Boruvka: every component picks its oldest outgoing edge. Each round at
+    // least halves the number of components that still have an edge; the
+    // round bound only guards against a fault.
+    for (int round = 0; round < 40; ++round) {
+        for (int v = tid; v < n; v += kH0Threads) st(&best[v], ~0ull);
+        gsync();
+        for (int64_t e = tid; e < ne; e += kH0Threads) {
+            const int ca = ld(&comp[E.a[e]]), cb = ld(&comp[E.b[e]]);
+            if (ca != cb) {
+                const u64 key = edge_key(E.diam[e], (u32)E.idx[e]);
+                atomicMin(&best[ca], key);
+                atomicMin(&best[cb], key);
+            }
+        }
+        if (tid == 0) s_flag = 0;
+        gsync();
+        for (int v = tid; v < n; v += kH0Threads) {
+            const int cv = ld(&comp[v]);
+            int h = cv; // non-roots keep pointing at their root
+            const u64 key = ld(&best[v]);
+            if (cv == v && key != ~0ull) {
+                int a, b;
+                edge_vertices(0xffffffffu - (u32)(key & 0xffffffffu), &a, &b);
+                const int ca = ld(&comp[a]), cb = ld(&comp[b]);
+                const int other = ca == v ? cb : ca;
+                const bool mutual = ld(&best[other]) == key;
+                // mutual choices form 2-cycles: the larger root hooks
+                if (!mutual || v > other) {
+                    h = other;
+                    const u64 slot = atomicAdd(&s->mst, 1ull);
+                    if (slot < (u64)n) W.mst[slot] = key;
+                    s_flag = 1;
+                }
+            }
+            st(&hook[v], h);
+        }
+        gsync();
+        if (!s_flag) break;
+        for (int v = tid; v < n; v += kH0Threads) st(&comp[v], ld(&hook[v]));
+        for (int jump = 0; jump < 40; ++jump) {
+            gsync();
+            if (tid == 0) s_flag = 0;
+            gsync();
+            for (int v = tid; v < n; v += kH0Threads) {
+                const int c = ld(&comp[v]), cc = ld(&comp[c]);
+                if (c != cc) {
+                    st(&comp[v], cc);
+                    s_flag = 1;
+                }
+            }
+            gsync();
+            if (!s_flag) break;
+        }
+    }
+    gsync();
+    // sort the forest edges by key: refined filtration order
+    const u64 mcount = ld(&s->mst);
+    if (mcount > (u64)(n > 0 ? n - 1 : 0) && tid == 0) s->status = 4; // cannot happen
+    const int m = (int)(mcount < (u64)n ? mcount : (u64)(n > 0 ? n - 1 : 0));
+    SortBufs sb;
+    sb.lo[0] = W.mst;
+    sb.lo[1] = W.mst2;
+    sb.hi[0] = W.hi;
+    sb.hi[1] = W.hi2;
+    sb.val[0] = W.val;
+    sb.val[1] = W.val2;
+    for (int e = tid; e < m; e += kH0Threads) {
+        W.hi[e] = 0;
+        W.val[e] = 0;
+    }
+    gsync();
+    const int cur = block_radix_sort<kH0Threads>(sb, m, 8, 0, S);
+    const u64 *keys = sb.lo[cur];
+    // elder rule, 64 forest edges per step on wave 0: roots at the start of
+    // the step come from the shared union-find; the merges inside the step
+    // are resolved in order with wave shuffles
+    int *parent = comp;
+    int *maxv = hook;
+    for (int v = tid; v < n; v += kH0Threads) {
+        st(&parent[v], v);
+        st(&maxv[v], v);
+        W.hdeath[v] = -1.0f; // no bar (yet) born at v
+    }
+    gsync();
+    if (tid < kWave) {
+        const int lane = tid;
+        for (int base = 0; base < m; base += kWave) {
+            const int e = base + lane;
+            const bool valid = e < m;
+            int ra = 0, rb = 0, ma = -1, mb = -1;
+            u32 idx = 0;
+            float dm = 0.0f;
+            if (valid) {
+                const u64 key = keys[e];
+                idx = 0xffffffffu - (u32)(key & 0xffffffffu);
+                dm = __uint_as_float((u32)(key >> 32));
+                int a, b;
+                edge_vertices(idx, &a, &b);
+                a = a < n ? a : n - 1;
+                b = b < n ? b : n - 1;
+                ra = uf_find(parent, a, n);
+                rb = uf_find(parent, b, n);
+                ma = ld(&maxv[ra]);
+                mb = ld(&maxv[rb]);
+            }
+            const int cnt = min(kWave, m - base);
+            int my_loser = 0, my_winner = 0, my_newmax = 0, my_birth = 0;
+            for (int q = 0; q < cnt; ++q) {
+                const int RA = __shfl(ra, q, kWave), RB = __shfl(rb, q, kWave);
+                const int MA = __shfl(ma, q, kWave), MB = __shfl(mb, q, kWave);
+                const int winner = MA > MB ? RA : RB;
+                const int loser = MA > MB ? RB : RA;
+                const int newmax = MA > MB ? MA : MB;
+                if (lane == q) {
+                    my_loser = loser;
+                    my_winner = winner;
+                    my_newmax = newmax;
+                    my_birth = MA > MB ? MB : MA;
+                }
+                if (ra == RA || ra == RB) {
+                    ra = winner;
+                    ma = newmax;
+                }
+                if (rb == RA || rb == RB) {
+                    rb = winner;
+                    mb = newmax;
+                }
+            }
+            if (valid) {
+                st(&parent[my_loser], my_winner);
+                atomicMax(&maxv[my_winner], my_newmax);
+                if (dm > 0.0f) {
+                    W.hdeath[my_birth] = dm;
+                    W.hdsimp[my_birth] = (int64_t)idx;
+                }
+                if ((int64_t)idx < all_edges) atomicOr(&W.bits[idx >> 5], 1u << (idx & 31));
+            }
+            __threadfence();
+        }
+    }
+    gsync();
+    // essential classes: one per component, born at its oldest vertex
+    for (int v = tid; v < n; v += kH0Threads)
+        if (ld(&parent[v]) == v) {
+            const int b = ld(&maxv[v]);
+            W.hdeath[b] = INFINITY;
+            W.hdsimp[b] = -1;
+        }
+    gsync();
+    // bars by birth simplex descending (canonical order: all births are 0)
+    int at = 0;
+    int nz = 0, ness = 0;
+    for (int base = 0; base < n; base += kH0Threads) {
+        const int v = n - 1 - (base + tid);
+        const float hd = v >= 0 ? W.hdeath[v] : -1.0f;
+        const bool has = hd >= 0.0f;
+        int tot;
+        const int ex = block_exclusive_scan<kH0Threads>(has ? 1 : 0, s_w, &tot);
+        if (has && at + ex < n) {
+            out.birth[at + ex] = 0.0f;
+            out.death[at + ex] = hd;
+            out.bs[at + ex] = v;
+            out.ds[at + ex] = W.hdsimp[v];
+            if (isinf(hd)) ++ness;
+            else ++nz;
+        }
+        at += tot;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        nz += __shfl_xor(nz, off, kWave);
+        ness += __shfl_xor(ness, off, kWave);
+    }
+    if (lane_id() == 0) {
+        atomicAdd(&s->stat[kStatBarsNonzero], (u64)nz);
+        atomicAdd(&s->stat[kStatEssential], (u64)ness);
+    }
+    if (tid == 0) s->nbars = at < n ? at : n;
+}
+
+// ---------------------------------------------------------------------------
+// expansion: all k-simplices <= t from the (k-1)-simplices, each exactly once
+// as the cofacet sigma u {j} with j above sigma's largest vertex ("Assembling
+// column indices": cofacets enumerated with all_cofacets = false).
+// ---------------------------------------------------------------------------
+template <int G, class Dist>
+__global__ void __launch_bounds__(256) k_expand(Ctx<Dist> c, int k, SimplexList in, int64_t count,
+                                                Scalars *s, SimplexList out, int64_t cap) {
+    const int gpb = blockDim.x / G;
+    const int lg = threadIdx.x & (G - 1);
+    const int64_t stride = (int64_t)gridDim.x * gpb;
+    for (int64_t e = blockIdx.x * (int64_t)gpb + threadIdx.x / G; e < count; e += stride) {
+        const int64_t idx = in.idx[e];
+        const float dm0 = in.diam[e];
+        int v[kMaxVerts];
+        decode(idx, k - 1, c.n, c.B, v);
+        const int top = v[0];
+        const int *L = nullptr;
+        int lo = top + 1, hi = c.n; // candidate range [lo, hi)
+        if (c.nb.off != nullptr) {
+            L = c.nb.idx + c.nb.off[top];
+            const int len = c.nb.off[top + 1] - c.nb.off[top];
+            // first neighbour above top
+            int a = 0, b = len;
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (L[mid] <= top) a = mid + 1;
+                else b = mid;
+            }
+            lo = a;
+            hi = len;
+        }
+        for (int q0 = lo; q0 < hi; q0 += G) {
+            const int q = q0 + lg;
+            bool ok = q < hi;
+            int j = 0;
+            float nd = dm0;
+            if (ok) {
+                j = L ? L[q] : q;
+                for (int m = 0; m < k; ++m) {
+                    const float d = c.d(v[m], j);
+                    ok = ok && (d <= c.t);
+                    nd = fmaxf(nd, d);
+                }
+            }
+            const int64_t slot = wave_append(&s->list, ok);
+            if (ok && slot < cap) {
+                out.idx[slot] = (int64_t)c.B(j, k + 1) + idx;
+                out.diam[slot] = nd;
+            }
+        }
+    }
+}
+
+// counting-only variant for the top dimension (throughput accounting)
+template <int G, class Dist>
+__global__ void __launch_bounds__(256) k_expand_count(Ctx<Dist> c, int k, SimplexList in,
+                                                      int64_t count, Scalars *s) {
+    const int gpb = blockDim.x / G;
+    const int lg = threadIdx.x & (G - 1);
+    const int64_t stride = (int64_t)gridDim.x * gpb;
+    u64 mine = 0;
+    for (int64_t e = blockIdx.x * (int64_t)gpb + threadIdx.x / G; e < count; e += stride) {
+        int v[kMaxVerts];
+        decode(in.idx[e], k - 1, c.n, c.B, v);
+        const int top = v[0];
+        const int *L = nullptr;
+        int lo = top + 1, hi = c.n;
+        if (c.nb.off != nullptr) {
+            L = c.nb.idx + c.nb.off[top];
+            const int len = c.nb.off[top + 1] - c.nb.off[top];
+            int a = 0, b = len;
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (L[mid] <= top) a = mid + 1;
+                else b = mid;
+            }
+            lo = a;
+            hi = len;
+        }
+        for (int q0 = lo; q0 < hi; q0 += G) {
+            const int q = q0 + lg;
+            bool ok = q < hi;
+            if (ok) {
+                const int j = L ? L[q] : q;
+                for (int m = 0; m < k; ++m) ok = ok && (c.d(v[m], j) <= c.t);
+            }
+            mine += ok ? 1 : 0;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) mine += __shfl_xor(mine, off, kWave);
+    if (lane_id() == 0 && mine) atomicAdd(&s->list, mine);
+}
+
+// ---------------------------------------------------------------------------
+// The enumeration / apparent-pair pass (the hot data-parallel pass): for each
+// candidate k-simplex sigma (diam <= t):
+//   - cleared: sigma is a pivot of dimension k-1 (clearing; k = 1: a forest
+//     edge of H0);
+//   - sigma in a zero apparent pair (sigma, tau): tau = sigma u {j}, j the
+//     largest vertex extending sigma at the same diameter, and sigma is tau's
+//     first same-diameter facet;
+//   - sigma in a zero apparent pair (rho, sigma) (k >= 2);
+//   - otherwise sigma is a column to reduce; its zero pivot cofacet j (or -1)
+//     and whether that cofacet is itself in a zero apparent pair are kept for
+//     the emergent shortcut of the reduction.
+// G lanes cooperate on one candidate (G candidate vertices per step).
+// ---------------------------------------------------------------------------
+template <int G, class Dist>
+__global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, int k, SimplexList in, int64_t count,
+                                                const u32 *mst_bits, PivotHash prev, Scalars *s,
+                                                Columns out) {
+    const int gpb = blockDim.x / G;
+    const int lg = threadIdx.x & (G - 1);
+    const int64_t stride = (int64_t)gridDim.x * gpb;
+    u64 n_clear = 0, n_acol = 0, n_apiv = 0;
+    for (int64_t e = blockIdx.x * (int64_t)gpb + threadIdx.x / G; e < count; e += stride) {
+        const int64_t idx = in.idx[e];
+        const float dm = in.diam[e];
+        int v[kMaxVerts];
+        bool cleared;
+        if (k == 1) {
+            edge_vertices((u32)idx, &v[0], &v[1]);
+            cleared = (mst_bits[idx >> 5] >> (idx & 31)) & 1u;
+        } else {
+            decode(idx, k, c.n, c.B, v);
+            cleared = ph_find(prev, idx) >= 0;
+        }
+        if (cleared) {
+            n_clear += (lg == 0);
+            continue;
+        }
+        const int j = group_find_max<G>(c, v, k, dm, -1);
+        if (j >= 0 && is_zero_apparent_cofacet(c, v, k, dm, j)) {
+            n_acol += (lg == 0);
+            continue;
+        }
+        if (k >= 2 && zero_apparent_facet<G>(c, v, k, dm) >= 0) {
+            n_apiv += (lg == 0);
+            continue;
+        }
+        uint8_t tapp = 0;
+        if (j >= 0) {
+            int tv[kMaxVerts];
+            insert_vertex(v, k, j, tv);
+            tapp = zero_apparent_facet<G>(c, tv, k + 1, dm) >= 0 ? 1 : 0;
+        }
+        if (lg == 0) {
+            const u64 slot = atomicAdd(&s->survivors, 1ull);
+            if (slot >= (u64)count) continue; // one survivor per candidate at most
+            out.idx[slot] = idx;
+            out.diam[slot] = dm;
+            out.j[slot] = j;
+            out.tapp[slot] = tapp;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        n_clear += __shfl_xor(n_clear, off, kWave);
+        n_acol += __shfl_xor(n_acol, off, kWave);
+        n_apiv += __shfl_xor(n_apiv, off, kWave);
+    }
+    if (lane_id() == 0) {
+        if (n_clear) atomicAdd(&s->stat[kStatCleared], n_clear);
+        if (n_acol) atomicAdd(&s->stat[kStatAppCol], n_acol);
+        if (n_apiv) atomicAdd(&s->stat[kStatAppPiv], n_apiv);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// sort of the columns: reverse filtration order, i.e. diameter descending,
+// then CNS index ascending (youngest first). Keys: hi = ~diameter bits
+// (diameters are >= +0, so bit order is value order), lo = index.
+// ---------------------------------------------------------------------------
+constexpr int kSortThreads = 1024;
+
+__global__ void __launch_bounds__(kSortThreads) k_sort_columns(Columns in, Scalars *s,
+                                                               SortBufs sb, int lo_bytes,
+                                                               Columns out) {
+    __shared__ SortShared<kSortThreads> S;
+    const int N = (int)s->survivors;
+    for (int e = threadIdx.x; e < N; e += kSortThreads) {
+        sb.lo[0][e] = (u64)in.idx[e];
+        sb.hi[0][e] = ~__float_as_uint(in.diam[e]);
+        sb.val[0][e] = (u32)e;
+    }
+    __syncthreads();
+    const int cur = block_radix_sort<kSortThreads>(sb, N, lo_bytes, 4, S);
+    for (int q = threadIdx.x; q < N; q += kSortThreads) {
+        const u32 e = sb.val[cur][q];
+        out.idx[q] = in.idx[e];
+        out.diam[q] = in.diam[e];
+        out.j[q] = in.j[e];
+        out.tapp[q] = in.tapp[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reduction of the surviving columns over Z/p (Algorithm 1 on the implicit
+// coboundary matrix, with clearing already applied, the emergent shortcut,
+// and pivot lookup = pivot table, then zero apparent facet).
+// One workgroup; columns in order; V keeps only death columns.
+// ---------------------------------------------------------------------------
+constexpr int kRedThreads = 256;
+
+template <class Dist>
+struct RedState {
+    Ctx<Dist> c;
+    int k;
+    u32 p;
+};
+
+// R += coef * (coboundary of the k-simplex v, diameter dv): all cofacets of
+// diameter <= t. Coefficient of sigma u {j}: (-1)^(vertices of sigma below j).
+template <class Dist>
+__device__ bool add_coboundary(const Ctx<Dist> &c, int k, const int *v, float dv, u32 coef, u32 p,
+                               const WorkHash &R) {
+    bool ok = true;
+    if (c.nb.off == nullptr) {
+        for (int j = threadIdx.x; j < c.n; j += blockDim.x) {
+            bool in = false;
+            float nd = dv;
+            for (int m = 0; m <= k; ++m) {
+                in = in || (j == v[m]);
+                nd = fmaxf(nd, c.d(v[m], j));
+            }
+            if (in || !(nd <= c.t)) continue;
+            int below;
+            const int64_t ci = cofacet_index(v, k, j, c.B, &below);
+            const u32 cc = (below & 1) ? (p - coef) % p : coef;
+            ok = ok && wh_add(R, ci, nd, cc, p);
+        }
+        return ok;
+    }
+    int u = v[0];
+    int du = c.nb.off[u + 1] - c.nb.off[u];
+    for (int m = 1; m <= k; ++m) {
+        const int dd = c.nb.off[v[m] + 1] - c.nb.off[v[m]];
+        if (dd < du) {
+            du = dd;
+            u = v[m];
+        }
+    }
+    const int *L = c.nb.idx + c.nb.off[u];
+    for (int q = threadIdx.x; q < du; q += blockDim.x) {
+        const int j = L[q];
+        bool in = false;
+        float nd = dv;
+        for (int m = 0; m <= k; ++m) {
+            in = in || (j == v[m]);
+            nd = fmaxf(nd, c.d(v[m], j));
+        }
+        if (in || !(nd <= c.t)) continue;
+        int below;
+        const int64_t ci = cofacet_index(v, k, j, c.B, &below);
+        const u32 cc = (below & 1) ? (p - coef) % p : coef;
+        ok = ok && wh_add(R, ci, nd, cc, p);
+    }
+    return ok;
+}
+
+template <class Dist>
+__global__ void __launch_bounds__(kRedThreads) k_reduce(Ctx<Dist> c, int k, u32 p, const u32 *inv,
+                                                       Columns cols, int ncols, PivotHash ph,
+                                                       VStore V, WorkHash Rg, WorkHash Vg,
+                                                       int use_lds, u32 capR, u32 capV,
+                                                       Scalars *s, BarBuf bars) {
+    extern __shared__ unsigned char smem[];
+    __shared__ int s_base, s_full, s_abort, s_m;
+    __shared__ int64_t s_owner;
+    __shared__ PivotCand s_wp[kRedThreads / kWave];
+    __shared__ PivotCand s_piv;
+    __shared__ int s_w[kRedThreads / kWave + 1];
+    __shared__ u64 s_stat[8];
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+
+    WorkHash R = Rg, Vw = Vg;
+    if (use_lds) {
+        unsigned char *q = smem;
+        R.keys = (int64_t *)q;
+        q += (size_t)capR * 8;
+        Vw.keys = (int64_t *)q;
+        q += (size_t)capV * 8;
+        R.coef = (u32 *)q;
+        q += (size_t)capR * 4;
+        R.diam = (float *)q;
+        q += (size_t)capR * 4;
+        Vw.coef = (u32 *)q;
+        q += (size_t)capV * 4;
+        Vw.diam = (float *)q;
+        R.mask = capR - 1;
+        Vw.mask = capV - 1;
+    }
+    if (tid == 0) {
+        s_base = 0;
+        s_abort = 0;
+    }
+    if (tid < 8) s_stat[tid] = 0;
+    int nbars = 0; // maintained by thread 0
+    gsync();
+
+    for (;;) {
+        gsync();
+        const int base = s_base;
+        const int stop = base >= ncols || s_abort;
+        gsync(); // everyone has read the cursor before wave 0 moves it
+        if (stop) break;
+        // ---- Phase A: emergent shortcut for up to 64 columns at once (wave 0)
+        if (w == 0) {
+            const int col = base + lane;
+            const bool valid = col < ncols;
+            bool ok = false;
+            int64_t tau = kEmpty;
+            u32 tcoef = 0;
+            if (valid) {
+                const int j = cols.j[col];
+                if (j >= 0 && !cols.tapp[col]) {
+                    int v[kMaxVerts];
+                    decode(cols.idx[col], k, c.n, c.B, v);
+                    int below;
+                    tau = cofacet_index(v, k, j, c.B, &below);
+                    tcoef = coeff_sign(below, p);
+                    ok = ph_find(ph, tau) < 0;
+                }
+            }
+            // a lower column of the batch that takes the same pivot owns it
+            for (int l = 0; l < kWave - 1; ++l) {
+                const int64_t tl = __shfl(tau, l, kWave);
+                const int okl = __shfl((int)ok, l, kWave);
+                if (l < lane && okl && tl == tau) ok = false;
+            }
+            const u64 bad = __ballot(!ok);
+            const int first_bad = bad ? __ffsll((unsigned long long)bad) - 1 : kWave;
+            if (lane < first_bad) {
+                ph_insert(ph, tau, col);
+                V.pivcoef[col] = tcoef;
+                V.len[col] = 0;
+                V.off[col] = 0;
+            }
+            if (lane == 0) {
+                s_base = base + first_bad;
+                s_full = (first_bad < kWave) && (base + first_bad < ncols);
+                s_stat[0] += first_bad; // emergent
+            }
+        }
+        gsync();
+        if (!s_full) continue;
+        // ---- Phase B: full reduction of column j
+        const int j = s_base;
+        const int64_t sidx = cols.idx[j];
+        const float sdm = cols.diam[j];
+        int v[kMaxVerts];
+        decode(sidx, k, c.n, c.B, v);
+        for (u32 q = tid; q <= R.mask; q += kRedThreads) {
+            __atomic_store_n(&R.keys[q], kEmpty, __ATOMIC_RELAXED);
+            __atomic_store_n(&R.coef[q], 0u, __ATOMIC_RELAXED);
+        }
+        for (u32 q = tid; q <= Vw.mask; q += kRedThreads) {
+            __atomic_store_n(&Vw.keys[q], kEmpty, __ATOMIC_RELAXED);
+            __atomic_store_n(&Vw.coef[q], 0u, __ATOMIC_RELAXED);
+        }
+        gsync();
+        if (!add_coboundary(c, k, v, sdm, 1u, p, R)) s_abort = 1;
+        int nadd = 0;
+        for (;;) {
+            gsync();
+            if (s_abort) break;
+            // every addition moves the pivot to a strictly younger row, so the
+            // loop ends; the cap only turns an arithmetic fault into an error
+            if (nadd > (1 << 16)) {
+                if (tid == 0) s_abort = 3;
+                gsync();
+                break;
+            }
+            // pivot: oldest nonzero entry
+            PivotCand best;
+            best.idx = kEmpty;
+            best.diam = 0.0f;
+            best.coef = 0;
+            for (u32 q = tid; q <= R.mask; q += kRedThreads) {
+                const int64_t key = ld(&R.keys[q]);
+                if (key == kEmpty) continue;
+                u32 cf = ld(&R.coef[q]);
+                if (p != 2 && cf >= p) {
+                    cf %= p;
+                    __atomic_store_n(&R.coef[q], cf, __ATOMIC_RELAXED);
+                }
+                if (cf == 0) continue;
+                PivotCand x;
+                x.idx = key;
+                x.diam = R.diam[q];
+                x.coef = cf;
+                if (older(x, best)) best = x;
+            }
+            best = wave_oldest(best);
+            if (lane == 0) s_wp[w] = best;
+            gsync();
+            if (tid == 0) {
+                PivotCand b = s_wp[0];
+                for (int q = 1; q < kRedThreads / kWave; ++q)
+                    if (older(s_wp[q], b)) b = s_wp[q];
+                s_piv = b;
+                s_owner = b.idx == kEmpty ? -1 : ph_find(ph, b.idx);
+            }
+            gsync();
+            const PivotCand piv = s_piv;
+            if (piv.idx == kEmpty) {
+                // zero column: essential class born at sigma
+                if (tid == 0 && nbars < ncols) {
+                    bars.birth[nbars] = sdm;
+                    bars.death[nbars] = INFINITY;
+                    bars.bs[nbars] = sidx;
+                    bars.ds[nbars] = -1;
+                    ++nbars;
+                    s_stat[4] += 1;
+                }
+                break;
+            }
+            const int64_t o = s_owner;
+            if (o >= 0) {
+                // R_j -= lambda R_o with R_o = D (e_o + V_o), lambda = piv / pivot(R_o)
+                const u32 lam = (u32)((u64)piv.coef * inv[V.pivcoef[o]] % p);
+                const u32 neg = (p - lam) % p;
+                const int nv = V.len[o];
+                const int64_t vo = V.off[o];
+                for (int it = 0; it <= nv; ++it) {
+                    const int64_t si = it == 0 ? cols.idx[o] : V.idx[vo + it - 1];
+                    const u32 sc = it == 0 ? 1u : V.coef[vo + it - 1];
+                    const u32 cc = (u32)((u64)neg * sc % p);
+                    int sv[kMaxVerts];
+                    decode(si, k, c.n, c.B, sv);
+                    const float sd = diam_of(c, sv, k);
+                    if (!add_coboundary(c, k, sv, sd, cc, p, R)) s_abort = 1;
+                    if ((it % kRedThreads) == tid)
+                        if (!wh_add(Vw, si, sd, cc, p)) s_abort = 1;
+                }
+                ++nadd;
+                continue;
+            }
+            // not in the table: is the pivot in a zero apparent pair (rho, tau)?
+            int tv[kMaxVerts];
+            decode(piv.idx, k + 1, c.n, c.B, tv);
+            if (w == 0) {
+                const int m = zero_apparent_facet<kWave>(c, tv, k + 1, piv.diam);
+                if (lane == 0) s_m = m;
+            }
+            gsync();
+            const int m = s_m;
+            if (m >= 0) {
+                int rv[kMaxVerts];
+                remove_vertex(tv, k + 1, m, rv);
+                // tau = rho u {tau[m]}; vertices of rho below tau[m]: k + 1 - m
+                const u32 crho = coeff_sign(k + 1 - m, p);
+                const u32 lam = (u32)((u64)piv.coef * inv[crho] % p);
+                const u32 neg = (p - lam) % p;
+                if (!add_coboundary(c, k, rv, piv.diam, neg, p, R)) s_abort = 1;
+                if (tid == 0)
+                    if (!wh_add(Vw, simplex_index(rv, k, c.B), piv.diam, neg, p)) s_abort = 1;
+                ++nadd;
+                continue;
+            }
+            // unowned pivot: persistence pair (sigma_j, pivot)
+            if (tid == 0) {
+                if (piv.diam > sdm && nbars < ncols) {
+                    bars.birth[nbars] = sdm;
+                    bars.death[nbars] = piv.diam;
+                    bars.bs[nbars] = sidx;
+                    bars.ds[nbars] = piv.idx;
+                    ++nbars;
+                    s_stat[3] += 1;
+                }
+                ph_insert(ph, piv.idx, j);
+                V.pivcoef[j] = piv.coef;
+            }
+            // store the nonzero entries of V_j
+            int cnt = 0;
+            for (u32 q = tid; q <= Vw.mask; q += kRedThreads) {
+                const u32 cf = ld(&Vw.coef[q]) % p;
+                cnt += (ld(&Vw.keys[q]) != kEmpty && cf != 0) ? 1 : 0;
+            }
+            int tot;
+            const int ex = block_exclusive_scan<kRedThreads>(cnt, s_w, &tot);
+            __shared__ unsigned long long s_vbase;
+            if (tid == 0) s_vbase = atomicAdd(&s->vcount, (unsigned long long)tot);
+            gsync();
+            const int64_t vb = (int64_t)s_vbase;
+            if (vb + tot > V.cap) {
+                if (tid == 0) s_abort = 2;
+            } else {
+                int at = ex;
+                for (u32 q = tid; q <= Vw.mask; q += kRedThreads) {
+                    const u32 cf = ld(&Vw.coef[q]) % p;
+                    const int64_t key = ld(&Vw.keys[q]);
+                    if (key != kEmpty && cf != 0) {
+                        V.idx[vb + at] = key;
+                        V.coef[vb + at] = cf;
+                        ++at;
+                    }
+                }
+                if (tid == 0) {
+                    V.off[j] = vb;
+                    V.len[j] = tot;
+                }
+            }
+            break;
+        }
+        if (tid == 0) {
+            s_stat[1] += nadd > 0 ? 1 : 0;
+            s_stat[2] += nadd;
+            s_base = j + 1;
+        }
+        gsync();
+    }
+    gsync();
+    if (tid == 0) {
+        s->status = s_abort;
+        s->nbars = nbars;
+        s->stat[kStatEmergent] += s_stat[0];
+        s->stat[kStatReduced] += s_stat[1];
+        s->stat[kStatAdditions] += s_stat[2];
+        s->stat[kStatBarsNonzero] += s_stat[3];
+        s->stat[kStatEssential] += s_stat[4];
+    }
+}
+
+// bars of one dimension into the caller's arrays; reverse = column order was
+// youngest first, the canonical order is the reverse
+__global__ void k_emit(BarBuf in, Scalars *s, int reverse, BarBuf out) {
+    const int64_t nb = s->nbars;
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < nb;
+         q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t src = reverse ? nb - 1 - q : q;
+        out.birth[q] = in.birth[src];
+        out.death[q] = in.death[src];
+        out.bs[q] = in.bs[src];
+        out.ds[q] = in.ds[src];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// instantiations / launchers
+// ---------------------------------------------------------------------------
+template <int G>
+static void launch_filter_g(const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
+                            const u32 *bits, PivotHash prev, Scalars *s, Columns out,
+                            hipStream_t st) {
+    const int gpb = 256 / G;
+    int64_t blocks = (count + gpb - 1) / gpb;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL((k_filter<G, DistFull>), dim3((unsigned)blocks), dim3(256), 0, st, c, k, in,
+                       count, bits, prev, s, out);
+}
+
+void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
+                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, hipStream_t st) {
+    switch (G) {
+    case 4: launch_filter_g<4>(c, k, in, count, bits, prev, s, out, st); break;
+    case 8: launch_filter_g<8>(c, k, in, count, bits, prev, s, out, st); break;
+    case 16: launch_filter_g<16>(c, k, in, count, bits, prev, s, out, st); break;
+    case 32: launch_filter_g<32>(c, k, in, count, bits, prev, s, out, st); break;
+    default: launch_filter_g<64>(c, k, in, count, bits, prev, s, out, st); break;
+    }
+}
+
+template <int G>
+static void launch_expand_g(const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
+                            Scalars *s, SimplexList out, int64_t cap, bool count_only,
+                            hipStream_t st) {
+    const int gpb = 256 / G;
+    int64_t blocks = (count + gpb - 1) / gpb;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 65536) blocks = 65536;
+    if (count_only)
+        hipLaunchKernelGGL((k_expand_count<G, DistFull>), dim3((unsigned)blocks), dim3(256), 0, st,
+                           c, k, in, count, s);
+    else
+        hipLaunchKernelGGL((k_expand<G, DistFull>), dim3((unsigned)blocks), dim3(256), 0, st, c, k,
+                           in, count, s, out, cap);
+}
+
+void launch_expand(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, Scalars *s,
+                   SimplexList out, int64_t cap, bool count_only, hipStream_t st) {
+    switch (G) {
+    case 8: launch_expand_g<8>(c, k, in, count, s, out, cap, count_only, st); break;
+    case 16: launch_expand_g<16>(c, k, in, count, s, out, cap, count_only, st); break;
+    case 32: launch_expand_g<32>(c, k, in, count, s, out, cap, count_only, st); break;
+    default: launch_expand_g<64>(c, k, in, count, s, out, cap, count_only, st); break;
+    }
+}
+
+void launch_binom(u64 *B, int stride, int n, int jmax, hipStream_t st) {
+    hipLaunchKernelGGL(k_binom, dim3((n + 1 + 255) / 256), dim3(256), 0, st, B, stride, n, jmax);
+}
+
+void launch_inverse(u32 *inv, u32 p, hipStream_t st) {
+    hipLaunchKernelGGL(k_inverse, dim3((p + 255) / 256), dim3(256), 0, st, inv, p);
+}
+
+void launch_dist(const float *data, int n, int m, float *D, int *bad, hipStream_t st) {
+    dim3 grid((n + 255) / 256, n);
+    if (m > 0) hipLaunchKernelGGL(k_dist_points, grid, dim3(256), 0, st, data, n, m, D, bad);
+    else hipLaunchKernelGGL(k_dist_matrix, grid, dim3(256), 0, st, data, n, D, bad);
+}
+
+void launch_init_scalars(Scalars *s, hipStream_t st) {
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(1), 0, st, s);
+}
+
+void launch_reset_dim(Scalars *s, hipStream_t st) {
+    hipLaunchKernelGGL(k_reset_dim, dim3(1), dim3(1), 0, st, s);
+}
+
+void launch_threshold(const float *D, int n, float t, Scalars *s, hipStream_t st) {
+    hipLaunchKernelGGL(k_rowmax, dim3((n + 3) / 4), dim3(256), 0, st, D, n, s);
+    hipLaunchKernelGGL(k_set_teff, dim3(1), dim3(1), 0, st, s, t);
+}
+
+void launch_edges(const float *D, int n, Scalars *s, EdgeList E, int64_t cap, int *deg,
+                  hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_int, dim3(64), dim3(256), 0, st, deg, (int64_t)n + 1);
+    hipLaunchKernelGGL(k_edges, dim3((n + 3) / 4), dim3(256), 0, st, D, n, s, E, cap, deg);
+}
+
+void launch_csr(const float *D, int n, Scalars *s, const int *deg, int *off, int *nbr,
+                hipStream_t st) {
+    hipLaunchKernelGGL(k_scan_deg, dim3(1), dim3(1024), 0, st, deg, n, off);
+    hipLaunchKernelGGL(k_csr_fill, dim3(n), dim3(256), 0, st, D, n, s, off, nbr);
+}
+
+__global__ void k_reset_mst(Scalars *s) { s->mst = 0; }
+
+void launch_h0(EdgeList E, Scalars *s, int n, H0Scratch W, BarBuf out, int64_t nbits_words,
+               hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_int, dim3(256), dim3(256), 0, st, (int *)W.bits, nbits_words);
+    hipLaunchKernelGGL(k_reset_mst, dim3(1), dim3(1), 0, st, s);
+    hipLaunchKernelGGL(k_h0, dim3(1), dim3(kH0Threads), 0, st, E, s, n, W, out);
+}
+
+void launch_fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t st) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)blocks), dim3(256), 0, st, a, n, v);
+}
+
+void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Columns out,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_sort_columns, dim3(1), dim3(kSortThreads), 0, st, in, s, sb, lo_bytes,
+                       out);
+}
+
+size_t reduce_lds_bytes(u32 capR, u32 capV) { return (size_t)capR * 16 + (size_t)capV * 16; }
+
+void launch_reduce(const Ctx<DistFull> &c, int k, u32 p, const u32 *inv, Columns cols, int ncols,
+                   PivotHash ph, VStore V, WorkHash Rg, WorkHash Vg, int use_lds, u32 capR,
+                   u32 capV, Scalars *s, BarBuf bars, hipStream_t st) {
+    const size_t lds = use_lds ? reduce_lds_bytes(capR, capV) : 0;
+    if (lds > 64 * 1024)
+        (void)hipFuncSetAttribute((const void *)k_reduce<DistFull>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k_reduce<DistFull>, dim3(1), dim3(kRedThreads), lds, st, c, k, p, inv, cols,
+                       ncols, ph, V, Rg, Vg, use_lds, capR, capV, s, bars);
+}
+
+void launch_emit(BarBuf in, Scalars *s, int reverse, BarBuf out, hipStream_t st) {
+    hipLaunchKernelGGL(k_emit, dim3(64), dim3(256), 0, st, in, s, reverse, out);
+}
+
+} // namespace rips

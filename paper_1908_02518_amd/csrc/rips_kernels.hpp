@@ -1,0 +1,111 @@
+// rips_kernels.hpp -- buffers shared by the host driver and the kernels of
+// the single-cloud path, and the launcher declarations.
+#pragma once
+
+#include "rips_device.hpp"
+
+namespace rips {
+
+enum {
+    kStatCleared = 0,
+    kStatAppCol,
+    kStatAppPiv,
+    kStatEmergent,
+    kStatReduced,
+    kStatAdditions,
+    kStatBarsNonzero,
+    kStatEssential,
+    kNumStats
+};
+
+// Device scalars of one call; read back by the host after a dimension ends.
+struct Scalars {
+    u32 renc_bits;    // enclosing radius as float bits (atomicMin target)
+    int bad;          // nonfinite / negative input seen
+    int status;       // reduction: 0 ok, 1 working column overflow, 2 V overflow
+    float r_enc;
+    float t_eff;
+    unsigned long long edges;     // edges <= t (may exceed capacity)
+    unsigned long long list;      // expanded simplices (may exceed capacity)
+    unsigned long long survivors; // columns left by the filter
+    unsigned long long vcount;    // entries appended to V
+    unsigned long long mst;       // forest edges
+    int64_t nbars;                // bars of the current dimension
+    int maxdeg;                   // largest vertex degree at the threshold
+    unsigned long long stat[kNumStats];
+};
+
+struct EdgeList {
+    int64_t *idx;
+    float *diam;
+    int *a; // larger vertex
+    int *b; // smaller vertex
+};
+
+struct SimplexList {
+    int64_t *idx;
+    float *diam;
+};
+
+struct Columns {
+    int64_t *idx;
+    float *diam;
+    int *j;         // zero pivot cofacet vertex, -1 if none
+    uint8_t *tapp;  // 1 if that cofacet lies in a zero apparent pair
+};
+
+struct VStore {
+    int64_t *off;   // per column
+    int *len;
+    u32 *pivcoef;   // pivot entry of R_j
+    int64_t *idx;   // append buffer of (simplex, coefficient)
+    u32 *coef;
+    int64_t cap;
+};
+
+struct BarBuf {
+    float *birth;
+    float *death;
+    int64_t *bs;
+    int64_t *ds;
+};
+
+struct H0Scratch {
+    int *comp;
+    int *hook;
+    u64 *best;
+    u64 *mst, *mst2;
+    u32 *hi, *hi2, *val, *val2;
+    int *parent;
+    int *maxv;
+    float *hdeath;
+    int64_t *hdsimp;
+    u32 *bits; // forest edges by edge index (clearing of dimension 1)
+};
+
+void launch_binom(u64 *B, int stride, int n, int jmax, hipStream_t st);
+void launch_inverse(u32 *inv, u32 p, hipStream_t st);
+void launch_dist(const float *data, int n, int m, float *D, int *bad, hipStream_t st);
+void launch_init_scalars(Scalars *s, hipStream_t st);
+void launch_reset_dim(Scalars *s, hipStream_t st);
+void launch_threshold(const float *D, int n, float t, Scalars *s, hipStream_t st);
+void launch_edges(const float *D, int n, Scalars *s, EdgeList E, int64_t cap, int *deg,
+                  hipStream_t st);
+void launch_csr(const float *D, int n, Scalars *s, const int *deg, int *off, int *nbr,
+                hipStream_t st);
+void launch_h0(EdgeList E, Scalars *s, int n, H0Scratch W, BarBuf out, int64_t nbits_words,
+               hipStream_t st);
+void launch_fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t st);
+void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
+                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, hipStream_t st);
+void launch_expand(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, Scalars *s,
+                   SimplexList out, int64_t cap, bool count_only, hipStream_t st);
+void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Columns out,
+                         hipStream_t st);
+size_t reduce_lds_bytes(u32 capR, u32 capV);
+void launch_reduce(const Ctx<DistFull> &c, int k, u32 p, const u32 *inv, Columns cols, int ncols,
+                   PivotHash ph, VStore V, WorkHash Rg, WorkHash Vg, int use_lds, u32 capR,
+                   u32 capV, Scalars *s, BarBuf bars, hipStream_t st);
+void launch_emit(BarBuf in, Scalars *s, int reverse, BarBuf out, hipStream_t st);
+
+} // namespace rips

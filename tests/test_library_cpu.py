@@ -1,0 +1,84 @@
+"""CPU-side checks of the HIP library: it loads, exports every symbol that
+include/rips.h declares, and rejects bad arguments before any HIP call."""
+
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rips.h")
+
+
+def _header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rips_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1908_02518_amd as rips
+    out = subprocess.run(["nm", "-D", "--defined-only", rips.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (rips_\w+)", out))
+    declared = _header_functions()
+    assert declared, "no declarations found"
+    missing = [f for f in declared if f not in exported]
+    assert not missing, missing
+    for f in declared:
+        getattr(rips.lib(), f)
+
+
+def test_binding_lists_the_header():
+    import paper_1908_02518_amd as rips
+    assert sorted(rips.EXPORTS) == _header_functions()
+
+
+def test_status_strings():
+    import paper_1908_02518_amd as rips
+    for code in rips.STATUS:
+        assert rips.lib().rips_status_string(code)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(p=4), -2),
+    (dict(p=1), -2),
+    (dict(p=65537), -2),
+    (dict(max_dim=4), -1),
+    (dict(max_dim=-1), -1),
+    (dict(threshold=float("nan")), -1),
+])
+def test_argument_validation_before_any_hip_call(kw, code):
+    import paper_1908_02518_amd as rips
+    x = np.zeros((5, 2), np.float32)
+    args = dict(max_dim=1, threshold=float("inf"), p=2)
+    args.update(kw)
+    with pytest.raises(rips.RipsError) as e:
+        rips.barcode(x, **args)
+    assert e.value.status == code
+
+
+def test_index_overflow_rejected():
+    import paper_1908_02518_amd as rips
+    # C(65535, 5) > 2^63
+    n = 65535
+    assert math.comb(n, 5) >= 2 ** 63
+    lib = rips.lib()
+    out = ctypes.POINTER(rips.rips_result)()
+    dummy = (ctypes.c_float * 1)()
+    st = lib.rips_barcode(dummy, n, 1, 3, ctypes.c_float(1.0), 2, ctypes.byref(out))
+    assert st == -3 and not out
+
+
+def test_empty_and_null_inputs_rejected():
+    import paper_1908_02518_amd as rips
+    lib = rips.lib()
+    out = ctypes.POINTER(rips.rips_result)()
+    assert lib.rips_barcode(None, 4, 2, 1, ctypes.c_float(1.0), 2, ctypes.byref(out)) == -1
+    dummy = (ctypes.c_float * 1)()
+    assert lib.rips_barcode(dummy, 0, 2, 1, ctypes.c_float(1.0), 2, ctypes.byref(out)) == -1
+    assert lib.rips_barcode(dummy, 4, -1, 1, ctypes.c_float(1.0), 2, ctypes.byref(out)) == -1
