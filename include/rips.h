@@ -161,6 +161,61 @@ rips_status rips_barcode_device(const float *d_data, int64_t n, int32_t dim, int
 rips_status rips_simplex_counts_device(const float *d_data, int64_t n, int32_t dim, int32_t top,
                                        float threshold, int64_t *counts, void *hip_stream);
 
+/*
+ * rips_barcode_batched_device -- barcodes of B point clouds of uneven sizes
+ * in one persistent launch (one workgroup per cloud from a queue ordered by
+ * decreasing size), replayed from a cached hipGraph when the arguments
+ * repeat. Same method and conventions as rips_barcode, per cloud.
+ *   d_points   device float32, all clouds' points concatenated row-major
+ *              (dim coordinates each); cloud b has rows
+ *              [d_offsets[b], d_offsets[b+1]).
+ *   d_offsets  device int64, B + 1 entries, nondecreasing, d_offsets[0] = 0.
+ *   n_max      an upper bound on every cloud's size, 1 <= n_max <= 2048
+ *              (sizes scratch memory; clouds above it give RIPS_E_INVALID_ARG).
+ *   max_dim    0 or 1.
+ *   out        caller-owned device arrays:
+ *                birth/death/birth_simplex/death_simplex: cap entries;
+ *                bar_offsets: B * (max_dim + 1) + 1 entries; the bars of
+ *                  cloud b in dimension d are [bar_offsets[b*(max_dim+1)+d],
+ *                  bar_offsets[b*(max_dim+1)+d+1]), canonical order inside;
+ *                stats: B * (max_dim + 1) entries, or NULL;
+ *                threshold_used: B entries, or NULL.
+ *              `needed` (host) receives the total number of bars; if it
+ *              exceeds cap the call returns RIPS_E_CAPACITY and the bar
+ *              arrays are not written (bar_offsets are).
+ * Work is queued on `hip_stream`; the call returns after it has finished.
+ */
+typedef struct {
+    int64_t cap;
+    float *birth;
+    float *death;
+    int64_t *birth_simplex;
+    int64_t *death_simplex;
+    int64_t *bar_offsets;
+    rips_dim_stats *stats;
+    float *threshold_used;
+    int64_t needed;
+} rips_batch_out;
+
+rips_status rips_barcode_batched_device(const float *d_points, const int64_t *d_offsets, int32_t B,
+                                        int32_t dim, int32_t n_max, int32_t max_dim,
+                                        float threshold, uint32_t p, rips_batch_out *out,
+                                        void *hip_stream);
+
+/*
+ * Diagnostics: GPU time per kernel class of the calls made while profiling
+ * is on, from hipEvents recorded around each launch on the caller's stream.
+ * rips_profile_enable(1) clears the totals and starts recording; (0) stops.
+ * Classes are numbered 0 .. rips_profile_count()-1 and named
+ * ("distances", "h0", "filter_d2", "reduce_d2", ...). Not thread-safe with
+ * concurrent rips_* calls on other threads.
+ */
+void rips_profile_enable(int on);
+int rips_profile_count(void);
+const char *rips_profile_name(int i);
+double rips_profile_ms(int i);      /* total milliseconds */
+int64_t rips_profile_calls(int i);  /* launches timed */
+
 #ifdef __cplusplus
 }
 #endif

@@ -47,6 +47,12 @@ EXPORTS = (
     "rips_last_error",
     "rips_barcode_device",
     "rips_simplex_counts_device",
+    "rips_barcode_batched_device",
+    "rips_profile_enable",
+    "rips_profile_count",
+    "rips_profile_name",
+    "rips_profile_ms",
+    "rips_profile_calls",
 )
 
 
@@ -104,6 +110,18 @@ class rips_device_out(ctypes.Structure):
                 ("needed_cap", ctypes.c_int64)]
 
 
+class rips_batch_out(ctypes.Structure):
+    _fields_ = [("cap", ctypes.c_int64),
+                ("birth", ctypes.c_void_p),
+                ("death", ctypes.c_void_p),
+                ("birth_simplex", ctypes.c_void_p),
+                ("death_simplex", ctypes.c_void_p),
+                ("bar_offsets", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p),
+                ("threshold_used", ctypes.c_void_p),
+                ("needed", ctypes.c_int64)]
+
+
 def _load():
     # One HIP runtime per process: torch ships its own libamdhip64 (SONAME
     # libamdhip64.so.7) and resolves it through its RPATH. Importing torch
@@ -115,7 +133,7 @@ def _load():
         pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it with `python -m paper_1908_02518_amd.build` "
+            f"{LIB_PATH} is missing: build it with `python paper_1908_02518_amd/build.py` "
             "(hipcc, gfx950). There is no fallback implementation.")
     lib = ctypes.CDLL(LIB_PATH)
     f32p = ctypes.POINTER(ctypes.c_float)
@@ -137,6 +155,21 @@ def _load():
                                                ctypes.c_int32, ctypes.c_float,
                                                ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
     lib.rips_simplex_counts_device.restype = ctypes.c_int
+    lib.rips_barcode_batched_device.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                                ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_float, ctypes.c_uint32,
+                                                ctypes.POINTER(rips_batch_out), ctypes.c_void_p]
+    lib.rips_barcode_batched_device.restype = ctypes.c_int
+    lib.rips_profile_enable.argtypes = [ctypes.c_int]
+    lib.rips_profile_enable.restype = None
+    lib.rips_profile_count.argtypes = []
+    lib.rips_profile_count.restype = ctypes.c_int
+    lib.rips_profile_name.argtypes = [ctypes.c_int]
+    lib.rips_profile_name.restype = ctypes.c_char_p
+    lib.rips_profile_ms.argtypes = [ctypes.c_int]
+    lib.rips_profile_ms.restype = ctypes.c_double
+    lib.rips_profile_calls.argtypes = [ctypes.c_int]
+    lib.rips_profile_calls.restype = ctypes.c_int64
     return lib
 
 
@@ -286,3 +319,97 @@ def simplex_counts(x, top: int, *, threshold: float = float("inf"), is_distance:
                                            ctypes.c_float(threshold), counts,
                                            _stream_ptr(torch, x.device)))
     return [int(c) for c in counts]
+
+
+def profile_enable(on: bool = True):
+    """Start (clearing the totals) or stop per-kernel-class GPU timing."""
+    _lib.rips_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """{kernel class: (total ms, launches)} for the classes that ran."""
+    out = {}
+    for i in range(_lib.rips_profile_count()):
+        c = int(_lib.rips_profile_calls(i))
+        if c:
+            out[_lib.rips_profile_name(i).decode()] = (float(_lib.rips_profile_ms(i)), c)
+    return out
+
+
+class BatchedBars:
+    """Bars of a batch: flat device tensors plus offsets[(b, d)] segments."""
+
+    def __init__(self, birth, death, birth_simplex, death_simplex, offsets, stats, thresholds,
+                 B, max_dim):
+        self.birth, self.death = birth, death
+        self.birth_simplex, self.death_simplex = birth_simplex, death_simplex
+        self.offsets, self.stats, self.thresholds = offsets, stats, thresholds
+        self.B, self.max_dim = B, max_dim
+
+    def segment(self, b: int, d: int):
+        i = b * (self.max_dim + 1) + d
+        lo, hi = int(self.offsets_host[i]), int(self.offsets_host[i + 1])
+        return (self.birth[lo:hi], self.death[lo:hi], self.birth_simplex[lo:hi],
+                self.death_simplex[lo:hi])
+
+    @property
+    def offsets_host(self):
+        if not hasattr(self, "_off_host"):
+            self._off_host = self.offsets.cpu().numpy()
+        return self._off_host
+
+
+def pack_clouds(clouds, device="cuda"):
+    """Concatenate a list of (n_b, m) float32 arrays / tensors into the
+    (points, offsets, n_max) triple the batched entry point takes."""
+    import torch
+    ts = [torch.as_tensor(c, dtype=torch.float32) for c in clouds]
+    sizes = [int(t.shape[0]) for t in ts]
+    offsets = torch.zeros(len(ts) + 1, dtype=torch.int64)
+    offsets[1:] = torch.cumsum(torch.tensor(sizes, dtype=torch.int64), 0)
+    x = torch.cat(ts, 0).contiguous().to(device)
+    return x, offsets.to(device), max(sizes)
+
+
+STATS_DTYPE = np.dtype([(f, np.int64) for f in STAT_FIELDS])
+
+
+def barcode_batched(x, offsets, n_max: int, *, max_dim: int = 1,
+                    threshold: float = float("inf"), p: int = 2, cap: int | None = None):
+    """Barcodes of a batch of point clouds in one persistent launch (a cached
+    hipGraph). x: (N, m) float32 CUDA tensor of all points; offsets: (B+1,)
+    int64 CUDA tensor; n_max: bound on cloud sizes. Returns BatchedBars."""
+    import torch
+    if not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 2:
+        raise ValueError("x must be a contiguous float32 CUDA tensor of rank 2")
+    if not offsets.is_cuda or offsets.dtype != torch.int64 or offsets.dim() != 1:
+        raise ValueError("offsets must be an int64 CUDA tensor")
+    B = offsets.shape[0] - 1
+    D1 = max_dim + 1
+    dev = x.device
+    cap = cap if cap is not None else max(1024, 4 * int(n_max) * B)
+    off = torch.empty(B * D1 + 1, dtype=torch.int64, device=dev)
+    stats = torch.empty(B * D1 * len(STAT_FIELDS), dtype=torch.int64, device=dev)
+    thr = torch.empty(B, dtype=torch.float32, device=dev)
+    while True:
+        birth = torch.empty(cap, dtype=torch.float32, device=dev)
+        death = torch.empty_like(birth)
+        bs = torch.empty(cap, dtype=torch.int64, device=dev)
+        ds = torch.empty_like(bs)
+        o = rips_batch_out()
+        o.cap = cap
+        o.birth, o.death = birth.data_ptr(), death.data_ptr()
+        o.birth_simplex, o.death_simplex = bs.data_ptr(), ds.data_ptr()
+        o.bar_offsets, o.stats, o.threshold_used = off.data_ptr(), stats.data_ptr(), thr.data_ptr()
+        st = _lib.rips_barcode_batched_device(ctypes.c_void_p(x.data_ptr()),
+                                              ctypes.c_void_p(offsets.data_ptr()), B,
+                                              x.shape[1], int(n_max), max_dim,
+                                              ctypes.c_float(threshold), p, ctypes.byref(o),
+                                              _stream_ptr(torch, dev))
+        if st == -6 and o.needed > cap:
+            cap = int(o.needed)
+            continue
+        _check(st)
+        break
+    return BatchedBars(birth, death, bs, ds, off, stats.view(B, D1, len(STAT_FIELDS)), thr, B,
+                       max_dim)

@@ -15,7 +15,7 @@
 #include <vector>
 
 #include "../../include/rips.h"
-#include "rips_kernels.hpp"
+#include "rips_batched.hpp"
 
 using namespace rips;
 
@@ -88,17 +88,72 @@ enum BufId {
     B_V_PIV,
     B_V_IDX,
     B_V_COEF,
+    B_V_DIAM,
     B_WR_KEYS,
     B_WR_COEF,
     B_WR_DIAM,
     B_WV_KEYS,
     B_WV_COEF,
     B_WV_DIAM,
+    B_WR_SLOTS,
+    B_WV_SLOTS,
     B_BAR_BIRTH, // + d
     B_BAR_DEATH = B_BAR_BIRTH + kMaxDim + 1,
     B_BAR_BS = B_BAR_DEATH + kMaxDim + 1,
     B_BAR_DS = B_BAR_BS + kMaxDim + 1,
     B_STAGE = B_BAR_DS + kMaxDim + 1,
+    // batched path
+    BB_DG,
+    BB_C_IDX0,
+    BB_C_IDX1,
+    BB_C_DM0,
+    BB_C_DM1,
+    BB_C_J0,
+    BB_C_J1,
+    BB_C_T0,
+    BB_C_T1,
+    BB_S_LO0,
+    BB_S_LO1,
+    BB_S_HI0,
+    BB_S_HI1,
+    BB_S_V0,
+    BB_S_V1,
+    BB_PH_KEYS,
+    BB_PH_VALS,
+    BB_V_OFF,
+    BB_V_LEN,
+    BB_V_PIV,
+    BB_V_IDX,
+    BB_V_DIAM,
+    BB_V_COEF,
+    BB_V_COUNT,
+    BB_BITS,
+    BB_RG_KEYS,
+    BB_RG_COEF,
+    BB_RG_DIAM,
+    BB_RG_SLOTS,
+    BB_ST_B,
+    BB_ST_D,
+    BB_ST_BS,
+    BB_ST_DS,
+    BB_UB,
+    BB_UD,
+    BB_UBS,
+    BB_UDS,
+    BB_SEG_START,
+    BB_SEG_COUNT,
+    BB_STATS,
+    BB_TUSED,
+    BB_LPT_LO0,
+    BB_LPT_LO1,
+    BB_LPT_HI0,
+    BB_LPT_HI1,
+    BB_LPT_V0,
+    BB_LPT_V1,
+    BB_ORDER,
+    BB_SCAL,
+    BB_BINOM,
+    BB_INV,
     B_NUM
 };
 
@@ -110,6 +165,14 @@ struct DevCtx {
     int64_t hint_edges = 0;
     int64_t hint_list[kMaxDim + 2] = {};
     int64_t hint_v = 0;
+    int lds_per_block = 0;
+    int num_cus = 0;
+    hipStream_t capture_stream = nullptr;
+    // cached graph of the batched launch and the arguments it was built for
+    hipGraphExec_t batch_exec = nullptr;
+    std::vector<unsigned char> batch_key;
+    int64_t batch_vstride = 0;
+    int64_t batch_rgstride = 0;
 
     hipError_t ensure(int id, size_t bytes, void **out) {
         if (bytes == 0) bytes = 16;
@@ -144,6 +207,10 @@ rips_status get_ctx(DevCtx **out) {
     if (!g_ctx[dev]) {
         DevCtx *c = new DevCtx();
         HIP_TRY(hipHostMalloc((void **)&c->host_scal, sizeof(Scalars), hipHostMallocDefault));
+        HIP_TRY(hipDeviceGetAttribute(&c->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                      dev));
+        HIP_TRY(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+        HIP_TRY(hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking));
         g_ctx[dev] = c;
     }
     *out = g_ctx[dev];
@@ -204,6 +271,108 @@ T *as(void *p) {
     return static_cast<T *>(p);
 }
 
+// ---------------------------------------------------------------------------
+// Optional per-kernel-class GPU timing (rips_profile_*): hipEvents recorded
+// on the caller's stream around each launch, resolved at the sync points.
+// ---------------------------------------------------------------------------
+enum ProfId {
+    P_TABLES,
+    P_DIST,
+    P_THRESHOLD,
+    P_EDGES,
+    P_CSR,
+    P_H0,
+    P_EXPAND1, // expansion to dimension k at P_EXPAND1 + k - 1 (k = 2..)
+    P_FILTER1 = P_EXPAND1 + kMaxDim + 1,
+    P_SORT1 = P_FILTER1 + kMaxDim,
+    P_REDUCE1 = P_SORT1 + kMaxDim,
+    P_EMIT = P_REDUCE1 + kMaxDim,
+    P_BATCHED,
+    P_NUM
+};
+
+const char *prof_name(int i) {
+    static char names[P_NUM][32];
+    static bool init = false;
+    if (!init) {
+        for (int q = 0; q < P_NUM; ++q) snprintf(names[q], 32, "k%d", q);
+        snprintf(names[P_TABLES], 32, "tables");
+        snprintf(names[P_DIST], 32, "distances");
+        snprintf(names[P_THRESHOLD], 32, "threshold");
+        snprintf(names[P_EDGES], 32, "edges");
+        snprintf(names[P_CSR], 32, "neighbour_lists");
+        snprintf(names[P_H0], 32, "h0");
+        for (int k = 1; k <= kMaxDim + 1; ++k) snprintf(names[P_EXPAND1 + k - 1], 32, "expand_d%d", k);
+        for (int k = 1; k <= kMaxDim; ++k) {
+            snprintf(names[P_FILTER1 + k - 1], 32, "filter_d%d", k);
+            snprintf(names[P_SORT1 + k - 1], 32, "sort_d%d", k);
+            snprintf(names[P_REDUCE1 + k - 1], 32, "reduce_d%d", k);
+        }
+        snprintf(names[P_EMIT], 32, "emit");
+        snprintf(names[P_BATCHED], 32, "batched_graph");
+        init = true;
+    }
+    return (i >= 0 && i < P_NUM) ? names[i] : "";
+}
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    double ms[P_NUM] = {};
+    int64_t calls[P_NUM] = {};
+    std::vector<hipEvent_t> pool;
+    struct Rec {
+        int id;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    size_t next = 0;
+    hipEvent_t get() {
+        if (next == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[next++];
+    }
+};
+Profiler g_prof;
+
+struct ProfScope {
+    hipStream_t st;
+    int id;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(int id_, hipStream_t st_) : st(st_), id(id_) {
+        if (!g_prof.on) return;
+        a = g_prof.get();
+        b = g_prof.get();
+        if (a && b) (void)hipEventRecord(a, st);
+    }
+    ~ProfScope() {
+        if (!a || !b) return;
+        (void)hipEventRecord(b, st);
+        g_prof.pending.push_back({id, a, b});
+    }
+};
+
+// after a stream synchronize: fold the finished intervals into the totals
+void prof_resolve() {
+    if (!g_prof.on) return;
+    for (auto &r : g_prof.pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            g_prof.ms[r.id] += ms;
+            g_prof.calls[r.id] += 1;
+        }
+    }
+    g_prof.pending.clear();
+    g_prof.next = 0;
+}
+
+#define PROF_CAT2(a, b) a##b
+#define PROF_CAT(a, b) PROF_CAT2(a, b)
+#define PROF(id) ProfScope PROF_CAT(prof_scope_, __LINE__)((id), st)
+
 struct RunOut {
     int n, max_dim;
     float t_eff, r_enc;
@@ -217,6 +386,7 @@ struct RunOut {
 rips_status read_scalars(DevCtx &C, Scalars *d_scal, hipStream_t st) {
     HIP_TRY(hipMemcpyAsync(C.host_scal, d_scal, sizeof(Scalars), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    prof_resolve();
     return RIPS_OK;
 }
 
@@ -248,17 +418,29 @@ rips_status prepare(DevCtx &C, const float *d_in, int n, int m, int jmax, float 
     const int stride = n + 1;
     HIP_TRY(C.ensure(B_BINOM, (size_t)(jmax + 1) * stride * 8, &q));
     P.B = as<u64>(q);
-    launch_binom(P.B, stride, n, jmax, st);
+    {
+        PROF(P_TABLES);
+        launch_binom(P.B, stride, n, jmax, st);
+    }
     HIP_TRY(C.ensure(B_INV, (size_t)p * 4, &q));
     P.inv = as<u32>(q);
-    launch_inverse(P.inv, p, st);
+    {
+        PROF(P_TABLES);
+        launch_inverse(P.inv, p, st);
+    }
     HIP_TRY(C.ensure(B_D, (size_t)n * n * 4, &q));
     P.D = as<float>(q);
     HIP_TRY(C.ensure(B_SCAL, sizeof(Scalars), &q));
     P.scal = as<Scalars>(q);
     launch_init_scalars(P.scal, st);
-    launch_dist(d_in, n, m, P.D, &P.scal->bad, st);
-    launch_threshold(P.D, n, t, P.scal, st);
+    {
+        PROF(P_DIST);
+        launch_dist(d_in, n, m, P.D, &P.scal->bad, st);
+    }
+    {
+        PROF(P_THRESHOLD);
+        launch_threshold(P.D, n, t, P.scal, st);
+    }
     const int64_t all_edges = (int64_t)n * (n - 1) / 2;
     int64_t cap = C.hint_edges > 0 ? C.hint_edges : std::min<int64_t>(all_edges, 1 << 16);
     if (cap > all_edges) cap = all_edges;
@@ -274,7 +456,10 @@ rips_status prepare(DevCtx &C, const float *d_in, int n, int m, int jmax, float 
         HIP_TRY(C.ensure(B_E_B, (size_t)cap * 4, &q));
         P.E.b = as<int>(q);
         hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, &P.scal->edges, 0ull);
-        launch_edges(P.D, n, P.scal, P.E, cap, P.deg, st);
+        {
+            PROF(P_EDGES);
+            launch_edges(P.D, n, P.scal, P.E, cap, P.deg, st);
+        }
         hipLaunchKernelGGL(k_maxdeg, dim3(1), dim3(256), 0, st, P.deg, n, &P.scal->maxdeg);
         rips_status rs = read_scalars(C, P.scal, st);
         if (rs) return rs;
@@ -294,6 +479,7 @@ rips_status prepare(DevCtx &C, const float *d_in, int n, int m, int jmax, float 
         P.off = as<int>(q);
         HIP_TRY(C.ensure(B_NBR, (size_t)(2 * P.nedges + 1) * 4, &q));
         P.nbr = as<int>(q);
+        PROF(P_CSR);
         launch_csr(P.D, n, P.scal, P.deg, P.off, P.nbr, st);
     }
     P.ctx.d.D = P.D;
@@ -377,7 +563,10 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
     };
     if ((rs = ensure_bars(0, n))) return rs;
     launch_reset_dim(P.scal, st);
-    launch_h0(P.E, P.scal, n, W, bars[0], nwords, st);
+    {
+        PROF(P_H0);
+        launch_h0(P.E, P.scal, n, W, bars[0], nwords, st);
+    }
     if ((rs = read_scalars(C, P.scal, st))) return rs;
     if (getenv("RIPS_DEBUG") && n <= 64) {
         // diagnostics: H0 internals of small inputs
@@ -424,7 +613,10 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
                 HIP_TRY(C.ensure(B_LIST_DIAM + k, (size_t)cap * 4, &q));
                 cand.diam = as<float>(q);
                 hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, &P.scal->list, 0ull);
-                launch_expand(G, P.ctx, k, prev_list, prev_count, P.scal, cand, cap, false, st);
+                {
+                    PROF(P_EXPAND1 + k - 1);
+                    launch_expand(G, P.ctx, k, prev_list, prev_count, P.scal, cand, cap, false, st);
+                }
                 if ((rs = read_scalars(C, P.scal, st))) return rs;
                 if ((int64_t)C.host_scal->list <= cap) break;
                 cap = (int64_t)C.host_scal->list;
@@ -443,7 +635,10 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         surv.j = as<int>(q);
         HIP_TRY(C.ensure(B_SURV_TAPP, (size_t)ncand, &q));
         surv.tapp = as<uint8_t>(q);
-        launch_filter(G, P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv, st);
+        {
+            PROF(P_FILTER1 + k - 1);
+            launch_filter(G, P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv, st);
+        }
         if ((rs = read_scalars(C, P.scal, st))) return rs;
         const int64_t S = std::min<int64_t>((int64_t)C.host_scal->survivors, ncand);
         if (S > 0x7fffffff) return fail(RIPS_E_CAPACITY, "too many columns");
@@ -476,7 +671,10 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         HIP_TRY(C.ensure(B_SORT_V1, (size_t)S * 4, &q));
         sb.val[1] = as<u32>(q);
         const int lo_bytes = bytes_for((uint64_t)choose_i64(n, k + 1));
-        launch_sort_columns(surv, P.scal, sb, lo_bytes, cols, st);
+        {
+            PROF(P_SORT1 + k - 1);
+            launch_sort_columns(surv, P.scal, sb, lo_bytes, cols, st);
+        }
         // ---- reduction
         const int slot = k & 1;
         PivotHash ph;
@@ -493,46 +691,57 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         V.len = as<int>(q);
         HIP_TRY(C.ensure(B_V_PIV, (size_t)S * 4, &q));
         V.pivcoef = as<u32>(q);
-        int64_t vcap = std::max<int64_t>(C.hint_v, 4 * S + 4096);
+        int64_t vcap = std::max<int64_t>(C.hint_v, 64 * S + 65536);
         if ((rs = ensure_bars(k, S))) return rs;
         const int bound = P.sparse ? P.maxdeg : n;
-        uint32_t capR = next_pow2(std::max<uint64_t>(256, 4ull * (uint64_t)bound));
-        uint32_t capV = 1024;
-        int use_lds = reduce_lds_bytes(capR, capV) <= 150 * 1024;
+        // working column: in LDS (as large as the workgroup's share allows),
+        // with a global table for the columns that outgrow it
+        const size_t lds_budget = C.lds_per_block > 32768 ? (size_t)C.lds_per_block - 24576 : 0;
+        uint32_t capR = 1u << 16;
+        while (capR > 256 && reduce_lds_bytes(capR) > lds_budget) capR >>= 1;
+        const int use_lds = reduce_lds_bytes(capR) <= lds_budget ? 1 : 0;
+        uint32_t capRg = next_pow2(std::max<uint64_t>(1u << 16, 64ull * (uint64_t)bound));
         for (int attempt = 0;; ++attempt) {
-            if (attempt > 8) return fail(RIPS_E_CAPACITY, "reduction scratch kept overflowing");
+            if (attempt > 6) return fail(RIPS_E_CAPACITY, "reduction scratch kept overflowing");
             HIP_TRY(C.ensure(B_V_IDX, (size_t)vcap * 8, &q));
             V.idx = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_V_DIAM, (size_t)vcap * 4, &q));
+            V.diam = as<float>(q);
             HIP_TRY(C.ensure(B_V_COEF, (size_t)vcap * 4, &q));
             V.coef = as<u32>(q);
             V.cap = vcap;
-            WorkHash Rg{nullptr, nullptr, nullptr, capR - 1}, Vg{nullptr, nullptr, nullptr, capV - 1};
-            if (!use_lds) {
-                HIP_TRY(C.ensure(B_WR_KEYS, (size_t)capR * 8, &q));
-                Rg.keys = as<int64_t>(q);
-                HIP_TRY(C.ensure(B_WR_COEF, (size_t)capR * 4, &q));
-                Rg.coef = as<u32>(q);
-                HIP_TRY(C.ensure(B_WR_DIAM, (size_t)capR * 4, &q));
-                Rg.diam = as<float>(q);
-                HIP_TRY(C.ensure(B_WV_KEYS, (size_t)capV * 8, &q));
-                Vg.keys = as<int64_t>(q);
-                HIP_TRY(C.ensure(B_WV_COEF, (size_t)capV * 4, &q));
-                Vg.coef = as<u32>(q);
-                HIP_TRY(C.ensure(B_WV_DIAM, (size_t)capV * 4, &q));
-                Vg.diam = as<float>(q);
-            }
+            WorkCol Rl{nullptr, nullptr, nullptr, nullptr, nullptr, capR - 1};
+            WorkCol Rg{nullptr, nullptr, nullptr, nullptr, nullptr, capRg - 1};
+            HIP_TRY(C.ensure(B_WR_KEYS, (size_t)capRg * 8, &q));
+            Rg.keys = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_WR_COEF, (size_t)capRg * 4, &q));
+            Rg.coef = as<u32>(q);
+            HIP_TRY(C.ensure(B_WR_DIAM, (size_t)capRg * 4, &q));
+            Rg.diam = as<float>(q);
+            HIP_TRY(C.ensure(B_WR_SLOTS, (size_t)capRg * 4, &q));
+            Rg.slots = as<u32>(q);
             launch_fill_i64(ph.keys, phcap, kEmpty, st);
             launch_reset_dim(P.scal, st);
-            launch_reduce(P.ctx, k, p, P.inv, cols, (int)S, ph, V, Rg, Vg, use_lds, capR, capV,
-                          P.scal, bars[k], st);
-            HIP_TRY(hipGetLastError());
+            ReduceJob<DistFull> J;
+            J.c = P.ctx;
+            J.k = k;
+            J.p = p;
+            J.inv = P.inv;
+            J.cols = cols;
+            J.ncols = (int)S;
+            J.ph = ph;
+            J.V = V;
+            J.vcount = &P.scal->vcount;
+            J.bars = bars[k];
+            {
+                PROF(P_REDUCE1 + k - 1);
+                HIP_TRY(launch_reduce(J, Rl, Rg, use_lds, P.scal, st));
+            }
             if ((rs = read_scalars(C, P.scal, st))) return rs;
             const int status = C.host_scal->status;
             if (status == 0) break;
             if (status == 1) {
-                use_lds = 0;
-                capR = capR < (1u << 26) ? capR * 8 : capR;
-                capV = capV < (1u << 24) ? capV * 8 : capV;
+                capRg = capRg < (1u << 27) ? capRg * 4 : capRg;
             } else if (status == 2) {
                 vcap *= 4;
             } else {
@@ -540,6 +749,14 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             }
         }
         if ((int64_t)C.host_scal->vcount > C.hint_v) C.hint_v = (int64_t)C.host_scal->vcount;
+        if (getenv("RIPS_DEBUG"))
+            fprintf(stderr,
+                    "[rips reduce d%d] cols=%lld lds=%d capR=%u capRg=%u lds_per_block=%d "
+                    "global_cols=%llu R_entries=%llu maxR_stored=%llu maxR=%llu additions=%llu\n",
+                    k, (long long)S, use_lds, capR, capRg, C.lds_per_block,
+                    C.host_scal->stat[kStatGlobalCols], C.host_scal->vcount,
+                    C.host_scal->stat[kStatMaxV], C.host_scal->stat[kStatMaxR],
+                    C.host_scal->stat[kStatAdditions]);
         o.count[k] = C.host_scal->nbars;
         o.stats[k].emergent = (int64_t)C.host_scal->stat[kStatEmergent];
         o.stats[k].reduced = (int64_t)C.host_scal->stat[kStatReduced];
@@ -564,6 +781,195 @@ BarBuf internal_bars(DevCtx &C, int d) {
 
 // set the device "nbars" scalar before an emit
 __global__ void k_set_nbars(Scalars *s, int64_t v) { s->nbars = v; }
+
+rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_offsets,
+                                int32_t B, int32_t dim, int32_t n_max, int32_t max_dim,
+                                float threshold, uint32_t p, rips_batch_out *out, void *hip_stream,
+                                bool *retry) {
+    DevCtx *C = &Cref;
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int D1 = max_dim + 1;
+    const bool lds_d = n_max <= kBatchLdsN;
+    int grid = std::max(1, C->num_cus);
+    if (grid > B) grid = B;
+    const int64_t npairs = (int64_t)n_max * (n_max - 1) / 2;
+    const int64_t col_stride = npairs + n_max + 16;
+    int64_t ph_stride = 64;
+    while (ph_stride < 2 * col_stride + 64) ph_stride <<= 1;
+    const int64_t v_stride = std::max<int64_t>(C->batch_vstride, std::max<int64_t>(1 << 18, 4 * col_stride));
+    const int64_t rg_stride = std::max<int64_t>(
+        C->batch_rgstride, next_pow2(std::max<uint64_t>(1u << 17, 64ull * (uint64_t)n_max)));
+    const int64_t st_stride = 2 * (int64_t)n_max + npairs + 16;
+    const int64_t d_stride = lds_d ? npairs + 4 : (int64_t)n_max * n_max + 4;
+    const int64_t bits_stride = npairs / 32 + 2;
+    const int64_t G = grid;
+    void *q;
+    BatchArgs A;
+    memset(&A, 0, sizeof(A));
+    A.X = d_points;
+    A.offsets = d_offsets;
+    A.B = B;
+    A.m = dim;
+    A.max_dim = max_dim;
+    A.threshold = threshold;
+    A.p = p;
+    A.nmax = n_max;
+#define ENS(id, bytes, field, T)                                                                   \
+    do {                                                                                           \
+        HIP_TRY(C->ensure(id, (size_t)(bytes), &q));                                               \
+        field = as<T>(q);                                                                          \
+    } while (0)
+    ENS(BB_BINOM, (size_t)4 * (n_max + 1) * 8, A.binom.t, const u64);
+    A.binom.stride = n_max + 1;
+    u32 *inv;
+    ENS(BB_INV, (size_t)p * 4, inv, u32);
+    A.inv = inv;
+    ENS(BB_DG, G * d_stride * 4, A.Dg, float);
+    A.d_stride = d_stride;
+    ENS(BB_C_IDX0, G * col_stride * 8, A.c_idx0, int64_t);
+    ENS(BB_C_IDX1, G * col_stride * 8, A.c_idx1, int64_t);
+    ENS(BB_C_DM0, G * col_stride * 4, A.c_dm0, float);
+    ENS(BB_C_DM1, G * col_stride * 4, A.c_dm1, float);
+    ENS(BB_C_J0, G * col_stride * 4, A.c_j0, int);
+    ENS(BB_C_J1, G * col_stride * 4, A.c_j1, int);
+    ENS(BB_C_T0, G * col_stride, A.c_t0, uint8_t);
+    ENS(BB_C_T1, G * col_stride, A.c_t1, uint8_t);
+    ENS(BB_S_LO0, G * col_stride * 8, A.s_lo0, u64);
+    ENS(BB_S_LO1, G * col_stride * 8, A.s_lo1, u64);
+    ENS(BB_S_HI0, G * col_stride * 4, A.s_hi0, u32);
+    ENS(BB_S_HI1, G * col_stride * 4, A.s_hi1, u32);
+    ENS(BB_S_V0, G * col_stride * 4, A.s_v0, u32);
+    ENS(BB_S_V1, G * col_stride * 4, A.s_v1, u32);
+    A.col_stride = col_stride;
+    ENS(BB_PH_KEYS, G * ph_stride * 8, A.ph_keys, int64_t);
+    ENS(BB_PH_VALS, G * ph_stride * 4, A.ph_vals, int32_t);
+    A.ph_stride = ph_stride;
+    ENS(BB_V_OFF, G * col_stride * 8, A.v_off, int64_t);
+    ENS(BB_V_LEN, G * col_stride * 4, A.v_len, int);
+    ENS(BB_V_PIV, G * col_stride * 4, A.v_piv, u32);
+    ENS(BB_V_IDX, G * v_stride * 8, A.v_idx, int64_t);
+    ENS(BB_V_DIAM, G * v_stride * 4, A.v_diam, float);
+    ENS(BB_V_COEF, G * v_stride * 4, A.v_coef, u32);
+    A.v_stride = v_stride;
+    ENS(BB_V_COUNT, G * 8, A.v_count, unsigned long long);
+    ENS(BB_BITS, G * bits_stride * 4, A.bits_g, u32);
+    A.bits_stride = bits_stride;
+    ENS(BB_RG_KEYS, G * rg_stride * 8, A.rg_keys, int64_t);
+    ENS(BB_RG_COEF, G * rg_stride * 4, A.rg_coef, u32);
+    ENS(BB_RG_DIAM, G * rg_stride * 4, A.rg_diam, float);
+    ENS(BB_RG_SLOTS, G * rg_stride * 4, A.rg_slots, u32);
+    A.rg_stride = rg_stride;
+    ENS(BB_ST_B, G * st_stride * 4, A.st_b, float);
+    ENS(BB_ST_D, G * st_stride * 4, A.st_d, float);
+    ENS(BB_ST_BS, G * st_stride * 8, A.st_bs, int64_t);
+    ENS(BB_ST_DS, G * st_stride * 8, A.st_ds, int64_t);
+    A.st_stride = st_stride;
+    const int64_t ucap = std::max<int64_t>(out->cap, 1);
+    ENS(BB_UB, ucap * 4, A.ub, float);
+    ENS(BB_UD, ucap * 4, A.ud, float);
+    ENS(BB_UBS, ucap * 8, A.ubs, int64_t);
+    ENS(BB_UDS, ucap * 8, A.uds, int64_t);
+    A.ucap = out->cap;
+    ENS(BB_SEG_START, (int64_t)B * D1 * 8, A.seg_start, int64_t);
+    ENS(BB_SEG_COUNT, (int64_t)B * D1 * 8, A.seg_count, int64_t);
+    if (out->stats) A.stats = out->stats;
+    else ENS(BB_STATS, (int64_t)B * D1 * sizeof(rips_dim_stats), A.stats, rips_dim_stats);
+    if (out->threshold_used) A.t_used = out->threshold_used;
+    else ENS(BB_TUSED, (int64_t)B * 4, A.t_used, float);
+    SortBufs lpt;
+    ENS(BB_LPT_LO0, (int64_t)B * 8, lpt.lo[0], u64);
+    ENS(BB_LPT_LO1, (int64_t)B * 8, lpt.lo[1], u64);
+    ENS(BB_LPT_HI0, (int64_t)B * 4, lpt.hi[0], u32);
+    ENS(BB_LPT_HI1, (int64_t)B * 4, lpt.hi[1], u32);
+    ENS(BB_LPT_V0, (int64_t)B * 4, lpt.val[0], u32);
+    ENS(BB_LPT_V1, (int64_t)B * 4, lpt.val[1], u32);
+    int *order;
+    ENS(BB_ORDER, (int64_t)B * 4, order, int);
+    A.order = order;
+    struct BatchScal {
+        unsigned long long queue, ucount;
+        int64_t total;
+        int status;
+    };
+    BatchScal *bs;
+    ENS(BB_SCAL, sizeof(BatchScal), bs, BatchScal);
+    A.queue = &bs->queue;
+    A.ucount = &bs->ucount;
+    A.status = &bs->status;
+#undef ENS
+    HIP_TRY(batched_prepare(lds_d, n_max));
+    // the graph is keyed by every argument and buffer address it captures
+    std::vector<unsigned char> key(sizeof(A) + sizeof(lpt) + 6 * sizeof(void *) + 16);
+    {
+        unsigned char *kp = key.data();
+        memcpy(kp, &A, sizeof(A));
+        kp += sizeof(A);
+        memcpy(kp, &lpt, sizeof(lpt));
+        kp += sizeof(lpt);
+        const void *ptrs[6] = {out->birth, out->death, out->birth_simplex, out->death_simplex,
+                               out->bar_offsets, (void *)(intptr_t)grid};
+        memcpy(kp, ptrs, sizeof(ptrs));
+        kp += sizeof(ptrs);
+        memcpy(kp, &out->cap, 8);
+        memcpy(kp + 8, &lds_d, 1);
+    }
+    if (!C->batch_exec || C->batch_key != key) {
+        if (C->batch_exec) {
+            (void)hipGraphExecDestroy(C->batch_exec);
+            C->batch_exec = nullptr;
+        }
+        // tables are built outside the graph (they depend only on n_max, p)
+        launch_binom((u64 *)A.binom.t, A.binom.stride, n_max, 3, st);
+        launch_inverse(inv, p, st);
+        HIP_TRY(hipStreamSynchronize(st));
+        hipGraph_t graph;
+        HIP_TRY(hipStreamBeginCapture(C->capture_stream, hipStreamCaptureModeThreadLocal));
+        launch_batched(A, lds_d, grid, lpt, C->capture_stream);
+        launch_batch_finalize(A, out->bar_offsets, &bs->total, out->cap, out->birth, out->death,
+                              out->birth_simplex, out->death_simplex, C->capture_stream);
+        HIP_TRY(hipStreamEndCapture(C->capture_stream, &graph));
+        hipError_t e = hipGraphInstantiate(&C->batch_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            C->batch_exec = nullptr;
+            return fail(RIPS_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+        }
+        C->batch_key = key;
+    }
+    {
+        PROF(P_BATCHED);
+        HIP_TRY(hipGraphLaunch(C->batch_exec, st));
+    }
+    struct {
+        int64_t total;
+        int status;
+    } hs;
+    HIP_TRY(hipMemcpyAsync(&hs.total, &bs->total, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&hs.status, &bs->status, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    prof_resolve();
+    out->needed = hs.total;
+    if (hs.status & 16) return fail(RIPS_E_INVALID_ARG, "a cloud is empty or larger than n_max");
+    if (hs.status & 4) return fail(RIPS_E_NONFINITE, "input holds NaN/Inf");
+    if (hs.status & 2) {
+        // column store too small for some cloud: grow and run again
+        C->batch_vstride = v_stride * 4;
+        if (C->batch_vstride > (1ll << 26)) return fail(RIPS_E_CAPACITY, "column store overflow");
+        *retry = true;
+        return RIPS_E_CAPACITY;
+    }
+    if (hs.status & 1) {
+        // a working column outgrew the global table: grow it and run again
+        C->batch_rgstride = rg_stride * 4;
+        if (C->batch_rgstride > (1ll << 26)) return fail(RIPS_E_CAPACITY, "working column overflow");
+        *retry = true;
+        return RIPS_E_CAPACITY;
+    }
+    if (hs.status & 8) return fail(RIPS_E_HIP, "batched reduction exceeded its addition bound");
+    if (hs.total > out->cap) return fail(RIPS_E_CAPACITY, "bar capacity too small");
+    return RIPS_OK;
+}
+
 
 } // namespace
 
@@ -616,11 +1022,13 @@ rips_status rips_barcode_device(const float *d_data, int64_t n, int32_t dim, int
     for (int d = 0; d <= max_dim; ++d) {
         BarBuf dst{out->birth + d * out->cap, out->death + d * out->cap,
                    out->birth_simplex + d * out->cap, out->death_simplex + d * out->cap};
+        PROF(P_EMIT);
         hipLaunchKernelGGL(k_set_nbars, dim3(1), dim3(1), 0, st, scal, o.count[d]);
         launch_emit(internal_bars(*C, d), scal, d > 0 ? 1 : 0, dst, st);
     }
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
+    prof_resolve();
     return RIPS_OK;
 }
 
@@ -789,5 +1197,49 @@ rips_status rips_simplex_counts_device(const float *d_data, int64_t n, int32_t d
     }
     return RIPS_OK;
 }
+
+rips_status rips_barcode_batched_device(const float *d_points, const int64_t *d_offsets, int32_t B,
+                                        int32_t dim, int32_t n_max, int32_t max_dim,
+                                        float threshold, uint32_t p, rips_batch_out *out,
+                                        void *hip_stream) {
+    g_err.clear();
+    if (!d_points || !d_offsets || !out || !out->bar_offsets)
+        return fail(RIPS_E_INVALID_ARG, "null pointer");
+    if (B < 1 || B > (1 << 24)) return fail(RIPS_E_INVALID_ARG, "B out of range");
+    if (dim < 1) return fail(RIPS_E_INVALID_ARG, "batched clouds are point clouds (dim >= 1)");
+    if (n_max < 1 || n_max > kBatchMaxN)
+        return fail(RIPS_E_INVALID_ARG, "n_max must be in [1, 2048]");
+    if (max_dim < 0 || max_dim > 1) return fail(RIPS_E_INVALID_ARG, "batched max_dim is 0 or 1");
+    if (std::isnan(threshold)) return fail(RIPS_E_INVALID_ARG, "threshold is NaN");
+    if (!is_prime_u32(p) || p >= 65536) return fail(RIPS_E_NOT_PRIME, "p must be a prime < 65536");
+    DevCtx *C;
+    rips_status rs;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    for (int attempt = 0;; ++attempt) {
+        bool retry = false;
+        rs = batched_once(*C, d_points, d_offsets, B, dim, n_max, max_dim, threshold, p, out,
+                          hip_stream, &retry);
+        if (!retry || attempt > 8) return rs;
+    }
+}
+
+void rips_profile_enable(int on) {
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.pending.clear();
+    g_prof.next = 0;
+    if (on) {
+        for (int i = 0; i < P_NUM; ++i) {
+            g_prof.ms[i] = 0.0;
+            g_prof.calls[i] = 0;
+        }
+    }
+    g_prof.on = on != 0;
+}
+
+int rips_profile_count(void) { return P_NUM; }
+const char *rips_profile_name(int i) { return prof_name(i); }
+double rips_profile_ms(int i) { return (i >= 0 && i < P_NUM) ? g_prof.ms[i] : 0.0; }
+int64_t rips_profile_calls(int i) { return (i >= 0 && i < P_NUM) ? g_prof.calls[i] : 0; }
 
 } // extern "C"

@@ -1,0 +1,625 @@
+// rips_batched.hip -- many point clouds of uneven sizes in one persistent
+// launch. Each workgroup takes the next cloud from a queue ordered by
+// decreasing size (longest processing time first) and runs the whole path on
+// it: distances (packed lower triangle in LDS for n <= 256, a full matrix in
+// its global scratch otherwise), enclosing radius, H0 (Boruvka + elder rule),
+// the enumeration / apparent-pair filter of dimension 1, the column sort and
+// the Z/p reduction (reduce_columns). Bars go to an unordered buffer with one
+// segment per (cloud, dimension); a final pass lays them out in cloud order.
+#include "../../include/rips.h"
+#include "rips_batched.hpp"
+
+namespace rips {
+
+constexpr int kBT = 256;         // threads per workgroup
+constexpr int kBatchG = 16;      // lanes per candidate in the filter
+constexpr int kBatchCapR = 2048; // LDS working-column slots
+
+struct BatchShared {
+    int cloud, n, nsurv, nbars0, flag, m;
+    float t;
+    unsigned long long mcount;
+    unsigned long long cnt[4];
+    int w[kBT / kWave + 1];
+};
+
+__device__ __forceinline__ void pair_of(int64_t e, int *a, int *b) {
+    int x = (int)((1.0 + sqrt(1.0 + 8.0 * (double)e)) * 0.5);
+    while ((int64_t)x * (x - 1) / 2 > e) --x;
+    while ((int64_t)(x + 1) * x / 2 <= e) ++x;
+    *a = x;
+    *b = (int)(e - (int64_t)x * (x - 1) / 2);
+}
+
+__device__ __forceinline__ u64 bkey(float d, u32 idx) {
+    return ((u64)__float_as_uint(d) << 32) | (u64)(0xffffffffu - idx);
+}
+
+// d(i, j) for i != j: coordinates in increasing order, each product and sum
+// rounded to float32, correctly rounded square root
+__device__ __forceinline__ float point_dist(const float *X, int m, int i, int j) {
+    float s = 0.0f;
+    for (int c = 0; c < m; ++c) {
+        const float t = X[i * m + c] - X[j * m + c];
+        const float sq = t * t;
+        s = s + sq;
+    }
+    return __builtin_sqrtf(s);
+}
+
+template <class Dist>
+struct CloudDist;
+
+template <>
+struct CloudDist<DistPacked> {
+    static __device__ DistPacked make(float *lds, float *, int n) { return DistPacked{lds, n}; }
+};
+template <>
+struct CloudDist<DistFull> {
+    static __device__ DistFull make(float *, float *g, int n) { return DistFull{g, n}; }
+};
+
+// One cloud by one workgroup. kLdsD: distances in LDS (packed) for the
+// enumeration and H0 phases, then copied to global for the reduction.
+template <class Dist>
+__device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, BatchShared &Sh,
+                            RedShared<kBT> &RS, SortShared<kBT> &SS) {
+    constexpr bool kLds = std::is_same<Dist, DistPacked>::value;
+    const int tid = threadIdx.x, lane = lane_id();
+    const int wg = blockIdx.x;
+    const int64_t o0 = A.offsets[b];
+    const int64_t nn = A.offsets[b + 1] - o0;
+    const int D1 = A.max_dim + 1;
+    if (nn < 1 || nn > A.nmax) {
+        // rejected by the order pass (status bit 16); publish empty segments
+        if (threadIdx.x == 0)
+            for (int d = 0; d < D1; ++d) {
+                A.seg_start[(int64_t)b * D1 + d] = 0;
+                A.seg_count[(int64_t)b * D1 + d] = 0;
+            }
+        __syncthreads();
+        return;
+    }
+    const int n = (int)nn;
+    const int m = A.m;
+    const float *X = A.X + o0 * m;
+    const int64_t npairs = (int64_t)n * (n - 1) / 2;
+    float *Dl = (float *)smem;                       // packed D in LDS (kLds)
+    float *Dgw = A.Dg + (int64_t)wg * A.d_stride;    // this workgroup's global D
+    // ---- distances
+    bool fin = true;
+    if (kLds) {
+        for (int64_t e = tid; e < npairs; e += kBT) {
+            int a, c;
+            pair_of(e, &a, &c);
+            const float d = point_dist(X, m, a, c);
+            fin = fin && isfinite(d);
+            Dl[e] = d;
+        }
+    } else {
+        for (int64_t q = tid; q < (int64_t)n * n; q += kBT) {
+            const int i = (int)(q / n), j = (int)(q % n);
+            const float d = i == j ? 0.0f : point_dist(X, m, i, j);
+            fin = fin && isfinite(d);
+            Dgw[q] = d;
+        }
+    }
+    if (!fin) atomicOr(A.status, 4);
+    if (tid == 0) {
+        Sh.flag = 0x7f800000; // enclosing radius as float bits
+        for (int q = 0; q < 4; ++q) Sh.cnt[q] = 0;
+    }
+    gsync();
+    const Dist dist = CloudDist<Dist>::make(Dl, Dgw, n);
+    // ---- enclosing radius min_x max_y d(x, y)
+    for (int i = tid; i < n; i += kBT) {
+        float mx = 0.0f;
+        for (int j = 0; j < n; ++j)
+            if (j != i) mx = fmaxf(mx, dist(i, j));
+        atomicMin((unsigned *)&Sh.flag, __float_as_uint(mx));
+    }
+    __syncthreads();
+    const float renc = n > 1 ? __uint_as_float((u32)Sh.flag) : 0.0f;
+    const float t = fminf(A.threshold, renc);
+    // ---- H0: Boruvka on the pairs <= t, union-find state in LDS
+    const int nm = A.nmax;
+    const int64_t npairs_max = (int64_t)nm * (nm - 1) / 2;
+    unsigned char *after = smem + (kLds ? ((size_t)npairs_max * 4 + 15) / 16 * 16 : 0);
+    u64 *best = (u64 *)after;
+    int *comp = (int *)(best + nm);
+    int *hook = comp + nm;
+    u32 *bits = kLds ? (u32 *)(hook + nm) : A.bits_g + (int64_t)wg * A.bits_stride;
+    const int64_t nwords = npairs / 32 + 1;
+    u64 *mst = A.s_lo0 + (int64_t)wg * A.col_stride;
+    for (int v = tid; v < n; v += kBT) st(&comp[v], v);
+    for (int64_t q = tid; q < nwords; q += kBT) bits[q] = 0;
+    if (tid == 0) Sh.mcount = 0;
+    __syncthreads();
+    for (int round = 0; round < 40; ++round) {
+        for (int v = tid; v < n; v += kBT) st(&best[v], ~0ull);
+        __syncthreads();
+        for (int64_t e = tid; e < npairs; e += kBT) {
+            int a, c;
+            pair_of(e, &a, &c);
+            const float d = dist(a, c);
+            if (!(d <= t)) continue;
+            const int ca = ld(&comp[a]), cb = ld(&comp[c]);
+            if (ca != cb) {
+                const u64 key = bkey(d, (u32)e);
+                atomicMin(&best[ca], key);
+                atomicMin(&best[cb], key);
+            }
+        }
+        if (tid == 0) Sh.flag = 0;
+        __syncthreads();
+        for (int v = tid; v < n; v += kBT) {
+            const int cv = ld(&comp[v]);
+            int h = cv;
+            const u64 key = ld(&best[v]);
+            if (cv == v && key != ~0ull) {
+                int a, c;
+                pair_of(0xffffffffu - (u32)(key & 0xffffffffu), &a, &c);
+                const int ca = ld(&comp[a]), cb = ld(&comp[c]);
+                const int other = ca == v ? cb : ca;
+                const bool mutual = ld(&best[other]) == key;
+                if (!mutual || v > other) {
+                    h = other;
+                    const unsigned long long slot = atomicAdd(&Sh.mcount, 1ull);
+                    if (slot < (unsigned long long)n) mst[slot] = key;
+                    Sh.flag = 1;
+                }
+            }
+            st(&hook[v], h);
+        }
+        gsync();
+        if (!Sh.flag) break;
+        for (int v = tid; v < n; v += kBT) st(&comp[v], ld(&hook[v]));
+        for (int jump = 0; jump < 40; ++jump) {
+            __syncthreads();
+            if (tid == 0) Sh.flag = 0;
+            __syncthreads();
+            for (int v = tid; v < n; v += kBT) {
+                const int c = ld(&comp[v]), cc = ld(&comp[c]);
+                if (c != cc) {
+                    st(&comp[v], cc);
+                    Sh.flag = 1;
+                }
+            }
+            __syncthreads();
+            if (!Sh.flag) break;
+        }
+    }
+    gsync();
+    const int mm = (int)min(Sh.mcount, (unsigned long long)(n > 0 ? n - 1 : 0));
+    SortBufs sb;
+    sb.lo[0] = mst;
+    sb.lo[1] = A.s_lo1 + (int64_t)wg * A.col_stride;
+    sb.hi[0] = A.s_hi0 + (int64_t)wg * A.col_stride;
+    sb.hi[1] = A.s_hi1 + (int64_t)wg * A.col_stride;
+    sb.val[0] = A.s_v0 + (int64_t)wg * A.col_stride;
+    sb.val[1] = A.s_v1 + (int64_t)wg * A.col_stride;
+    for (int e = tid; e < mm; e += kBT) {
+        sb.hi[0][e] = 0;
+        sb.val[0][e] = 0;
+    }
+    gsync();
+    const int cur = block_radix_sort<kBT>(sb, mm, 8, 0, SS);
+    const u64 *keys = sb.lo[cur];
+    // elder rule on wave 0 (parent = comp, maxv = hook arrays)
+    int *parent = comp, *maxv = hook;
+    float *hdeath = (float *)best;          // reuse: n floats
+    int64_t *hds = (int64_t *)(A.st_ds + (int64_t)wg * A.st_stride + A.st_stride - n);
+    for (int v = tid; v < n; v += kBT) {
+        st(&parent[v], v);
+        st(&maxv[v], v);
+        hdeath[v] = -1.0f;
+    }
+    __syncthreads();
+    if (tid < kWave) {
+        for (int base = 0; base < mm; base += kWave) {
+            const int e = base + lane;
+            const bool valid = e < mm;
+            int ra = 0, rb = 0, ma = -1, mb = -1;
+            u32 idx = 0;
+            float dm = 0.0f;
+            if (valid) {
+                const u64 key = keys[e];
+                idx = 0xffffffffu - (u32)(key & 0xffffffffu);
+                dm = __uint_as_float((u32)(key >> 32));
+                int a, c;
+                pair_of(idx, &a, &c);
+                a = min(a, n - 1);
+                c = min(c, n - 1);
+                ra = a;
+                for (int g = 0; g < n && ld(&parent[ra]) != ra; ++g) ra = ld(&parent[ra]);
+                rb = c;
+                for (int g = 0; g < n && ld(&parent[rb]) != rb; ++g) rb = ld(&parent[rb]);
+                ma = ld(&maxv[ra]);
+                mb = ld(&maxv[rb]);
+            }
+            const int cnt = min(kWave, mm - base);
+            int my_loser = 0, my_winner = 0, my_newmax = 0, my_birth = 0;
+            for (int q = 0; q < cnt; ++q) {
+                const int RA = __shfl(ra, q, kWave), RB = __shfl(rb, q, kWave);
+                const int MA = __shfl(ma, q, kWave), MB = __shfl(mb, q, kWave);
+                const int winner = MA > MB ? RA : RB;
+                const int loser = MA > MB ? RB : RA;
+                const int newmax = MA > MB ? MA : MB;
+                if (lane == q) {
+                    my_loser = loser;
+                    my_winner = winner;
+                    my_newmax = newmax;
+                    my_birth = MA > MB ? MB : MA;
+                }
+                if (ra == RA || ra == RB) {
+                    ra = winner;
+                    ma = newmax;
+                }
+                if (rb == RA || rb == RB) {
+                    rb = winner;
+                    mb = newmax;
+                }
+            }
+            if (valid) {
+                st(&parent[my_loser], my_winner);
+                atomicMax(&maxv[my_winner], my_newmax);
+                if (dm > 0.0f) {
+                    hdeath[my_birth] = dm;
+                    hds[my_birth] = (int64_t)idx;
+                }
+                if ((int64_t)idx < npairs) atomicOr(&bits[idx >> 5], 1u << (idx & 31));
+            }
+        }
+    }
+    gsync();
+    for (int v = tid; v < n; v += kBT)
+        if (ld(&parent[v]) == v) {
+            const int bb = ld(&maxv[v]);
+            hdeath[bb] = INFINITY;
+            hds[bb] = -1;
+        }
+    gsync();
+    // H0 bars into the stage, by birth vertex descending
+    float *sb_b = A.st_b + (int64_t)wg * A.st_stride;
+    float *sb_d = A.st_d + (int64_t)wg * A.st_stride;
+    int64_t *sb_bs = A.st_bs + (int64_t)wg * A.st_stride;
+    int64_t *sb_ds = A.st_ds + (int64_t)wg * A.st_stride;
+    {
+        int at = 0, nz = 0, ne = 0;
+        for (int base = 0; base < n; base += kBT) {
+            const int v = n - 1 - (base + tid);
+            const float hd = v >= 0 ? hdeath[v] : -1.0f;
+            const bool has = hd >= 0.0f;
+            int tot;
+            const int ex = block_scan_excl<kBT>(has ? 1 : 0, Sh.w, &tot);
+            if (has) {
+                sb_b[at + ex] = 0.0f;
+                sb_d[at + ex] = hd;
+                sb_bs[at + ex] = v;
+                sb_ds[at + ex] = hds[v];
+                if (isinf(hd)) ++ne;
+                else ++nz;
+            }
+            at += tot;
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            nz += __shfl_xor(nz, off, kWave);
+            ne += __shfl_xor(ne, off, kWave);
+        }
+        if (lane == 0) {
+            atomicAdd(&Sh.cnt[0], (unsigned long long)nz);
+            atomicAdd(&Sh.cnt[1], (unsigned long long)ne);
+        }
+        if (tid == 0) Sh.nbars0 = at;
+    }
+    gsync();
+    if (tid == 0) {
+        rips_dim_stats &s0 = A.stats[(int64_t)b * D1];
+        s0.candidates = n;
+        s0.cleared = 0;
+        s0.apparent_col = 0;
+        s0.apparent_pivot = 0;
+        s0.columns = n;
+        s0.emergent = 0;
+        s0.reduced = 0;
+        s0.additions = 0;
+        s0.bars_nonzero = (int64_t)Sh.cnt[0];
+        s0.essential = (int64_t)Sh.cnt[1];
+        A.t_used[b] = t;
+        Sh.nsurv = 0;
+        Sh.cnt[0] = Sh.cnt[1] = Sh.cnt[2] = Sh.cnt[3] = 0;
+    }
+    __syncthreads();
+    int nb1 = 0;
+    if (A.max_dim >= 1) {
+        // ---- dimension 1: enumeration / apparent-pair filter over the edges
+        Ctx<Dist> c;
+        c.d = dist;
+        c.B = A.binom;
+        c.nb.off = nullptr;
+        c.nb.idx = nullptr;
+        c.n = n;
+        c.t = t;
+        Columns surv{A.c_idx0 + (int64_t)wg * A.col_stride, A.c_dm0 + (int64_t)wg * A.col_stride,
+                     A.c_j0 + (int64_t)wg * A.col_stride, A.c_t0 + (int64_t)wg * A.col_stride};
+        const int lg = tid & (kBatchG - 1);
+        unsigned long long n_clear = 0, n_acol = 0, n_cand = 0;
+        for (int64_t e = tid / kBatchG; e < npairs; e += kBT / kBatchG) {
+            int v[kMaxVerts];
+            pair_of(e, &v[0], &v[1]);
+            const float dm = dist(v[0], v[1]);
+            if (!(dm <= t)) continue;
+            n_cand += (lg == 0);
+            if ((bits[e >> 5] >> (e & 31)) & 1u) {
+                n_clear += (lg == 0);
+                continue;
+            }
+            const int j = group_find_max<kBatchG>(c, v, 1, dm, -1);
+            if (j >= 0 && is_zero_apparent_cofacet(c, v, 1, dm, j)) {
+                n_acol += (lg == 0);
+                continue;
+            }
+            uint8_t tapp = 0;
+            if (j >= 0) {
+                int tv[kMaxVerts];
+                insert_vertex(v, 1, j, tv);
+                tapp = zero_apparent_facet<kBatchG>(c, tv, 2, dm) >= 0 ? 1 : 0;
+            }
+            if (lg == 0) {
+                const int slot = atomicAdd(&Sh.nsurv, 1);
+                if (slot < A.col_stride) {
+                    surv.idx[slot] = e;
+                    surv.diam[slot] = dm;
+                    surv.j[slot] = j;
+                    surv.tapp[slot] = tapp;
+                }
+            }
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            n_clear += __shfl_xor(n_clear, off, kWave);
+            n_acol += __shfl_xor(n_acol, off, kWave);
+            n_cand += __shfl_xor(n_cand, off, kWave);
+        }
+        if (lane == 0) {
+            atomicAdd(&Sh.cnt[0], n_cand);
+            atomicAdd(&Sh.cnt[1], n_clear);
+            atomicAdd(&Sh.cnt[2], n_acol);
+        }
+        gsync();
+        const int S = min(Sh.nsurv, (int)A.col_stride);
+        // ---- sort: diameter descending, then index ascending
+        for (int e = tid; e < S; e += kBT) {
+            sb.lo[0][e] = (u64)surv.idx[e];
+            sb.hi[0][e] = ~__float_as_uint(surv.diam[e]);
+            sb.val[0][e] = (u32)e;
+        }
+        gsync();
+        const int cs = block_radix_sort<kBT>(sb, S, 4, 4, SS);
+        Columns cols{A.c_idx1 + (int64_t)wg * A.col_stride, A.c_dm1 + (int64_t)wg * A.col_stride,
+                     A.c_j1 + (int64_t)wg * A.col_stride, A.c_t1 + (int64_t)wg * A.col_stride};
+        for (int q = tid; q < S; q += kBT) {
+            const u32 e = sb.val[cs][q];
+            cols.idx[q] = surv.idx[e];
+            cols.diam[q] = surv.diam[e];
+            cols.j[q] = surv.j[e];
+            cols.tapp[q] = surv.tapp[e];
+        }
+        // ---- the reduction reads D from global; LDS now holds its working column
+        if (kLds)
+            for (int64_t e = tid; e < npairs; e += kBT) Dgw[e] = Dl[e];
+        u32 phcap = 64;
+        while (phcap < 2u * (u32)S + 64u && (int64_t)phcap < A.ph_stride) phcap <<= 1;
+        PivotHash ph{A.ph_keys + (int64_t)wg * A.ph_stride, A.ph_vals + (int64_t)wg * A.ph_stride,
+                     phcap - 1};
+        for (u32 q = tid; q < phcap; q += kBT) st(&ph.keys[q], kEmpty);
+        if (tid == 0) A.v_count[wg] = 0;
+        gsync();
+        ReduceJob<Dist> J;
+        J.c = c;
+        J.c.d = CloudDist<Dist>::make(Dgw, Dgw, n);
+        J.k = 1;
+        J.p = A.p;
+        J.inv = A.inv;
+        J.cols = cols;
+        J.ncols = S;
+        J.ph = ph;
+        J.V.off = A.v_off + (int64_t)wg * A.col_stride;
+        J.V.len = A.v_len + (int64_t)wg * A.col_stride;
+        J.V.pivcoef = A.v_piv + (int64_t)wg * A.col_stride;
+        J.V.idx = A.v_idx + (int64_t)wg * A.v_stride;
+        J.V.diam = A.v_diam + (int64_t)wg * A.v_stride;
+        J.V.coef = A.v_coef + (int64_t)wg * A.v_stride;
+        J.V.cap = A.v_stride;
+        J.vcount = &A.v_count[wg];
+        J.bars = BarBuf{sb_b + n, sb_d + n, sb_bs + n, sb_ds + n};
+        __shared__ int s_nsl, s_nsg;
+        WorkCol Rl;
+        unsigned char *q = smem;
+        Rl.keys = (int64_t *)q;
+        q += (size_t)kBatchCapR * 8;
+        Rl.coef = (u32 *)q;
+        q += (size_t)kBatchCapR * 4;
+        Rl.diam = (float *)q;
+        q += (size_t)kBatchCapR * 4;
+        Rl.slots = (u32 *)q;
+        Rl.nslots = &s_nsl;
+        Rl.mask = kBatchCapR - 1;
+        WorkCol Rg{A.rg_keys + (int64_t)wg * A.rg_stride, A.rg_coef + (int64_t)wg * A.rg_stride,
+                   A.rg_diam + (int64_t)wg * A.rg_stride, A.rg_slots + (int64_t)wg * A.rg_stride,
+                   &s_nsg, (u32)A.rg_stride - 1};
+        gsync();
+        const int rstat = reduce_columns<kBT>(J, Rl, Rg, RS);
+        if (rstat && tid == 0) atomicOr(A.status, rstat == 1 ? 1 : (rstat == 2 ? 2 : 8));
+        nb1 = RS.nbars;
+        if (tid == 0) {
+            rips_dim_stats &s1 = A.stats[(int64_t)b * D1 + 1];
+            s1.candidates = (int64_t)Sh.cnt[0];
+            s1.cleared = (int64_t)Sh.cnt[1];
+            s1.apparent_col = (int64_t)Sh.cnt[2];
+            s1.apparent_pivot = 0;
+            s1.columns = S;
+            s1.emergent = (int64_t)RS.stat[0];
+            s1.reduced = (int64_t)RS.stat[1];
+            s1.additions = (int64_t)RS.stat[2];
+            s1.bars_nonzero = (int64_t)RS.stat[3];
+            s1.essential = (int64_t)RS.stat[4];
+        }
+    }
+    // ---- publish: one segment per dimension in the unordered buffer
+    const int nb0 = Sh.nbars0;
+    __shared__ unsigned long long s_base;
+    if (tid == 0) s_base = atomicAdd(A.ucount, (unsigned long long)(nb0 + nb1));
+    gsync();
+    const int64_t base = (int64_t)s_base;
+    const bool fits = base + nb0 + nb1 <= A.ucap;
+    for (int q = tid; q < nb0 && fits; q += kBT) {
+        A.ub[base + q] = sb_b[q];
+        A.ud[base + q] = sb_d[q];
+        A.ubs[base + q] = sb_bs[q];
+        A.uds[base + q] = sb_ds[q];
+    }
+    // dimension 1: column order is youngest first, the canonical order its reverse
+    for (int q = tid; q < nb1 && fits; q += kBT) {
+        const int src = n + nb1 - 1 - q;
+        A.ub[base + nb0 + q] = sb_b[src];
+        A.ud[base + nb0 + q] = sb_d[src];
+        A.ubs[base + nb0 + q] = sb_bs[src];
+        A.uds[base + nb0 + q] = sb_ds[src];
+    }
+    if (tid == 0) {
+        A.seg_start[(int64_t)b * D1] = base;
+        A.seg_count[(int64_t)b * D1] = nb0;
+        if (D1 > 1) {
+            A.seg_start[(int64_t)b * D1 + 1] = base + nb0;
+            A.seg_count[(int64_t)b * D1 + 1] = nb1;
+        }
+    }
+    gsync();
+}
+
+template <class Dist>
+__global__ void __launch_bounds__(kBT) k_batched(BatchArgs A) {
+    extern __shared__ unsigned char smem[];
+    __shared__ BatchShared Sh;
+    __shared__ RedShared<kBT> RS;
+    __shared__ SortShared<kBT> SS;
+    for (;;) {
+        if (threadIdx.x == 0) Sh.cloud = (int)atomicAdd(A.queue, 1ull);
+        __syncthreads();
+        const int qi = Sh.cloud;
+        __syncthreads();
+        if (qi >= A.B) break;
+        batch_cloud<Dist>(A, A.order[qi], smem, Sh, RS, SS);
+    }
+}
+
+// clouds by decreasing size (longest processing time first); one block
+__global__ void __launch_bounds__(1024) k_lpt_order(const int64_t *offsets, int B, SortBufs sb,
+                                                    int *order, unsigned long long *queue,
+                                                    unsigned long long *ucount, int *status,
+                                                    int nmax) {
+    __shared__ SortShared<1024> S;
+    for (int b = threadIdx.x; b < B; b += 1024) {
+        const int64_t n = offsets[b + 1] - offsets[b];
+        if (n < 1 || n > nmax) atomicOr(status, 16);
+        sb.lo[0][b] = (u64)b;
+        sb.hi[0][b] = 0xffffffffu - (u32)(n < 0 ? 0 : n);
+        sb.val[0][b] = (u32)b;
+    }
+    if (threadIdx.x == 0) {
+        *queue = 0;
+        *ucount = 0;
+    }
+    gsync();
+    const int cur = block_radix_sort<1024>(sb, B, 4, 4, S);
+    for (int q = threadIdx.x; q < B; q += 1024) order[q] = (int)sb.val[cur][q];
+}
+
+__global__ void k_batch_status_reset(int *status) { *status = 0; }
+
+// canonical layout: segments in (cloud, dimension) order
+__global__ void __launch_bounds__(1024) k_batch_offsets(const int64_t *seg_count, int nseg,
+                                                        int64_t *offsets, int64_t *total) {
+    __shared__ int64_t s_w[1024 / kWave + 1];
+    int64_t carry = 0;
+    for (int base = 0; base < nseg; base += 1024) {
+        const int i = base + threadIdx.x;
+        const int64_t x = i < nseg ? seg_count[i] : 0;
+        const int lane = lane_id(), w = threadIdx.x / kWave;
+        int64_t inc = x;
+        for (int o = 1; o < kWave; o <<= 1) {
+            int64_t t = __shfl_up(inc, o, kWave);
+            if (lane >= o) inc += t;
+        }
+        if (lane == kWave - 1) s_w[w] = inc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int64_t acc = 0;
+            for (int q = 0; q < 1024 / kWave; ++q) {
+                int64_t t = s_w[q];
+                s_w[q] = acc;
+                acc += t;
+            }
+            s_w[1024 / kWave] = acc;
+        }
+        __syncthreads();
+        if (i < nseg) offsets[i] = carry + s_w[w] + inc - x;
+        carry += s_w[1024 / kWave];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        offsets[nseg] = carry;
+        *total = carry;
+    }
+}
+
+__global__ void k_batch_copy(const int64_t *seg_start, const int64_t *seg_count,
+                             const int64_t *offsets, int nseg, const float *ub, const float *ud,
+                             const int64_t *ubs, const int64_t *uds, int64_t cap, float *ob,
+                             float *od, int64_t *obs, int64_t *ods) {
+    const int sgi = blockIdx.x;
+    if (sgi >= nseg) return;
+    const int64_t src = seg_start[sgi], cnt = seg_count[sgi], dst = offsets[sgi];
+    if (dst + cnt > cap) return;
+    for (int64_t q = threadIdx.x; q < cnt; q += blockDim.x) {
+        ob[dst + q] = ub[src + q];
+        od[dst + q] = ud[src + q];
+        obs[dst + q] = ubs[src + q];
+        ods[dst + q] = uds[src + q];
+    }
+}
+
+size_t batched_lds_bytes(bool lds_d, int nmax) {
+    const size_t npairs = (size_t)nmax * (nmax - 1) / 2;
+    const size_t dpart = lds_d ? (npairs * 4 + 15) / 16 * 16 : 0;
+    const size_t uf = (size_t)nmax * (8 + 4 + 4) + (lds_d ? (npairs / 32 + 1) * 4 : 0);
+    const size_t red = (size_t)kBatchCapR * 20;
+    return std::max(dpart + uf, red);
+}
+
+hipError_t batched_prepare(bool lds_d, int nmax) {
+    const size_t lds = batched_lds_bytes(lds_d, nmax);
+    return hipFuncSetAttribute(lds_d ? (const void *)k_batched<DistPacked>
+                                     : (const void *)k_batched<DistFull>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+void launch_batched(const BatchArgs &A, bool lds_d, int grid, SortBufs lpt, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_status_reset, dim3(1), dim3(1), 0, st, A.status);
+    hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, st, A.offsets, A.B, lpt,
+                       (int *)A.order, A.queue, A.ucount, A.status, A.nmax);
+    const size_t lds = batched_lds_bytes(lds_d, A.nmax);
+    if (lds_d) hipLaunchKernelGGL(k_batched<DistPacked>, dim3(grid), dim3(kBT), lds, st, A);
+    else hipLaunchKernelGGL(k_batched<DistFull>, dim3(grid), dim3(kBT), lds, st, A);
+}
+
+void launch_batch_finalize(const BatchArgs &A, int64_t *offsets_out, int64_t *total, int64_t cap,
+                           float *ob, float *od, int64_t *obs, int64_t *ods, hipStream_t st) {
+    const int nseg = A.B * (A.max_dim + 1);
+    hipLaunchKernelGGL(k_batch_offsets, dim3(1), dim3(1024), 0, st, A.seg_count, nseg, offsets_out,
+                       total);
+    hipLaunchKernelGGL(k_batch_copy, dim3(nseg), dim3(256), 0, st, A.seg_start, A.seg_count,
+                       offsets_out, nseg, A.ub, A.ud, A.ubs, A.uds, cap, ob, od, obs, ods);
+}
+
+} // namespace rips

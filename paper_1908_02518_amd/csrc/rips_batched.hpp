@@ -1,0 +1,72 @@
+// rips_batched.hpp -- arguments of the batched persistent kernel.
+#pragma once
+
+#include "../../include/rips.h"
+#include "rips_reduce.hpp"
+
+namespace rips {
+
+constexpr int kBatchMaxN = 2048; // largest cloud of the batched path
+constexpr int kBatchLdsN = 256;  // clouds up to this size keep D in LDS
+
+struct BatchArgs {
+    const float *X;          // points, cloud b at rows [offsets[b], offsets[b+1])
+    const int64_t *offsets;  // B + 1
+    int B, m, max_dim;
+    float threshold;
+    u32 p;
+    const u32 *inv;
+    Binom binom;             // table for n <= nmax
+    int nmax;
+    const int *order;        // clouds by decreasing size
+    unsigned long long *queue;
+    // per-workgroup scratch, indexed by blockIdx.x
+    float *Dg;               // packed (LDS variant) or full (global variant) distances
+    int64_t d_stride;
+    int64_t *c_idx0, *c_idx1;  // candidate columns / sorted columns (idx)
+    float *c_dm0, *c_dm1;
+    int *c_j0, *c_j1;
+    uint8_t *c_t0, *c_t1;
+    u64 *s_lo0, *s_lo1;
+    u32 *s_hi0, *s_hi1, *s_v0, *s_v1;
+    int64_t col_stride;      // C(nmax, 2)
+    int64_t *ph_keys;
+    int32_t *ph_vals;
+    int64_t ph_stride;       // power of two >= 2 C(nmax,2) + 64
+    int64_t *v_off;
+    int *v_len;
+    u32 *v_piv;
+    int64_t *v_idx;
+    float *v_diam;
+    u32 *v_coef;
+    int64_t v_stride;        // column-store capacity per workgroup
+    unsigned long long *v_count; // per workgroup
+    u32 *bits_g;             // forest-edge bitmap per workgroup (global variant)
+    int64_t bits_stride;
+    int64_t *rg_keys;
+    u32 *rg_coef;
+    float *rg_diam;
+    u32 *rg_slots;
+    int64_t rg_stride;       // global working-column slots per workgroup (power of two)
+    float *st_b, *st_d;      // staged bars of the current cloud
+    int64_t *st_bs, *st_ds;
+    int64_t st_stride;       // nmax + C(nmax, 2)
+    // results
+    float *ub, *ud;          // unordered bars
+    int64_t *ubs, *uds;
+    int64_t ucap;
+    unsigned long long *ucount;
+    int64_t *seg_start, *seg_count; // B * (max_dim + 1)
+    rips_dim_stats *stats;          // B * (max_dim + 1)
+    float *t_used;                  // B
+    int *status;
+};
+
+
+size_t batched_lds_bytes(bool lds_d, int nmax);
+hipError_t batched_prepare(bool lds_d, int nmax);
+void launch_batched(const BatchArgs &A, bool lds_d, int grid, SortBufs lpt, hipStream_t st);
+void launch_batch_finalize(const BatchArgs &A, int64_t *offsets_out, int64_t *total, int64_t cap,
+                           float *ob, float *od, int64_t *obs, int64_t *ods, hipStream_t st);
+
+} // namespace rips

@@ -341,39 +341,6 @@ __device__ __forceinline__ bool ph_insert(const PivotHash &h, int64_t key, int32
     return false;
 }
 
-// Working column R_j (or V_j) of the reduction: a sparse vector over Z/p
-// keyed by simplex index, in LDS when it fits. Coefficients accumulate with
-// 32-bit atomics and are reduced mod p when read (XOR for p = 2).
-struct WorkHash {
-    int64_t *keys;
-    u32 *coef;
-    float *diam;
-    u32 mask;
-};
-
-// Add c * e_key (c in [0, p)); false on overflow.
-__device__ __forceinline__ bool wh_add(const WorkHash &h, int64_t key, float dm, u32 c, u32 p) {
-    u32 s = mix64((u64)key) & h.mask;
-    for (u32 probe = 0; probe <= h.mask; ++probe) {
-        const int64_t cur = __atomic_load_n(&h.keys[s], __ATOMIC_RELAXED);
-        bool mine = cur == key;
-        if (!mine && cur == kEmpty) {
-            const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
-            if (prev == (u64)kEmpty) {
-                h.diam[s] = dm;
-                mine = true;
-            } else mine = prev == (u64)key;
-        }
-        if (mine) {
-            if (p == 2) atomicXor(&h.coef[s], c & 1u);
-            else atomicAdd(&h.coef[s], c);
-            return true;
-        }
-        s = (s + 1) & h.mask;
-    }
-    return false;
-}
-
 // ---------------------------------------------------------------------------
 // Block-wide reductions of a (diameter, index) pivot candidate: the oldest
 // entry of a coboundary column is the one of smallest diameter, then largest

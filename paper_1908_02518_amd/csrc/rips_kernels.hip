@@ -10,7 +10,7 @@
 //   columns  SoA (idx, diam, j*, tau-apparent flag) of the surviving columns
 //   pivots   open-addressing table pivot -> column per dimension
 //   V        death columns of the reduction matrix, CSR-like append buffer
-#include "rips_kernels.hpp"
+#include "rips_reduce.hpp"
 
 namespace rips {
 
@@ -680,330 +680,45 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_columns(Columns in, Scala
 }
 
 // ---------------------------------------------------------------------------
-// Reduction of the surviving columns over Z/p (Algorithm 1 on the implicit
-// coboundary matrix, with clearing already applied, the emergent shortcut,
-// and pivot lookup = pivot table, then zero apparent facet).
-// One workgroup; columns in order; V keeps only death columns.
+// Reduction of the surviving columns over Z/p: one workgroup runs
+// reduce_columns (rips_reduce.hpp) over the sorted columns of one dimension.
+// The working columns live in LDS (kGlobal = false) or, when they outgrow
+// it, in global scratch.
 // ---------------------------------------------------------------------------
-constexpr int kRedThreads = 256;
-
 template <class Dist>
-struct RedState {
-    Ctx<Dist> c;
-    int k;
-    u32 p;
-};
-
-// R += coef * (coboundary of the k-simplex v, diameter dv): all cofacets of
-// diameter <= t. Coefficient of sigma u {j}: (-1)^(vertices of sigma below j).
-template <class Dist>
-__device__ bool add_coboundary(const Ctx<Dist> &c, int k, const int *v, float dv, u32 coef, u32 p,
-                               const WorkHash &R) {
-    bool ok = true;
-    if (c.nb.off == nullptr) {
-        for (int j = threadIdx.x; j < c.n; j += blockDim.x) {
-            bool in = false;
-            float nd = dv;
-            for (int m = 0; m <= k; ++m) {
-                in = in || (j == v[m]);
-                nd = fmaxf(nd, c.d(v[m], j));
-            }
-            if (in || !(nd <= c.t)) continue;
-            int below;
-            const int64_t ci = cofacet_index(v, k, j, c.B, &below);
-            const u32 cc = (below & 1) ? (p - coef) % p : coef;
-            ok = ok && wh_add(R, ci, nd, cc, p);
-        }
-        return ok;
-    }
-    int u = v[0];
-    int du = c.nb.off[u + 1] - c.nb.off[u];
-    for (int m = 1; m <= k; ++m) {
-        const int dd = c.nb.off[v[m] + 1] - c.nb.off[v[m]];
-        if (dd < du) {
-            du = dd;
-            u = v[m];
-        }
-    }
-    const int *L = c.nb.idx + c.nb.off[u];
-    for (int q = threadIdx.x; q < du; q += blockDim.x) {
-        const int j = L[q];
-        bool in = false;
-        float nd = dv;
-        for (int m = 0; m <= k; ++m) {
-            in = in || (j == v[m]);
-            nd = fmaxf(nd, c.d(v[m], j));
-        }
-        if (in || !(nd <= c.t)) continue;
-        int below;
-        const int64_t ci = cofacet_index(v, k, j, c.B, &below);
-        const u32 cc = (below & 1) ? (p - coef) % p : coef;
-        ok = ok && wh_add(R, ci, nd, cc, p);
-    }
-    return ok;
-}
-
-template <class Dist>
-__global__ void __launch_bounds__(kRedThreads) k_reduce(Ctx<Dist> c, int k, u32 p, const u32 *inv,
-                                                       Columns cols, int ncols, PivotHash ph,
-                                                       VStore V, WorkHash Rg, WorkHash Vg,
-                                                       int use_lds, u32 capR, u32 capV,
-                                                       Scalars *s, BarBuf bars) {
+__global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, WorkCol Rl, WorkCol Rg,
+                                                       Scalars *s) {
     extern __shared__ unsigned char smem[];
-    __shared__ int s_base, s_full, s_abort, s_m;
-    __shared__ int64_t s_owner;
-    __shared__ PivotCand s_wp[kRedThreads / kWave];
-    __shared__ PivotCand s_piv;
-    __shared__ int s_w[kRedThreads / kWave + 1];
-    __shared__ u64 s_stat[8];
-    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-
-    WorkHash R = Rg, Vw = Vg;
-    if (use_lds) {
+    __shared__ RedShared<kRedThreads> S;
+    __shared__ int s_ns[2];
+    WorkCol R = Rl, RG = Rg;
+    R.nslots = &s_ns[0];
+    RG.nslots = &s_ns[1];
+    if (Rl.mask != 0) {
         unsigned char *q = smem;
+        const size_t cr = (size_t)Rl.mask + 1;
         R.keys = (int64_t *)q;
-        q += (size_t)capR * 8;
-        Vw.keys = (int64_t *)q;
-        q += (size_t)capV * 8;
+        q += cr * 8;
         R.coef = (u32 *)q;
-        q += (size_t)capR * 4;
+        q += cr * 4;
         R.diam = (float *)q;
-        q += (size_t)capR * 4;
-        Vw.coef = (u32 *)q;
-        q += (size_t)capV * 4;
-        Vw.diam = (float *)q;
-        R.mask = capR - 1;
-        Vw.mask = capV - 1;
+        q += cr * 4;
+        R.slots = (u32 *)q;
+    } else {
+        R.keys = nullptr;
     }
-    if (tid == 0) {
-        s_base = 0;
-        s_abort = 0;
-    }
-    if (tid < 8) s_stat[tid] = 0;
-    int nbars = 0; // maintained by thread 0
-    gsync();
-
-    for (;;) {
-        gsync();
-        const int base = s_base;
-        const int stop = base >= ncols || s_abort;
-        gsync(); // everyone has read the cursor before wave 0 moves it
-        if (stop) break;
-        // ---- Phase A: emergent shortcut for up to 64 columns at once (wave 0)
-        if (w == 0) {
-            const int col = base + lane;
-            const bool valid = col < ncols;
-            bool ok = false;
-            int64_t tau = kEmpty;
-            u32 tcoef = 0;
-            if (valid) {
-                const int j = cols.j[col];
-                if (j >= 0 && !cols.tapp[col]) {
-                    int v[kMaxVerts];
-                    decode(cols.idx[col], k, c.n, c.B, v);
-                    int below;
-                    tau = cofacet_index(v, k, j, c.B, &below);
-                    tcoef = coeff_sign(below, p);
-                    ok = ph_find(ph, tau) < 0;
-                }
-            }
-            // a lower column of the batch that takes the same pivot owns it
-            for (int l = 0; l < kWave - 1; ++l) {
-                const int64_t tl = __shfl(tau, l, kWave);
-                const int okl = __shfl((int)ok, l, kWave);
-                if (l < lane && okl && tl == tau) ok = false;
-            }
-            const u64 bad = __ballot(!ok);
-            const int first_bad = bad ? __ffsll((unsigned long long)bad) - 1 : kWave;
-            if (lane < first_bad) {
-                ph_insert(ph, tau, col);
-                V.pivcoef[col] = tcoef;
-                V.len[col] = 0;
-                V.off[col] = 0;
-            }
-            if (lane == 0) {
-                s_base = base + first_bad;
-                s_full = (first_bad < kWave) && (base + first_bad < ncols);
-                s_stat[0] += first_bad; // emergent
-            }
-        }
-        gsync();
-        if (!s_full) continue;
-        // ---- Phase B: full reduction of column j
-        const int j = s_base;
-        const int64_t sidx = cols.idx[j];
-        const float sdm = cols.diam[j];
-        int v[kMaxVerts];
-        decode(sidx, k, c.n, c.B, v);
-        for (u32 q = tid; q <= R.mask; q += kRedThreads) {
-            __atomic_store_n(&R.keys[q], kEmpty, __ATOMIC_RELAXED);
-            __atomic_store_n(&R.coef[q], 0u, __ATOMIC_RELAXED);
-        }
-        for (u32 q = tid; q <= Vw.mask; q += kRedThreads) {
-            __atomic_store_n(&Vw.keys[q], kEmpty, __ATOMIC_RELAXED);
-            __atomic_store_n(&Vw.coef[q], 0u, __ATOMIC_RELAXED);
-        }
-        gsync();
-        if (!add_coboundary(c, k, v, sdm, 1u, p, R)) s_abort = 1;
-        int nadd = 0;
-        for (;;) {
-            gsync();
-            if (s_abort) break;
-            // every addition moves the pivot to a strictly younger row, so the
-            // loop ends; the cap only turns an arithmetic fault into an error
-            if (nadd > (1 << 16)) {
-                if (tid == 0) s_abort = 3;
-                gsync();
-                break;
-            }
-            // pivot: oldest nonzero entry
-            PivotCand best;
-            best.idx = kEmpty;
-            best.diam = 0.0f;
-            best.coef = 0;
-            for (u32 q = tid; q <= R.mask; q += kRedThreads) {
-                const int64_t key = ld(&R.keys[q]);
-                if (key == kEmpty) continue;
-                u32 cf = ld(&R.coef[q]);
-                if (p != 2 && cf >= p) {
-                    cf %= p;
-                    __atomic_store_n(&R.coef[q], cf, __ATOMIC_RELAXED);
-                }
-                if (cf == 0) continue;
-                PivotCand x;
-                x.idx = key;
-                x.diam = R.diam[q];
-                x.coef = cf;
-                if (older(x, best)) best = x;
-            }
-            best = wave_oldest(best);
-            if (lane == 0) s_wp[w] = best;
-            gsync();
-            if (tid == 0) {
-                PivotCand b = s_wp[0];
-                for (int q = 1; q < kRedThreads / kWave; ++q)
-                    if (older(s_wp[q], b)) b = s_wp[q];
-                s_piv = b;
-                s_owner = b.idx == kEmpty ? -1 : ph_find(ph, b.idx);
-            }
-            gsync();
-            const PivotCand piv = s_piv;
-            if (piv.idx == kEmpty) {
-                // zero column: essential class born at sigma
-                if (tid == 0 && nbars < ncols) {
-                    bars.birth[nbars] = sdm;
-                    bars.death[nbars] = INFINITY;
-                    bars.bs[nbars] = sidx;
-                    bars.ds[nbars] = -1;
-                    ++nbars;
-                    s_stat[4] += 1;
-                }
-                break;
-            }
-            const int64_t o = s_owner;
-            if (o >= 0) {
-                // R_j -= lambda R_o with R_o = D (e_o + V_o), lambda = piv / pivot(R_o)
-                const u32 lam = (u32)((u64)piv.coef * inv[V.pivcoef[o]] % p);
-                const u32 neg = (p - lam) % p;
-                const int nv = V.len[o];
-                const int64_t vo = V.off[o];
-                for (int it = 0; it <= nv; ++it) {
-                    const int64_t si = it == 0 ? cols.idx[o] : V.idx[vo + it - 1];
-                    const u32 sc = it == 0 ? 1u : V.coef[vo + it - 1];
-                    const u32 cc = (u32)((u64)neg * sc % p);
-                    int sv[kMaxVerts];
-                    decode(si, k, c.n, c.B, sv);
-                    const float sd = diam_of(c, sv, k);
-                    if (!add_coboundary(c, k, sv, sd, cc, p, R)) s_abort = 1;
-                    if ((it % kRedThreads) == tid)
-                        if (!wh_add(Vw, si, sd, cc, p)) s_abort = 1;
-                }
-                ++nadd;
-                continue;
-            }
-            // not in the table: is the pivot in a zero apparent pair (rho, tau)?
-            int tv[kMaxVerts];
-            decode(piv.idx, k + 1, c.n, c.B, tv);
-            if (w == 0) {
-                const int m = zero_apparent_facet<kWave>(c, tv, k + 1, piv.diam);
-                if (lane == 0) s_m = m;
-            }
-            gsync();
-            const int m = s_m;
-            if (m >= 0) {
-                int rv[kMaxVerts];
-                remove_vertex(tv, k + 1, m, rv);
-                // tau = rho u {tau[m]}; vertices of rho below tau[m]: k + 1 - m
-                const u32 crho = coeff_sign(k + 1 - m, p);
-                const u32 lam = (u32)((u64)piv.coef * inv[crho] % p);
-                const u32 neg = (p - lam) % p;
-                if (!add_coboundary(c, k, rv, piv.diam, neg, p, R)) s_abort = 1;
-                if (tid == 0)
-                    if (!wh_add(Vw, simplex_index(rv, k, c.B), piv.diam, neg, p)) s_abort = 1;
-                ++nadd;
-                continue;
-            }
-            // unowned pivot: persistence pair (sigma_j, pivot)
-            if (tid == 0) {
-                if (piv.diam > sdm && nbars < ncols) {
-                    bars.birth[nbars] = sdm;
-                    bars.death[nbars] = piv.diam;
-                    bars.bs[nbars] = sidx;
-                    bars.ds[nbars] = piv.idx;
-                    ++nbars;
-                    s_stat[3] += 1;
-                }
-                ph_insert(ph, piv.idx, j);
-                V.pivcoef[j] = piv.coef;
-            }
-            // store the nonzero entries of V_j
-            int cnt = 0;
-            for (u32 q = tid; q <= Vw.mask; q += kRedThreads) {
-                const u32 cf = ld(&Vw.coef[q]) % p;
-                cnt += (ld(&Vw.keys[q]) != kEmpty && cf != 0) ? 1 : 0;
-            }
-            int tot;
-            const int ex = block_exclusive_scan<kRedThreads>(cnt, s_w, &tot);
-            __shared__ unsigned long long s_vbase;
-            if (tid == 0) s_vbase = atomicAdd(&s->vcount, (unsigned long long)tot);
-            gsync();
-            const int64_t vb = (int64_t)s_vbase;
-            if (vb + tot > V.cap) {
-                if (tid == 0) s_abort = 2;
-            } else {
-                int at = ex;
-                for (u32 q = tid; q <= Vw.mask; q += kRedThreads) {
-                    const u32 cf = ld(&Vw.coef[q]) % p;
-                    const int64_t key = ld(&Vw.keys[q]);
-                    if (key != kEmpty && cf != 0) {
-                        V.idx[vb + at] = key;
-                        V.coef[vb + at] = cf;
-                        ++at;
-                    }
-                }
-                if (tid == 0) {
-                    V.off[j] = vb;
-                    V.len[j] = tot;
-                }
-            }
-            break;
-        }
-        if (tid == 0) {
-            s_stat[1] += nadd > 0 ? 1 : 0;
-            s_stat[2] += nadd;
-            s_base = j + 1;
-        }
-        gsync();
-    }
-    gsync();
-    if (tid == 0) {
-        s->status = s_abort;
-        s->nbars = nbars;
-        s->stat[kStatEmergent] += s_stat[0];
-        s->stat[kStatReduced] += s_stat[1];
-        s->stat[kStatAdditions] += s_stat[2];
-        s->stat[kStatBarsNonzero] += s_stat[3];
-        s->stat[kStatEssential] += s_stat[4];
+    const int status = reduce_columns<kRedThreads>(J, R, RG, S);
+    if (threadIdx.x == 0) {
+        s->status = status;
+        s->nbars = S.nbars;
+        s->stat[kStatEmergent] += S.stat[0];
+        s->stat[kStatReduced] += S.stat[1];
+        s->stat[kStatAdditions] += S.stat[2];
+        s->stat[kStatBarsNonzero] += S.stat[3];
+        s->stat[kStatEssential] += S.stat[4];
+        s->stat[kStatGlobalCols] += S.stat[5];
+        s->stat[kStatMaxV] = S.stat[6];
+        s->stat[kStatMaxR] = S.stat[7];
     }
 }
 
@@ -1134,17 +849,21 @@ void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Colu
                        out);
 }
 
-size_t reduce_lds_bytes(u32 capR, u32 capV) { return (size_t)capR * 16 + (size_t)capV * 16; }
+size_t reduce_lds_bytes(u32 capR) { return (size_t)capR * 20; }
 
-void launch_reduce(const Ctx<DistFull> &c, int k, u32 p, const u32 *inv, Columns cols, int ncols,
-                   PivotHash ph, VStore V, WorkHash Rg, WorkHash Vg, int use_lds, u32 capR,
-                   u32 capV, Scalars *s, BarBuf bars, hipStream_t st) {
-    const size_t lds = use_lds ? reduce_lds_bytes(capR, capV) : 0;
-    if (lds > 64 * 1024)
-        (void)hipFuncSetAttribute((const void *)k_reduce<DistFull>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k_reduce<DistFull>, dim3(1), dim3(kRedThreads), lds, st, c, k, p, inv, cols,
-                       ncols, ph, V, Rg, Vg, use_lds, capR, capV, s, bars);
+hipError_t launch_reduce(const ReduceJob<DistFull> &J, WorkCol Rl, WorkCol Rg, int use_lds,
+                         Scalars *s, hipStream_t st) {
+    size_t lds = 0;
+    if (use_lds) {
+        lds = reduce_lds_bytes(Rl.mask + 1);
+        hipError_t e = hipFuncSetAttribute((const void *)k_reduce<DistFull>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    } else {
+        Rl.mask = 0;
+    }
+    hipLaunchKernelGGL((k_reduce<DistFull>), dim3(1), dim3(kRedThreads), lds, st, J, Rl, Rg, s);
+    return hipGetLastError();
 }
 
 void launch_emit(BarBuf in, Scalars *s, int reverse, BarBuf out, hipStream_t st) {

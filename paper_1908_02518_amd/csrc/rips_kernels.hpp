@@ -15,6 +15,9 @@ enum {
     kStatAdditions,
     kStatBarsNonzero,
     kStatEssential,
+    kStatGlobalCols, // columns that outgrew the LDS working tables
+    kStatMaxV,       // longest stored V column
+    kStatMaxR,       // most entries touched by one working column
     kNumStats
 };
 
@@ -54,11 +57,15 @@ struct Columns {
     uint8_t *tapp;  // 1 if that cofacet lies in a zero apparent pair
 };
 
+// Reduced columns R_j of the non-emergent death columns, kept once column j
+// is final: an addition of column o then touches |R_o| entries. Emergent
+// columns keep len = -1: their R_o is the coboundary of sigma_o (implicit).
 struct VStore {
     int64_t *off;   // per column
     int *len;
     u32 *pivcoef;   // pivot entry of R_j
-    int64_t *idx;   // append buffer of (simplex, coefficient)
+    int64_t *idx;   // append buffer of (cofacet index, diameter, coefficient)
+    float *diam;
     u32 *coef;
     int64_t cap;
 };
@@ -102,10 +109,8 @@ void launch_expand(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t
                    SimplexList out, int64_t cap, bool count_only, hipStream_t st);
 void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Columns out,
                          hipStream_t st);
-size_t reduce_lds_bytes(u32 capR, u32 capV);
-void launch_reduce(const Ctx<DistFull> &c, int k, u32 p, const u32 *inv, Columns cols, int ncols,
-                   PivotHash ph, VStore V, WorkHash Rg, WorkHash Vg, int use_lds, u32 capR,
-                   u32 capV, Scalars *s, BarBuf bars, hipStream_t st);
 void launch_emit(BarBuf in, Scalars *s, int reverse, BarBuf out, hipStream_t st);
+
+constexpr int kRedThreads = 256;
 
 } // namespace rips
