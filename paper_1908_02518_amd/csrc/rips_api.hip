@@ -89,14 +89,24 @@ enum BufId {
     B_V_IDX,
     B_V_COEF,
     B_V_DIAM,
-    B_WR_KEYS,
-    B_WR_COEF,
-    B_WR_DIAM,
-    B_WV_KEYS,
-    B_WV_COEF,
-    B_WV_DIAM,
-    B_WR_SLOTS,
-    B_WV_SLOTS,
+    B_SB_IDX0, // sorted base of the working column, two buffers
+    B_SB_IDX1,
+    B_SB_DIA0,
+    B_SB_DIA1,
+    B_SB_COEF0,
+    B_SB_COEF1,
+    B_F_IDX0, // far list of the working column, two buffers
+    B_F_IDX1,
+    B_F_DIA0,
+    B_F_DIA1,
+    B_F_COEF0,
+    B_F_COEF1,
+    B_VW_KEYS, // working V column
+    B_VW_COEF,
+    B_VW_DIAM,
+    B_VW_SLOTS,
+    B_V_ROFF,
+    B_V_RLEN,
     B_BAR_BIRTH, // + d
     B_BAR_DEATH = B_BAR_BIRTH + kMaxDim + 1,
     B_BAR_BS = B_BAR_DEATH + kMaxDim + 1,
@@ -128,10 +138,24 @@ enum BufId {
     BB_V_COEF,
     BB_V_COUNT,
     BB_BITS,
-    BB_RG_KEYS,
-    BB_RG_COEF,
-    BB_RG_DIAM,
-    BB_RG_SLOTS,
+    BB_SB_IDX0,
+    BB_SB_IDX1,
+    BB_SB_DIA0,
+    BB_SB_DIA1,
+    BB_SB_COEF0,
+    BB_SB_COEF1,
+    BB_F_IDX0,
+    BB_F_IDX1,
+    BB_F_DIA0,
+    BB_F_DIA1,
+    BB_F_COEF0,
+    BB_F_COEF1,
+    BB_VW_KEYS,
+    BB_VW_COEF,
+    BB_VW_DIAM,
+    BB_VW_SLOTS,
+    BB_V_ROFF,
+    BB_V_RLEN,
     BB_ST_B,
     BB_ST_D,
     BB_ST_BS,
@@ -165,6 +189,9 @@ struct DevCtx {
     int64_t hint_edges = 0;
     int64_t hint_list[kMaxDim + 2] = {};
     int64_t hint_v = 0;
+    int64_t hint_sb = 0;
+    int64_t hint_far = 0;
+    int64_t hint_vw = 0;
     int lds_per_block = 0;
     int num_cus = 0;
     hipStream_t capture_stream = nullptr;
@@ -172,7 +199,10 @@ struct DevCtx {
     hipGraphExec_t batch_exec = nullptr;
     std::vector<unsigned char> batch_key;
     int64_t batch_vstride = 0;
-    int64_t batch_rgstride = 0;
+    int64_t batch_sbstride = 0;
+    int64_t batch_fstride = 0;
+    int64_t batch_vwstride = 0;
+    u32 batch_capD = 0; // 0 = default delta size of the batched reduction
 
     hipError_t ensure(int id, size_t bytes, void **out) {
         if (bytes == 0) bytes = 16;
@@ -691,18 +721,23 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         V.len = as<int>(q);
         HIP_TRY(C.ensure(B_V_PIV, (size_t)S * 4, &q));
         V.pivcoef = as<u32>(q);
+        HIP_TRY(C.ensure(B_V_ROFF, (size_t)S * 8, &q));
+        V.roff = as<int64_t>(q);
+        HIP_TRY(C.ensure(B_V_RLEN, (size_t)S * 4, &q));
+        V.rlen = as<int>(q);
         int64_t vcap = std::max<int64_t>(C.hint_v, 64 * S + 65536);
         if ((rs = ensure_bars(k, S))) return rs;
         const int bound = P.sparse ? P.maxdeg : n;
-        // working column: in LDS (as large as the workgroup's share allows),
-        // with a global table for the columns that outgrow it
-        const size_t lds_budget = C.lds_per_block > 32768 ? (size_t)C.lds_per_block - 24576 : 0;
-        uint32_t capR = 1u << 16;
-        while (capR > 256 && reduce_lds_bytes(capR) > lds_budget) capR >>= 1;
-        const int use_lds = reduce_lds_bytes(capR) <= lds_budget ? 1 : 0;
-        uint32_t capRg = next_pow2(std::max<uint64_t>(1u << 16, 64ull * (uint64_t)bound));
+        // working column: the delta in LDS (as large as a workgroup's share
+        // allows), the sorted base in global scratch (grown on overflow)
+        const size_t lds_budget = C.lds_per_block > 16384 ? (size_t)C.lds_per_block - 12288 : 0;
+        uint32_t capD = 4096;
+        while (capD > 256 && reduce_lds_bytes(capD) > lds_budget) capD >>= 1;
+        int64_t sbcap = std::max<int64_t>(C.hint_sb, std::max<int64_t>(1 << 16, 16ll * bound));
+        int64_t fcap = std::max<int64_t>(C.hint_far, std::max<int64_t>(1 << 18, 256ll * bound));
+        int64_t vwcap = std::max<int64_t>(C.hint_vw, 1 << 14);
         for (int attempt = 0;; ++attempt) {
-            if (attempt > 6) return fail(RIPS_E_CAPACITY, "reduction scratch kept overflowing");
+            if (attempt > 12) return fail(RIPS_E_CAPACITY, "reduction scratch kept overflowing");
             HIP_TRY(C.ensure(B_V_IDX, (size_t)vcap * 8, &q));
             V.idx = as<int64_t>(q);
             HIP_TRY(C.ensure(B_V_DIAM, (size_t)vcap * 4, &q));
@@ -710,16 +745,37 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             HIP_TRY(C.ensure(B_V_COEF, (size_t)vcap * 4, &q));
             V.coef = as<u32>(q);
             V.cap = vcap;
-            WorkCol Rl{nullptr, nullptr, nullptr, nullptr, nullptr, capR - 1};
-            WorkCol Rg{nullptr, nullptr, nullptr, nullptr, nullptr, capRg - 1};
-            HIP_TRY(C.ensure(B_WR_KEYS, (size_t)capRg * 8, &q));
-            Rg.keys = as<int64_t>(q);
-            HIP_TRY(C.ensure(B_WR_COEF, (size_t)capRg * 4, &q));
-            Rg.coef = as<u32>(q);
-            HIP_TRY(C.ensure(B_WR_DIAM, (size_t)capRg * 4, &q));
-            Rg.diam = as<float>(q);
-            HIP_TRY(C.ensure(B_WR_SLOTS, (size_t)capRg * 4, &q));
-            Rg.slots = as<u32>(q);
+            SortedBase SB;
+            for (int b = 0; b < 2; ++b) {
+                HIP_TRY(C.ensure(B_SB_IDX0 + b, (size_t)sbcap * 8, &q));
+                SB.idx[b] = as<int64_t>(q);
+                HIP_TRY(C.ensure(B_SB_DIA0 + b, (size_t)sbcap * 4, &q));
+                SB.dia[b] = as<float>(q);
+                HIP_TRY(C.ensure(B_SB_COEF0 + b, (size_t)sbcap * 4, &q));
+                SB.coef[b] = as<u32>(q);
+            }
+            SB.cap = sbcap;
+            ReduceScratch SC;
+            SC.SB = SB;
+            for (int b = 0; b < 2; ++b) {
+                HIP_TRY(C.ensure(B_F_IDX0 + b, (size_t)fcap * 8, &q));
+                SC.F.idx[b] = as<int64_t>(q);
+                HIP_TRY(C.ensure(B_F_DIA0 + b, (size_t)fcap * 4, &q));
+                SC.F.dia[b] = as<float>(q);
+                HIP_TRY(C.ensure(B_F_COEF0 + b, (size_t)fcap * 4, &q));
+                SC.F.coef[b] = as<u32>(q);
+            }
+            SC.F.cap = fcap;
+            HIP_TRY(C.ensure(B_VW_KEYS, (size_t)vwcap * 8, &q));
+            SC.Vw.keys = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_VW_COEF, (size_t)vwcap * 4, &q));
+            SC.Vw.coef = as<u32>(q);
+            HIP_TRY(C.ensure(B_VW_DIAM, (size_t)vwcap * 4, &q));
+            SC.Vw.diam = as<float>(q);
+            HIP_TRY(C.ensure(B_VW_SLOTS, (size_t)vwcap * 4, &q));
+            SC.Vw.slots = as<u32>(q);
+            SC.Vw.nslots = nullptr; // set by the kernel (LDS)
+            SC.Vw.mask = (u32)vwcap - 1;
             launch_fill_i64(ph.keys, phcap, kEmpty, st);
             launch_reset_dim(P.scal, st);
             ReduceJob<DistFull> J;
@@ -733,17 +789,26 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             J.V = V;
             J.vcount = &P.scal->vcount;
             J.bars = bars[k];
+            J.cand_avg = P.sparse ? (float)(2.0 * (double)P.nedges / (double)std::max<int64_t>(n, 1))
+                                  : (float)n;
             {
                 PROF(P_REDUCE1 + k - 1);
-                HIP_TRY(launch_reduce(J, Rl, Rg, use_lds, P.scal, st));
+                HIP_TRY(launch_reduce(J, capD, SC, P.scal, st));
             }
             if ((rs = read_scalars(C, P.scal, st))) return rs;
             const int status = C.host_scal->status;
             if (status == 0) break;
-            if (status == 1) {
-                capRg = capRg < (1u << 27) ? capRg * 4 : capRg;
-            } else if (status == 2) {
+            if (status == kRedBaseFull) {
+                sbcap *= 4;
+                C.hint_sb = sbcap;
+            } else if (status == kRedStoreFull) {
                 vcap *= 4;
+            } else if (status == kRedFarFull) {
+                fcap *= 4;
+                C.hint_far = fcap;
+            } else if (status == kRedVFull) {
+                vwcap *= 4;
+                C.hint_vw = vwcap;
             } else {
                 return fail(RIPS_E_HIP, "reduction exceeded its addition bound");
             }
@@ -751,9 +816,9 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         if ((int64_t)C.host_scal->vcount > C.hint_v) C.hint_v = (int64_t)C.host_scal->vcount;
         if (getenv("RIPS_DEBUG"))
             fprintf(stderr,
-                    "[rips reduce d%d] cols=%lld lds=%d capR=%u capRg=%u lds_per_block=%d "
-                    "global_cols=%llu R_entries=%llu maxR_stored=%llu maxR=%llu additions=%llu\n",
-                    k, (long long)S, use_lds, capR, capRg, C.lds_per_block,
+                    "[rips reduce d%d] cols=%lld capD=%u sbcap=%lld lds_per_block=%d "
+                    "base_cols=%llu R_entries=%llu maxR_stored=%llu maxR=%llu additions=%llu\n",
+                    k, (long long)S, capD, (long long)sbcap, C.lds_per_block,
                     C.host_scal->stat[kStatGlobalCols], C.host_scal->vcount,
                     C.host_scal->stat[kStatMaxV], C.host_scal->stat[kStatMaxR],
                     C.host_scal->stat[kStatAdditions]);
@@ -797,8 +862,12 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     int64_t ph_stride = 64;
     while (ph_stride < 2 * col_stride + 64) ph_stride <<= 1;
     const int64_t v_stride = std::max<int64_t>(C->batch_vstride, std::max<int64_t>(1 << 18, 4 * col_stride));
-    const int64_t rg_stride = std::max<int64_t>(
-        C->batch_rgstride, next_pow2(std::max<uint64_t>(1u << 17, 64ull * (uint64_t)n_max)));
+    const int64_t sb_stride =
+        std::max<int64_t>(C->batch_sbstride, std::max<int64_t>(1 << 15, 16ll * n_max));
+    const u32 capD = C->batch_capD ? C->batch_capD : batched_default_capD(lds_d, n_max);
+    const int64_t f_stride =
+        std::max<int64_t>(C->batch_fstride, std::max<int64_t>(1 << 15, 64ll * n_max));
+    const int64_t vw_stride = std::max<int64_t>(C->batch_vwstride, 1 << 12);
     const int64_t st_stride = 2 * (int64_t)n_max + npairs + 16;
     const int64_t d_stride = lds_d ? npairs + 4 : (int64_t)n_max * n_max + 4;
     const int64_t bits_stride = npairs / 32 + 2;
@@ -854,11 +923,26 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     ENS(BB_V_COUNT, G * 8, A.v_count, unsigned long long);
     ENS(BB_BITS, G * bits_stride * 4, A.bits_g, u32);
     A.bits_stride = bits_stride;
-    ENS(BB_RG_KEYS, G * rg_stride * 8, A.rg_keys, int64_t);
-    ENS(BB_RG_COEF, G * rg_stride * 4, A.rg_coef, u32);
-    ENS(BB_RG_DIAM, G * rg_stride * 4, A.rg_diam, float);
-    ENS(BB_RG_SLOTS, G * rg_stride * 4, A.rg_slots, u32);
-    A.rg_stride = rg_stride;
+    for (int h = 0; h < 2; ++h) {
+        ENS(BB_SB_IDX0 + h, G * sb_stride * 8, A.sb_idx[h], int64_t);
+        ENS(BB_SB_DIA0 + h, G * sb_stride * 4, A.sb_dia[h], float);
+        ENS(BB_SB_COEF0 + h, G * sb_stride * 4, A.sb_coef[h], u32);
+    }
+    A.sb_stride = sb_stride;
+    A.capD = capD;
+    for (int h = 0; h < 2; ++h) {
+        ENS(BB_F_IDX0 + h, G * f_stride * 8, A.f_idx[h], int64_t);
+        ENS(BB_F_DIA0 + h, G * f_stride * 4, A.f_dia[h], float);
+        ENS(BB_F_COEF0 + h, G * f_stride * 4, A.f_coef[h], u32);
+    }
+    A.f_stride = f_stride;
+    ENS(BB_VW_KEYS, G * vw_stride * 8, A.vw_keys, int64_t);
+    ENS(BB_VW_COEF, G * vw_stride * 4, A.vw_coef, u32);
+    ENS(BB_VW_DIAM, G * vw_stride * 4, A.vw_diam, float);
+    ENS(BB_VW_SLOTS, G * vw_stride * 4, A.vw_slots, u32);
+    A.vw_stride = vw_stride;
+    ENS(BB_V_ROFF, G * col_stride * 8, A.v_roff, int64_t);
+    ENS(BB_V_RLEN, G * col_stride * 4, A.v_rlen, int);
     ENS(BB_ST_B, G * st_stride * 4, A.st_b, float);
     ENS(BB_ST_D, G * st_stride * 4, A.st_d, float);
     ENS(BB_ST_BS, G * st_stride * 8, A.st_bs, int64_t);
@@ -897,7 +981,7 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     A.ucount = &bs->ucount;
     A.status = &bs->status;
 #undef ENS
-    HIP_TRY(batched_prepare(lds_d, n_max));
+    HIP_TRY(batched_prepare(lds_d, n_max, capD));
     // the graph is keyed by every argument and buffer address it captures
     std::vector<unsigned char> key(sizeof(A) + sizeof(lpt) + 6 * sizeof(void *) + 16);
     {
@@ -959,9 +1043,21 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
         return RIPS_E_CAPACITY;
     }
     if (hs.status & 1) {
-        // a working column outgrew the global table: grow it and run again
-        C->batch_rgstride = rg_stride * 4;
-        if (C->batch_rgstride > (1ll << 26)) return fail(RIPS_E_CAPACITY, "working column overflow");
+        // a working column outgrew its sorted base: grow it and run again
+        C->batch_sbstride = sb_stride * 4;
+        if (C->batch_sbstride > (1ll << 26)) return fail(RIPS_E_CAPACITY, "working column overflow");
+        *retry = true;
+        return RIPS_E_CAPACITY;
+    }
+    if (hs.status & 32) {
+        C->batch_fstride = f_stride * 4;
+        if (C->batch_fstride > (1ll << 28)) return fail(RIPS_E_CAPACITY, "far list overflow");
+        *retry = true;
+        return RIPS_E_CAPACITY;
+    }
+    if (hs.status & 64) {
+        C->batch_vwstride = vw_stride * 4;
+        if (C->batch_vwstride > (1ll << 24)) return fail(RIPS_E_CAPACITY, "V table overflow");
         *retry = true;
         return RIPS_E_CAPACITY;
     }

@@ -13,7 +13,6 @@ namespace rips {
 
 constexpr int kBT = 256;         // threads per workgroup
 constexpr int kBatchG = 16;      // lanes per candidate in the filter
-constexpr int kBatchCapR = 2048; // LDS working-column slots
 
 struct BatchShared {
     int cloud, n, nsurv, nbars0, flag, m;
@@ -426,30 +425,46 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         J.V.off = A.v_off + (int64_t)wg * A.col_stride;
         J.V.len = A.v_len + (int64_t)wg * A.col_stride;
         J.V.pivcoef = A.v_piv + (int64_t)wg * A.col_stride;
+        J.V.roff = A.v_roff + (int64_t)wg * A.col_stride;
+        J.V.rlen = A.v_rlen + (int64_t)wg * A.col_stride;
         J.V.idx = A.v_idx + (int64_t)wg * A.v_stride;
         J.V.diam = A.v_diam + (int64_t)wg * A.v_stride;
         J.V.coef = A.v_coef + (int64_t)wg * A.v_stride;
         J.V.cap = A.v_stride;
         J.vcount = &A.v_count[wg];
         J.bars = BarBuf{sb_b + n, sb_d + n, sb_bs + n, sb_ds + n};
-        __shared__ int s_nsl, s_nsg;
-        WorkCol Rl;
-        unsigned char *q = smem;
-        Rl.keys = (int64_t *)q;
-        q += (size_t)kBatchCapR * 8;
-        Rl.coef = (u32 *)q;
-        q += (size_t)kBatchCapR * 4;
-        Rl.diam = (float *)q;
-        q += (size_t)kBatchCapR * 4;
-        Rl.slots = (u32 *)q;
-        Rl.nslots = &s_nsl;
-        Rl.mask = kBatchCapR - 1;
-        WorkCol Rg{A.rg_keys + (int64_t)wg * A.rg_stride, A.rg_coef + (int64_t)wg * A.rg_stride,
-                   A.rg_diam + (int64_t)wg * A.rg_stride, A.rg_slots + (int64_t)wg * A.rg_stride,
-                   &s_nsg, (u32)A.rg_stride - 1};
+        __shared__ int s_nsl;
+        WorkCol Dw;
+        Staging Gs;
+        carve_reduce_lds(smem, A.capD, &s_nsl, &Dw, &Gs);
+        ReduceScratch SC;
+        for (int h = 0; h < 2; ++h) {
+            SC.SB.idx[h] = A.sb_idx[h] + (int64_t)wg * A.sb_stride;
+            SC.SB.dia[h] = A.sb_dia[h] + (int64_t)wg * A.sb_stride;
+            SC.SB.coef[h] = A.sb_coef[h] + (int64_t)wg * A.sb_stride;
+            SC.F.idx[h] = A.f_idx[h] + (int64_t)wg * A.f_stride;
+            SC.F.dia[h] = A.f_dia[h] + (int64_t)wg * A.f_stride;
+            SC.F.coef[h] = A.f_coef[h] + (int64_t)wg * A.f_stride;
+        }
+        SC.SB.cap = A.sb_stride;
+        SC.F.cap = A.f_stride;
+        SC.Vw.keys = A.vw_keys + (int64_t)wg * A.vw_stride;
+        SC.Vw.coef = A.vw_coef + (int64_t)wg * A.vw_stride;
+        SC.Vw.diam = A.vw_diam + (int64_t)wg * A.vw_stride;
+        SC.Vw.slots = A.vw_slots + (int64_t)wg * A.vw_stride;
+        SC.Vw.nslots = &RS.vns;
+        SC.Vw.mask = (u32)A.vw_stride - 1;
+        J.cand_avg = (float)n;
         gsync();
-        const int rstat = reduce_columns<kBT>(J, Rl, Rg, RS);
-        if (rstat && tid == 0) atomicOr(A.status, rstat == 1 ? 1 : (rstat == 2 ? 2 : 8));
+        const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, RS);
+        if (rstat && tid == 0) {
+            const int bit = rstat == kRedBaseFull    ? 1
+                            : rstat == kRedStoreFull ? 2
+                            : rstat == kRedFarFull   ? 32
+                            : rstat == kRedVFull     ? 64
+                                                     : 8;
+            atomicOr(A.status, bit);
+        }
         nb1 = RS.nbars;
         if (tid == 0) {
             rips_dim_stats &s1 = A.stats[(int64_t)b * D1 + 1];
@@ -589,16 +604,24 @@ __global__ void k_batch_copy(const int64_t *seg_start, const int64_t *seg_count,
     }
 }
 
-size_t batched_lds_bytes(bool lds_d, int nmax) {
+size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD) {
     const size_t npairs = (size_t)nmax * (nmax - 1) / 2;
     const size_t dpart = lds_d ? (npairs * 4 + 15) / 16 * 16 : 0;
     const size_t uf = (size_t)nmax * (8 + 4 + 4) + (lds_d ? (npairs / 32 + 1) * 4 : 0);
-    const size_t red = (size_t)kBatchCapR * 20;
-    return std::max(dpart + uf, red);
+    return std::max(dpart + uf, reduce_lds_bytes(capD));
 }
 
-hipError_t batched_prepare(bool lds_d, int nmax) {
-    const size_t lds = batched_lds_bytes(lds_d, nmax);
+// the largest delta that does not raise the kernel's LDS beyond what its
+// distance phase needs (at least 1024 slots)
+u32 batched_default_capD(bool lds_d, int nmax) {
+    const size_t base = batched_lds_bytes(lds_d, nmax, 256);
+    u32 c = 1024;
+    while (c < 4096 && reduce_lds_bytes(c * 2) <= base) c *= 2;
+    return c;
+}
+
+hipError_t batched_prepare(bool lds_d, int nmax, u32 capD) {
+    const size_t lds = batched_lds_bytes(lds_d, nmax, capD);
     return hipFuncSetAttribute(lds_d ? (const void *)k_batched<DistPacked>
                                      : (const void *)k_batched<DistFull>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -608,7 +631,7 @@ void launch_batched(const BatchArgs &A, bool lds_d, int grid, SortBufs lpt, hipS
     hipLaunchKernelGGL(k_batch_status_reset, dim3(1), dim3(1), 0, st, A.status);
     hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, st, A.offsets, A.B, lpt,
                        (int *)A.order, A.queue, A.ucount, A.status, A.nmax);
-    const size_t lds = batched_lds_bytes(lds_d, A.nmax);
+    const size_t lds = batched_lds_bytes(lds_d, A.nmax, A.capD);
     if (lds_d) hipLaunchKernelGGL(k_batched<DistPacked>, dim3(grid), dim3(kBT), lds, st, A);
     else hipLaunchKernelGGL(k_batched<DistFull>, dim3(grid), dim3(kBT), lds, st, A);
 }

@@ -43,11 +43,22 @@ struct BatchArgs {
     unsigned long long *v_count; // per workgroup
     u32 *bits_g;             // forest-edge bitmap per workgroup (global variant)
     int64_t bits_stride;
-    int64_t *rg_keys;
-    u32 *rg_coef;
-    float *rg_diam;
-    u32 *rg_slots;
-    int64_t rg_stride;       // global working-column slots per workgroup (power of two)
+    int64_t *sb_idx[2];      // sorted base of the working column, two buffers
+    float *sb_dia[2];
+    u32 *sb_coef[2];
+    int64_t sb_stride;       // sorted-base entries per workgroup and buffer
+    u32 capD;                // LDS delta slots of the working column (power of two)
+    int64_t *f_idx[2];       // far list of the working column, two buffers
+    float *f_dia[2];
+    u32 *f_coef[2];
+    int64_t f_stride;        // far-list entries per workgroup and buffer
+    int64_t *vw_keys;        // working V column (table)
+    u32 *vw_coef;
+    float *vw_diam;
+    u32 *vw_slots;
+    int64_t vw_stride;       // its slots per workgroup (power of two)
+    int64_t *v_roff;         // per column: stored R_j, if any
+    int *v_rlen;
     float *st_b, *st_d;      // staged bars of the current cloud
     int64_t *st_bs, *st_ds;
     int64_t st_stride;       // nmax + C(nmax, 2)
@@ -63,8 +74,9 @@ struct BatchArgs {
 };
 
 
-size_t batched_lds_bytes(bool lds_d, int nmax);
-hipError_t batched_prepare(bool lds_d, int nmax);
+size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD);
+u32 batched_default_capD(bool lds_d, int nmax);
+hipError_t batched_prepare(bool lds_d, int nmax, u32 capD);
 void launch_batched(const BatchArgs &A, bool lds_d, int grid, SortBufs lpt, hipStream_t st);
 void launch_batch_finalize(const BatchArgs &A, int64_t *offsets_out, int64_t *total, int64_t cap,
                            float *ob, float *od, int64_t *obs, int64_t *ods, hipStream_t st);

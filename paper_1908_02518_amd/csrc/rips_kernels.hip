@@ -681,33 +681,21 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_columns(Columns in, Scala
 
 // ---------------------------------------------------------------------------
 // Reduction of the surviving columns over Z/p: one workgroup runs
-// reduce_columns (rips_reduce.hpp) over the sorted columns of one dimension.
-// The working columns live in LDS (kGlobal = false) or, when they outgrow
-// it, in global scratch.
+// reduce_columns (rips_reduce.hpp) over the sorted columns of one dimension,
+// with the working column's delta in LDS and its sorted base in global
+// scratch.
 // ---------------------------------------------------------------------------
 template <class Dist>
-__global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, WorkCol Rl, WorkCol Rg,
-                                                       Scalars *s) {
+__global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 capD,
+                                                       ReduceScratch SC, Scalars *s) {
     extern __shared__ unsigned char smem[];
     __shared__ RedShared<kRedThreads> S;
-    __shared__ int s_ns[2];
-    WorkCol R = Rl, RG = Rg;
-    R.nslots = &s_ns[0];
-    RG.nslots = &s_ns[1];
-    if (Rl.mask != 0) {
-        unsigned char *q = smem;
-        const size_t cr = (size_t)Rl.mask + 1;
-        R.keys = (int64_t *)q;
-        q += cr * 8;
-        R.coef = (u32 *)q;
-        q += cr * 4;
-        R.diam = (float *)q;
-        q += cr * 4;
-        R.slots = (u32 *)q;
-    } else {
-        R.keys = nullptr;
-    }
-    const int status = reduce_columns<kRedThreads>(J, R, RG, S);
+    __shared__ int s_ns;
+    WorkCol D;
+    Staging G;
+    carve_reduce_lds(smem, capD, &s_ns, &D, &G);
+    SC.Vw.nslots = &S.vns;
+    const int status = reduce_columns<kRedThreads>(J, D, G, SC, S);
     if (threadIdx.x == 0) {
         s->status = status;
         s->nbars = S.nbars;
@@ -849,20 +837,13 @@ void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Colu
                        out);
 }
 
-size_t reduce_lds_bytes(u32 capR) { return (size_t)capR * 20; }
-
-hipError_t launch_reduce(const ReduceJob<DistFull> &J, WorkCol Rl, WorkCol Rg, int use_lds,
-                         Scalars *s, hipStream_t st) {
-    size_t lds = 0;
-    if (use_lds) {
-        lds = reduce_lds_bytes(Rl.mask + 1);
-        hipError_t e = hipFuncSetAttribute((const void *)k_reduce<DistFull>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-    } else {
-        Rl.mask = 0;
-    }
-    hipLaunchKernelGGL((k_reduce<DistFull>), dim3(1), dim3(kRedThreads), lds, st, J, Rl, Rg, s);
+hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceScratch SC, Scalars *s,
+                         hipStream_t st) {
+    const size_t lds = reduce_lds_bytes(capD);
+    hipError_t e = hipFuncSetAttribute((const void *)k_reduce<DistFull>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reduce<DistFull>), dim3(1), dim3(kRedThreads), lds, st, J, capD, SC, s);
     return hipGetLastError();
 }
 

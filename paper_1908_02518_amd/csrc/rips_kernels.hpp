@@ -60,11 +60,17 @@ struct Columns {
 // Reduced columns R_j of the non-emergent death columns, kept once column j
 // is final: an addition of column o then touches |R_o| entries. Emergent
 // columns keep len = -1: their R_o is the coboundary of sigma_o (implicit).
+// Stored columns of the reduction. Column j keeps V_j (the simplices whose
+// coboundaries sum to R_j) and, when that is cheaper to add later, R_j
+// itself. Entries (simplex index, diameter, coefficient) live in one append
+// pool.
 struct VStore {
-    int64_t *off;   // per column
-    int *len;
+    int64_t *off;   // per column: V_j in the pool
+    int *len;       // -1: V_j is the column's own simplex (emergent pair)
+    int64_t *roff;  // per column: R_j in the pool
+    int *rlen;      // -1: R_j not stored
     u32 *pivcoef;   // pivot entry of R_j
-    int64_t *idx;   // append buffer of (cofacet index, diameter, coefficient)
+    int64_t *idx;   // append pool
     float *diam;
     u32 *coef;
     int64_t cap;

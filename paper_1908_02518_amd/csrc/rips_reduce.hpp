@@ -3,24 +3,123 @@
 // coboundary matrix of one dimension, columns already cleared; the emergent
 // shortcut; pivot lookup = pivot table, then zero apparent facet). Used by
 // the single-cloud kernel and by the batched persistent kernel.
+//
+// Stored columns (the implicit representation of the paper's reduction
+// section): column j keeps V_j, the combination of simplices whose
+// coboundaries sum to its reduced column R_j, and re-enumerates those
+// coboundaries when R_j is added to a later column. R_j itself is kept as
+// well when it is cheaper to add than to recompute.
+//
+// The working column R_j is split at a diameter bound kd:
+//  - near part (diameter <= kd): a delta D in LDS (open addressing keyed by
+//    simplex index, with the list of used slots; every near addition goes
+//    here) plus a sorted base S in global memory (age ascending: diameter
+//    ascending, then index descending) read from a front pointer f;
+//  - far part (diameter > kd): an unsorted append-only list F in global
+//    memory; repeated keys are combined only when they are pulled in.
+// The pivot of R_j is its oldest entry with a nonzero coefficient, so it is
+// in the near part whenever the near part has a live entry. During the
+// reduction of one column the pivot only moves to younger rows (an addition
+// cancels the pivot and brings in younger entries only), so entries of S
+// before f are dead for good. Maintenance:
+//  - D holds more than an eighth of its slots: its live entries are sorted
+//    in LDS and merged into S;
+//  - S holds more than capD live entries: kd drops to the diameter in the
+//    middle of S and the tail moves to F;
+//  - the near part has no live entry: kd rises (a diameter histogram of F
+//    picks the bound) and the entries under it move from F into D.
+// Each entry is thus touched O(1) times in the far list and the near part
+// stays small, whatever the size of the column.
 #pragma once
 
 #include "rips_kernels.hpp"
 
 namespace rips {
 
-// Working column (R_j or V_j): open addressing keyed by simplex index plus
-// the list of used slots, so that pivot search, clearing and compaction cost
-// O(entries touched) instead of O(capacity). Coefficients accumulate with
-// atomics and are reduced mod p when read (XOR for p = 2).
 struct WorkCol {
     int64_t *keys;
     u32 *coef;
-    float *diam; // null for V (diameters recomputed when needed)
+    float *diam;
     u32 *slots;
     int *nslots; // in LDS
     u32 mask;
 };
+
+// Merge staging in LDS (capacity = a quarter of the delta's slots).
+struct Staging {
+    int64_t *idx;
+    float *dia;
+    u32 *coef;
+    u32 *cnt; // cap + 1
+    int *nd;  // cap + 1
+    int cap;
+};
+
+// Sorted base in global memory, two buffers of cap entries each.
+struct SortedBase {
+    int64_t *idx[2];
+    float *dia[2];
+    u32 *coef[2];
+    int64_t cap;
+};
+
+// Far list in global memory, two buffers of cap entries each.
+struct FarList {
+    int64_t *idx[2];
+    float *dia[2];
+    u32 *coef[2];
+    int64_t cap;
+};
+
+// Global scratch of one workgroup's reduction: sorted base, far list and the
+// working V column (a global table; its slot count lives in LDS).
+struct ReduceScratch {
+    SortedBase SB;
+    FarList F;
+    WorkCol Vw;
+};
+
+// Result codes of the reduction.
+enum : int {
+    kRedOk = 0,
+    kRedBaseFull = 1,  // sorted base too small
+    kRedStoreFull = 2, // column store too small
+    kRedBound = 3,     // addition bound reached
+    kRedFarFull = 4,   // far list too small
+    kRedVFull = 5,     // working V table too small
+};
+
+// LDS bytes of a delta of capD slots and its staging.
+__host__ __device__ constexpr size_t reduce_lds_bytes(u32 capD) {
+    return (size_t)capD * 20 + (size_t)(capD / 4) * 16 + 2 * ((size_t)(capD / 4) + 1) * 4;
+}
+
+// Carve the delta and its staging out of an LDS block (capD a power of two,
+// at least 256).
+__device__ __forceinline__ void carve_reduce_lds(unsigned char *q, u32 capD, int *nslots,
+                                                 WorkCol *D, Staging *G) {
+    const size_t c = capD, m = capD / 4;
+    D->keys = (int64_t *)q;
+    q += c * 8;
+    G->idx = (int64_t *)q;
+    q += m * 8;
+    D->coef = (u32 *)q;
+    q += c * 4;
+    D->diam = (float *)q;
+    q += c * 4;
+    D->slots = (u32 *)q;
+    q += c * 4;
+    G->dia = (float *)q;
+    q += m * 4;
+    G->coef = (u32 *)q;
+    q += m * 4;
+    G->cnt = (u32 *)q;
+    q += (m + 1) * 4;
+    G->nd = (int *)q;
+    G->cap = (int)m;
+    D->nslots = nslots;
+    D->mask = capD - 1;
+}
 
 __device__ __forceinline__ bool wc_add(const WorkCol &h, int64_t key, float dm, u32 c, u32 p) {
     u32 s = mix64((u64)key) & h.mask;
@@ -30,7 +129,7 @@ __device__ __forceinline__ bool wc_add(const WorkCol &h, int64_t key, float dm, 
         if (!mine && cur == kEmpty) {
             const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
             if (prev == (u64)kEmpty) {
-                if (h.diam) h.diam[s] = dm;
+                h.diam[s] = dm;
                 const int q = atomicAdd(h.nslots, 1);
                 if ((u32)q <= h.mask) h.slots[q] = s;
                 mine = true;
@@ -46,6 +145,30 @@ __device__ __forceinline__ bool wc_add(const WorkCol &h, int64_t key, float dm, 
     return false;
 }
 
+// slot holding key, or -1
+__device__ __forceinline__ int wc_find(const WorkCol &h, int64_t key) {
+    u32 s = mix64((u64)key) & h.mask;
+    for (u32 probe = 0; probe <= h.mask; ++probe) {
+        const int64_t cur = ld(&h.keys[s]);
+        if (cur == key) return (int)s;
+        if (cur == kEmpty) return -1;
+        s = (s + 1) & h.mask;
+    }
+    return -1;
+}
+
+// one of two buffers, selected without indexing an array (which would put
+// the pointer pair in scratch memory)
+template <class T>
+__device__ __forceinline__ T *pick(T *const (&a)[2], int b) {
+    return b ? a[1] : a[0];
+}
+
+// Entry order: older first = (diameter ascending, index descending).
+__device__ __forceinline__ bool older_key(float da, int64_t ia, float db, int64_t ib) {
+    return da < db || (da == db && ia > ib);
+}
+
 // Everything the routine needs about one dimension of one cloud.
 template <class Dist>
 struct ReduceJob {
@@ -57,28 +180,37 @@ struct ReduceJob {
     int ncols;
     PivotHash ph;
     VStore V;
-    unsigned long long *vcount; // V append counter (global)
+    unsigned long long *vcount; // column-store append counter (global)
     BarBuf bars;                // capacity ncols
+    float cand_avg;             // mean coboundary candidates of a k-simplex
 };
 
 // Shared state of the routine (one per workgroup).
 template <int BT>
 struct RedShared {
-    int base, full, abort, m, nbars, nitems, total;
-    int64_t owner;
+    int base, full, abort, m, nbars, cur, merged, nit, vns, refine;
+    int fw, fwn;    // far list: buffer appended to, entries in it
+    int fr, nr;     // far list being pulled: buffer, entries
+    float kd, kdn;  // near bound, its next value
+    int64_t len, f; // sorted base: length and front
+    int64_t owner, qsplit;
+    u32 lo, bound;
+    int shift;
     unsigned long long vbase;
     PivotCand wp[BT / kWave];
-    PivotCand piv;
+    PivotCand piv, spiv;
     int w[BT / kWave + 1];
+    u32 mm[2][BT / kWave];
     unsigned long long stat[8];
-    // one batch of coboundaries to add: simplex, coefficient, candidate
-    // source and prefix offsets into the flattened (item, candidate) space
-    int64_t it_idx[BT];
-    u32 it_coef[BT];
+    u32 hist[256];
+    // simplices whose coboundaries are added next: vertices, coefficient,
+    // diameter, candidate source (vertex with the fewest neighbours, -1 =
+    // all vertices) and prefix offsets of their candidate counts
     int it_v[BT][kMaxDim + 1];
+    u32 it_coef[BT];
     float it_diam[BT];
-    int it_off[BT + 1];
     int it_u[BT];
+    int it_off[BT + 1];
 };
 
 template <int BT>
@@ -107,83 +239,37 @@ __device__ __forceinline__ int block_scan_excl(int x, int *s_w, int *total) {
     return r;
 }
 
-// Barrier of the routine: a plain workgroup barrier while the working
-// columns live in LDS, a fenced one when they live in global memory.
-__device__ __forceinline__ void rsync(bool global) {
-    if (global) gsync();
-    else __syncthreads();
-}
-
-// Add the coboundaries of S.nitems simplices (S.it_*) with their
-// coefficients to R: the (item, candidate) pairs are spread over the whole
-// workgroup. Dense candidates: all n vertices; sparse: the neighbours of the
-// item's vertex with the fewest neighbours. Coefficient of sigma u {j}:
-// (-1)^(vertices of sigma below j) times the item's coefficient.
-template <int BT, class Dist>
-__device__ bool add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &R) {
-    const Ctx<Dist> &c = J.c;
-    const int k = J.k;
-    const u32 p = J.p;
-    const int tid = threadIdx.x;
-    // per item: candidate source and count
-    int cnt = 0;
-    if (tid < S.nitems) {
-        if (c.nb.off == nullptr) {
-            cnt = c.n;
-            S.it_u[tid] = -1;
-        } else {
-            int u = S.it_v[tid][0];
-            int du = c.nb.off[u + 1] - c.nb.off[u];
-            for (int m = 1; m <= k; ++m) {
-                const int vm = S.it_v[tid][m];
-                const int dd = c.nb.off[vm + 1] - c.nb.off[vm];
-                if (dd < du) {
-                    du = dd;
-                    u = vm;
-                }
-            }
-            S.it_u[tid] = u;
-            cnt = du;
-        }
-    }
-    int total;
-    const int off = block_scan_excl<BT>(cnt, S.w, &total);
-    if (tid < S.nitems) S.it_off[tid] = off;
-    if (tid == 0) S.it_off[S.nitems] = total;
-    __syncthreads();
-    bool ok = true;
-    for (int f = tid; f < total; f += BT) {
-        // item holding flat index f: last it with it_off[it] <= f
-        int lo = 0, hi = S.nitems - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (S.it_off[mid] <= f) lo = mid;
-            else hi = mid - 1;
-        }
-        const int it = lo;
-        const int q = f - S.it_off[it];
-        const int u = S.it_u[it];
-        const int j = u < 0 ? q : c.nb.idx[c.nb.off[u] + q];
-        const int *v = S.it_v[it];
-        bool in = false;
-        float nd = S.it_diam[it];
-        for (int m = 0; m <= k; ++m) {
-            in = in || (j == v[m]);
-            nd = fmaxf(nd, c.d(v[m], j));
-        }
-        if (in || !(nd <= c.t)) continue;
-        int below;
-        const int64_t ci = cofacet_index(v, k, j, c.B, &below);
-        const u32 coef = S.it_coef[it];
-        const u32 cc = (below & 1) ? (p - coef) % p : coef;
-        ok = ok && wc_add(R, ci, nd, cc, p);
-    }
-    return ok;
-}
-
-// Oldest nonzero entry of R (block-wide); coefficients normalised mod p.
+// ---------------------------------------------------------------------------
+// tables (all threads of the block)
+// ---------------------------------------------------------------------------
 template <int BT>
-__device__ PivotCand wc_pivot(const WorkCol &R, u32 p, RedShared<BT> &S, bool g) {
+__device__ void wc_reset(const WorkCol &h) {
+    const int ns = min(*h.nslots, (int)h.mask + 1);
+    for (int i = threadIdx.x; i < ns; i += BT) {
+        const u32 s = h.slots[i];
+        st(&h.keys[s], kEmpty);
+        st(&h.coef[s], 0u);
+    }
+    gsync();
+    if (threadIdx.x == 0) *h.nslots = 0;
+    __syncthreads();
+}
+
+template <int BT>
+__device__ void wc_clear_all(const WorkCol &h) {
+    for (u32 q = threadIdx.x; q <= h.mask; q += BT) {
+        st(&h.keys[q], kEmpty);
+        st(&h.coef[q], 0u);
+    }
+    gsync();
+    if (threadIdx.x == 0) *h.nslots = 0;
+    __syncthreads();
+}
+
+// Oldest live entry of the delta (block-wide). Coefficients are normalised
+// mod p on the way (no addition runs concurrently).
+template <int BT>
+__device__ PivotCand wc_oldest(const WorkCol &R, u32 p, RedShared<BT> &S) {
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     PivotCand best;
     best.idx = kEmpty;
@@ -206,117 +292,625 @@ __device__ PivotCand wc_pivot(const WorkCol &R, u32 p, RedShared<BT> &S, bool g)
     }
     best = wave_oldest(best);
     if (lane == 0) S.wp[w] = best;
-    rsync(g);
+    __syncthreads();
     if (tid == 0) {
         PivotCand b = S.wp[0];
         for (int q = 1; q < BT / kWave; ++q)
             if (older(S.wp[q], b)) b = S.wp[q];
         S.piv = b;
     }
-    rsync(g);
+    __syncthreads();
     return S.piv;
 }
 
-// Empty the used slots of a working column.
+// Append an entry to the far list (any thread). False when it is full.
 template <int BT>
-__device__ void wc_reset(const WorkCol &h, bool g) {
-    const int ns = min(*h.nslots, (int)h.mask + 1);
-    for (int i = threadIdx.x; i < ns; i += BT) {
-        const u32 s = h.slots[i];
-        st(&h.keys[s], kEmpty);
-        st(&h.coef[s], 0u);
-    }
-    rsync(g);
-    if (threadIdx.x == 0) *h.nslots = 0;
-    rsync(g);
+__device__ __forceinline__ bool far_append(const FarList &F, RedShared<BT> &S, int64_t key,
+                                           float dm, u32 c) {
+    const int pos = atomicAdd(&S.fwn, 1);
+    if ((int64_t)pos >= F.cap) return false;
+    const int b = S.fw;
+    pick(F.idx, b)[pos] = key;
+    pick(F.dia, b)[pos] = dm;
+    pick(F.coef, b)[pos] = c;
+    return true;
 }
 
-// Empty a whole table (its contents are unknown).
+// Add an entry of the working column: near -> delta, far -> far list.
+// Returns 0 or a result code.
 template <int BT>
-__device__ void wc_clear_all(const WorkCol &h, bool g) {
-    for (u32 q = threadIdx.x; q <= h.mask; q += BT) {
-        st(&h.keys[q], kEmpty);
-        st(&h.coef[q], 0u);
-    }
-    rsync(g);
-    if (threadIdx.x == 0) *h.nslots = 0;
-    rsync(g);
+__device__ __forceinline__ int add_entry(const WorkCol &D, const FarList &F, RedShared<BT> &S,
+                                         int64_t key, float dm, u32 c, u32 p) {
+    if (dm <= S.kd) return wc_add(D, key, dm, c, p) ? kRedOk : kRedBaseFull;
+    return far_append<BT>(F, S, key, dm, c) ? kRedOk : kRedFarFull;
 }
 
-// Drop the entries whose coefficient cancelled to zero once more than half
-// the table is in use. Each thread moves at most kPer entries; tables hold at
-// most 2 * kPer * BT slots.
-template <int BT, int kPer>
-__device__ void wc_compact(const WorkCol &h, u32 p, int *nslots_shared, bool g) {
-    const int ns = min(*h.nslots, (int)h.mask + 1);
-    if (2 * ns <= (int)h.mask + 1) return;
-    if ((int)h.mask + 1 > 2 * kPer * BT) return; // larger tables are not compacted
-    int64_t kk[kPer];
-    u32 cc[kPer];
-    float dd[kPer];
-    int mine = 0;
-    for (int i = threadIdx.x; i < ns && mine < kPer; i += BT) {
-        const u32 s = h.slots[i];
-        const u32 cf = ld(&h.coef[s]) % p;
+// ---------------------------------------------------------------------------
+// sorted base
+// ---------------------------------------------------------------------------
+
+// Wave 0 moves the front of S past entries whose total coefficient (S + D)
+// is zero; the delta's copies of those keys are zeroed, since their part of
+// the sum is spent. S.spiv = the first live entry with its total, if any.
+template <int BT>
+__device__ void base_advance(const WorkCol &D, const SortedBase &SB, u32 p, RedShared<BT> &S) {
+    if (threadIdx.x >= kWave) return;
+    const int lane = lane_id();
+    const int cur = S.cur;
+    int64_t f = S.f;
+    const int64_t len = S.len;
+    PivotCand out;
+    out.idx = kEmpty;
+    out.diam = 0.0f;
+    out.coef = 0;
+    while (f < len) {
+        const int64_t q = f + lane;
+        const bool valid = q < len;
+        u32 total = 0;
+        int slot = -1;
+        int64_t id = 0;
+        float dm = 0.0f;
+        if (valid) {
+            id = pick(SB.idx, cur)[q];
+            dm = pick(SB.dia, cur)[q];
+            const u32 cs = pick(SB.coef, cur)[q];
+            slot = wc_find(D, id);
+            const u32 cd = slot >= 0 ? ld(&D.coef[slot]) % p : 0u;
+            total = (cs + cd) % p;
+        }
+        const u64 live = __ballot(valid && total != 0);
+        const int first = live ? __ffsll((unsigned long long)live) - 1 : kWave;
+        if (valid && lane < first && slot >= 0) st(&D.coef[slot], 0u);
+        if (live) {
+            out.idx = __shfl(id, first, kWave);
+            out.diam = __shfl(dm, first, kWave);
+            out.coef = __shfl(total, first, kWave);
+            f += first;
+            break;
+        }
+        f += kWave;
+    }
+    if (f > len) f = len;
+    if (lane == 0) {
+        S.f = f;
+        S.spiv = out;
+    }
+}
+
+// Merge the live entries of D into S[f, len) (all threads); D is empty
+// afterwards. Returns 0 or a result code.
+template <int BT>
+__device__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &SB, u32 p,
+                          RedShared<BT> &S) {
+    const int tid = threadIdx.x;
+    const int ns = min(*D.nslots, (int)D.mask + 1);
+    // 1. gather the live entries into the staging area, unsorted
+    int cnt = 0;
+    for (int i = tid; i < ns; i += BT) cnt += (ld(&D.coef[D.slots[i]]) % p) != 0 ? 1 : 0;
+    int m;
+    int at = block_scan_excl<BT>(cnt, S.w, &m);
+    if (m > G.cap) return kRedBaseFull; // cannot happen: D holds at most G.cap slots here
+    const int64_t f = S.f, sl = S.len - S.f;
+    if (sl + m > SB.cap) return kRedBaseFull;
+    for (int i = tid; i < ns; i += BT) {
+        const u32 s = D.slots[i];
+        const u32 cf = ld(&D.coef[s]) % p;
         if (cf != 0) {
-            kk[mine] = ld(&h.keys[s]);
-            cc[mine] = cf;
-            dd[mine] = h.diam ? h.diam[s] : 0.0f;
-            ++mine;
+            G.idx[at] = ld(&D.keys[s]);
+            G.dia[at] = D.diam[s];
+            G.coef[at] = cf;
+            ++at;
         }
     }
-    rsync(g);
-    for (int i = threadIdx.x; i < ns; i += BT) {
-        const u32 s = h.slots[i];
-        st(&h.keys[s], kEmpty);
-        st(&h.coef[s], 0u);
+    __syncthreads();
+    // 2. sort by rank (keys are distinct): M = D's first m slots
+    int64_t *Mi = D.keys;
+    float *Md = D.diam;
+    u32 *Mc = D.coef;
+    for (int e = tid; e < m; e += BT) {
+        const int64_t ie = G.idx[e];
+        const float de = G.dia[e];
+        int r = 0;
+        for (int q = 0; q < m; ++q) r += older_key(G.dia[q], G.idx[q], de, ie) ? 1 : 0;
+        Mi[r] = ie;
+        Md[r] = de;
+        Mc[r] = G.coef[e];
     }
-    rsync(g);
-    if (threadIdx.x == 0) *nslots_shared = 0;
-    rsync(g);
-    for (int q = 0; q < mine; ++q) wc_add(h, kk[q], dd[q], cc[q], p);
-    rsync(g);
+    for (int i = tid; i <= m; i += BT) G.cnt[i] = 0;
+    __syncthreads();
+    // 3. every base entry: lower bound in M (first entry not older than
+    // it), and the duplicate flag (bit 31 of M's coefficient)
+    const int cur = S.cur, nxt = cur ^ 1;
+    for (int64_t r = tid; r < sl; r += BT) {
+        const int64_t id = pick(SB.idx, cur)[f + r];
+        const float dm = pick(SB.dia, cur)[f + r];
+        int lo = 0, hi = m;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (older_key(Md[mid], Mi[mid], dm, id)) lo = mid + 1;
+            else hi = mid;
+        }
+        atomicAdd(&G.cnt[lo], 1u);
+        if (lo < m && Mi[lo] == id) atomicOr(&Mc[lo], 0x80000000u);
+    }
+    __syncthreads();
+    // 4. inclusive prefix of the counts (base entries older than M[i] for a
+    // non-duplicate i), exclusive prefix of the non-duplicates
+    int carry_c = 0, carry_n = 0;
+    for (int b0 = 0; b0 <= m; b0 += BT) {
+        const int i = b0 + tid;
+        const int c = i <= m ? (int)G.cnt[i] : 0;
+        const int nd = i < m ? ((ld(&Mc[i]) & 0x80000000u) ? 0 : 1) : 0;
+        int tc, tn;
+        const int ec = block_scan_excl<BT>(c, S.w, &tc);
+        const int en = block_scan_excl<BT>(nd, S.w, &tn);
+        if (i <= m) {
+            G.cnt[i] = (u32)(carry_c + ec + c);
+            G.nd[i] = carry_n + en;
+        }
+        carry_c += tc;
+        carry_n += tn;
+    }
+    __syncthreads();
+    // 5. scatter: base entry r goes to r + (non-duplicates before its lower
+    // bound); non-duplicate M[i] goes to (base entries older) + (non-
+    // duplicates before it)
+    for (int64_t r = tid; r < sl; r += BT) {
+        const int64_t id = pick(SB.idx, cur)[f + r];
+        const float dm = pick(SB.dia, cur)[f + r];
+        u32 cf = pick(SB.coef, cur)[f + r];
+        int lo = 0, hi = m;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (older_key(Md[mid], Mi[mid], dm, id)) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < m && Mi[lo] == id) cf = (cf + (Mc[lo] & 0x7fffffffu)) % p;
+        const int64_t dst = r + G.nd[lo];
+        pick(SB.idx, nxt)[dst] = id;
+        pick(SB.dia, nxt)[dst] = dm;
+        pick(SB.coef, nxt)[dst] = cf;
+    }
+    for (int i = tid; i < m; i += BT) {
+        const u32 cf = Mc[i];
+        if (cf & 0x80000000u) continue;
+        const int64_t dst = (int64_t)G.cnt[i] + G.nd[i];
+        pick(SB.idx, nxt)[dst] = Mi[i];
+        pick(SB.dia, nxt)[dst] = Md[i];
+        pick(SB.coef, nxt)[dst] = cf;
+    }
+    const int nondup = carry_n;
+    gsync();
+    if (tid == 0) {
+        S.cur = nxt;
+        S.f = 0;
+        S.len = sl + nondup;
+        S.merged = 1;
+    }
+    wc_clear_all<BT>(D);
+    return kRedOk;
 }
 
-// Full reduction of column j with the working column R. Returns 0 when
-// done, 1 on working-column overflow (nothing of column j has been published
-// then), 2 on column store overflow, 3 on the addition bound.
-template <int BT, class Dist>
-__device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &R, bool g, int j,
+// S longer than smax live entries: lower kd to the diameter in the middle
+// of S and move the entries above it to the far list (D is empty here).
+template <int BT>
+__device__ int base_split(const SortedBase &SB, const FarList &F, u32 p, int smax,
                           RedShared<BT> &S) {
-    constexpr int kPer = 16;
+    const int tid = threadIdx.x;
+    if (S.len - S.f <= smax) return kRedOk;
+    const int cur = S.cur;
+    if (tid == 0) {
+        const int64_t q0 = S.f + smax / 2;
+        const float kd = pick(SB.dia, cur)[q0];
+        int64_t lo = q0, hi = S.len; // first entry with a larger diameter
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (pick(SB.dia, cur)[mid] > kd) hi = mid;
+            else lo = mid + 1;
+        }
+        S.qsplit = lo;
+        S.kdn = kd;
+    }
+    __syncthreads();
+    const int64_t q = S.qsplit, len = S.len;
+    const float kd = S.kdn;
+    __syncthreads();
+    if (q >= len) return kRedOk; // one diameter from the middle on: keep it all
+    bool ok = true;
+    for (int64_t r = q + tid; r < len; r += BT) {
+        const u32 cf = pick(SB.coef, cur)[r] % p;
+        if (cf != 0) ok = ok && far_append<BT>(F, S, pick(SB.idx, cur)[r], pick(SB.dia, cur)[r], cf);
+    }
+    if (!ok) S.abort = kRedFarFull;
+    gsync();
+    if (S.abort) return S.abort;
+    if (tid == 0) {
+        S.len = q;
+        S.kd = kd;
+        S.merged = 1;
+    }
+    __syncthreads();
+    return kRedOk;
+}
+
+// keep D at most an eighth full and S at most capD live entries
+template <int BT>
+__device__ __forceinline__ int delta_check(const WorkCol &D, const Staging &G,
+                                           const ReduceScratch &SC, u32 p, RedShared<BT> &S) {
+    const int capD = (int)D.mask + 1;
+    if (*D.nslots <= capD / 8) return kRedOk;
+    int r = base_merge<BT>(D, G, SC.SB, p, S);
+    if (r) return r;
+    return base_split<BT>(SC.SB, SC.F, p, capD, S);
+}
+
+// The near part is empty and the far list is not: raise kd so that about
+// `target` far entries fall under it (a diameter histogram over the bits
+// of the non-negative float diameters, refined while one bin is far too
+// full), and move those entries into the delta.
+template <int BT>
+__device__ int far_pull(const WorkCol &D, const Staging &G, const ReduceScratch &SC, u32 p,
+                        int target, RedShared<BT> &S) {
+    const FarList &F = SC.F;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    if (tid == 0) {
+        S.fr = S.fw;
+        S.nr = S.fwn;
+        S.fw = S.fw ^ 1;
+        S.fwn = 0;
+        S.merged = 1;
+    }
+    __syncthreads();
+    const int fr = S.fr, nr = S.nr;
+    // 1. smallest and largest diameter bits
+    u32 mn = 0xffffffffu, mx = 0;
+    for (int r = tid; r < nr; r += BT) {
+        const u32 b = __float_as_uint(pick(F.dia, fr)[r]);
+        mn = min(mn, b);
+        mx = max(mx, b);
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        mn = min(mn, (u32)__shfl_xor((int)mn, o, kWave));
+        mx = max(mx, (u32)__shfl_xor((int)mx, o, kWave));
+    }
+    if (lane == 0) {
+        S.mm[0][w] = mn;
+        S.mm[1][w] = mx;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        u32 a = S.mm[0][0], b = S.mm[1][0];
+        for (int q = 1; q < BT / kWave; ++q) {
+            a = min(a, S.mm[0][q]);
+            b = max(b, S.mm[1][q]);
+        }
+        const u32 span = b - a;
+        const int nb = span ? 32 - __clz(span) : 0;
+        S.lo = a;
+        S.shift = nb > 8 ? nb - 8 : 0;
+        S.bound = b;
+        S.refine = 1;
+    }
+    __syncthreads();
+    // 2. pick the bound: bins of 2^shift bit patterns from lo
+    int below = 0; // entries under S.lo (all pulled)
+    while (S.refine) {
+        for (int i = tid; i < 256; i += BT) S.hist[i] = 0;
+        __syncthreads();
+        const u32 lo = S.lo;
+        const int sh = S.shift;
+        for (int r = tid; r < nr; r += BT) {
+            const u32 b = __float_as_uint(pick(F.dia, fr)[r]);
+            if (b < lo) continue;
+            const u32 bin = (b - lo) >> sh;
+            if (bin < 256) atomicAdd(&S.hist[bin], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int cum = below, i = 0;
+            for (; i < 256; ++i) {
+                cum += (int)S.hist[i];
+                if (cum >= target) break;
+            }
+            if (i == 256) i = 255;
+            const int before = cum - (int)S.hist[i];
+            if (cum > 8 * target && sh > 0 && S.hist[i] > 1) {
+                // bin i alone is far too full: split it
+                S.lo = lo + ((u32)i << sh);
+                S.shift = sh > 8 ? sh - 8 : 0;
+                S.nr = before; // reuse as the running count below lo
+            } else {
+                const u64 top = (u64)lo + ((u64)(i + 1) << sh) - 1;
+                S.bound = top > 0xffffffffull ? 0xffffffffu : (u32)top;
+                S.refine = 0;
+            }
+        }
+        __syncthreads();
+        below = S.refine ? S.nr : below;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        S.kd = __uint_as_float(S.bound);
+        S.nr = nr;
+    }
+    __syncthreads();
+    // 3. move the entries under the bound into D, keep the rest, in segments
+    const int seg = ((int)D.mask + 1) / 8;
+    for (int s0 = 0; s0 < nr; s0 += seg) {
+        const int s1 = min(nr, s0 + seg);
+        int bad = 0;
+        for (int r = s0 + tid; r < s1; r += BT) {
+            const int rr = add_entry<BT>(D, F, S, pick(F.idx, fr)[r], pick(F.dia, fr)[r], pick(F.coef, fr)[r], p);
+            if (rr) bad = rr;
+        }
+        if (bad) S.abort = bad;
+        gsync();
+        if (S.abort) return S.abort;
+        const int r = delta_check<BT>(D, G, SC, p, S);
+        if (r) return r;
+    }
+    return kRedOk;
+}
+
+// ---------------------------------------------------------------------------
+// additions
+// ---------------------------------------------------------------------------
+
+// Add the coboundaries of the S.nit simplices in S.it_* (each times its
+// coefficient) to the working column. The (item, candidate) pairs are spread
+// over the workgroup, in segments of an eighth of D with maintenance
+// between. Cofacet sigma u {j} gets (-1)^(vertices of sigma below j) times
+// the item's coefficient. Dense candidates: all vertices; sparse: the
+// neighbours of the item's vertex with the fewest.
+template <int BT, class Dist>
+__device__ int add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
+                         const Staging &G, const ReduceScratch &SC) {
+    const Ctx<Dist> &c = J.c;
+    const int k = J.k;
+    const u32 p = J.p;
+    const int tid = threadIdx.x;
+    const int nit = S.nit;
+    int cnt = 0;
+    if (tid < nit) {
+        if (c.nb.off == nullptr) {
+            S.it_u[tid] = -1;
+            cnt = c.n;
+        } else {
+            int u = S.it_v[tid][0];
+            int du = c.nb.off[u + 1] - c.nb.off[u];
+            for (int m = 1; m <= k; ++m) {
+                const int vm = S.it_v[tid][m];
+                const int dd = c.nb.off[vm + 1] - c.nb.off[vm];
+                if (dd < du) {
+                    du = dd;
+                    u = vm;
+                }
+            }
+            S.it_u[tid] = u;
+            cnt = du;
+        }
+    }
+    int total;
+    const int off = block_scan_excl<BT>(cnt, S.w, &total);
+    if (tid < nit) S.it_off[tid] = off;
+    if (tid == 0) S.it_off[nit] = total;
+    __syncthreads();
+    const int seg = ((int)D.mask + 1) / 8;
+    for (int s0 = 0; s0 < total; s0 += seg) {
+        const int s1 = min(total, s0 + seg);
+        int bad = 0;
+        for (int fl = s0 + tid; fl < s1; fl += BT) {
+            int lo = 0, hi = nit - 1; // last item with it_off <= fl
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (S.it_off[mid] <= fl) lo = mid;
+                else hi = mid - 1;
+            }
+            const int it = lo;
+            const int q = fl - S.it_off[it];
+            const int u = S.it_u[it];
+            const int j = u < 0 ? q : c.nb.idx[c.nb.off[u] + q];
+            const int *v = S.it_v[it];
+            bool in = false;
+            float nd = S.it_diam[it];
+            for (int m = 0; m <= k; ++m) {
+                in = in || (j == v[m]);
+                nd = fmaxf(nd, c.d(v[m], j));
+            }
+            if (in || !(nd <= c.t)) continue;
+            int below;
+            const int64_t ci = cofacet_index(v, k, j, c.B, &below);
+            const u32 coef = S.it_coef[it];
+            const u32 cc = (below & 1) ? (p - coef) % p : coef;
+            const int rr = add_entry<BT>(D, SC.F, S, ci, nd, cc, p);
+            if (rr) bad = rr;
+        }
+        if (bad) S.abort = bad;
+        gsync();
+        if (S.abort) return S.abort;
+        const int r = delta_check<BT>(D, G, SC, p, S);
+        if (r) return r;
+    }
+    __syncthreads(); // the items are read before anyone rewrites them
+    return kRedOk;
+}
+
+// Add mul times the coboundaries of the simplices of a stored V column.
+template <int BT, class Dist>
+__device__ int add_vcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
+                           const Staging &G, const ReduceScratch &SC, int64_t off, int len,
+                           u32 mul) {
+    const int tid = threadIdx.x;
+    const u32 p = J.p;
+    for (int c0 = 0; c0 < len; c0 += BT) {
+        const int nit = min(BT, len - c0);
+        if (tid < nit) {
+            const int64_t e = off + c0 + tid;
+            decode(J.V.idx[e], J.k, J.c.n, J.c.B, S.it_v[tid]);
+            S.it_diam[tid] = J.V.diam[e];
+            S.it_coef[tid] = (u32)((u64)mul * J.V.coef[e] % p);
+        }
+        if (tid == 0) S.nit = nit;
+        __syncthreads();
+        const int r = add_items<BT>(J, S, D, G, SC);
+        if (r) return r;
+    }
+    return kRedOk;
+}
+
+// Add neg times the stored R column entries [off, off + len), in segments.
+template <int BT, class Dist>
+__device__ int add_rcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
+                           const Staging &G, const ReduceScratch &SC, int64_t off, int len,
+                           u32 neg) {
+    const u32 p = J.p;
+    const int seg = ((int)D.mask + 1) / 8;
+    for (int s0 = 0; s0 < len; s0 += seg) {
+        const int s1 = min(len, s0 + seg);
+        int bad = 0;
+        for (int e = s0 + threadIdx.x; e < s1; e += BT) {
+            const u32 cc = (u32)((u64)neg * J.V.coef[off + e] % p);
+            const int rr = add_entry<BT>(D, SC.F, S, J.V.idx[off + e], J.V.diam[off + e], cc, p);
+            if (rr) bad = rr;
+        }
+        if (bad) S.abort = bad;
+        gsync();
+        if (S.abort) return S.abort;
+        const int r = delta_check<BT>(D, G, SC, p, S);
+        if (r) return r;
+    }
+    return kRedOk;
+}
+
+// Append the live entries of a table (V_j) or of the sorted base to the
+// column store; returns the count, or -1 when the store is full.
+template <int BT>
+__device__ int store_table(const WorkCol &T, const VStore &V, unsigned long long *vcount, u32 p,
+                           RedShared<BT> &S, int64_t *off_out) {
+    const int tid = threadIdx.x;
+    const int ns = min(*T.nslots, (int)T.mask + 1);
+    int cnt = 0;
+    for (int i = tid; i < ns; i += BT) cnt += (ld(&T.coef[T.slots[i]]) % p) != 0 ? 1 : 0;
+    int tot;
+    int at = block_scan_excl<BT>(cnt, S.w, &tot);
+    if (tid == 0) S.vbase = atomicAdd(vcount, (unsigned long long)tot);
+    __syncthreads();
+    const int64_t vb = (int64_t)S.vbase;
+    if (vb + tot > V.cap) return -1;
+    for (int i = tid; i < ns; i += BT) {
+        const u32 s = T.slots[i];
+        const u32 cf = ld(&T.coef[s]) % p;
+        if (cf != 0) {
+            V.idx[vb + at] = ld(&T.keys[s]);
+            V.diam[vb + at] = T.diam[s];
+            V.coef[vb + at] = cf;
+            ++at;
+        }
+    }
+    *off_out = vb;
+    return tot;
+}
+
+template <int BT>
+__device__ int store_base(const SortedBase &SB, const VStore &V, unsigned long long *vcount,
+                          u32 p, RedShared<BT> &S, int64_t *off_out) {
+    const int tid = threadIdx.x;
+    const int cur = S.cur;
+    const int64_t f0 = S.f, nsrc = S.len - S.f;
+    int cnt = 0;
+    for (int64_t i = tid; i < nsrc; i += BT) cnt += (pick(SB.coef, cur)[f0 + i] % p) != 0 ? 1 : 0;
+    int tot;
+    int at = block_scan_excl<BT>(cnt, S.w, &tot);
+    if (tid == 0) S.vbase = atomicAdd(vcount, (unsigned long long)tot);
+    __syncthreads();
+    const int64_t vb = (int64_t)S.vbase;
+    if (vb + tot > V.cap) return -1;
+    for (int64_t i = tid; i < nsrc; i += BT) {
+        const u32 cf = pick(SB.coef, cur)[f0 + i] % p;
+        if (cf != 0) {
+            V.idx[vb + at] = pick(SB.idx, cur)[f0 + i];
+            V.diam[vb + at] = pick(SB.dia, cur)[f0 + i];
+            V.coef[vb + at] = cf;
+            ++at;
+        }
+    }
+    *off_out = vb;
+    return tot;
+}
+
+// live entries of the working column's near part (D merged into S first
+// when S is in use); -1 on failure
+template <int BT>
+__device__ int count_live(const WorkCol &T, u32 p, RedShared<BT> &S) {
+    const int ns = min(*T.nslots, (int)T.mask + 1);
+    int cnt = 0;
+    for (int i = threadIdx.x; i < ns; i += BT) cnt += (ld(&T.coef[T.slots[i]]) % p) != 0 ? 1 : 0;
+    int tot;
+    (void)block_scan_excl<BT>(cnt, S.w, &tot);
+    return tot;
+}
+
+template <int BT>
+__device__ int64_t count_live_base(const SortedBase &SB, u32 p, RedShared<BT> &S) {
+    const int cur = S.cur;
+    int cnt = 0;
+    for (int64_t i = S.f + threadIdx.x; i < S.len; i += BT) cnt += (pick(SB.coef, cur)[i] % p) != 0;
+    int tot;
+    (void)block_scan_excl<BT>(cnt, S.w, &tot);
+    return tot;
+}
+
+// Full reduction of column j. Returns a result code; on anything but kRedOk
+// nothing of column j has been published.
+template <int BT, class Dist>
+__device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Staging &G,
+                          const ReduceScratch &SC, int j, RedShared<BT> &S) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
     const u32 p = J.p;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const int64_t sidx = J.cols.idx[j];
     const float sdm = J.cols.diam[j];
+    const WorkCol &Vw = SC.Vw;
     if (tid == 0) {
         S.abort = 0;
-        S.nitems = 1;
-        S.it_idx[0] = sidx;
+        S.len = 0;
+        S.f = 0;
+        S.merged = 0;
+        S.kd = INFINITY;
+        S.fw = 0;
+        S.fwn = 0;
+        S.nit = 1;
         S.it_coef[0] = 1u;
         S.it_diam[0] = sdm;
         decode(sidx, k, c.n, c.B, S.it_v[0]);
+        if (!wc_add(Vw, sidx, sdm, 1u, p)) S.abort = kRedVFull;
     }
-    __syncthreads();
-    if (!add_items<BT>(J, S, R)) S.abort = 1;
+    gsync();
+    int result = S.abort ? S.abort : add_items<BT>(J, S, D, G, SC);
     int nadd = 0;
-    int result = 0;
-    for (;;) {
-        rsync(g);
-        if (S.abort) {
-            result = S.abort;
-            break;
-        }
+    while (result == kRedOk) {
+        __syncthreads();
         // every addition moves the pivot to a strictly younger row, so the
         // loop ends; the bound only turns a fault into an error
-        if (nadd > (1 << 16)) {
-            result = 3;
+        if (nadd > (1 << 18)) {
+            result = kRedBound;
             break;
         }
-        wc_compact<BT, kPer>(R, p, R.nslots, g);
-        const PivotCand piv = wc_pivot<BT>(R, p, S, g);
+        PivotCand piv;
+        for (;;) {
+            base_advance<BT>(D, SC.SB, p, S);
+            __syncthreads();
+            const PivotCand dmin = wc_oldest<BT>(D, p, S);
+            const PivotCand smin = S.spiv;
+            if (smin.idx == kEmpty) piv = dmin;
+            else if (dmin.idx == kEmpty || dmin.idx == smin.idx) piv = smin;
+            else piv = older(dmin, smin) ? dmin : smin;
+            if (piv.idx != kEmpty || S.fwn == 0) break;
+            result = far_pull<BT>(D, G, SC, p, ((int)D.mask + 1) / 2, S);
+            if (result) break;
+        }
+        if (result) break;
         if (piv.idx == kEmpty) {
             // zero column: essential class born at sigma
             if (tid == 0) {
@@ -335,29 +929,41 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &R, bool g, in
         __syncthreads();
         const int64_t o = S.owner;
         if (o >= 0) {
-            // R_j -= lambda R_o, lambda = piv / pivot(R_o)
+            // R_j -= lambda R_o and V_j -= lambda V_o, lambda = piv / pivot(R_o)
             const u32 lam = (u32)((u64)piv.coef * J.inv[J.V.pivcoef[o]] % p);
             const u32 neg = (p - lam) % p;
-            const int len = J.V.len[o];
-            if (len < 0) {
+            const int vlen = J.V.len[o];
+            const int rlen = J.V.rlen[o];
+            // V_j first (small), then R_j
+            bool vok = true;
+            if (vlen < 0) {
+                if (tid == 0) vok = wc_add(Vw, J.cols.idx[o], J.cols.diam[o], neg, p);
+            } else {
+                const int64_t vo = J.V.off[o];
+                for (int e = tid; e < vlen; e += BT)
+                    vok = vok && wc_add(Vw, J.V.idx[vo + e],
+                                        J.V.diam[vo + e], (u32)((u64)neg * J.V.coef[vo + e] % p), p);
+            }
+            if (!vok) S.abort = kRedVFull;
+            gsync();
+            if (S.abort) {
+                result = S.abort;
+                break;
+            }
+            if (rlen >= 0) {
+                result = add_rcolumn<BT>(J, S, D, G, SC, J.V.roff[o], rlen, neg);
+            } else if (vlen < 0) {
                 // emergent column: R_o is the coboundary of sigma_o
                 if (tid == 0) {
-                    S.nitems = 1;
-                    S.it_idx[0] = J.cols.idx[o];
+                    S.nit = 1;
                     S.it_coef[0] = neg;
                     S.it_diam[0] = J.cols.diam[o];
                     decode(J.cols.idx[o], k, c.n, c.B, S.it_v[0]);
                 }
                 __syncthreads();
-                if (!add_items<BT>(J, S, R)) S.abort = 1;
+                result = add_items<BT>(J, S, D, G, SC);
             } else {
-                const int64_t off = J.V.off[o];
-                bool ok = true;
-                for (int e = tid; e < len; e += BT) {
-                    const u32 cc = (u32)((u64)neg * J.V.coef[off + e] % p);
-                    ok = ok && wc_add(R, J.V.idx[off + e], J.V.diam[off + e], cc, p);
-                }
-                if (!ok) S.abort = 1;
+                result = add_vcolumn<BT>(J, S, D, G, SC, J.V.off[o], vlen, neg);
             }
             ++nadd;
             continue;
@@ -375,46 +981,56 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &R, bool g, in
                     // tau = rho u {tau[m]}; vertices of rho below tau[m]: k + 1 - m
                     const u32 crho = coeff_sign(k + 1 - m, p);
                     const u32 lam = (u32)((u64)piv.coef * J.inv[crho] % p);
-                    S.nitems = 1;
                     for (int q = 0; q <= k; ++q) S.it_v[0][q] = rv[q];
-                    S.it_idx[0] = simplex_index(rv, k, c.B);
+                    S.nit = 1;
                     S.it_coef[0] = (p - lam) % p;
                     S.it_diam[0] = piv.diam;
+                    if (!wc_add(Vw, simplex_index(rv, k, c.B), piv.diam, (p - lam) % p, p))
+                        S.abort = kRedVFull;
                 }
             }
         }
-        __syncthreads();
+        gsync();
+        if (S.abort) {
+            result = S.abort;
+            break;
+        }
         if (S.m >= 0) {
-            if (!add_items<BT>(J, S, R)) S.abort = 1;
+            result = add_items<BT>(J, S, D, G, SC);
             ++nadd;
             continue;
         }
-        // unowned pivot: persistence pair (sigma_j, pivot); keep R_j
-        const int ns = min(*R.nslots, (int)R.mask + 1);
-        int cnt = 0;
-        for (int i = tid; i < ns; i += BT) cnt += (ld(&R.coef[R.slots[i]]) % p) != 0 ? 1 : 0;
-        int tot;
-        const int ex = block_scan_excl<BT>(cnt, S.w, &tot);
-        if (tid == 0) S.vbase = atomicAdd(J.vcount, (unsigned long long)tot);
-        __syncthreads();
-        const int64_t vb = (int64_t)S.vbase;
-        if (vb + tot > J.V.cap) {
-            result = 2;
+        // unowned pivot: persistence pair (sigma_j, pivot). Store V_j, and
+        // R_j as well when it has no far part and is cheaper to add than
+        // V_j's coboundaries are to recompute.
+        int64_t voff = 0;
+        const int vn = store_table<BT>(Vw, J.V, J.vcount, p, S, &voff);
+        if (vn < 0) {
+            result = kRedStoreFull;
             break;
         }
-        int at = ex;
-        for (int i = tid; i < ns; i += BT) {
-            const u32 s = R.slots[i];
-            const u32 cf = ld(&R.coef[s]) % p;
-            if (cf != 0) {
-                J.V.idx[vb + at] = ld(&R.keys[s]);
-                J.V.diam[vb + at] = R.diam[s];
-                J.V.coef[vb + at] = cf;
-                ++at;
+        int64_t roff = 0;
+        int rn = -1;
+        if (S.fwn == 0) {
+            if (S.len > 0 && *D.nslots > 0) {
+                result = base_merge<BT>(D, G, SC.SB, p, S);
+                if (result) break;
+            }
+            __syncthreads();
+            const bool from_base = S.len > 0;
+            const int64_t live = from_base ? count_live_base<BT>(SC.SB, p, S)
+                                           : (int64_t)count_live<BT>(D, p, S);
+            if ((float)live <= 2.0f * (float)vn * J.cand_avg) {
+                rn = from_base ? store_base<BT>(SC.SB, J.V, J.vcount, p, S, &roff)
+                               : store_table<BT>(D, J.V, J.vcount, p, S, &roff);
+                if (rn < 0) {
+                    result = kRedStoreFull;
+                    break;
+                }
             }
         }
         if (tid == 0) {
-            if ((unsigned long long)tot > S.stat[6]) S.stat[6] = tot;
+            if ((unsigned long long)vn > S.stat[6]) S.stat[6] = vn;
             if (piv.diam > sdm) {
                 if (S.nbars < J.ncols) {
                     J.bars.birth[S.nbars] = sdm;
@@ -427,39 +1043,49 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &R, bool g, in
             }
             ph_insert(J.ph, piv.idx, j);
             J.V.pivcoef[j] = piv.coef;
-            J.V.off[j] = vb;
-            J.V.len[j] = tot;
+            J.V.off[j] = voff;
+            J.V.len[j] = vn;
+            J.V.roff[j] = roff;
+            J.V.rlen[j] = rn;
         }
         break;
     }
-    if (tid == 0 && result == 0) {
-        S.stat[1] += nadd > 0 ? 1 : 0;
-        S.stat[2] += nadd;
+    if (tid == 0) {
+        if (result == kRedOk) {
+            S.stat[1] += nadd > 0 ? 1 : 0;
+            S.stat[2] += nadd;
+            if (S.merged) S.stat[5] += 1;
+        }
+        const unsigned long long sz = (unsigned long long)(S.len - S.f + S.fwn + *D.nslots);
+        if (sz > S.stat[7]) S.stat[7] = sz;
     }
-    if (tid == 0 && (unsigned long long)*R.nslots > S.stat[7]) S.stat[7] = *R.nslots;
-    wc_reset<BT>(R, g);
+    __syncthreads();
+    wc_reset<BT>(D);
+    wc_reset<BT>(Vw);
     return result;
 }
 
-// The reduction of J.ncols columns by one workgroup of BT threads. A working
-// column starts in the LDS table Rl; a column that outgrows it is redone with
-// the global table Rg. Returns 0, or 1 (global working column overflow), 2
-// (column store overflow), 3 (addition bound).
-// Stats: S.stat = emergent, reduced, additions, bars_nonzero, essential.
+// The reduction of J.ncols columns by one workgroup of BT threads, with the
+// delta D (and its staging G) in LDS and the rest of the working column in
+// global scratch. Returns a result code. Stats: S.stat = emergent, reduced,
+// additions, bars_nonzero, essential, columns that used the sorted base or
+// far list, largest stored V column, largest working column.
 template <int BT, class Dist>
-__device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &Rl, const WorkCol &Rg,
-                              RedShared<BT> &S) {
+__device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &D, const Staging &G,
+                              const ReduceScratch &SC, RedShared<BT> &S) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
     const u32 p = J.p;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-    const bool lds_ok = Rl.keys != nullptr;
-    if (lds_ok) wc_clear_all<BT>(Rl, false);
-    bool g_clean = false;
+    wc_clear_all<BT>(D);
+    wc_clear_all<BT>(SC.Vw);
     if (tid == 0) {
         S.base = 0;
         S.abort = 0;
         S.nbars = 0;
+        S.cur = 0;
+        S.len = 0;
+        S.f = 0;
     }
     if (tid < 8) S.stat[tid] = 0;
     int status = 0;
@@ -501,8 +1127,10 @@ __device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &Rl, const
             if (lane < first_bad) {
                 ph_insert(J.ph, tau, col);
                 J.V.pivcoef[col] = tcoef;
-                J.V.len[col] = -1; // R_col is the coboundary of sigma_col
+                J.V.len[col] = -1; // V_col = sigma_col, R_col = its coboundary
                 J.V.off[col] = 0;
+                J.V.rlen[col] = -1;
+                J.V.roff[col] = 0;
             }
             if (lane == 0) {
                 S.base = base + first_bad;
@@ -510,20 +1138,10 @@ __device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &Rl, const
                 S.stat[0] += first_bad;
             }
         }
-        gsync(); // V metadata of the batch is visible to every wave
+        gsync(); // column metadata of the batch is visible to every wave
         if (!S.full) continue;
         const int j = S.base;
-        int r = 1;
-        if (lds_ok) r = reduce_one<BT>(J, Rl, false, j, S);
-        if (r == 1) {
-            if (tid == 0) S.stat[5] += 1;
-            if (!g_clean) {
-                wc_clear_all<BT>(Rg, true);
-                g_clean = true;
-            }
-            r = reduce_one<BT>(J, Rg, true, j, S);
-        }
-        status = r;
+        status = reduce_one<BT>(J, D, G, SC, j, S);
         if (tid == 0) S.base = j + 1;
         gsync(); // V_j and the table entry are visible before the next column
     }
@@ -531,8 +1149,7 @@ __device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &Rl, const
     return status;
 }
 
-size_t reduce_lds_bytes(u32 capR);
-hipError_t launch_reduce(const ReduceJob<DistFull> &J, WorkCol Rl, WorkCol Rg, int use_lds,
-                         Scalars *s, hipStream_t st);
+hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceScratch SC, Scalars *s,
+                         hipStream_t st);
 
 } // namespace rips
