@@ -203,6 +203,66 @@ rips_status rips_barcode_batched_device(const float *d_points, const int64_t *d_
                                         void *hip_stream);
 
 /*
+ * rips_backward_device -- gradient of a loss through the bars. The paper
+ * does not differentiate barcodes; the reading here: every finite bar
+ * endpoint equals the length of one edge of its simplex, its critical edge
+ * (the edge of largest float32 length, as the forward computes it, ties to
+ * the smallest CNS edge index), so d(loss)/d(endpoint) flows to the two
+ * points of that edge: d||x_u - x_v||/dx_u = (x_u - x_v)/||x_u - x_v|| and
+ * the negative for x_v (nothing at zero length). Vertex births (k = 0) and
+ * absent simplices (index -1) contribute nothing.
+ *   d_data        the forward's device input: points (rows x dim) or, with
+ *                 dim == 0, the n x n distance matrix; then the gradient goes
+ *                 to matrix entry (u, v), u > v, the entry the forward read.
+ *   n             points per cloud (an upper bound for batched clouds).
+ *   nbars         bars; k_birth: dimension of their birth simplices (death
+ *                 simplices have k_birth + 1).
+ *   d_row0        per bar, the row of its cloud's first point (batched
+ *                 bars), or NULL for one cloud; must be NULL when dim == 0.
+ *   d_birth_simplex, d_death_simplex   device int64 CNS indices per bar.
+ *   d_grad_birth, d_grad_death         device float32 d(loss)/d(endpoint).
+ *   d_grad        device float32, same shape as d_data; accumulated into
+ *                 (+=) with float32 atomics (summation order unspecified).
+ * Indices must come from the forward on the same input; every vertex read
+ * is below n. Returns after the stream has finished.
+ */
+rips_status rips_backward_device(const float *d_data, int64_t n, int32_t dim, int64_t nbars,
+                                 int32_t k_birth, const int64_t *d_row0,
+                                 const int64_t *d_birth_simplex, const int64_t *d_death_simplex,
+                                 const float *d_grad_birth, const float *d_grad_death,
+                                 float *d_grad, void *hip_stream);
+
+/*
+ * Launch configuration of the batched path (per device, the current one):
+ *   delta_slots        LDS slots of each workgroup's working-column delta:
+ *                      1024, 2048 or 4096 (0 = default: the largest that
+ *                      does not raise the kernel's LDS footprint, >= 1024);
+ *   workgroups_per_cu  persistent workgroups per compute unit, 1..4
+ *                      (0 = default 1).
+ * Results do not depend on the configuration (bit-identical bars); only
+ * speed does. Returns RIPS_E_INVALID_ARG for other values.
+ */
+rips_status rips_batched_set_config(int32_t delta_slots, int32_t workgroups_per_cu);
+rips_status rips_batched_get_config(int32_t *delta_slots, int32_t *workgroups_per_cu);
+
+/*
+ * rips_batched_autotune -- time the batched launch on the caller's batch
+ * (same arguments as rips_barcode_batched_device) for every configuration
+ * of delta_slots in {1024, 2048, 4096} x workgroups_per_cu in {1, 2, 4},
+ * `reps` timed replays each (hipEvents, after one untimed run), keep the
+ * fastest with rips_batched_set_config and report it. Every configuration's
+ * bar offsets are compared with the first one's; a mismatch returns
+ * RIPS_E_HIP. `out` receives the bars of the last run. best_ms: mean
+ * milliseconds per launch of the chosen configuration (any pointer may be
+ * NULL).
+ */
+rips_status rips_batched_autotune(const float *d_points, const int64_t *d_offsets, int32_t B,
+                                  int32_t dim, int32_t n_max, int32_t max_dim, float threshold,
+                                  uint32_t p, rips_batch_out *out, void *hip_stream, int32_t reps,
+                                  int32_t *best_delta_slots, int32_t *best_workgroups_per_cu,
+                                  float *best_ms);
+
+/*
  * Diagnostics: GPU time per kernel class of the calls made while profiling
  * is on, from hipEvents recorded around each launch on the caller's stream.
  * rips_profile_enable(1) clears the totals and starts recording; (0) stops.

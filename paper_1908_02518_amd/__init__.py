@@ -48,6 +48,10 @@ EXPORTS = (
     "rips_barcode_device",
     "rips_simplex_counts_device",
     "rips_barcode_batched_device",
+    "rips_backward_device",
+    "rips_batched_set_config",
+    "rips_batched_get_config",
+    "rips_batched_autotune",
     "rips_profile_enable",
     "rips_profile_count",
     "rips_profile_name",
@@ -160,6 +164,24 @@ def _load():
                                                 ctypes.c_float, ctypes.c_uint32,
                                                 ctypes.POINTER(rips_batch_out), ctypes.c_void_p]
     lib.rips_barcode_batched_device.restype = ctypes.c_int
+    lib.rips_backward_device.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                         ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    lib.rips_backward_device.restype = ctypes.c_int
+    lib.rips_batched_set_config.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.rips_batched_set_config.restype = ctypes.c_int
+    lib.rips_batched_get_config.argtypes = [ctypes.POINTER(ctypes.c_int32),
+                                            ctypes.POINTER(ctypes.c_int32)]
+    lib.rips_batched_get_config.restype = ctypes.c_int
+    lib.rips_batched_autotune.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_float, ctypes.c_uint32,
+                                          ctypes.POINTER(rips_batch_out), ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_float)]
+    lib.rips_batched_autotune.restype = ctypes.c_int
     lib.rips_profile_enable.argtypes = [ctypes.c_int]
     lib.rips_profile_enable.restype = None
     lib.rips_profile_count.argtypes = []
@@ -413,3 +435,64 @@ def barcode_batched(x, offsets, n_max: int, *, max_dim: int = 1,
         break
     return BatchedBars(birth, death, bs, ds, off, stats.view(B, D1, len(STAT_FIELDS)), thr, B,
                        max_dim)
+
+
+def batched_set_config(delta_slots: int = 0, workgroups_per_cu: int = 0):
+    """Launch configuration of the batched path (0 = defaults)."""
+    _check(_lib.rips_batched_set_config(int(delta_slots), int(workgroups_per_cu)))
+
+
+def batched_get_config():
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(_lib.rips_batched_get_config(ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
+def batched_autotune(x, offsets, n_max: int, *, max_dim: int = 1,
+                     threshold: float = float("inf"), p: int = 2, reps: int = 2,
+                     cap: int | None = None):
+    """Time every batched launch configuration on this batch and keep the
+    fastest (rips_batched_autotune). Returns (delta_slots, workgroups_per_cu,
+    ms per launch)."""
+    import torch
+    bb = barcode_batched(x, offsets, n_max, max_dim=max_dim, threshold=threshold, p=p, cap=cap)
+    B = offsets.shape[0] - 1
+    o = rips_batch_out()
+    o.cap = bb.birth.shape[0]
+    o.birth, o.death = bb.birth.data_ptr(), bb.death.data_ptr()
+    o.birth_simplex, o.death_simplex = bb.birth_simplex.data_ptr(), bb.death_simplex.data_ptr()
+    o.bar_offsets = bb.offsets.data_ptr()
+    o.stats, o.threshold_used = None, None
+    a, w, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_float()
+    _check(_lib.rips_batched_autotune(ctypes.c_void_p(x.data_ptr()),
+                                      ctypes.c_void_p(offsets.data_ptr()), B, x.shape[1],
+                                      int(n_max), max_dim, ctypes.c_float(threshold), p,
+                                      ctypes.byref(o), _stream_ptr(torch, x.device), int(reps),
+                                      ctypes.byref(a), ctypes.byref(w), ctypes.byref(ms)))
+    return int(a.value), int(w.value), float(ms.value)
+
+
+def backward_scatter(x, n: int, dim: int, k_birth: int, birth_simplex, death_simplex,
+                     grad_birth, grad_death, grad_out, row0=None):
+    """rips_backward_device: grad_out += d(loss)/d(input) through the critical
+    edges of the bars' birth and death simplices (device tensors)."""
+    import torch
+    nb = int(birth_simplex.shape[0])
+    if nb == 0:
+        return grad_out
+    for t, dt in ((birth_simplex, torch.int64), (death_simplex, torch.int64),
+                  (grad_birth, torch.float32), (grad_death, torch.float32)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous() or t.shape[0] != nb:
+            raise ValueError("bar tensors must be contiguous CUDA tensors of one length")
+    if row0 is not None and (row0.dtype != torch.int64 or not row0.is_contiguous()):
+        raise ValueError("row0 must be a contiguous int64 CUDA tensor")
+    _check(_lib.rips_backward_device(
+        ctypes.c_void_p(x.data_ptr()), int(n), int(dim), nb, int(k_birth),
+        ctypes.c_void_p(row0.data_ptr() if row0 is not None else 0),
+        ctypes.c_void_p(birth_simplex.data_ptr()), ctypes.c_void_p(death_simplex.data_ptr()),
+        ctypes.c_void_p(grad_birth.data_ptr()), ctypes.c_void_p(grad_death.data_ptr()),
+        ctypes.c_void_p(grad_out.data_ptr()), _stream_ptr(torch, x.device)))
+    return grad_out
+
+
+from .autograd import Bars, diagram, batched_diagram, top_persistence_loss  # noqa: E402,F401

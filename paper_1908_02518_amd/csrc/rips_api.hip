@@ -40,6 +40,9 @@ enum BufId {
     B_INPUT,
     B_D,
     B_BINOM,
+    B_BW_BINOM, // binomial table of the backward entry
+    B_APP_KEYS, // zero apparent pairs of the current dimension
+    B_APP_VALS,
     B_INV,
     B_SCAL,
     B_E_IDX,
@@ -203,6 +206,7 @@ struct DevCtx {
     int64_t batch_fstride = 0;
     int64_t batch_vwstride = 0;
     u32 batch_capD = 0; // 0 = default delta size of the batched reduction
+    int batch_wgpcu = 0; // 0 = default (1 persistent workgroup per CU)
 
     hipError_t ensure(int id, size_t bytes, void **out) {
         if (bytes == 0) bytes = 16;
@@ -665,9 +669,20 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         surv.j = as<int>(q);
         HIP_TRY(C.ensure(B_SURV_TAPP, (size_t)ncand, &q));
         surv.tapp = as<uint8_t>(q);
+        // zero apparent pairs (rho, tau) found by the filter, for the
+        // reduction's pivot test; twice the candidates, so inserts never fail
+        PairHash app;
+        if (ncand > (1ll << 30)) return fail(RIPS_E_CAPACITY, "too many candidate simplices");
+        const uint32_t appcap = next_pow2((uint64_t)2 * ncand + 64);
+        HIP_TRY(C.ensure(B_APP_KEYS, (size_t)appcap * 8, &q));
+        app.keys = as<int64_t>(q);
+        HIP_TRY(C.ensure(B_APP_VALS, (size_t)appcap * 8, &q));
+        app.vals = as<int64_t>(q);
+        app.mask = appcap - 1;
+        launch_fill_i64(app.keys, appcap, kEmpty, st);
         {
             PROF(P_FILTER1 + k - 1);
-            launch_filter(G, P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv, st);
+            launch_filter(G, P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv, app, st);
         }
         if ((rs = read_scalars(C, P.scal, st))) return rs;
         const int64_t S = std::min<int64_t>((int64_t)C.host_scal->survivors, ncand);
@@ -789,6 +804,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             J.V = V;
             J.vcount = &P.scal->vcount;
             J.bars = bars[k];
+            J.app = app;
             J.cand_avg = P.sparse ? (float)(2.0 * (double)P.nedges / (double)std::max<int64_t>(n, 1))
                                   : (float)n;
             {
@@ -817,11 +833,26 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         if (getenv("RIPS_DEBUG"))
             fprintf(stderr,
                     "[rips reduce d%d] cols=%lld capD=%u sbcap=%lld lds_per_block=%d "
-                    "base_cols=%llu R_entries=%llu maxR_stored=%llu maxR=%llu additions=%llu\n",
+                    "base_cols=%llu entries=%llu maxV=%llu maxR=%llu additions=%llu pulls=%llu "
+                    "merges=%llu splits=%llu pulled=%llu\n",
                     k, (long long)S, capD, (long long)sbcap, C.lds_per_block,
                     C.host_scal->stat[kStatGlobalCols], C.host_scal->vcount,
                     C.host_scal->stat[kStatMaxV], C.host_scal->stat[kStatMaxR],
-                    C.host_scal->stat[kStatAdditions]);
+                    C.host_scal->stat[kStatAdditions], C.host_scal->stat[kStatPulls],
+                    C.host_scal->stat[kStatMerges], C.host_scal->stat[kStatSplits],
+                    C.host_scal->stat[kStatPulled]);
+        if (getenv("RIPS_DEBUG")) {
+            int khz = 0;
+            (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0);
+            const double f = khz > 0 ? 1.0 / khz : 1e-5;
+            const unsigned long long *T = C.host_scal->stat + kStatTime;
+            fprintf(stderr,
+                    "[rips reduce d%d] ms (clock %d kHz): total %.2f setup %.2f pivot %.2f "
+                    "owner %.2f add %.2f apparent %.2f store %.2f reset %.2f emergent %.2f | "
+                    "merge %.2f pull %.2f split %.2f\n",
+                    k, khz, T[10] * f, T[6] * f, T[0] * f, T[11] * f, T[1] * f, T[7] * f,
+                    T[5] * f, T[9] * f, T[8] * f, T[2] * f, T[3] * f, T[4] * f);
+        }
         o.count[k] = C.host_scal->nbars;
         o.stats[k].emergent = (int64_t)C.host_scal->stat[kStatEmergent];
         o.stats[k].reduced = (int64_t)C.host_scal->stat[kStatReduced];
@@ -855,7 +886,7 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     hipStream_t st = (hipStream_t)hip_stream;
     const int D1 = max_dim + 1;
     const bool lds_d = n_max <= kBatchLdsN;
-    int grid = std::max(1, C->num_cus);
+    int grid = std::max(1, C->num_cus) * std::max(1, C->batch_wgpcu);
     if (grid > B) grid = B;
     const int64_t npairs = (int64_t)n_max * (n_max - 1) / 2;
     const int64_t col_stride = npairs + n_max + 16;
@@ -1318,6 +1349,135 @@ rips_status rips_barcode_batched_device(const float *d_points, const int64_t *d_
                           hip_stream, &retry);
         if (!retry || attempt > 8) return rs;
     }
+}
+
+rips_status rips_backward_device(const float *d_data, int64_t n, int32_t dim, int64_t nbars,
+                                 int32_t k_birth, const int64_t *d_row0,
+                                 const int64_t *d_birth_simplex, const int64_t *d_death_simplex,
+                                 const float *d_grad_birth, const float *d_grad_death,
+                                 float *d_grad, void *hip_stream) {
+    g_err.clear();
+    if (n < 1 || n > RIPS_MAX_POINTS) return fail(RIPS_E_INVALID_ARG, "n out of range");
+    if (dim < 0) return fail(RIPS_E_INVALID_ARG, "dim < 0");
+    if (dim == 0 && d_row0) return fail(RIPS_E_INVALID_ARG, "distance input has one cloud");
+    if (k_birth < 0 || k_birth > RIPS_MAX_DIM)
+        return fail(RIPS_E_INVALID_ARG, "k_birth out of range");
+    if (nbars < 0) return fail(RIPS_E_INVALID_ARG, "nbars < 0");
+    if (nbars == 0) return RIPS_OK;
+    if (!d_data || !d_birth_simplex || !d_death_simplex || !d_grad_birth || !d_grad_death ||
+        !d_grad)
+        return fail(RIPS_E_INVALID_ARG, "null pointer");
+    DevCtx *C;
+    rips_status rs;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int jmax = kMaxDim + 2;
+    const int stride = (int)n + 1;
+    void *q;
+    HIP_TRY(C->ensure(B_BW_BINOM, (size_t)(jmax + 1) * stride * 8, &q));
+    Binom B{as<u64>(q), stride};
+    launch_binom(as<u64>(q), stride, (int)n, jmax, st);
+    launch_backward(d_data, dim, n, (int)n, B, nbars, k_birth, d_row0, d_birth_simplex,
+                    d_death_simplex, d_grad_birth, d_grad_death, d_grad, st);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(st));
+    return RIPS_OK;
+}
+
+rips_status rips_batched_set_config(int32_t delta_slots, int32_t workgroups_per_cu) {
+    g_err.clear();
+    if (!(delta_slots == 0 || delta_slots == 1024 || delta_slots == 2048 || delta_slots == 4096))
+        return fail(RIPS_E_INVALID_ARG, "delta_slots must be 0, 1024, 2048 or 4096");
+    if (workgroups_per_cu < 0 || workgroups_per_cu > 4)
+        return fail(RIPS_E_INVALID_ARG, "workgroups_per_cu must be in [0, 4]");
+    DevCtx *C;
+    rips_status rs;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    C->batch_capD = (u32)delta_slots;
+    C->batch_wgpcu = workgroups_per_cu;
+    return RIPS_OK;
+}
+
+rips_status rips_batched_get_config(int32_t *delta_slots, int32_t *workgroups_per_cu) {
+    g_err.clear();
+    DevCtx *C;
+    rips_status rs;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    if (delta_slots) *delta_slots = (int32_t)C->batch_capD;
+    if (workgroups_per_cu) *workgroups_per_cu = C->batch_wgpcu;
+    return RIPS_OK;
+}
+
+rips_status rips_batched_autotune(const float *d_points, const int64_t *d_offsets, int32_t B,
+                                  int32_t dim, int32_t n_max, int32_t max_dim, float threshold,
+                                  uint32_t p, rips_batch_out *out, void *hip_stream, int32_t reps,
+                                  int32_t *best_delta_slots, int32_t *best_workgroups_per_cu,
+                                  float *best_ms) {
+    g_err.clear();
+    if (reps < 1 || reps > 1000) return fail(RIPS_E_INVALID_ARG, "reps must be in [1, 1000]");
+    if (!out || !out->bar_offsets) return fail(RIPS_E_INVALID_ARG, "null pointer");
+    const int32_t slots[3] = {1024, 2048, 4096};
+    const int32_t wgs[3] = {1, 2, 4};
+    hipStream_t st = (hipStream_t)hip_stream;
+    const int64_t noff = (int64_t)B * (max_dim + 1) + 1;
+    std::vector<int64_t> ref, cur;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(RIPS_E_HIP, "hipEventCreate failed");
+    float best = -1.0f;
+    int32_t bs = 0, bw = 0;
+    rips_status rs = RIPS_OK;
+    for (int a = 0; a < 3 && rs == RIPS_OK; ++a) {
+        for (int b = 0; b < 3 && rs == RIPS_OK; ++b) {
+            if ((rs = rips_batched_set_config(slots[a], wgs[b]))) break;
+            // untimed run: builds the graph and grows scratch
+            if ((rs = rips_barcode_batched_device(d_points, d_offsets, B, dim, n_max, max_dim,
+                                                  threshold, p, out, hip_stream)))
+                break;
+            cur.resize(noff);
+            if (hipMemcpy(cur.data(), out->bar_offsets, noff * 8, hipMemcpyDeviceToHost) !=
+                hipSuccess) {
+                rs = fail(RIPS_E_HIP, "copy of bar offsets failed");
+                break;
+            }
+            if (ref.empty()) ref = cur;
+            else if (ref != cur) {
+                rs = fail(RIPS_E_HIP, "configurations disagree on the bar counts");
+                break;
+            }
+            (void)hipEventRecord(e0, st);
+            for (int r = 0; r < reps && rs == RIPS_OK; ++r)
+                rs = rips_barcode_batched_device(d_points, d_offsets, B, dim, n_max, max_dim,
+                                                 threshold, p, out, hip_stream);
+            if (rs) break;
+            (void)hipEventRecord(e1, st);
+            (void)hipEventSynchronize(e1);
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            ms /= (float)reps;
+            if (best < 0.0f || ms < best) {
+                best = ms;
+                bs = slots[a];
+                bw = wgs[b];
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rs) {
+        const std::string err = g_err;
+        (void)rips_batched_set_config(0, 0);
+        g_err = err;
+        return rs;
+    }
+    if ((rs = rips_batched_set_config(bs, bw))) return rs;
+    if (best_delta_slots) *best_delta_slots = bs;
+    if (best_workgroups_per_cu) *best_workgroups_per_cu = bw;
+    if (best_ms) *best_ms = best;
+    return RIPS_OK;
 }
 
 void rips_profile_enable(int on) {

@@ -455,6 +455,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         SC.Vw.nslots = &RS.vns;
         SC.Vw.mask = (u32)A.vw_stride - 1;
         J.cand_avg = (float)n;
+        J.app = PairHash{nullptr, nullptr, 0};
         gsync();
         const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, RS);
         if (rstat && tid == 0) {
@@ -611,13 +612,13 @@ size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD) {
     return std::max(dpart + uf, reduce_lds_bytes(capD));
 }
 
-// the largest delta that does not raise the kernel's LDS beyond what its
-// distance phase needs (at least 1024 slots)
+// default delta: the largest (4096 slots, about 106 KB of LDS with its
+// staging), which the autotuner picked on both the mixture and the circle
+// workloads; the LDS variant needs that much for its distances anyway
 u32 batched_default_capD(bool lds_d, int nmax) {
-    const size_t base = batched_lds_bytes(lds_d, nmax, 256);
-    u32 c = 1024;
-    while (c < 4096 && reduce_lds_bytes(c * 2) <= base) c *= 2;
-    return c;
+    (void)lds_d;
+    (void)nmax;
+    return 4096;
 }
 
 hipError_t batched_prepare(bool lds_d, int nmax, u32 capD) {

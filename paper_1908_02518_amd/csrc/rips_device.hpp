@@ -90,22 +90,43 @@ __host__ __device__ __forceinline__ int64_t simplex_index(const int *v, int k, B
     return s;
 }
 
-// Vertices of the k-simplex with index idx on n vertices: the largest vertex
-// is the largest i with C(i, k+1) <= idx (Lemma of the "Vertices and
-// simplices" paragraph), found by binary search; then recurse on the rest.
+// Largest i in [lo, hi] with C(i, r) <= x, 2 <= r <= 5. The start comes
+// from C(i, r) ~ (i - (r - 1) / 2)^r / r! in double precision and is then
+// corrected against the exact table: two independent table reads in the
+// usual case instead of a binary search's chain of dependent ones.
+__host__ __device__ __forceinline__ int top_vertex(u64 x, int r, int lo, int hi, Binom B) {
+    const double xd = (double)x;
+    double g;
+    if (r == 2) g = 0.5 + sqrt(2.0 * xd + 0.25);
+    else if (r == 3) g = cbrt(6.0 * xd) + 1.0;
+    else if (r == 4) g = sqrt(sqrt(24.0 * xd)) + 1.5;
+    else g = pow(120.0 * xd, 0.2) + 2.0;
+    int i = g < (double)lo ? lo : (g > (double)hi ? hi : (int)g);
+    u64 a = B(i, r);
+    u64 b = i < hi ? B(i + 1, r) : ~0ull;
+    while (a > x && i > lo) {
+        --i;
+        b = a;
+        a = B(i, r);
+    }
+    while (b <= x && i < hi) {
+        ++i;
+        a = b;
+        b = i < hi ? B(i + 1, r) : ~0ull;
+    }
+    return i;
+}
+
+// Vertices of the k-simplex with index idx on n vertices, decreasing: the
+// largest vertex is the largest i with C(i, k+1) <= idx (Lemma of the
+// "Vertices and simplices" paragraph); then recurse on the rest.
 __host__ __device__ __forceinline__ void decode(int64_t idx, int k, int n, Binom B, int *v) {
     int hi = n - 1;
     for (int l = k; l >= 1; --l) {
-        int lo = l;
-        int h = hi;
-        while (lo < h) {
-            int mid = (lo + h + 1) >> 1;
-            if (B(mid, l + 1) <= (u64)idx) lo = mid;
-            else h = mid - 1;
-        }
-        v[k - l] = lo;
-        idx -= (int64_t)B(lo, l + 1);
-        hi = lo - 1;
+        const int i = top_vertex((u64)(idx < 0 ? 0 : idx), l + 1, l, hi < l ? l : hi, B);
+        v[k - l] = i;
+        idx -= (int64_t)B(i, l + 1);
+        hi = i - 1;
     }
     // valid indices leave 0 <= idx <= hi; the clamp only keeps a corrupted
     // index from addressing outside the distance matrix
@@ -194,23 +215,25 @@ __device__ __forceinline__ int zero_pivot_facet(const Ctx<Dist> &c, const int *v
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
-// Barrier for phases that hand data between waves through global memory:
-// an agent-scope fence first, so that every store and atomic of this wave
-// has completed in L2 and later loads do not hit stale L1 lines (atomics
-// execute in L2, plain accesses go through the per-CU L1).
-__device__ __forceinline__ void gsync() {
-    __threadfence();
-    __syncthreads();
-}
+// Barrier for phases that hand data between the waves of one workgroup
+// through global memory. The workgroup barrier's release/acquire fences
+// cover global memory as well as LDS, and every kernel here shares global
+// scratch only inside one workgroup (other workgroups see it after the
+// kernel ends), so workgroup scope is enough. An agent-scope fence would
+// write back and invalidate the L2 at every call.
+__device__ __forceinline__ void gsync() { __syncthreads(); }
 
+// Relaxed workgroup-scope atomic load / store, for words that other waves
+// of the workgroup update with atomics (atomics execute in L2; these loads
+// do not return a stale L1 copy).
 template <class T>
 __device__ __forceinline__ T ld(const T *p) {
-    return __atomic_load_n(p, __ATOMIC_RELAXED);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <class T>
 __device__ __forceinline__ void st(T *p, T v) {
-    __atomic_store_n(p, v, __ATOMIC_RELAXED);
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <int G>
@@ -320,8 +343,8 @@ struct PivotHash {
 __device__ __forceinline__ int32_t ph_find(const PivotHash &h, int64_t key) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
-        const int64_t cur = __atomic_load_n(&h.keys[s], __ATOMIC_RELAXED);
-        if (cur == key) return __atomic_load_n(&h.vals[s], __ATOMIC_RELAXED);
+        const int64_t cur = ld(&h.keys[s]);
+        if (cur == key) return ld(&h.vals[s]);
         if (cur == kEmpty) return -1;
         s = (s + 1) & h.mask;
     }
@@ -333,7 +356,42 @@ __device__ __forceinline__ bool ph_insert(const PivotHash &h, int64_t key, int32
     for (u32 probe = 0; probe <= h.mask; ++probe) {
         const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
         if (prev == (u64)kEmpty || prev == (u64)key) {
-            __atomic_store_n(&h.vals[s], val, __ATOMIC_RELAXED);
+            st(&h.vals[s], val);
+            return true;
+        }
+        s = (s + 1) & h.mask;
+    }
+    return false;
+}
+
+// Zero apparent pairs (rho, tau) of one dimension, recorded by the filter:
+// tau -> (rho << 3) | m, m = position in tau's decreasing vertex list of the
+// vertex tau adds to rho. Sized at twice the candidates, so inserts never
+// fail; the reduction then finds whether its pivot is such a tau with one
+// lookup.
+struct PairHash {
+    int64_t *keys; // kEmpty when free; null = no table
+    int64_t *vals;
+    u32 mask;
+};
+
+__device__ __forceinline__ int64_t pair_find(const PairHash &h, int64_t key) {
+    u32 s = mix64((u64)key) & h.mask;
+    for (u32 probe = 0; probe <= h.mask; ++probe) {
+        const int64_t cur = ld(&h.keys[s]);
+        if (cur == key) return ld(&h.vals[s]);
+        if (cur == kEmpty) return -1;
+        s = (s + 1) & h.mask;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ bool pair_insert(const PairHash &h, int64_t key, int64_t val) {
+    u32 s = mix64((u64)key) & h.mask;
+    for (u32 probe = 0; probe <= h.mask; ++probe) {
+        const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
+        if (prev == (u64)kEmpty || prev == (u64)key) {
+            st(&h.vals[s], val);
             return true;
         }
         s = (s + 1) & h.mask;

@@ -274,10 +274,10 @@ __device__ __forceinline__ void edge_vertices(u32 idx, int *a, int *b) {
 }
 
 __device__ __forceinline__ int uf_find(int *parent, int v, int n) {
-    int p = __atomic_load_n(&parent[v], __ATOMIC_RELAXED);
+    int p = ld(&parent[v]);
     for (int guard = 0; p != v && guard < n; ++guard) {
         v = p;
-        p = __atomic_load_n(&parent[v], __ATOMIC_RELAXED);
+        p = ld(&parent[v]);
     }
     return v;
 }
@@ -441,7 +441,7 @@ __global__ void __launch_bounds__(kH0Threads) k_h0(EdgeList E, Scalars *s, int n
                 }
                 if ((int64_t)idx < all_edges) atomicOr(&W.bits[idx >> 5], 1u << (idx & 31));
             }
-            __threadfence();
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         }
     }
     gsync();
@@ -594,7 +594,7 @@ __global__ void __launch_bounds__(256) k_expand_count(Ctx<Dist> c, int k, Simple
 template <int G, class Dist>
 __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, int k, SimplexList in, int64_t count,
                                                 const u32 *mst_bits, PivotHash prev, Scalars *s,
-                                                Columns out) {
+                                                Columns out, PairHash app) {
     const int gpb = blockDim.x / G;
     const int lg = threadIdx.x & (G - 1);
     const int64_t stride = (int64_t)gridDim.x * gpb;
@@ -618,6 +618,12 @@ __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, int k, SimplexList 
         const int j = group_find_max<G>(c, v, k, dm, -1);
         if (j >= 0 && is_zero_apparent_cofacet(c, v, k, dm, j)) {
             n_acol += (lg == 0);
+            if (lg == 0 && app.keys) {
+                int tv[kMaxVerts];
+                const int pos = insert_vertex(v, k, j, tv);
+                // capacity is twice the candidates: the insert cannot fail
+                (void)pair_insert(app, simplex_index(tv, k + 1, c.B), (idx << 3) | pos);
+            }
             continue;
         }
         if (k >= 2 && zero_apparent_facet<G>(c, v, k, dm) >= 0) {
@@ -707,7 +713,90 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 c
         s->stat[kStatGlobalCols] += S.stat[5];
         s->stat[kStatMaxV] = S.stat[6];
         s->stat[kStatMaxR] = S.stat[7];
+        s->stat[kStatPulls] += S.stat[8];
+        s->stat[kStatMerges] += S.stat[9];
+        s->stat[kStatSplits] += S.stat[10];
+        s->stat[kStatPulled] += S.stat[11];
+        for (int q = 0; q < 12; ++q) s->stat[kStatTime + q] += S.tm[q];
     }
+}
+
+// ---------------------------------------------------------------------------
+// Backward: d(loss)/d(bar endpoint) scattered onto the critical edge of the
+// endpoint's simplex (the edge of largest float32 length, ties to the
+// smallest CNS edge index, i.e. the edge whose arrival gives the simplex its
+// diameter in the refined order). One thread per (bar, endpoint).
+// Points input: d ||x_u - x_v|| / d x_u = (x_u - x_v) / ||x_u - x_v||,
+// the negative for x_v (no contribution at zero length). Distance-matrix
+// input (m = 0): the gradient goes to entry (u, v), u > v, of the n x n
+// matrix the forward read.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bw_dist(const float *X, int m, const float *M, int64_t nrow,
+                                         int64_t u, int64_t v) {
+    if (m == 0) return M[u * nrow + v];
+    float s = 0.0f;
+    for (int c = 0; c < m; ++c) {
+        const float t = X[u * m + c] - X[v * m + c];
+        const float sq = t * t;
+        s = s + sq;
+    }
+    return __builtin_sqrtf(s);
+}
+
+__global__ void k_backward(const float *X, int m, int64_t nrow, int nmax, Binom B, int64_t nbars,
+                           int kb, const int64_t *row0, const int64_t *bs, const int64_t *ds,
+                           const float *gb, const float *gd, float *grad) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= 2 * nbars) return;
+    const int64_t bar = t >> 1;
+    const bool death = t & 1;
+    const int k = death ? kb + 1 : kb;
+    const int64_t idx = death ? ds[bar] : bs[bar];
+    const float g = death ? gd[bar] : gb[bar];
+    if (k < 1 || k > kMaxDim + 1 || idx < 0 || g == 0.0f) return;
+    int v[kMaxVerts + 1];
+    decode(idx, k, nmax, B, v); // decreasing vertices
+    const int64_t r0 = row0 ? row0[bar] : 0;
+    const float *Xc = m ? X + r0 * m : nullptr;
+    const float *Mc = m ? nullptr : X;
+    float best = -1.0f;
+    int64_t beste = 0;
+    int bu = 0, bv = 0;
+    for (int a = 0; a <= k; ++a)
+        for (int b = a + 1; b <= k; ++b) {
+            const int u = v[a], w = v[b]; // u > w
+            const float d = bw_dist(Xc, m, Mc, nrow, u, w);
+            const int64_t e = (int64_t)B(u, 2) + w;
+            if (d > best || (d == best && e < beste)) {
+                best = d;
+                beste = e;
+                bu = u;
+                bv = w;
+            }
+        }
+    if (m == 0) {
+        atomicAdd(&grad[(int64_t)bu * nrow + bv], g);
+        return;
+    }
+    if (!(best > 0.0f)) return;
+    const float sc = g / best;
+    float *gu = grad + (r0 + bu) * m;
+    float *gv = grad + (r0 + bv) * m;
+    for (int c = 0; c < m; ++c) {
+        const float diff = Xc[(int64_t)bu * m + c] - Xc[(int64_t)bv * m + c];
+        const float q = sc * diff;
+        atomicAdd(&gu[c], q);
+        atomicAdd(&gv[c], -q);
+    }
+}
+
+void launch_backward(const float *X, int m, int64_t nrow, int nmax, Binom B, int64_t nbars,
+                     int kb, const int64_t *row0, const int64_t *bs, const int64_t *ds,
+                     const float *gb, const float *gd, float *grad, hipStream_t st) {
+    if (nbars <= 0) return;
+    const int64_t threads = 2 * nbars;
+    hipLaunchKernelGGL(k_backward, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, X, m,
+                       nrow, nmax, B, nbars, kb, row0, bs, ds, gb, gd, grad);
 }
 
 // bars of one dimension into the caller's arrays; reverse = column order was
@@ -728,7 +817,7 @@ __global__ void k_emit(BarBuf in, Scalars *s, int reverse, BarBuf out) {
 // instantiations / launchers
 // ---------------------------------------------------------------------------
 template <int G>
-static void launch_filter_g(const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
+static void launch_filter_g(const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, PairHash app,
                             const u32 *bits, PivotHash prev, Scalars *s, Columns out,
                             hipStream_t st) {
     const int gpb = 256 / G;
@@ -736,17 +825,18 @@ static void launch_filter_g(const Ctx<DistFull> &c, int k, SimplexList in, int64
     if (blocks < 1) blocks = 1;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL((k_filter<G, DistFull>), dim3((unsigned)blocks), dim3(256), 0, st, c, k, in,
-                       count, bits, prev, s, out);
+                       count, bits, prev, s, out, app);
 }
 
 void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
-                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, hipStream_t st) {
+                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app,
+                   hipStream_t st) {
     switch (G) {
-    case 4: launch_filter_g<4>(c, k, in, count, bits, prev, s, out, st); break;
-    case 8: launch_filter_g<8>(c, k, in, count, bits, prev, s, out, st); break;
-    case 16: launch_filter_g<16>(c, k, in, count, bits, prev, s, out, st); break;
-    case 32: launch_filter_g<32>(c, k, in, count, bits, prev, s, out, st); break;
-    default: launch_filter_g<64>(c, k, in, count, bits, prev, s, out, st); break;
+    case 4: launch_filter_g<4>(c, k, in, count, app, bits, prev, s, out, st); break;
+    case 8: launch_filter_g<8>(c, k, in, count, app, bits, prev, s, out, st); break;
+    case 16: launch_filter_g<16>(c, k, in, count, app, bits, prev, s, out, st); break;
+    case 32: launch_filter_g<32>(c, k, in, count, app, bits, prev, s, out, st); break;
+    default: launch_filter_g<64>(c, k, in, count, app, bits, prev, s, out, st); break;
     }
 }
 

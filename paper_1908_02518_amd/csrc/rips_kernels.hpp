@@ -18,7 +18,12 @@ enum {
     kStatGlobalCols, // columns that outgrew the LDS working tables
     kStatMaxV,       // longest stored V column
     kStatMaxR,       // most entries touched by one working column
-    kNumStats
+    kStatPulls,      // far-list pulls
+    kStatMerges,     // delta merges into the sorted base
+    kStatSplits,     // sorted-base splits into the far list
+    kStatPulled,     // far-list entries scanned by pulls
+    kStatTime,       // 12 phase timers of the reduction (wall-clock ticks)
+    kNumStats = kStatTime + 12
 };
 
 // Device scalars of one call; read back by the host after a dimension ends.
@@ -97,6 +102,9 @@ struct H0Scratch {
 };
 
 void launch_binom(u64 *B, int stride, int n, int jmax, hipStream_t st);
+void launch_backward(const float *X, int m, int64_t nrow, int nmax, Binom B, int64_t nbars,
+                     int kb, const int64_t *row0, const int64_t *bs, const int64_t *ds,
+                     const float *gb, const float *gd, float *grad, hipStream_t st);
 void launch_inverse(u32 *inv, u32 p, hipStream_t st);
 void launch_dist(const float *data, int n, int m, float *D, int *bad, hipStream_t st);
 void launch_init_scalars(Scalars *s, hipStream_t st);
@@ -110,7 +118,8 @@ void launch_h0(EdgeList E, Scalars *s, int n, H0Scratch W, BarBuf out, int64_t n
                hipStream_t st);
 void launch_fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t st);
 void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
-                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, hipStream_t st);
+                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app,
+                   hipStream_t st);
 void launch_expand(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, Scalars *s,
                    SimplexList out, int64_t cap, bool count_only, hipStream_t st);
 void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Columns out,

@@ -183,6 +183,7 @@ struct ReduceJob {
     unsigned long long *vcount; // column-store append counter (global)
     BarBuf bars;                // capacity ncols
     float cand_avg;             // mean coboundary candidates of a k-simplex
+    PairHash app;               // zero apparent pairs (rho, tau) of this dimension, or none
 };
 
 // Shared state of the routine (one per workgroup).
@@ -193,7 +194,7 @@ struct RedShared {
     int fr, nr;     // far list being pulled: buffer, entries
     float kd, kdn;  // near bound, its next value
     int64_t len, f; // sorted base: length and front
-    int64_t owner, qsplit;
+    int64_t owner, qsplit, appv;
     u32 lo, bound;
     int shift;
     unsigned long long vbase;
@@ -201,7 +202,8 @@ struct RedShared {
     PivotCand piv, spiv;
     int w[BT / kWave + 1];
     u32 mm[2][BT / kWave];
-    unsigned long long stat[8];
+    unsigned long long stat[12];
+    unsigned long long tm[12]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner
     u32 hist[256];
     // simplices whose coboundaries are added next: vertices, coefficient,
     // diameter, candidate source (vertex with the fewest neighbours, -1 =
@@ -212,6 +214,13 @@ struct RedShared {
     int it_u[BT];
     int it_off[BT + 1];
 };
+
+// phase timers (thread 0, wall clock)
+#define RED_T0(v) const unsigned long long v = threadIdx.x == 0 ? wall_clock64() : 0ull
+#define RED_T1(S, i, v)                                                                            \
+    do {                                                                                           \
+        if (threadIdx.x == 0) (S).tm[i] += wall_clock64() - v;                                     \
+    } while (0)
 
 template <int BT>
 __device__ __forceinline__ int block_scan_excl(int x, int *s_w, int *total) {
@@ -382,6 +391,7 @@ __device__ void base_advance(const WorkCol &D, const SortedBase &SB, u32 p, RedS
 template <int BT>
 __device__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &SB, u32 p,
                           RedShared<BT> &S) {
+    RED_T0(t_mrg);
     const int tid = threadIdx.x;
     const int ns = min(*D.nslots, (int)D.mask + 1);
     // 1. gather the live entries into the staging area, unsorted
@@ -486,8 +496,10 @@ __device__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &
         S.f = 0;
         S.len = sl + nondup;
         S.merged = 1;
+        S.stat[9] += 1;
     }
     wc_clear_all<BT>(D);
+    RED_T1(S, 2, t_mrg);
     return kRedOk;
 }
 
@@ -498,6 +510,7 @@ __device__ int base_split(const SortedBase &SB, const FarList &F, u32 p, int sma
                           RedShared<BT> &S) {
     const int tid = threadIdx.x;
     if (S.len - S.f <= smax) return kRedOk;
+    RED_T0(t_spl);
     const int cur = S.cur;
     if (tid == 0) {
         const int64_t q0 = S.f + smax / 2;
@@ -528,17 +541,63 @@ __device__ int base_split(const SortedBase &SB, const FarList &F, u32 p, int sma
         S.len = q;
         S.kd = kd;
         S.merged = 1;
+        S.stat[10] += 1;
     }
     __syncthreads();
+    RED_T1(S, 4, t_spl);
     return kRedOk;
 }
 
-// keep D at most an eighth full and S at most capD live entries
+// Rehash D's live entries in place when there are at most `most` of them
+// (all threads; most <= G.cap). Returns the number of live entries; D is
+// unchanged when that is above `most`.
+template <int BT>
+__device__ int delta_compact(const WorkCol &D, const Staging &G, u32 p, int most,
+                             RedShared<BT> &S) {
+    const int tid = threadIdx.x;
+    const int ns = min(*D.nslots, (int)D.mask + 1);
+    int cnt = 0;
+    for (int i = tid; i < ns; i += BT) cnt += (ld(&D.coef[D.slots[i]]) % p) != 0 ? 1 : 0;
+    int m;
+    int at = block_scan_excl<BT>(cnt, S.w, &m);
+    if (m > most) return m;
+    for (int i = tid; i < ns; i += BT) {
+        const u32 s = D.slots[i];
+        const u32 cf = ld(&D.coef[s]) % p;
+        if (cf != 0) {
+            G.idx[at] = ld(&D.keys[s]);
+            G.dia[at] = D.diam[s];
+            G.coef[at] = cf;
+            ++at;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < ns; i += BT) {
+        const u32 s = D.slots[i];
+        st(&D.keys[s], kEmpty);
+        st(&D.coef[s], 0u);
+    }
+    __syncthreads();
+    if (tid == 0) *D.nslots = 0;
+    __syncthreads();
+    for (int e = tid; e < m; e += BT) wc_add(D, G.idx[e], G.dia[e], G.coef[e], p);
+    __syncthreads();
+    return m;
+}
+
+// keep D at most an eighth full (compacting it when few of its entries are
+// live, else merging it into S) and S at most capD live entries
 template <int BT>
 __device__ __forceinline__ int delta_check(const WorkCol &D, const Staging &G,
                                            const ReduceScratch &SC, u32 p, RedShared<BT> &S) {
     const int capD = (int)D.mask + 1;
     if (*D.nslots <= capD / 8) return kRedOk;
+    {
+        RED_T0(t_cmp);
+        const int live = delta_compact<BT>(D, G, p, capD / 32, S);
+        RED_T1(S, 2, t_cmp);
+        if (live <= capD / 32) return kRedOk;
+    }
     int r = base_merge<BT>(D, G, SC.SB, p, S);
     if (r) return r;
     return base_split<BT>(SC.SB, SC.F, p, capD, S);
@@ -553,12 +612,15 @@ __device__ int far_pull(const WorkCol &D, const Staging &G, const ReduceScratch 
                         int target, RedShared<BT> &S) {
     const FarList &F = SC.F;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    RED_T0(t_pull);
     if (tid == 0) {
         S.fr = S.fw;
         S.nr = S.fwn;
         S.fw = S.fw ^ 1;
         S.fwn = 0;
         S.merged = 1;
+        S.stat[8] += 1;
+        S.stat[11] += S.nr;
     }
     __syncthreads();
     const int fr = S.fr, nr = S.nr;
@@ -634,6 +696,7 @@ __device__ int far_pull(const WorkCol &D, const Staging &G, const ReduceScratch 
         S.nr = nr;
     }
     __syncthreads();
+    RED_T1(S, 3, t_pull);
     // 3. move the entries under the bound into D, keep the rest, in segments
     const int seg = ((int)D.mask + 1) / 8;
     for (int s0 = 0; s0 < nr; s0 += seg) {
@@ -872,6 +935,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
     const int64_t sidx = J.cols.idx[j];
     const float sdm = J.cols.diam[j];
     const WorkCol &Vw = SC.Vw;
+    RED_T0(t_setup);
     if (tid == 0) {
         S.abort = 0;
         S.len = 0;
@@ -888,6 +952,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
     }
     gsync();
     int result = S.abort ? S.abort : add_items<BT>(J, S, D, G, SC);
+    RED_T1(S, 6, t_setup);
     int nadd = 0;
     while (result == kRedOk) {
         __syncthreads();
@@ -898,6 +963,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
             break;
         }
         PivotCand piv;
+        RED_T0(t_piv);
         for (;;) {
             base_advance<BT>(D, SC.SB, p, S);
             __syncthreads();
@@ -910,6 +976,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
             result = far_pull<BT>(D, G, SC, p, ((int)D.mask + 1) / 2, S);
             if (result) break;
         }
+        RED_T1(S, 0, t_piv);
         if (result) break;
         if (piv.idx == kEmpty) {
             // zero column: essential class born at sigma
@@ -925,8 +992,12 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
             }
             break;
         }
+        RED_T0(t_own);
+        // pivot table and apparent-pair table, looked up by two waves at once
         if (tid == 0) S.owner = ph_find(J.ph, piv.idx);
+        if (J.app.keys && tid == kWave) S.appv = pair_find(J.app, piv.idx);
         __syncthreads();
+        RED_T1(S, 11, t_own);
         const int64_t o = S.owner;
         if (o >= 0) {
             // R_j -= lambda R_o and V_j -= lambda V_o, lambda = piv / pivot(R_o)
@@ -950,6 +1021,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
                 result = S.abort;
                 break;
             }
+            RED_T0(t_add);
             if (rlen >= 0) {
                 result = add_rcolumn<BT>(J, S, D, G, SC, J.V.roff[o], rlen, neg);
             } else if (vlen < 0) {
@@ -965,11 +1037,30 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
             } else {
                 result = add_vcolumn<BT>(J, S, D, G, SC, J.V.off[o], vlen, neg);
             }
+            RED_T1(S, 1, t_add);
             ++nadd;
             continue;
         }
         // not in the table: is the pivot in a zero apparent pair (rho, tau)?
-        if (w == 0) {
+        RED_T0(t_app);
+        if (J.app.keys) {
+            // recorded by the filter: tau -> (rho, position m of the added vertex)
+            if (tid == 0) {
+                const int64_t a = S.appv;
+                S.m = a < 0 ? -1 : (int)(a & 7);
+                if (a >= 0) {
+                    const int m = (int)(a & 7);
+                    decode(a >> 3, k, c.n, c.B, S.it_v[0]);
+                    // tau = rho u {tau[m]}; vertices of rho below tau[m]: k + 1 - m
+                    const u32 crho = coeff_sign(k + 1 - m, p);
+                    const u32 lam = (u32)((u64)piv.coef * J.inv[crho] % p);
+                    S.nit = 1;
+                    S.it_coef[0] = (p - lam) % p;
+                    S.it_diam[0] = piv.diam;
+                    if (!wc_add(Vw, a >> 3, piv.diam, (p - lam) % p, p)) S.abort = kRedVFull;
+                }
+            }
+        } else if (w == 0) {
             int tv[kMaxVerts];
             decode(piv.idx, k + 1, c.n, c.B, tv);
             const int m = zero_apparent_facet<kWave>(c, tv, k + 1, piv.diam);
@@ -991,6 +1082,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
             }
         }
         gsync();
+        RED_T1(S, 7, t_app);
         if (S.abort) {
             result = S.abort;
             break;
@@ -1003,6 +1095,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
         // unowned pivot: persistence pair (sigma_j, pivot). Store V_j, and
         // R_j as well when it has no far part and is cheaper to add than
         // V_j's coboundaries are to recompute.
+        RED_T0(t_st);
         int64_t voff = 0;
         const int vn = store_table<BT>(Vw, J.V, J.vcount, p, S, &voff);
         if (vn < 0) {
@@ -1048,6 +1141,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
             J.V.roff[j] = roff;
             J.V.rlen[j] = rn;
         }
+        RED_T1(S, 5, t_st);
         break;
     }
     if (tid == 0) {
@@ -1060,8 +1154,10 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
         if (sz > S.stat[7]) S.stat[7] = sz;
     }
     __syncthreads();
+    RED_T0(t_rst);
     wc_reset<BT>(D);
     wc_reset<BT>(Vw);
+    RED_T1(S, 9, t_rst);
     return result;
 }
 
@@ -1087,15 +1183,18 @@ __device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &D, const 
         S.len = 0;
         S.f = 0;
     }
-    if (tid < 8) S.stat[tid] = 0;
+    if (tid < 12) S.stat[tid] = 0;
+    if (tid < 12) S.tm[tid] = 0;
     int status = 0;
     gsync();
+    RED_T0(t_total);
     for (;;) {
         __syncthreads();
         const int base = S.base;
         const int stop = base >= J.ncols;
         __syncthreads(); // everyone has read the cursor before wave 0 moves it
         if (stop || status) break;
+        RED_T0(t_em);
         // ---- emergent shortcut for up to 64 columns at once (wave 0): a
         // column whose zero pivot cofacet is free (not in the pivot table,
         // not in a zero apparent pair, not taken by a lower column of the
@@ -1139,6 +1238,7 @@ __device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &D, const 
             }
         }
         gsync(); // column metadata of the batch is visible to every wave
+        RED_T1(S, 8, t_em);
         if (!S.full) continue;
         const int j = S.base;
         status = reduce_one<BT>(J, D, G, SC, j, S);
@@ -1146,6 +1246,7 @@ __device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &D, const 
         gsync(); // V_j and the table entry are visible before the next column
     }
     gsync();
+    RED_T1(S, 10, t_total);
     return status;
 }
 

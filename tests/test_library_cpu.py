@@ -82,3 +82,27 @@ def test_empty_and_null_inputs_rejected():
     dummy = (ctypes.c_float * 1)()
     assert lib.rips_barcode(dummy, 0, 2, 1, ctypes.c_float(1.0), 2, ctypes.byref(out)) == -1
     assert lib.rips_barcode(dummy, 4, -1, 1, ctypes.c_float(1.0), 2, ctypes.byref(out)) == -1
+
+
+def test_backward_validation_before_any_hip_call():
+    import paper_1908_02518_amd as rips
+    lib = rips.lib()
+    d = ctypes.c_void_p(8)  # never dereferenced: rejected before any HIP call
+    # n out of range, k_birth out of range, distance input with row offsets,
+    # negative bar count
+    assert lib.rips_backward_device(d, 0, 2, 1, 1, None, d, d, d, d, d, None) == -1
+    assert lib.rips_backward_device(d, 10, 2, 1, 9, None, d, d, d, d, d, None) == -1
+    assert lib.rips_backward_device(d, 10, 0, 1, 1, d, d, d, d, d, d, None) == -1
+    assert lib.rips_backward_device(d, 10, 2, -1, 1, None, d, d, d, d, d, None) == -1
+    # nothing to do
+    assert lib.rips_backward_device(d, 10, 2, 0, 1, None, d, d, d, d, d, None) == 0
+
+
+def test_batched_config_validation():
+    import paper_1908_02518_amd as rips
+    lib = rips.lib()
+    # rejected before the device context is touched
+    assert lib.rips_batched_set_config(3000, 1) == -1
+    assert lib.rips_batched_set_config(1024, 9) == -1
+    assert lib.rips_batched_autotune(None, None, 1, 2, 8, 1, ctypes.c_float(1.0), 2, None, None,
+                                     0, None, None, None) == -1
