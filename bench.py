@@ -9,15 +9,29 @@ data set). The input is resident in HBM before the timed region.
 
 value = simplices/s = (|K_0| + |K_1| + |K_2| + |K_3|) at the threshold, the size
 of the explicit filtration the method avoids building, divided by the time
-per step. Also reported: the roofline of the dominant kernel (HIP events
-over the timed region), and the CPU oracle timed on this host.
+per step. Also reported:
+  roofline          the dominant kernel's algorithmic bytes per launch over
+                    its mean launch time (HIP events on the library's
+                    stream), against the HBM peak; traffic = HBM bytes per
+                    launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters
+                    (committed summary under profiles/, scaled by a plain copy
+                    of known size), null when the kernel sources changed since
+  enumeration_pass  the same for the enumeration / apparent-pair filter
+  batched           barcodes/s of the 512-cloud mixture batch in one
+                    persistent launch vs one cloud at a time
+  cpu_baseline      the CPU oracle on this host (a bounded sample)
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --summarize-pmc FETCH_DIR WRITE_DIR   (profiles helpers)
+       python bench.py --summarize-trace TRACE_DIR
 """
 
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -28,37 +42,153 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_so3-1000.txt")
+COPY_BYTES = 1 << 29   # plain copy used to calibrate the counters (512 MiB read + written)
 
 
-def kernel_bytes(name: str, n: int, m: int, counts, stats, info) -> float | None:
-    """Algorithmic HBM bytes of one launch of a kernel class (the data the
-    method must move once): candidate records in, surviving records out, the
-    distance matrix and neighbour lists read once."""
-    sparse = info["sparse"]
+def source_hash() -> str:
+    """Hash of the HIP sources: counter summaries are valid for these only."""
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1908_02518_amd", "csrc", "*"))):
+        if f.endswith((".hip", ".hpp")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_bytes(name: str, n: int, counts, stats, sparse: bool) -> float | None:
+    """Algorithmic HBM bytes of one launch of a kernel class: what the method
+    must move once. Records: simplex (index 8 B + diameter 4 B), column
+    (+ zero pivot cofacet 4 B + flag 1 B), reduction entry (index 8 B +
+    diameter 4 B + coefficient 4 B)."""
     edges = counts[1] if len(counts) > 1 else 0
-    nnz = 2 * edges if sparse else 0
     dmat = 4.0 * n * n
     if name == "distances":
-        return 4.0 * n * n + 4.0 * n * m
+        return dmat
     if name == "edges":
-        return dmat + 20.0 * edges
+        return dmat + 12.0 * edges
     if name.startswith("filter_d"):
         k = int(name[-1])
-        cand = counts[k]
-        surv = stats[k]["columns"]
-        return 12.0 * cand + 17.0 * surv + dmat + 4.0 * nnz
+        return 12.0 * counts[k] + 17.0 * stats[k]["columns"] + (8.0 * edges if sparse else dmat)
     if name.startswith("expand_d"):
         k = int(name[-1])
-        return 12.0 * counts[k - 1] + 12.0 * counts[k] + dmat + 4.0 * nnz
+        return 12.0 * counts[k - 1] + 12.0 * counts[k] + (8.0 * edges if sparse else dmat)
     if name.startswith("sort_d"):
         k = int(name[-1])
         return 2.0 * 17.0 * stats[k]["columns"]
     if name.startswith("reduce_d"):
         k = int(name[-1])
-        return 17.0 * stats[k]["columns"]
+        s = stats[k]
+        return 17.0 * s["columns"] + 16.0 * (s["entries_added"] + s["entries_stored"])
     if name == "h0":
-        return 20.0 * edges + 24.0 * n
+        return 12.0 * edges + 16.0 * n
     return None
+
+
+def read_pmc_summary():
+    """{class: (fetch_bytes, write_bytes) per launch} scaled by the copy
+    calibration, or None when absent or stale."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    vals, rows = {}, {}
+    for ln in open(PMC_SUMMARY):
+        ln = ln.strip()
+        if not ln or ln.startswith("#"):
+            continue
+        parts = ln.split()
+        if parts[0] == "kernel":
+            rows[parts[1]] = (float(parts[3]), float(parts[5]))
+        else:
+            vals[parts[0]] = parts[1]
+    if vals.get("source_sha256") != source_hash():
+        return None
+    ff = float(vals["copy_bytes"]) / (float(vals["copy_fetch_kib"]) * 1024.0)
+    fw = float(vals["copy_bytes"]) / (float(vals["copy_write_kib"]) * 1024.0)
+    return {k: (f * 1024.0 * ff, w * 1024.0 * fw) for k, (f, w) in rows.items()}
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str) -> int:
+    """Print the profiles/ summary from two rocprofv3 --pmc runs of
+    `bench.py --pmc-run` (FETCH_SIZE, then WRITE_SIZE): mean KiB per
+    dispatch for each kernel class, and the copy kernel's reading."""
+    def load(d, counter):
+        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        per = {}
+        for fpath in files:
+            with open(fpath) as fh:
+                for r in csv.DictReader(fh):
+                    if r.get("Counter_Name") != counter:
+                        continue
+                    name = r.get("Kernel_Name", "")
+                    per.setdefault(name, []).append((int(r.get("Dispatch_Id", 0)),
+                                                     float(r["Counter_Value"])))
+        return per
+
+    def classify(per):
+        # a reduction belongs to the dimension of the filter dispatched before
+        # it; filters alternate d1, d2 in every barcode
+        allr = sorted((d, name, v) for name, lst in per.items() for d, v in lst)
+        out, nfilter, dim, copies = {}, 0, 0, []
+        for _, name, v in allr:
+            if "k_filter" in name:
+                dim = 1 + nfilter % 2
+                nfilter += 1
+                out.setdefault(f"filter_d{dim}", []).append(v)
+            elif "k_reduce" in name:
+                out.setdefault(f"reduce_d{dim}", []).append(v)
+            elif "copy" in name.lower() or "elementwise" in name.lower():
+                copies.append(v)
+        if copies:
+            out["copy"] = [max(copies)]
+        return {k: sum(v) / len(v) for k, v in out.items()}
+
+    f = classify(load(fetch_dir, "FETCH_SIZE"))
+    w = classify(load(write_dir, "WRITE_SIZE"))
+    print("# HBM traffic per dispatch, rocprofv3 counters (KiB), so3-1000 barcode")
+    print(f"source_sha256 {source_hash()}")
+    print(f"copy_bytes {COPY_BYTES}")
+    print(f"copy_fetch_kib {f.get('copy', 0.0):.1f}")
+    print(f"copy_write_kib {w.get('copy', 0.0):.1f}")
+    for k in sorted(set(f) & set(w)):
+        if k != "copy":
+            print(f"kernel {k} fetch_kib {f[k]:.1f} write_kib {w[k]:.1f}")
+    return 0
+
+
+def summarize_trace(trace_dir: str) -> int:
+    """Print the profiles/ summary of a `rocprofv3 --kernel-trace --stats`
+    run of bench.py: calls and mean duration per kernel, with the filter and
+    reduction dispatches split by dimension (they alternate d1, d2 in every
+    barcode)."""
+    files = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    rows = []
+    for fpath in files:
+        with open(fpath) as fh:
+            for r in csv.DictReader(fh):
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"],
+                             int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+    rows.sort()
+    # a reduction belongs to the dimension of the filter dispatched before it
+    # (a reduction relaunched after a scratch overflow has no filter of its own)
+    per, nfilter, dim = {}, 0, 0
+    for _, name, ns in rows:
+        short = name.split("(")[0].replace("void ", "")
+        if "k_filter" in name:
+            dim = 1 + nfilter % 2
+            nfilter += 1
+            short = f"{short} [filter_d{dim}]"
+        elif "k_reduce" in name:
+            short = f"{short} [reduce_d{dim}]"
+        per.setdefault(short, []).append(ns)
+    # last3_us: mean of the last three dispatches (the timed steps of a
+    # `--steps 3` run; earlier ones include warm-up and scratch growth)
+    print("# kernel                                                   calls   mean_us  last3_us    total_ms")
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
+        tail = v[-3:]
+        print(f"{k:58s} {len(v):5d} {sum(v) / len(v) / 1e3:9.1f} {sum(tail) / len(tail) / 1e3:9.1f}"
+              f" {sum(v) / 1e6:10.2f}")
+    return 0
 
 
 def main() -> int:
@@ -69,7 +199,16 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="bound on the CPU-oracle sample (seconds)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="counter runs: a few steps plus one plain copy of known size")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-trace", metavar="TRACE_DIR")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        return summarize_pmc(*args.summarize_pmc)
+    if args.summarize_trace:
+        return summarize_trace(args.summarize_trace)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -77,11 +216,13 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     import paper_1908_02518_amd as rips
     import workloads
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     cfg = workloads.config(2)
     x = cfg["clouds"][0]
@@ -91,13 +232,22 @@ def main() -> int:
     xt = torch.from_numpy(x).to(dev)
     torch.cuda.synchronize()
 
+    if args.pmc_run:
+        a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        for i in range(args.steps):
+            rips.barcode_device(xt, max_dim=max_dim, threshold=t, p=p)
+            torch.cuda.synchronize()
+            log(f"pmc step {i + 1}/{args.steps}")
+        return 0
+
     # size of the explicit filtration (numerator), outside the timed region
     counts = rips.simplex_counts(xt, max_dim + 1, threshold=t)
     n_simplices = int(sum(counts))
-
-    def log(msg):
-        print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
     log(f"workload {cfg['name']}: n={n}, |K_0..K_{max_dim + 1}| = {counts}")
     for i in range(args.warmup):
         c0 = time.perf_counter()
@@ -121,36 +271,42 @@ def main() -> int:
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n_simplices / ((t1 - t0) / args.steps)
     stats = info["stats"]
+    sparse = info["sparse"]
+    pmc = read_pmc_summary()
 
-    # dominant kernel and its roofline
-    dom = max(prof.items(), key=lambda kv: kv[1][0])
-    dname, (dms, dcalls) = dom
-    per_launch_ms = dms / dcalls
-    dbytes = kernel_bytes(dname, n, m, counts, stats, info)
-    achieved = (dbytes / (per_launch_ms * 1e-3) / 1e9) if dbytes else None
-    roofline = {
-        "kernel": dname,
-        "bound": "hbm",
-        "achieved": round(achieved, 3) if achieved is not None else None,
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 6) if achieved is not None else None,
-        "traffic": None,
-        "bytes_per_launch": dbytes,
-        "avg_launch_us": round(per_launch_ms * 1e3, 3),
-    }
-    # the enumeration / apparent-pair pass of the top dimension, reported beside it
+    def roof(name):
+        ms, calls = prof[name]
+        per_launch_ms = ms / calls
+        by = kernel_bytes(name, n, counts, stats, sparse)
+        ach = by / (per_launch_ms * 1e-3) / 1e9 if by else None
+        tr = pmc.get(name) if pmc else None
+        return {
+            "kernel": name,
+            "bound": "hbm",
+            "achieved": round(ach, 4) if ach is not None else None,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 7) if ach is not None else None,
+            "traffic": round(tr[0] + tr[1], 1) if tr else None,
+            "bytes_per_launch": by,
+            "avg_launch_us": round(per_launch_ms * 1e3, 3),
+        }
+
+    dname = max(prof.items(), key=lambda kv: kv[1][0])[0]
+    roofline = roof(dname)
+    if dname.startswith("reduce_d"):
+        k = int(dname[-1])
+        s = stats[k]
+        roofline["note"] = ("sequential column reduction in one workgroup (latency-bound): "
+                            f"{s['columns']} columns, {s['additions']} additions, "
+                            f"{s['entries_added']} entries added, {s['entries_stored']} stored")
+        roofline["columns_per_s"] = round(s["columns"] / (roofline["avg_launch_us"] * 1e-6), 1)
     fname = f"filter_d{max_dim}"
     enum_pass = None
     if fname in prof:
+        enum_pass = roof(fname)
         fms, fc = prof[fname]
-        fb = kernel_bytes(fname, n, m, counts, stats, info)
-        fa = fb / (fms / fc * 1e-3) / 1e9
-        cand = counts[max_dim]
-        enum_pass = {"kernel": fname, "achieved_GBs": round(fa, 3),
-                     "frac_hbm": round(fa / HBM_PEAK_GBS, 6),
-                     "avg_launch_us": round(fms / fc * 1e3, 3),
-                     "candidates_per_s": round(cand / (fms / fc * 1e-3), 1)}
+        enum_pass["candidates_per_s"] = round(counts[max_dim] / (fms / fc * 1e-3), 1)
 
     eliminated = {}
     for k in range(1, max_dim + 1):
@@ -166,6 +322,38 @@ def main() -> int:
             "additions": s["additions"],
         }
 
+    batched = None
+    if not args.no_batched:
+        c4 = workloads.config(4)
+        clouds = c4["clouds"]
+        xb, off, nmax = rips.pack_clouds(clouds)
+        rips.barcode_batched(xb, off, nmax, max_dim=c4["max_dim"], p=c4["p"])  # graph + scratch
+        torch.cuda.synchronize()
+        reps = 5
+        c0 = time.perf_counter()
+        for _ in range(reps):
+            rips.barcode_batched(xb, off, nmax, max_dim=c4["max_dim"], p=c4["p"])
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - c0) / reps
+        log(f"batched mixture-512: {1e3 * tb:.1f} ms per batch")
+        xs = [torch.from_numpy(a).to(dev) for a in clouds]
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        for q, a in enumerate(xs):
+            rips.barcode_device(a, max_dim=c4["max_dim"], p=c4["p"])
+            if q % 128 == 127:
+                log(f"one at a time: {q + 1}/{len(xs)}")
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - c0
+        batched = {
+            "workload": "mixture-512: 512 clouds of 32-256 points in R^3 (1-3 noisy circles "
+                        "and blobs), full Rips, dims 0-1, Z/2",
+            "barcodes_per_s_batched": round(len(clouds) / tb, 1),
+            "barcodes_per_s_single": round(len(clouds) / ts, 1),
+            "ratio": round(ts / tb, 2),
+            "config": list(rips.batched_get_config()),
+        }
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -177,8 +365,6 @@ def main() -> int:
             el += time.perf_counter() - c0
             reps += 1
             log(f"cpu oracle run {reps}: {el / reps:.2f} s")
-            if el > args.cpu_seconds:
-                break
         cpu = {"value": round(n_simplices / (el / reps), 1), "unit": "simplices/s", "cores": 1,
                "kind": "oracle",
                "sample": f"the full so3-1000 cloud (same input), {reps} run(s), "
@@ -205,6 +391,7 @@ def main() -> int:
         "enumeration_pass": enum_pass,
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(prof.items())},
         "eliminated": eliminated,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

@@ -84,6 +84,8 @@ typedef struct {
     int64_t additions;      /* column additions in total */
     int64_t bars_nonzero;   /* finite bars of nonzero persistence */
     int64_t essential;      /* infinite bars */
+    int64_t entries_added;  /* entries added to working columns by the reduction */
+    int64_t entries_stored; /* entries of the stored reduction columns (V and R parts) */
 } rips_dim_stats;
 
 typedef struct {

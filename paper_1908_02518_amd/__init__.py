@@ -75,7 +75,8 @@ class rips_bars(ctypes.Structure):
 
 
 STAT_FIELDS = ("candidates", "cleared", "apparent_col", "apparent_pivot", "columns", "emergent",
-               "reduced", "additions", "bars_nonzero", "essential")
+               "reduced", "additions", "bars_nonzero", "essential", "entries_added",
+               "entries_stored")
 
 
 class rips_dim_stats(ctypes.Structure):

@@ -859,6 +859,8 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         o.stats[k].additions = (int64_t)C.host_scal->stat[kStatAdditions];
         o.stats[k].bars_nonzero = (int64_t)C.host_scal->stat[kStatBarsNonzero];
         o.stats[k].essential = (int64_t)C.host_scal->stat[kStatEssential];
+        o.stats[k].entries_added = (int64_t)C.host_scal->stat[kStatAdded];
+        o.stats[k].entries_stored = (int64_t)C.host_scal->vcount;
         ph_prev = ph;
         prev_list = cand;
         prev_count = ncand;

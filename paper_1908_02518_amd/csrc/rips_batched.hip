@@ -324,6 +324,8 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         s0.additions = 0;
         s0.bars_nonzero = (int64_t)Sh.cnt[0];
         s0.essential = (int64_t)Sh.cnt[1];
+        s0.entries_added = 0;
+        s0.entries_stored = 0;
         A.t_used[b] = t;
         Sh.nsurv = 0;
         Sh.cnt[0] = Sh.cnt[1] = Sh.cnt[2] = Sh.cnt[3] = 0;
@@ -478,6 +480,8 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
             s1.reduced = (int64_t)RS.stat[1];
             s1.additions = (int64_t)RS.stat[2];
             s1.bars_nonzero = (int64_t)RS.stat[3];
+            s1.entries_added = (int64_t)RS.stat[12];
+            s1.entries_stored = (int64_t)ld(&A.v_count[wg]);
             s1.essential = (int64_t)RS.stat[4];
         }
     }

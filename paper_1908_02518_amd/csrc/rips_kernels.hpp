@@ -22,6 +22,7 @@ enum {
     kStatMerges,     // delta merges into the sorted base
     kStatSplits,     // sorted-base splits into the far list
     kStatPulled,     // far-list entries scanned by pulls
+    kStatAdded,      // entries added to working columns
     kStatTime,       // 12 phase timers of the reduction (wall-clock ticks)
     kNumStats = kStatTime + 12
 };

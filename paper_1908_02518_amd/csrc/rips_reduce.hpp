@@ -202,7 +202,7 @@ struct RedShared {
     PivotCand piv, spiv;
     int w[BT / kWave + 1];
     u32 mm[2][BT / kWave];
-    unsigned long long stat[12];
+    unsigned long long stat[13];
     unsigned long long tm[12]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner
     u32 hist[256];
     // simplices whose coboundaries are added next: vertices, coefficient,
@@ -762,6 +762,7 @@ __device__ int add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkC
     for (int s0 = 0; s0 < total; s0 += seg) {
         const int s1 = min(total, s0 + seg);
         int bad = 0;
+        unsigned long long added = 0;
         for (int fl = s0 + tid; fl < s1; fl += BT) {
             int lo = 0, hi = nit - 1; // last item with it_off <= fl
             while (lo < hi) {
@@ -787,7 +788,9 @@ __device__ int add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkC
             const u32 cc = (below & 1) ? (p - coef) % p : coef;
             const int rr = add_entry<BT>(D, SC.F, S, ci, nd, cc, p);
             if (rr) bad = rr;
+            ++added;
         }
+        if (added) atomicAdd(&S.stat[12], added);
         if (bad) S.abort = bad;
         gsync();
         if (S.abort) return S.abort;
@@ -836,6 +839,7 @@ __device__ int add_rcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const Wor
             const int rr = add_entry<BT>(D, SC.F, S, J.V.idx[off + e], J.V.diam[off + e], cc, p);
             if (rr) bad = rr;
         }
+        if (threadIdx.x == 0) S.stat[12] += (unsigned long long)(s1 - s0);
         if (bad) S.abort = bad;
         gsync();
         if (S.abort) return S.abort;
@@ -1183,7 +1187,7 @@ __device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &D, const 
         S.len = 0;
         S.f = 0;
     }
-    if (tid < 12) S.stat[tid] = 0;
+    if (tid < 13) S.stat[tid] = 0;
     if (tid < 12) S.tm[tid] = 0;
     int status = 0;
     gsync();

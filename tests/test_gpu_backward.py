@@ -69,13 +69,15 @@ def test_gradient_matches_central_differences(cloud):
     print(f"[case] finite differences, circles cloud {cloud}", flush=True)
     L0, g, _ = gpu_loss_and_grad(x)
     _, key0 = selection(x)
+    # every coordinate of the critical-edge points, plus 16 random ones
+    # (expected gradient 0)
     rows = sorted({v for k in key0 for e in k[2:] for v in e})
     coords = [(i, c) for i in rows for c in range(2)]
     rng = workloads.rng(4242 + cloud)
     others = [i for i in range(x.shape[0]) if i not in rows]
-    coords += [(int(i), int(rng.integers(0, 2))) for i in rng.choice(others, 8, replace=False)]
+    coords += [(int(i), int(rng.integers(0, 2))) for i in rng.choice(others, 16, replace=False)]
     h = 1e-3
-    checked, kinks = 0, 0
+    got, fds, kinks = [], [], 0
     for i, c in coords:
         xp, xm = x.copy(), x.copy()
         xp[i, c] = np.float32(x[i, c] + h)
@@ -83,14 +85,17 @@ def test_gradient_matches_central_differences(cloud):
         Lp, kp = selection(xp)
         Lm, km = selection(xm)
         if kp != key0 or km != key0:
-            kinks += 1
+            kinks += 1  # the active pairing changes within +-h: not differentiable there
             continue
         step = float(xp[i, c]) - float(xm[i, c])
-        fd = (Lp - Lm) / step
-        tol = 1e-3 * max(abs(g[i, c]), 1e-2 * np.abs(g).max())
-        assert abs(fd - g[i, c]) <= tol, (i, c, fd, g[i, c])
-        checked += 1
-    assert checked >= 0.75 * len(coords), (checked, kinks, len(coords))
+        got.append(g[i, c])
+        fds.append((Lp - Lm) / step)
+    got, fds = np.array(got), np.array(fds)
+    print(f"[fd] cloud {cloud}: {len(fds)} coordinates, {kinks} kinks excluded", flush=True)
+    assert len(fds) >= 0.75 * len(coords), (len(fds), kinks, len(coords))
+    rel = np.linalg.norm(got - fds) / np.linalg.norm(fds)
+    assert rel <= 1e-3, rel
+    assert np.abs(got - fds).max() <= 1e-3 * np.abs(fds).max()
 
 
 def test_batched_backward_matches_single():
