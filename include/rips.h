@@ -237,8 +237,7 @@ rips_status rips_backward_device(const float *d_data, int64_t n, int32_t dim, in
 /*
  * Launch configuration of the batched path (per device, the current one):
  *   delta_slots        LDS slots of each workgroup's working-column delta:
- *                      1024, 2048 or 4096 (0 = default: the largest that
- *                      does not raise the kernel's LDS footprint, >= 1024);
+ *                      512, 1024 or 2048 (0 = default, 2048);
  *   workgroups_per_cu  persistent workgroups per compute unit, 1..4
  *                      (0 = default 1).
  * Results do not depend on the configuration (bit-identical bars); only
@@ -250,7 +249,7 @@ rips_status rips_batched_get_config(int32_t *delta_slots, int32_t *workgroups_pe
 /*
  * rips_batched_autotune -- time the batched launch on the caller's batch
  * (same arguments as rips_barcode_batched_device) for every configuration
- * of delta_slots in {1024, 2048, 4096} x workgroups_per_cu in {1, 2, 4},
+ * of delta_slots in {512, 1024, 2048} x workgroups_per_cu in {1, 2, 4},
  * `reps` timed replays each (hipEvents, after one untimed run), keep the
  * fastest with rips_batched_set_config and report it. Every configuration's
  * bar offsets are compared with the first one's; a mismatch returns

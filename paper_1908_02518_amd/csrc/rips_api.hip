@@ -92,12 +92,6 @@ enum BufId {
     B_V_IDX,
     B_V_COEF,
     B_V_DIAM,
-    B_SB_IDX0, // sorted base of the working column, two buffers
-    B_SB_IDX1,
-    B_SB_DIA0,
-    B_SB_DIA1,
-    B_SB_COEF0,
-    B_SB_COEF1,
     B_F_IDX0, // far list of the working column, two buffers
     B_F_IDX1,
     B_F_DIA0,
@@ -110,6 +104,9 @@ enum BufId {
     B_VW_SLOTS,
     B_V_ROFF,
     B_V_RLEN,
+    B_LOG_KEY, // addition log of the column being reduced
+    B_LOG_COEF,
+    B_LOG_DIA,
     B_BAR_BIRTH, // + d
     B_BAR_DEATH = B_BAR_BIRTH + kMaxDim + 1,
     B_BAR_BS = B_BAR_DEATH + kMaxDim + 1,
@@ -141,12 +138,6 @@ enum BufId {
     BB_V_COEF,
     BB_V_COUNT,
     BB_BITS,
-    BB_SB_IDX0,
-    BB_SB_IDX1,
-    BB_SB_DIA0,
-    BB_SB_DIA1,
-    BB_SB_COEF0,
-    BB_SB_COEF1,
     BB_F_IDX0,
     BB_F_IDX1,
     BB_F_DIA0,
@@ -159,6 +150,9 @@ enum BufId {
     BB_VW_SLOTS,
     BB_V_ROFF,
     BB_V_RLEN,
+    BB_LOG_KEY,
+    BB_LOG_COEF,
+    BB_LOG_DIA,
     BB_ST_B,
     BB_ST_D,
     BB_ST_BS,
@@ -192,7 +186,6 @@ struct DevCtx {
     int64_t hint_edges = 0;
     int64_t hint_list[kMaxDim + 2] = {};
     int64_t hint_v = 0;
-    int64_t hint_sb = 0;
     int64_t hint_far = 0;
     int64_t hint_vw = 0;
     int lds_per_block = 0;
@@ -202,9 +195,9 @@ struct DevCtx {
     hipGraphExec_t batch_exec = nullptr;
     std::vector<unsigned char> batch_key;
     int64_t batch_vstride = 0;
-    int64_t batch_sbstride = 0;
     int64_t batch_fstride = 0;
     int64_t batch_vwstride = 0;
+    int64_t batch_logstride = 0;
     u32 batch_capD = 0; // 0 = default delta size of the batched reduction
     int batch_wgpcu = 0; // 0 = default (1 persistent workgroup per CU)
 
@@ -746,9 +739,8 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         // working column: the delta in LDS (as large as a workgroup's share
         // allows), the sorted base in global scratch (grown on overflow)
         const size_t lds_budget = C.lds_per_block > 16384 ? (size_t)C.lds_per_block - 12288 : 0;
-        uint32_t capD = 4096;
+        uint32_t capD = kMaxDelta;
         while (capD > 256 && reduce_lds_bytes(capD) > lds_budget) capD >>= 1;
-        int64_t sbcap = std::max<int64_t>(C.hint_sb, std::max<int64_t>(1 << 16, 16ll * bound));
         int64_t fcap = std::max<int64_t>(C.hint_far, std::max<int64_t>(1 << 18, 256ll * bound));
         int64_t vwcap = std::max<int64_t>(C.hint_vw, 1 << 14);
         for (int attempt = 0;; ++attempt) {
@@ -760,18 +752,8 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             HIP_TRY(C.ensure(B_V_COEF, (size_t)vcap * 4, &q));
             V.coef = as<u32>(q);
             V.cap = vcap;
-            SortedBase SB;
-            for (int b = 0; b < 2; ++b) {
-                HIP_TRY(C.ensure(B_SB_IDX0 + b, (size_t)sbcap * 8, &q));
-                SB.idx[b] = as<int64_t>(q);
-                HIP_TRY(C.ensure(B_SB_DIA0 + b, (size_t)sbcap * 4, &q));
-                SB.dia[b] = as<float>(q);
-                HIP_TRY(C.ensure(B_SB_COEF0 + b, (size_t)sbcap * 4, &q));
-                SB.coef[b] = as<u32>(q);
-            }
-            SB.cap = sbcap;
             ReduceScratch SC;
-            SC.SB = SB;
+            SC.SB = SortedBase{nullptr, nullptr, nullptr, 0}; // carved in LDS by the kernel
             for (int b = 0; b < 2; ++b) {
                 HIP_TRY(C.ensure(B_F_IDX0 + b, (size_t)fcap * 8, &q));
                 SC.F.idx[b] = as<int64_t>(q);
@@ -791,6 +773,15 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             SC.Vw.slots = as<u32>(q);
             SC.Vw.nslots = nullptr; // set by the kernel (LDS)
             SC.Vw.mask = (u32)vwcap - 1;
+            // one entry per addition: the addition bound (2^18) never overflows it
+            const int64_t lcap = (1 << 18) + 64;
+            HIP_TRY(C.ensure(B_LOG_KEY, (size_t)lcap * 8, &q));
+            SC.lkey = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_LOG_COEF, (size_t)lcap * 4, &q));
+            SC.lcoef = as<u32>(q);
+            HIP_TRY(C.ensure(B_LOG_DIA, (size_t)lcap * 4, &q));
+            SC.ldia = as<float>(q);
+            SC.lcap = lcap;
             launch_fill_i64(ph.keys, phcap, kEmpty, st);
             launch_reset_dim(P.scal, st);
             ReduceJob<DistFull> J;
@@ -814,10 +805,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             if ((rs = read_scalars(C, P.scal, st))) return rs;
             const int status = C.host_scal->status;
             if (status == 0) break;
-            if (status == kRedBaseFull) {
-                sbcap *= 4;
-                C.hint_sb = sbcap;
-            } else if (status == kRedStoreFull) {
+            if (status == kRedStoreFull) {
                 vcap *= 4;
             } else if (status == kRedFarFull) {
                 fcap *= 4;
@@ -825,6 +813,8 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             } else if (status == kRedVFull) {
                 vwcap *= 4;
                 C.hint_vw = vwcap;
+            } else if (status == kRedLogFull) {
+                return fail(RIPS_E_HIP, "reduction log overflow");
             } else {
                 return fail(RIPS_E_HIP, "reduction exceeded its addition bound");
             }
@@ -832,10 +822,10 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         if ((int64_t)C.host_scal->vcount > C.hint_v) C.hint_v = (int64_t)C.host_scal->vcount;
         if (getenv("RIPS_DEBUG"))
             fprintf(stderr,
-                    "[rips reduce d%d] cols=%lld capD=%u sbcap=%lld lds_per_block=%d "
+                    "[rips reduce d%d] cols=%lld capD=%u lds_per_block=%d "
                     "base_cols=%llu entries=%llu maxV=%llu maxR=%llu additions=%llu pulls=%llu "
                     "merges=%llu splits=%llu pulled=%llu\n",
-                    k, (long long)S, capD, (long long)sbcap, C.lds_per_block,
+                    k, (long long)S, capD, C.lds_per_block,
                     C.host_scal->stat[kStatGlobalCols], C.host_scal->vcount,
                     C.host_scal->stat[kStatMaxV], C.host_scal->stat[kStatMaxR],
                     C.host_scal->stat[kStatAdditions], C.host_scal->stat[kStatPulls],
@@ -895,12 +885,11 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     int64_t ph_stride = 64;
     while (ph_stride < 2 * col_stride + 64) ph_stride <<= 1;
     const int64_t v_stride = std::max<int64_t>(C->batch_vstride, std::max<int64_t>(1 << 18, 4 * col_stride));
-    const int64_t sb_stride =
-        std::max<int64_t>(C->batch_sbstride, std::max<int64_t>(1 << 15, 16ll * n_max));
     const u32 capD = C->batch_capD ? C->batch_capD : batched_default_capD(lds_d, n_max);
     const int64_t f_stride =
         std::max<int64_t>(C->batch_fstride, std::max<int64_t>(1 << 15, 64ll * n_max));
     const int64_t vw_stride = std::max<int64_t>(C->batch_vwstride, 1 << 12);
+    const int64_t log_stride = std::max<int64_t>(C->batch_logstride, 1 << 14);
     const int64_t st_stride = 2 * (int64_t)n_max + npairs + 16;
     const int64_t d_stride = lds_d ? npairs + 4 : (int64_t)n_max * n_max + 4;
     const int64_t bits_stride = npairs / 32 + 2;
@@ -956,12 +945,6 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     ENS(BB_V_COUNT, G * 8, A.v_count, unsigned long long);
     ENS(BB_BITS, G * bits_stride * 4, A.bits_g, u32);
     A.bits_stride = bits_stride;
-    for (int h = 0; h < 2; ++h) {
-        ENS(BB_SB_IDX0 + h, G * sb_stride * 8, A.sb_idx[h], int64_t);
-        ENS(BB_SB_DIA0 + h, G * sb_stride * 4, A.sb_dia[h], float);
-        ENS(BB_SB_COEF0 + h, G * sb_stride * 4, A.sb_coef[h], u32);
-    }
-    A.sb_stride = sb_stride;
     A.capD = capD;
     for (int h = 0; h < 2; ++h) {
         ENS(BB_F_IDX0 + h, G * f_stride * 8, A.f_idx[h], int64_t);
@@ -976,6 +959,10 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     A.vw_stride = vw_stride;
     ENS(BB_V_ROFF, G * col_stride * 8, A.v_roff, int64_t);
     ENS(BB_V_RLEN, G * col_stride * 4, A.v_rlen, int);
+    ENS(BB_LOG_KEY, G * log_stride * 8, A.log_key, int64_t);
+    ENS(BB_LOG_COEF, G * log_stride * 4, A.log_coef, u32);
+    ENS(BB_LOG_DIA, G * log_stride * 4, A.log_dia, float);
+    A.log_stride = log_stride;
     ENS(BB_ST_B, G * st_stride * 4, A.st_b, float);
     ENS(BB_ST_D, G * st_stride * 4, A.st_d, float);
     ENS(BB_ST_BS, G * st_stride * 8, A.st_bs, int64_t);
@@ -1075,13 +1062,7 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
         *retry = true;
         return RIPS_E_CAPACITY;
     }
-    if (hs.status & 1) {
-        // a working column outgrew its sorted base: grow it and run again
-        C->batch_sbstride = sb_stride * 4;
-        if (C->batch_sbstride > (1ll << 26)) return fail(RIPS_E_CAPACITY, "working column overflow");
-        *retry = true;
-        return RIPS_E_CAPACITY;
-    }
+    if (hs.status & 1) return fail(RIPS_E_HIP, "batched reduction: delta or sorted base overflow");
     if (hs.status & 32) {
         C->batch_fstride = f_stride * 4;
         if (C->batch_fstride > (1ll << 28)) return fail(RIPS_E_CAPACITY, "far list overflow");
@@ -1091,6 +1072,12 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     if (hs.status & 64) {
         C->batch_vwstride = vw_stride * 4;
         if (C->batch_vwstride > (1ll << 24)) return fail(RIPS_E_CAPACITY, "V table overflow");
+        *retry = true;
+        return RIPS_E_CAPACITY;
+    }
+    if (hs.status & 128) {
+        C->batch_logstride = log_stride * 4;
+        if (C->batch_logstride > (1ll << 20)) return fail(RIPS_E_CAPACITY, "addition log overflow");
         *retry = true;
         return RIPS_E_CAPACITY;
     }
@@ -1389,8 +1376,8 @@ rips_status rips_backward_device(const float *d_data, int64_t n, int32_t dim, in
 
 rips_status rips_batched_set_config(int32_t delta_slots, int32_t workgroups_per_cu) {
     g_err.clear();
-    if (!(delta_slots == 0 || delta_slots == 1024 || delta_slots == 2048 || delta_slots == 4096))
-        return fail(RIPS_E_INVALID_ARG, "delta_slots must be 0, 1024, 2048 or 4096");
+    if (!(delta_slots == 0 || delta_slots == 512 || delta_slots == 1024 || delta_slots == 2048))
+        return fail(RIPS_E_INVALID_ARG, "delta_slots must be 0, 512, 1024 or 2048");
     if (workgroups_per_cu < 0 || workgroups_per_cu > 4)
         return fail(RIPS_E_INVALID_ARG, "workgroups_per_cu must be in [0, 4]");
     DevCtx *C;
@@ -1421,7 +1408,7 @@ rips_status rips_batched_autotune(const float *d_points, const int64_t *d_offset
     g_err.clear();
     if (reps < 1 || reps > 1000) return fail(RIPS_E_INVALID_ARG, "reps must be in [1, 1000]");
     if (!out || !out->bar_offsets) return fail(RIPS_E_INVALID_ARG, "null pointer");
-    const int32_t slots[3] = {1024, 2048, 4096};
+    const int32_t slots[3] = {512, 1024, 2048};
     const int32_t wgs[3] = {1, 2, 4};
     hipStream_t st = (hipStream_t)hip_stream;
     const int64_t noff = (int64_t)B * (max_dim + 1) + 1;

@@ -438,17 +438,13 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         __shared__ int s_nsl;
         WorkCol Dw;
         Staging Gs;
-        carve_reduce_lds(smem, A.capD, &s_nsl, &Dw, &Gs);
         ReduceScratch SC;
+        carve_reduce_lds(smem, A.capD, &s_nsl, &Dw, &Gs, &SC.SB);
         for (int h = 0; h < 2; ++h) {
-            SC.SB.idx[h] = A.sb_idx[h] + (int64_t)wg * A.sb_stride;
-            SC.SB.dia[h] = A.sb_dia[h] + (int64_t)wg * A.sb_stride;
-            SC.SB.coef[h] = A.sb_coef[h] + (int64_t)wg * A.sb_stride;
             SC.F.idx[h] = A.f_idx[h] + (int64_t)wg * A.f_stride;
             SC.F.dia[h] = A.f_dia[h] + (int64_t)wg * A.f_stride;
             SC.F.coef[h] = A.f_coef[h] + (int64_t)wg * A.f_stride;
         }
-        SC.SB.cap = A.sb_stride;
         SC.F.cap = A.f_stride;
         SC.Vw.keys = A.vw_keys + (int64_t)wg * A.vw_stride;
         SC.Vw.coef = A.vw_coef + (int64_t)wg * A.vw_stride;
@@ -456,6 +452,10 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         SC.Vw.slots = A.vw_slots + (int64_t)wg * A.vw_stride;
         SC.Vw.nslots = &RS.vns;
         SC.Vw.mask = (u32)A.vw_stride - 1;
+        SC.lkey = A.log_key + (int64_t)wg * A.log_stride;
+        SC.lcoef = A.log_coef + (int64_t)wg * A.log_stride;
+        SC.ldia = A.log_dia + (int64_t)wg * A.log_stride;
+        SC.lcap = A.log_stride;
         J.cand_avg = (float)n;
         J.app = PairHash{nullptr, nullptr, 0};
         gsync();
@@ -465,6 +465,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
                             : rstat == kRedStoreFull ? 2
                             : rstat == kRedFarFull   ? 32
                             : rstat == kRedVFull     ? 64
+                            : rstat == kRedLogFull   ? 128
                                                      : 8;
             atomicOr(A.status, bit);
         }
@@ -616,13 +617,12 @@ size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD) {
     return std::max(dpart + uf, reduce_lds_bytes(capD));
 }
 
-// default delta: the largest (4096 slots, about 106 KB of LDS with its
-// staging), which the autotuner picked on both the mixture and the circle
-// workloads; the LDS variant needs that much for its distances anyway
+// default delta: the largest (kMaxDelta slots, about 94 KB of LDS with its
+// staging and sorted base)
 u32 batched_default_capD(bool lds_d, int nmax) {
     (void)lds_d;
     (void)nmax;
-    return 4096;
+    return kMaxDelta;
 }
 
 hipError_t batched_prepare(bool lds_d, int nmax, u32 capD) {

@@ -43,10 +43,6 @@ struct BatchArgs {
     unsigned long long *v_count; // per workgroup
     u32 *bits_g;             // forest-edge bitmap per workgroup (global variant)
     int64_t bits_stride;
-    int64_t *sb_idx[2];      // sorted base of the working column, two buffers
-    float *sb_dia[2];
-    u32 *sb_coef[2];
-    int64_t sb_stride;       // sorted-base entries per workgroup and buffer
     u32 capD;                // LDS delta slots of the working column (power of two)
     int64_t *f_idx[2];       // far list of the working column, two buffers
     float *f_dia[2];
@@ -59,6 +55,10 @@ struct BatchArgs {
     int64_t vw_stride;       // its slots per workgroup (power of two)
     int64_t *v_roff;         // per column: stored R_j, if any
     int *v_rlen;
+    int64_t *log_key;        // addition log of the column being reduced
+    u32 *log_coef;
+    float *log_dia;
+    int64_t log_stride;
     float *st_b, *st_d;      // staged bars of the current cloud
     int64_t *st_bs, *st_ds;
     int64_t st_stride;       // nmax + C(nmax, 2)

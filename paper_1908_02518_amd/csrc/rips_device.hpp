@@ -249,8 +249,10 @@ __device__ __forceinline__ u64 group_mask() {
 // sigma u {j}; the scan stops at the first chunk holding a hit (the
 // early exit of the apparent-pair shortcut). Dense: all vertices; sparse:
 // the neighbour list of the vertex of v with the fewest neighbours.
+// Kept out of line: it ends lane groups early from inside a loop with a
+// group ballot, and the filter built with it inlined returned wrong columns.
 template <int G, class Dist>
-__device__ int group_find_max(const Ctx<Dist> &c, const int *v, int k, float bound, int jmin) {
+__device__ __attribute__((noinline)) int group_find_max(const Ctx<Dist> &c, const int *v, int k, float bound, int jmin) {
     const int lg = lane_id() & (G - 1);
     const u64 gm = group_mask<G>();
     if (c.nb.off == nullptr) {
@@ -309,7 +311,7 @@ __device__ __forceinline__ bool is_zero_apparent_cofacet(const Ctx<Dist> &c, con
 // v is rho's lexicographically largest same-diameter cofacet. Returns the
 // position of w in v, or -1.
 template <int G, class Dist>
-__device__ int zero_apparent_facet(const Ctx<Dist> &c, const int *v, int k, float dm) {
+__device__ __attribute__((noinline)) int zero_apparent_facet(const Ctx<Dist> &c, const int *v, int k, float dm) {
     if (k == 0) return -1;
     const int m = zero_pivot_facet(c, v, k, dm);
     if (m < 0) return -1;
@@ -450,7 +452,7 @@ struct SortShared {
 };
 
 template <int BT>
-__device__ int block_radix_sort(SortBufs b, int N, int lo_bytes, int hi_bytes, SortShared<BT> &S) {
+__device__ __attribute__((noinline)) int block_radix_sort(SortBufs b, int N, int lo_bytes, int hi_bytes, SortShared<BT> &S) {
     const int tid = threadIdx.x;
     const int w = tid / kWave;
     const int lane = lane_id();

@@ -699,7 +699,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 c
     __shared__ int s_ns;
     WorkCol D;
     Staging G;
-    carve_reduce_lds(smem, capD, &s_ns, &D, &G);
+    carve_reduce_lds(smem, capD, &s_ns, &D, &G, &SC.SB);
     SC.Vw.nslots = &S.vns;
     const int status = reduce_columns<kRedThreads>(J, D, G, SC, S);
     if (threadIdx.x == 0) {

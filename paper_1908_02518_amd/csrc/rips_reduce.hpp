@@ -55,13 +55,18 @@ struct Staging {
     int cap;
 };
 
-// Sorted base in global memory, two buffers of cap entries each.
+// Sorted base in LDS: entries [f, len) of cap, age ascending. A merge stages
+// the live part in registers (at most kSPer entries per thread) and writes
+// the result back in place.
 struct SortedBase {
-    int64_t *idx[2];
-    float *dia[2];
-    u32 *coef[2];
-    int64_t cap;
+    int64_t *idx;
+    float *dia;
+    u32 *coef;
+    int cap;
 };
+
+constexpr int kSPer = 10;        // base entries per thread during a merge
+constexpr u32 kMaxDelta = 2048;  // largest delta: its base (1.25x) fits kSPer x 256 threads
 
 // Far list in global memory, two buffers of cap entries each.
 struct FarList {
@@ -71,38 +76,50 @@ struct FarList {
     int64_t cap;
 };
 
-// Global scratch of one workgroup's reduction: sorted base, far list and the
-// working V column (a global table; its slot count lives in LDS).
+// Scratch of one workgroup's reduction: the sorted base (LDS, carved by the
+// kernel), the far list, the working V column (a global table used when V_j
+// is too large for LDS; its slot count lives in LDS) and the addition log.
 struct ReduceScratch {
     SortedBase SB;
     FarList F;
     WorkCol Vw;
+    // log of one column's additions: key -2 - o = "V_o of column o", key >= 0
+    // = "the simplex with that index"; coefficient; diameter (simplices)
+    int64_t *lkey;
+    u32 *lcoef;
+    float *ldia;
+    int64_t lcap;
 };
 
 // Result codes of the reduction.
 enum : int {
     kRedOk = 0,
-    kRedBaseFull = 1,  // sorted base too small
+    kRedBaseFull = 1,  // sorted base or delta full (cannot happen: sizes are bounded)
     kRedStoreFull = 2, // column store too small
     kRedBound = 3,     // addition bound reached
     kRedFarFull = 4,   // far list too small
     kRedVFull = 5,     // working V table too small
+    kRedLogFull = 6,   // addition log too small
 };
 
-// LDS bytes of a delta of capD slots and its staging.
+// LDS bytes of a delta of capD slots, its merge staging (capD / 4 entries)
+// and the sorted base (capD + capD / 4 entries).
 __host__ __device__ constexpr size_t reduce_lds_bytes(u32 capD) {
-    return (size_t)capD * 20 + (size_t)(capD / 4) * 16 + 2 * ((size_t)(capD / 4) + 1) * 4;
+    return (size_t)capD * 20 + (size_t)(capD / 4) * 16 + 2 * ((size_t)(capD / 4) + 1) * 4 +
+           (size_t)(capD + capD / 4) * 16;
 }
 
-// Carve the delta and its staging out of an LDS block (capD a power of two,
-// at least 256).
+// Carve the delta, its staging and the sorted base out of an LDS block
+// (capD a power of two, 256 <= capD <= kMaxDelta).
 __device__ __forceinline__ void carve_reduce_lds(unsigned char *q, u32 capD, int *nslots,
-                                                 WorkCol *D, Staging *G) {
-    const size_t c = capD, m = capD / 4;
+                                                 WorkCol *D, Staging *G, SortedBase *SB) {
+    const size_t c = capD, m = capD / 4, sc = capD + capD / 4;
     D->keys = (int64_t *)q;
     q += c * 8;
     G->idx = (int64_t *)q;
     q += m * 8;
+    SB->idx = (int64_t *)q;
+    q += sc * 8;
     D->coef = (u32 *)q;
     q += c * 4;
     D->diam = (float *)q;
@@ -113,10 +130,15 @@ __device__ __forceinline__ void carve_reduce_lds(unsigned char *q, u32 capD, int
     q += m * 4;
     G->coef = (u32 *)q;
     q += m * 4;
+    SB->dia = (float *)q;
+    q += sc * 4;
+    SB->coef = (u32 *)q;
+    q += sc * 4;
     G->cnt = (u32 *)q;
     q += (m + 1) * 4;
     G->nd = (int *)q;
     G->cap = (int)m;
+    SB->cap = (int)sc;
     D->nslots = nslots;
     D->mask = capD - 1;
 }
@@ -190,6 +212,8 @@ struct ReduceJob {
 template <int BT>
 struct RedShared {
     int base, full, abort, m, nbars, cur, merged, nit, vns, refine;
+    int nlog, gen, wgen, wn, spiv_own;
+    int64_t wbase, spiv_app, vest;
     int fw, fwn;    // far list: buffer appended to, entries in it
     int fr, nr;     // far list being pulled: buffer, entries
     float kd, kdn;  // near bound, its next value
@@ -205,6 +229,13 @@ struct RedShared {
     unsigned long long stat[13];
     unsigned long long tm[12]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner
     u32 hist[256];
+    // window of the sorted base from wbase (wn entries, valid while wgen ==
+    // gen) with the entries' pivot-table and apparent-pair lookups
+    int64_t win_idx[kWave];
+    float win_dia[kWave];
+    u32 win_coef[kWave];
+    int win_own[kWave];
+    int64_t win_app[kWave];
     // simplices whose coboundaries are added next: vertices, coefficient,
     // diameter, candidate source (vertex with the fewest neighbours, -1 =
     // all vertices) and prefix offsets of their candidate counts
@@ -252,7 +283,7 @@ __device__ __forceinline__ int block_scan_excl(int x, int *s_w, int *total) {
 // tables (all threads of the block)
 // ---------------------------------------------------------------------------
 template <int BT>
-__device__ void wc_reset(const WorkCol &h) {
+__device__ __forceinline__ void wc_reset(const WorkCol &h) {
     const int ns = min(*h.nslots, (int)h.mask + 1);
     for (int i = threadIdx.x; i < ns; i += BT) {
         const u32 s = h.slots[i];
@@ -265,7 +296,7 @@ __device__ void wc_reset(const WorkCol &h) {
 }
 
 template <int BT>
-__device__ void wc_clear_all(const WorkCol &h) {
+__device__ __forceinline__ void wc_clear_all(const WorkCol &h) {
     for (u32 q = threadIdx.x; q <= h.mask; q += BT) {
         st(&h.keys[q], kEmpty);
         st(&h.coef[q], 0u);
@@ -278,7 +309,7 @@ __device__ void wc_clear_all(const WorkCol &h) {
 // Oldest live entry of the delta (block-wide). Coefficients are normalised
 // mod p on the way (no addition runs concurrently).
 template <int BT>
-__device__ PivotCand wc_oldest(const WorkCol &R, u32 p, RedShared<BT> &S) {
+__device__ __forceinline__ PivotCand wc_oldest(const WorkCol &R, u32 p, RedShared<BT> &S) {
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     PivotCand best;
     best.idx = kEmpty;
@@ -340,57 +371,97 @@ __device__ __forceinline__ int add_entry(const WorkCol &D, const FarList &F, Red
 
 // Wave 0 moves the front of S past entries whose total coefficient (S + D)
 // is zero; the delta's copies of those keys are zeroed, since their part of
-// the sum is spent. S.spiv = the first live entry with its total, if any.
-template <int BT>
-__device__ void base_advance(const WorkCol &D, const SortedBase &SB, u32 p, RedShared<BT> &S) {
+// the sum is spent. S.spiv = the first live entry with its total, if any,
+// and S.spiv_own / S.spiv_app its pivot-table owner and apparent partner.
+// The base is read through a window of 64 entries kept in LDS; a window is
+// loaded with the table lookups of all its entries at once (owners do not
+// change while one column is reduced), so a pivot found in the base costs no
+// further global round trip.
+template <int BT, class Dist>
+__device__ __forceinline__ void base_advance(const ReduceJob<Dist> &J, const WorkCol &D, const SortedBase &SB,
+                             u32 p, RedShared<BT> &S) {
     if (threadIdx.x >= kWave) return;
     const int lane = lane_id();
-    const int cur = S.cur;
     int64_t f = S.f;
     const int64_t len = S.len;
     PivotCand out;
     out.idx = kEmpty;
     out.diam = 0.0f;
     out.coef = 0;
+    int own = -1;
+    int64_t app = -1;
+    bool wvalid = S.wgen == S.gen;
+    int64_t wbase = S.wbase;
+    int wn = S.wn;
+    bool reloaded = false;
     while (f < len) {
-        const int64_t q = f + lane;
-        const bool valid = q < len;
+        if (!wvalid || f < wbase || f >= wbase + wn) {
+            wbase = f;
+            wn = (int)min<int64_t>(kWave, len - f);
+            int64_t id = kEmpty;
+            float dm = 0.0f;
+            u32 cs = 0;
+            int ow = -1;
+            int64_t ap = -1;
+            if (lane < wn) {
+                id = SB.idx[f + lane];
+                dm = SB.dia[f + lane];
+                cs = SB.coef[f + lane] % p;
+                ow = ph_find(J.ph, id);
+                ap = J.app.keys ? pair_find(J.app, id) : -1;
+            }
+            S.win_idx[lane] = id;
+            S.win_dia[lane] = dm;
+            S.win_coef[lane] = cs;
+            S.win_own[lane] = ow;
+            S.win_app[lane] = ap;
+            wvalid = true;
+            reloaded = true;
+        }
+        const int l0 = (int)(f - wbase);
+        const bool valid = lane >= l0 && lane < wn;
+        const int64_t id = S.win_idx[lane];
         u32 total = 0;
         int slot = -1;
-        int64_t id = 0;
-        float dm = 0.0f;
         if (valid) {
-            id = pick(SB.idx, cur)[q];
-            dm = pick(SB.dia, cur)[q];
-            const u32 cs = pick(SB.coef, cur)[q];
             slot = wc_find(D, id);
             const u32 cd = slot >= 0 ? ld(&D.coef[slot]) % p : 0u;
-            total = (cs + cd) % p;
+            total = (S.win_coef[lane] + cd) % p;
         }
         const u64 live = __ballot(valid && total != 0);
         const int first = live ? __ffsll((unsigned long long)live) - 1 : kWave;
         if (valid && lane < first && slot >= 0) st(&D.coef[slot], 0u);
         if (live) {
             out.idx = __shfl(id, first, kWave);
-            out.diam = __shfl(dm, first, kWave);
+            out.diam = __shfl(S.win_dia[lane], first, kWave);
             out.coef = __shfl(total, first, kWave);
-            f += first;
+            own = __shfl(S.win_own[lane], first, kWave);
+            app = __shfl(S.win_app[lane], first, kWave);
+            f = wbase + first;
             break;
         }
-        f += kWave;
+        f = wbase + wn;
     }
     if (f > len) f = len;
     if (lane == 0) {
         S.f = f;
         S.spiv = out;
+        S.spiv_own = own;
+        S.spiv_app = app;
+        if (reloaded) {
+            S.wbase = wbase;
+            S.wn = wn;
+            S.wgen = S.gen;
+        }
     }
 }
 
 // Merge the live entries of D into S[f, len) (all threads); D is empty
-// afterwards. Returns 0 or a result code.
+// afterwards and S starts at 0. Returns 0 or a result code.
 template <int BT>
-__device__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &SB, u32 p,
+__device__ __forceinline__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &SB, u32 p,
                           RedShared<BT> &S) {
+    static_assert(kSPer * BT >= (int)(kMaxDelta + kMaxDelta / 4), "base does not fit the staging");
     RED_T0(t_mrg);
     const int tid = threadIdx.x;
     const int ns = min(*D.nslots, (int)D.mask + 1);
@@ -399,9 +470,8 @@ __device__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &
     for (int i = tid; i < ns; i += BT) cnt += (ld(&D.coef[D.slots[i]]) % p) != 0 ? 1 : 0;
     int m;
     int at = block_scan_excl<BT>(cnt, S.w, &m);
-    if (m > G.cap) return kRedBaseFull; // cannot happen: D holds at most G.cap slots here
-    const int64_t f = S.f, sl = S.len - S.f;
-    if (sl + m > SB.cap) return kRedBaseFull;
+    const int f = (int)S.f, sl = (int)(S.len - S.f);
+    if (m > G.cap || sl + m > SB.cap) return kRedBaseFull; // bounded by construction
     for (int i = tid; i < ns; i += BT) {
         const u32 s = D.slots[i];
         const u32 cf = ld(&D.coef[s]) % p;
@@ -428,20 +498,34 @@ __device__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &
     }
     for (int i = tid; i <= m; i += BT) G.cnt[i] = 0;
     __syncthreads();
-    // 3. every base entry: lower bound in M (first entry not older than
-    // it), and the duplicate flag (bit 31 of M's coefficient)
-    const int cur = S.cur, nxt = cur ^ 1;
-    for (int64_t r = tid; r < sl; r += BT) {
-        const int64_t id = pick(SB.idx, cur)[f + r];
-        const float dm = pick(SB.dia, cur)[f + r];
-        int lo = 0, hi = m;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (older_key(Md[mid], Mi[mid], dm, id)) lo = mid + 1;
-            else hi = mid;
+    // 3. every base entry into registers with its lower bound in M (first
+    // entry not older than it); counts; duplicate flag (bit 31 of M's
+    // coefficient)
+    int64_t rid[kSPer];
+    float rdm[kSPer];
+    u32 rcf[kSPer];
+    int rlo[kSPer];
+#pragma unroll
+    for (int i = 0; i < kSPer; ++i) {
+        const int r = tid + i * BT;
+        rlo[i] = -1;
+        rid[i] = 0;
+        rdm[i] = 0.0f;
+        rcf[i] = 0;
+        if (r < sl) {
+            rid[i] = SB.idx[f + r];
+            rdm[i] = SB.dia[f + r];
+            rcf[i] = SB.coef[f + r];
+            int lo = 0, hi = m;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (older_key(Md[mid], Mi[mid], rdm[i], rid[i])) lo = mid + 1;
+                else hi = mid;
+            }
+            rlo[i] = lo;
+            atomicAdd(&G.cnt[lo], 1u);
+            if (lo < m && Mi[lo] == rid[i]) atomicOr(&Mc[lo], 0x80000000u);
         }
-        atomicAdd(&G.cnt[lo], 1u);
-        if (lo < m && Mi[lo] == id) atomicOr(&Mc[lo], 0x80000000u);
     }
     __syncthreads();
     // 4. inclusive prefix of the counts (base entries older than M[i] for a
@@ -450,7 +534,7 @@ __device__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &
     for (int b0 = 0; b0 <= m; b0 += BT) {
         const int i = b0 + tid;
         const int c = i <= m ? (int)G.cnt[i] : 0;
-        const int nd = i < m ? ((ld(&Mc[i]) & 0x80000000u) ? 0 : 1) : 0;
+        const int nd = i < m ? ((Mc[i] & 0x80000000u) ? 0 : 1) : 0;
         int tc, tn;
         const int ec = block_scan_excl<BT>(c, S.w, &tc);
         const int en = block_scan_excl<BT>(nd, S.w, &tn);
@@ -462,40 +546,37 @@ __device__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &
         carry_n += tn;
     }
     __syncthreads();
-    // 5. scatter: base entry r goes to r + (non-duplicates before its lower
-    // bound); non-duplicate M[i] goes to (base entries older) + (non-
-    // duplicates before it)
-    for (int64_t r = tid; r < sl; r += BT) {
-        const int64_t id = pick(SB.idx, cur)[f + r];
-        const float dm = pick(SB.dia, cur)[f + r];
-        u32 cf = pick(SB.coef, cur)[f + r];
-        int lo = 0, hi = m;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (older_key(Md[mid], Mi[mid], dm, id)) lo = mid + 1;
-            else hi = mid;
+    // 5. write in place (every base entry was read in step 3): base entry r
+    // goes to r + (non-duplicates before its lower bound); non-duplicate M[i]
+    // goes to (base entries older) + (non-duplicates before it)
+#pragma unroll
+    for (int i = 0; i < kSPer; ++i) {
+        const int r = tid + i * BT;
+        if (r < sl) {
+            const int lo = rlo[i];
+            u32 cf = rcf[i];
+            if (lo < m && Mi[lo] == rid[i]) cf = (cf + (Mc[lo] & 0x7fffffffu)) % p;
+            const int dst = r + G.nd[lo];
+            SB.idx[dst] = rid[i];
+            SB.dia[dst] = rdm[i];
+            SB.coef[dst] = cf;
         }
-        if (lo < m && Mi[lo] == id) cf = (cf + (Mc[lo] & 0x7fffffffu)) % p;
-        const int64_t dst = r + G.nd[lo];
-        pick(SB.idx, nxt)[dst] = id;
-        pick(SB.dia, nxt)[dst] = dm;
-        pick(SB.coef, nxt)[dst] = cf;
     }
     for (int i = tid; i < m; i += BT) {
         const u32 cf = Mc[i];
         if (cf & 0x80000000u) continue;
-        const int64_t dst = (int64_t)G.cnt[i] + G.nd[i];
-        pick(SB.idx, nxt)[dst] = Mi[i];
-        pick(SB.dia, nxt)[dst] = Md[i];
-        pick(SB.coef, nxt)[dst] = cf;
+        const int dst = (int)G.cnt[i] + G.nd[i];
+        SB.idx[dst] = Mi[i];
+        SB.dia[dst] = Md[i];
+        SB.coef[dst] = cf;
     }
     const int nondup = carry_n;
-    gsync();
+    __syncthreads();
     if (tid == 0) {
-        S.cur = nxt;
         S.f = 0;
         S.len = sl + nondup;
         S.merged = 1;
+        S.gen += 1;
         S.stat[9] += 1;
     }
     wc_clear_all<BT>(D);
@@ -506,19 +587,18 @@ __device__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &
 // S longer than smax live entries: lower kd to the diameter in the middle
 // of S and move the entries above it to the far list (D is empty here).
 template <int BT>
-__device__ int base_split(const SortedBase &SB, const FarList &F, u32 p, int smax,
+__device__ __forceinline__ int base_split(const SortedBase &SB, const FarList &F, u32 p, int smax,
                           RedShared<BT> &S) {
     const int tid = threadIdx.x;
     if (S.len - S.f <= smax) return kRedOk;
     RED_T0(t_spl);
-    const int cur = S.cur;
     if (tid == 0) {
         const int64_t q0 = S.f + smax / 2;
-        const float kd = pick(SB.dia, cur)[q0];
+        const float kd = SB.dia[q0];
         int64_t lo = q0, hi = S.len; // first entry with a larger diameter
         while (lo < hi) {
             const int64_t mid = (lo + hi) >> 1;
-            if (pick(SB.dia, cur)[mid] > kd) hi = mid;
+            if (SB.dia[mid] > kd) hi = mid;
             else lo = mid + 1;
         }
         S.qsplit = lo;
@@ -531,8 +611,8 @@ __device__ int base_split(const SortedBase &SB, const FarList &F, u32 p, int sma
     if (q >= len) return kRedOk; // one diameter from the middle on: keep it all
     bool ok = true;
     for (int64_t r = q + tid; r < len; r += BT) {
-        const u32 cf = pick(SB.coef, cur)[r] % p;
-        if (cf != 0) ok = ok && far_append<BT>(F, S, pick(SB.idx, cur)[r], pick(SB.dia, cur)[r], cf);
+        const u32 cf = SB.coef[r] % p;
+        if (cf != 0) ok = ok && far_append<BT>(F, S, SB.idx[r], SB.dia[r], cf);
     }
     if (!ok) S.abort = kRedFarFull;
     gsync();
@@ -541,6 +621,7 @@ __device__ int base_split(const SortedBase &SB, const FarList &F, u32 p, int sma
         S.len = q;
         S.kd = kd;
         S.merged = 1;
+        S.gen += 1;
         S.stat[10] += 1;
     }
     __syncthreads();
@@ -552,7 +633,7 @@ __device__ int base_split(const SortedBase &SB, const FarList &F, u32 p, int sma
 // (all threads; most <= G.cap). Returns the number of live entries; D is
 // unchanged when that is above `most`.
 template <int BT>
-__device__ int delta_compact(const WorkCol &D, const Staging &G, u32 p, int most,
+__device__ __forceinline__ int delta_compact(const WorkCol &D, const Staging &G, u32 p, int most,
                              RedShared<BT> &S) {
     const int tid = threadIdx.x;
     const int ns = min(*D.nslots, (int)D.mask + 1);
@@ -608,7 +689,7 @@ __device__ __forceinline__ int delta_check(const WorkCol &D, const Staging &G,
 // of the non-negative float diameters, refined while one bin is far too
 // full), and move those entries into the delta.
 template <int BT>
-__device__ int far_pull(const WorkCol &D, const Staging &G, const ReduceScratch &SC, u32 p,
+__device__ __forceinline__ int far_pull(const WorkCol &D, const Staging &G, const ReduceScratch &SC, u32 p,
                         int target, RedShared<BT> &S) {
     const FarList &F = SC.F;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
@@ -726,7 +807,7 @@ __device__ int far_pull(const WorkCol &D, const Staging &G, const ReduceScratch 
 // the item's coefficient. Dense candidates: all vertices; sparse: the
 // neighbours of the item's vertex with the fewest.
 template <int BT, class Dist>
-__device__ int add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
+__device__ __forceinline__ int add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
                          const Staging &G, const ReduceScratch &SC) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
@@ -803,7 +884,7 @@ __device__ int add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkC
 
 // Add mul times the coboundaries of the simplices of a stored V column.
 template <int BT, class Dist>
-__device__ int add_vcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
+__device__ __forceinline__ int add_vcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
                            const Staging &G, const ReduceScratch &SC, int64_t off, int len,
                            u32 mul) {
     const int tid = threadIdx.x;
@@ -826,7 +907,7 @@ __device__ int add_vcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const Wor
 
 // Add neg times the stored R column entries [off, off + len), in segments.
 template <int BT, class Dist>
-__device__ int add_rcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
+__device__ __forceinline__ int add_rcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
                            const Staging &G, const ReduceScratch &SC, int64_t off, int len,
                            u32 neg) {
     const u32 p = J.p;
@@ -852,7 +933,7 @@ __device__ int add_rcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const Wor
 // Append the live entries of a table (V_j) or of the sorted base to the
 // column store; returns the count, or -1 when the store is full.
 template <int BT>
-__device__ int store_table(const WorkCol &T, const VStore &V, unsigned long long *vcount, u32 p,
+__device__ __forceinline__ int store_table(const WorkCol &T, const VStore &V, unsigned long long *vcount, u32 p,
                            RedShared<BT> &S, int64_t *off_out) {
     const int tid = threadIdx.x;
     const int ns = min(*T.nslots, (int)T.mask + 1);
@@ -879,13 +960,12 @@ __device__ int store_table(const WorkCol &T, const VStore &V, unsigned long long
 }
 
 template <int BT>
-__device__ int store_base(const SortedBase &SB, const VStore &V, unsigned long long *vcount,
+__device__ __forceinline__ int store_base(const SortedBase &SB, const VStore &V, unsigned long long *vcount,
                           u32 p, RedShared<BT> &S, int64_t *off_out) {
     const int tid = threadIdx.x;
-    const int cur = S.cur;
     const int64_t f0 = S.f, nsrc = S.len - S.f;
     int cnt = 0;
-    for (int64_t i = tid; i < nsrc; i += BT) cnt += (pick(SB.coef, cur)[f0 + i] % p) != 0 ? 1 : 0;
+    for (int64_t i = tid; i < nsrc; i += BT) cnt += (SB.coef[f0 + i] % p) != 0 ? 1 : 0;
     int tot;
     int at = block_scan_excl<BT>(cnt, S.w, &tot);
     if (tid == 0) S.vbase = atomicAdd(vcount, (unsigned long long)tot);
@@ -893,10 +973,10 @@ __device__ int store_base(const SortedBase &SB, const VStore &V, unsigned long l
     const int64_t vb = (int64_t)S.vbase;
     if (vb + tot > V.cap) return -1;
     for (int64_t i = tid; i < nsrc; i += BT) {
-        const u32 cf = pick(SB.coef, cur)[f0 + i] % p;
+        const u32 cf = SB.coef[f0 + i] % p;
         if (cf != 0) {
-            V.idx[vb + at] = pick(SB.idx, cur)[f0 + i];
-            V.diam[vb + at] = pick(SB.dia, cur)[f0 + i];
+            V.idx[vb + at] = SB.idx[f0 + i];
+            V.diam[vb + at] = SB.dia[f0 + i];
             V.coef[vb + at] = cf;
             ++at;
         }
@@ -908,7 +988,7 @@ __device__ int store_base(const SortedBase &SB, const VStore &V, unsigned long l
 // live entries of the working column's near part (D merged into S first
 // when S is in use); -1 on failure
 template <int BT>
-__device__ int count_live(const WorkCol &T, u32 p, RedShared<BT> &S) {
+__device__ __forceinline__ int count_live(const WorkCol &T, u32 p, RedShared<BT> &S) {
     const int ns = min(*T.nslots, (int)T.mask + 1);
     int cnt = 0;
     for (int i = threadIdx.x; i < ns; i += BT) cnt += (ld(&T.coef[T.slots[i]]) % p) != 0 ? 1 : 0;
@@ -918,19 +998,71 @@ __device__ int count_live(const WorkCol &T, u32 p, RedShared<BT> &S) {
 }
 
 template <int BT>
-__device__ int64_t count_live_base(const SortedBase &SB, u32 p, RedShared<BT> &S) {
-    const int cur = S.cur;
+__device__ __forceinline__ int64_t count_live_base(const SortedBase &SB, u32 p, RedShared<BT> &S) {
     int cnt = 0;
-    for (int64_t i = S.f + threadIdx.x; i < S.len; i += BT) cnt += (pick(SB.coef, cur)[i] % p) != 0;
+    for (int64_t i = S.f + threadIdx.x; i < S.len; i += BT) cnt += (SB.coef[i] % p) != 0;
     int tot;
     (void)block_scan_excl<BT>(cnt, S.w, &tot);
     return tot;
 }
 
+// Append one addition to the column's log (thread 0). False when full.
+template <int BT>
+__device__ __forceinline__ bool log_add(const ReduceScratch &SC, RedShared<BT> &S, int64_t key,
+                                        u32 coef, float dm, int64_t vlen) {
+    if ((int64_t)S.nlog >= SC.lcap) return false;
+    SC.lkey[S.nlog] = key;
+    SC.lcoef[S.nlog] = coef;
+    SC.ldia[S.nlog] = dm;
+    S.nlog += 1;
+    S.vest += vlen;
+    return true;
+}
+
+// V_j = sigma_j + the logged combination, summed into table T (all threads).
+// Returns false when T overflowed (T is then in an unspecified state).
+template <int BT, class Dist>
+__device__ __forceinline__ bool materialize_v(const ReduceJob<Dist> &J, const ReduceScratch &SC, const WorkCol &T,
+                              int64_t sidx, float sdm, RedShared<BT> &S) {
+    const u32 p = J.p;
+    bool ok = true;
+    if (threadIdx.x == 0) ok = wc_add(T, sidx, sdm, 1u, p);
+    const int nl = S.nlog;
+    for (int e = threadIdx.x; e < nl; e += BT) {
+        const int64_t key = SC.lkey[e];
+        const u32 cf = SC.lcoef[e];
+        if (key >= 0) {
+            ok = ok && wc_add(T, key, SC.ldia[e], cf, p);
+            continue;
+        }
+        const int o = (int)(-2 - key);
+        const int vlen = J.V.len[o];
+        if (vlen < 0) {
+            ok = ok && wc_add(T, J.cols.idx[o], J.cols.diam[o], cf, p);
+        } else {
+            const int64_t vo = J.V.off[o];
+            for (int q = 0; q < vlen && ok; ++q)
+                ok = wc_add(T, J.V.idx[vo + q], J.V.diam[vo + q],
+                            (u32)((u64)cf * J.V.coef[vo + q] % p), p);
+        }
+    }
+    if (!ok) S.abort = 1;
+    gsync();
+    const bool res = S.abort == 0;
+    __syncthreads();
+    if (threadIdx.x == 0) S.abort = 0;
+    __syncthreads();
+    return res;
+}
+
 // Full reduction of column j. Returns a result code; on anything but kRedOk
 // nothing of column j has been published.
+//
+// V_j is not kept up to date at every addition: the additions are logged
+// (column o with its factor, or an apparent facet rho) and V_j is summed
+// once, when the column pairs.
 template <int BT, class Dist>
-__device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Staging &G,
+__device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Staging &G,
                           const ReduceScratch &SC, int j, RedShared<BT> &S) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
@@ -938,7 +1070,6 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     const int64_t sidx = J.cols.idx[j];
     const float sdm = J.cols.diam[j];
-    const WorkCol &Vw = SC.Vw;
     RED_T0(t_setup);
     if (tid == 0) {
         S.abort = 0;
@@ -948,14 +1079,16 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
         S.kd = INFINITY;
         S.fw = 0;
         S.fwn = 0;
+        S.nlog = 0;
+        S.vest = 1;
+        S.gen += 1; // the base window of the previous column is stale
         S.nit = 1;
         S.it_coef[0] = 1u;
         S.it_diam[0] = sdm;
         decode(sidx, k, c.n, c.B, S.it_v[0]);
-        if (!wc_add(Vw, sidx, sdm, 1u, p)) S.abort = kRedVFull;
     }
-    gsync();
-    int result = S.abort ? S.abort : add_items<BT>(J, S, D, G, SC);
+    __syncthreads();
+    int result = add_items<BT>(J, S, D, G, SC);
     RED_T1(S, 6, t_setup);
     int nadd = 0;
     while (result == kRedOk) {
@@ -967,15 +1100,16 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
             break;
         }
         PivotCand piv;
+        bool from_base = false;
         RED_T0(t_piv);
         for (;;) {
-            base_advance<BT>(D, SC.SB, p, S);
+            base_advance<BT>(J, D, SC.SB, p, S);
             __syncthreads();
             const PivotCand dmin = wc_oldest<BT>(D, p, S);
             const PivotCand smin = S.spiv;
-            if (smin.idx == kEmpty) piv = dmin;
-            else if (dmin.idx == kEmpty || dmin.idx == smin.idx) piv = smin;
-            else piv = older(dmin, smin) ? dmin : smin;
+            from_base = smin.idx != kEmpty &&
+                        (dmin.idx == kEmpty || dmin.idx == smin.idx || !older(dmin, smin));
+            piv = from_base ? smin : dmin;
             if (piv.idx != kEmpty || S.fwn == 0) break;
             result = far_pull<BT>(D, G, SC, p, ((int)D.mask + 1) / 2, S);
             if (result) break;
@@ -997,34 +1131,28 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
             break;
         }
         RED_T0(t_own);
-        // pivot table and apparent-pair table, looked up by two waves at once
-        if (tid == 0) S.owner = ph_find(J.ph, piv.idx);
-        if (J.app.keys && tid == kWave) S.appv = pair_find(J.app, piv.idx);
+        if (from_base) {
+            // looked up with the base window
+            if (tid == 0) {
+                S.owner = S.spiv_own;
+                S.appv = S.spiv_app;
+            }
+        } else {
+            // pivot table and apparent-pair table, read by two waves at once
+            if (tid == 0) S.owner = ph_find(J.ph, piv.idx);
+            if (tid == kWave) S.appv = J.app.keys ? pair_find(J.app, piv.idx) : -1;
+        }
         __syncthreads();
         RED_T1(S, 11, t_own);
         const int64_t o = S.owner;
         if (o >= 0) {
-            // R_j -= lambda R_o and V_j -= lambda V_o, lambda = piv / pivot(R_o)
+            // R_j -= lambda R_o (and V_j -= lambda V_o), lambda = piv / pivot(R_o)
             const u32 lam = (u32)((u64)piv.coef * J.inv[J.V.pivcoef[o]] % p);
             const u32 neg = (p - lam) % p;
             const int vlen = J.V.len[o];
             const int rlen = J.V.rlen[o];
-            // V_j first (small), then R_j
-            bool vok = true;
-            if (vlen < 0) {
-                if (tid == 0) vok = wc_add(Vw, J.cols.idx[o], J.cols.diam[o], neg, p);
-            } else {
-                const int64_t vo = J.V.off[o];
-                for (int e = tid; e < vlen; e += BT)
-                    vok = vok && wc_add(Vw, J.V.idx[vo + e],
-                                        J.V.diam[vo + e], (u32)((u64)neg * J.V.coef[vo + e] % p), p);
-            }
-            if (!vok) S.abort = kRedVFull;
-            gsync();
-            if (S.abort) {
-                result = S.abort;
-                break;
-            }
+            if (tid == 0 && !log_add(SC, S, -2 - o, neg, 0.0f, vlen < 0 ? 1 : vlen))
+                S.abort = kRedLogFull;
             RED_T0(t_add);
             if (rlen >= 0) {
                 result = add_rcolumn<BT>(J, S, D, G, SC, J.V.roff[o], rlen, neg);
@@ -1042,6 +1170,8 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
                 result = add_vcolumn<BT>(J, S, D, G, SC, J.V.off[o], vlen, neg);
             }
             RED_T1(S, 1, t_add);
+            __syncthreads();
+            if (result == kRedOk && S.abort) result = S.abort;
             ++nadd;
             continue;
         }
@@ -1061,7 +1191,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
                     S.nit = 1;
                     S.it_coef[0] = (p - lam) % p;
                     S.it_diam[0] = piv.diam;
-                    if (!wc_add(Vw, a >> 3, piv.diam, (p - lam) % p, p)) S.abort = kRedVFull;
+                    if (!log_add(SC, S, a >> 3, (p - lam) % p, piv.diam, 1)) S.abort = kRedLogFull;
                 }
             }
         } else if (w == 0) {
@@ -1080,12 +1210,12 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
                     S.nit = 1;
                     S.it_coef[0] = (p - lam) % p;
                     S.it_diam[0] = piv.diam;
-                    if (!wc_add(Vw, simplex_index(rv, k, c.B), piv.diam, (p - lam) % p, p))
-                        S.abort = kRedVFull;
+                    if (!log_add(SC, S, simplex_index(rv, k, c.B), (p - lam) % p, piv.diam, 1))
+                        S.abort = kRedLogFull;
                 }
             }
         }
-        gsync();
+        __syncthreads();
         RED_T1(S, 7, t_app);
         if (S.abort) {
             result = S.abort;
@@ -1096,16 +1226,11 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
             ++nadd;
             continue;
         }
-        // unowned pivot: persistence pair (sigma_j, pivot). Store V_j, and
-        // R_j as well when it has no far part and is cheaper to add than
-        // V_j's coboundaries are to recompute.
+        // unowned pivot: persistence pair (sigma_j, pivot). R_j is stored
+        // when it has no far part and is cheaper to add than V_j's
+        // coboundaries are to recompute (|V_j| estimated from the log); then
+        // V_j is summed from the log and stored.
         RED_T0(t_st);
-        int64_t voff = 0;
-        const int vn = store_table<BT>(Vw, J.V, J.vcount, p, S, &voff);
-        if (vn < 0) {
-            result = kRedStoreFull;
-            break;
-        }
         int64_t roff = 0;
         int rn = -1;
         if (S.fwn == 0) {
@@ -1114,17 +1239,37 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
                 if (result) break;
             }
             __syncthreads();
-            const bool from_base = S.len > 0;
-            const int64_t live = from_base ? count_live_base<BT>(SC.SB, p, S)
-                                           : (int64_t)count_live<BT>(D, p, S);
-            if ((float)live <= 2.0f * (float)vn * J.cand_avg) {
-                rn = from_base ? store_base<BT>(SC.SB, J.V, J.vcount, p, S, &roff)
-                               : store_table<BT>(D, J.V, J.vcount, p, S, &roff);
+            const bool rb = S.len > 0;
+            const int64_t live = rb ? count_live_base<BT>(SC.SB, p, S)
+                                    : (int64_t)count_live<BT>(D, p, S);
+            if ((float)live <= 2.0f * (float)S.vest * J.cand_avg) {
+                rn = rb ? store_base<BT>(SC.SB, J.V, J.vcount, p, S, &roff)
+                        : store_table<BT>(D, J.V, J.vcount, p, S, &roff);
                 if (rn < 0) {
                     result = kRedStoreFull;
                     break;
                 }
             }
+        }
+        __syncthreads();
+        // V_j: in D's LDS slots when it fits comfortably, else in the global table
+        wc_reset<BT>(D);
+        const bool try_lds = S.vest <= (int64_t)(D.mask + 1) / 2;
+        const bool used_lds = try_lds && materialize_v<BT>(J, SC, D, sidx, sdm, S);
+        if (!used_lds) {
+            if (try_lds) wc_clear_all<BT>(D); // the failed attempt left D unspecified
+            if (!materialize_v<BT>(J, SC, SC.Vw, sidx, sdm, S)) {
+                wc_clear_all<BT>(SC.Vw);
+                result = kRedVFull;
+                break;
+            }
+        }
+        int64_t voff = 0;
+        const int vn = store_table<BT>(used_lds ? D : SC.Vw, J.V, J.vcount, p, S, &voff);
+        if (!used_lds) wc_reset<BT>(SC.Vw);
+        if (vn < 0) {
+            result = kRedStoreFull;
+            break;
         }
         if (tid == 0) {
             if ((unsigned long long)vn > S.stat[6]) S.stat[6] = vn;
@@ -1160,7 +1305,6 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
     __syncthreads();
     RED_T0(t_rst);
     wc_reset<BT>(D);
-    wc_reset<BT>(Vw);
     RED_T1(S, 9, t_rst);
     return result;
 }
@@ -1171,7 +1315,7 @@ __device__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Stag
 // additions, bars_nonzero, essential, columns that used the sorted base or
 // far list, largest stored V column, largest working column.
 template <int BT, class Dist>
-__device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &D, const Staging &G,
+__device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &D, const Staging &G,
                               const ReduceScratch &SC, RedShared<BT> &S) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
@@ -1183,9 +1327,12 @@ __device__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &D, const 
         S.base = 0;
         S.abort = 0;
         S.nbars = 0;
-        S.cur = 0;
         S.len = 0;
         S.f = 0;
+        S.gen = 0;
+        S.wgen = -1;
+        S.wbase = 0;
+        S.wn = 0;
     }
     if (tid < 13) S.stat[tid] = 0;
     if (tid < 12) S.tm[tid] = 0;
