@@ -66,6 +66,7 @@ struct SortedBase {
 };
 
 constexpr int kSPer = 10;        // base entries per thread during a merge
+constexpr int kPullUnroll = 8;   // far-list entries in flight per thread in a pull
 constexpr u32 kMaxDelta = 2048;  // largest delta: its base (1.25x) fits kSPer x 256 threads
 
 // Far list in global memory, two buffers of cap entries each.
@@ -212,11 +213,12 @@ struct ReduceJob {
 template <int BT>
 struct RedShared {
     int base, full, abort, m, nbars, cur, merged, nit, vns, refine;
-    int nlog, gen, wgen, wn, spiv_own;
-    int64_t wbase, spiv_app, vest;
+    int nlog, gen;
+    int64_t vest;
     int fw, fwn;    // far list: buffer appended to, entries in it
-    int fr, nr;     // far list being pulled: buffer, entries
-    float kd, kdn;  // near bound, its next value
+    int fr, nr, pn; // far list being pulled: buffer, entries; entries pulled
+    float kd;       // near part = entries older than (kd, kidx)
+    int64_t kidx;
     int64_t len, f; // sorted base: length and front
     int64_t owner, qsplit, appv;
     u32 lo, bound;
@@ -229,13 +231,6 @@ struct RedShared {
     unsigned long long stat[13];
     unsigned long long tm[12]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner
     u32 hist[256];
-    // window of the sorted base from wbase (wn entries, valid while wgen ==
-    // gen) with the entries' pivot-table and apparent-pair lookups
-    int64_t win_idx[kWave];
-    float win_dia[kWave];
-    u32 win_coef[kWave];
-    int win_own[kWave];
-    int64_t win_app[kWave];
     // simplices whose coboundaries are added next: vertices, coefficient,
     // diameter, candidate source (vertex with the fewest neighbours, -1 =
     // all vertices) and prefix offsets of their candidate counts
@@ -343,11 +338,27 @@ __device__ __forceinline__ PivotCand wc_oldest(const WorkCol &R, u32 p, RedShare
     return S.piv;
 }
 
-// Append an entry to the far list (any thread). False when it is full.
+// Is (dm, key) in the near part, i.e. older than the boundary (kd, kidx)?
 template <int BT>
-__device__ __forceinline__ bool far_append(const FarList &F, RedShared<BT> &S, int64_t key,
-                                           float dm, u32 c) {
-    const int pos = atomicAdd(&S.fwn, 1);
+__device__ __forceinline__ bool is_near(const RedShared<BT> &S, float dm, int64_t key) {
+    return older_key(dm, key, S.kd, S.kidx);
+}
+
+// Append the lanes' entries with pred to the far list, one atomic per wave.
+// Every lane of the wave must call it. Returns false on the lanes whose
+// entry did not fit.
+template <int BT>
+__device__ __forceinline__ bool far_append_w(const FarList &F, RedShared<BT> &S, bool pred,
+                                             int64_t key, float dm, u32 c) {
+    const u64 m = __ballot(pred);
+    if (!m) return true;
+    const int lane = lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&S.fwn, __popcll(m));
+    base = __shfl(base, leader, kWave);
+    if (!pred) return true;
+    const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
     if ((int64_t)pos >= F.cap) return false;
     const int b = S.fw;
     pick(F.idx, b)[pos] = key;
@@ -356,13 +367,16 @@ __device__ __forceinline__ bool far_append(const FarList &F, RedShared<BT> &S, i
     return true;
 }
 
-// Add an entry of the working column: near -> delta, far -> far list.
-// Returns 0 or a result code.
+// Add the lanes' entries (act) to the working column: near -> delta, far ->
+// far list. Every lane of the wave must call it. Returns 0 or a result code.
 template <int BT>
-__device__ __forceinline__ int add_entry(const WorkCol &D, const FarList &F, RedShared<BT> &S,
-                                         int64_t key, float dm, u32 c, u32 p) {
-    if (dm <= S.kd) return wc_add(D, key, dm, c, p) ? kRedOk : kRedBaseFull;
-    return far_append<BT>(F, S, key, dm, c) ? kRedOk : kRedFarFull;
+__device__ __forceinline__ int add_entry_w(const WorkCol &D, const FarList &F, RedShared<BT> &S,
+                                           bool act, int64_t key, float dm, u32 c, u32 p) {
+    const bool near = act && is_near(S, dm, key);
+    int r = kRedOk;
+    if (near && !wc_add(D, key, dm, c, p)) r = kRedBaseFull;
+    if (!far_append_w<BT>(F, S, act && !near, key, dm, c)) r = kRedFarFull;
+    return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -371,15 +385,11 @@ __device__ __forceinline__ int add_entry(const WorkCol &D, const FarList &F, Red
 
 // Wave 0 moves the front of S past entries whose total coefficient (S + D)
 // is zero; the delta's copies of those keys are zeroed, since their part of
-// the sum is spent. S.spiv = the first live entry with its total, if any,
-// and S.spiv_own / S.spiv_app its pivot-table owner and apparent partner.
-// The base is read through a window of 64 entries kept in LDS; a window is
-// loaded with the table lookups of all its entries at once (owners do not
-// change while one column is reduced), so a pivot found in the base costs no
-// further global round trip.
+// the sum is spent. S.spiv = the first live entry with its total, if any.
 template <int BT, class Dist>
-__device__ __forceinline__ void base_advance(const ReduceJob<Dist> &J, const WorkCol &D, const SortedBase &SB,
-                             u32 p, RedShared<BT> &S) {
+__device__ __forceinline__ void base_advance(const ReduceJob<Dist> &J, const WorkCol &D,
+                                             const SortedBase &SB, u32 p, RedShared<BT> &S) {
+    (void)J;
     if (threadIdx.x >= kWave) return;
     const int lane = lane_id();
     int64_t f = S.f;
@@ -388,71 +398,36 @@ __device__ __forceinline__ void base_advance(const ReduceJob<Dist> &J, const Wor
     out.idx = kEmpty;
     out.diam = 0.0f;
     out.coef = 0;
-    int own = -1;
-    int64_t app = -1;
-    bool wvalid = S.wgen == S.gen;
-    int64_t wbase = S.wbase;
-    int wn = S.wn;
-    bool reloaded = false;
     while (f < len) {
-        if (!wvalid || f < wbase || f >= wbase + wn) {
-            wbase = f;
-            wn = (int)min<int64_t>(kWave, len - f);
-            int64_t id = kEmpty;
-            float dm = 0.0f;
-            u32 cs = 0;
-            int ow = -1;
-            int64_t ap = -1;
-            if (lane < wn) {
-                id = SB.idx[f + lane];
-                dm = SB.dia[f + lane];
-                cs = SB.coef[f + lane] % p;
-                ow = ph_find(J.ph, id);
-                ap = J.app.keys ? pair_find(J.app, id) : -1;
-            }
-            S.win_idx[lane] = id;
-            S.win_dia[lane] = dm;
-            S.win_coef[lane] = cs;
-            S.win_own[lane] = ow;
-            S.win_app[lane] = ap;
-            wvalid = true;
-            reloaded = true;
-        }
-        const int l0 = (int)(f - wbase);
-        const bool valid = lane >= l0 && lane < wn;
-        const int64_t id = S.win_idx[lane];
+        const int64_t q = f + lane;
+        const bool valid = q < len;
         u32 total = 0;
         int slot = -1;
+        int64_t id = 0;
+        float dm = 0.0f;
         if (valid) {
+            id = SB.idx[q];
+            dm = SB.dia[q];
             slot = wc_find(D, id);
             const u32 cd = slot >= 0 ? ld(&D.coef[slot]) % p : 0u;
-            total = (S.win_coef[lane] + cd) % p;
+            total = (SB.coef[q] + cd) % p;
         }
         const u64 live = __ballot(valid && total != 0);
         const int first = live ? __ffsll((unsigned long long)live) - 1 : kWave;
         if (valid && lane < first && slot >= 0) st(&D.coef[slot], 0u);
         if (live) {
             out.idx = __shfl(id, first, kWave);
-            out.diam = __shfl(S.win_dia[lane], first, kWave);
+            out.diam = __shfl(dm, first, kWave);
             out.coef = __shfl(total, first, kWave);
-            own = __shfl(S.win_own[lane], first, kWave);
-            app = __shfl(S.win_app[lane], first, kWave);
-            f = wbase + first;
+            f += first;
             break;
         }
-        f = wbase + wn;
+        f += kWave;
     }
     if (f > len) f = len;
     if (lane == 0) {
         S.f = f;
         S.spiv = out;
-        S.spiv_own = own;
-        S.spiv_app = app;
-        if (reloaded) {
-            S.wbase = wbase;
-            S.wn = wn;
-            S.wgen = S.gen;
-        }
     }
 }
 
@@ -588,31 +563,22 @@ __device__ __forceinline__ int base_merge(const WorkCol &D, const Staging &G, co
 // of S and move the entries above it to the far list (D is empty here).
 template <int BT>
 __device__ __forceinline__ int base_split(const SortedBase &SB, const FarList &F, u32 p, int smax,
-                          RedShared<BT> &S) {
+                                          RedShared<BT> &S) {
     const int tid = threadIdx.x;
     if (S.len - S.f <= smax) return kRedOk;
     RED_T0(t_spl);
-    if (tid == 0) {
-        const int64_t q0 = S.f + smax / 2;
-        const float kd = SB.dia[q0];
-        int64_t lo = q0, hi = S.len; // first entry with a larger diameter
-        while (lo < hi) {
-            const int64_t mid = (lo + hi) >> 1;
-            if (SB.dia[mid] > kd) hi = mid;
-            else lo = mid + 1;
-        }
-        S.qsplit = lo;
-        S.kdn = kd;
-    }
-    __syncthreads();
-    const int64_t q = S.qsplit, len = S.len;
-    const float kd = S.kdn;
-    __syncthreads();
-    if (q >= len) return kRedOk; // one diameter from the middle on: keep it all
+    // the entry in the middle becomes the boundary: it and everything
+    // younger move to the far list (the key includes the index, so blocks of
+    // equal diameters split too)
+    const int q = (int)S.f + smax / 2, len = (int)S.len;
+    const float kd = SB.dia[q];
+    const int64_t kidx = SB.idx[q];
     bool ok = true;
-    for (int64_t r = q + tid; r < len; r += BT) {
-        const u32 cf = SB.coef[r] % p;
-        if (cf != 0) ok = ok && far_append<BT>(F, S, SB.idx[r], SB.dia[r], cf);
+    for (int b0 = q; b0 < len; b0 += BT) {
+        const int r = b0 + tid;
+        const bool act = r < len;
+        const u32 cf = act ? SB.coef[r] % p : 0u;
+        ok = far_append_w<BT>(F, S, cf != 0, act ? SB.idx[r] : 0, act ? SB.dia[r] : 0.0f, cf) && ok;
     }
     if (!ok) S.abort = kRedFarFull;
     gsync();
@@ -620,6 +586,7 @@ __device__ __forceinline__ int base_split(const SortedBase &SB, const FarList &F
     if (tid == 0) {
         S.len = q;
         S.kd = kd;
+        S.kidx = kidx;
         S.merged = 1;
         S.gen += 1;
         S.stat[10] += 1;
@@ -684,15 +651,17 @@ __device__ __forceinline__ int delta_check(const WorkCol &D, const Staging &G,
     return base_split<BT>(SC.SB, SC.F, p, capD, S);
 }
 
-// The near part is empty and the far list is not: raise kd so that about
-// `target` far entries fall under it (a diameter histogram over the bits
-// of the non-negative float diameters, refined while one bin is far too
-// full), and move those entries into the delta.
+// The near part is empty and the far list is not: raise the boundary to a
+// diameter d such that about `target` far entries have diameter <= d, and
+// move those into the delta. d comes from a histogram of the diameters' bit
+// patterns (non-negative floats order like their bits) over [kd, tmax],
+// refined while the chosen bin holds far more than the target.
 template <int BT>
-__device__ __forceinline__ int far_pull(const WorkCol &D, const Staging &G, const ReduceScratch &SC, u32 p,
-                        int target, RedShared<BT> &S) {
+__device__ __forceinline__ int far_pull(const WorkCol &D, const Staging &G,
+                                        const ReduceScratch &SC, u32 p, int target, float tmax,
+                                        RedShared<BT> &S) {
     const FarList &F = SC.F;
-    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const int tid = threadIdx.x;
     RED_T0(t_pull);
     if (tid == 0) {
         S.fr = S.fw;
@@ -702,51 +671,42 @@ __device__ __forceinline__ int far_pull(const WorkCol &D, const Staging &G, cons
         S.merged = 1;
         S.stat[8] += 1;
         S.stat[11] += S.nr;
-    }
-    __syncthreads();
-    const int fr = S.fr, nr = S.nr;
-    // 1. smallest and largest diameter bits
-    u32 mn = 0xffffffffu, mx = 0;
-    for (int r = tid; r < nr; r += BT) {
-        const u32 b = __float_as_uint(pick(F.dia, fr)[r]);
-        mn = min(mn, b);
-        mx = max(mx, b);
-    }
-    for (int o = 32; o >= 1; o >>= 1) {
-        mn = min(mn, (u32)__shfl_xor((int)mn, o, kWave));
-        mx = max(mx, (u32)__shfl_xor((int)mx, o, kWave));
-    }
-    if (lane == 0) {
-        S.mm[0][w] = mn;
-        S.mm[1][w] = mx;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        u32 a = S.mm[0][0], b = S.mm[1][0];
-        for (int q = 1; q < BT / kWave; ++q) {
-            a = min(a, S.mm[0][q]);
-            b = max(b, S.mm[1][q]);
-        }
-        const u32 span = b - a;
+        const u32 lo = __float_as_uint(S.kd);
+        const u32 hi = max(lo, __float_as_uint(tmax));
+        const u32 span = hi - lo;
         const int nb = span ? 32 - __clz(span) : 0;
-        S.lo = a;
+        S.lo = lo;
         S.shift = nb > 8 ? nb - 8 : 0;
-        S.bound = b;
+        S.bound = hi;
         S.refine = 1;
     }
     __syncthreads();
-    // 2. pick the bound: bins of 2^shift bit patterns from lo
+    const int fr = S.fr, nr = S.nr;
+    // the new buffer holds the kept entries at the bottom and the pulled ones
+    // at the top; a segment's worth of slack keeps the entries sent back
+    // while a segment is being read below the part not read yet
+    if ((int64_t)nr + ((int)D.mask + 1) / 8 > F.cap) return kRedFarFull;
     int below = 0; // entries under S.lo (all pulled)
     while (S.refine) {
         for (int i = tid; i < 256; i += BT) S.hist[i] = 0;
         __syncthreads();
         const u32 lo = S.lo;
         const int sh = S.shift;
-        for (int r = tid; r < nr; r += BT) {
-            const u32 b = __float_as_uint(pick(F.dia, fr)[r]);
-            if (b < lo) continue;
-            const u32 bin = (b - lo) >> sh;
-            if (bin < 256) atomicAdd(&S.hist[bin], 1u);
+        const float *fd = pick(F.dia, fr);
+        // kPullUnroll independent loads in flight per thread
+        for (int b0 = 0; b0 < nr; b0 += kPullUnroll * BT) {
+            u32 bb[kPullUnroll];
+#pragma unroll
+            for (int u = 0; u < kPullUnroll; ++u) {
+                const int r = b0 + u * BT + tid;
+                bb[u] = r < nr ? __float_as_uint(fd[r]) : 0xffffffffu;
+            }
+#pragma unroll
+            for (int u = 0; u < kPullUnroll; ++u) {
+                if (bb[u] == 0xffffffffu || bb[u] < lo) continue;
+                const u32 bin = (bb[u] - lo) >> sh;
+                atomicAdd(&S.hist[bin < 256 ? bin : 255], 1u);
+            }
         }
         __syncthreads();
         if (tid == 0) {
@@ -763,8 +723,12 @@ __device__ __forceinline__ int far_pull(const WorkCol &D, const Staging &G, cons
                 S.shift = sh > 8 ? sh - 8 : 0;
                 S.nr = before; // reuse as the running count below lo
             } else {
-                const u64 top = (u64)lo + ((u64)(i + 1) << sh) - 1;
-                S.bound = top > 0xffffffffull ? 0xffffffffu : (u32)top;
+                // the last bin takes everything: +inf, whose bits bound every
+                // finite diameter (a larger pattern would be a NaN boundary,
+                // which nothing is older than)
+                const u64 inf_bits = 0x7f800000ull;
+                const u64 top = i == 255 ? inf_bits : (u64)lo + ((u64)(i + 1) << sh) - 1;
+                S.bound = (u32)(top > inf_bits ? inf_bits : top);
                 S.refine = 0;
             }
         }
@@ -773,18 +737,75 @@ __device__ __forceinline__ int far_pull(const WorkCol &D, const Staging &G, cons
         __syncthreads();
     }
     if (tid == 0) {
+        // new boundary (d, -1): every entry of diameter <= d is near
         S.kd = __uint_as_float(S.bound);
+        S.kidx = -1;
         S.nr = nr;
+        S.pn = 0;
     }
     __syncthreads();
     RED_T1(S, 3, t_pull);
-    // 3. move the entries under the bound into D, keep the rest, in segments
+    // partition without barriers: entries under the bound go to the top of
+    // the new buffer (slot cap - 1 - i for the i-th), the rest to its bottom
+    const u32 bound = S.bound;
+    const int nb = S.fw;
+    bool ok = true;
+    const int64_t *fi = pick(F.idx, fr);
+    const float *fd = pick(F.dia, fr);
+    const u32 *fc = pick(F.coef, fr);
+    for (int b0 = 0; b0 < nr; b0 += kPullUnroll * BT) {
+        int64_t ids[kPullUnroll];
+        float dms[kPullUnroll];
+        u32 cfs[kPullUnroll];
+#pragma unroll
+        for (int u = 0; u < kPullUnroll; ++u) {
+            const int r = b0 + u * BT + tid;
+            const bool act = r < nr;
+            ids[u] = act ? fi[r] : 0;
+            dms[u] = act ? fd[r] : 0.0f;
+            cfs[u] = act ? fc[r] : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kPullUnroll; ++u) {
+            const int r = b0 + u * BT + tid;
+            const bool act = r < nr;
+            const bool pull = act && __float_as_uint(dms[u]) <= bound;
+            ok = far_append_w<BT>(F, S, act && !pull, ids[u], dms[u], cfs[u]) && ok;
+            const u64 m = __ballot(pull);
+            if (m) {
+                const int lane = lane_id();
+                const int leader = __ffsll((unsigned long long)m) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(&S.pn, __popcll(m));
+                base = __shfl(base, leader, kWave);
+                if (pull) {
+                    const int64_t pos = F.cap - 1 - (base + __popcll(m & ((1ull << lane) - 1ull)));
+                    pick(F.idx, nb)[pos] = ids[u];
+                    pick(F.dia, nb)[pos] = dms[u];
+                    pick(F.coef, nb)[pos] = cfs[u];
+                }
+            }
+        }
+    }
+    if (!ok) S.abort = kRedFarFull;
+    gsync();
+    if (S.abort) return S.abort;
+    // the pulled entries into D, in segments, read upwards from the lowest
+    // slot: whatever a split sends back to the bottom of the buffer stays
+    // below the part not read yet (both come out of the same nr entries)
+    const int pn = S.pn;
+    const int64_t pbase = F.cap - pn;
     const int seg = ((int)D.mask + 1) / 8;
-    for (int s0 = 0; s0 < nr; s0 += seg) {
-        const int s1 = min(nr, s0 + seg);
+    for (int s0 = 0; s0 < pn; s0 += seg) {
+        const int s1 = min(pn, s0 + seg);
         int bad = 0;
-        for (int r = s0 + tid; r < s1; r += BT) {
-            const int rr = add_entry<BT>(D, F, S, pick(F.idx, fr)[r], pick(F.dia, fr)[r], pick(F.coef, fr)[r], p);
+        for (int b0 = s0; b0 < s1; b0 += BT) {
+            const int e = b0 + tid;
+            const bool act = e < s1;
+            const int64_t pos = pbase + e;
+            const int rr = add_entry_w<BT>(D, F, S, act, act ? pick(F.idx, nb)[pos] : 0,
+                                           act ? pick(F.dia, nb)[pos] : 0.0f,
+                                           act ? pick(F.coef, nb)[pos] : 0u, p);
             if (rr) bad = rr;
         }
         if (bad) S.abort = bad;
@@ -793,6 +814,10 @@ __device__ __forceinline__ int far_pull(const WorkCol &D, const Staging &G, cons
         const int r = delta_check<BT>(D, G, SC, p, S);
         if (r) return r;
     }
+    // every entry of the smallest diameter in the list is under the bound,
+    // so the near part cannot be empty now; if it were, the caller would
+    // pull forever: report it instead
+    if (*D.nslots == 0 && S.len == S.f) return kRedBound;
     return kRedOk;
 }
 
@@ -844,32 +869,41 @@ __device__ __forceinline__ int add_items(const ReduceJob<Dist> &J, RedShared<BT>
         const int s1 = min(total, s0 + seg);
         int bad = 0;
         unsigned long long added = 0;
-        for (int fl = s0 + tid; fl < s1; fl += BT) {
-            int lo = 0, hi = nit - 1; // last item with it_off <= fl
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (S.it_off[mid] <= fl) lo = mid;
-                else hi = mid - 1;
+        for (int b0 = s0; b0 < s1; b0 += BT) {
+            const int fl = b0 + tid;
+            bool act = fl < s1;
+            int64_t ci = 0;
+            float nd = 0.0f;
+            u32 cc = 0;
+            if (act) {
+                int lo = 0, hi = nit - 1; // last item with it_off <= fl
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (S.it_off[mid] <= fl) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int it = lo;
+                const int q = fl - S.it_off[it];
+                const int u = S.it_u[it];
+                const int j = u < 0 ? q : c.nb.idx[c.nb.off[u] + q];
+                const int *v = S.it_v[it];
+                bool in = false;
+                nd = S.it_diam[it];
+                for (int m = 0; m <= k; ++m) {
+                    in = in || (j == v[m]);
+                    nd = fmaxf(nd, c.d(v[m], j));
+                }
+                act = !in && nd <= c.t;
+                if (act) {
+                    int below;
+                    ci = cofacet_index(v, k, j, c.B, &below);
+                    const u32 coef = S.it_coef[it];
+                    cc = (below & 1) ? (p - coef) % p : coef;
+                    ++added;
+                }
             }
-            const int it = lo;
-            const int q = fl - S.it_off[it];
-            const int u = S.it_u[it];
-            const int j = u < 0 ? q : c.nb.idx[c.nb.off[u] + q];
-            const int *v = S.it_v[it];
-            bool in = false;
-            float nd = S.it_diam[it];
-            for (int m = 0; m <= k; ++m) {
-                in = in || (j == v[m]);
-                nd = fmaxf(nd, c.d(v[m], j));
-            }
-            if (in || !(nd <= c.t)) continue;
-            int below;
-            const int64_t ci = cofacet_index(v, k, j, c.B, &below);
-            const u32 coef = S.it_coef[it];
-            const u32 cc = (below & 1) ? (p - coef) % p : coef;
-            const int rr = add_entry<BT>(D, SC.F, S, ci, nd, cc, p);
+            const int rr = add_entry_w<BT>(D, SC.F, S, act, ci, nd, cc, p);
             if (rr) bad = rr;
-            ++added;
         }
         if (added) atomicAdd(&S.stat[12], added);
         if (bad) S.abort = bad;
@@ -915,9 +949,12 @@ __device__ __forceinline__ int add_rcolumn(const ReduceJob<Dist> &J, RedShared<B
     for (int s0 = 0; s0 < len; s0 += seg) {
         const int s1 = min(len, s0 + seg);
         int bad = 0;
-        for (int e = s0 + threadIdx.x; e < s1; e += BT) {
-            const u32 cc = (u32)((u64)neg * J.V.coef[off + e] % p);
-            const int rr = add_entry<BT>(D, SC.F, S, J.V.idx[off + e], J.V.diam[off + e], cc, p);
+        for (int b0 = s0; b0 < s1; b0 += BT) {
+            const int e = b0 + threadIdx.x;
+            const bool act = e < s1;
+            const u32 cc = act ? (u32)((u64)neg * J.V.coef[off + e] % p) : 0u;
+            const int rr = add_entry_w<BT>(D, SC.F, S, act, act ? J.V.idx[off + e] : 0,
+                                           act ? J.V.diam[off + e] : 0.0f, cc, p);
             if (rr) bad = rr;
         }
         if (threadIdx.x == 0) S.stat[12] += (unsigned long long)(s1 - s0);
@@ -1077,11 +1114,11 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const WorkCo
         S.f = 0;
         S.merged = 0;
         S.kd = INFINITY;
+        S.kidx = -1;
         S.fw = 0;
         S.fwn = 0;
         S.nlog = 0;
         S.vest = 1;
-        S.gen += 1; // the base window of the previous column is stale
         S.nit = 1;
         S.it_coef[0] = 1u;
         S.it_diam[0] = sdm;
@@ -1111,7 +1148,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const WorkCo
                         (dmin.idx == kEmpty || dmin.idx == smin.idx || !older(dmin, smin));
             piv = from_base ? smin : dmin;
             if (piv.idx != kEmpty || S.fwn == 0) break;
-            result = far_pull<BT>(D, G, SC, p, ((int)D.mask + 1) / 2, S);
+            result = far_pull<BT>(D, G, SC, p, ((int)D.mask + 1) / 2, c.t, S);
             if (result) break;
         }
         RED_T1(S, 0, t_piv);
@@ -1131,17 +1168,9 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const WorkCo
             break;
         }
         RED_T0(t_own);
-        if (from_base) {
-            // looked up with the base window
-            if (tid == 0) {
-                S.owner = S.spiv_own;
-                S.appv = S.spiv_app;
-            }
-        } else {
-            // pivot table and apparent-pair table, read by two waves at once
-            if (tid == 0) S.owner = ph_find(J.ph, piv.idx);
-            if (tid == kWave) S.appv = J.app.keys ? pair_find(J.app, piv.idx) : -1;
-        }
+        // pivot table and apparent-pair table, read by two waves at once
+        if (tid == 0) S.owner = ph_find(J.ph, piv.idx);
+        if (tid == kWave) S.appv = J.app.keys ? pair_find(J.app, piv.idx) : -1;
         __syncthreads();
         RED_T1(S, 11, t_own);
         const int64_t o = S.owner;
@@ -1330,9 +1359,6 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Wo
         S.len = 0;
         S.f = 0;
         S.gen = 0;
-        S.wgen = -1;
-        S.wbase = 0;
-        S.wn = 0;
     }
     if (tid < 13) S.stat[tid] = 0;
     if (tid < 12) S.tm[tid] = 0;
