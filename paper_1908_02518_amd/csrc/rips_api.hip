@@ -752,36 +752,34 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             HIP_TRY(C.ensure(B_V_COEF, (size_t)vcap * 4, &q));
             V.coef = as<u32>(q);
             V.cap = vcap;
-            ReduceScratch SC;
-            SC.SB = SortedBase{nullptr, nullptr, nullptr, 0}; // carved in LDS by the kernel
+            ReduceBuffers RB;
             for (int b = 0; b < 2; ++b) {
                 HIP_TRY(C.ensure(B_F_IDX0 + b, (size_t)fcap * 8, &q));
-                SC.F.idx[b] = as<int64_t>(q);
+                RB.F.idx[b] = as<int64_t>(q);
                 HIP_TRY(C.ensure(B_F_DIA0 + b, (size_t)fcap * 4, &q));
-                SC.F.dia[b] = as<float>(q);
+                RB.F.dia[b] = as<float>(q);
                 HIP_TRY(C.ensure(B_F_COEF0 + b, (size_t)fcap * 4, &q));
-                SC.F.coef[b] = as<u32>(q);
+                RB.F.coef[b] = as<u32>(q);
             }
-            SC.F.cap = fcap;
+            RB.F.cap = fcap;
             HIP_TRY(C.ensure(B_VW_KEYS, (size_t)vwcap * 8, &q));
-            SC.Vw.keys = as<int64_t>(q);
+            RB.vw_keys = as<int64_t>(q);
             HIP_TRY(C.ensure(B_VW_COEF, (size_t)vwcap * 4, &q));
-            SC.Vw.coef = as<u32>(q);
+            RB.vw_coef = as<u32>(q);
             HIP_TRY(C.ensure(B_VW_DIAM, (size_t)vwcap * 4, &q));
-            SC.Vw.diam = as<float>(q);
+            RB.vw_diam = as<float>(q);
             HIP_TRY(C.ensure(B_VW_SLOTS, (size_t)vwcap * 4, &q));
-            SC.Vw.slots = as<u32>(q);
-            SC.Vw.nslots = nullptr; // set by the kernel (LDS)
-            SC.Vw.mask = (u32)vwcap - 1;
+            RB.vw_slots = as<u32>(q);
+            RB.vw_cap = vwcap;
             // one entry per addition: the addition bound (2^18) never overflows it
             const int64_t lcap = (1 << 18) + 64;
             HIP_TRY(C.ensure(B_LOG_KEY, (size_t)lcap * 8, &q));
-            SC.lkey = as<int64_t>(q);
+            RB.lkey = as<int64_t>(q);
             HIP_TRY(C.ensure(B_LOG_COEF, (size_t)lcap * 4, &q));
-            SC.lcoef = as<u32>(q);
+            RB.lcoef = as<u32>(q);
             HIP_TRY(C.ensure(B_LOG_DIA, (size_t)lcap * 4, &q));
-            SC.ldia = as<float>(q);
-            SC.lcap = lcap;
+            RB.ldia = as<float>(q);
+            RB.lcap = lcap;
             launch_fill_i64(ph.keys, phcap, kEmpty, st);
             launch_reset_dim(P.scal, st);
             ReduceJob<DistFull> J;
@@ -800,7 +798,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
                                   : (float)n;
             {
                 PROF(P_REDUCE1 + k - 1);
-                HIP_TRY(launch_reduce(J, capD, SC, P.scal, st));
+                HIP_TRY(launch_reduce(J, capD, RB, P.scal, st));
             }
             if ((rs = read_scalars(C, P.scal, st))) return rs;
             const int status = C.host_scal->status;

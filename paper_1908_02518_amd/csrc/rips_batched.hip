@@ -436,10 +436,10 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         J.vcount = &A.v_count[wg];
         J.bars = BarBuf{sb_b + n, sb_d + n, sb_bs + n, sb_ds + n};
         __shared__ int s_nsl;
-        WorkCol Dw;
+        LdsCol Dw;
         Staging Gs;
         ReduceScratch SC;
-        carve_reduce_lds(smem, A.capD, &s_nsl, &Dw, &Gs, &SC.SB);
+        carve_reduce_lds(smem, A.capD, (LDS int *)&s_nsl, &Dw, &Gs, &SC.SB);
         for (int h = 0; h < 2; ++h) {
             SC.F.idx[h] = A.f_idx[h] + (int64_t)wg * A.f_stride;
             SC.F.dia[h] = A.f_dia[h] + (int64_t)wg * A.f_stride;
@@ -450,7 +450,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         SC.Vw.coef = A.vw_coef + (int64_t)wg * A.vw_stride;
         SC.Vw.diam = A.vw_diam + (int64_t)wg * A.vw_stride;
         SC.Vw.slots = A.vw_slots + (int64_t)wg * A.vw_stride;
-        SC.Vw.nslots = &RS.vns;
+        SC.Vw.nslots = (LDS int *)&RS.vns;
         SC.Vw.mask = (u32)A.vw_stride - 1;
         SC.lkey = A.log_key + (int64_t)wg * A.log_stride;
         SC.lcoef = A.log_coef + (int64_t)wg * A.log_stride;

@@ -236,11 +236,26 @@ __device__ __forceinline__ void st(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Pointers into LDS carry the local address space, so that accesses compile
+// to ds_* instructions rather than flat ones (a flat access also waits for
+// every outstanding global load of the wave).
+#define LDS __attribute__((address_space(3)))
+
+template <class T>
+__device__ __forceinline__ T ld(const LDS T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <class T>
+__device__ __forceinline__ void st(LDS T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <int G>
 __device__ __forceinline__ u64 group_mask() {
-    if (G == 64) return ~0ull;
+    if (G >= 64) return ~0ull;
     const int base = lane_id() & ~(G - 1);
-    return ((1ull << G) - 1) << base;
+    return ((1ull << (G & 63)) - 1) << base;
 }
 
 // Largest candidate vertex j > jmin, j not in v[0..k], with d(j, v_m) <= bound

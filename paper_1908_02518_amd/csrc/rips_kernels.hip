@@ -693,14 +693,15 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_columns(Columns in, Scala
 // ---------------------------------------------------------------------------
 template <class Dist>
 __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 capD,
-                                                       ReduceScratch SC, Scalars *s) {
+                                                       ReduceBuffers RB, Scalars *s) {
     extern __shared__ unsigned char smem[];
     __shared__ RedShared<kRedThreads> S;
     __shared__ int s_ns;
-    WorkCol D;
+    LdsCol D;
     Staging G;
-    carve_reduce_lds(smem, capD, &s_ns, &D, &G, &SC.SB);
-    SC.Vw.nslots = &S.vns;
+    SortedBase SB;
+    carve_reduce_lds(smem, capD, (LDS int *)&s_ns, &D, &G, &SB);
+    const ReduceScratch SC = make_scratch(RB, SB, (LDS int *)&S.vns);
     const int status = reduce_columns<kRedThreads>(J, D, G, SC, S);
     if (threadIdx.x == 0) {
         s->status = status;
@@ -928,13 +929,13 @@ void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Colu
                        out);
 }
 
-hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceScratch SC, Scalars *s,
+hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceBuffers RB, Scalars *s,
                          hipStream_t st) {
     const size_t lds = reduce_lds_bytes(capD);
     hipError_t e = hipFuncSetAttribute((const void *)k_reduce<DistFull>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_reduce<DistFull>), dim3(1), dim3(kRedThreads), lds, st, J, capD, SC, s);
+    hipLaunchKernelGGL((k_reduce<DistFull>), dim3(1), dim3(kRedThreads), lds, st, J, capD, RB, s);
     return hipGetLastError();
 }
 

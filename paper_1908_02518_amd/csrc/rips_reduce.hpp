@@ -36,22 +36,36 @@
 
 namespace rips {
 
+// Open-addressing table keyed by simplex index, with the list of its used
+// slots (so that scans, clearing and compaction cost O(entries touched)).
+// Coefficients accumulate with atomics and are reduced mod p when read (XOR
+// for p = 2). WorkCol lives in global memory (the V table), LdsCol in LDS
+// (the delta); the routines below are templates over both.
 struct WorkCol {
     int64_t *keys;
     u32 *coef;
     float *diam;
     u32 *slots;
-    int *nslots; // in LDS
+    LDS int *nslots;
+    u32 mask;
+};
+
+struct LdsCol {
+    LDS int64_t *keys;
+    LDS u32 *coef;
+    LDS float *diam;
+    LDS u32 *slots;
+    LDS int *nslots;
     u32 mask;
 };
 
 // Merge staging in LDS (capacity = a quarter of the delta's slots).
 struct Staging {
-    int64_t *idx;
-    float *dia;
-    u32 *coef;
-    u32 *cnt; // cap + 1
-    int *nd;  // cap + 1
+    LDS int64_t *idx;
+    LDS float *dia;
+    LDS u32 *coef;
+    LDS u32 *cnt; // cap + 1
+    LDS int *nd;  // cap + 1
     int cap;
 };
 
@@ -59,15 +73,15 @@ struct Staging {
 // the live part in registers (at most kSPer entries per thread) and writes
 // the result back in place.
 struct SortedBase {
-    int64_t *idx;
-    float *dia;
-    u32 *coef;
+    LDS int64_t *idx;
+    LDS float *dia;
+    LDS u32 *coef;
     int cap;
 };
 
 constexpr int kSPer = 10;        // base entries per thread during a merge
-constexpr int kPullUnroll = 8;   // far-list entries in flight per thread in a pull
 constexpr u32 kMaxDelta = 2048;  // largest delta: its base (1.25x) fits kSPer x 256 threads
+constexpr int kPullUnroll = 8;   // far-list entries in flight per thread in a pull
 
 // Far list in global memory, two buffers of cap entries each.
 struct FarList {
@@ -77,13 +91,17 @@ struct FarList {
     int64_t cap;
 };
 
-// Scratch of one workgroup's reduction: the sorted base (LDS, carved by the
-// kernel), the far list, the working V column (a global table used when V_j
-// is too large for LDS; its slot count lives in LDS) and the addition log.
-struct ReduceScratch {
-    SortedBase SB;
+// Global scratch of one workgroup's reduction as the host allocates it and
+// passes it to the kernel. It holds no LDS pointer: those are 32 bits wide on
+// the device and 64 on the host, so a kernel argument holding one would be
+// laid out differently on the two sides.
+struct ReduceBuffers {
     FarList F;
-    WorkCol Vw;
+    int64_t *vw_keys; // working V column (table used when V_j is too large for LDS)
+    u32 *vw_coef;
+    float *vw_diam;
+    u32 *vw_slots;
+    int64_t vw_cap;   // power of two
     // log of one column's additions: key -2 - o = "V_o of column o", key >= 0
     // = "the simplex with that index"; coefficient; diameter (simplices)
     int64_t *lkey;
@@ -91,6 +109,31 @@ struct ReduceScratch {
     float *ldia;
     int64_t lcap;
 };
+
+// The device view of a workgroup's scratch: the sorted base (LDS), the far
+// list, the working V column (its slot count in LDS) and the addition log.
+struct ReduceScratch {
+    SortedBase SB;
+    FarList F;
+    WorkCol Vw;
+    int64_t *lkey;
+    u32 *lcoef;
+    float *ldia;
+    int64_t lcap;
+};
+
+__device__ __forceinline__ ReduceScratch make_scratch(const ReduceBuffers &b, SortedBase sb,
+                                                      LDS int *vw_nslots) {
+    ReduceScratch sc;
+    sc.SB = sb;
+    sc.F = b.F;
+    sc.Vw = WorkCol{b.vw_keys, b.vw_coef, b.vw_diam, b.vw_slots, vw_nslots, (u32)b.vw_cap - 1};
+    sc.lkey = b.lkey;
+    sc.lcoef = b.lcoef;
+    sc.ldia = b.ldia;
+    sc.lcap = b.lcap;
+    return sc;
+}
 
 // Result codes of the reduction.
 enum : int {
@@ -112,55 +155,64 @@ __host__ __device__ constexpr size_t reduce_lds_bytes(u32 capD) {
 
 // Carve the delta, its staging and the sorted base out of an LDS block
 // (capD a power of two, 256 <= capD <= kMaxDelta).
-__device__ __forceinline__ void carve_reduce_lds(unsigned char *q, u32 capD, int *nslots,
-                                                 WorkCol *D, Staging *G, SortedBase *SB) {
+__device__ __forceinline__ void carve_reduce_lds(unsigned char *smem, u32 capD, LDS int *nslots,
+                                                 LdsCol *D, Staging *G, SortedBase *SB) {
+    LDS unsigned char *q = (LDS unsigned char *)smem;
     const size_t c = capD, m = capD / 4, sc = capD + capD / 4;
-    D->keys = (int64_t *)q;
+    D->keys = (LDS int64_t *)q;
     q += c * 8;
-    G->idx = (int64_t *)q;
+    G->idx = (LDS int64_t *)q;
     q += m * 8;
-    SB->idx = (int64_t *)q;
+    SB->idx = (LDS int64_t *)q;
     q += sc * 8;
-    D->coef = (u32 *)q;
+    D->coef = (LDS u32 *)q;
     q += c * 4;
-    D->diam = (float *)q;
+    D->diam = (LDS float *)q;
     q += c * 4;
-    D->slots = (u32 *)q;
+    D->slots = (LDS u32 *)q;
     q += c * 4;
-    G->dia = (float *)q;
+    G->dia = (LDS float *)q;
     q += m * 4;
-    G->coef = (u32 *)q;
+    G->coef = (LDS u32 *)q;
     q += m * 4;
-    SB->dia = (float *)q;
+    SB->dia = (LDS float *)q;
     q += sc * 4;
-    SB->coef = (u32 *)q;
+    SB->coef = (LDS u32 *)q;
     q += sc * 4;
-    G->cnt = (u32 *)q;
+    G->cnt = (LDS u32 *)q;
     q += (m + 1) * 4;
-    G->nd = (int *)q;
+    G->nd = (LDS int *)q;
     G->cap = (int)m;
     SB->cap = (int)sc;
     D->nslots = nslots;
     D->mask = capD - 1;
 }
 
-__device__ __forceinline__ bool wc_add(const WorkCol &h, int64_t key, float dm, u32 c, u32 p) {
+template <class T>
+__device__ __forceinline__ bool wc_add(const T &h, int64_t key, float dm, u32 c, u32 p) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
         const int64_t cur = ld(&h.keys[s]);
         bool mine = cur == key;
         if (!mine && cur == kEmpty) {
-            const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
-            if (prev == (u64)kEmpty) {
+            int64_t expected = kEmpty;
+            if (__hip_atomic_compare_exchange_strong(&h.keys[s], &expected, key, __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP)) {
                 h.diam[s] = dm;
-                const int q = atomicAdd(h.nslots, 1);
+                const int q = __hip_atomic_fetch_add(h.nslots, 1, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_WORKGROUP);
                 if ((u32)q <= h.mask) h.slots[q] = s;
                 mine = true;
-            } else mine = prev == (u64)key;
+            } else mine = expected == key;
         }
         if (mine) {
-            if (p == 2) atomicXor(&h.coef[s], c & 1u);
-            else atomicAdd(&h.coef[s], c);
+            if (p == 2)
+                __hip_atomic_fetch_xor(&h.coef[s], c & 1u, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            else
+                __hip_atomic_fetch_add(&h.coef[s], c, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             return true;
         }
         s = (s + 1) & h.mask;
@@ -169,7 +221,8 @@ __device__ __forceinline__ bool wc_add(const WorkCol &h, int64_t key, float dm, 
 }
 
 // slot holding key, or -1
-__device__ __forceinline__ int wc_find(const WorkCol &h, int64_t key) {
+template <class T>
+__device__ __forceinline__ int wc_find(const T &h, int64_t key) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
         const int64_t cur = ld(&h.keys[s]);
@@ -277,8 +330,8 @@ __device__ __forceinline__ int block_scan_excl(int x, int *s_w, int *total) {
 // ---------------------------------------------------------------------------
 // tables (all threads of the block)
 // ---------------------------------------------------------------------------
-template <int BT>
-__device__ __forceinline__ void wc_reset(const WorkCol &h) {
+template <int BT, class T>
+__device__ __forceinline__ void wc_reset(const T &h) {
     const int ns = min(*h.nslots, (int)h.mask + 1);
     for (int i = threadIdx.x; i < ns; i += BT) {
         const u32 s = h.slots[i];
@@ -290,8 +343,8 @@ __device__ __forceinline__ void wc_reset(const WorkCol &h) {
     __syncthreads();
 }
 
-template <int BT>
-__device__ __forceinline__ void wc_clear_all(const WorkCol &h) {
+template <int BT, class T>
+__device__ __forceinline__ void wc_clear_all(const T &h) {
     for (u32 q = threadIdx.x; q <= h.mask; q += BT) {
         st(&h.keys[q], kEmpty);
         st(&h.coef[q], 0u);
@@ -304,7 +357,7 @@ __device__ __forceinline__ void wc_clear_all(const WorkCol &h) {
 // Oldest live entry of the delta (block-wide). Coefficients are normalised
 // mod p on the way (no addition runs concurrently).
 template <int BT>
-__device__ __forceinline__ PivotCand wc_oldest(const WorkCol &R, u32 p, RedShared<BT> &S) {
+__device__ __forceinline__ PivotCand wc_oldest(const LdsCol &R, u32 p, RedShared<BT> &S) {
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
     PivotCand best;
     best.idx = kEmpty;
@@ -370,7 +423,7 @@ __device__ __forceinline__ bool far_append_w(const FarList &F, RedShared<BT> &S,
 // Add the lanes' entries (act) to the working column: near -> delta, far ->
 // far list. Every lane of the wave must call it. Returns 0 or a result code.
 template <int BT>
-__device__ __forceinline__ int add_entry_w(const WorkCol &D, const FarList &F, RedShared<BT> &S,
+__device__ __forceinline__ int add_entry_w(const LdsCol &D, const FarList &F, RedShared<BT> &S,
                                            bool act, int64_t key, float dm, u32 c, u32 p) {
     const bool near = act && is_near(S, dm, key);
     int r = kRedOk;
@@ -387,7 +440,7 @@ __device__ __forceinline__ int add_entry_w(const WorkCol &D, const FarList &F, R
 // is zero; the delta's copies of those keys are zeroed, since their part of
 // the sum is spent. S.spiv = the first live entry with its total, if any.
 template <int BT, class Dist>
-__device__ __forceinline__ void base_advance(const ReduceJob<Dist> &J, const WorkCol &D,
+__device__ __forceinline__ void base_advance(const ReduceJob<Dist> &J, const LdsCol &D,
                                              const SortedBase &SB, u32 p, RedShared<BT> &S) {
     (void)J;
     if (threadIdx.x >= kWave) return;
@@ -434,7 +487,7 @@ __device__ __forceinline__ void base_advance(const ReduceJob<Dist> &J, const Wor
 // Merge the live entries of D into S[f, len) (all threads); D is empty
 // afterwards and S starts at 0. Returns 0 or a result code.
 template <int BT>
-__device__ __forceinline__ int base_merge(const WorkCol &D, const Staging &G, const SortedBase &SB, u32 p,
+__device__ __forceinline__ int base_merge(const LdsCol &D, const Staging &G, const SortedBase &SB, u32 p,
                           RedShared<BT> &S) {
     static_assert(kSPer * BT >= (int)(kMaxDelta + kMaxDelta / 4), "base does not fit the staging");
     RED_T0(t_mrg);
@@ -459,9 +512,9 @@ __device__ __forceinline__ int base_merge(const WorkCol &D, const Staging &G, co
     }
     __syncthreads();
     // 2. sort by rank (keys are distinct): M = D's first m slots
-    int64_t *Mi = D.keys;
-    float *Md = D.diam;
-    u32 *Mc = D.coef;
+    LDS int64_t *Mi = D.keys;
+    LDS float *Md = D.diam;
+    LDS u32 *Mc = D.coef;
     for (int e = tid; e < m; e += BT) {
         const int64_t ie = G.idx[e];
         const float de = G.dia[e];
@@ -498,8 +551,10 @@ __device__ __forceinline__ int base_merge(const WorkCol &D, const Staging &G, co
                 else hi = mid;
             }
             rlo[i] = lo;
-            atomicAdd(&G.cnt[lo], 1u);
-            if (lo < m && Mi[lo] == rid[i]) atomicOr(&Mc[lo], 0x80000000u);
+            __hip_atomic_fetch_add(&G.cnt[lo], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (lo < m && Mi[lo] == rid[i])
+                __hip_atomic_fetch_or(&Mc[lo], 0x80000000u, __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WORKGROUP);
         }
     }
     __syncthreads();
@@ -600,7 +655,7 @@ __device__ __forceinline__ int base_split(const SortedBase &SB, const FarList &F
 // (all threads; most <= G.cap). Returns the number of live entries; D is
 // unchanged when that is above `most`.
 template <int BT>
-__device__ __forceinline__ int delta_compact(const WorkCol &D, const Staging &G, u32 p, int most,
+__device__ __forceinline__ int delta_compact(const LdsCol &D, const Staging &G, u32 p, int most,
                              RedShared<BT> &S) {
     const int tid = threadIdx.x;
     const int ns = min(*D.nslots, (int)D.mask + 1);
@@ -636,7 +691,7 @@ __device__ __forceinline__ int delta_compact(const WorkCol &D, const Staging &G,
 // keep D at most an eighth full (compacting it when few of its entries are
 // live, else merging it into S) and S at most capD live entries
 template <int BT>
-__device__ __forceinline__ int delta_check(const WorkCol &D, const Staging &G,
+__device__ __forceinline__ int delta_check(const LdsCol &D, const Staging &G,
                                            const ReduceScratch &SC, u32 p, RedShared<BT> &S) {
     const int capD = (int)D.mask + 1;
     if (*D.nslots <= capD / 8) return kRedOk;
@@ -657,7 +712,7 @@ __device__ __forceinline__ int delta_check(const WorkCol &D, const Staging &G,
 // patterns (non-negative floats order like their bits) over [kd, tmax],
 // refined while the chosen bin holds far more than the target.
 template <int BT>
-__device__ __forceinline__ int far_pull(const WorkCol &D, const Staging &G,
+__device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
                                         const ReduceScratch &SC, u32 p, int target, float tmax,
                                         RedShared<BT> &S) {
     const FarList &F = SC.F;
@@ -832,7 +887,7 @@ __device__ __forceinline__ int far_pull(const WorkCol &D, const Staging &G,
 // the item's coefficient. Dense candidates: all vertices; sparse: the
 // neighbours of the item's vertex with the fewest.
 template <int BT, class Dist>
-__device__ __forceinline__ int add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
+__device__ __forceinline__ int add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, const LdsCol &D,
                          const Staging &G, const ReduceScratch &SC) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
@@ -918,7 +973,7 @@ __device__ __forceinline__ int add_items(const ReduceJob<Dist> &J, RedShared<BT>
 
 // Add mul times the coboundaries of the simplices of a stored V column.
 template <int BT, class Dist>
-__device__ __forceinline__ int add_vcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
+__device__ __forceinline__ int add_vcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const LdsCol &D,
                            const Staging &G, const ReduceScratch &SC, int64_t off, int len,
                            u32 mul) {
     const int tid = threadIdx.x;
@@ -941,7 +996,7 @@ __device__ __forceinline__ int add_vcolumn(const ReduceJob<Dist> &J, RedShared<B
 
 // Add neg times the stored R column entries [off, off + len), in segments.
 template <int BT, class Dist>
-__device__ __forceinline__ int add_rcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const WorkCol &D,
+__device__ __forceinline__ int add_rcolumn(const ReduceJob<Dist> &J, RedShared<BT> &S, const LdsCol &D,
                            const Staging &G, const ReduceScratch &SC, int64_t off, int len,
                            u32 neg) {
     const u32 p = J.p;
@@ -969,8 +1024,8 @@ __device__ __forceinline__ int add_rcolumn(const ReduceJob<Dist> &J, RedShared<B
 
 // Append the live entries of a table (V_j) or of the sorted base to the
 // column store; returns the count, or -1 when the store is full.
-template <int BT>
-__device__ __forceinline__ int store_table(const WorkCol &T, const VStore &V, unsigned long long *vcount, u32 p,
+template <int BT, class Tb>
+__device__ __forceinline__ int store_table(const Tb &T, const VStore &V, unsigned long long *vcount, u32 p,
                            RedShared<BT> &S, int64_t *off_out) {
     const int tid = threadIdx.x;
     const int ns = min(*T.nslots, (int)T.mask + 1);
@@ -1024,8 +1079,8 @@ __device__ __forceinline__ int store_base(const SortedBase &SB, const VStore &V,
 
 // live entries of the working column's near part (D merged into S first
 // when S is in use); -1 on failure
-template <int BT>
-__device__ __forceinline__ int count_live(const WorkCol &T, u32 p, RedShared<BT> &S) {
+template <int BT, class Tb>
+__device__ __forceinline__ int count_live(const Tb &T, u32 p, RedShared<BT> &S) {
     const int ns = min(*T.nslots, (int)T.mask + 1);
     int cnt = 0;
     for (int i = threadIdx.x; i < ns; i += BT) cnt += (ld(&T.coef[T.slots[i]]) % p) != 0 ? 1 : 0;
@@ -1058,8 +1113,8 @@ __device__ __forceinline__ bool log_add(const ReduceScratch &SC, RedShared<BT> &
 
 // V_j = sigma_j + the logged combination, summed into table T (all threads).
 // Returns false when T overflowed (T is then in an unspecified state).
-template <int BT, class Dist>
-__device__ __forceinline__ bool materialize_v(const ReduceJob<Dist> &J, const ReduceScratch &SC, const WorkCol &T,
+template <int BT, class Dist, class Tb>
+__device__ __forceinline__ bool materialize_v(const ReduceJob<Dist> &J, const ReduceScratch &SC, const Tb &T,
                               int64_t sidx, float sdm, RedShared<BT> &S) {
     const u32 p = J.p;
     bool ok = true;
@@ -1099,7 +1154,7 @@ __device__ __forceinline__ bool materialize_v(const ReduceJob<Dist> &J, const Re
 // (column o with its factor, or an apparent facet rho) and V_j is summed
 // once, when the column pairs.
 template <int BT, class Dist>
-__device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const WorkCol &D, const Staging &G,
+__device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol &D, const Staging &G,
                           const ReduceScratch &SC, int j, RedShared<BT> &S) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
@@ -1294,7 +1349,8 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const WorkCo
             }
         }
         int64_t voff = 0;
-        const int vn = store_table<BT>(used_lds ? D : SC.Vw, J.V, J.vcount, p, S, &voff);
+        const int vn = used_lds ? store_table<BT>(D, J.V, J.vcount, p, S, &voff)
+                                : store_table<BT>(SC.Vw, J.V, J.vcount, p, S, &voff);
         if (!used_lds) wc_reset<BT>(SC.Vw);
         if (vn < 0) {
             result = kRedStoreFull;
@@ -1344,7 +1400,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const WorkCo
 // additions, bars_nonzero, essential, columns that used the sorted base or
 // far list, largest stored V column, largest working column.
 template <int BT, class Dist>
-__device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const WorkCol &D, const Staging &G,
+__device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const LdsCol &D, const Staging &G,
                               const ReduceScratch &SC, RedShared<BT> &S) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
@@ -1427,7 +1483,7 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Wo
     return status;
 }
 
-hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceScratch SC, Scalars *s,
+hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceBuffers RB, Scalars *s,
                          hipStream_t st);
 
 } // namespace rips

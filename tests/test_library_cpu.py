@@ -106,3 +106,48 @@ def test_batched_config_validation():
     assert lib.rips_batched_set_config(1024, 9) == -1
     assert lib.rips_batched_autotune(None, None, 1, 2, 8, 1, ctypes.c_float(1.0), 2, None, None,
                                      0, None, None, None) == -1
+
+
+def _record_layouts(src: str, side: str):
+    """{record: (size, field offsets)} of the rips:: records as one compiler
+    pass (host or device) lays them out."""
+    csrc = os.path.join(ROOT, "paper_1908_02518_amd", "csrc")
+    r = subprocess.run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-std=c++17", "-I",
+                        os.path.join(ROOT, "include"), f"--cuda-{side}-only", "-fsyntax-only", src,
+                        "-Xclang", "-fdump-record-layouts-simple"],
+                       capture_output=True, text=True, cwd=csrc)
+    out = {}
+    for blk in r.stdout.split("*** Dumping AST Record Layout")[1:]:
+        t = re.search(r"Type: (.*)", blk).group(1).strip()
+        if "rips::" in t:
+            out[t] = (re.search(r"Size:(\d+)", blk).group(1),
+                      re.search(r"FieldOffsets: \[(.*?)\]", blk).group(1))
+    return out
+
+
+def _kernel_argument_records(src: str):
+    """Record names that appear in the parameter lists of the file's kernels."""
+    text = open(os.path.join(ROOT, "paper_1908_02518_amd", "csrc", src)).read()
+    text = re.sub(r"__launch_bounds__\s*\([^)]*\)", "", text)
+    names = set()
+    for m in re.finditer(r"__global__[^{;]*?\w+\s*\(([^)]*)\)", text, flags=re.S):
+        names.update(re.findall(r"\b([A-Z]\w*)\b", m.group(1)))
+    return names
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/bin/hipcc"), reason="needs hipcc")
+@pytest.mark.parametrize("src", ["rips_kernels.hip", "rips_batched.hip"])
+def test_kernel_argument_layouts_match_between_host_and_device(src):
+    # a record passed by value to a kernel is laid out by the host and read by
+    # the device: an LDS pointer (32 bits on the device, 64 on the host) in
+    # one would shift every later field
+    host, dev = _record_layouts(src, "host"), _record_layouts(src, "device")
+    wanted = _kernel_argument_records(src)
+    assert wanted
+    checked = 0
+    for t, lay in host.items():
+        short = re.sub(r"^struct |^class ", "", t).replace("rips::", "").split("<")[0]
+        if short in wanted:
+            assert dev.get(t) == lay, (t, lay, dev.get(t))
+            checked += 1
+    assert checked >= 2
