@@ -719,7 +719,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 c
         s->stat[kStatSplits] += S.stat[10];
         s->stat[kStatPulled] += S.stat[11];
         s->stat[kStatAdded] += S.stat[12];
-        for (int q = 0; q < 12; ++q) s->stat[kStatTime + q] += S.tm[q];
+        for (int q = 0; q < 16; ++q) s->stat[kStatTime + q] += S.tm[q];
     }
 }
 

@@ -282,7 +282,7 @@ struct RedShared {
     int w[BT / kWave + 1];
     u32 mm[2][BT / kWave];
     unsigned long long stat[13];
-    unsigned long long tm[12]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner
+    unsigned long long tm[16]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner; merge: gather, rank, base pass, prefix
     u32 hist[256];
     // simplices whose coboundaries are added next: vertices, coefficient,
     // diameter, candidate source (vertex with the fewest neighbours, -1 =
@@ -493,6 +493,7 @@ __device__ __forceinline__ int base_merge(const LdsCol &D, const Staging &G, con
     RED_T0(t_mrg);
     const int tid = threadIdx.x;
     const int ns = min(*D.nslots, (int)D.mask + 1);
+    RED_T0(t_m1);
     // 1. gather the live entries into the staging area, unsorted
     int cnt = 0;
     for (int i = tid; i < ns; i += BT) cnt += (ld(&D.coef[D.slots[i]]) % p) != 0 ? 1 : 0;
@@ -511,21 +512,70 @@ __device__ __forceinline__ int base_merge(const LdsCol &D, const Staging &G, con
         }
     }
     __syncthreads();
-    // 2. sort by rank (keys are distinct): M = D's first m slots
+    RED_T1(S, 12, t_m1);
+    RED_T0(t_m2);
+    // 2. sort into M = D's first m slots (keys are distinct): every wave
+    // sorts 64-entry chunks of the staging area in place with a bitonic
+    // network over shuffles; an entry's rank is then its place in its chunk
+    // plus, for every other chunk, how many of its entries are older
     LDS int64_t *Mi = D.keys;
     LDS float *Md = D.diam;
     LDS u32 *Mc = D.coef;
-    for (int e = tid; e < m; e += BT) {
-        const int64_t ie = G.idx[e];
-        const float de = G.dia[e];
-        int r = 0;
-        for (int q = 0; q < m; ++q) r += older_key(G.dia[q], G.idx[q], de, ie) ? 1 : 0;
-        Mi[r] = ie;
-        Md[r] = de;
-        Mc[r] = G.coef[e];
+    {
+        const int lane = lane_id(), w = tid / kWave;
+        const int nc = (m + kWave - 1) / kWave;
+        for (int ch = w; ch < nc; ch += BT / kWave) {
+            const int e = ch * kWave + lane;
+            const bool real = e < m;
+            float d = real ? G.dia[e] : INFINITY;
+            int64_t id = real ? G.idx[e] : (int64_t)-1;
+            u32 cf = real ? G.coef[e] : 0u;
+            for (int kk = 2; kk <= kWave; kk <<= 1) {
+                for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+                    const float pd = __shfl_xor(d, jj, kWave);
+                    const int64_t pi = __shfl_xor(id, jj, kWave);
+                    const u32 pc = (u32)__shfl_xor((int)cf, jj, kWave);
+                    const bool up = (lane & kk) == 0;
+                    const bool lower = (lane & jj) == 0;
+                    const bool p_older = older_key(pd, pi, d, id);
+                    if (lower == up ? p_older : (!p_older && (pd != d || pi != id))) {
+                        d = pd;
+                        id = pi;
+                        cf = pc;
+                    }
+                }
+            }
+            if (real) {
+                G.dia[e] = d;
+                G.idx[e] = id;
+                G.coef[e] = cf;
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < m; e += BT) {
+            const int ch = e / kWave;
+            const float de = G.dia[e];
+            const int64_t ie = G.idx[e];
+            int r = e - ch * kWave;
+            for (int c2 = 0; c2 < nc; ++c2) {
+                if (c2 == ch) continue;
+                int lo = c2 * kWave, hi = min(m, lo + kWave); // first entry not older
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (older_key(G.dia[mid], G.idx[mid], de, ie)) lo = mid + 1;
+                    else hi = mid;
+                }
+                r += lo - c2 * kWave;
+            }
+            Mi[r] = ie;
+            Md[r] = de;
+            Mc[r] = G.coef[e];
+        }
     }
     for (int i = tid; i <= m; i += BT) G.cnt[i] = 0;
     __syncthreads();
+    RED_T1(S, 13, t_m2);
+    RED_T0(t_m3);
     // 3. every base entry into registers with its lower bound in M (first
     // entry not older than it); counts; duplicate flag (bit 31 of M's
     // coefficient)
@@ -558,6 +608,8 @@ __device__ __forceinline__ int base_merge(const LdsCol &D, const Staging &G, con
         }
     }
     __syncthreads();
+    RED_T1(S, 14, t_m3);
+    RED_T0(t_m4);
     // 4. inclusive prefix of the counts (base entries older than M[i] for a
     // non-duplicate i), exclusive prefix of the non-duplicates
     int carry_c = 0, carry_n = 0;
@@ -576,6 +628,7 @@ __device__ __forceinline__ int base_merge(const LdsCol &D, const Staging &G, con
         carry_n += tn;
     }
     __syncthreads();
+    RED_T1(S, 15, t_m4);
     // 5. write in place (every base entry was read in step 3): base entry r
     // goes to r + (non-duplicates before its lower bound); non-duplicate M[i]
     // goes to (base entries older) + (non-duplicates before it)
@@ -1417,7 +1470,7 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
         S.gen = 0;
     }
     if (tid < 13) S.stat[tid] = 0;
-    if (tid < 12) S.tm[tid] = 0;
+    if (tid < 16) S.tm[tid] = 0;
     int status = 0;
     gsync();
     RED_T0(t_total);
