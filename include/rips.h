@@ -235,6 +235,21 @@ rips_status rips_backward_device(const float *d_data, int64_t n, int32_t dim, in
                                  float *d_grad, void *hip_stream);
 
 /*
+ * Workgroups of the single-cloud reduction (per device, the current one).
+ * 0 (default): one per compute unit. Each takes the next column in the
+ * reduction order and reduces it against the pivot table as it stands; a
+ * column commits its pivot only once no earlier column can still end with
+ * it, which gives exactly the pairs of the column-by-column order
+ * (Algorithm 2 on the coboundary matrix, section "Persistent cohomology",
+ * with the shortcut of section "Emergent persistence pairs"). 1: the
+ * columns one after another in one workgroup.
+ * Results are bit-identical either way. Returns RIPS_E_INVALID_ARG for a
+ * negative count; rips_get_reduce_workgroups reads the setting back.
+ */
+rips_status rips_set_reduce_workgroups(int32_t workgroups);
+rips_status rips_get_reduce_workgroups(int32_t *workgroups);
+
+/*
  * Launch configuration of the batched path (per device, the current one):
  *   delta_slots        LDS slots of each workgroup's working-column delta:
  *                      512, 1024 or 2048 (0 = default, 2048);

@@ -49,6 +49,8 @@ EXPORTS = (
     "rips_simplex_counts_device",
     "rips_barcode_batched_device",
     "rips_backward_device",
+    "rips_set_reduce_workgroups",
+    "rips_get_reduce_workgroups",
     "rips_batched_set_config",
     "rips_batched_get_config",
     "rips_batched_autotune",
@@ -170,6 +172,10 @@ def _load():
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
     lib.rips_backward_device.restype = ctypes.c_int
+    lib.rips_set_reduce_workgroups.argtypes = [ctypes.c_int32]
+    lib.rips_set_reduce_workgroups.restype = ctypes.c_int
+    lib.rips_get_reduce_workgroups.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+    lib.rips_get_reduce_workgroups.restype = ctypes.c_int
     lib.rips_batched_set_config.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.rips_batched_set_config.restype = ctypes.c_int
     lib.rips_batched_get_config.argtypes = [ctypes.POINTER(ctypes.c_int32),
@@ -436,6 +442,18 @@ def barcode_batched(x, offsets, n_max: int, *, max_dim: int = 1,
         break
     return BatchedBars(birth, death, bs, ds, off, stats.view(B, D1, len(STAT_FIELDS)), thr, B,
                        max_dim)
+
+
+def set_reduce_workgroups(workgroups: int = 0):
+    """Workgroups of the single-cloud reduction: 0 = one per compute unit,
+    1 = one workgroup, columns one after another (same bars either way)."""
+    _check(_lib.rips_set_reduce_workgroups(int(workgroups)))
+
+
+def get_reduce_workgroups() -> int:
+    a = ctypes.c_int32()
+    _check(_lib.rips_get_reduce_workgroups(ctypes.byref(a)))
+    return int(a.value)
 
 
 def batched_set_config(delta_slots: int = 0, workgroups_per_cu: int = 0):

@@ -107,6 +107,12 @@ enum BufId {
     B_LOG_KEY, // addition log of the column being reduced
     B_LOG_COEF,
     B_LOG_DIA,
+    B_CBAR_BIRTH, // per-column bar slots of the spread-out reduction
+    B_CBAR_DEATH,
+    B_CBAR_BS,
+    B_CBAR_DS,
+    B_CST,        // per-column state of the spread-out reduction
+    B_CTL,        // its cursor, frontier and abort flag
     B_BAR_BIRTH, // + d
     B_BAR_DEATH = B_BAR_BIRTH + kMaxDim + 1,
     B_BAR_BS = B_BAR_DEATH + kMaxDim + 1,
@@ -188,8 +194,10 @@ struct DevCtx {
     int64_t hint_v = 0;
     int64_t hint_far = 0;
     int64_t hint_vw = 0;
+    int64_t hint_log = 0;
     int lds_per_block = 0;
     int num_cus = 0;
+    int reduce_groups = 0; // workgroups of the single-cloud reduction: 0 = one per CU
     hipStream_t capture_stream = nullptr;
     // cached graph of the batched launch and the arguments it was built for
     hipGraphExec_t batch_exec = nullptr;
@@ -741,8 +749,28 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         const size_t lds_budget = C.lds_per_block > 16384 ? (size_t)C.lds_per_block - 12288 : 0;
         uint32_t capD = kMaxDelta;
         while (capD > 256 && reduce_lds_bytes(capD) > lds_budget) capD >>= 1;
-        int64_t fcap = std::max<int64_t>(C.hint_far, std::max<int64_t>(1 << 18, 256ll * bound));
+        // the columns spread over one workgroup per CU, each with its own
+        // scratch (smaller first sizes, grown on overflow), or one workgroup
+        const int64_t want = C.reduce_groups > 0 ? C.reduce_groups : std::max(1, C.num_cus);
+        const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(want, S));
+        const bool spread = groups > 1;
+        int64_t fcap = spread ? std::max<int64_t>(C.hint_far, 1 << 16)
+                              : std::max<int64_t>(C.hint_far, std::max<int64_t>(1 << 18, 256ll * bound));
         int64_t vwcap = std::max<int64_t>(C.hint_vw, 1 << 14);
+        // one log entry per addition: (2^18 + 64) never overflows
+        const int64_t lmax = (1 << 18) + 64;
+        int64_t lcap = spread ? std::max<int64_t>(C.hint_log, 1 << 14) : lmax;
+        BarBuf cbars = bars[k];
+        if (spread) {
+            HIP_TRY(C.ensure(B_CBAR_BIRTH, (size_t)S * 4, &q));
+            cbars.birth = as<float>(q);
+            HIP_TRY(C.ensure(B_CBAR_DEATH, (size_t)S * 4, &q));
+            cbars.death = as<float>(q);
+            HIP_TRY(C.ensure(B_CBAR_BS, (size_t)S * 8, &q));
+            cbars.bs = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_CBAR_DS, (size_t)S * 8, &q));
+            cbars.ds = as<int64_t>(q);
+        }
         for (int attempt = 0;; ++attempt) {
             if (attempt > 12) return fail(RIPS_E_CAPACITY, "reduction scratch kept overflowing");
             HIP_TRY(C.ensure(B_V_IDX, (size_t)vcap * 8, &q));
@@ -753,35 +781,44 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             V.coef = as<u32>(q);
             V.cap = vcap;
             ReduceBuffers RB;
+            // one far list, working-V table and log per workgroup
             for (int b = 0; b < 2; ++b) {
-                HIP_TRY(C.ensure(B_F_IDX0 + b, (size_t)fcap * 8, &q));
+                HIP_TRY(C.ensure(B_F_IDX0 + b, (size_t)(groups * fcap) * 8, &q));
                 RB.F.idx[b] = as<int64_t>(q);
-                HIP_TRY(C.ensure(B_F_DIA0 + b, (size_t)fcap * 4, &q));
+                HIP_TRY(C.ensure(B_F_DIA0 + b, (size_t)(groups * fcap) * 4, &q));
                 RB.F.dia[b] = as<float>(q);
-                HIP_TRY(C.ensure(B_F_COEF0 + b, (size_t)fcap * 4, &q));
+                HIP_TRY(C.ensure(B_F_COEF0 + b, (size_t)(groups * fcap) * 4, &q));
                 RB.F.coef[b] = as<u32>(q);
             }
             RB.F.cap = fcap;
-            HIP_TRY(C.ensure(B_VW_KEYS, (size_t)vwcap * 8, &q));
+            HIP_TRY(C.ensure(B_VW_KEYS, (size_t)(groups * vwcap) * 8, &q));
             RB.vw_keys = as<int64_t>(q);
-            HIP_TRY(C.ensure(B_VW_COEF, (size_t)vwcap * 4, &q));
+            HIP_TRY(C.ensure(B_VW_COEF, (size_t)(groups * vwcap) * 4, &q));
             RB.vw_coef = as<u32>(q);
-            HIP_TRY(C.ensure(B_VW_DIAM, (size_t)vwcap * 4, &q));
+            HIP_TRY(C.ensure(B_VW_DIAM, (size_t)(groups * vwcap) * 4, &q));
             RB.vw_diam = as<float>(q);
-            HIP_TRY(C.ensure(B_VW_SLOTS, (size_t)vwcap * 4, &q));
+            HIP_TRY(C.ensure(B_VW_SLOTS, (size_t)(groups * vwcap) * 4, &q));
             RB.vw_slots = as<u32>(q);
             RB.vw_cap = vwcap;
-            // one entry per addition: the addition bound (2^18) never overflows it
-            const int64_t lcap = (1 << 18) + 64;
-            HIP_TRY(C.ensure(B_LOG_KEY, (size_t)lcap * 8, &q));
+            HIP_TRY(C.ensure(B_LOG_KEY, (size_t)(groups * lcap) * 8, &q));
             RB.lkey = as<int64_t>(q);
-            HIP_TRY(C.ensure(B_LOG_COEF, (size_t)lcap * 4, &q));
+            HIP_TRY(C.ensure(B_LOG_COEF, (size_t)(groups * lcap) * 4, &q));
             RB.lcoef = as<u32>(q);
-            HIP_TRY(C.ensure(B_LOG_DIA, (size_t)lcap * 4, &q));
+            HIP_TRY(C.ensure(B_LOG_DIA, (size_t)(groups * lcap) * 4, &q));
             RB.ldia = as<float>(q);
             RB.lcap = lcap;
             launch_fill_i64(ph.keys, phcap, kEmpty, st);
             launch_reset_dim(P.scal, st);
+            ParState par{nullptr, nullptr};
+            if (spread) {
+                HIP_TRY(C.ensure(B_CST, (size_t)S * 4, &q));
+                par.cst = as<u32>(q);
+                HIP_TRY(C.ensure(B_CTL, (size_t)kCtlWords * 4, &q));
+                par.ctl = as<u32>(q);
+                launch_fill_u32(par.cst, S, 0u, st);
+                launch_fill_u32(par.ctl, kCtlWords, 0u, st);
+                launch_fill_u32((u32 *)ph.vals, phcap, 0xffffffffu, st); // -1: no value yet
+            }
             ReduceJob<DistFull> J;
             J.c = P.ctx;
             J.k = k;
@@ -792,13 +829,15 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             J.ph = ph;
             J.V = V;
             J.vcount = &P.scal->vcount;
-            J.bars = bars[k];
+            J.bars = spread ? cbars : bars[k];
             J.app = app;
+            J.par = par;
             J.cand_avg = P.sparse ? (float)(2.0 * (double)P.nedges / (double)std::max<int64_t>(n, 1))
                                   : (float)n;
             {
                 PROF(P_REDUCE1 + k - 1);
-                HIP_TRY(launch_reduce(J, capD, RB, P.scal, st));
+                if (spread) HIP_TRY(launch_reduce_par(J, capD, RB, (int)groups, bars[k], P.scal, st));
+                else HIP_TRY(launch_reduce(J, capD, RB, P.scal, st));
             }
             if ((rs = read_scalars(C, P.scal, st))) return rs;
             const int status = C.host_scal->status;
@@ -811,8 +850,13 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             } else if (status == kRedVFull) {
                 vwcap *= 4;
                 C.hint_vw = vwcap;
+            } else if (status == kRedLogFull && lcap < lmax) {
+                lcap = std::min(lmax, lcap * 4);
+                C.hint_log = lcap;
             } else if (status == kRedLogFull) {
                 return fail(RIPS_E_HIP, "reduction log overflow");
+            } else if (status == kRedWait) {
+                return fail(RIPS_E_HIP, "reduction: a wait for earlier columns exceeded its bound");
             } else {
                 return fail(RIPS_E_HIP, "reduction exceeded its addition bound");
             }
@@ -1370,6 +1414,27 @@ rips_status rips_backward_device(const float *d_data, int64_t n, int32_t dim, in
                     d_death_simplex, d_grad_birth, d_grad_death, d_grad, st);
     HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(st));
+    return RIPS_OK;
+}
+
+rips_status rips_set_reduce_workgroups(int32_t workgroups) {
+    g_err.clear();
+    if (workgroups < 0) return fail(RIPS_E_INVALID_ARG, "workgroups must be >= 0");
+    DevCtx *C;
+    rips_status rs;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    C->reduce_groups = workgroups;
+    return RIPS_OK;
+}
+
+rips_status rips_get_reduce_workgroups(int32_t *workgroups) {
+    g_err.clear();
+    DevCtx *C;
+    rips_status rs;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    if (workgroups) *workgroups = C->reduce_groups;
     return RIPS_OK;
 }
 

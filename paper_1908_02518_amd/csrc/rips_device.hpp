@@ -217,11 +217,28 @@ __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
 // Barrier for phases that hand data between the waves of one workgroup
 // through global memory. The workgroup barrier's release/acquire fences
-// cover global memory as well as LDS, and every kernel here shares global
-// scratch only inside one workgroup (other workgroups see it after the
-// kernel ends), so workgroup scope is enough. An agent-scope fence would
-// write back and invalidate the L2 at every call.
+// cover global memory as well as LDS, and a workgroup's scratch is its own,
+// so workgroup scope is enough. An agent-scope fence writes back (release)
+// or invalidates (acquire) the L2 of the XCD, whose L2s are not coherent
+// with each other: it is kept to the few places where workgroups of one
+// launch hand data to each other (the reduction spread over workgroups).
 __device__ __forceinline__ void gsync() { __syncthreads(); }
+
+// Agent-scope relaxed loads / stores, for words that workgroups of one
+// launch exchange (they bypass the non-coherent caches), and agent-scope
+// fences that order the plain accesses around them.
+template <class T>
+__device__ __forceinline__ T ld_dev(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class T>
+__device__ __forceinline__ void st_dev(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void fence_release_dev() { __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent"); }
+__device__ __forceinline__ void fence_acquire_dev() { __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent"); }
 
 // Relaxed workgroup-scope atomic load / store, for words that other waves
 // of the workgroup update with atomics (atomics execute in L2; these loads
@@ -374,6 +391,37 @@ __device__ __forceinline__ bool ph_insert(const PivotHash &h, int64_t key, int32
         const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
         if (prev == (u64)kEmpty || prev == (u64)key) {
             st(&h.vals[s], val);
+            return true;
+        }
+        s = (s + 1) & h.mask;
+    }
+    return false;
+}
+
+// The same table shared by the workgroups of one launch. A slot's value is
+// -1 until its writer stores it, and a reader takes -1 for "not there": the
+// writer stores the value after everything it publishes with it, behind an
+// agent-scope release fence, and a reader that finds a value and then reads
+// what it refers to issues an agent-scope acquire fence first.
+__device__ __forceinline__ int32_t ph_find_dev(const PivotHash &h, int64_t key) {
+    u32 s = mix64((u64)key) & h.mask;
+    for (u32 probe = 0; probe <= h.mask; ++probe) {
+        const int64_t cur = ld_dev(&h.keys[s]);
+        if (cur == key) return ld_dev(&h.vals[s]);
+        if (cur == kEmpty) return -1;
+        s = (s + 1) & h.mask;
+    }
+    return -1;
+}
+
+__device__ __forceinline__ bool ph_insert_dev(const PivotHash &h, int64_t key, int32_t val) {
+    u32 s = mix64((u64)key) & h.mask;
+    for (u32 probe = 0; probe <= h.mask; ++probe) {
+        int64_t expect = kEmpty;
+        const bool won = __hip_atomic_compare_exchange_strong(&h.keys[s], &expect, key, __ATOMIC_RELAXED,
+                                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (won || expect == key) {
+            st_dev(&h.vals[s], val);
             return true;
         }
         s = (s + 1) & h.mask;

@@ -185,6 +185,12 @@ __global__ void k_zero_int(int *a, int64_t n) {
         a[q] = 0;
 }
 
+__global__ void k_fill_u32(u32 *a, int64_t n, u32 v) {
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
+         q += (int64_t)gridDim.x * blockDim.x)
+        a[q] = v;
+}
+
 __global__ void k_fill_i64(int64_t *a, int64_t n, int64_t v) {
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n;
          q += (int64_t)gridDim.x * blockDim.x)
@@ -723,6 +729,76 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 c
     }
 }
 
+// The reduction spread over a launch of `groups` workgroups (one per CU: the
+// working column takes the LDS). Each workgroup has its own far list,
+// working-V table and addition log, at blockIdx.x times their capacities.
+template <class Dist>
+__global__ void __launch_bounds__(kRedThreads) k_reduce_par(ReduceJob<Dist> J, u32 capD,
+                                                           ReduceBuffers RB, Scalars *s) {
+    extern __shared__ unsigned char smem[];
+    __shared__ RedShared<kRedThreads> S;
+    __shared__ int s_ns;
+    LdsCol D;
+    Staging G;
+    SortedBase SB;
+    carve_reduce_lds(smem, capD, (LDS int *)&s_ns, &D, &G, &SB);
+    const int64_t g = blockIdx.x;
+    ReduceBuffers R = RB;
+    for (int b = 0; b < 2; ++b) {
+        R.F.idx[b] += g * RB.F.cap;
+        R.F.dia[b] += g * RB.F.cap;
+        R.F.coef[b] += g * RB.F.cap;
+    }
+    R.vw_keys += g * RB.vw_cap;
+    R.vw_coef += g * RB.vw_cap;
+    R.vw_diam += g * RB.vw_cap;
+    R.vw_slots += g * RB.vw_cap;
+    R.lkey += g * RB.lcap;
+    R.lcoef += g * RB.lcap;
+    R.ldia += g * RB.lcap;
+    const ReduceScratch SC = make_scratch(R, SB, (LDS int *)&S.vns);
+    const int status = reduce_columns_par<kRedThreads>(J, D, G, SC, S);
+    if (threadIdx.x == 0) {
+        if (status && status != kRedAbort) atomicCAS(&s->status, 0, status);
+        atomicAdd(&s->stat[kStatEmergent], S.stat[0]);
+        atomicAdd(&s->stat[kStatReduced], S.stat[1]);
+        atomicAdd(&s->stat[kStatAdditions], S.stat[2]);
+        atomicAdd(&s->stat[kStatBarsNonzero], S.stat[3]);
+        atomicAdd(&s->stat[kStatEssential], S.stat[4]);
+        atomicAdd(&s->stat[kStatGlobalCols], S.stat[5]);
+        atomicMax(&s->stat[kStatMaxV], S.stat[6]);
+        atomicMax(&s->stat[kStatMaxR], S.stat[7]);
+        atomicAdd(&s->stat[kStatPulls], S.stat[8]);
+        atomicAdd(&s->stat[kStatMerges], S.stat[9]);
+        atomicAdd(&s->stat[kStatSplits], S.stat[10]);
+        atomicAdd(&s->stat[kStatPulled], S.stat[11]);
+        atomicAdd(&s->stat[kStatAdded], S.stat[12]);
+        for (int q = 0; q < 16; ++q) atomicAdd(&s->stat[kStatTime + q], S.tm[q]);
+    }
+}
+
+// Bars of the spread-out reduction, one slot per column in column order
+// (birth simplex -1: none), compacted in that order by one workgroup.
+__global__ void __launch_bounds__(1024) k_compact_bars(BarBuf in, int64_t ncols, BarBuf out, Scalars *s) {
+    __shared__ int s_w[1024 / kWave + 1];
+    int64_t base = 0;
+    for (int64_t c0 = 0; c0 < ncols; c0 += 1024) {
+        const int64_t q = c0 + threadIdx.x;
+        const bool keep = q < ncols && in.bs[q] >= 0;
+        int tot;
+        const int at = block_exclusive_scan<1024>(keep ? 1 : 0, s_w, &tot);
+        if (keep) {
+            const int64_t d = base + at;
+            out.birth[d] = in.birth[q];
+            out.death[d] = in.death[q];
+            out.bs[d] = in.bs[q];
+            out.ds[d] = in.ds[q];
+        }
+        base += tot;
+    }
+    if (threadIdx.x == 0) s->nbars = base;
+}
+
 // ---------------------------------------------------------------------------
 // Backward: d(loss)/d(bar endpoint) scattered onto the critical edge of the
 // endpoint's simplex (the edge of largest float32 length, ties to the
@@ -923,6 +999,14 @@ void launch_fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t st) {
     hipLaunchKernelGGL(k_fill_i64, dim3((unsigned)blocks), dim3(256), 0, st, a, n, v);
 }
 
+void launch_fill_u32(u32 *a, int64_t n, u32 v, hipStream_t st) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, a, n, v);
+}
+
+
 void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Columns out,
                          hipStream_t st) {
     hipLaunchKernelGGL(k_sort_columns, dim3(1), dim3(kSortThreads), 0, st, in, s, sb, lo_bytes,
@@ -936,6 +1020,21 @@ hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceBuffers R
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_reduce<DistFull>), dim3(1), dim3(kRedThreads), lds, st, J, capD, RB, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_par(const ReduceJob<DistFull> &J, u32 capD, ReduceBuffers RB, int groups,
+                             BarBuf out, Scalars *s, hipStream_t st) {
+    const size_t lds = reduce_lds_bytes(capD);
+    hipError_t e = hipFuncSetAttribute((const void *)k_reduce_par<DistFull>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_reduce_par<DistFull>), dim3(groups), dim3(kRedThreads), lds, st, J, capD, RB,
+                       s);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_compact_bars, dim3(1), dim3(1024), 0, st, J.bars, (int64_t)J.ncols,
+                       out, s);
     return hipGetLastError();
 }
 

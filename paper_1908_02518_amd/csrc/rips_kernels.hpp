@@ -75,7 +75,7 @@ struct VStore {
     int *len;       // -1: V_j is the column's own simplex (emergent pair)
     int64_t *roff;  // per column: R_j in the pool
     int *rlen;      // -1: R_j not stored
-    u32 *pivcoef;   // pivot entry of R_j
+    u32 *pivcoef;   // inverse of the pivot entry of R_j (mod p)
     int64_t *idx;   // append pool
     float *diam;
     u32 *coef;
@@ -118,6 +118,7 @@ void launch_csr(const float *D, int n, Scalars *s, const int *deg, int *off, int
 void launch_h0(EdgeList E, Scalars *s, int n, H0Scratch W, BarBuf out, int64_t nbits_words,
                hipStream_t st);
 void launch_fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t st);
+void launch_fill_u32(u32 *a, int64_t n, u32 v, hipStream_t st);
 void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
                    const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app,
                    hipStream_t st);

@@ -144,7 +144,14 @@ enum : int {
     kRedFarFull = 4,   // far list too small
     kRedVFull = 5,     // working V table too small
     kRedLogFull = 6,   // addition log too small
+    kRedAbort = 7,     // another workgroup of the launch failed
+    kRedWait = 8,      // a wait for the columns before exceeded its bound
 };
+
+// Bound of one wait in the spread-out reduction, in wall-clock ticks
+// (100 MHz): far above any wait a correct run has, it only turns a fault
+// into an error.
+constexpr unsigned long long kWaitTicks = 1000000000ull;
 
 // LDS bytes of a delta of capD slots, its merge staging (capD / 4 entries)
 // and the sorted base (capD + capD / 4 entries).
@@ -246,6 +253,24 @@ __device__ __forceinline__ bool older_key(float da, int64_t ia, float db, int64_
 }
 
 // Everything the routine needs about one dimension of one cloud.
+// State shared by the workgroups of a reduction spread over a launch. Each
+// workgroup takes the next column in order and reduces it against the pivot
+// table as it stands. Pivots only move to younger rows while a column is
+// reduced (every addition clears the pivot and adds entries younger than it),
+// so a column whose current pivot has a larger diameter than tau can never
+// end with tau. A column whose pivot tau is free therefore waits until every
+// column before it is committed or has its pivot past tau's diameter, looks
+// tau up once more, and then either adds the owner's column or commits:
+// every pair is the one the column-by-column order gives.
+constexpr u32 kColDone = 0xffffffffu;
+enum : int { kCtlNext = 0, kCtlFront = 1, kCtlAbort = 2, kCtlWords = 4 };
+struct ParState {
+    u32 *cst; // per column: float bits of a lower bound of its final pivot's diameter
+              // (0 before it starts), kColDone once committed
+    u32 *ctl; // kCtlWords words: column cursor, frontier (columns below it are
+              // committed; only raised), abort flag
+};
+
 template <class Dist>
 struct ReduceJob {
     Ctx<Dist> c;
@@ -260,6 +285,7 @@ struct ReduceJob {
     BarBuf bars;                // capacity ncols
     float cand_avg;             // mean coboundary candidates of a k-simplex
     PairHash app;               // zero apparent pairs (rho, tau) of this dimension, or none
+    ParState par;               // reduction spread over workgroups (cst null: one workgroup)
 };
 
 // Shared state of the routine (one per workgroup).
@@ -274,6 +300,9 @@ struct RedShared {
     int64_t kidx;
     int64_t len, f; // sorted base: length and front
     int64_t owner, qsplit, appv;
+    int64_t tau;    // spread-out reduction: emergent candidate
+    u32 tcoef, pub; // its coefficient; diameter bits published for this column
+    int wbad, wopen, wstop;
     u32 lo, bound;
     int shift;
     unsigned long long vbase;
@@ -1200,13 +1229,72 @@ __device__ __forceinline__ bool materialize_v(const ReduceJob<Dist> &J, const Re
     return res;
 }
 
+// Block-wide minimum of two values (all threads; every thread gets both).
+template <int BT>
+__device__ __forceinline__ void block_min2(int &a, int &b, RedShared<BT> &S) {
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        a = min(a, __shfl_xor(a, o, kWave));
+        b = min(b, __shfl_xor(b, o, kWave));
+    }
+    const int w = threadIdx.x / kWave;
+    if (lane_id() == 0) {
+        S.mm[0][w] = (u32)a;
+        S.mm[1][w] = (u32)b;
+    }
+    __syncthreads();
+    for (int q = 0; q < BT / kWave; ++q) {
+        a = min(a, (int)S.mm[0][q]);
+        b = min(b, (int)S.mm[1][q]);
+    }
+    __syncthreads();
+}
+
+// Spread-out reduction: wait until no column before j can still end with a
+// pivot of diameter bits <= dbits, i.e. each one is committed or its current
+// pivot is past that diameter (a column's published bound only grows).
+// Returns 0, or kRedAbort / kRedWait (all threads get the same answer).
+template <int BT, class Dist>
+__device__ int par_wait(const ReduceJob<Dist> &J, RedShared<BT> &S, int j, u32 dbits) {
+    const int tid = threadIdx.x;
+    u32 *ctl = J.par.ctl;
+    if (tid == 0) S.wbad = (int)ld_dev(&ctl[kCtlFront]);
+    __syncthreads();
+    int from = min(S.wbad, j);
+    const unsigned long long t0 = tid == 0 ? wall_clock64() : 0ull;
+    for (bool first = true;; first = false) {
+        int bad = j, open = j;
+        for (int o = from + tid; o < j; o += BT) {
+            const u32 st = ld_dev(&J.par.cst[o]);
+            if (st != kColDone) open = min(open, o);
+            if (st <= dbits) bad = min(bad, o);
+        }
+        block_min2<BT>(bad, open, S);
+        // the frontier may move up only past columns this scan saw committed
+        if (tid == 0 && first && open > from) atomicMax(&ctl[kCtlFront], (u32)open);
+        if (bad == j) break;
+        // the columns in [from, bad) stay past dbits: scan from bad next time
+        from = bad;
+        if (tid == 0) {
+            S.wstop = 0;
+            if (ld_dev(&ctl[kCtlAbort])) S.wstop = kRedAbort;
+            else if (wall_clock64() - t0 > kWaitTicks) S.wstop = kRedWait;
+        }
+        __syncthreads();
+        const int stop = S.wstop;
+        __syncthreads();
+        if (stop) return stop;
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return 0;
+}
+
 // Full reduction of column j. Returns a result code; on anything but kRedOk
 // nothing of column j has been published.
 //
 // V_j is not kept up to date at every addition: the additions are logged
 // (column o with its factor, or an apparent facet rho) and V_j is summed
 // once, when the column pairs.
-template <int BT, class Dist>
+template <int BT, class Dist, bool kPar>
 __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol &D, const Staging &G,
                           const ReduceScratch &SC, int j, RedShared<BT> &S) {
     const Ctx<Dist> &c = J.c;
@@ -1231,6 +1319,11 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         S.it_coef[0] = 1u;
         S.it_diam[0] = sdm;
         decode(sidx, k, c.n, c.B, S.it_v[0]);
+        if (kPar) {
+            // every cofacet of sigma is at least as old as sigma
+            S.pub = __float_as_uint(sdm);
+            st_dev(&J.par.cst[j], S.pub);
+        }
     }
     __syncthreads();
     int result = add_items<BT>(J, S, D, G, SC);
@@ -1262,8 +1355,20 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         RED_T1(S, 0, t_piv);
         if (result) break;
         if (piv.idx == kEmpty) {
-            // zero column: essential class born at sigma
-            if (tid == 0) {
+            // zero column: essential class born at sigma (final as it is:
+            // nothing is left to look up)
+            if (kPar) {
+                if (tid == 0) {
+                    J.bars.birth[j] = sdm;
+                    J.bars.death[j] = INFINITY;
+                    J.bars.bs[j] = sidx;
+                    J.bars.ds[j] = -1;
+                    S.stat[4] += 1;
+                }
+                fence_release_dev();
+                __syncthreads();
+                if (tid == 0) st_dev(&J.par.cst[j], kColDone);
+            } else if (tid == 0) {
                 if (S.nbars < J.ncols) {
                     J.bars.birth[S.nbars] = sdm;
                     J.bars.death[S.nbars] = INFINITY;
@@ -1275,16 +1380,33 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             }
             break;
         }
+        if (kPar && tid == 0 && __float_as_uint(piv.diam) > S.pub) {
+            S.pub = __float_as_uint(piv.diam);
+            st_dev(&J.par.cst[j], S.pub);
+        }
         RED_T0(t_own);
         // pivot table and apparent-pair table, read by two waves at once
-        if (tid == 0) S.owner = ph_find(J.ph, piv.idx);
+        if (tid == 0) S.owner = kPar ? ph_find_dev(J.ph, piv.idx) : ph_find(J.ph, piv.idx);
         if (tid == kWave) S.appv = J.app.keys ? pair_find(J.app, piv.idx) : -1;
         __syncthreads();
+        if (kPar && S.owner < 0 && S.appv < 0) {
+            // free pivot: final once no column before can still take it
+            result = par_wait<BT>(J, S, j, __float_as_uint(piv.diam));
+            if (result) break;
+            if (tid == 0) S.owner = ph_find_dev(J.ph, piv.idx);
+            __syncthreads();
+        }
         RED_T1(S, 11, t_own);
         const int64_t o = S.owner;
+        if (kPar && o >= j) {
+            result = kRedBound; // only a column before j can own a pivot j looks up
+            break;
+        }
+        if (kPar && o >= 0) fence_acquire_dev(); // the owner's published column
         if (o >= 0) {
             // R_j -= lambda R_o (and V_j -= lambda V_o), lambda = piv / pivot(R_o)
-            const u32 lam = (u32)((u64)piv.coef * J.inv[J.V.pivcoef[o]] % p);
+            // over Z/2 every nonzero entry is 1: no lookup
+            const u32 lam = p == 2 ? 1u : (u32)((u64)piv.coef * J.V.pivcoef[o] % p);
             const u32 neg = (p - lam) % p;
             const int vlen = J.V.len[o];
             const int rlen = J.V.rlen[o];
@@ -1409,7 +1531,29 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             result = kRedStoreFull;
             break;
         }
-        if (tid == 0) {
+        if (kPar) {
+            // publish V_j, R_j and the bar, then the table entry, then "done"
+            if (tid == 0) {
+                if ((unsigned long long)vn > S.stat[6]) S.stat[6] = vn;
+                J.bars.birth[j] = sdm;
+                J.bars.death[j] = piv.diam;
+                J.bars.bs[j] = piv.diam > sdm ? sidx : -1; // -1: no bar
+                J.bars.ds[j] = piv.idx;
+                if (piv.diam > sdm) S.stat[3] += 1;
+                J.V.pivcoef[j] = J.inv[piv.coef];
+                J.V.off[j] = voff;
+                J.V.len[j] = vn;
+                J.V.roff[j] = roff;
+                J.V.rlen[j] = rn;
+            }
+            fence_release_dev();
+            __syncthreads();
+            if (tid == 0) {
+                ph_insert_dev(J.ph, piv.idx, j);
+                fence_release_dev();
+                st_dev(&J.par.cst[j], kColDone);
+            }
+        } else if (tid == 0) {
             if ((unsigned long long)vn > S.stat[6]) S.stat[6] = vn;
             if (piv.diam > sdm) {
                 if (S.nbars < J.ncols) {
@@ -1422,7 +1566,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
                 S.stat[3] += 1;
             }
             ph_insert(J.ph, piv.idx, j);
-            J.V.pivcoef[j] = piv.coef;
+            J.V.pivcoef[j] = J.inv[piv.coef];
             J.V.off[j] = voff;
             J.V.len[j] = vn;
             J.V.roff[j] = roff;
@@ -1491,9 +1635,12 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
             bool ok = false;
             int64_t tau = kEmpty;
             u32 tcoef = 0;
-            if (valid) {
+            // no probe at all when the first column cannot be emergent (no
+            // zero pivot cofacet, or that cofacet is in an apparent pair)
+            const bool cand = valid && J.cols.j[col] >= 0 && !J.cols.tapp[col];
+            if (__shfl((int)cand, 0, kWave)) {
                 const int j = J.cols.j[col];
-                if (j >= 0 && !J.cols.tapp[col]) {
+                if (cand) {
                     int v[kMaxVerts];
                     decode(J.cols.idx[col], k, c.n, c.B, v);
                     int below;
@@ -1511,7 +1658,7 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
             const int first_bad = bad ? __ffsll((unsigned long long)bad) - 1 : kWave;
             if (lane < first_bad) {
                 ph_insert(J.ph, tau, col);
-                J.V.pivcoef[col] = tcoef;
+                J.V.pivcoef[col] = J.inv[tcoef];
                 J.V.len[col] = -1; // V_col = sigma_col, R_col = its coboundary
                 J.V.off[col] = 0;
                 J.V.rlen[col] = -1;
@@ -1527,7 +1674,7 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
         RED_T1(S, 8, t_em);
         if (!S.full) continue;
         const int j = S.base;
-        status = reduce_one<BT>(J, D, G, SC, j, S);
+        status = reduce_one<BT, Dist, false>(J, D, G, SC, j, S);
         if (tid == 0) S.base = j + 1;
         gsync(); // V_j and the table entry are visible before the next column
     }
@@ -1536,7 +1683,100 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
     return status;
 }
 
+// The same reduction spread over the workgroups of a launch (ParState):
+// each workgroup takes the next column from the cursor and reduces it; a
+// column whose zero pivot cofacet tau is not in a zero apparent pair takes
+// the emergent shortcut when tau is still free after the wait. Bars go to
+// the column's own slot of J.bars (birth simplex -1: none). Returns a result
+// code; on failure the abort flag stops the other workgroups.
+template <int BT, class Dist>
+__device__ __forceinline__ int reduce_columns_par(const ReduceJob<Dist> &J, const LdsCol &D,
+                                                  const Staging &G, const ReduceScratch &SC,
+                                                  RedShared<BT> &S) {
+    const Ctx<Dist> &c = J.c;
+    const int k = J.k;
+    const u32 p = J.p;
+    const int tid = threadIdx.x;
+    wc_clear_all<BT>(D);
+    wc_clear_all<BT>(SC.Vw);
+    if (tid == 0) {
+        S.abort = 0;
+        S.nbars = 0;
+        S.len = 0;
+        S.f = 0;
+        S.gen = 0;
+    }
+    if (tid < 13) S.stat[tid] = 0;
+    if (tid < 16) S.tm[tid] = 0;
+    int status = 0;
+    gsync();
+    RED_T0(t_total);
+    for (;;) {
+        if (tid == 0) {
+            int col = J.ncols;
+            if (ld_dev(&J.par.ctl[kCtlAbort]) == 0) col = (int)min(atomicAdd(&J.par.ctl[kCtlNext], 1u), (u32)J.ncols);
+            S.cur = col;
+            S.m = 0;
+            if (col < J.ncols && J.cols.j[col] >= 0 && !J.cols.tapp[col]) {
+                // emergent candidate: tau = sigma u {j}, at sigma's diameter
+                int v[kMaxVerts];
+                decode(J.cols.idx[col], k, c.n, c.B, v);
+                int below;
+                S.tau = cofacet_index(v, k, J.cols.j[col], c.B, &below);
+                S.tcoef = coeff_sign(below, p);
+                S.m = 1;
+                st_dev(&J.par.cst[col], __float_as_uint(J.cols.diam[col]));
+            }
+        }
+        __syncthreads();
+        const int col = S.cur;
+        const int emerg = S.m;
+        __syncthreads();
+        if (col >= J.ncols) break;
+        if (emerg) {
+            RED_T0(t_em);
+            status = par_wait<BT>(J, S, col, __float_as_uint(J.cols.diam[col]));
+            if (status) break;
+            if (tid == 0) S.owner = ph_find_dev(J.ph, S.tau);
+            __syncthreads();
+            const bool free = S.owner < 0;
+            if (free) {
+                // V_col = sigma_col, R_col = its coboundary; zero persistence
+                if (tid == 0) {
+                    J.V.pivcoef[col] = J.inv[S.tcoef];
+                    J.V.len[col] = -1;
+                    J.V.off[col] = 0;
+                    J.V.rlen[col] = -1;
+                    J.V.roff[col] = 0;
+                    J.bars.bs[col] = -1;
+                    S.stat[0] += 1;
+                }
+                fence_release_dev();
+                __syncthreads();
+                if (tid == 0) {
+                    ph_insert_dev(J.ph, S.tau, col);
+                    fence_release_dev();
+                    st_dev(&J.par.cst[col], kColDone);
+                }
+            }
+            __syncthreads();
+            RED_T1(S, 8, t_em);
+            if (free) continue;
+        }
+        status = reduce_one<BT, Dist, true>(J, D, G, SC, col, S);
+        if (status) break;
+    }
+    if (status && status != kRedAbort && tid == 0) st_dev(&J.par.ctl[kCtlAbort], 1u);
+    __syncthreads();
+    RED_T1(S, 10, t_total);
+    return status;
+}
+
 hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceBuffers RB, Scalars *s,
                          hipStream_t st);
+// J.bars: one slot per column; the bars are compacted into `out` in column
+// order and s->nbars set
+hipError_t launch_reduce_par(const ReduceJob<DistFull> &J, u32 capD, ReduceBuffers RB, int groups,
+                             BarBuf out, Scalars *s, hipStream_t st);
 
 } // namespace rips

@@ -143,3 +143,28 @@ def test_simplex_counts(cfg, top):
     ref = oracle.barcode(x, max_dim=top - 1, threshold=c["threshold"], p=2)
     got = rips().simplex_counts(torch.from_numpy(x).cuda(), top, threshold=c["threshold"])
     assert got == ref.counts
+
+
+@pytest.mark.parametrize("cfg", [2, 3])
+def test_reduce_workgroups_agree(cfg):
+    """The reduction spread over workgroups (several counts, so that columns
+    wait on each other in different interleavings) gives the oracle's bars
+    and the same counters as the one-workgroup reduction."""
+    c = workloads.config(cfg)
+    x = c["clouds"][0]
+    ref = oracle.barcode(x, max_dim=c["max_dim"], threshold=c["threshold"], p=c["p"])
+    r = rips()
+    base = None
+    try:
+        for g in (1, 2, 7, 64, 0):
+            print(f"[case] config {cfg} {c['name']} reduce workgroups {g}", flush=True)
+            r.set_reduce_workgroups(g)
+            assert r.get_reduce_workgroups() == g
+            got = r.barcode(x, max_dim=c["max_dim"], threshold=c["threshold"], p=c["p"])
+            assert_same(got, ref, c["max_dim"], tag=f"{c['name']} workgroups={g}")
+            if base is None:
+                base = got
+            for k in range(1, c["max_dim"] + 1):
+                assert got.stats[k] == base.stats[k], (g, k, got.stats[k], base.stats[k])
+    finally:
+        r.set_reduce_workgroups(0)
