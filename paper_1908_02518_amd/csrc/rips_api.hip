@@ -881,10 +881,11 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             fprintf(stderr,
                     "[rips reduce d%d] ms (clock %d kHz): total %.2f setup %.2f pivot %.2f "
                     "owner %.2f add %.2f apparent %.2f store %.2f reset %.2f emergent %.2f | "
-                    "merge %.2f (gather %.2f rank %.2f base %.2f prefix %.2f) pull %.2f split %.2f\n",
+                    "merge %.2f (gather %.2f rank %.2f base %.2f prefix %.2f) pull %.2f split %.2f "
+                    "apparent-add %.2f wait %.2f apparent-run %.2f (summed over %lld workgroups)\n",
                     k, khz, T[10] * f, T[6] * f, T[0] * f, T[11] * f, T[1] * f, T[7] * f,
                     T[5] * f, T[9] * f, T[8] * f, T[2] * f, T[12] * f, T[13] * f, T[14] * f,
-                    T[15] * f, T[3] * f, T[4] * f);
+                    T[15] * f, T[3] * f, T[4] * f, T[16] * f, T[17] * f, T[18] * f, (long long)groups);
         }
         o.count[k] = C.host_scal->nbars;
         o.stats[k].emergent = (int64_t)C.host_scal->stat[kStatEmergent];

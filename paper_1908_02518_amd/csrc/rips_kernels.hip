@@ -725,7 +725,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 c
         s->stat[kStatSplits] += S.stat[10];
         s->stat[kStatPulled] += S.stat[11];
         s->stat[kStatAdded] += S.stat[12];
-        for (int q = 0; q < 16; ++q) s->stat[kStatTime + q] += S.tm[q];
+        for (int q = 0; q < kRedTimers; ++q) s->stat[kStatTime + q] += S.tm[q];
     }
 }
 
@@ -773,7 +773,7 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce_par(ReduceJob<Dist> J, u
         atomicAdd(&s->stat[kStatSplits], S.stat[10]);
         atomicAdd(&s->stat[kStatPulled], S.stat[11]);
         atomicAdd(&s->stat[kStatAdded], S.stat[12]);
-        for (int q = 0; q < 16; ++q) atomicAdd(&s->stat[kStatTime + q], S.tm[q]);
+        for (int q = 0; q < kRedTimers; ++q) atomicAdd(&s->stat[kStatTime + q], S.tm[q]);
     }
 }
 

@@ -23,8 +23,8 @@ enum {
     kStatSplits,     // sorted-base splits into the far list
     kStatPulled,     // far-list entries scanned by pulls
     kStatAdded,      // entries added to working columns
-    kStatTime,       // 16 phase timers of the reduction (wall-clock ticks)
-    kNumStats = kStatTime + 16
+    kStatTime,       // kRedTimers phase timers of the reduction (wall-clock ticks)
+    kNumStats = kStatTime + 20
 };
 
 // Device scalars of one call; read back by the host after a dimension ends.

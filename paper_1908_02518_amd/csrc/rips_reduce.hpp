@@ -288,6 +288,8 @@ struct ReduceJob {
     ParState par;               // reduction spread over workgroups (cst null: one workgroup)
 };
 
+constexpr int kRedTimers = 20;
+
 // Shared state of the routine (one per workgroup).
 template <int BT>
 struct RedShared {
@@ -303,6 +305,7 @@ struct RedShared {
     int64_t tau;    // spread-out reduction: emergent candidate
     u32 tcoef, pub; // its coefficient; diameter bits published for this column
     int wbad, wopen, wstop;
+    int fa_n, fa_r; // apparent steps of wave 0: additions made, result
     u32 lo, bound;
     int shift;
     unsigned long long vbase;
@@ -311,7 +314,7 @@ struct RedShared {
     int w[BT / kWave + 1];
     u32 mm[2][BT / kWave];
     unsigned long long stat[13];
-    unsigned long long tm[16]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner; merge: gather, rank, base pass, prefix
+    unsigned long long tm[kRedTimers]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner; merge: gather, rank, base pass, prefix; apparent addition, wait
     u32 hist[256];
     // simplices whose coboundaries are added next: vertices, coefficient,
     // diameter, candidate source (vertex with the fewest neighbours, -1 =
@@ -320,6 +323,7 @@ struct RedShared {
     u32 it_coef[BT];
     float it_diam[BT];
     int it_u[BT];
+    int it_start[BT]; // first candidate of the item in the neighbour list
     int it_off[BT + 1];
 };
 
@@ -469,17 +473,17 @@ __device__ __forceinline__ int add_entry_w(const LdsCol &D, const FarList &F, Re
 // is zero; the delta's copies of those keys are zeroed, since their part of
 // the sum is spent. S.spiv = the first live entry with its total, if any.
 template <int BT, class Dist>
-__device__ __forceinline__ void base_advance(const ReduceJob<Dist> &J, const LdsCol &D,
-                                             const SortedBase &SB, u32 p, RedShared<BT> &S) {
+__device__ __forceinline__ PivotCand base_advance(const ReduceJob<Dist> &J, const LdsCol &D,
+                                                  const SortedBase &SB, u32 p, RedShared<BT> &S) {
     (void)J;
-    if (threadIdx.x >= kWave) return;
-    const int lane = lane_id();
-    int64_t f = S.f;
-    const int64_t len = S.len;
     PivotCand out;
     out.idx = kEmpty;
     out.diam = 0.0f;
     out.coef = 0;
+    if (threadIdx.x >= kWave) return out;
+    const int lane = lane_id();
+    int64_t f = S.f;
+    const int64_t len = S.len;
     while (f < len) {
         const int64_t q = f + lane;
         const bool valid = q < len;
@@ -511,6 +515,7 @@ __device__ __forceinline__ void base_advance(const ReduceJob<Dist> &J, const Lds
         S.f = f;
         S.spiv = out;
     }
+    return out; // the same in every lane of wave 0
 }
 
 // Merge the live entries of D into S[f, len) (all threads); D is empty
@@ -980,27 +985,42 @@ __device__ __forceinline__ int add_items(const ReduceJob<Dist> &J, RedShared<BT>
     if (tid < nit) {
         if (c.nb.off == nullptr) {
             S.it_u[tid] = -1;
+            S.it_start[tid] = 0;
             cnt = c.n;
         } else {
             int u = S.it_v[tid][0];
-            int du = c.nb.off[u + 1] - c.nb.off[u];
+            int lo = c.nb.off[u];
+            int du = c.nb.off[u + 1] - lo;
             for (int m = 1; m <= k; ++m) {
                 const int vm = S.it_v[tid][m];
-                const int dd = c.nb.off[vm + 1] - c.nb.off[vm];
+                const int lm = c.nb.off[vm];
+                const int dd = c.nb.off[vm + 1] - lm;
                 if (dd < du) {
                     du = dd;
                     u = vm;
+                    lo = lm;
                 }
             }
             S.it_u[tid] = u;
+            S.it_start[tid] = lo;
             cnt = du;
         }
     }
     int total;
-    const int off = block_scan_excl<BT>(cnt, S.w, &total);
-    if (tid < nit) S.it_off[tid] = off;
-    if (tid == 0) S.it_off[nit] = total;
-    __syncthreads();
+    if (nit == 1) {
+        // one item (an apparent facet, a single simplex): no scan
+        if (tid == 0) {
+            S.it_off[0] = 0;
+            S.it_off[1] = cnt;
+        }
+        __syncthreads();
+        total = S.it_off[1];
+    } else {
+        const int off = block_scan_excl<BT>(cnt, S.w, &total);
+        if (tid < nit) S.it_off[tid] = off;
+        if (tid == 0) S.it_off[nit] = total;
+        __syncthreads();
+    }
     const int seg = ((int)D.mask + 1) / 8;
     for (int s0 = 0; s0 < total; s0 += seg) {
         const int s1 = min(total, s0 + seg);
@@ -1022,7 +1042,7 @@ __device__ __forceinline__ int add_items(const ReduceJob<Dist> &J, RedShared<BT>
                 const int it = lo;
                 const int q = fl - S.it_off[it];
                 const int u = S.it_u[it];
-                const int j = u < 0 ? q : c.nb.idx[c.nb.off[u] + q];
+                const int j = u < 0 ? q : c.nb.idx[S.it_start[it] + q];
                 const int *v = S.it_v[it];
                 bool in = false;
                 nd = S.it_diam[it];
@@ -1229,6 +1249,126 @@ __device__ __forceinline__ bool materialize_v(const ReduceJob<Dist> &J, const Re
     return res;
 }
 
+// Steps of the reduction of column j taken by wave 0 alone, without
+// workgroup barriers, while the pivot tau lies in a zero apparent pair
+// (rho, tau) recorded by the filter: R_j -= lambda coboundary(rho), the same
+// addition the general step makes there (such a tau is never in the pivot
+// table). It stops, leaving the pivot to the general step, at a pivot that
+// is not such a tau, at an empty near part, at a coboundary that does not
+// fit the delta before its next maintenance, once that maintenance is due,
+// or after `budget` additions. Returns the additions made (the same in every
+// lane); *res gets 0 or a result code.
+template <int BT, class Dist, bool kPar>
+__device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsCol &D,
+                                            const ReduceScratch &SC, int j, int budget,
+                                            RedShared<BT> &S, int *res) {
+    const Ctx<Dist> &c = J.c;
+    const int k = J.k;
+    const u32 p = J.p;
+    const int lane = lane_id();
+    const int capD = (int)D.mask + 1;
+    int nadd = 0;
+    *res = kRedOk;
+    while (nadd < budget) {
+        const int ns0 = min(*D.nslots, capD);
+        if (ns0 > capD / 8) break; // maintenance due
+        const PivotCand smin = base_advance<BT>(J, D, SC.SB, p, S);
+        PivotCand best;
+        best.idx = kEmpty;
+        best.diam = 0.0f;
+        best.coef = 0;
+        const int ns = min(*D.nslots, capD);
+        for (int i = lane; i < ns; i += kWave) {
+            const u32 sl = D.slots[i];
+            u32 cf = ld(&D.coef[sl]);
+            if (p != 2 && cf >= p) {
+                cf %= p;
+                st(&D.coef[sl], cf);
+            }
+            if (cf == 0) continue;
+            PivotCand x;
+            x.idx = ld(&D.keys[sl]);
+            x.diam = D.diam[sl];
+            x.coef = cf;
+            if (older(x, best)) best = x;
+        }
+        const PivotCand dmin = wave_oldest(best);
+        const bool from_base = smin.idx != kEmpty &&
+                               (dmin.idx == kEmpty || dmin.idx == smin.idx || !older(dmin, smin));
+        const PivotCand piv = from_base ? smin : dmin;
+        if (piv.idx == kEmpty) break;
+        if (kPar && lane == 0 && __float_as_uint(piv.diam) > S.pub) {
+            S.pub = __float_as_uint(piv.diam);
+            st_dev(&J.par.cst[j], S.pub);
+        }
+        int64_t a = -1;
+        if (lane == 0) a = pair_find(J.app, piv.idx);
+        a = __shfl(a, 0, kWave);
+        if (a < 0) break;
+        // rho's vertices, and the candidate source: its vertex with the
+        // fewest neighbours (all vertices when dense)
+        int rv[kMaxVerts];
+        decode(a >> 3, k, c.n, c.B, rv);
+        int u = -1, lo = 0, du = c.n;
+        if (c.nb.off != nullptr) {
+            u = rv[0];
+            lo = c.nb.off[u];
+            du = c.nb.off[u + 1] - lo;
+            for (int m = 1; m <= k; ++m) {
+                const int lm = c.nb.off[rv[m]];
+                const int dd = c.nb.off[rv[m] + 1] - lm;
+                if (dd < du) {
+                    du = dd;
+                    u = rv[m];
+                    lo = lm;
+                }
+            }
+        }
+        if (ns + du > capD / 4) break; // more than the delta takes before its maintenance
+        // tau = rho u {tau[m]}; vertices of rho below tau[m]: k + 1 - m
+        const int m = (int)(a & 7);
+        const u32 lam = p == 2 ? 1u : (u32)((u64)piv.coef * J.inv[coeff_sign(k + 1 - m, p)] % p);
+        const u32 neg = (p - lam) % p;
+        int bad = 0;
+        if (lane == 0 && !log_add(SC, S, a >> 3, neg, piv.diam, 1)) bad = kRedLogFull;
+        int added = 0;
+        for (int q0 = 0; q0 < du; q0 += kWave) {
+            const int q = q0 + lane;
+            bool act = q < du;
+            int64_t ci = 0;
+            float nd = 0.0f;
+            u32 cc = 0;
+            if (act) {
+                const int jv = u < 0 ? q : c.nb.idx[lo + q];
+                bool in = false;
+                nd = piv.diam;
+                for (int mm = 0; mm <= k; ++mm) {
+                    in = in || (jv == rv[mm]);
+                    nd = fmaxf(nd, c.d(rv[mm], jv));
+                }
+                act = !in && nd <= c.t;
+                if (act) {
+                    int below;
+                    ci = cofacet_index(rv, k, jv, c.B, &below);
+                    cc = (below & 1) ? (p - neg) % p : neg;
+                }
+            }
+            added += __popcll(__ballot(act));
+            const int rr = add_entry_w<BT>(D, SC.F, S, act, ci, nd, cc, p);
+            if (rr) bad = rr;
+        }
+        if (lane == 0) S.stat[12] += (unsigned long long)added;
+        ++nadd;
+        // a failure in any lane ends the run
+        const u64 fail = __ballot(bad != 0);
+        if (fail) {
+            *res = __shfl(bad, __ffsll((unsigned long long)fail) - 1, kWave);
+            break;
+        }
+    }
+    return nadd;
+}
+
 // Block-wide minimum of two values (all threads; every thread gets both).
 template <int BT>
 __device__ __forceinline__ void block_min2(int &a, int &b, RedShared<BT> &S) {
@@ -1337,6 +1477,29 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             result = kRedBound;
             break;
         }
+        if (J.app.keys != nullptr) {
+            // the run of pivots in zero apparent pairs, by wave 0 alone
+            RED_T0(t_fast);
+            if (w == 0) {
+                int r;
+                const int na = apparent_run<BT, Dist, kPar>(J, D, SC, j, (1 << 18) + 1 - nadd, S, &r);
+                if (lane == 0) {
+                    S.fa_n = na;
+                    S.fa_r = r;
+                }
+            }
+            __syncthreads();
+            const int na = S.fa_n;
+            result = S.fa_r;
+            RED_T1(S, 18, t_fast);
+            if (result) break;
+            nadd += na;
+            if (na > 0) {
+                result = delta_check<BT>(D, G, SC, p, S);
+                if (result) break;
+                __syncthreads();
+            }
+        }
         PivotCand piv;
         bool from_base = false;
         RED_T0(t_piv);
@@ -1386,12 +1549,16 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         }
         RED_T0(t_own);
         // pivot table and apparent-pair table, read by two waves at once
-        if (tid == 0) S.owner = kPar ? ph_find_dev(J.ph, piv.idx) : ph_find(J.ph, piv.idx);
+        // (spread out: a cached copy can only miss an entry, and a miss is
+        // checked again below after the wait)
+        if (tid == 0) S.owner = ph_find(J.ph, piv.idx);
         if (tid == kWave) S.appv = J.app.keys ? pair_find(J.app, piv.idx) : -1;
         __syncthreads();
         if (kPar && S.owner < 0 && S.appv < 0) {
             // free pivot: final once no column before can still take it
+            RED_T0(t_w);
             result = par_wait<BT>(J, S, j, __float_as_uint(piv.diam));
+            RED_T1(S, 17, t_w);
             if (result) break;
             if (tid == 0) S.owner = ph_find_dev(J.ph, piv.idx);
             __syncthreads();
@@ -1481,7 +1648,9 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             break;
         }
         if (S.m >= 0) {
+            RED_T0(t_aa);
             result = add_items<BT>(J, S, D, G, SC);
+            RED_T1(S, 16, t_aa);
             ++nadd;
             continue;
         }
@@ -1614,7 +1783,7 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
         S.gen = 0;
     }
     if (tid < 13) S.stat[tid] = 0;
-    if (tid < 16) S.tm[tid] = 0;
+    if (tid < kRedTimers) S.tm[tid] = 0;
     int status = 0;
     gsync();
     RED_T0(t_total);
@@ -1707,7 +1876,7 @@ __device__ __forceinline__ int reduce_columns_par(const ReduceJob<Dist> &J, cons
         S.gen = 0;
     }
     if (tid < 13) S.stat[tid] = 0;
-    if (tid < 16) S.tm[tid] = 0;
+    if (tid < kRedTimers) S.tm[tid] = 0;
     int status = 0;
     gsync();
     RED_T0(t_total);
@@ -1735,7 +1904,9 @@ __device__ __forceinline__ int reduce_columns_par(const ReduceJob<Dist> &J, cons
         if (col >= J.ncols) break;
         if (emerg) {
             RED_T0(t_em);
+            RED_T0(t_w);
             status = par_wait<BT>(J, S, col, __float_as_uint(J.cols.diam[col]));
+            RED_T1(S, 17, t_w);
             if (status) break;
             if (tid == 0) S.owner = ph_find_dev(J.ph, S.tau);
             __syncthreads();
