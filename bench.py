@@ -297,7 +297,8 @@ def main() -> int:
     if dname.startswith("reduce_d"):
         k = int(dname[-1])
         s = stats[k]
-        roofline["note"] = ("sequential column reduction in one workgroup (latency-bound): "
+        roofline["note"] = ("column reduction spread over one workgroup per CU, bound by the "
+                            "latency of the longest chain of dependent additions: "
                             f"{s['columns']} columns, {s['additions']} additions, "
                             f"{s['entries_added']} entries added, {s['entries_stored']} stored")
         roofline["columns_per_s"] = round(s["columns"] / (roofline["avg_launch_us"] * 1e-6), 1)
