@@ -43,6 +43,8 @@ enum BufId {
     B_BW_BINOM, // binomial table of the backward entry
     B_APP_KEYS, // zero apparent pairs of the current dimension
     B_APP_VALS,
+    B_APP_VERTS, // rho's vertices, per slot
+    B_APP_NBR,   // rho's shortest neighbour list, per slot
     B_INV,
     B_SCAL,
     B_E_IDX,
@@ -679,6 +681,10 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         app.keys = as<int64_t>(q);
         HIP_TRY(C.ensure(B_APP_VALS, (size_t)appcap * 8, &q));
         app.vals = as<int64_t>(q);
+        HIP_TRY(C.ensure(B_APP_VERTS, (size_t)appcap * 8, &q));
+        app.verts = as<u64>(q);
+        HIP_TRY(C.ensure(B_APP_NBR, (size_t)appcap * 8, &q));
+        app.nbr = as<u64>(q);
         app.mask = appcap - 1;
         launch_fill_i64(app.keys, appcap, kEmpty, st);
         {
@@ -882,10 +888,12 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
                     "[rips reduce d%d] ms (clock %d kHz): total %.2f setup %.2f pivot %.2f "
                     "owner %.2f add %.2f apparent %.2f store %.2f reset %.2f emergent %.2f | "
                     "merge %.2f (gather %.2f rank %.2f base %.2f prefix %.2f) pull %.2f split %.2f "
-                    "apparent-add %.2f wait %.2f apparent-run %.2f (summed over %lld workgroups)\n",
+                    "apparent-add %.2f wait %.2f apparent-run %.2f (pivot %.2f lookup %.2f add %.2f) "
+                    "(summed over %lld workgroups)\n",
                     k, khz, T[10] * f, T[6] * f, T[0] * f, T[11] * f, T[1] * f, T[7] * f,
                     T[5] * f, T[9] * f, T[8] * f, T[2] * f, T[12] * f, T[13] * f, T[14] * f,
-                    T[15] * f, T[3] * f, T[4] * f, T[16] * f, T[17] * f, T[18] * f, (long long)groups);
+                    T[15] * f, T[3] * f, T[4] * f, T[16] * f, T[17] * f, T[18] * f, T[19] * f, T[20] * f, T[21] * f,
+                    (long long)groups);
         }
         o.count[k] = C.host_scal->nbars;
         o.stats[k].emergent = (int64_t)C.host_scal->stat[kStatEmergent];

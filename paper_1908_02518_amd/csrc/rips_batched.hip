@@ -457,7 +457,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         SC.ldia = A.log_dia + (int64_t)wg * A.log_stride;
         SC.lcap = A.log_stride;
         J.cand_avg = (float)n;
-        J.app = PairHash{nullptr, nullptr, 0};
+        J.app = PairHash{nullptr, nullptr, nullptr, nullptr, 0};
         gsync();
         const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, RS);
         if (rstat && tid == 0) {

@@ -433,30 +433,72 @@ __device__ __forceinline__ bool ph_insert_dev(const PivotHash &h, int64_t key, i
 // tau -> (rho << 3) | m, m = position in tau's decreasing vertex list of the
 // vertex tau adds to rho. Sized at twice the candidates, so inserts never
 // fail; the reduction then finds whether its pivot is such a tau with one
-// lookup.
+// lookup. Beside the value, each slot keeps what the addition of rho's
+// coboundary needs next, so that it costs no further dependent load: rho's
+// vertices (decreasing, 16 bits each; kNoVerts when n > 65536) and, with
+// neighbour lists, the list of rho's vertex with the fewest neighbours
+// (first entry << 32 | length).
+constexpr u64 kNoVerts = ~0ull;
+
 struct PairHash {
     int64_t *keys; // kEmpty when free; null = no table
     int64_t *vals;
+    u64 *verts;
+    u64 *nbr;
     u32 mask;
 };
 
+// Everything a slot holds for a key (val -1: not there).
+struct PairHit {
+    int64_t val;
+    u64 verts, nbr;
+};
+
+__device__ __forceinline__ PairHit pair_find_all(const PairHash &h, int64_t key) {
+    u32 s = mix64((u64)key) & h.mask;
+    PairHit r{-1, kNoVerts, 0};
+    for (u32 probe = 0; probe <= h.mask; ++probe) {
+        // the slot's words are loaded together: one round trip per probe
+        const int64_t cur = h.keys[s];
+        const int64_t v = h.vals[s];
+        const u64 w = h.verts[s];
+        const u64 nb = h.nbr[s];
+        if (cur == key) {
+            r.val = v;
+            r.verts = w;
+            r.nbr = nb;
+            return r;
+        }
+        if (cur == kEmpty) return r;
+        s = (s + 1) & h.mask;
+    }
+    return r;
+}
+
+// The table is read-only while the reduction runs (the filter, an earlier
+// kernel, wrote it), so plain loads serve, and the value is loaded with the
+// key.
 __device__ __forceinline__ int64_t pair_find(const PairHash &h, int64_t key) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
-        const int64_t cur = ld(&h.keys[s]);
-        if (cur == key) return ld(&h.vals[s]);
+        const int64_t cur = h.keys[s];
+        const int64_t v = h.vals[s];
+        if (cur == key) return v;
         if (cur == kEmpty) return -1;
         s = (s + 1) & h.mask;
     }
     return -1;
 }
 
-__device__ __forceinline__ bool pair_insert(const PairHash &h, int64_t key, int64_t val) {
+__device__ __forceinline__ bool pair_insert(const PairHash &h, int64_t key, int64_t val, u64 verts,
+                                            u64 nbr) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
         const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
         if (prev == (u64)kEmpty || prev == (u64)key) {
-            st(&h.vals[s], val);
+            h.vals[s] = val;
+            h.verts[s] = verts;
+            h.nbr[s] = nbr;
             return true;
         }
         s = (s + 1) & h.mask;

@@ -628,7 +628,25 @@ __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, int k, SimplexList 
                 int tv[kMaxVerts];
                 const int pos = insert_vertex(v, k, j, tv);
                 // capacity is twice the candidates: the insert cannot fail
-                (void)pair_insert(app, simplex_index(tv, k + 1, c.B), (idx << 3) | pos);
+                u64 packed = kNoVerts;
+                if (c.n <= 65536) {
+                    packed = 0;
+                    for (int q = 0; q <= k; ++q) packed |= (u64)(u32)v[q] << (16 * q);
+                }
+                u64 nbr = 0;
+                if (c.nb.off != nullptr) {
+                    int lo = c.nb.off[v[0]], du = c.nb.off[v[0] + 1] - lo;
+                    for (int q = 1; q <= k; ++q) {
+                        const int lq = c.nb.off[v[q]];
+                        const int dq = c.nb.off[v[q] + 1] - lq;
+                        if (dq < du) {
+                            du = dq;
+                            lo = lq;
+                        }
+                    }
+                    nbr = ((u64)(u32)lo << 32) | (u32)du;
+                }
+                (void)pair_insert(app, simplex_index(tv, k + 1, c.B), (idx << 3) | pos, packed, nbr);
             }
             continue;
         }

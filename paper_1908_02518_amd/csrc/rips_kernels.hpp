@@ -24,7 +24,7 @@ enum {
     kStatPulled,     // far-list entries scanned by pulls
     kStatAdded,      // entries added to working columns
     kStatTime,       // kRedTimers phase timers of the reduction (wall-clock ticks)
-    kNumStats = kStatTime + 20
+    kNumStats = kStatTime + 24
 };
 
 // Device scalars of one call; read back by the host after a dimension ends.

@@ -288,7 +288,7 @@ struct ReduceJob {
     ParState par;               // reduction spread over workgroups (cst null: one workgroup)
 };
 
-constexpr int kRedTimers = 20;
+constexpr int kRedTimers = 24;
 
 // Shared state of the routine (one per workgroup).
 template <int BT>
@@ -314,7 +314,7 @@ struct RedShared {
     int w[BT / kWave + 1];
     u32 mm[2][BT / kWave];
     unsigned long long stat[13];
-    unsigned long long tm[kRedTimers]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner; merge: gather, rank, base pass, prefix; apparent addition, wait
+    unsigned long long tm[kRedTimers]; // wall-clock ticks: pivot, add, merge, pull, split, store, setup, apparent, emergent, reset, total, owner; merge: gather, rank, base pass, prefix; apparent addition, wait, apparent run; its pivot search, table lookup, coboundary
     u32 hist[256];
     // simplices whose coboundaries are added next: vertices, coefficient,
     // diameter, candidate source (vertex with the fewest neighbours, -1 =
@@ -1262,9 +1262,15 @@ template <int BT, class Dist, bool kPar>
 __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsCol &D,
                                             const ReduceScratch &SC, int j, int budget,
                                             RedShared<BT> &S, int *res) {
-    const Ctx<Dist> &c = J.c;
+    // values, not references into the job: read once per run and kept in
+    // registers (the job itself lives in scratch memory)
+    const Ctx<Dist> c = J.c;
+    const PairHash app = J.app;
     const int k = J.k;
     const u32 p = J.p;
+    const u32 *inv = J.inv;
+    const FarList F = SC.F;
+    const SortedBase SB = SC.SB;
     const int lane = lane_id();
     const int capD = (int)D.mask + 1;
     int nadd = 0;
@@ -1272,7 +1278,8 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
     while (nadd < budget) {
         const int ns0 = min(*D.nslots, capD);
         if (ns0 > capD / 8) break; // maintenance due
-        const PivotCand smin = base_advance<BT>(J, D, SC.SB, p, S);
+        RED_T0(t_r0);
+        const PivotCand smin = base_advance<BT>(J, D, SB, p, S);
         PivotCand best;
         best.idx = kEmpty;
         best.diam = 0.0f;
@@ -1301,33 +1308,32 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
             S.pub = __float_as_uint(piv.diam);
             st_dev(&J.par.cst[j], S.pub);
         }
-        int64_t a = -1;
-        if (lane == 0) a = pair_find(J.app, piv.idx);
-        a = __shfl(a, 0, kWave);
+        RED_T1(S, 19, t_r0);
+        RED_T0(t_r1);
+        PairHit hit{-1, kNoVerts, 0};
+        if (lane == 0) hit = pair_find_all(app, piv.idx);
+        const int64_t a = __shfl(hit.val, 0, kWave);
+        RED_T1(S, 20, t_r1);
         if (a < 0) break;
-        // rho's vertices, and the candidate source: its vertex with the
-        // fewest neighbours (all vertices when dense)
+        RED_T0(t_r2);
+        const u64 vw = (u64)__shfl((long long)hit.verts, 0, kWave);
+        const u64 nbw = (u64)__shfl((long long)hit.nbr, 0, kWave);
+        // rho's vertices, and the candidate source: the neighbour list of its
+        // vertex with the fewest neighbours (all vertices when dense), both
+        // from the table slot
         int rv[kMaxVerts];
-        decode(a >> 3, k, c.n, c.B, rv);
-        int u = -1, lo = 0, du = c.n;
-        if (c.nb.off != nullptr) {
-            u = rv[0];
-            lo = c.nb.off[u];
-            du = c.nb.off[u + 1] - lo;
-            for (int m = 1; m <= k; ++m) {
-                const int lm = c.nb.off[rv[m]];
-                const int dd = c.nb.off[rv[m] + 1] - lm;
-                if (dd < du) {
-                    du = dd;
-                    u = rv[m];
-                    lo = lm;
-                }
-            }
+        if (vw != kNoVerts) {
+            for (int q = 0; q <= k; ++q) rv[q] = (int)((vw >> (16 * q)) & 0xffffu);
+        } else {
+            decode(a >> 3, k, c.n, c.B, rv);
         }
+        const int u = c.nb.off == nullptr ? -1 : 0;
+        const int lo = u < 0 ? 0 : (int)(nbw >> 32);
+        const int du = u < 0 ? c.n : (int)(u32)nbw;
         if (ns + du > capD / 4) break; // more than the delta takes before its maintenance
         // tau = rho u {tau[m]}; vertices of rho below tau[m]: k + 1 - m
         const int m = (int)(a & 7);
-        const u32 lam = p == 2 ? 1u : (u32)((u64)piv.coef * J.inv[coeff_sign(k + 1 - m, p)] % p);
+        const u32 lam = p == 2 ? 1u : (u32)((u64)piv.coef * inv[coeff_sign(k + 1 - m, p)] % p);
         const u32 neg = (p - lam) % p;
         int bad = 0;
         if (lane == 0 && !log_add(SC, S, a >> 3, neg, piv.diam, 1)) bad = kRedLogFull;
@@ -1354,10 +1360,11 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
                 }
             }
             added += __popcll(__ballot(act));
-            const int rr = add_entry_w<BT>(D, SC.F, S, act, ci, nd, cc, p);
+            const int rr = add_entry_w<BT>(D, F, S, act, ci, nd, cc, p);
             if (rr) bad = rr;
         }
         if (lane == 0) S.stat[12] += (unsigned long long)added;
+        RED_T1(S, 21, t_r2);
         ++nadd;
         // a failure in any lane ends the run
         const u64 fail = __ballot(bad != 0);
