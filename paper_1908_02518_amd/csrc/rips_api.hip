@@ -138,6 +138,9 @@ enum BufId {
     BB_S_V1,
     BB_PH_KEYS,
     BB_PH_VALS,
+    BB_APP_KEYS,
+    BB_APP_VALS,
+    BB_APP_VERTS,
     BB_V_OFF,
     BB_V_LEN,
     BB_V_PIV,
@@ -987,6 +990,9 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     ENS(BB_PH_KEYS, G * ph_stride * 8, A.ph_keys, int64_t);
     ENS(BB_PH_VALS, G * ph_stride * 4, A.ph_vals, int32_t);
     A.ph_stride = ph_stride;
+    ENS(BB_APP_KEYS, G * ph_stride * 8, A.app_keys, int64_t);
+    ENS(BB_APP_VALS, G * ph_stride * 8, A.app_vals, int64_t);
+    ENS(BB_APP_VERTS, G * ph_stride * 8, A.app_verts, u64);
     ENS(BB_V_OFF, G * col_stride * 8, A.v_off, int64_t);
     ENS(BB_V_LEN, G * col_stride * 4, A.v_len, int);
     ENS(BB_V_PIV, G * col_stride * 4, A.v_piv, u32);

@@ -344,6 +344,14 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         Columns surv{A.c_idx0 + (int64_t)wg * A.col_stride, A.c_dm0 + (int64_t)wg * A.col_stride,
                      A.c_j0 + (int64_t)wg * A.col_stride, A.c_t0 + (int64_t)wg * A.col_stride};
         const int lg = tid & (kBatchG - 1);
+        // the zero apparent pairs (rho, tau) found here serve the reduction's
+        // pivot tests (one lookup instead of facet and cofacet scans)
+        u32 appcap = 64;
+        while (appcap < 2u * (u32)npairs + 64u && (int64_t)appcap < A.ph_stride) appcap <<= 1;
+        const PairHash app{A.app_keys + (int64_t)wg * A.ph_stride, A.app_vals + (int64_t)wg * A.ph_stride,
+                           A.app_verts + (int64_t)wg * A.ph_stride, nullptr, appcap - 1};
+        for (u32 q = tid; q < appcap; q += kBT) app.keys[q] = kEmpty;
+        gsync();
         unsigned long long n_clear = 0, n_acol = 0, n_cand = 0;
         for (int64_t e = tid / kBatchG; e < npairs; e += kBT / kBatchG) {
             int v[kMaxVerts];
@@ -358,6 +366,13 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
             const int j = group_find_max<kBatchG>(c, v, 1, dm, -1);
             if (j >= 0 && is_zero_apparent_cofacet(c, v, 1, dm, j)) {
                 n_acol += (lg == 0);
+                if (lg == 0) {
+                    int tv[kMaxVerts];
+                    const int pos = insert_vertex(v, 1, j, tv);
+                    // capacity is at least twice the pairs: the insert cannot fail
+                    (void)pair_insert(app, simplex_index(tv, 2, c.B), (e << 3) | pos,
+                                      (u64)(u32)v[0] | ((u64)(u32)v[1] << 16), 0);
+                }
                 continue;
             }
             uint8_t tapp = 0;
@@ -457,7 +472,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         SC.ldia = A.log_dia + (int64_t)wg * A.log_stride;
         SC.lcap = A.log_stride;
         J.cand_avg = (float)n;
-        J.app = PairHash{nullptr, nullptr, nullptr, nullptr, 0};
+        J.app = app;
         gsync();
         const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, RS);
         if (rstat && tid == 0) {

@@ -33,6 +33,9 @@ struct BatchArgs {
     int64_t *ph_keys;
     int32_t *ph_vals;
     int64_t ph_stride;       // power of two >= 2 C(nmax,2) + 64
+    int64_t *app_keys;       // zero apparent pairs of dimension 1 (PairHash), ph_stride slots
+    int64_t *app_vals;
+    u64 *app_verts;
     int64_t *v_off;
     int *v_len;
     u32 *v_piv;

@@ -437,7 +437,7 @@ __device__ __forceinline__ bool ph_insert_dev(const PivotHash &h, int64_t key, i
 // coboundary needs next, so that it costs no further dependent load: rho's
 // vertices (decreasing, 16 bits each; kNoVerts when n > 65536) and, with
 // neighbour lists, the list of rho's vertex with the fewest neighbours
-// (first entry << 32 | length).
+// (first entry << 32 | length). Either array may be absent (null).
 constexpr u64 kNoVerts = ~0ull;
 
 struct PairHash {
@@ -461,8 +461,8 @@ __device__ __forceinline__ PairHit pair_find_all(const PairHash &h, int64_t key)
         // the slot's words are loaded together: one round trip per probe
         const int64_t cur = h.keys[s];
         const int64_t v = h.vals[s];
-        const u64 w = h.verts[s];
-        const u64 nb = h.nbr[s];
+        const u64 w = h.verts ? h.verts[s] : kNoVerts;
+        const u64 nb = h.nbr ? h.nbr[s] : 0;
         if (cur == key) {
             r.val = v;
             r.verts = w;
@@ -475,9 +475,9 @@ __device__ __forceinline__ PairHit pair_find_all(const PairHash &h, int64_t key)
     return r;
 }
 
-// The table is read-only while the reduction runs (the filter, an earlier
-// kernel, wrote it), so plain loads serve, and the value is loaded with the
-// key.
+// The table is read-only while the reduction runs (the filter wrote it in an
+// earlier kernel, or earlier in the same workgroup behind a barrier), so
+// plain loads serve, and the value is loaded with the key.
 __device__ __forceinline__ int64_t pair_find(const PairHash &h, int64_t key) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
@@ -497,8 +497,8 @@ __device__ __forceinline__ bool pair_insert(const PairHash &h, int64_t key, int6
         const u64 prev = atomicCAS((u64 *)&h.keys[s], (u64)kEmpty, (u64)key);
         if (prev == (u64)kEmpty || prev == (u64)key) {
             h.vals[s] = val;
-            h.verts[s] = verts;
-            h.nbr[s] = nbr;
+            if (h.verts) h.verts[s] = verts;
+            if (h.nbr) h.nbr[s] = nbr;
             return true;
         }
         s = (s + 1) & h.mask;
