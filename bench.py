@@ -20,6 +20,8 @@ per step. Also reported:
   batched           barcodes/s of the 512-cloud mixture batch in one
                     persistent launch vs one cloud at a time
   cpu_baseline      the CPU oracle on this host (a bounded sample)
+  cpu_paper_algorithm  the single-threaded CPU implementation of the paper's
+                    algorithm (cpu_baseline/) on the same cloud, same host
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --summarize-pmc FETCH_DIR WRITE_DIR   (profiles helpers)
@@ -198,7 +200,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="bound on the CPU-oracle sample (seconds)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip both CPU legs (oracle and the paper's algorithm)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter runs: a few steps plus one plain copy of known size")
@@ -216,6 +219,7 @@ def main() -> int:
               file=sys.stderr)
         return 2
 
+    import numpy as np
     import torch
 
     import paper_1908_02518_amd as rips
@@ -371,6 +375,28 @@ def main() -> int:
                "sample": f"the full so3-1000 cloud (same input), {reps} run(s), "
                          f"{el / reps:.3f} s each, single thread"}
 
+    cpu_paper = None
+    if not args.no_cpu_baseline:
+        import cpu_baseline
+        import oracle
+        cpu_baseline.build(force=False)
+        dl = oracle.distances(x)  # the same float32 distances (not timed)
+        reps, el = 0, 0.0
+        while reps == 0 or el < 5.0:
+            c0 = time.perf_counter()
+            cb = cpu_baseline.barcode(dl, n, max_dim=max_dim, threshold=t, p=p)
+            el += time.perf_counter() - c0
+            reps += 1
+        log(f"cpu paper algorithm: {el / reps:.3f} s per barcode ({reps} runs)")
+        same = all(np.array_equal(getattr(cb.bars[d], f), g.cpu().numpy())
+                   for d in range(max_dim + 1)
+                   for f, g in zip(("birth", "death", "birth_simplex", "death_simplex"), bars[d]))
+        cpu_paper = {"value": round(n_simplices / (el / reps), 1), "unit": "simplices/s", "cores": 1,
+                     "kind": "paper algorithm, single thread (cpu_baseline/)",
+                     "sample": f"the full so3-1000 cloud, {reps} run(s), {el / reps:.3f} s each; "
+                               f"distances precomputed",
+                     "bars_equal_gpu": bool(same)}
+
     line = {
         "metric": "simplices/s (one barcode of the so3-1000 workload per step)",
         "value": round(value, 1),
@@ -394,6 +420,7 @@ def main() -> int:
         "eliminated": eliminated,
         "batched": batched,
         "cpu_baseline": cpu,
+        "cpu_paper_algorithm": cpu_paper,
     }
     print(json.dumps(line))
     return 0

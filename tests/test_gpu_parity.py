@@ -168,3 +168,24 @@ def test_reduce_workgroups_agree(cfg):
                 assert got.stats[k] == base.stats[k], (g, k, got.stats[k], base.stats[k])
     finally:
         r.set_reduce_workgroups(0)
+
+
+SPREAD = [c for c in SMALL if c[0] in ("cube-30x3-p5", "cube-24x4-dim3", "lattice-30x3-dups-p3",
+                                       "cube-300x3-sparse-p3", "torus-500-sparse", "so3-300")]
+
+
+@pytest.mark.parametrize("name,make,max_dim,t,p", SPREAD, ids=[c[0] for c in SPREAD])
+def test_reduce_workgroups_small(name, make, max_dim, t, p):
+    """Few workgroups (2 and 3) make columns wait on each other most often;
+    ties, duplicate points, Z/3 and Z/5 and dimension 3 included."""
+    x = make()
+    ref = oracle.barcode(x, max_dim=max_dim, threshold=t, p=p)
+    r = rips()
+    try:
+        for g in (2, 3):
+            print(f"[case] {name} reduce workgroups {g}", flush=True)
+            r.set_reduce_workgroups(g)
+            got = r.barcode(x, max_dim=max_dim, threshold=t, p=p)
+            assert_same(got, ref, max_dim, tag=f"{name} workgroups={g}")
+    finally:
+        r.set_reduce_workgroups(0)
