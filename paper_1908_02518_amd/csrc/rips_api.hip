@@ -45,6 +45,9 @@ enum BufId {
     B_APP_VALS,
     B_APP_VERTS, // rho's vertices, per slot
     B_APP_NBR,   // rho's shortest neighbour list, per slot
+    B_APP_COB,   // rho's coboundary list, per slot
+    B_COB_KEY,   // the coboundary lists
+    B_COB_DIA,
     B_INV,
     B_SCAL,
     B_E_IDX,
@@ -200,6 +203,7 @@ struct DevCtx {
     int64_t hint_far = 0;
     int64_t hint_vw = 0;
     int64_t hint_log = 0;
+    int64_t hint_cob = 0;
     int lds_per_block = 0;
     int num_cus = 0;
     int reduce_groups = 0; // workgroups of the single-cloud reduction: 0 = one per CU
@@ -326,7 +330,8 @@ enum ProfId {
     P_FILTER1 = P_EXPAND1 + kMaxDim + 1,
     P_SORT1 = P_FILTER1 + kMaxDim,
     P_REDUCE1 = P_SORT1 + kMaxDim,
-    P_EMIT = P_REDUCE1 + kMaxDim,
+    P_COB1 = P_REDUCE1 + kMaxDim,
+    P_EMIT = P_COB1 + kMaxDim,
     P_BATCHED,
     P_NUM
 };
@@ -347,6 +352,7 @@ const char *prof_name(int i) {
             snprintf(names[P_FILTER1 + k - 1], 32, "filter_d%d", k);
             snprintf(names[P_SORT1 + k - 1], 32, "sort_d%d", k);
             snprintf(names[P_REDUCE1 + k - 1], 32, "reduce_d%d", k);
+            snprintf(names[P_COB1 + k - 1], 32, "cob_lists_d%d", k);
         }
         snprintf(names[P_EMIT], 32, "emit");
         snprintf(names[P_BATCHED], 32, "batched_graph");
@@ -688,13 +694,32 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         app.verts = as<u64>(q);
         HIP_TRY(C.ensure(B_APP_NBR, (size_t)appcap * 8, &q));
         app.nbr = as<u64>(q);
+        HIP_TRY(C.ensure(B_APP_COB, (size_t)appcap * 8, &q));
+        app.cob = as<u64>(q);
+        // room for the coboundary lists of the apparent pairs: a slot reserves
+        // as many entries as rho has candidates (grown from the last call's need)
+        const int64_t per = P.sparse ? std::min<int64_t>(std::max(P.maxdeg, 1), 64) : n;
+        const int64_t cobcap = std::max<int64_t>(C.hint_cob, std::min<int64_t>(ncand * per, 1ll << 25));
+        HIP_TRY(C.ensure(B_COB_KEY, (size_t)cobcap * 8, &q));
+        app.ckey = as<int64_t>(q);
+        int64_t *ckey_w = as<int64_t>(q);
+        HIP_TRY(C.ensure(B_COB_DIA, (size_t)cobcap * 4, &q));
+        app.cdia = as<float>(q);
+        float *cdia_w = as<float>(q);
         app.mask = appcap - 1;
         launch_fill_i64(app.keys, appcap, kEmpty, st);
         {
             PROF(P_FILTER1 + k - 1);
             launch_filter(G, P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv, app, st);
         }
+        {
+            PROF(P_COB1 + k - 1);
+            hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, &P.scal->cob, 0ull);
+            launch_cob_lists(P.ctx, k, app, ckey_w, cdia_w, &P.scal->cob, cobcap, st);
+        }
         if ((rs = read_scalars(C, P.scal, st))) return rs;
+        if ((int64_t)C.host_scal->cob > C.hint_cob)
+            C.hint_cob = std::min<int64_t>((int64_t)C.host_scal->cob, 1ll << 28);
         const int64_t S = std::min<int64_t>((int64_t)C.host_scal->survivors, ncand);
         if (S > 0x7fffffff) return fail(RIPS_E_CAPACITY, "too many columns");
         o.ncols[k] = S;

@@ -349,7 +349,8 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         u32 appcap = 64;
         while (appcap < 2u * (u32)npairs + 64u && (int64_t)appcap < A.ph_stride) appcap <<= 1;
         const PairHash app{A.app_keys + (int64_t)wg * A.ph_stride, A.app_vals + (int64_t)wg * A.ph_stride,
-                           A.app_verts + (int64_t)wg * A.ph_stride, nullptr, appcap - 1};
+                           A.app_verts + (int64_t)wg * A.ph_stride, nullptr, nullptr, nullptr, nullptr,
+                           appcap - 1};
         for (u32 q = tid; q < appcap; q += kBT) app.keys[q] = kEmpty;
         gsync();
         unsigned long long n_clear = 0, n_acol = 0, n_cand = 0;

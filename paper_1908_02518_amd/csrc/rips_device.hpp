@@ -445,28 +445,35 @@ struct PairHash {
     int64_t *vals;
     u64 *verts;
     u64 *nbr;
+    u64 *cob;          // rho's coboundary list: offset << 24 | length, kNoList when absent
+    const int64_t *ckey; // the lists: cofacet index | (orientation bit << 62)
+    const float *cdia;   // and cofacet diameter
     u32 mask;
 };
+constexpr u64 kNoList = ~0ull;
+constexpr int64_t kCobIdx = (1ll << 62) - 1; // index bits of a list key
 
 // Everything a slot holds for a key (val -1: not there).
 struct PairHit {
     int64_t val;
-    u64 verts, nbr;
+    u64 verts, nbr, cob;
 };
 
 __device__ __forceinline__ PairHit pair_find_all(const PairHash &h, int64_t key) {
     u32 s = mix64((u64)key) & h.mask;
-    PairHit r{-1, kNoVerts, 0};
+    PairHit r{-1, kNoVerts, 0, kNoList};
     for (u32 probe = 0; probe <= h.mask; ++probe) {
         // the slot's words are loaded together: one round trip per probe
         const int64_t cur = h.keys[s];
         const int64_t v = h.vals[s];
         const u64 w = h.verts ? h.verts[s] : kNoVerts;
         const u64 nb = h.nbr ? h.nbr[s] : 0;
+        const u64 cb = h.cob ? h.cob[s] : kNoList;
         if (cur == key) {
             r.val = v;
             r.verts = w;
             r.nbr = nb;
+            r.cob = cb;
             return r;
         }
         if (cur == kEmpty) return r;

@@ -817,6 +817,94 @@ __global__ void __launch_bounds__(1024) k_compact_bars(BarBuf in, int64_t ncols,
     if (threadIdx.x == 0) s->nbars = base;
 }
 
+// The coboundary of the rho of every zero apparent pair (rho, tau) the filter
+// recorded, listed once, in parallel: the reduction then adds such a
+// coboundary by reading its list instead of scanning rho's neighbours. One
+// wave per group of 64 table slots, one rho at a time (all control flow is
+// uniform in the wave); a wave reserves room for its slots with one atomic.
+// A slot whose list would not fit gets kNoList, and the reduction scans.
+template <class Dist>
+__global__ void __launch_bounds__(256) k_cob_lists(Ctx<Dist> c, int k, PairHash app, int64_t *ckey,
+                                                   float *cdia, unsigned long long *count, int64_t cap) {
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const bool dense = c.nb.off == nullptr;
+    for (int64_t s0 = wave * kWave; s0 <= (int64_t)app.mask; s0 += nwaves * kWave) {
+        const int64_t s = s0 + lane;
+        const bool full = s <= (int64_t)app.mask && app.keys[s] != kEmpty;
+        // candidates of this lane's rho, then room for all of the wave's lists
+        int du = 0;
+        if (full) du = dense ? c.n : (int)(u32)app.nbr[s];
+        int incl = du;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int t = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += t;
+        }
+        const int total = __shfl(incl, kWave - 1, kWave);
+        unsigned long long wbase = 0;
+        if (lane == 0 && total > 0) wbase = atomicAdd(count, (unsigned long long)total);
+        wbase = __shfl(wbase, 0, kWave);
+        const unsigned long long mybase = wbase + (unsigned long long)(incl - du);
+        u64 todo = __ballot(full);
+        while (todo) {
+            const int l = __ffsll((unsigned long long)todo) - 1;
+            todo &= todo - 1;
+            const int64_t slot = s0 + l;
+            const unsigned long long base = __shfl(mybase, l, kWave);
+            const int n_cand = __shfl(du, l, kWave);
+            if ((int64_t)(base + n_cand) > cap || n_cand > 0xffffff) {
+                if (lane == 0) app.cob[slot] = kNoList;
+                continue;
+            }
+            int rv[kMaxVerts];
+            const u64 vw = app.verts[slot];
+            if (vw != kNoVerts) {
+                for (int q = 0; q <= k; ++q) rv[q] = (int)((vw >> (16 * q)) & 0xffffu);
+            } else {
+                decode(app.vals[slot] >> 3, k, c.n, c.B, rv);
+            }
+            const float rd = diam_of(c, rv, k);
+            const int lo = dense ? 0 : (int)(app.nbr[slot] >> 32);
+            int w = 0;
+            for (int q0 = 0; q0 < n_cand; q0 += kWave) {
+                const int q = q0 + lane;
+                bool ok = q < n_cand;
+                int64_t ci = 0;
+                float nd = rd;
+                int below = 0;
+                if (ok) {
+                    const int jv = dense ? q : c.nb.idx[lo + q];
+                    for (int m = 0; m <= k; ++m) {
+                        ok = ok && jv != rv[m];
+                        nd = fmaxf(nd, c.d(rv[m], jv));
+                    }
+                    ok = ok && nd <= c.t;
+                    if (ok) ci = cofacet_index(rv, k, jv, c.B, &below);
+                }
+                const u64 b = __ballot(ok);
+                if (ok) {
+                    const int pos = w + __popcll(b & ((1ull << lane) - 1ull));
+                    ckey[base + pos] = ci | ((int64_t)(below & 1) << 62);
+                    cdia[base + pos] = nd;
+                }
+                w += __popcll(b);
+            }
+            if (lane == 0) app.cob[slot] = ((u64)base << 24) | (u64)w;
+        }
+    }
+}
+
+void launch_cob_lists(const Ctx<DistFull> &c, int k, PairHash app, int64_t *ckey, float *cdia,
+                      unsigned long long *count, int64_t cap, hipStream_t st) {
+    const int64_t slots = (int64_t)app.mask + 1;
+    int64_t blocks = (slots + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL((k_cob_lists<DistFull>), dim3((unsigned)blocks), dim3(256), 0, st, c, k, app, ckey,
+                       cdia, count, cap);
+}
+
 // ---------------------------------------------------------------------------
 // Backward: d(loss)/d(bar endpoint) scattered onto the critical edge of the
 // endpoint's simplex (the edge of largest float32 length, ties to the

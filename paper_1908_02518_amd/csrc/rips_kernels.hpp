@@ -36,6 +36,7 @@ struct Scalars {
     float t_eff;
     unsigned long long edges;     // edges <= t (may exceed capacity)
     unsigned long long list;      // expanded simplices (may exceed capacity)
+    unsigned long long cob;       // coboundary-list entries reserved (may exceed capacity)
     unsigned long long survivors; // columns left by the filter
     unsigned long long vcount;    // entries appended to V
     unsigned long long mst;       // forest edges
@@ -118,6 +119,10 @@ void launch_csr(const float *D, int n, Scalars *s, const int *deg, int *off, int
 void launch_h0(EdgeList E, Scalars *s, int n, H0Scratch W, BarBuf out, int64_t nbits_words,
                hipStream_t st);
 void launch_fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t st);
+// rho's coboundary list for every slot of the apparent-pair table (app.cob,
+// ckey, cdia; count = entries used, to be zeroed before)
+void launch_cob_lists(const Ctx<DistFull> &c, int k, PairHash app, int64_t *ckey, float *cdia,
+                      unsigned long long *count, int64_t cap, hipStream_t st);
 void launch_fill_u32(u32 *a, int64_t n, u32 v, hipStream_t st);
 void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
                    const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app,

@@ -1310,7 +1310,7 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
         }
         RED_T1(S, 19, t_r0);
         RED_T0(t_r1);
-        PairHit hit{-1, kNoVerts, 0};
+        PairHit hit{-1, kNoVerts, 0, kNoList};
         if (lane == 0) hit = pair_find_all(app, piv.idx);
         const int64_t a = __shfl(hit.val, 0, kWave);
         RED_T1(S, 20, t_r1);
@@ -1318,6 +1318,7 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
         RED_T0(t_r2);
         const u64 vw = (u64)__shfl((long long)hit.verts, 0, kWave);
         const u64 nbw = (u64)__shfl((long long)hit.nbr, 0, kWave);
+        const u64 cbw = (u64)__shfl((long long)hit.cob, 0, kWave);
         // rho's vertices, and the candidate source: the neighbour list of its
         // vertex with the fewest neighbours (all vertices when dense), both
         // from the table slot
@@ -1328,8 +1329,12 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
             decode(a >> 3, k, c.n, c.B, rv);
         }
         const int u = c.nb.off == nullptr ? -1 : 0;
+        // rho's coboundary: its list from the table when there is one, else
+        // the candidates of its shortest neighbour list
+        const bool listed = cbw != kNoList;
+        const int64_t loff = listed ? (int64_t)(cbw >> 24) : 0;
         const int lo = u < 0 ? 0 : (int)(nbw >> 32);
-        const int du = u < 0 ? c.n : (int)(u32)nbw;
+        const int du = listed ? (int)(cbw & 0xffffffu) : (u < 0 ? c.n : (int)(u32)nbw);
         if (ns + du > capD / 4) break; // more than the delta takes before its maintenance
         // tau = rho u {tau[m]}; vertices of rho below tau[m]: k + 1 - m
         const int m = (int)(a & 7);
@@ -1344,7 +1349,12 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
             int64_t ci = 0;
             float nd = 0.0f;
             u32 cc = 0;
-            if (act) {
+            if (act && listed) {
+                const int64_t key = app.ckey[loff + q];
+                ci = key & kCobIdx;
+                nd = app.cdia[loff + q];
+                cc = (key >> 62) ? (p - neg) % p : neg;
+            } else if (act) {
                 const int jv = u < 0 ? q : c.nb.idx[lo + q];
                 bool in = false;
                 nd = piv.diam;
