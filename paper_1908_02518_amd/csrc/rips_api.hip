@@ -550,6 +550,20 @@ int group_size_for(const Prepared &P) {
     return P.ctx.n <= 128 ? 16 : 32;
 }
 
+// Lanes per candidate of the apparent-pair filter. Its time goes into the
+// per-candidate tests every lane of a group repeats, more than into the
+// scan, so groups are narrower than the expansion's: one lane per candidate
+// for sparse dimensions >= 2, four for edges, eight for small dense clouds.
+int filter_group_size_for(const Prepared &P, int k) {
+    const char *env = getenv("RIPS_FILTER_GROUP");
+    if (env) {
+        int g = atoi(env);
+        if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64) return g;
+    }
+    if (P.sparse) return k == 1 ? 4 : 1;
+    return P.ctx.n <= 128 ? 8 : 32;
+}
+
 rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, float t, uint32_t p,
                        hipStream_t st, RunOut &o) {
     memset(&o, 0, sizeof(o));
@@ -710,7 +724,8 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         launch_fill_i64(app.keys, appcap, kEmpty, st);
         {
             PROF(P_FILTER1 + k - 1);
-            launch_filter(G, P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv, app, st);
+            launch_filter(filter_group_size_for(P, k), P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv,
+                          app, st);
         }
         {
             PROF(P_COB1 + k - 1);

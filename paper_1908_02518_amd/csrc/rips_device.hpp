@@ -354,6 +354,131 @@ __device__ __attribute__((noinline)) int zero_apparent_facet(const Ctx<Dist> &c,
 }
 
 // ---------------------------------------------------------------------------
+// The same tests with the dimension K fixed at compile time, for the
+// enumeration / apparent-pair pass: every tuple is indexed by constants, so
+// it stays in registers. The scans are called by every lane of the wave at
+// once; their loops run until every group of the wave is done, so no lane
+// leaves a loop holding a wave operation while others stay in it.
+// ---------------------------------------------------------------------------
+
+// v[m] for a run-time m, by selects over constant positions.
+template <int N>
+__device__ __forceinline__ int pick_vertex(const int (&v)[N], int m) {
+    int r = v[0];
+#pragma unroll
+    for (int q = 1; q < N; ++q) r = q == m ? v[q] : r;
+    return r;
+}
+
+// sigma u {j} for the decreasing tuple v of a K-simplex, j not in v; pos =
+// the position of j (the number of vertices above it).
+template <int K>
+__device__ __forceinline__ void insert_k(const int (&v)[K + 1], int j, int (&out)[K + 2], int &pos) {
+    int above = 0;
+#pragma unroll
+    for (int m = 0; m <= K; ++m) above += v[m] > j ? 1 : 0;
+    pos = above;
+#pragma unroll
+    for (int q = 0; q <= K + 1; ++q) {
+        const int lo = v[q <= K ? q : K];     // v[q], when q < above
+        const int hi = v[q >= 1 ? q - 1 : 0]; // v[q - 1], when q > above
+        out[q] = q < above ? lo : (q == above ? j : hi);
+    }
+}
+
+// The facet of the K-simplex v without v[m].
+template <int K>
+__device__ __forceinline__ void remove_k(const int (&v)[K + 1], int m, int (&out)[K]) {
+#pragma unroll
+    for (int q = 0; q < K; ++q) out[q] = q < m ? v[q] : v[q + 1];
+}
+
+// Position of the removed vertex of the zero pivot facet of the K-simplex v
+// (diameter dm): the first facet, removing v[0], v[1], ..., whose diameter
+// is dm; -1 if none.
+template <int K, class Dist>
+__device__ __forceinline__ int zero_pivot_facet_k(const Ctx<Dist> &c, const int (&v)[K + 1], float dm) {
+    float pd[K + 1][K + 1];
+#pragma unroll
+    for (int a = 0; a <= K; ++a)
+#pragma unroll
+        for (int b = a + 1; b <= K; ++b) pd[a][b] = c.d(v[a], v[b]);
+    int res = -1;
+#pragma unroll
+    for (int m = K; m >= 0; --m) {
+        float mx = 0.0f;
+#pragma unroll
+        for (int a = 0; a <= K; ++a)
+#pragma unroll
+            for (int b = a + 1; b <= K; ++b)
+                if (a != m && b != m) mx = fmaxf(mx, pd[a][b]);
+        if (mx == dm) res = m;
+    }
+    return res;
+}
+
+// Largest vertex j > jmin, j not in the K-simplex v, with d(j, v_m) <= bound
+// for every m; -1 if none, or if the group is not active. The candidates of
+// group_find_max, in the same decreasing order and G at a time; all lanes of
+// a group get the same result.
+template <int G, int K, class Dist>
+__device__ __forceinline__ int scan_max_k(const Ctx<Dist> &c, const int (&v)[K + 1], float bound,
+                                          int jmin, bool active) {
+    const int lg = lane_id() & (G - 1);
+    const u64 gm = group_mask<G>();
+    const bool dense = c.nb.off == nullptr;
+    const int *L = nullptr;
+    int top = c.n - 1; // dense: next vertex; sparse: next position in L
+    if (active && !dense) {
+        int u = v[0];
+        int du = c.nb.off[u + 1] - c.nb.off[u];
+#pragma unroll
+        for (int m = 1; m <= K; ++m) {
+            const int dq = c.nb.off[v[m] + 1] - c.nb.off[v[m]];
+            if (dq < du) {
+                du = dq;
+                u = v[m];
+            }
+        }
+        L = c.nb.idx + c.nb.off[u];
+        top = du - 1;
+    }
+    int res = -1;
+    bool done = !active;
+    while (__ballot(!done) != 0) {
+        bool ok = false;
+        int j = -1;
+        if (!done) {
+            // the rest of a sparse list is smaller still once its top is <= jmin
+            if (dense ? top <= jmin : (top < 0 || L[top] <= jmin)) {
+                done = true;
+            } else {
+                const int q = top - lg;
+                j = dense ? q : (q >= 0 ? L[q] : -1);
+                ok = j > jmin;
+#pragma unroll
+                for (int m = 0; m <= K; ++m) ok = ok && j != v[m];
+                if (ok) {
+#pragma unroll
+                    for (int m = 0; m <= K; ++m) ok = ok && c.d(v[m], j) <= bound;
+                }
+            }
+        }
+        const u64 hit = __ballot(ok) & gm;
+        const int jj = __shfl(j, hit ? __ffsll((unsigned long long)hit) - 1 : lane_id(), kWave);
+        if (!done) {
+            if (hit) {
+                res = jj;
+                done = true;
+            } else {
+                top -= G;
+            }
+        }
+    }
+    return res;
+}
+
+// ---------------------------------------------------------------------------
 // Hashing.
 // ---------------------------------------------------------------------------
 __host__ __device__ __forceinline__ u32 mix64(u64 x) {

@@ -595,48 +595,67 @@ __global__ void __launch_bounds__(256) k_expand_count(Ctx<Dist> c, int k, Simple
 //   - otherwise sigma is a column to reduce; its zero pivot cofacet j (or -1)
 //     and whether that cofacet is itself in a zero apparent pair are kept for
 //     the emergent shortcut of the reduction.
-// G lanes cooperate on one candidate (G candidate vertices per step).
+// G lanes cooperate on one candidate (G candidate vertices per step); the
+// dimension k is a template parameter, so vertex tuples stay in registers.
+// The loop over candidates is uniform in the wave (one candidate per group
+// per turn) and the tests are predicates, as the scans need every lane.
 // ---------------------------------------------------------------------------
-template <int G, class Dist>
-__global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, int k, SimplexList in, int64_t count,
+template <int G, int K, class Dist>
+__global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, SimplexList in, int64_t count,
                                                 const u32 *mst_bits, PivotHash prev, Scalars *s,
                                                 Columns out, PairHash app) {
-    const int gpb = blockDim.x / G;
-    const int lg = threadIdx.x & (G - 1);
-    const int64_t stride = (int64_t)gridDim.x * gpb;
+    constexpr int kGroups = kWave / G; // groups per wave
+    const int lane = lane_id();
+    const bool leader = (lane & (G - 1)) == 0;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
     u64 n_clear = 0, n_acol = 0, n_apiv = 0;
-    for (int64_t e = blockIdx.x * (int64_t)gpb + threadIdx.x / G; e < count; e += stride) {
-        const int64_t idx = in.idx[e];
-        const float dm = in.diam[e];
-        int v[kMaxVerts];
-        bool cleared;
-        if (k == 1) {
-            edge_vertices((u32)idx, &v[0], &v[1]);
-            cleared = (mst_bits[idx >> 5] >> (idx & 31)) & 1u;
-        } else {
-            decode(idx, k, c.n, c.B, v);
-            cleared = ph_find(prev, idx) >= 0;
+    for (int64_t e0 = wave * kGroups; e0 < count; e0 += nwaves * kGroups) {
+        const int64_t e = e0 + lane / G;
+        bool live = e < count;
+        int64_t idx = 0;
+        float dm = 0.0f;
+        int v[K + 1];
+#pragma unroll
+        for (int q = 0; q <= K; ++q) v[q] = 0;
+        if (live) {
+            idx = in.idx[e];
+            dm = in.diam[e];
+            bool cleared;
+            if constexpr (K == 1) {
+                edge_vertices((u32)idx, &v[0], &v[1]);
+                cleared = (mst_bits[idx >> 5] >> (idx & 31)) & 1u;
+            } else {
+                decode(idx, K, c.n, c.B, v);
+                cleared = ph_find(prev, idx) >= 0;
+            }
+            if (cleared) {
+                n_clear += leader;
+                live = false;
+            }
         }
-        if (cleared) {
-            n_clear += (lg == 0);
-            continue;
-        }
-        const int j = group_find_max<G>(c, v, k, dm, -1);
-        if (j >= 0 && is_zero_apparent_cofacet(c, v, k, dm, j)) {
-            n_acol += (lg == 0);
-            if (lg == 0 && app.keys) {
-                int tv[kMaxVerts];
-                const int pos = insert_vertex(v, k, j, tv);
+        // sigma's zero pivot cofacet sigma u {j}, if any
+        const int j = scan_max_k<G, K>(c, v, dm, -1, live);
+        int tv[K + 2];
+        int pos = 0;
+        insert_k<K>(v, j, tv, pos);
+        if (live && j >= 0 && zero_pivot_facet_k<K + 1>(c, tv, dm) == pos) {
+            // (sigma, sigma u {j}) is a zero apparent pair
+            n_acol += leader;
+            live = false;
+            if (leader && app.keys) {
                 // capacity is twice the candidates: the insert cannot fail
                 u64 packed = kNoVerts;
                 if (c.n <= 65536) {
                     packed = 0;
-                    for (int q = 0; q <= k; ++q) packed |= (u64)(u32)v[q] << (16 * q);
+#pragma unroll
+                    for (int q = 0; q <= K; ++q) packed |= (u64)(u32)v[q] << (16 * q);
                 }
                 u64 nbr = 0;
                 if (c.nb.off != nullptr) {
                     int lo = c.nb.off[v[0]], du = c.nb.off[v[0] + 1] - lo;
-                    for (int q = 1; q <= k; ++q) {
+#pragma unroll
+                    for (int q = 1; q <= K; ++q) {
                         const int lq = c.nb.off[v[q]];
                         const int dq = c.nb.off[v[q] + 1] - lq;
                         if (dq < du) {
@@ -646,27 +665,47 @@ __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, int k, SimplexList 
                     }
                     nbr = ((u64)(u32)lo << 32) | (u32)du;
                 }
-                (void)pair_insert(app, simplex_index(tv, k + 1, c.B), (idx << 3) | pos, packed, nbr);
+                (void)pair_insert(app, simplex_index(tv, K + 1, c.B), (idx << 3) | pos, packed, nbr);
             }
-            continue;
         }
-        if (k >= 2 && zero_apparent_facet<G>(c, v, k, dm) >= 0) {
-            n_apiv += (lg == 0);
-            continue;
+        if constexpr (K >= 2) {
+            // sigma in a zero apparent pair (rho, sigma): rho = sigma's zero
+            // pivot facet, and no vertex above the removed one extends rho at
+            // the same diameter
+            const int m = live ? zero_pivot_facet_k<K>(c, v, dm) : -1;
+            int rv[K];
+            remove_k<K>(v, m < 0 ? 0 : m, rv);
+            const bool test = live && m >= 0;
+            const int jr = scan_max_k<G, K - 1>(c, rv, dm, pick_vertex(v, m), test);
+            if (test && jr < 0) {
+                n_apiv += leader;
+                live = false;
+            }
         }
-        uint8_t tapp = 0;
-        if (j >= 0) {
-            int tv[kMaxVerts];
-            insert_vertex(v, k, j, tv);
-            tapp = zero_apparent_facet<G>(c, tv, k + 1, dm) >= 0 ? 1 : 0;
-        }
-        if (lg == 0) {
-            const u64 slot = atomicAdd(&s->survivors, 1ull);
-            if (slot >= (u64)count) continue; // one survivor per candidate at most
-            out.idx[slot] = idx;
-            out.diam[slot] = dm;
-            out.j[slot] = j;
-            out.tapp[slot] = tapp;
+        // the same test for the zero pivot cofacet, for the emergent shortcut
+        const bool tj = live && j >= 0;
+        const int mt = tj ? zero_pivot_facet_k<K + 1>(c, tv, dm) : -1;
+        int rt[K + 1];
+        remove_k<K + 1>(tv, mt < 0 ? 0 : mt, rt);
+        const bool ttest = tj && mt >= 0;
+        const int jt = scan_max_k<G, K>(c, rt, dm, pick_vertex(tv, mt), ttest);
+        const uint8_t tapp = (ttest && jt < 0) ? 1 : 0;
+        // survivors: one atomic per wave
+        const u64 keep = __ballot(live && leader);
+        if (keep) {
+            unsigned long long base = 0;
+            const int first = __ffsll((unsigned long long)keep) - 1;
+            if (lane == first) base = atomicAdd(&s->survivors, (unsigned long long)__popcll(keep));
+            base = __shfl(base, first, kWave);
+            if (live && leader) {
+                const u64 slot = base + (u64)__popcll(keep & ((1ull << lane) - 1ull));
+                if (slot < (u64)count) { // one survivor per candidate at most
+                    out.idx[slot] = idx;
+                    out.diam[slot] = dm;
+                    out.j[slot] = j;
+                    out.tapp[slot] = tapp;
+                }
+            }
         }
     }
     for (int off = 32; off >= 1; off >>= 1) {
@@ -674,7 +713,7 @@ __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, int k, SimplexList 
         n_acol += __shfl_xor(n_acol, off, kWave);
         n_apiv += __shfl_xor(n_apiv, off, kWave);
     }
-    if (lane_id() == 0) {
+    if (lane == 0) {
         if (n_clear) atomicAdd(&s->stat[kStatCleared], n_clear);
         if (n_acol) atomicAdd(&s->stat[kStatAppCol], n_acol);
         if (n_apiv) atomicAdd(&s->stat[kStatAppPiv], n_apiv);
@@ -823,17 +862,25 @@ __global__ void __launch_bounds__(1024) k_compact_bars(BarBuf in, int64_t ncols,
 // wave per group of 64 table slots, one rho at a time (all control flow is
 // uniform in the wave); a wave reserves room for its slots with one atomic.
 // A slot whose list would not fit gets kNoList, and the reduction scans.
+// spw (1..64) slots per wave: fewer slots give more waves, i.e. more
+// independent chains of loads in flight. The room is reserved with one
+// atomic per workgroup of 256 threads (one counter serializes its atomics).
 template <class Dist>
 __global__ void __launch_bounds__(256) k_cob_lists(Ctx<Dist> c, int k, PairHash app, int64_t *ckey,
-                                                   float *cdia, unsigned long long *count, int64_t cap) {
+                                                   float *cdia, unsigned long long *count, int64_t cap,
+                                                   int spw) {
+    constexpr int kWaves = 256 / kWave;
+    __shared__ unsigned long long wsum[kWaves];
     const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * blockDim.x / kWave;
+    const int w = threadIdx.x / kWave;
     const bool dense = c.nb.off == nullptr;
-    for (int64_t s0 = wave * kWave; s0 <= (int64_t)app.mask; s0 += nwaves * kWave) {
+    // block-uniform loop: every wave of a workgroup takes the same turns
+    for (int64_t b0 = (int64_t)blockIdx.x * kWaves * spw; b0 <= (int64_t)app.mask;
+         b0 += (int64_t)gridDim.x * kWaves * spw) {
+        const int64_t s0 = b0 + (int64_t)w * spw;
         const int64_t s = s0 + lane;
-        const bool full = s <= (int64_t)app.mask && app.keys[s] != kEmpty;
-        // candidates of this lane's rho, then room for all of the wave's lists
+        const bool full = lane < spw && s <= (int64_t)app.mask && app.keys[s] != kEmpty;
+        // candidates of this lane's rho, then room for all of the block's lists
         int du = 0;
         if (full) du = dense ? c.n : (int)(u32)app.nbr[s];
         int incl = du;
@@ -842,9 +889,21 @@ __global__ void __launch_bounds__(256) k_cob_lists(Ctx<Dist> c, int k, PairHash 
             if (lane >= o) incl += t;
         }
         const int total = __shfl(incl, kWave - 1, kWave);
-        unsigned long long wbase = 0;
-        if (lane == 0 && total > 0) wbase = atomicAdd(count, (unsigned long long)total);
-        wbase = __shfl(wbase, 0, kWave);
+        if (lane == 0) wsum[w] = (unsigned long long)total;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long run = 0;
+            for (int q = 0; q < kWaves; ++q) {
+                const unsigned long long t = wsum[q];
+                wsum[q] = run;
+                run += t;
+            }
+            const unsigned long long bbase = run > 0 ? atomicAdd(count, run) : 0ull;
+            for (int q = 0; q < kWaves; ++q) wsum[q] += bbase;
+        }
+        __syncthreads();
+        const unsigned long long wbase = wsum[w];
+        __syncthreads(); // wsum is rewritten next turn
         const unsigned long long mybase = wbase + (unsigned long long)(incl - du);
         u64 todo = __ballot(full);
         while (todo) {
@@ -897,12 +956,18 @@ __global__ void __launch_bounds__(256) k_cob_lists(Ctx<Dist> c, int k, PairHash 
 
 void launch_cob_lists(const Ctx<DistFull> &c, int k, PairHash app, int64_t *ckey, float *cdia,
                       unsigned long long *count, int64_t cap, hipStream_t st) {
+    int spw = 16;
+    if (const char *env = getenv("RIPS_COB_SPW")) {
+        const int v = atoi(env);
+        if (v >= 1 && v <= kWave) spw = v;
+    }
     const int64_t slots = (int64_t)app.mask + 1;
-    int64_t blocks = (slots + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
+    const int64_t waves = (slots + spw - 1) / spw;
+    int64_t blocks = (waves + 3) / 4; // 4 waves per workgroup of 256
+    if (blocks > 65536) blocks = 65536;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL((k_cob_lists<DistFull>), dim3((unsigned)blocks), dim3(256), 0, st, c, k, app, ckey,
-                       cdia, count, cap);
+                       cdia, count, cap, spw);
 }
 
 // ---------------------------------------------------------------------------
@@ -1000,22 +1065,34 @@ __global__ void k_emit(BarBuf in, Scalars *s, int reverse, BarBuf out) {
 // ---------------------------------------------------------------------------
 // instantiations / launchers
 // ---------------------------------------------------------------------------
-template <int G>
-static void launch_filter_g(const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, PairHash app,
-                            const u32 *bits, PivotHash prev, Scalars *s, Columns out,
-                            hipStream_t st) {
+template <int G, int K>
+static void launch_filter_gk(const Ctx<DistFull> &c, SimplexList in, int64_t count, PairHash app,
+                             const u32 *bits, PivotHash prev, Scalars *s, Columns out, hipStream_t st) {
     const int gpb = 256 / G;
     int64_t blocks = (count + gpb - 1) / gpb;
     if (blocks < 1) blocks = 1;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL((k_filter<G, DistFull>), dim3((unsigned)blocks), dim3(256), 0, st, c, k, in,
-                       count, bits, prev, s, out, app);
+    hipLaunchKernelGGL((k_filter<G, K, DistFull>), dim3((unsigned)blocks), dim3(256), 0, st, c, in, count,
+                       bits, prev, s, out, app);
+}
+
+template <int G>
+static void launch_filter_g(const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, PairHash app,
+                            const u32 *bits, PivotHash prev, Scalars *s, Columns out,
+                            hipStream_t st) {
+    switch (k) {
+    case 1: launch_filter_gk<G, 1>(c, in, count, app, bits, prev, s, out, st); break;
+    case 2: launch_filter_gk<G, 2>(c, in, count, app, bits, prev, s, out, st); break;
+    default: launch_filter_gk<G, 3>(c, in, count, app, bits, prev, s, out, st); break;
+    }
 }
 
 void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
                    const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app,
                    hipStream_t st) {
     switch (G) {
+    case 1: launch_filter_g<1>(c, k, in, count, app, bits, prev, s, out, st); break;
+    case 2: launch_filter_g<2>(c, k, in, count, app, bits, prev, s, out, st); break;
     case 4: launch_filter_g<4>(c, k, in, count, app, bits, prev, s, out, st); break;
     case 8: launch_filter_g<8>(c, k, in, count, app, bits, prev, s, out, st); break;
     case 16: launch_filter_g<16>(c, k, in, count, app, bits, prev, s, out, st); break;
