@@ -12,7 +12,7 @@
 namespace rips {
 
 constexpr int kBT = 256;         // threads per workgroup
-constexpr int kBatchG = 16;      // lanes per candidate in the filter
+constexpr int kBatchFilterG = 8; // lanes per candidate edge in the filter
 
 struct BatchShared {
     int cloud, n, nsurv, nbars0, flag, m;
@@ -343,7 +343,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         c.t = t;
         Columns surv{A.c_idx0 + (int64_t)wg * A.col_stride, A.c_dm0 + (int64_t)wg * A.col_stride,
                      A.c_j0 + (int64_t)wg * A.col_stride, A.c_t0 + (int64_t)wg * A.col_stride};
-        const int lg = tid & (kBatchG - 1);
+        const bool leader = (lane & (kBatchFilterG - 1)) == 0;
         // the zero apparent pairs (rho, tau) found here serve the reduction's
         // pivot tests (one lookup instead of facet and cofacet scans)
         u32 appcap = 64;
@@ -354,41 +354,53 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         for (u32 q = tid; q < appcap; q += kBT) app.keys[q] = kEmpty;
         gsync();
         unsigned long long n_clear = 0, n_acol = 0, n_cand = 0;
-        for (int64_t e = tid / kBatchG; e < npairs; e += kBT / kBatchG) {
-            int v[kMaxVerts];
-            pair_of(e, &v[0], &v[1]);
-            const float dm = dist(v[0], v[1]);
-            if (!(dm <= t)) continue;
-            n_cand += (lg == 0);
-            if ((bits[e >> 5] >> (e & 31)) & 1u) {
-                n_clear += (lg == 0);
-                continue;
+        // one edge per group of kBatchFilterG lanes; the loop is uniform in
+        // the wave and the tests are predicates (the scans need every lane)
+        constexpr int kGroups = kWave / kBatchFilterG;
+        for (int64_t e0 = (int64_t)(tid / kWave) * kGroups; e0 < npairs; e0 += (kBT / kWave) * kGroups) {
+            const int64_t e = e0 + lane / kBatchFilterG;
+            bool live = e < npairs;
+            int v[2] = {0, 0};
+            float dm = 0.0f;
+            if (live) {
+                pair_of(e, &v[0], &v[1]);
+                dm = dist(v[0], v[1]);
+                live = dm <= t;
             }
-            const int j = group_find_max<kBatchG>(c, v, 1, dm, -1);
-            if (j >= 0 && is_zero_apparent_cofacet(c, v, 1, dm, j)) {
-                n_acol += (lg == 0);
-                if (lg == 0) {
-                    int tv[kMaxVerts];
-                    const int pos = insert_vertex(v, 1, j, tv);
-                    // capacity is at least twice the pairs: the insert cannot fail
+            if (live) {
+                n_cand += leader;
+                if ((bits[e >> 5] >> (e & 31)) & 1u) {
+                    n_clear += leader;
+                    live = false;
+                }
+            }
+            const int j = scan_max_k<kBatchFilterG, 1>(c, v, dm, -1, live);
+            int tv[3];
+            int pos = 0;
+            insert_k<1>(v, j, tv, pos);
+            if (live && j >= 0 && zero_pivot_facet_k<2>(c, tv, dm) == pos) {
+                n_acol += leader;
+                live = false;
+                // capacity is at least twice the pairs: the insert cannot fail
+                if (leader)
                     (void)pair_insert(app, simplex_index(tv, 2, c.B), (e << 3) | pos,
                                       (u64)(u32)v[0] | ((u64)(u32)v[1] << 16), 0);
-                }
-                continue;
             }
-            uint8_t tapp = 0;
-            if (j >= 0) {
-                int tv[kMaxVerts];
-                insert_vertex(v, 1, j, tv);
-                tapp = zero_apparent_facet<kBatchG>(c, tv, 2, dm) >= 0 ? 1 : 0;
-            }
-            if (lg == 0) {
+            // is the zero pivot cofacet itself in a zero apparent pair (for
+            // the emergent shortcut)?
+            const bool tj = live && j >= 0;
+            const int mt = tj ? zero_pivot_facet_k<2>(c, tv, dm) : -1;
+            int rt[2];
+            remove_k<2>(tv, mt < 0 ? 0 : mt, rt);
+            const bool ttest = tj && mt >= 0;
+            const int jt = scan_max_k<kBatchFilterG, 1>(c, rt, dm, pick_vertex(tv, mt), ttest);
+            if (live && leader) {
                 const int slot = atomicAdd(&Sh.nsurv, 1);
                 if (slot < A.col_stride) {
                     surv.idx[slot] = e;
                     surv.diam[slot] = dm;
                     surv.j[slot] = j;
-                    surv.tapp[slot] = tapp;
+                    surv.tapp[slot] = (ttest && jt < 0) ? 1 : 0;
                 }
             }
         }
