@@ -17,6 +17,10 @@ per step. Also reported:
                     (committed summary under profiles/, scaled by a plain copy
                     of known size), null when the kernel sources changed since
   enumeration_pass  the same for the enumeration / apparent-pair filter
+  valu              (in both) the kernel's vector-ALU issue rate: VALU wave
+                    instructions per dispatch from a committed rocprofv3
+                    counter summary over the live launch time, against
+                    256 CUs x 2.4 GHz x one wave64 instruction per CU-cycle
   batched           barcodes/s of the 512-cloud mixture batch in one
                     persistent launch vs one cloud at a time
   cpu_baseline      the CPU oracle on this host (a bounded sample)
@@ -26,6 +30,7 @@ per step. Also reported:
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --summarize-pmc FETCH_DIR WRITE_DIR   (profiles helpers)
        python bench.py --summarize-trace TRACE_DIR
+       python bench.py --summarize-valu PMC_DIR
 """
 
 from __future__ import annotations
@@ -45,6 +50,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_so3-1000.txt")
+PMC_VALU_SUMMARY = os.path.join(ROOT, "profiles", "pmc_valu_so3-1000.txt")
 COPY_BYTES = 1 << 29   # plain copy used to calibrate the counters (512 MiB read + written)
 
 
@@ -62,8 +68,8 @@ def source_hash() -> str:
 def kernel_bytes(name: str, n: int, counts, stats, sparse: bool) -> float | None:
     """Algorithmic HBM bytes of one launch of a kernel class: what the method
     must move once. Records: simplex (index 8 B + diameter 4 B), column
-    (+ zero pivot cofacet 4 B + flag 1 B), reduction entry (index 8 B +
-    diameter 4 B + coefficient 4 B)."""
+    (+ zero pivot cofacet 4 B + flag 1 B), apparent-pair table record (4 x
+    8 B), reduction entry (index 8 B + diameter 4 B + coefficient 4 B)."""
     edges = counts[1] if len(counts) > 1 else 0
     dmat = 4.0 * n * n
     if name == "distances":
@@ -71,8 +77,11 @@ def kernel_bytes(name: str, n: int, counts, stats, sparse: bool) -> float | None
     if name == "edges":
         return dmat + 12.0 * edges
     if name.startswith("filter_d"):
+        # + one apparent-pair table record per zero apparent pair (tau key,
+        # rho value, rho's vertices, its neighbour-list span: 4 x 8 B)
         k = int(name[-1])
-        return 12.0 * counts[k] + 17.0 * stats[k]["columns"] + (8.0 * edges if sparse else dmat)
+        return (12.0 * counts[k] + 17.0 * stats[k]["columns"] + 32.0 * stats[k]["apparent_col"]
+                + (8.0 * edges if sparse else dmat))
     if name.startswith("expand_d"):
         k = int(name[-1])
         return 12.0 * counts[k - 1] + 12.0 * counts[k] + (8.0 * edges if sparse else dmat)
@@ -110,43 +119,84 @@ def read_pmc_summary():
     return {k: (f * 1024.0 * ff, w * 1024.0 * fw) for k, (f, w) in rows.items()}
 
 
+def _load_counter(d: str, counter: str):
+    """{kernel name: [(dispatch id, value)]} for one counter of a rocprofv3
+    --pmc run (csv output)."""
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    per = {}
+    for fpath in files:
+        with open(fpath) as fh:
+            for r in csv.DictReader(fh):
+                if r.get("Counter_Name") != counter:
+                    continue
+                name = r.get("Kernel_Name", "")
+                per.setdefault(name, []).append((int(r.get("Dispatch_Id", 0)),
+                                                 float(r["Counter_Value"])))
+    return per
+
+
+def _classify(per):
+    """Mean value per dispatch of each kernel class. A reduction belongs to
+    the dimension of the filter dispatched before it; filters alternate d1,
+    d2 in every barcode."""
+    allr = sorted((d, name, v) for name, lst in per.items() for d, v in lst)
+    out, nfilter, dim, copies = {}, 0, 0, []
+    for _, name, v in allr:
+        if "k_filter" in name:
+            dim = 1 + nfilter % 2
+            nfilter += 1
+            out.setdefault(f"filter_d{dim}", []).append(v)
+        elif "k_reduce" in name:
+            out.setdefault(f"reduce_d{dim}", []).append(v)
+        elif "copy" in name.lower() or "elementwise" in name.lower():
+            copies.append(v)
+    if copies:
+        out["copy"] = [max(copies)]
+    return {k: sum(v) / len(v) for k, v in out.items()}
+
+
+# Instruction counters of the vector-ALU pass (one rocprofv3 --pmc run)
+VALU_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD",
+                 "SQ_INSTS_LDS", "SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY")
+# Vector-ALU issue peak: 256 CUs x 2.4 GHz x one wave64 instruction per CU
+# per cycle (four SIMD16 units, four cycles per wave64 instruction each)
+VALU_PEAK_GIPS = 256 * 2.4 * 1.0
+
+
+def summarize_valu(d: str) -> int:
+    """Print the profiles/ summary of a rocprofv3 --pmc run of
+    `bench.py --pmc-run` with VALU_COUNTERS: mean per dispatch per class."""
+    per = {c: _classify(_load_counter(d, c)) for c in VALU_COUNTERS}
+    print("# instruction counters per dispatch, rocprofv3 --pmc, so3-1000 barcode")
+    print(f"source_sha256 {source_hash()}")
+    kinds = sorted({k for v in per.values() for k in v if k != "copy"})
+    for k in kinds:
+        print(f"kernel {k} " + " ".join(f"{c} {per[c].get(k, 0.0):.0f}" for c in VALU_COUNTERS))
+    return 0
+
+
+def read_valu_summary():
+    """{class: {counter: value per dispatch}} or None when absent or stale."""
+    if not os.path.exists(PMC_VALU_SUMMARY):
+        return None
+    out, sha = {}, None
+    for ln in open(PMC_VALU_SUMMARY):
+        parts = ln.split()
+        if not parts or parts[0].startswith("#"):
+            continue
+        if parts[0] == "source_sha256":
+            sha = parts[1]
+        elif parts[0] == "kernel":
+            out[parts[1]] = {parts[q]: float(parts[q + 1]) for q in range(2, len(parts) - 1, 2)}
+    return out if sha == source_hash() else None
+
+
 def summarize_pmc(fetch_dir: str, write_dir: str) -> int:
     """Print the profiles/ summary from two rocprofv3 --pmc runs of
     `bench.py --pmc-run` (FETCH_SIZE, then WRITE_SIZE): mean KiB per
     dispatch for each kernel class, and the copy kernel's reading."""
-    def load(d, counter):
-        files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-        per = {}
-        for fpath in files:
-            with open(fpath) as fh:
-                for r in csv.DictReader(fh):
-                    if r.get("Counter_Name") != counter:
-                        continue
-                    name = r.get("Kernel_Name", "")
-                    per.setdefault(name, []).append((int(r.get("Dispatch_Id", 0)),
-                                                     float(r["Counter_Value"])))
-        return per
-
-    def classify(per):
-        # a reduction belongs to the dimension of the filter dispatched before
-        # it; filters alternate d1, d2 in every barcode
-        allr = sorted((d, name, v) for name, lst in per.items() for d, v in lst)
-        out, nfilter, dim, copies = {}, 0, 0, []
-        for _, name, v in allr:
-            if "k_filter" in name:
-                dim = 1 + nfilter % 2
-                nfilter += 1
-                out.setdefault(f"filter_d{dim}", []).append(v)
-            elif "k_reduce" in name:
-                out.setdefault(f"reduce_d{dim}", []).append(v)
-            elif "copy" in name.lower() or "elementwise" in name.lower():
-                copies.append(v)
-        if copies:
-            out["copy"] = [max(copies)]
-        return {k: sum(v) / len(v) for k, v in out.items()}
-
-    f = classify(load(fetch_dir, "FETCH_SIZE"))
-    w = classify(load(write_dir, "WRITE_SIZE"))
+    f = _classify(_load_counter(fetch_dir, "FETCH_SIZE"))
+    w = _classify(_load_counter(write_dir, "WRITE_SIZE"))
     print("# HBM traffic per dispatch, rocprofv3 counters (KiB), so3-1000 barcode")
     print(f"source_sha256 {source_hash()}")
     print(f"copy_bytes {COPY_BYTES}")
@@ -207,9 +257,12 @@ def main() -> int:
                     help="counter runs: a few steps plus one plain copy of known size")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR")
+    ap.add_argument("--summarize-valu", metavar="PMC_DIR")
     args = ap.parse_args()
     if args.summarize_pmc:
         return summarize_pmc(*args.summarize_pmc)
+    if args.summarize_valu:
+        return summarize_valu(args.summarize_valu)
     if args.summarize_trace:
         return summarize_trace(args.summarize_trace)
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -277,6 +330,7 @@ def main() -> int:
     stats = info["stats"]
     sparse = info["sparse"]
     pmc = read_pmc_summary()
+    valu = read_valu_summary()
 
     def roof(name):
         ms, calls = prof[name]
@@ -296,8 +350,24 @@ def main() -> int:
             "avg_launch_us": round(per_launch_ms * 1e3, 3),
         }
 
+    def alu(name):
+        """Vector-ALU issue rate of a kernel class: VALU wave instructions
+        per dispatch (committed counter summary) over the live launch time;
+        LDS instructions alongside. None when the summary is stale."""
+        row = valu.get(name) if valu else None
+        if not row:
+            return None
+        ms, calls = prof[name]
+        sec = ms / calls * 1e-3
+        ach = row["SQ_INSTS_VALU"] / sec / 1e9
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_GIPS,
+                "unit": "G wave64 VALU instructions/s", "frac": round(ach / VALU_PEAK_GIPS, 5),
+                "lds_instructions": row.get("SQ_INSTS_LDS"),
+                "vmem_read_instructions": row.get("SQ_INSTS_VMEM_RD")}
+
     dname = max(prof.items(), key=lambda kv: kv[1][0])[0]
     roofline = roof(dname)
+    roofline["valu"] = alu(dname)
     if dname.startswith("reduce_d"):
         k = int(dname[-1])
         s = stats[k]
@@ -312,6 +382,7 @@ def main() -> int:
         enum_pass = roof(fname)
         fms, fc = prof[fname]
         enum_pass["candidates_per_s"] = round(counts[max_dim] / (fms / fc * 1e-3), 1)
+        enum_pass["valu"] = alu(fname)
 
     eliminated = {}
     for k in range(1, max_dim + 1):
