@@ -38,7 +38,9 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in sources():
         obj = os.path.join(CSRC, os.path.basename(src) + ".o")
-        cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
+        # RIPS_PHASE_TIMERS=1 compiles the reduction's phase timers in (profiling only)
+        extra = ["-DRIPS_PHASE_TIMERS=1"] if os.environ.get("RIPS_PHASE_TIMERS") == "1" else []
+        cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         out = "\n".join(ln for ln in (r.stdout + r.stderr).splitlines()
                         if "packed-fp32-ops" not in ln)

@@ -656,15 +656,68 @@ __device__ __forceinline__ bool older(const PivotCand &a, const PivotCand &b) {
     return a.idx > b.idx;
 }
 
-__device__ __forceinline__ PivotCand wave_oldest(PivotCand x) {
-    for (int off = 32; off >= 1; off >>= 1) {
-        PivotCand y;
-        y.diam = __shfl_xor(x.diam, off, kWave);
-        y.idx = __shfl_xor(x.idx, off, kWave);
-        y.coef = __shfl_xor(x.coef, off, kWave);
-        if (older(y, x)) x = y;
+// Wave reductions over DPP lane moves (no LDS round trips): row shifts by
+// 1, 2, 4 and 8 leave each row's minimum (maximum) in its last lane, and the
+// row broadcasts of lanes 15 and 31 carry those to lane 63. Lanes whose
+// source lies outside the row get the identity. Every lane of the wave must
+// be active; every lane gets the result.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ u32 dpp_min_step(u32 x) {
+    const u32 y = (u32)__builtin_amdgcn_update_dpp(-1, (int)x, kCtrl, kRowMask, 0xf, false);
+    return y < x ? y : x;
+}
+
+__device__ __forceinline__ u32 wave_min_u32(u32 x) {
+    x = dpp_min_step<0x111, 0xf>(x); // row_shr:1
+    x = dpp_min_step<0x112, 0xf>(x); // row_shr:2
+    x = dpp_min_step<0x114, 0xf>(x); // row_shr:4
+    x = dpp_min_step<0x118, 0xf>(x); // row_shr:8
+    x = dpp_min_step<0x142, 0xa>(x); // row_bcast:15 into rows 1 and 3
+    x = dpp_min_step<0x143, 0xc>(x); // row_bcast:31 into rows 2 and 3
+    return (u32)__builtin_amdgcn_readlane((int)x, kWave - 1);
+}
+
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ void dpp_max64_step(u32 &lo, u32 &hi) {
+    const u32 ylo = (u32)__builtin_amdgcn_update_dpp(0, (int)lo, kCtrl, kRowMask, 0xf, false);
+    const u32 yhi = (u32)__builtin_amdgcn_update_dpp(0, (int)hi, kCtrl, kRowMask, 0xf, false);
+    if (((u64)yhi << 32 | ylo) > ((u64)hi << 32 | lo)) {
+        lo = ylo;
+        hi = yhi;
     }
-    return x;
+}
+
+__device__ __forceinline__ u64 wave_max_u64(u64 v) {
+    u32 lo = (u32)v, hi = (u32)(v >> 32);
+    dpp_max64_step<0x111, 0xf>(lo, hi);
+    dpp_max64_step<0x112, 0xf>(lo, hi);
+    dpp_max64_step<0x114, 0xf>(lo, hi);
+    dpp_max64_step<0x118, 0xf>(lo, hi);
+    dpp_max64_step<0x142, 0xa>(lo, hi);
+    dpp_max64_step<0x143, 0xc>(lo, hi);
+    const u32 rlo = (u32)__builtin_amdgcn_readlane((int)lo, kWave - 1);
+    const u32 rhi = (u32)__builtin_amdgcn_readlane((int)hi, kWave - 1);
+    return (u64)rhi << 32 | rlo;
+}
+
+// The oldest candidate of the wave (smallest diameter, then largest index),
+// in every lane. Diameters are >= +0, so their bit patterns order as the
+// values do. All 64 lanes must be active.
+__device__ __forceinline__ PivotCand wave_oldest(PivotCand x) {
+    const u32 dk = x.idx == kEmpty ? 0xffffffffu : __float_as_uint(x.diam);
+    const u32 mn = wave_min_u32(dk);
+    PivotCand r;
+    r.idx = kEmpty;
+    r.diam = 0.0f;
+    r.coef = 0;
+    if (mn == 0xffffffffu) return r;
+    const u64 key = dk == mn ? (u64)x.idx + 1ull : 0ull; // 0 = not of the smallest diameter
+    const u64 mx = wave_max_u64(key);
+    const u64 win = __ballot(key == mx);
+    r.idx = (int64_t)(mx - 1ull);
+    r.diam = __uint_as_float(mn);
+    r.coef = (u32)__builtin_amdgcn_readlane((int)x.coef, __ffsll((unsigned long long)win) - 1);
+    return r;
 }
 
 // ---------------------------------------------------------------------------

@@ -327,12 +327,25 @@ struct RedShared {
     int it_off[BT + 1];
 };
 
-// phase timers (thread 0, wall clock)
+// Phase timers (thread 0, wall clock), compiled in only with
+// RIPS_PHASE_TIMERS=1: reading the clock waits for the wave's outstanding
+// LDS and scalar loads, which costs about 5 % of the reduction's time.
+#ifndef RIPS_PHASE_TIMERS
+#define RIPS_PHASE_TIMERS 0
+#endif
+#if RIPS_PHASE_TIMERS
 #define RED_T0(v) const unsigned long long v = threadIdx.x == 0 ? wall_clock64() : 0ull
 #define RED_T1(S, i, v)                                                                            \
     do {                                                                                           \
         if (threadIdx.x == 0) (S).tm[i] += wall_clock64() - v;                                     \
     } while (0)
+#else
+#define RED_T0(v) const unsigned long long v = 0ull
+#define RED_T1(S, i, v)                                                                            \
+    do {                                                                                           \
+        (void)(v);                                                                                 \
+    } while (0)
+#endif
 
 template <int BT>
 __device__ __forceinline__ int block_scan_excl(int x, int *s_w, int *total) {
