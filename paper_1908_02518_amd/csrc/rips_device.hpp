@@ -700,6 +700,36 @@ __device__ __forceinline__ u64 wave_max_u64(u64 v) {
     return (u64)rhi << 32 | rlo;
 }
 
+// Inclusive prefix sum over the wave with the same DPP moves.
+template <int kCtrl, int kRowMask>
+__device__ __forceinline__ int dpp_add_step(int x) {
+    return x + __builtin_amdgcn_update_dpp(0, x, kCtrl, kRowMask, 0xf, false);
+}
+
+__device__ __forceinline__ int wave_scan_incl(int x) {
+    x = dpp_add_step<0x111, 0xf>(x);
+    x = dpp_add_step<0x112, 0xf>(x);
+    x = dpp_add_step<0x114, 0xf>(x);
+    x = dpp_add_step<0x118, 0xf>(x);
+    x = dpp_add_step<0x142, 0xa>(x);
+    x = dpp_add_step<0x143, 0xc>(x);
+    return x;
+}
+
+// Lane l's value in every lane, through the scalar unit (v_readlane): for a
+// source lane that is the same in the whole wave, in place of an LDS shuffle.
+__device__ __forceinline__ int lane_bcast(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ u32 lane_bcast(u32 x, int l) { return (u32)__builtin_amdgcn_readlane((int)x, l); }
+__device__ __forceinline__ float lane_bcast(float x, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ u64 lane_bcast(u64 x, int l) {
+    const u32 lo = (u32)__builtin_amdgcn_readlane((int)(u32)x, l);
+    const u32 hi = (u32)__builtin_amdgcn_readlane((int)(u32)(x >> 32), l);
+    return (u64)hi << 32 | lo;
+}
+__device__ __forceinline__ int64_t lane_bcast(int64_t x, int l) { return (int64_t)lane_bcast((u64)x, l); }
+
 // The oldest candidate of the wave (smallest diameter, then largest index),
 // in every lane. Diameters are >= +0, so their bit patterns order as the
 // values do. All 64 lanes must be active.

@@ -350,11 +350,7 @@ struct RedShared {
 template <int BT>
 __device__ __forceinline__ int block_scan_excl(int x, int *s_w, int *total) {
     const int lane = lane_id(), w = threadIdx.x / kWave;
-    int inc = x;
-    for (int o = 1; o < kWave; o <<= 1) {
-        int t = __shfl_up(inc, o, kWave);
-        if (lane >= o) inc += t;
-    }
+    const int inc = wave_scan_incl(x);
     if (lane == kWave - 1) s_w[w] = inc;
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -455,7 +451,7 @@ __device__ __forceinline__ bool far_append_w(const FarList &F, RedShared<BT> &S,
     const int leader = __ffsll((unsigned long long)m) - 1;
     int base = 0;
     if (lane == leader) base = atomicAdd(&S.fwn, __popcll(m));
-    base = __shfl(base, leader, kWave);
+    base = lane_bcast(base, leader);
     if (!pred) return true;
     const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
     if ((int64_t)pos >= F.cap) return false;
@@ -515,9 +511,9 @@ __device__ __forceinline__ PivotCand base_advance(const ReduceJob<Dist> &J, cons
         const int first = live ? __ffsll((unsigned long long)live) - 1 : kWave;
         if (valid && lane < first && slot >= 0) st(&D.coef[slot], 0u);
         if (live) {
-            out.idx = __shfl(id, first, kWave);
-            out.diam = __shfl(dm, first, kWave);
-            out.coef = __shfl(total, first, kWave);
+            out.idx = lane_bcast(id, first);
+            out.diam = lane_bcast(dm, first);
+            out.coef = lane_bcast(total, first);
             f += first;
             break;
         }
@@ -932,7 +928,7 @@ __device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
                 const int leader = __ffsll((unsigned long long)m) - 1;
                 int base = 0;
                 if (lane == leader) base = atomicAdd(&S.pn, __popcll(m));
-                base = __shfl(base, leader, kWave);
+                base = lane_bcast(base, leader);
                 if (pull) {
                     const int64_t pos = F.cap - 1 - (base + __popcll(m & ((1ull << lane) - 1ull)));
                     pick(F.idx, nb)[pos] = ids[u];
@@ -1325,13 +1321,13 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
         RED_T0(t_r1);
         PairHit hit{-1, kNoVerts, 0, kNoList};
         if (lane == 0) hit = pair_find_all(app, piv.idx);
-        const int64_t a = __shfl(hit.val, 0, kWave);
+        const int64_t a = lane_bcast(hit.val, 0);
         RED_T1(S, 20, t_r1);
         if (a < 0) break;
         RED_T0(t_r2);
-        const u64 vw = (u64)__shfl((long long)hit.verts, 0, kWave);
-        const u64 nbw = (u64)__shfl((long long)hit.nbr, 0, kWave);
-        const u64 cbw = (u64)__shfl((long long)hit.cob, 0, kWave);
+        const u64 vw = lane_bcast(hit.verts, 0);
+        const u64 nbw = lane_bcast(hit.nbr, 0);
+        const u64 cbw = lane_bcast(hit.cob, 0);
         // rho's vertices, and the candidate source: the neighbour list of its
         // vertex with the fewest neighbours (all vertices when dense), both
         // from the table slot
@@ -1392,7 +1388,7 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
         // a failure in any lane ends the run
         const u64 fail = __ballot(bad != 0);
         if (fail) {
-            *res = __shfl(bad, __ffsll((unsigned long long)fail) - 1, kWave);
+            *res = lane_bcast(bad, __ffsll((unsigned long long)fail) - 1);
             break;
         }
     }
@@ -1402,10 +1398,9 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
 // Block-wide minimum of two values (all threads; every thread gets both).
 template <int BT>
 __device__ __forceinline__ void block_min2(int &a, int &b, RedShared<BT> &S) {
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        a = min(a, __shfl_xor(a, o, kWave));
-        b = min(b, __shfl_xor(b, o, kWave));
-    }
+    // both are column positions (>= 0): unsigned minima
+    a = (int)wave_min_u32((u32)a);
+    b = (int)wave_min_u32((u32)b);
     const int w = threadIdx.x / kWave;
     if (lane_id() == 0) {
         S.mm[0][w] = (u32)a;
@@ -1837,7 +1832,7 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
             // no probe at all when the first column cannot be emergent (no
             // zero pivot cofacet, or that cofacet is in an apparent pair)
             const bool cand = valid && J.cols.j[col] >= 0 && !J.cols.tapp[col];
-            if (__shfl((int)cand, 0, kWave)) {
+            if (lane_bcast((int)cand, 0)) {
                 const int j = J.cols.j[col];
                 if (cand) {
                     int v[kMaxVerts];
@@ -1849,8 +1844,8 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
                 }
             }
             for (int l = 0; l < kWave - 1; ++l) {
-                const int64_t tl = __shfl(tau, l, kWave);
-                const int okl = __shfl((int)ok, l, kWave);
+                const int64_t tl = lane_bcast(tau, l);
+                const int okl = lane_bcast((int)ok, l);
                 if (l < lane && okl && tl == tau) ok = false;
             }
             const u64 bad = __ballot(!ok);
