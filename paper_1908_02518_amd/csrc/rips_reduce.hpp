@@ -1267,6 +1267,8 @@ __device__ __forceinline__ bool materialize_v(const ReduceJob<Dist> &J, const Re
 // fit the delta before its next maintenance, once that maintenance is due,
 // or after `budget` additions. Returns the additions made (the same in every
 // lane); *res gets 0 or a result code.
+constexpr int kRunScan = 4; // delta slots an apparent run scans, in units of a wave
+
 template <int BT, class Dist, bool kPar>
 __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsCol &D,
                                             const ReduceScratch &SC, int j, int budget,
@@ -1294,19 +1296,57 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
         best.diam = 0.0f;
         best.coef = 0;
         const int ns = min(*D.nslots, capD);
-        for (int i = lane; i < ns; i += kWave) {
-            const u32 sl = D.slots[i];
-            u32 cf = ld(&D.coef[sl]);
-            if (p != 2 && cf >= p) {
-                cf %= p;
-                st(&D.coef[sl], cf);
+        if (ns <= kRunScan * kWave) {
+            // at most capD / 8 <= 256 slots here: every load is issued at
+            // once, two LDS round trips in all instead of three per 64
+            // slots. Lanes past ns read list entry 0, which may never have
+            // been written: the mask keeps that slot inside the table, and
+            // the lane's result is dropped.
+            u32 sl[kRunScan];
+#pragma unroll
+            for (int r = 0; r < kRunScan; ++r) {
+                const int i = lane + r * kWave;
+                sl[r] = D.slots[i < ns ? i : 0] & D.mask;
             }
-            if (cf == 0) continue;
-            PivotCand x;
-            x.idx = ld(&D.keys[sl]);
-            x.diam = D.diam[sl];
-            x.coef = cf;
-            if (older(x, best)) best = x;
+            u32 cfs[kRunScan];
+            int64_t kys[kRunScan];
+            float dgs[kRunScan];
+#pragma unroll
+            for (int r = 0; r < kRunScan; ++r) {
+                cfs[r] = ld(&D.coef[sl[r]]);
+                kys[r] = ld(&D.keys[sl[r]]);
+                dgs[r] = D.diam[sl[r]];
+            }
+#pragma unroll
+            for (int r = 0; r < kRunScan; ++r) {
+                if (lane + r * kWave >= ns) continue;
+                u32 cf = cfs[r];
+                if (p != 2 && cf >= p) {
+                    cf %= p;
+                    st(&D.coef[sl[r]], cf);
+                }
+                if (cf == 0) continue;
+                PivotCand x;
+                x.idx = kys[r];
+                x.diam = dgs[r];
+                x.coef = cf;
+                if (older(x, best)) best = x;
+            }
+        } else {
+            for (int i = lane; i < ns; i += kWave) {
+                const u32 sl = D.slots[i];
+                u32 cf = ld(&D.coef[sl]);
+                if (p != 2 && cf >= p) {
+                    cf %= p;
+                    st(&D.coef[sl], cf);
+                }
+                if (cf == 0) continue;
+                PivotCand x;
+                x.idx = ld(&D.keys[sl]);
+                x.diam = D.diam[sl];
+                x.coef = cf;
+                if (older(x, best)) best = x;
+            }
         }
         const PivotCand dmin = wave_oldest(best);
         const bool from_base = smin.idx != kEmpty &&
