@@ -23,6 +23,9 @@ per step. Also reported:
                     256 CUs x 2.4 GHz x one wave64 instruction per CU-cycle
   batched           barcodes/s of the 512-cloud mixture batch in one
                     persistent launch vs one cloud at a time
+  paper_scale       one barcode of a paper-scale workload (o3 shape, 1024
+                    points, threshold 1.8, dims 0-3), against the CPU
+                    implementation of the paper's algorithm
   cpu_baseline      the CPU oracle on this host (a bounded sample)
   cpu_paper_algorithm  the single-threaded CPU implementation of the paper's
                     algorithm (cpu_baseline/) on the same cloud, same host
@@ -253,6 +256,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip both CPU legs (oracle and the paper's algorithm)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-paper-scale", action="store_true",
+                    help="skip the paper-scale o3-1024 (t = 1.8, dims 0-3) leg")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter runs: a few steps plus one plain copy of known size")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
@@ -430,6 +435,47 @@ def main() -> int:
             "config": list(rips.batched_get_config()),
         }
 
+    paper_scale = None
+    if not args.no_paper_scale:
+        c6 = workloads.config(6)
+        x6 = c6["clouds"][0]
+        x6t = torch.from_numpy(x6).to(dev)
+        k6 = dict(max_dim=c6["max_dim"], threshold=c6["threshold"], p=c6["p"])
+        counts6 = rips.simplex_counts(x6t, c6["max_dim"] + 1, threshold=c6["threshold"])
+        bars6, _ = rips.barcode_device(x6t, **k6)  # warm-up: scratch sizes
+        torch.cuda.synchronize()
+        ts6 = []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            bars6, _ = rips.barcode_device(x6t, **k6)
+            torch.cuda.synchronize()
+            ts6.append(time.perf_counter() - c0)
+        t6 = sorted(ts6)[1]
+        log(f"paper scale {c6['name']}: {t6:.3f} s per barcode (median of 3)")
+        paper_scale = {
+            "workload": "o3-1024-t1.8: 1024 Haar SO(3) rotations in R^9, float32, threshold 1.8, "
+                        "dims 0-3, Z/2 (the shape of the paper's o3 1024 run)",
+            "simplex_counts": counts6,
+            "seconds_per_barcode": round(t6, 4),
+            "simplices_per_s": round(sum(counts6) / t6, 1),
+            "context": "the paper reports 2.1 s for Ripser on its own o3 1024 data (t = 1.8, "
+                       "4 GHz Core i7): other data, other machine, not a target",
+        }
+        if not args.no_cpu_baseline:
+            import cpu_baseline
+            import oracle
+            cpu_baseline.build(force=False)
+            dl6 = oracle.distances(x6)  # not timed
+            c0 = time.perf_counter()
+            cb6 = cpu_baseline.barcode(dl6, x6.shape[0], **k6)
+            tc6 = time.perf_counter() - c0
+            log(f"paper scale, cpu paper algorithm: {tc6:.2f} s")
+            paper_scale["cpu_paper_algorithm_seconds"] = round(tc6, 3)
+            paper_scale["bars_equal_cpu_paper_algorithm"] = bool(all(
+                np.array_equal(getattr(cb6.bars[d], f), g.cpu().numpy())
+                for d in range(c6["max_dim"] + 1)
+                for f, g in zip(("birth", "death", "birth_simplex", "death_simplex"), bars6[d])))
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -490,6 +536,7 @@ def main() -> int:
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(prof.items())},
         "eliminated": eliminated,
         "batched": batched,
+        "paper_scale": paper_scale,
         "cpu_baseline": cpu,
         "cpu_paper_algorithm": cpu_paper,
     }

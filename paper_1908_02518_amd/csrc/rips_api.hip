@@ -699,6 +699,8 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         // reduction's pivot test; twice the candidates, so inserts never fail
         PairHash app;
         if (ncand > (1ll << 30)) return fail(RIPS_E_CAPACITY, "too many candidate simplices");
+        // table sizes are 32-bit powers of two
+        if ((uint64_t)2 * ncand + 64 > (1ull << 31)) return fail(RIPS_E_CAPACITY, "too many candidates");
         const uint32_t appcap = next_pow2((uint64_t)2 * ncand + 64);
         HIP_TRY(C.ensure(B_APP_KEYS, (size_t)appcap * 8, &q));
         app.keys = as<int64_t>(q);
@@ -773,6 +775,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         // ---- reduction
         const int slot = k & 1;
         PivotHash ph;
+        if ((uint64_t)2 * S + 64 > (1ull << 31)) return fail(RIPS_E_CAPACITY, "too many columns");
         const uint32_t phcap = next_pow2((uint64_t)2 * S + 64);
         HIP_TRY(C.ensure(B_PH_KEYS0 + slot, (size_t)phcap * 8, &q));
         ph.keys = as<int64_t>(q);

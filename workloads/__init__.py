@@ -37,6 +37,7 @@ __all__ = [
     "integer_lattice",
     "config",
     "CONFIGS",
+    "PAPER_SCALE",
 ]
 
 
@@ -174,7 +175,9 @@ def integer_lattice(n: int, m: int, seed: int, side: int = 4) -> np.ndarray:
 
 # name -> (generator thunk, max_dim, threshold (inf = none), p)
 def config(cfg_id: int):
-    """The five benchmark workloads: returns a dict describing one of them."""
+    """The five benchmark workloads (1-5), and 6: a paper-scale workload of the
+    shape of the paper's o3 run on 1024 orthogonal matrices (threshold 1.8,
+    homology up to dimension 3). Returns a dict describing one of them."""
     inf = float("inf")
     if cfg_id == 1:
         return dict(name="sphere-100", clouds=[sphere(100, SEED_BASE + 1)], max_dim=1,
@@ -191,7 +194,11 @@ def config(cfg_id: int):
     if cfg_id == 5:
         return dict(name="circles-64x400", clouds=circle_batch(64, 5), max_dim=1,
                     threshold=inf, p=2)
+    if cfg_id == 6:
+        return dict(name="o3-1024-t1.8", clouds=[so3(1024, SEED_BASE + 6)], max_dim=3,
+                    threshold=1.8, p=2)
     raise ValueError(cfg_id)
 
 
 CONFIGS = (1, 2, 3, 4, 5)
+PAPER_SCALE = (6,)
