@@ -910,7 +910,9 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             } else if (status == kRedWait) {
                 return fail(RIPS_E_HIP, "reduction: a wait for earlier columns exceeded its bound");
             } else {
-                return fail(RIPS_E_HIP, "reduction exceeded its addition bound");
+                char msg[96];
+                snprintf(msg, sizeof(msg), "reduction exceeded its addition bound (status %d)", status);
+                return fail(RIPS_E_HIP, msg);
             }
         }
         if ((int64_t)C.host_scal->vcount > C.hint_v) C.hint_v = (int64_t)C.host_scal->vcount;

@@ -298,6 +298,11 @@ struct RedShared {
     int64_t vest;
     int fw, fwn;    // far list: buffer appended to, entries in it
     int fr, nr, pn; // far list being pulled: buffer, entries; entries pulled
+    // middle level of the far part: the top quarter of each far buffer holds
+    // the far entries of diameter bits <= mb (when mon), the rest the others
+    int mw, mwn, mon;
+    u32 mb;
+    int pcount, nr2; // far_bound: entries at or under the bound; running count
     float kd;       // near part = entries older than (kd, kidx)
     int64_t kidx;
     int64_t len, f; // sorted base: length and front
@@ -439,27 +444,50 @@ __device__ __forceinline__ bool is_near(const RedShared<BT> &S, float dm, int64_
     return older_key(dm, key, S.kd, S.kidx);
 }
 
-// Append the lanes' entries with pred to the far list, one atomic per wave.
+// The far part has two levels in each of its two buffers: the bottom holds
+// the far list proper, the top quarter (from far_mbase) a middle level with
+// every far entry of diameter bits <= mb while it is in use. A pull then
+// scans the middle level only; when that runs empty, one pass over the far
+// list moves its oldest entries up. Buffers too small for a middle level
+// keep the far list alone.
+__device__ __forceinline__ int64_t far_mcap(const FarList &F) {
+    return F.cap >= (int64_t)16 * kMaxDelta ? F.cap / 4 : 0;
+}
+
+// One wave's appends with pred to one level: one atomic per wave. Positions
+// at or past lim fail.
+__device__ __forceinline__ bool far_level_append(const FarList &F, int *count, int buf, int64_t base,
+                                                 int64_t lim, bool pred, int64_t key, float dm, u32 c) {
+    const u64 m = __ballot(pred);
+    if (!m) return true;
+    const int lane = lane_id();
+    const int leader = __ffsll((unsigned long long)m) - 1;
+    int at = 0;
+    if (lane == leader) at = atomicAdd(count, __popcll(m));
+    at = lane_bcast(at, leader);
+    if (!pred) return true;
+    const int64_t pos = at + __popcll(m & ((1ull << lane) - 1ull));
+    if (pos >= lim) return false;
+    pick(F.idx, buf)[base + pos] = key;
+    pick(F.dia, buf)[base + pos] = dm;
+    pick(F.coef, buf)[base + pos] = c;
+    return true;
+}
+
+// Append the lanes' entries with pred to the far part, each to its level.
 // Every lane of the wave must call it. Returns false on the lanes whose
 // entry did not fit.
 template <int BT>
 __device__ __forceinline__ bool far_append_w(const FarList &F, RedShared<BT> &S, bool pred,
                                              int64_t key, float dm, u32 c) {
-    const u64 m = __ballot(pred);
-    if (!m) return true;
-    const int lane = lane_id();
-    const int leader = __ffsll((unsigned long long)m) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(&S.fwn, __popcll(m));
-    base = lane_bcast(base, leader);
-    if (!pred) return true;
-    const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
-    if ((int64_t)pos >= F.cap) return false;
-    const int b = S.fw;
-    pick(F.idx, b)[pos] = key;
-    pick(F.dia, b)[pos] = dm;
-    pick(F.coef, b)[pos] = c;
-    return true;
+    const int64_t mcap = far_mcap(F);
+    const bool mid = pred && S.mon && __float_as_uint(dm) <= S.mb;
+    // the far list stays below the middle level; the middle level keeps a
+    // segment of slack at its top for the entries a pull reads from there
+    const bool a = far_level_append(F, &S.fwn, S.fw, 0, F.cap - mcap, pred && !mid, key, dm, c);
+    const bool b = far_level_append(F, &S.mwn, S.mw, F.cap - mcap, mcap - kMaxDelta / 8, mid, key, dm,
+                                    c);
+    return a && b;
 }
 
 // Add the lanes' entries (act) to the working column: near -> delta, far ->
@@ -802,60 +830,41 @@ __device__ __forceinline__ int delta_check(const LdsCol &D, const Staging &G,
     return base_split<BT>(SC.SB, SC.F, p, capD, S);
 }
 
-// The near part is empty and the far list is not: raise the boundary to a
-// diameter d such that about `target` far entries have diameter <= d, and
-// move those into the delta. d comes from a histogram of the diameters' bit
-// patterns (non-negative floats order like their bits) over [kd, tmax],
-// refined while the chosen bin holds far more than the target.
+// Bound of a histogram over the diameter bit patterns (non-negative floats
+// order like their bits) of n far entries fd[0, n), over [lo, hi]: the
+// smallest bin top with about `target` entries at or under it, refined while
+// the chosen bin alone holds more than `factor` times the target. Sets
+// S.bound (capped at cap_bits) and S.pcount, the entries at or under it.
 template <int BT>
-__device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
-                                        const ReduceScratch &SC, u32 p, int target, float tmax,
-                                        RedShared<BT> &S) {
-    const FarList &F = SC.F;
+__device__ __forceinline__ void far_bound(const float *fd, int n, u32 lo, u32 hi, u32 cap_bits,
+                                          int target, int factor, RedShared<BT> &S) {
     const int tid = threadIdx.x;
-    RED_T0(t_pull);
     if (tid == 0) {
-        S.fr = S.fw;
-        S.nr = S.fwn;
-        S.fw = S.fw ^ 1;
-        S.fwn = 0;
-        S.merged = 1;
-        S.stat[8] += 1;
-        S.stat[11] += S.nr;
-        const u32 lo = __float_as_uint(S.kd);
-        const u32 hi = max(lo, __float_as_uint(tmax));
-        const u32 span = hi - lo;
+        const u32 span = max(lo, hi) - lo;
         const int nb = span ? 32 - __clz(span) : 0;
         S.lo = lo;
         S.shift = nb > 8 ? nb - 8 : 0;
-        S.bound = hi;
         S.refine = 1;
     }
     __syncthreads();
-    const int fr = S.fr, nr = S.nr;
-    // the new buffer holds the kept entries at the bottom and the pulled ones
-    // at the top; a segment's worth of slack keeps the entries sent back
-    // while a segment is being read below the part not read yet
-    if ((int64_t)nr + ((int)D.mask + 1) / 8 > F.cap) return kRedFarFull;
-    int below = 0; // entries under S.lo (all pulled)
+    int below = 0; // entries under S.lo (all taken)
     while (S.refine) {
         for (int i = tid; i < 256; i += BT) S.hist[i] = 0;
         __syncthreads();
-        const u32 lo = S.lo;
+        const u32 l = S.lo;
         const int sh = S.shift;
-        const float *fd = pick(F.dia, fr);
         // kPullUnroll independent loads in flight per thread
-        for (int b0 = 0; b0 < nr; b0 += kPullUnroll * BT) {
+        for (int b0 = 0; b0 < n; b0 += kPullUnroll * BT) {
             u32 bb[kPullUnroll];
 #pragma unroll
             for (int u = 0; u < kPullUnroll; ++u) {
                 const int r = b0 + u * BT + tid;
-                bb[u] = r < nr ? __float_as_uint(fd[r]) : 0xffffffffu;
+                bb[u] = r < n ? __float_as_uint(fd[r]) : 0xffffffffu;
             }
 #pragma unroll
             for (int u = 0; u < kPullUnroll; ++u) {
-                if (bb[u] == 0xffffffffu || bb[u] < lo) continue;
-                const u32 bin = (bb[u] - lo) >> sh;
+                if (bb[u] == 0xffffffffu || bb[u] < l) continue;
+                const u32 bin = (bb[u] - l) >> sh;
                 atomicAdd(&S.hist[bin < 256 ? bin : 255], 1u);
             }
         }
@@ -868,50 +877,63 @@ __device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
             }
             if (i == 256) i = 255;
             const int before = cum - (int)S.hist[i];
-            if (cum > 8 * target && sh > 0 && S.hist[i] > 1) {
+            if (cum > factor * target && sh > 0 && S.hist[i] > 1) {
                 // bin i alone is far too full: split it
-                S.lo = lo + ((u32)i << sh);
+                S.lo = l + ((u32)i << sh);
                 S.shift = sh > 8 ? sh - 8 : 0;
-                S.nr = before; // reuse as the running count below lo
+                S.nr2 = before; // the running count below lo
             } else {
-                // the last bin takes everything: +inf, whose bits bound every
-                // finite diameter (a larger pattern would be a NaN boundary,
-                // which nothing is older than)
-                const u64 inf_bits = 0x7f800000ull;
-                const u64 top = i == 255 ? inf_bits : (u64)lo + ((u64)(i + 1) << sh) - 1;
-                S.bound = (u32)(top > inf_bits ? inf_bits : top);
+                // the last bin takes everything up to cap_bits (+inf for the
+                // far list: its bits bound every finite diameter, and a larger
+                // pattern would be a NaN boundary, which nothing is older than)
+                const u64 top = i == 255 ? (u64)cap_bits : (u64)l + ((u64)(i + 1) << sh) - 1;
+                S.bound = (u32)(top > (u64)cap_bits ? (u64)cap_bits : top);
+                // entries in bin 255 above cap_bits cannot exist: every source
+                // holds entries at or under its cap only
+                S.pcount = cum;
                 S.refine = 0;
             }
         }
         __syncthreads();
-        below = S.refine ? S.nr : below;
+        below = S.refine ? S.nr2 : below;
         __syncthreads();
     }
+}
+
+// Pull from n entries at src (buffer sb, from offset so): raise the boundary
+// to S.bound, move the entries at or under it to the top of buffer db and
+// append the rest to the far part (far_append_w puts each in its level),
+// then feed the moved ones into the delta in segments. `room` is the space
+// the top of db may take (a segment of slack included).
+template <int BT>
+__device__ __forceinline__ int far_pull_core(const LdsCol &D, const Staging &G, const ReduceScratch &SC,
+                                             u32 p, int sb, int64_t so, int n, int db, int64_t room,
+                                             RedShared<BT> &S) {
+    const FarList &F = SC.F;
+    const int tid = threadIdx.x;
+    if ((int64_t)n + ((int)D.mask + 1) / 8 > room) return kRedFarFull;
     if (tid == 0) {
         // new boundary (d, -1): every entry of diameter <= d is near
         S.kd = __uint_as_float(S.bound);
         S.kidx = -1;
-        S.nr = nr;
         S.pn = 0;
     }
     __syncthreads();
-    RED_T1(S, 3, t_pull);
     // partition without barriers: entries under the bound go to the top of
-    // the new buffer (slot cap - 1 - i for the i-th), the rest to its bottom
+    // buffer db (slot cap - 1 - i for the i-th), the rest to the far part
     const u32 bound = S.bound;
-    const int nb = S.fw;
     bool ok = true;
-    const int64_t *fi = pick(F.idx, fr);
-    const float *fd = pick(F.dia, fr);
-    const u32 *fc = pick(F.coef, fr);
-    for (int b0 = 0; b0 < nr; b0 += kPullUnroll * BT) {
+    const int64_t *fi = pick(F.idx, sb) + so;
+    const float *fd = pick(F.dia, sb) + so;
+    const u32 *fc = pick(F.coef, sb) + so;
+    for (int b0 = 0; b0 < n; b0 += kPullUnroll * BT) {
         int64_t ids[kPullUnroll];
         float dms[kPullUnroll];
         u32 cfs[kPullUnroll];
 #pragma unroll
         for (int u = 0; u < kPullUnroll; ++u) {
             const int r = b0 + u * BT + tid;
-            const bool act = r < nr;
+            const bool act = r < n;
             ids[u] = act ? fi[r] : 0;
             dms[u] = act ? fd[r] : 0.0f;
             cfs[u] = act ? fc[r] : 0u;
@@ -919,7 +941,7 @@ __device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
 #pragma unroll
         for (int u = 0; u < kPullUnroll; ++u) {
             const int r = b0 + u * BT + tid;
-            const bool act = r < nr;
+            const bool act = r < n;
             const bool pull = act && __float_as_uint(dms[u]) <= bound;
             ok = far_append_w<BT>(F, S, act && !pull, ids[u], dms[u], cfs[u]) && ok;
             const u64 m = __ballot(pull);
@@ -931,9 +953,9 @@ __device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
                 base = lane_bcast(base, leader);
                 if (pull) {
                     const int64_t pos = F.cap - 1 - (base + __popcll(m & ((1ull << lane) - 1ull)));
-                    pick(F.idx, nb)[pos] = ids[u];
-                    pick(F.dia, nb)[pos] = dms[u];
-                    pick(F.coef, nb)[pos] = cfs[u];
+                    pick(F.idx, db)[pos] = ids[u];
+                    pick(F.dia, db)[pos] = dms[u];
+                    pick(F.coef, db)[pos] = cfs[u];
                 }
             }
         }
@@ -942,9 +964,15 @@ __device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
     gsync();
     if (S.abort) return S.abort;
     // the pulled entries into D, in segments, read upwards from the lowest
-    // slot: whatever a split sends back to the bottom of the buffer stays
-    // below the part not read yet (both come out of the same nr entries)
+    // slot: whatever a split sends back to the bottom of the level stays
+    // below the part not read yet (both come out of the same n entries)
     const int pn = S.pn;
+    // the entries of the smallest diameter in the source are under the
+    // bound, so a pull always moves some; one that moved none would repeat
+    // forever: report it instead. (The near part may still end up empty:
+    // copies of one key in the far part can cancel. The caller then pulls
+    // again, from a far part that has shrunk.)
+    if (pn == 0) return kRedBound;
     const int64_t pbase = F.cap - pn;
     const int seg = ((int)D.mask + 1) / 8;
     for (int s0 = 0; s0 < pn; s0 += seg) {
@@ -954,9 +982,9 @@ __device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
             const int e = b0 + tid;
             const bool act = e < s1;
             const int64_t pos = pbase + e;
-            const int rr = add_entry_w<BT>(D, F, S, act, act ? pick(F.idx, nb)[pos] : 0,
-                                           act ? pick(F.dia, nb)[pos] : 0.0f,
-                                           act ? pick(F.coef, nb)[pos] : 0u, p);
+            const int rr = add_entry_w<BT>(D, F, S, act, act ? pick(F.idx, db)[pos] : 0,
+                                           act ? pick(F.dia, db)[pos] : 0.0f,
+                                           act ? pick(F.coef, db)[pos] : 0u, p);
             if (rr) bad = rr;
         }
         if (bad) S.abort = bad;
@@ -965,11 +993,106 @@ __device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
         const int r = delta_check<BT>(D, G, SC, p, S);
         if (r) return r;
     }
-    // every entry of the smallest diameter in the list is under the bound,
-    // so the near part cannot be empty now; if it were, the caller would
-    // pull forever: report it instead
-    if (*D.nslots == 0 && S.len == S.f) return kRedBound;
     return kRedOk;
+}
+
+// The near part is empty and the far part is not: raise the boundary to a
+// diameter d such that about `target` far entries have diameter <= d, and
+// move those into the delta. From the middle level while it holds entries;
+// when it is empty and the far list is long, one pass first moves the far
+// list's oldest entries (about sqrt(far list x target) of them) up into it;
+// otherwise straight from the far list.
+template <int BT>
+__device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
+                                        const ReduceScratch &SC, u32 p, int target, float tmax,
+                                        RedShared<BT> &S) {
+    const FarList &F = SC.F;
+    const int tid = threadIdx.x;
+    const int64_t mcap = far_mcap(F);
+    const int64_t mbase = F.cap - mcap;
+    RED_T0(t_pull);
+    // every thread reads the middle level's count before thread 0 rewrites it
+    const int mwn0 = S.mwn;
+    __syncthreads();
+    if (mwn0 == 0) {
+        // middle level empty: the far list's buffers swap
+        if (tid == 0) {
+            S.fr = S.fw;
+            S.nr = S.fwn;
+            S.fw = S.fw ^ 1;
+            S.fwn = 0;
+            S.mon = 0;
+            S.merged = 1;
+            S.stat[8] += 1;
+            S.stat[11] += S.nr;
+        }
+        __syncthreads();
+        const int fr = S.fr, nr = S.nr;
+        const u32 lo = __float_as_uint(S.kd);
+        const u32 hi = max(lo, __float_as_uint(tmax));
+        const int64_t want = (int64_t)sqrtf((float)nr * (float)target);
+        bool refilled = false;
+        if (mcap > 0 && nr > 8 * target && want > 2 * (int64_t)target) {
+            const int tm = (int)min(want, mcap / 4);
+            far_bound<BT>(pick(F.dia, fr), nr, lo, hi, 0x7f800000u, tm, 2, S);
+            if (S.pcount > 0 && (int64_t)S.pcount <= mcap / 2) {
+                // refill: everything goes back to the far part, the entries
+                // at or under mb into the middle level (empty before)
+                if (tid == 0) {
+                    S.mon = 1;
+                    S.mb = S.bound;
+                    S.mw = 0;
+                    S.mwn = 0;
+                }
+                __syncthreads();
+                bool ok = true;
+                const int64_t *fi = pick(F.idx, fr);
+                const float *fd = pick(F.dia, fr);
+                const u32 *fc = pick(F.coef, fr);
+                for (int b0 = 0; b0 < nr; b0 += kPullUnroll * BT) {
+#pragma unroll
+                    for (int u = 0; u < kPullUnroll; ++u) {
+                        const int r = b0 + u * BT + tid;
+                        const bool act = r < nr;
+                        ok = far_append_w<BT>(F, S, act, act ? fi[r] : 0, act ? fd[r] : 0.0f,
+                                              act ? fc[r] : 0u) &&
+                             ok;
+                    }
+                }
+                if (!ok) S.abort = kRedFarFull;
+                gsync();
+                if (S.abort) return S.abort;
+                // pcount entries are at or under mb: the middle level holds them
+                const int got = S.mwn;
+                __syncthreads(); // read by every thread before the pull below rewrites it
+                if (got == 0) return kRedBound;
+                refilled = true;
+            }
+        }
+        if (!refilled) {
+            // straight from the far list (the middle level is off and empty,
+            // so the top of the new buffer is free)
+            far_bound<BT>(pick(F.dia, fr), nr, lo, hi, 0x7f800000u, target, 8, S);
+            RED_T1(S, 3, t_pull);
+            return far_pull_core<BT>(D, G, SC, p, fr, 0, nr, S.fw, F.cap, S);
+        }
+    }
+    // from the middle level: its buffers swap; the bound stays at or under mb
+    if (tid == 0) {
+        S.nr = S.mwn;
+        S.fr = S.mw;
+        S.mw = S.mw ^ 1;
+        S.mwn = 0;
+        S.merged = 1;
+        S.stat[8] += 1;
+        S.stat[11] += S.nr;
+    }
+    __syncthreads();
+    const int mr = S.fr, nm = S.nr;
+    const u32 lo = __float_as_uint(S.kd);
+    far_bound<BT>(pick(F.dia, mr) + mbase, nm, lo, max(lo, S.mb), S.mb, target, 8, S);
+    RED_T1(S, 3, t_pull);
+    return far_pull_core<BT>(D, G, SC, p, mr, mbase, nm, S.mw, mcap, S);
 }
 
 // ---------------------------------------------------------------------------
@@ -1518,6 +1641,10 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         S.kidx = -1;
         S.fw = 0;
         S.fwn = 0;
+        S.mw = 0;
+        S.mwn = 0;
+        S.mon = 0;
+        S.mb = 0;
         S.nlog = 0;
         S.vest = 1;
         S.nit = 1;
@@ -1576,7 +1703,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             from_base = smin.idx != kEmpty &&
                         (dmin.idx == kEmpty || dmin.idx == smin.idx || !older(dmin, smin));
             piv = from_base ? smin : dmin;
-            if (piv.idx != kEmpty || S.fwn == 0) break;
+            if (piv.idx != kEmpty || (S.fwn == 0 && S.mwn == 0)) break;
             result = far_pull<BT>(D, G, SC, p, ((int)D.mask + 1) / 2, c.t, S);
             if (result) break;
         }
@@ -1726,7 +1853,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         RED_T0(t_st);
         int64_t roff = 0;
         int rn = -1;
-        if (S.fwn == 0) {
+        if (S.fwn == 0 && S.mwn == 0) {
             if (S.len > 0 && *D.nslots > 0) {
                 result = base_merge<BT>(D, G, SC.SB, p, S);
                 if (result) break;
@@ -1815,7 +1942,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             S.stat[2] += nadd;
             if (S.merged) S.stat[5] += 1;
         }
-        const unsigned long long sz = (unsigned long long)(S.len - S.f + S.fwn + *D.nslots);
+        const unsigned long long sz = (unsigned long long)(S.len - S.f + S.fwn + S.mwn + *D.nslots);
         if (sz > S.stat[7]) S.stat[7] = sz;
     }
     __syncthreads();
