@@ -809,9 +809,9 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         int64_t fcap = spread ? std::max<int64_t>(C.hint_far, 1 << 16)
                               : std::max<int64_t>(C.hint_far, std::max<int64_t>(1 << 18, 256ll * bound));
         int64_t vwcap = std::max<int64_t>(C.hint_vw, 1 << 14);
-        // one log entry per addition: (2^18 + 64) never overflows
-        const int64_t lmax = (1 << 18) + 64;
-        int64_t lcap = spread ? std::max<int64_t>(C.hint_log, 1 << 14) : lmax;
+        // one log entry per addition: the log grows on overflow, up to the addition bound
+        const int64_t lmax = (int64_t)kMaxAdditions + 64;
+        int64_t lcap = std::max<int64_t>(C.hint_log, spread ? 1 << 14 : (1 << 18) + 64);
         BarBuf cbars = bars[k];
         if (spread) {
             HIP_TRY(C.ensure(B_CBAR_BIRTH, (size_t)S * 4, &q));
@@ -909,9 +909,11 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
                 return fail(RIPS_E_HIP, "reduction log overflow");
             } else if (status == kRedWait) {
                 return fail(RIPS_E_HIP, "reduction: a wait for earlier columns exceeded its bound");
+            } else if (status == kRedBound) {
+                return fail(RIPS_E_CAPACITY, "reduction: a column exceeded the bound of 2^24 additions");
             } else {
                 char msg[96];
-                snprintf(msg, sizeof(msg), "reduction exceeded its addition bound (status %d)", status);
+                snprintf(msg, sizeof(msg), "reduction: internal consistency check %d failed", status);
                 return fail(RIPS_E_HIP, msg);
             }
         }

@@ -135,6 +135,12 @@ __device__ __forceinline__ ReduceScratch make_scratch(const ReduceBuffers &b, So
     return sc;
 }
 
+// Additions one column may take before the reduction reports an error: every
+// addition moves the pivot to a strictly younger row, so the loop ends; the
+// bound only turns a fault into an error. The addition log (one entry per
+// addition) grows on demand up to it.
+constexpr int kMaxAdditions = 1 << 24;
+
 // Result codes of the reduction.
 enum : int {
     kRedOk = 0,
@@ -146,6 +152,9 @@ enum : int {
     kRedLogFull = 6,   // addition log too small
     kRedAbort = 7,     // another workgroup of the launch failed
     kRedWait = 8,      // a wait for the columns before exceeded its bound
+    kRedNoPull = 9,    // a pull of the far part moved nothing (cannot happen)
+    kRedOrder = 10,    // a column after j owns a pivot j looks up (cannot happen)
+    kRedRefill = 11,   // the middle level came out of a refill empty (cannot happen)
 };
 
 // Bound of one wait in the spread-out reduction, in wall-clock ticks
@@ -972,7 +981,7 @@ __device__ __forceinline__ int far_pull_core(const LdsCol &D, const Staging &G, 
     // forever: report it instead. (The near part may still end up empty:
     // copies of one key in the far part can cancel. The caller then pulls
     // again, from a far part that has shrunk.)
-    if (pn == 0) return kRedBound;
+    if (pn == 0) return kRedNoPull;
     const int64_t pbase = F.cap - pn;
     const int seg = ((int)D.mask + 1) / 8;
     for (int s0 = 0; s0 < pn; s0 += seg) {
@@ -1065,7 +1074,7 @@ __device__ __forceinline__ int far_pull(const LdsCol &D, const Staging &G,
                 // pcount entries are at or under mb: the middle level holds them
                 const int got = S.mwn;
                 __syncthreads(); // read by every thread before the pull below rewrites it
-                if (got == 0) return kRedBound;
+                if (got == 0) return kRedRefill;
                 refilled = true;
             }
         }
@@ -1665,7 +1674,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         __syncthreads();
         // every addition moves the pivot to a strictly younger row, so the
         // loop ends; the bound only turns a fault into an error
-        if (nadd > (1 << 18)) {
+        if (nadd > kMaxAdditions) {
             result = kRedBound;
             break;
         }
@@ -1674,7 +1683,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             RED_T0(t_fast);
             if (w == 0) {
                 int r;
-                const int na = apparent_run<BT, Dist, kPar>(J, D, SC, j, (1 << 18) + 1 - nadd, S, &r);
+                const int na = apparent_run<BT, Dist, kPar>(J, D, SC, j, kMaxAdditions + 1 - nadd, S, &r);
                 if (lane == 0) {
                     S.fa_n = na;
                     S.fa_r = r;
@@ -1758,7 +1767,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         RED_T1(S, 11, t_own);
         const int64_t o = S.owner;
         if (kPar && o >= j) {
-            result = kRedBound; // only a column before j can own a pivot j looks up
+            result = kRedOrder; // only a column before j can own a pivot j looks up
             break;
         }
         if (kPar && o >= 0) fence_acquire_dev(); // the owner's published column
