@@ -175,9 +175,11 @@ def integer_lattice(n: int, m: int, seed: int, side: int = 4) -> np.ndarray:
 
 # name -> (generator thunk, max_dim, threshold (inf = none), p)
 def config(cfg_id: int):
-    """The five benchmark workloads (1-5), and 6: a paper-scale workload of the
-    shape of the paper's o3 run on 1024 orthogonal matrices (threshold 1.8,
-    homology up to dimension 3). Returns a dict describing one of them."""
+    """The five benchmark workloads (1-5), and two at paper scale: 6, the shape
+    of the paper's o3 run on 1024 orthogonal matrices (threshold 1.8, homology
+    up to dimension 3), and 7, a 10,000-point Clifford torus (threshold 0.25,
+    up to dimension 2) on the way to the paper's 50,000-point torus. Returns a
+    dict describing one of them."""
     inf = float("inf")
     if cfg_id == 1:
         return dict(name="sphere-100", clouds=[sphere(100, SEED_BASE + 1)], max_dim=1,
@@ -197,8 +199,11 @@ def config(cfg_id: int):
     if cfg_id == 6:
         return dict(name="o3-1024-t1.8", clouds=[so3(1024, SEED_BASE + 6)], max_dim=3,
                     threshold=1.8, p=2)
+    if cfg_id == 7:
+        return dict(name="torus4-10000-t0.25", clouds=[clifford_torus(10000, 0.02, SEED_BASE + 7)],
+                    max_dim=2, threshold=0.25, p=2)
     raise ValueError(cfg_id)
 
 
 CONFIGS = (1, 2, 3, 4, 5)
-PAPER_SCALE = (6,)
+PAPER_SCALE = (6, 7)
