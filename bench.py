@@ -23,6 +23,9 @@ per step. Also reported:
                     256 CUs x 2.4 GHz x one wave64 instruction per CU-cycle
   batched           barcodes/s of the 512-cloud mixture batch in one
                     persistent launch vs one cloud at a time
+  shortcuts         the shortcut ablation of the paper's Table 3 on the same
+                    cloud: ms per barcode with no shortcut, the emergent
+                    one, both (the default), and the apparent one alone
   paper_scale       one barcode of a paper-scale workload (o3 shape, 1024
                     points, threshold 1.8, dims 0-3), against the CPU
                     implementation of the paper's algorithm
@@ -256,6 +259,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip both CPU legs (oracle and the paper's algorithm)")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-shortcuts", action="store_true",
+                    help="skip the shortcut ablation leg (Table 3 of the paper, on so3-1000)")
     ap.add_argument("--no-paper-scale", action="store_true",
                     help="skip the paper-scale o3-1024 (t = 1.8, dims 0-3) leg")
     ap.add_argument("--pmc-run", action="store_true",
@@ -435,6 +440,36 @@ def main() -> int:
             "config": list(rips.batched_get_config()),
         }
 
+    shortcuts = None
+    if not args.no_shortcuts:
+        # the ablation of the paper's Table 3 on the bench cloud: no shortcut
+        # ("discarded"), the emergent shortcut, both ("apparent"); and the
+        # apparent one alone
+        names = {0: "none", 2: "emergent", 3: "emergent + apparent (default)", 1: "apparent"}
+        shortcuts = []
+        try:
+            for flags in (0, 2, 3, 1):
+                rips.set_shortcuts(flags)
+                rips.barcode_device(xt, max_dim=max_dim, threshold=t, p=p)  # warm-up
+                torch.cuda.synchronize()
+                tt = []
+                for _ in range(3):
+                    c0 = time.perf_counter()
+                    _, inf_s = rips.barcode_device(xt, max_dim=max_dim, threshold=t, p=p)
+                    torch.cuda.synchronize()
+                    tt.append(time.perf_counter() - c0)
+                st_s = inf_s["stats"]
+                shortcuts.append({
+                    "shortcuts": names[flags],
+                    "ms_per_barcode": round(1e3 * sorted(tt)[1], 3),
+                    "columns": [st_s[k]["columns"] for k in range(1, max_dim + 1)],
+                    "emergent": [st_s[k]["emergent"] for k in range(1, max_dim + 1)],
+                    "additions": [st_s[k]["additions"] for k in range(1, max_dim + 1)],
+                })
+                log(f"shortcuts {names[flags]}: {1e3 * sorted(tt)[1]:.1f} ms")
+        finally:
+            rips.set_shortcuts()
+
     paper_scale = None
     if not args.no_paper_scale:
         c6 = workloads.config(6)
@@ -536,6 +571,7 @@ def main() -> int:
         "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(prof.items())},
         "eliminated": eliminated,
         "batched": batched,
+        "shortcuts": shortcuts,
         "paper_scale": paper_scale,
         "cpu_baseline": cpu,
         "cpu_paper_algorithm": cpu_paper,

@@ -250,6 +250,27 @@ rips_status rips_set_reduce_workgroups(int32_t workgroups);
 rips_status rips_get_reduce_workgroups(int32_t *workgroups);
 
 /*
+ * Shortcuts of the single-cloud path (per device, the current one), as the
+ * ablation switches of the experiments section (Table 3): the barcode is the
+ * same with any of them off, only the work changes.
+ *   RIPS_SHORTCUT_APPARENT: zero apparent pairs (section "Apparent pairs") are
+ *     found by the data-parallel filter and never become columns, and a pivot
+ *     in such a pair is added from its facet without a column of its own.
+ *     Off: every candidate that is not cleared is a column, and the pivot
+ *     test uses the pivot table only.
+ *   RIPS_SHORTCUT_EMERGENT: a column whose oldest cofacet no column owns
+ *     pairs with it without enumerating its coboundary (paragraph "Emergent
+ *     persistence pairs").
+ * Default: both. flags outside the two bits: RIPS_E_INVALID_ARG;
+ * rips_get_shortcuts reads the setting back. The batched path always uses
+ * both. Clearing and cohomology are always on.
+ */
+#define RIPS_SHORTCUT_APPARENT 1
+#define RIPS_SHORTCUT_EMERGENT 2
+rips_status rips_set_shortcuts(int32_t flags);
+rips_status rips_get_shortcuts(int32_t *flags);
+
+/*
  * Launch configuration of the batched path (per device, the current one):
  *   delta_slots        LDS slots of each workgroup's working-column delta:
  *                      512, 1024 or 2048 (0 = default, 2048);

@@ -51,6 +51,8 @@ EXPORTS = (
     "rips_backward_device",
     "rips_set_reduce_workgroups",
     "rips_get_reduce_workgroups",
+    "rips_set_shortcuts",
+    "rips_get_shortcuts",
     "rips_batched_set_config",
     "rips_batched_get_config",
     "rips_batched_autotune",
@@ -176,6 +178,10 @@ def _load():
     lib.rips_set_reduce_workgroups.restype = ctypes.c_int
     lib.rips_get_reduce_workgroups.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     lib.rips_get_reduce_workgroups.restype = ctypes.c_int
+    lib.rips_set_shortcuts.argtypes = [ctypes.c_int32]
+    lib.rips_set_shortcuts.restype = ctypes.c_int
+    lib.rips_get_shortcuts.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+    lib.rips_get_shortcuts.restype = ctypes.c_int
     lib.rips_batched_set_config.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.rips_batched_set_config.restype = ctypes.c_int
     lib.rips_batched_get_config.argtypes = [ctypes.POINTER(ctypes.c_int32),
@@ -453,6 +459,24 @@ def set_reduce_workgroups(workgroups: int = 0):
 def get_reduce_workgroups() -> int:
     a = ctypes.c_int32()
     _check(_lib.rips_get_reduce_workgroups(ctypes.byref(a)))
+    return int(a.value)
+
+
+SHORTCUT_APPARENT = 1
+SHORTCUT_EMERGENT = 2
+
+
+def set_shortcuts(flags: int = SHORTCUT_APPARENT | SHORTCUT_EMERGENT):
+    """Shortcuts of the single-cloud path (the ablation switches of the
+    paper's Table 3): SHORTCUT_APPARENT skips zero apparent pairs,
+    SHORTCUT_EMERGENT pairs emergent columns at once. The bars are the same
+    with any of them off."""
+    _check(_lib.rips_set_shortcuts(int(flags)))
+
+
+def get_shortcuts() -> int:
+    a = ctypes.c_int32()
+    _check(_lib.rips_get_shortcuts(ctypes.byref(a)))
     return int(a.value)
 
 

@@ -207,6 +207,7 @@ struct DevCtx {
     int lds_per_block = 0;
     int num_cus = 0;
     int reduce_groups = 0; // workgroups of the single-cloud reduction: 0 = one per CU
+    int shortcuts = kShortApparent | kShortEmergent; // shortcuts of the single-cloud path
     hipStream_t capture_stream = nullptr;
     // cached graph of the batched launch and the arguments it was built for
     hipGraphExec_t batch_exec = nullptr;
@@ -697,39 +698,46 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         surv.tapp = as<uint8_t>(q);
         // zero apparent pairs (rho, tau) found by the filter, for the
         // reduction's pivot test; twice the candidates, so inserts never fail
-        PairHash app;
+        // (none without the apparent shortcut: those pairs are columns then)
+        const bool apparent = (C.shortcuts & kShortApparent) != 0;
+        PairHash app{};
+        int64_t *ckey_w = nullptr;
+        float *cdia_w = nullptr;
+        int64_t cobcap = 0;
         if (ncand > (1ll << 30)) return fail(RIPS_E_CAPACITY, "too many candidate simplices");
         // table sizes are 32-bit powers of two
         if ((uint64_t)2 * ncand + 64 > (1ull << 31)) return fail(RIPS_E_CAPACITY, "too many candidates");
         const uint32_t appcap = next_pow2((uint64_t)2 * ncand + 64);
-        HIP_TRY(C.ensure(B_APP_KEYS, (size_t)appcap * 8, &q));
-        app.keys = as<int64_t>(q);
-        HIP_TRY(C.ensure(B_APP_VALS, (size_t)appcap * 8, &q));
-        app.vals = as<int64_t>(q);
-        HIP_TRY(C.ensure(B_APP_VERTS, (size_t)appcap * 8, &q));
-        app.verts = as<u64>(q);
-        HIP_TRY(C.ensure(B_APP_NBR, (size_t)appcap * 8, &q));
-        app.nbr = as<u64>(q);
-        HIP_TRY(C.ensure(B_APP_COB, (size_t)appcap * 8, &q));
-        app.cob = as<u64>(q);
-        // room for the coboundary lists of the apparent pairs: a slot reserves
-        // as many entries as rho has candidates (grown from the last call's need)
-        const int64_t per = P.sparse ? std::min<int64_t>(std::max(P.maxdeg, 1), 64) : n;
-        const int64_t cobcap = std::max<int64_t>(C.hint_cob, std::min<int64_t>(ncand * per, 1ll << 25));
-        HIP_TRY(C.ensure(B_COB_KEY, (size_t)cobcap * 8, &q));
-        app.ckey = as<int64_t>(q);
-        int64_t *ckey_w = as<int64_t>(q);
-        HIP_TRY(C.ensure(B_COB_DIA, (size_t)cobcap * 4, &q));
-        app.cdia = as<float>(q);
-        float *cdia_w = as<float>(q);
-        app.mask = appcap - 1;
-        launch_fill_i64(app.keys, appcap, kEmpty, st);
+        if (apparent) {
+            HIP_TRY(C.ensure(B_APP_KEYS, (size_t)appcap * 8, &q));
+            app.keys = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_APP_VALS, (size_t)appcap * 8, &q));
+            app.vals = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_APP_VERTS, (size_t)appcap * 8, &q));
+            app.verts = as<u64>(q);
+            HIP_TRY(C.ensure(B_APP_NBR, (size_t)appcap * 8, &q));
+            app.nbr = as<u64>(q);
+            HIP_TRY(C.ensure(B_APP_COB, (size_t)appcap * 8, &q));
+            app.cob = as<u64>(q);
+            // room for the coboundary lists of the apparent pairs: a slot reserves
+            // as many entries as rho has candidates (grown from the last call's need)
+            const int64_t per = P.sparse ? std::min<int64_t>(std::max(P.maxdeg, 1), 64) : n;
+            cobcap = std::max<int64_t>(C.hint_cob, std::min<int64_t>(ncand * per, 1ll << 25));
+            HIP_TRY(C.ensure(B_COB_KEY, (size_t)cobcap * 8, &q));
+            app.ckey = as<int64_t>(q);
+            ckey_w = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_COB_DIA, (size_t)cobcap * 4, &q));
+            app.cdia = as<float>(q);
+            cdia_w = as<float>(q);
+            app.mask = appcap - 1;
+            launch_fill_i64(app.keys, appcap, kEmpty, st);
+        }
         {
             PROF(P_FILTER1 + k - 1);
             launch_filter(filter_group_size_for(P, k), P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv,
-                          app, st);
+                          app, apparent ? 1 : 0, st);
         }
-        {
+        if (apparent) {
             PROF(P_COB1 + k - 1);
             hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, &P.scal->cob, 0ull);
             launch_cob_lists(P.ctx, k, app, ckey_w, cdia_w, &P.scal->cob, cobcap, st);
@@ -884,6 +892,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             J.bars = spread ? cbars : bars[k];
             J.app = app;
             J.par = par;
+            J.shortcuts = C.shortcuts;
             J.cand_avg = P.sparse ? (float)(2.0 * (double)P.nedges / (double)std::max<int64_t>(n, 1))
                                   : (float)n;
             {
@@ -1497,6 +1506,31 @@ rips_status rips_get_reduce_workgroups(int32_t *workgroups) {
     if ((rs = get_ctx(&C))) return rs;
     std::lock_guard<std::mutex> lk(C->mu);
     if (workgroups) *workgroups = C->reduce_groups;
+    return RIPS_OK;
+}
+
+rips_status rips_set_shortcuts(int32_t flags) {
+    g_err.clear();
+    if (flags < 0 || flags > (RIPS_SHORTCUT_APPARENT | RIPS_SHORTCUT_EMERGENT))
+        return fail(RIPS_E_INVALID_ARG, "unknown shortcut flags");
+    DevCtx *C;
+    rips_status rs;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    C->shortcuts = (flags & RIPS_SHORTCUT_APPARENT ? kShortApparent : 0) |
+                   (flags & RIPS_SHORTCUT_EMERGENT ? kShortEmergent : 0);
+    return RIPS_OK;
+}
+
+rips_status rips_get_shortcuts(int32_t *flags) {
+    g_err.clear();
+    DevCtx *C;
+    rips_status rs;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    if (flags)
+        *flags = (C->shortcuts & kShortApparent ? RIPS_SHORTCUT_APPARENT : 0) |
+                 (C->shortcuts & kShortEmergent ? RIPS_SHORTCUT_EMERGENT : 0);
     return RIPS_OK;
 }
 

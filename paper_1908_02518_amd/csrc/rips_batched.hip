@@ -486,6 +486,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         SC.lcap = A.log_stride;
         J.cand_avg = (float)n;
         J.app = app;
+        J.shortcuts = kShortApparent | kShortEmergent;
         gsync();
         const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, RS);
         if (rstat && tid == 0) {

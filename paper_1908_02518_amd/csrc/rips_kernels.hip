@@ -603,7 +603,7 @@ __global__ void __launch_bounds__(256) k_expand_count(Ctx<Dist> c, int k, Simple
 template <int G, int K, class Dist>
 __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, SimplexList in, int64_t count,
                                                 const u32 *mst_bits, PivotHash prev, Scalars *s,
-                                                Columns out, PairHash app) {
+                                                Columns out, PairHash app, int apparent) {
     constexpr int kGroups = kWave / G; // groups per wave
     const int lane = lane_id();
     const bool leader = (lane & (G - 1)) == 0;
@@ -639,7 +639,7 @@ __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, SimplexList in, int
         int tv[K + 2];
         int pos = 0;
         insert_k<K>(v, j, tv, pos);
-        if (live && j >= 0 && zero_pivot_facet_k<K + 1>(c, tv, dm) == pos) {
+        if (apparent && live && j >= 0 && zero_pivot_facet_k<K + 1>(c, tv, dm) == pos) {
             // (sigma, sigma u {j}) is a zero apparent pair
             n_acol += leader;
             live = false;
@@ -672,7 +672,7 @@ __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, SimplexList in, int
             // sigma in a zero apparent pair (rho, sigma): rho = sigma's zero
             // pivot facet, and no vertex above the removed one extends rho at
             // the same diameter
-            const int m = live ? zero_pivot_facet_k<K>(c, v, dm) : -1;
+            const int m = live && apparent ? zero_pivot_facet_k<K>(c, v, dm) : -1;
             int rv[K];
             remove_k<K>(v, m < 0 ? 0 : m, rv);
             const bool test = live && m >= 0;
@@ -683,7 +683,8 @@ __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, SimplexList in, int
             }
         }
         // the same test for the zero pivot cofacet, for the emergent shortcut
-        const bool tj = live && j >= 0;
+        // (without the apparent shortcut, that cofacet's pair is a column too)
+        const bool tj = apparent && live && j >= 0;
         const int mt = tj ? zero_pivot_facet_k<K + 1>(c, tv, dm) : -1;
         int rt[K + 1];
         remove_k<K + 1>(tv, mt < 0 ? 0 : mt, rt);
@@ -1067,37 +1068,38 @@ __global__ void k_emit(BarBuf in, Scalars *s, int reverse, BarBuf out) {
 // ---------------------------------------------------------------------------
 template <int G, int K>
 static void launch_filter_gk(const Ctx<DistFull> &c, SimplexList in, int64_t count, PairHash app,
-                             const u32 *bits, PivotHash prev, Scalars *s, Columns out, hipStream_t st) {
+                             const u32 *bits, PivotHash prev, Scalars *s, Columns out, int apparent,
+                             hipStream_t st) {
     const int gpb = 256 / G;
     int64_t blocks = (count + gpb - 1) / gpb;
     if (blocks < 1) blocks = 1;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL((k_filter<G, K, DistFull>), dim3((unsigned)blocks), dim3(256), 0, st, c, in, count,
-                       bits, prev, s, out, app);
+                       bits, prev, s, out, app, apparent);
 }
 
 template <int G>
 static void launch_filter_g(const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, PairHash app,
-                            const u32 *bits, PivotHash prev, Scalars *s, Columns out,
+                            const u32 *bits, PivotHash prev, Scalars *s, Columns out, int apparent,
                             hipStream_t st) {
     switch (k) {
-    case 1: launch_filter_gk<G, 1>(c, in, count, app, bits, prev, s, out, st); break;
-    case 2: launch_filter_gk<G, 2>(c, in, count, app, bits, prev, s, out, st); break;
-    default: launch_filter_gk<G, 3>(c, in, count, app, bits, prev, s, out, st); break;
+    case 1: launch_filter_gk<G, 1>(c, in, count, app, bits, prev, s, out, apparent, st); break;
+    case 2: launch_filter_gk<G, 2>(c, in, count, app, bits, prev, s, out, apparent, st); break;
+    default: launch_filter_gk<G, 3>(c, in, count, app, bits, prev, s, out, apparent, st); break;
     }
 }
 
 void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
-                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app,
+                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app, int apparent,
                    hipStream_t st) {
     switch (G) {
-    case 1: launch_filter_g<1>(c, k, in, count, app, bits, prev, s, out, st); break;
-    case 2: launch_filter_g<2>(c, k, in, count, app, bits, prev, s, out, st); break;
-    case 4: launch_filter_g<4>(c, k, in, count, app, bits, prev, s, out, st); break;
-    case 8: launch_filter_g<8>(c, k, in, count, app, bits, prev, s, out, st); break;
-    case 16: launch_filter_g<16>(c, k, in, count, app, bits, prev, s, out, st); break;
-    case 32: launch_filter_g<32>(c, k, in, count, app, bits, prev, s, out, st); break;
-    default: launch_filter_g<64>(c, k, in, count, app, bits, prev, s, out, st); break;
+    case 1: launch_filter_g<1>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
+    case 2: launch_filter_g<2>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
+    case 4: launch_filter_g<4>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
+    case 8: launch_filter_g<8>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
+    case 16: launch_filter_g<16>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
+    case 32: launch_filter_g<32>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
+    default: launch_filter_g<64>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
     }
 }
 

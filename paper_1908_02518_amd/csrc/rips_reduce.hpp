@@ -135,6 +135,14 @@ __device__ __forceinline__ ReduceScratch make_scratch(const ReduceBuffers &b, So
     return sc;
 }
 
+// The shortcuts of the reduction, each of which leaves the barcode as it is
+// (an ablation switch per shortcut): pivots in zero apparent pairs added from
+// their facet rho without a column of their own ("Apparent pairs"; the filter
+// then also skips the columns of such pairs), and the emergent pair of a
+// column whose oldest cofacet nobody owns ("Emergent persistence pairs").
+constexpr int kShortApparent = 1;
+constexpr int kShortEmergent = 2;
+
 // Additions one column may take before the reduction reports an error: every
 // addition moves the pivot to a strictly younger row, so the loop ends; the
 // bound only turns a fault into an error. The addition log (one entry per
@@ -295,6 +303,7 @@ struct ReduceJob {
     float cand_avg;             // mean coboundary candidates of a k-simplex
     PairHash app;               // zero apparent pairs (rho, tau) of this dimension, or none
     ParState par;               // reduction spread over workgroups (cst null: one workgroup)
+    int shortcuts;              // kShortApparent | kShortEmergent: the shortcuts in use
 };
 
 constexpr int kRedTimers = 24;
@@ -1821,6 +1830,8 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
                     if (!log_add(SC, S, a >> 3, (p - lam) % p, piv.diam, 1)) S.abort = kRedLogFull;
                 }
             }
+        } else if (!(J.shortcuts & kShortApparent)) {
+            if (tid == 0) S.m = -1; // no apparent shortcut: the pivot is free
         } else if (w == 0) {
             int tv[kMaxVerts];
             decode(piv.idx, k + 1, c.n, c.B, tv);
@@ -2007,7 +2018,8 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
             u32 tcoef = 0;
             // no probe at all when the first column cannot be emergent (no
             // zero pivot cofacet, or that cofacet is in an apparent pair)
-            const bool cand = valid && J.cols.j[col] >= 0 && !J.cols.tapp[col];
+            const bool cand = (J.shortcuts & kShortEmergent) && valid && J.cols.j[col] >= 0 &&
+                              !J.cols.tapp[col];
             if (lane_bcast((int)cand, 0)) {
                 const int j = J.cols.j[col];
                 if (cand) {
@@ -2087,7 +2099,8 @@ __device__ __forceinline__ int reduce_columns_par(const ReduceJob<Dist> &J, cons
             if (ld_dev(&J.par.ctl[kCtlAbort]) == 0) col = (int)min(atomicAdd(&J.par.ctl[kCtlNext], 1u), (u32)J.ncols);
             S.cur = col;
             S.m = 0;
-            if (col < J.ncols && J.cols.j[col] >= 0 && !J.cols.tapp[col]) {
+            if ((J.shortcuts & kShortEmergent) && col < J.ncols && J.cols.j[col] >= 0 &&
+                !J.cols.tapp[col]) {
                 // emergent candidate: tau = sigma u {j}, at sigma's diameter
                 int v[kMaxVerts];
                 decode(J.cols.idx[col], k, c.n, c.B, v);

@@ -1,0 +1,65 @@
+"""The shortcuts as ablation switches (the paper's Table 3): with the apparent
+pair shortcut, the emergent pair shortcut, or both turned off, the HIP path
+must still give the oracle's bars bit for bit, and its counters must show the
+shortcut off: no apparent columns or pivots (every candidate that is not
+cleared becomes a column), or no emergent pairs."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+INF = float("inf")
+
+
+def rips():
+    import paper_1908_02518_amd as r
+    return r
+
+
+CASES = [
+    ("rectangle-p3", lambda: workloads.rectangle(), 2, INF, 3),
+    ("hexagon", lambda: workloads.regular_polygon(6), 2, INF, 2),
+    ("lattice-ties", lambda: workloads.integer_lattice(27, 3, 5, side=3), 2, INF, 2),
+    ("cube-40-p5", lambda: workloads.uniform_cube(40, 3, 31), 3, INF, 5),
+    ("sphere-100", lambda: workloads.config(1)["clouds"][0], 1, INF, 2),
+    ("so3-1000", lambda: workloads.config(2)["clouds"][0], 2, 1.4, 2),
+    ("torus4-2000", lambda: workloads.config(3)["clouds"][0], 2, 0.5, 3),
+]
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2])
+@pytest.mark.parametrize("name,make,max_dim,t,p", CASES, ids=[c[0] for c in CASES])
+def test_bars_unchanged_without_shortcuts(flags, name, make, max_dim, t, p):
+    r = rips()
+    x = make()
+    print(f"[case] shortcuts {flags} {name}", flush=True)
+    ref = oracle.barcode(x, max_dim=max_dim, threshold=t, p=p)
+    r.set_shortcuts(flags)
+    try:
+        assert r.get_shortcuts() == flags
+        got = r.barcode(x, max_dim=max_dim, threshold=t, p=p)
+    finally:
+        r.set_shortcuts()
+    for d in range(max_dim + 1):
+        for f in ("birth", "death", "birth_simplex", "death_simplex"):
+            assert np.array_equal(getattr(got.bars[d], f), getattr(ref.bars[d], f)), (name, d, f)
+    for k in range(1, max_dim + 1):
+        s = got.stats[k]
+        assert s["candidates"] == ref.counts[k]
+        if not flags & r.SHORTCUT_APPARENT:
+            assert s["apparent_col"] == 0 and s["apparent_pivot"] == 0, (name, k)
+            assert s["columns"] == s["candidates"] - s["cleared"], (name, k)
+        if not flags & r.SHORTCUT_EMERGENT:
+            assert s["emergent"] == 0, (name, k)
+
+
+def test_defaults_restored_and_both_shortcuts_used():
+    r = rips()
+    assert r.get_shortcuts() == r.SHORTCUT_APPARENT | r.SHORTCUT_EMERGENT
+    c = workloads.config(2)
+    got = r.barcode(c["clouds"][0], max_dim=2, threshold=1.4, p=2)
+    assert got.stats[1]["apparent_col"] > 0
+    assert got.stats[2]["emergent"] > 0
