@@ -120,6 +120,35 @@ rips_status rips_barcode(const float *data, int64_t n, int32_t dim, int32_t max_
                          float threshold, uint32_t p, rips_result **out);
 
 void rips_result_free(rips_result *r);
+
+/*
+ * Representative cocycles of the bars of one dimension d >= 1 (section
+ * "Matrix reduction": the columns V_j of the reduction matrix, together with
+ * the reduced columns, form a basis of the filtered complex; here, in
+ * cohomology, the columns of the coboundary matrix). For the bar born at the
+ * d-simplex sigma_j and dying at tau, the cochain V_j (sigma_j plus the
+ * combination of the columns added to it) has tau as the oldest simplex of
+ * its coboundary: it is a cocycle on every simplex older than tau. For an
+ * essential bar, V_j is a cocycle. Runs rips_barcode up to dimension d.
+ * data, n, dim, threshold, p: as for rips_barcode. Bars of dimension d in the
+ * same canonical order; the cocycle of bar b is entries
+ * [offsets[b], offsets[b + 1]) of simplex (CNS indices of d-simplices) and
+ * coef (in Z/p, nonzero). The library allocates *out; rips_cocycles_free
+ * releases it. d < 1 or out of range: RIPS_E_INVALID_ARG; *out = NULL on
+ * error. Uses the shortcuts set by rips_set_shortcuts (V_j is the same).
+ */
+typedef struct {
+    int32_t dim;
+    int64_t count;
+    float *birth, *death;
+    int64_t *birth_simplex, *death_simplex;
+    int64_t *offsets; /* count + 1 */
+    int64_t *simplex; /* offsets[count] */
+    uint32_t *coef;
+} rips_cocycles;
+rips_status rips_barcode_cocycles(const float *data, int64_t n, int32_t dim, int32_t d, float threshold,
+                                  uint32_t p, rips_cocycles **out);
+void rips_cocycles_free(rips_cocycles *c);
 const char *rips_status_string(rips_status s);
 const char *rips_last_error(void);
 

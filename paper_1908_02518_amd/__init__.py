@@ -43,6 +43,8 @@ STATUS = {
 EXPORTS = (
     "rips_barcode",
     "rips_result_free",
+    "rips_barcode_cocycles",
+    "rips_cocycles_free",
     "rips_status_string",
     "rips_last_error",
     "rips_barcode_device",
@@ -102,6 +104,18 @@ class rips_result(ctypes.Structure):
                 ("column_diam", ctypes.POINTER(ctypes.POINTER(ctypes.c_float)))]
 
 
+class rips_cocycles(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32),
+                ("count", ctypes.c_int64),
+                ("birth", ctypes.POINTER(ctypes.c_float)),
+                ("death", ctypes.POINTER(ctypes.c_float)),
+                ("birth_simplex", ctypes.POINTER(ctypes.c_int64)),
+                ("death_simplex", ctypes.POINTER(ctypes.c_int64)),
+                ("offsets", ctypes.POINTER(ctypes.c_int64)),
+                ("simplex", ctypes.POINTER(ctypes.c_int64)),
+                ("coef", ctypes.POINTER(ctypes.c_uint32))]
+
+
 _D1 = RIPS_MAX_DIM + 1
 
 
@@ -152,6 +166,12 @@ def _load():
     lib.rips_barcode.restype = ctypes.c_int
     lib.rips_result_free.argtypes = [ctypes.POINTER(rips_result)]
     lib.rips_result_free.restype = None
+    lib.rips_barcode_cocycles.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_float, ctypes.c_uint32,
+                                          ctypes.POINTER(ctypes.POINTER(rips_cocycles))]
+    lib.rips_barcode_cocycles.restype = ctypes.c_int
+    lib.rips_cocycles_free.argtypes = [ctypes.POINTER(rips_cocycles)]
+    lib.rips_cocycles_free.restype = None
     lib.rips_status_string.argtypes = [ctypes.c_int]
     lib.rips_status_string.restype = ctypes.c_char_p
     lib.rips_last_error.argtypes = []
@@ -295,6 +315,49 @@ def barcode(points: np.ndarray | None = None, *, dist: np.ndarray | None = None,
                       simplex_count=counts, columns=cols)
     finally:
         _lib.rips_result_free(out)
+
+
+@dataclass
+class Cocycles:
+    bars: Bars
+    cocycles: list  # per bar: (CNS indices of its simplices, coefficients in Z/p)
+
+
+def cocycles(points: np.ndarray | None = None, *, dist: np.ndarray | None = None, dim: int = 1,
+             threshold: float = float("inf"), p: int = 2) -> Cocycles:
+    """Bars of dimension `dim` >= 1 with a representative cocycle each, via
+    the C ABI rips_barcode_cocycles: `cocycles[b]` = (CNS indices of
+    dim-simplices, coefficients in Z/p) of bar b."""
+    if (points is None) == (dist is None):
+        raise ValueError("give exactly one of points, dist")
+    if points is not None:
+        x = np.ascontiguousarray(points, dtype=np.float32)
+        if x.ndim != 2:
+            raise ValueError("points must be (n, m)")
+        n, m = x.shape
+    else:
+        x = np.ascontiguousarray(dist, dtype=np.float32)
+        if x.ndim != 2 or x.shape[0] != x.shape[1]:
+            raise ValueError("dist must be (n, n)")
+        n, m = x.shape[0], 0
+    out = ctypes.POINTER(rips_cocycles)()
+    _check(_lib.rips_barcode_cocycles(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, m, dim,
+                                      ctypes.c_float(threshold), p, ctypes.byref(out)))
+    try:
+        r = out.contents
+        c = int(r.count)
+
+        def arr(ptr, k, dt):
+            return np.ctypeslib.as_array(ptr, shape=(k,)).astype(dt, copy=True) if k else np.empty(0, dt)
+        bars = Bars(arr(r.birth, c, np.float32), arr(r.death, c, np.float32),
+                    arr(r.birth_simplex, c, np.int64), arr(r.death_simplex, c, np.int64))
+        off = arr(r.offsets, c + 1, np.int64)
+        ne = int(off[-1]) if c else 0
+        simp, coef = arr(r.simplex, ne, np.int64), arr(r.coef, ne, np.uint32)
+        cc = [(simp[off[b]:off[b + 1]], coef[off[b]:off[b + 1]]) for b in range(c)]
+        return Cocycles(bars, cc)
+    finally:
+        _lib.rips_cocycles_free(out)
 
 
 def _stream_ptr(torch, device):

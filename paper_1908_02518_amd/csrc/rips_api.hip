@@ -13,6 +13,7 @@
 #include <mutex>
 #include <string>
 #include <vector>
+#include <unordered_map>
 
 #include "../../include/rips.h"
 #include "rips_batched.hpp"
@@ -208,6 +209,7 @@ struct DevCtx {
     int num_cus = 0;
     int reduce_groups = 0; // workgroups of the single-cloud reduction: 0 = one per CU
     int shortcuts = kShortApparent | kShortEmergent; // shortcuts of the single-cloud path
+    int cocycle_dim = -1; // dimension whose zero columns also store V_j (cocycle requests)
     hipStream_t capture_stream = nullptr;
     // cached graph of the batched launch and the arguments it was built for
     hipGraphExec_t batch_exec = nullptr;
@@ -893,6 +895,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             J.app = app;
             J.par = par;
             J.shortcuts = C.shortcuts;
+            J.keep_essential_v = k == C.cocycle_dim ? 1 : 0;
             J.cand_avg = P.sparse ? (float)(2.0 * (double)P.nedges / (double)std::max<int64_t>(n, 1))
                                   : (float)n;
             {
@@ -1353,6 +1356,128 @@ rips_status rips_barcode(const float *data, int64_t n, int32_t dim, int32_t max_
                 return fail(RIPS_E_HIP, "copying columns to the host");
             }
         }
+    }
+    *out = r;
+    return RIPS_OK;
+}
+
+void rips_cocycles_free(rips_cocycles *c) {
+    if (!c) return;
+    free(c->birth);
+    free(c->death);
+    free(c->birth_simplex);
+    free(c->death_simplex);
+    free(c->offsets);
+    free(c->simplex);
+    free(c->coef);
+    free(c);
+}
+
+rips_status rips_barcode_cocycles(const float *data, int64_t n, int32_t dim, int32_t d, float threshold,
+                                  uint32_t p, rips_cocycles **out) {
+    g_err.clear();
+    if (!out) return fail(RIPS_E_INVALID_ARG, "null out");
+    *out = nullptr;
+    if (!data) return fail(RIPS_E_INVALID_ARG, "null data");
+    if (d < 1) return fail(RIPS_E_INVALID_ARG, "cocycles are given for dimensions >= 1");
+    rips_status rs = validate(n, dim, d, threshold, p, 0);
+    if (rs) return rs;
+    DevCtx *C;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    hipStream_t st = nullptr;
+    void *q;
+    const size_t in_elems = dim > 0 ? (size_t)n * dim : (size_t)n * n;
+    HIP_TRY(C->ensure(B_INPUT, in_elems * 4, &q));
+    float *d_in = as<float>(q);
+    HIP_TRY(hipMemcpyAsync(d_in, data, in_elems * 4, hipMemcpyHostToDevice, st));
+    RunOut o;
+    C->cocycle_dim = d;
+    rs = run_single(*C, d_in, (int)n, dim, d, threshold, p, st, o);
+    C->cocycle_dim = -1;
+    if (rs) return rs;
+    // the bars of dimension d in the canonical order
+    const int64_t c = o.count[d];
+    std::vector<float> birth(c), death(c);
+    std::vector<int64_t> bs(c), ds(c);
+    if (c > 0) {
+        HIP_TRY(C->ensure(B_STAGE, (size_t)c * 24, &q));
+        char *sg = as<char>(q);
+        BarBuf dst{(float *)sg, (float *)(sg + c * 4), (int64_t *)(sg + c * 8), (int64_t *)(sg + c * 16)};
+        Scalars *scal = as<Scalars>(C->buf[B_SCAL]);
+        hipLaunchKernelGGL(k_set_nbars, dim3(1), dim3(1), 0, st, scal, c);
+        launch_emit(internal_bars(*C, d), scal, 1, dst, st);
+        HIP_TRY(hipMemcpyAsync(birth.data(), dst.birth, c * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(death.data(), dst.death, c * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(bs.data(), dst.bs, c * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(ds.data(), dst.ds, c * 8, hipMemcpyDeviceToHost, st));
+    }
+    // the columns of dimension d (still resident: d is the last dimension
+    // run) and the stored V_j of each
+    const int64_t S = o.ncols[d];
+    const int64_t nv = o.stats[d].entries_stored;
+    std::vector<int64_t> cidx(S), voff(S), vidx(nv);
+    std::vector<int> vlen(S);
+    std::vector<u32> vcoef(nv);
+    if (S > 0) {
+        HIP_TRY(hipMemcpyAsync(cidx.data(), C->buf[B_COL_IDX + d], S * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(voff.data(), C->buf[B_V_OFF], S * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(vlen.data(), C->buf[B_V_LEN], S * 4, hipMemcpyDeviceToHost, st));
+    }
+    if (nv > 0) {
+        HIP_TRY(hipMemcpyAsync(vidx.data(), C->buf[B_V_IDX], nv * 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(vcoef.data(), C->buf[B_V_COEF], nv * 4, hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    std::unordered_map<int64_t, int64_t> col_of;
+    col_of.reserve((size_t)S * 2);
+    for (int64_t j = 0; j < S; ++j) col_of[cidx[j]] = j;
+    std::vector<int64_t> offs(c + 1, 0), simp;
+    std::vector<u32> cf;
+    for (int64_t b = 0; b < c; ++b) {
+        auto it = col_of.find(bs[b]);
+        if (it == col_of.end()) return fail(RIPS_E_HIP, "cocycles: a bar without a column");
+        const int64_t j = it->second;
+        if (vlen[j] < 0) {
+            // emergent column: V_j is its own simplex
+            simp.push_back(bs[b]);
+            cf.push_back(1u);
+        } else {
+            if (voff[j] < 0 || voff[j] + vlen[j] > nv) return fail(RIPS_E_HIP, "cocycles: column store out of range");
+            for (int e = 0; e < vlen[j]; ++e) {
+                simp.push_back(vidx[voff[j] + e]);
+                cf.push_back(vcoef[voff[j] + e] % p);
+            }
+        }
+        offs[b + 1] = (int64_t)simp.size();
+    }
+    rips_cocycles *r = (rips_cocycles *)calloc(1, sizeof(rips_cocycles));
+    if (!r) return fail(RIPS_E_OOM, "host allocation");
+    const int64_t ne = (int64_t)simp.size();
+    r->dim = d;
+    r->count = c;
+    r->birth = (float *)malloc(sizeof(float) * (c ? c : 1));
+    r->death = (float *)malloc(sizeof(float) * (c ? c : 1));
+    r->birth_simplex = (int64_t *)malloc(sizeof(int64_t) * (c ? c : 1));
+    r->death_simplex = (int64_t *)malloc(sizeof(int64_t) * (c ? c : 1));
+    r->offsets = (int64_t *)malloc(sizeof(int64_t) * (c + 1));
+    r->simplex = (int64_t *)malloc(sizeof(int64_t) * (ne ? ne : 1));
+    r->coef = (uint32_t *)malloc(sizeof(uint32_t) * (ne ? ne : 1));
+    if (!r->birth || !r->death || !r->birth_simplex || !r->death_simplex || !r->offsets || !r->simplex ||
+        !r->coef) {
+        rips_cocycles_free(r);
+        return fail(RIPS_E_OOM, "host allocation");
+    }
+    if (c) {
+        memcpy(r->birth, birth.data(), c * 4);
+        memcpy(r->death, death.data(), c * 4);
+        memcpy(r->birth_simplex, bs.data(), c * 8);
+        memcpy(r->death_simplex, ds.data(), c * 8);
+    }
+    memcpy(r->offsets, offs.data(), (c + 1) * 8);
+    if (ne) {
+        memcpy(r->simplex, simp.data(), ne * 8);
+        memcpy(r->coef, cf.data(), ne * 4);
     }
     *out = r;
     return RIPS_OK;

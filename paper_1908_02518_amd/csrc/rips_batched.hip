@@ -487,6 +487,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         J.cand_avg = (float)n;
         J.app = app;
         J.shortcuts = kShortApparent | kShortEmergent;
+        J.keep_essential_v = 0;
         gsync();
         const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, RS);
         if (rstat && tid == 0) {

@@ -304,6 +304,7 @@ struct ReduceJob {
     PairHash app;               // zero apparent pairs (rho, tau) of this dimension, or none
     ParState par;               // reduction spread over workgroups (cst null: one workgroup)
     int shortcuts;              // kShortApparent | kShortEmergent: the shortcuts in use
+    int keep_essential_v;       // also store V_j of zero columns (their cocycles)
 };
 
 constexpr int kRedTimers = 24;
@@ -1634,6 +1635,28 @@ __device__ int par_wait(const ReduceJob<Dist> &J, RedShared<BT> &S, int j, u32 d
     return 0;
 }
 
+// V_j = sigma_j + the logged combination, summed (in D's LDS slots when it
+// fits comfortably, else in the global table) and appended to the column
+// store. Returns its length, or minus a result code (all threads).
+template <int BT, class Dist>
+__device__ __forceinline__ int store_v(const ReduceJob<Dist> &J, const LdsCol &D, const ReduceScratch &SC,
+                                      int64_t sidx, float sdm, RedShared<BT> &S, int64_t *voff) {
+    wc_reset<BT>(D);
+    const bool try_lds = S.vest <= (int64_t)(D.mask + 1) / 2;
+    const bool used_lds = try_lds && materialize_v<BT>(J, SC, D, sidx, sdm, S);
+    if (!used_lds) {
+        if (try_lds) wc_clear_all<BT>(D); // the failed attempt left D unspecified
+        if (!materialize_v<BT>(J, SC, SC.Vw, sidx, sdm, S)) {
+            wc_clear_all<BT>(SC.Vw);
+            return -kRedVFull;
+        }
+    }
+    const int vn = used_lds ? store_table<BT>(D, J.V, J.vcount, J.p, S, voff)
+                            : store_table<BT>(SC.Vw, J.V, J.vcount, J.p, S, voff);
+    if (!used_lds) wc_reset<BT>(SC.Vw);
+    return vn < 0 ? -kRedStoreFull : vn;
+}
+
 // Full reduction of column j. Returns a result code; on anything but kRedOk
 // nothing of column j has been published.
 //
@@ -1729,7 +1752,18 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         if (result) break;
         if (piv.idx == kEmpty) {
             // zero column: essential class born at sigma (final as it is:
-            // nothing is left to look up)
+            // nothing is left to look up); its cocycle V_j is stored only
+            // when asked for
+            int64_t voff = 0;
+            int vn = -1;
+            if (J.keep_essential_v) {
+                __syncthreads();
+                vn = store_v<BT>(J, D, SC, sidx, sdm, S, &voff);
+                if (vn < 0) {
+                    result = -vn;
+                    break;
+                }
+            }
             if (kPar) {
                 if (tid == 0) {
                     J.bars.birth[j] = sdm;
@@ -1737,6 +1771,10 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
                     J.bars.bs[j] = sidx;
                     J.bars.ds[j] = -1;
                     S.stat[4] += 1;
+                    if (J.keep_essential_v) {
+                        J.V.off[j] = voff;
+                        J.V.len[j] = vn;
+                    }
                 }
                 fence_release_dev();
                 __syncthreads();
@@ -1750,6 +1788,10 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
                     S.nbars++;
                 }
                 S.stat[4] += 1;
+                if (J.keep_essential_v) {
+                    J.V.off[j] = voff;
+                    J.V.len[j] = vn;
+                }
             }
             break;
         }
@@ -1892,24 +1934,10 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             }
         }
         __syncthreads();
-        // V_j: in D's LDS slots when it fits comfortably, else in the global table
-        wc_reset<BT>(D);
-        const bool try_lds = S.vest <= (int64_t)(D.mask + 1) / 2;
-        const bool used_lds = try_lds && materialize_v<BT>(J, SC, D, sidx, sdm, S);
-        if (!used_lds) {
-            if (try_lds) wc_clear_all<BT>(D); // the failed attempt left D unspecified
-            if (!materialize_v<BT>(J, SC, SC.Vw, sidx, sdm, S)) {
-                wc_clear_all<BT>(SC.Vw);
-                result = kRedVFull;
-                break;
-            }
-        }
         int64_t voff = 0;
-        const int vn = used_lds ? store_table<BT>(D, J.V, J.vcount, p, S, &voff)
-                                : store_table<BT>(SC.Vw, J.V, J.vcount, p, S, &voff);
-        if (!used_lds) wc_reset<BT>(SC.Vw);
+        const int vn = store_v<BT>(J, D, SC, sidx, sdm, S, &voff);
         if (vn < 0) {
-            result = kRedStoreFull;
+            result = -vn;
             break;
         }
         if (kPar) {
