@@ -290,12 +290,16 @@ rips_status rips_get_reduce_workgroups(int32_t *workgroups);
  *   RIPS_SHORTCUT_EMERGENT: a column whose oldest cofacet no column owns
  *     pairs with it without enumerating its coboundary (paragraph "Emergent
  *     persistence pairs").
- * Default: both. flags outside the two bits: RIPS_E_INVALID_ARG;
+ *   RIPS_SHORTCUT_CLEARING: a simplex that is a pivot of the dimension below
+ *     gets no column (section "Clearing inessential birth columns"). Off:
+ *     its column is reduced, to zero, and gives no bar.
+ * Default: all three. flags outside the three bits: RIPS_E_INVALID_ARG;
  * rips_get_shortcuts reads the setting back. The batched path always uses
- * both. Clearing and cohomology are always on.
+ * all three. Cohomology is always computed.
  */
 #define RIPS_SHORTCUT_APPARENT 1
 #define RIPS_SHORTCUT_EMERGENT 2
+#define RIPS_SHORTCUT_CLEARING 4
 rips_status rips_set_shortcuts(int32_t flags);
 rips_status rips_get_shortcuts(int32_t *flags);
 

@@ -527,12 +527,14 @@ def get_reduce_workgroups() -> int:
 
 SHORTCUT_APPARENT = 1
 SHORTCUT_EMERGENT = 2
+SHORTCUT_CLEARING = 4
 
 
-def set_shortcuts(flags: int = SHORTCUT_APPARENT | SHORTCUT_EMERGENT):
+def set_shortcuts(flags: int = SHORTCUT_APPARENT | SHORTCUT_EMERGENT | SHORTCUT_CLEARING):
     """Shortcuts of the single-cloud path (the ablation switches of the
     paper's Table 3): SHORTCUT_APPARENT skips zero apparent pairs,
-    SHORTCUT_EMERGENT pairs emergent columns at once. The bars are the same
+    SHORTCUT_EMERGENT pairs emergent columns at once, SHORTCUT_CLEARING
+    gives no column to a pivot of the dimension below. The bars are the same
     with any of them off."""
     _check(_lib.rips_set_shortcuts(int(flags)))
 

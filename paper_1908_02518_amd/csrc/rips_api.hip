@@ -208,7 +208,7 @@ struct DevCtx {
     int lds_per_block = 0;
     int num_cus = 0;
     int reduce_groups = 0; // workgroups of the single-cloud reduction: 0 = one per CU
-    int shortcuts = kShortApparent | kShortEmergent; // shortcuts of the single-cloud path
+    int shortcuts = kShortApparent | kShortEmergent | kShortClearing; // of the single-cloud path
     int cocycle_dim = -1; // dimension whose zero columns also store V_j (cocycle requests)
     hipStream_t capture_stream = nullptr;
     // cached graph of the batched launch and the arguments it was built for
@@ -737,7 +737,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         {
             PROF(P_FILTER1 + k - 1);
             launch_filter(filter_group_size_for(P, k), P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv,
-                          app, apparent ? 1 : 0, st);
+                          app, (apparent ? kShortApparent : 0) | (C.shortcuts & kShortClearing), st);
         }
         if (apparent) {
             PROF(P_COB1 + k - 1);
@@ -896,6 +896,8 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             J.par = par;
             J.shortcuts = C.shortcuts;
             J.keep_essential_v = k == C.cocycle_dim ? 1 : 0;
+            J.prev_bits = W.bits;
+            J.prev = ph_prev;
             J.cand_avg = P.sparse ? (float)(2.0 * (double)P.nedges / (double)std::max<int64_t>(n, 1))
                                   : (float)n;
             {
@@ -1636,14 +1638,15 @@ rips_status rips_get_reduce_workgroups(int32_t *workgroups) {
 
 rips_status rips_set_shortcuts(int32_t flags) {
     g_err.clear();
-    if (flags < 0 || flags > (RIPS_SHORTCUT_APPARENT | RIPS_SHORTCUT_EMERGENT))
+    if (flags < 0 || flags > (RIPS_SHORTCUT_APPARENT | RIPS_SHORTCUT_EMERGENT | RIPS_SHORTCUT_CLEARING))
         return fail(RIPS_E_INVALID_ARG, "unknown shortcut flags");
     DevCtx *C;
     rips_status rs;
     if ((rs = get_ctx(&C))) return rs;
     std::lock_guard<std::mutex> lk(C->mu);
     C->shortcuts = (flags & RIPS_SHORTCUT_APPARENT ? kShortApparent : 0) |
-                   (flags & RIPS_SHORTCUT_EMERGENT ? kShortEmergent : 0);
+                   (flags & RIPS_SHORTCUT_EMERGENT ? kShortEmergent : 0) |
+                   (flags & RIPS_SHORTCUT_CLEARING ? kShortClearing : 0);
     return RIPS_OK;
 }
 
@@ -1655,7 +1658,8 @@ rips_status rips_get_shortcuts(int32_t *flags) {
     std::lock_guard<std::mutex> lk(C->mu);
     if (flags)
         *flags = (C->shortcuts & kShortApparent ? RIPS_SHORTCUT_APPARENT : 0) |
-                 (C->shortcuts & kShortEmergent ? RIPS_SHORTCUT_EMERGENT : 0);
+                 (C->shortcuts & kShortEmergent ? RIPS_SHORTCUT_EMERGENT : 0) |
+                 (C->shortcuts & kShortClearing ? RIPS_SHORTCUT_CLEARING : 0);
     return RIPS_OK;
 }
 

@@ -486,8 +486,10 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         SC.lcap = A.log_stride;
         J.cand_avg = (float)n;
         J.app = app;
-        J.shortcuts = kShortApparent | kShortEmergent;
+        J.shortcuts = kShortApparent | kShortEmergent | kShortClearing;
         J.keep_essential_v = 0;
+        J.prev_bits = nullptr;
+        J.prev = PivotHash{nullptr, nullptr, 0};
         gsync();
         const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, RS);
         if (rstat && tid == 0) {

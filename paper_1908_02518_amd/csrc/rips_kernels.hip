@@ -603,7 +603,10 @@ __global__ void __launch_bounds__(256) k_expand_count(Ctx<Dist> c, int k, Simple
 template <int G, int K, class Dist>
 __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, SimplexList in, int64_t count,
                                                 const u32 *mst_bits, PivotHash prev, Scalars *s,
-                                                Columns out, PairHash app, int apparent) {
+                                                Columns out, PairHash app, int flags) {
+    // flags: kShortApparent (zero apparent pairs are no columns), kShortClearing
+    const bool apparent = (flags & kShortApparent) != 0;
+    const bool clearing = (flags & kShortClearing) != 0;
     constexpr int kGroups = kWave / G; // groups per wave
     const int lane = lane_id();
     const bool leader = (lane & (G - 1)) == 0;
@@ -629,7 +632,7 @@ __global__ void __launch_bounds__(256) k_filter(Ctx<Dist> c, SimplexList in, int
                 decode(idx, K, c.n, c.B, v);
                 cleared = ph_find(prev, idx) >= 0;
             }
-            if (cleared) {
+            if (clearing && cleared) {
                 n_clear += leader;
                 live = false;
             }
@@ -1068,38 +1071,38 @@ __global__ void k_emit(BarBuf in, Scalars *s, int reverse, BarBuf out) {
 // ---------------------------------------------------------------------------
 template <int G, int K>
 static void launch_filter_gk(const Ctx<DistFull> &c, SimplexList in, int64_t count, PairHash app,
-                             const u32 *bits, PivotHash prev, Scalars *s, Columns out, int apparent,
+                             const u32 *bits, PivotHash prev, Scalars *s, Columns out, int flags,
                              hipStream_t st) {
     const int gpb = 256 / G;
     int64_t blocks = (count + gpb - 1) / gpb;
     if (blocks < 1) blocks = 1;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL((k_filter<G, K, DistFull>), dim3((unsigned)blocks), dim3(256), 0, st, c, in, count,
-                       bits, prev, s, out, app, apparent);
+                       bits, prev, s, out, app, flags);
 }
 
 template <int G>
 static void launch_filter_g(const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, PairHash app,
-                            const u32 *bits, PivotHash prev, Scalars *s, Columns out, int apparent,
+                            const u32 *bits, PivotHash prev, Scalars *s, Columns out, int flags,
                             hipStream_t st) {
     switch (k) {
-    case 1: launch_filter_gk<G, 1>(c, in, count, app, bits, prev, s, out, apparent, st); break;
-    case 2: launch_filter_gk<G, 2>(c, in, count, app, bits, prev, s, out, apparent, st); break;
-    default: launch_filter_gk<G, 3>(c, in, count, app, bits, prev, s, out, apparent, st); break;
+    case 1: launch_filter_gk<G, 1>(c, in, count, app, bits, prev, s, out, flags, st); break;
+    case 2: launch_filter_gk<G, 2>(c, in, count, app, bits, prev, s, out, flags, st); break;
+    default: launch_filter_gk<G, 3>(c, in, count, app, bits, prev, s, out, flags, st); break;
     }
 }
 
 void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
-                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app, int apparent,
+                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app, int flags,
                    hipStream_t st) {
     switch (G) {
-    case 1: launch_filter_g<1>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
-    case 2: launch_filter_g<2>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
-    case 4: launch_filter_g<4>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
-    case 8: launch_filter_g<8>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
-    case 16: launch_filter_g<16>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
-    case 32: launch_filter_g<32>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
-    default: launch_filter_g<64>(c, k, in, count, app, bits, prev, s, out, apparent, st); break;
+    case 1: launch_filter_g<1>(c, k, in, count, app, bits, prev, s, out, flags, st); break;
+    case 2: launch_filter_g<2>(c, k, in, count, app, bits, prev, s, out, flags, st); break;
+    case 4: launch_filter_g<4>(c, k, in, count, app, bits, prev, s, out, flags, st); break;
+    case 8: launch_filter_g<8>(c, k, in, count, app, bits, prev, s, out, flags, st); break;
+    case 16: launch_filter_g<16>(c, k, in, count, app, bits, prev, s, out, flags, st); break;
+    case 32: launch_filter_g<32>(c, k, in, count, app, bits, prev, s, out, flags, st); break;
+    default: launch_filter_g<64>(c, k, in, count, app, bits, prev, s, out, flags, st); break;
     }
 }
 

@@ -125,7 +125,7 @@ void launch_cob_lists(const Ctx<DistFull> &c, int k, PairHash app, int64_t *ckey
                       unsigned long long *count, int64_t cap, hipStream_t st);
 void launch_fill_u32(u32 *a, int64_t n, u32 v, hipStream_t st);
 void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count,
-                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app, int apparent,
+                   const u32 *bits, PivotHash prev, Scalars *s, Columns out, PairHash app, int flags,
                    hipStream_t st);
 void launch_expand(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, Scalars *s,
                    SimplexList out, int64_t cap, bool count_only, hipStream_t st);

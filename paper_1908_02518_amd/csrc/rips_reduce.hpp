@@ -142,6 +142,10 @@ __device__ __forceinline__ ReduceScratch make_scratch(const ReduceBuffers &b, So
 // column whose oldest cofacet nobody owns ("Emergent persistence pairs").
 constexpr int kShortApparent = 1;
 constexpr int kShortEmergent = 2;
+// Clearing ("Clearing inessential birth columns"): a simplex that is a pivot
+// of the dimension below gets no column. Without it that column reduces to
+// zero and is not an essential class.
+constexpr int kShortClearing = 4;
 
 // Additions one column may take before the reduction reports an error: every
 // addition moves the pivot to a strictly younger row, so the loop ends; the
@@ -303,8 +307,12 @@ struct ReduceJob {
     float cand_avg;             // mean coboundary candidates of a k-simplex
     PairHash app;               // zero apparent pairs (rho, tau) of this dimension, or none
     ParState par;               // reduction spread over workgroups (cst null: one workgroup)
-    int shortcuts;              // kShortApparent | kShortEmergent: the shortcuts in use
+    int shortcuts;              // kShortApparent | kShortEmergent | kShortClearing: those in use
     int keep_essential_v;       // also store V_j of zero columns (their cocycles)
+    // the pivots of the dimension below (read only without clearing): forest
+    // edges of H0 as bits (k = 1), else that dimension's pivot table
+    const u32 *prev_bits;
+    PivotHash prev;
 };
 
 constexpr int kRedTimers = 24;
@@ -1753,10 +1761,14 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         if (piv.idx == kEmpty) {
             // zero column: essential class born at sigma (final as it is:
             // nothing is left to look up); its cocycle V_j is stored only
-            // when asked for
+            // when asked for. Without clearing, the zero column of a pivot
+            // of the dimension below is no class at all.
+            const bool lower = !(J.shortcuts & kShortClearing) &&
+                               (k == 1 ? ((J.prev_bits[sidx >> 5] >> (sidx & 31)) & 1u) != 0
+                                       : ph_find(J.prev, sidx) >= 0);
             int64_t voff = 0;
             int vn = -1;
-            if (J.keep_essential_v) {
+            if (J.keep_essential_v && !lower) {
                 __syncthreads();
                 vn = store_v<BT>(J, D, SC, sidx, sdm, S, &voff);
                 if (vn < 0) {
@@ -1768,9 +1780,9 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
                 if (tid == 0) {
                     J.bars.birth[j] = sdm;
                     J.bars.death[j] = INFINITY;
-                    J.bars.bs[j] = sidx;
+                    J.bars.bs[j] = lower ? -1 : sidx; // -1: no bar
                     J.bars.ds[j] = -1;
-                    S.stat[4] += 1;
+                    if (!lower) S.stat[4] += 1;
                     if (J.keep_essential_v) {
                         J.V.off[j] = voff;
                         J.V.len[j] = vn;
@@ -1779,7 +1791,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
                 fence_release_dev();
                 __syncthreads();
                 if (tid == 0) st_dev(&J.par.cst[j], kColDone);
-            } else if (tid == 0) {
+            } else if (tid == 0 && !lower) {
                 if (S.nbars < J.ncols) {
                     J.bars.birth[S.nbars] = sdm;
                     J.bars.death[S.nbars] = INFINITY;

@@ -1,8 +1,12 @@
-"""The shortcuts as ablation switches (the paper's Table 3): with the apparent
-pair shortcut, the emergent pair shortcut, or both turned off, the HIP path
-must still give the oracle's bars bit for bit, and its counters must show the
-shortcut off: no apparent columns or pivots (every candidate that is not
-cleared becomes a column), or no emergent pairs."""
+"""The shortcuts as ablation switches (the paper's Table 3): with any of the
+apparent pair shortcut, the emergent pair shortcut and clearing turned off,
+the HIP path must still give the oracle's bars bit for bit, and its counters
+must show the shortcut off: no apparent columns or pivots (every candidate
+that is not cleared becomes a column), no emergent pairs, or nothing cleared
+(the columns of pivots of the dimension below reduce to zero and give no
+bar)."""
+
+from functools import lru_cache
 
 import numpy as np
 import pytest
@@ -30,17 +34,26 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("flags", [0, 1, 2])
+@lru_cache(maxsize=None)
+def case(name):
+    _, make, max_dim, t, p = next(c for c in CASES if c[0] == name)
+    x = make()
+    return x, oracle.barcode(x, max_dim=max_dim, threshold=t, p=p)
+
+
+@pytest.mark.parametrize("flags", [0, 1, 2, 3, 5, 6])
 @pytest.mark.parametrize("name,make,max_dim,t,p", CASES, ids=[c[0] for c in CASES])
 def test_bars_unchanged_without_shortcuts(flags, name, make, max_dim, t, p):
     r = rips()
-    x = make()
     print(f"[case] shortcuts {flags} {name}", flush=True)
-    ref = oracle.barcode(x, max_dim=max_dim, threshold=t, p=p)
+    x, ref = case(name)
     r.set_shortcuts(flags)
     try:
         assert r.get_shortcuts() == flags
         got = r.barcode(x, max_dim=max_dim, threshold=t, p=p)
+        if not flags & r.SHORTCUT_CLEARING:
+            r.set_shortcuts(flags | r.SHORTCUT_CLEARING)
+            on = r.barcode(x, max_dim=max_dim, threshold=t, p=p)
     finally:
         r.set_shortcuts()
     for d in range(max_dim + 1):
@@ -54,12 +67,19 @@ def test_bars_unchanged_without_shortcuts(flags, name, make, max_dim, t, p):
             assert s["columns"] == s["candidates"] - s["cleared"], (name, k)
         if not flags & r.SHORTCUT_EMERGENT:
             assert s["emergent"] == 0, (name, k)
+        if not flags & r.SHORTCUT_CLEARING:
+            assert s["cleared"] == 0, (name, k)
+            # a pivot of dimension k-1 is no zero apparent pair's birth, so
+            # what clearing removed comes back as columns, and nothing else
+            c = on.stats[k]
+            assert s["columns"] == c["columns"] + c["cleared"], (name, k)
 
 
-def test_defaults_restored_and_both_shortcuts_used():
+def test_defaults_restored_and_all_shortcuts_used():
     r = rips()
-    assert r.get_shortcuts() == r.SHORTCUT_APPARENT | r.SHORTCUT_EMERGENT
+    assert r.get_shortcuts() == r.SHORTCUT_APPARENT | r.SHORTCUT_EMERGENT | r.SHORTCUT_CLEARING
     c = workloads.config(2)
     got = r.barcode(c["clouds"][0], max_dim=2, threshold=1.4, p=2)
     assert got.stats[1]["apparent_col"] > 0
     assert got.stats[2]["emergent"] > 0
+    assert got.stats[1]["cleared"] > 0 and got.stats[2]["cleared"] > 0

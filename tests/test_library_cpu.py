@@ -106,7 +106,7 @@ def test_batched_config_validation():
     assert lib.rips_batched_set_config(1024, 9) == -1
     assert lib.rips_set_reduce_workgroups(-1) == -1
     assert lib.rips_set_shortcuts(-1) == -1
-    assert lib.rips_set_shortcuts(4) == -1
+    assert lib.rips_set_shortcuts(8) == -1
     assert lib.rips_batched_autotune(None, None, 1, 2, 8, 1, ctypes.c_float(1.0), 2, None, None,
                                      0, None, None, None) == -1
 
