@@ -304,6 +304,28 @@ rips_status rips_set_shortcuts(int32_t flags);
 rips_status rips_get_shortcuts(int32_t *flags);
 
 /*
+ * The homology variant, for the ablation of the sections "Clearing
+ * inessential birth columns" and "Cohomology": the filtration boundary
+ * matrices are reduced with clearing (Algorithm 2 on boundary matrices),
+ * from dimension max_dim + 1 down to 1, one column after another, with the
+ * reduced columns stored explicitly. The pairs of a filtration and of its
+ * dual coincide, so the bars equal rips_barcode's (same canonical order);
+ * what differs is the work: clearing cannot skip any column of the top
+ * dimension, which cohomology never reduces. Arguments and result as for
+ * rips_barcode, with max_dim <= 2 (else RIPS_E_INVALID_ARG); the shortcuts
+ * of rips_set_shortcuts do not apply. stats[d] describes the boundary of the
+ * (d+1)-simplices: candidates = their number, cleared = columns skipped
+ * (pivots of the boundary above), columns = columns reduced, reduced =
+ * columns left nonzero (every pair of dimension d), additions = column
+ * additions, bars_nonzero = pairs of positive length, essential = essential
+ * bars of dimension d, entries_stored = entries of the stored columns; the
+ * other fields are 0. column_count is 0. RIPS_E_CAPACITY when a reduced
+ * column exceeds 2048 entries or 2^24 additions.
+ */
+rips_status rips_barcode_homology(const float *data, int64_t n, int32_t dim, int32_t max_dim,
+                                  float threshold, uint32_t p, rips_result **out);
+
+/*
  * Launch configuration of the batched path (per device, the current one):
  *   delta_slots        LDS slots of each workgroup's working-column delta:
  *                      512, 1024 or 2048 (0 = default, 2048);

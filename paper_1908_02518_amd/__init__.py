@@ -44,6 +44,7 @@ EXPORTS = (
     "rips_barcode",
     "rips_result_free",
     "rips_barcode_cocycles",
+    "rips_barcode_homology",
     "rips_cocycles_free",
     "rips_status_string",
     "rips_last_error",
@@ -164,6 +165,8 @@ def _load():
                                  ctypes.c_float, ctypes.c_uint32,
                                  ctypes.POINTER(ctypes.POINTER(rips_result))]
     lib.rips_barcode.restype = ctypes.c_int
+    lib.rips_barcode_homology.argtypes = lib.rips_barcode.argtypes
+    lib.rips_barcode_homology.restype = ctypes.c_int
     lib.rips_result_free.argtypes = [ctypes.POINTER(rips_result)]
     lib.rips_result_free.restype = None
     lib.rips_barcode_cocycles.argtypes = [f32p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
@@ -273,6 +276,19 @@ def barcode(points: np.ndarray | None = None, *, dist: np.ndarray | None = None,
             max_dim: int = 1, threshold: float = float("inf"), p: int = 2) -> Result:
     """Barcode of a host point cloud (float32 (n, m)) or full distance matrix
     (float32 (n, n), entries i > j read) via the C ABI rips_barcode."""
+    return _run_result(_lib.rips_barcode, points, dist, max_dim, threshold, p)
+
+
+def barcode_homology(points: np.ndarray | None = None, *, dist: np.ndarray | None = None,
+                     max_dim: int = 1, threshold: float = float("inf"), p: int = 2) -> Result:
+    """The same barcode by the homology variant (rips_barcode_homology):
+    boundary matrices reduced with clearing from the top dimension down, for
+    the ablation against cohomology; max_dim <= 2. stats[d] counts the
+    columns of the boundary of the (d+1)-simplices."""
+    return _run_result(_lib.rips_barcode_homology, points, dist, max_dim, threshold, p)
+
+
+def _run_result(entry, points, dist, max_dim, threshold, p) -> Result:
     if (points is None) == (dist is None):
         raise ValueError("give exactly one of points, dist")
     if points is not None:
@@ -286,8 +302,8 @@ def barcode(points: np.ndarray | None = None, *, dist: np.ndarray | None = None,
             raise ValueError("dist must be (n, n)")
         n, m = x.shape[0], 0
     out = ctypes.POINTER(rips_result)()
-    _check(_lib.rips_barcode(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, m, max_dim,
-                             ctypes.c_float(threshold), p, ctypes.byref(out)))
+    _check(entry(x.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), n, m, max_dim,
+                 ctypes.c_float(threshold), p, ctypes.byref(out)))
     try:
         r = out.contents
         bars, stats, counts, cols = [], [], [], []

@@ -190,6 +190,11 @@ enum BufId {
     BB_SCAL,
     BB_BINOM,
     BB_INV,
+    // homology variant
+    B_HOM_OUT,
+    B_HOM_PERM,
+    B_HOM_PERM2,
+    B_HOM_TAPP,
     B_NUM
 };
 
@@ -974,6 +979,198 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
     return RIPS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// The homology variant (ablation): boundary matrices with clearing, from the
+// top dimension down (section "Clearing inessential birth columns"); the
+// same bars as the cohomology path, with column counters that show what
+// clearing leaves to reduce in homology.
+// ---------------------------------------------------------------------------
+struct HomRun {
+    float t_eff, r_enc;
+    int sparse;
+    int64_t count[kMaxDim + 1];          // bars per dimension (unordered in B_BAR_* + d)
+    int64_t simplex_count[kMaxDim + 2];
+    rips_dim_stats stats[kMaxDim + 1];
+};
+
+rips_status run_homology(DevCtx &C, const float *d_in, int n, int m, int max_dim, float t, uint32_t p,
+                         hipStream_t st, HomRun &o) {
+    memset(&o, 0, sizeof(o));
+    Prepared P;
+    rips_status rs = prepare(C, d_in, n, m, max_dim + 2, t, p, st, P);
+    if (rs) return rs;
+    o.t_eff = C.host_scal->t_eff;
+    o.r_enc = C.host_scal->r_enc;
+    o.sparse = P.sparse;
+    void *q;
+    const int top = max_dim + 1;
+    // the simplices of every dimension up to the top
+    SimplexList list[kMaxDim + 2];
+    int64_t cnt[kMaxDim + 2] = {};
+    cnt[0] = n;
+    list[1] = SimplexList{P.E.idx, P.E.diam};
+    cnt[1] = P.nedges;
+    const int G = group_size_for(P);
+    for (int k = 2; k <= top; ++k) {
+        int64_t cap = C.hint_list[k] > 0 ? C.hint_list[k] : std::max<int64_t>(cnt[k - 1] * 4, 1024);
+        bool fits = false;
+        for (int attempt = 0; attempt < 3 && !fits; ++attempt) {
+            HIP_TRY(C.ensure(B_LIST_IDX + k, (size_t)cap * 8, &q));
+            list[k].idx = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_LIST_DIAM + k, (size_t)cap * 4, &q));
+            list[k].diam = as<float>(q);
+            hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, &P.scal->list, 0ull);
+            launch_expand(G, P.ctx, k, list[k - 1], cnt[k - 1], P.scal, list[k], cap, false, st);
+            if ((rs = read_scalars(C, P.scal, st))) return rs;
+            fits = (int64_t)C.host_scal->list <= cap;
+            if (!fits) cap = (int64_t)C.host_scal->list;
+        }
+        if (!fits) return fail(RIPS_E_CAPACITY, "simplex list did not fit");
+        cnt[k] = (int64_t)C.host_scal->list;
+        if (cnt[k] > C.hint_list[k]) C.hint_list[k] = cnt[k];
+    }
+    for (int k = 0; k <= top; ++k) o.simplex_count[k] = cnt[k];
+    // each dimension's simplices younger first (the column sort)
+    Columns sorted[kMaxDim + 2] = {};
+    for (int k = 1; k <= top; ++k) {
+        const int64_t N = cnt[k];
+        if (N > 0x7fffffff) return fail(RIPS_E_CAPACITY, "too many simplices for the homology variant");
+        Columns in{list[k].idx, list[k].diam, nullptr, nullptr}, out;
+        HIP_TRY(C.ensure(B_SURV_J, (size_t)N * 4, &q));
+        in.j = as<int>(q);
+        HIP_TRY(C.ensure(B_SURV_TAPP, (size_t)N, &q));
+        in.tapp = as<uint8_t>(q);
+        HIP_TRY(C.ensure(B_COL_IDX + k, (size_t)N * 8, &q));
+        out.idx = as<int64_t>(q);
+        HIP_TRY(C.ensure(B_COL_DIAM + k, (size_t)N * 4, &q));
+        out.diam = as<float>(q);
+        HIP_TRY(C.ensure(B_COL_J + k, (size_t)N * 4, &q));
+        out.j = as<int>(q);
+        HIP_TRY(C.ensure(B_COL_TAPP + k, (size_t)N, &q));
+        out.tapp = as<uint8_t>(q);
+        sorted[k] = out;
+        if (N == 0) continue;
+        SortBufs sb;
+        HIP_TRY(C.ensure(B_SORT_LO0, (size_t)N * 8, &q));
+        sb.lo[0] = as<u64>(q);
+        HIP_TRY(C.ensure(B_SORT_LO1, (size_t)N * 8, &q));
+        sb.lo[1] = as<u64>(q);
+        HIP_TRY(C.ensure(B_SORT_HI0, (size_t)N * 4, &q));
+        sb.hi[0] = as<u32>(q);
+        HIP_TRY(C.ensure(B_SORT_HI1, (size_t)N * 4, &q));
+        sb.hi[1] = as<u32>(q);
+        HIP_TRY(C.ensure(B_SORT_V0, (size_t)N * 4, &q));
+        sb.val[0] = as<u32>(q);
+        HIP_TRY(C.ensure(B_SORT_V1, (size_t)N * 4, &q));
+        sb.val[1] = as<u32>(q);
+        hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, &P.scal->survivors, (unsigned long long)N);
+        launch_sort_columns(in, P.scal, sb, bytes_for((uint64_t)choose_i64(n, k + 1)), out, st);
+    }
+    // bars of dimension d: at most one per d-simplex
+    BarBuf bars[kMaxDim + 1];
+    int64_t bcap[kMaxDim + 1];
+    for (int d = 0; d <= max_dim; ++d) {
+        bcap[d] = std::max<int64_t>(cnt[d], 1);
+        HIP_TRY(C.ensure(B_BAR_BIRTH + d, (size_t)bcap[d] * 4, &q));
+        bars[d].birth = as<float>(q);
+        HIP_TRY(C.ensure(B_BAR_DEATH + d, (size_t)bcap[d] * 4, &q));
+        bars[d].death = as<float>(q);
+        HIP_TRY(C.ensure(B_BAR_BS + d, (size_t)bcap[d] * 8, &q));
+        bars[d].bs = as<int64_t>(q);
+        HIP_TRY(C.ensure(B_BAR_DS + d, (size_t)bcap[d] * 8, &q));
+        bars[d].ds = as<int64_t>(q);
+    }
+    HIP_TRY(C.ensure(B_HOM_OUT, sizeof(HomOut), &q));
+    HomOut *hout = as<HomOut>(q);
+    int64_t npairs[kMaxDim + 1] = {}, ness[kMaxDim + 1] = {};
+    PivotHash above{nullptr, nullptr, 0};
+    for (int k = top; k >= 1; --k) {
+        const int64_t N = cnt[k];
+        if ((uint64_t)2 * N + 64 > (1ull << 31)) return fail(RIPS_E_CAPACITY, "too many columns");
+        const uint32_t phcap = next_pow2((uint64_t)2 * N + 64);
+        const int slot = k & 1;
+        HomJob J{};
+        HIP_TRY(C.ensure(B_PH_KEYS0 + slot, (size_t)phcap * 8, &q));
+        J.piv.keys = as<int64_t>(q);
+        HIP_TRY(C.ensure(B_PH_VALS0 + slot, (size_t)phcap * 4, &q));
+        J.piv.vals = as<int32_t>(q);
+        J.piv.mask = phcap - 1;
+        HIP_TRY(C.ensure(B_V_OFF, (size_t)std::max<int64_t>(N, 1) * 8, &q));
+        J.roff = as<int64_t>(q);
+        HIP_TRY(C.ensure(B_V_LEN, (size_t)std::max<int64_t>(N, 1) * 4, &q));
+        J.rlen = as<int>(q);
+        J.c = P.ctx;
+        J.k = k;
+        J.cidx = sorted[k].idx;
+        J.cdia = sorted[k].diam;
+        J.ncols = N;
+        J.p = p;
+        J.inv = P.inv;
+        J.clear = above;
+        J.pairs = bars[k - 1];
+        J.pairs_cap = bcap[k - 1];
+        J.essential = k <= max_dim ? 1 : 0;
+        if (J.essential) {
+            J.ess = BarBuf{bars[k].birth + npairs[k], bars[k].death + npairs[k], bars[k].bs + npairs[k],
+                           bars[k].ds + npairs[k]};
+            J.ess_cap = bcap[k] - npairs[k];
+        }
+        J.out = hout;
+        int64_t pcap = std::max<int64_t>(C.hint_v, 8 * N + 4096);
+        HomOut h{};
+        for (int attempt = 0; attempt < 6; ++attempt) {
+            HIP_TRY(C.ensure(B_V_IDX, (size_t)pcap * 8, &q));
+            J.pidx = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_V_DIAM, (size_t)pcap * 4, &q));
+            J.pdia = as<float>(q);
+            HIP_TRY(C.ensure(B_V_COEF, (size_t)pcap * 4, &q));
+            J.pcoef = as<u32>(q);
+            J.pcap = pcap;
+            launch_fill_i64(J.piv.keys, phcap, kEmpty, st);
+            HIP_TRY(launch_hom_reduce(J, st));
+            HIP_TRY(hipMemcpyAsync(&h, hout, sizeof(h), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (h.status != kHomPool) break;
+            pcap *= 4;
+        }
+        if (h.status == kHomPool) return fail(RIPS_E_CAPACITY, "stored columns exceed the pool");
+        if (h.status == kHomFull)
+            return fail(RIPS_E_CAPACITY, "a column of the homology variant exceeded " +
+                                             std::to_string(kHomCap) + " entries");
+        if (h.status == kHomBound)
+            return fail(RIPS_E_CAPACITY, "a column of the homology variant exceeded 2^24 additions");
+        if (h.status != kHomOk) return fail(RIPS_E_HIP, "homology variant: internal consistency check failed");
+        if (h.stored > C.hint_v) C.hint_v = h.stored;
+        npairs[k - 1] = h.pairs;
+        if (J.essential) ness[k] = h.essential;
+        rips_dim_stats &sd = o.stats[k - 1];
+        sd.candidates = N;
+        sd.cleared = h.cleared;
+        sd.columns = h.reduced;
+        sd.reduced = h.nonzero;
+        sd.additions = h.additions;
+        sd.bars_nonzero = h.pairs;
+        sd.entries_stored = h.stored;
+        above = J.piv;
+    }
+    // dimension 0: vertices that no edge column has as its pivot
+    hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, (unsigned long long *)&hout->essential, 0ull);
+    launch_hom_vertices(n, above, BarBuf{bars[0].birth + npairs[0], bars[0].death + npairs[0],
+                                         bars[0].bs + npairs[0], bars[0].ds + npairs[0]},
+                        hout, st);
+    {
+        HomOut h{};
+        HIP_TRY(hipMemcpyAsync(&h, hout, sizeof(h), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        ness[0] = h.essential;
+    }
+    for (int d = 0; d <= max_dim; ++d) {
+        o.count[d] = npairs[d] + ness[d];
+        o.stats[d].essential = ness[d];
+    }
+    return RIPS_OK;
+}
+
 BarBuf internal_bars(DevCtx &C, int d) {
     BarBuf b;
     b.birth = as<float>(C.buf[B_BAR_BIRTH + d]);
@@ -1357,6 +1554,113 @@ rips_status rips_barcode(const float *data, int64_t n, int32_t dim, int32_t max_
                 rips_result_free(r);
                 return fail(RIPS_E_HIP, "copying columns to the host");
             }
+        }
+    }
+    *out = r;
+    return RIPS_OK;
+}
+
+rips_status rips_barcode_homology(const float *data, int64_t n, int32_t dim, int32_t max_dim,
+                                  float threshold, uint32_t p, rips_result **out) {
+    g_err.clear();
+    if (!out) return fail(RIPS_E_INVALID_ARG, "null out");
+    *out = nullptr;
+    if (!data) return fail(RIPS_E_INVALID_ARG, "null data");
+    rips_status rs = validate(n, dim, max_dim, threshold, p, 0);
+    if (rs) return rs;
+    if (max_dim > 2) return fail(RIPS_E_INVALID_ARG, "the homology variant computes dimensions 0-2");
+    DevCtx *C;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    hipStream_t st = nullptr;
+    void *q;
+    const size_t in_elems = dim > 0 ? (size_t)n * dim : (size_t)n * n;
+    HIP_TRY(C->ensure(B_INPUT, in_elems * 4, &q));
+    float *d_in = as<float>(q);
+    HIP_TRY(hipMemcpyAsync(d_in, data, in_elems * 4, hipMemcpyHostToDevice, st));
+    HomRun o;
+    rs = run_homology(*C, d_in, (int)n, dim, max_dim, threshold, p, st, o);
+    if (rs) return rs;
+    rips_result *r = (rips_result *)calloc(1, sizeof(rips_result));
+    if (!r) return fail(RIPS_E_OOM, "host allocation");
+    r->n = (int32_t)n;
+    r->max_dim = max_dim;
+    r->p = p;
+    r->sparse = o.sparse;
+    r->threshold_used = o.t_eff;
+    r->enclosing_radius = o.r_enc;
+    const int nd = max_dim + 1;
+    r->dims = (rips_bars *)calloc(nd, sizeof(rips_bars));
+    r->stats = (rips_dim_stats *)calloc(nd, sizeof(rips_dim_stats));
+    r->simplex_count = (int64_t *)calloc(nd, sizeof(int64_t));
+    r->column_count = (int64_t *)calloc(nd, sizeof(int64_t));
+    r->column_index = (int64_t **)calloc(nd, sizeof(int64_t *));
+    r->column_diam = (float **)calloc(nd, sizeof(float *));
+    if (!r->dims || !r->stats || !r->simplex_count || !r->column_count || !r->column_index ||
+        !r->column_diam) {
+        rips_result_free(r);
+        return fail(RIPS_E_OOM, "host allocation");
+    }
+    Scalars *scal = as<Scalars>(C->buf[B_SCAL]);
+    for (int d = 0; d < nd; ++d) {
+        const int64_t c = o.count[d];
+        r->stats[d] = o.stats[d];
+        r->simplex_count[d] = o.simplex_count[d];
+        rips_bars &b = r->dims[d];
+        b.count = c;
+        b.birth = (float *)malloc(sizeof(float) * (c ? c : 1));
+        b.death = (float *)malloc(sizeof(float) * (c ? c : 1));
+        b.birth_simplex = (int64_t *)malloc(sizeof(int64_t) * (c ? c : 1));
+        b.death_simplex = (int64_t *)malloc(sizeof(int64_t) * (c ? c : 1));
+        r->column_index[d] = (int64_t *)malloc(sizeof(int64_t));
+        r->column_diam[d] = (float *)malloc(sizeof(float));
+        if (!b.birth || !b.death || !b.birth_simplex || !b.death_simplex || !r->column_index[d] ||
+            !r->column_diam[d]) {
+            rips_result_free(r);
+            return fail(RIPS_E_OOM, "host allocation");
+        }
+        if (c == 0) continue;
+        // canonical order: sort by birth simplex (younger first, carrying
+        // the bar's slot), then gather in reverse
+        const BarBuf in = internal_bars(*C, d);
+        Columns ci{in.bs, in.birth, nullptr, nullptr}, co;
+        hipError_t e = hipSuccess;
+        auto need = [&](int id, size_t bytes) -> void * {
+            void *pp = nullptr;
+            if (e == hipSuccess) e = C->ensure(id, bytes, &pp);
+            return pp;
+        };
+        ci.j = (int *)need(B_HOM_PERM, (size_t)c * 4);
+        ci.tapp = (uint8_t *)need(B_SURV_TAPP, (size_t)c);
+        co.idx = (int64_t *)need(B_SURV_IDX, (size_t)c * 8);
+        co.diam = (float *)need(B_SURV_DIAM, (size_t)c * 4);
+        co.j = (int *)need(B_HOM_PERM2, (size_t)c * 4);
+        co.tapp = (uint8_t *)need(B_HOM_TAPP, (size_t)c);
+        SortBufs sb;
+        sb.lo[0] = (u64 *)need(B_SORT_LO0, (size_t)c * 8);
+        sb.lo[1] = (u64 *)need(B_SORT_LO1, (size_t)c * 8);
+        sb.hi[0] = (u32 *)need(B_SORT_HI0, (size_t)c * 4);
+        sb.hi[1] = (u32 *)need(B_SORT_HI1, (size_t)c * 4);
+        sb.val[0] = (u32 *)need(B_SORT_V0, (size_t)c * 4);
+        sb.val[1] = (u32 *)need(B_SORT_V1, (size_t)c * 4);
+        char *sg = (char *)need(B_STAGE, (size_t)c * 24);
+        if (e != hipSuccess) {
+            rips_result_free(r);
+            return fail(RIPS_E_OOM, "sort buffers");
+        }
+        launch_hom_iota(ci.j, c, st);
+        hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, &scal->survivors, (unsigned long long)c);
+        launch_sort_columns(ci, scal, sb, bytes_for((uint64_t)choose_i64(n, d + 1)), co, st);
+        BarBuf dst{(float *)sg, (float *)(sg + c * 4), (int64_t *)(sg + c * 8), (int64_t *)(sg + c * 16)};
+        launch_hom_gather(in, co.j, c, dst, st);
+        hipError_t e1 = hipMemcpyAsync(b.birth, dst.birth, c * 4, hipMemcpyDeviceToHost, st);
+        hipError_t e2 = hipMemcpyAsync(b.death, dst.death, c * 4, hipMemcpyDeviceToHost, st);
+        hipError_t e3 = hipMemcpyAsync(b.birth_simplex, dst.bs, c * 8, hipMemcpyDeviceToHost, st);
+        hipError_t e4 = hipMemcpyAsync(b.death_simplex, dst.ds, c * 8, hipMemcpyDeviceToHost, st);
+        hipError_t e5 = hipStreamSynchronize(st);
+        if (e1 || e2 || e3 || e4 || e5) {
+            rips_result_free(r);
+            return fail(RIPS_E_HIP, "copying bars to the host");
         }
     }
     *out = r;

@@ -133,6 +133,55 @@ void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Colu
                          hipStream_t st);
 void launch_emit(BarBuf in, Scalars *s, int reverse, BarBuf out, hipStream_t st);
 
+// ---- the homology variant (rips_homology.hip)
+constexpr int kHomThreads = 256;
+constexpr int kHomCap = 2048;            // entries of the working column and of a stored one
+constexpr int64_t kHomMaxAdds = 1 << 24; // additions per column
+constexpr int kHomOk = 0, kHomFull = 1, kHomPool = 2, kHomTable = 3, kHomBound = 4;
+
+struct HomOut {
+    int status; // kHomOk, or what stopped the reduction
+    int pad;
+    long long pairs;     // bars of dimension k-1 (pairs of distinct diameters)
+    long long nonzero;   // columns left nonzero (every pair)
+    long long essential; // essential bars of dimension k
+    long long cleared;   // columns skipped by clearing
+    long long reduced;   // columns reduced
+    long long additions; // column additions
+    long long stored;    // entries of the stored columns
+    long long longest;   // longest reduced column
+};
+
+struct HomJob {
+    Ctx<DistFull> c;
+    int k;               // columns are k-simplices
+    const int64_t *cidx; // the k-simplices <= t, younger first
+    const float *cdia;
+    int64_t ncols;
+    u32 p;
+    const u32 *inv;
+    PivotHash clear;     // pivots of the boundary of the (k+1)-simplices (keys null: none)
+    PivotHash piv;       // this boundary's pivots -> stored column
+    int64_t *roff;       // stored column s: entries [roff[s], roff[s] + rlen[s]) of the pool
+    int *rlen;
+    int64_t *pidx;       // the pool, younger first within a column
+    float *pdia;
+    u32 *pcoef;
+    int64_t pcap;
+    BarBuf pairs;        // dimension k-1
+    int64_t pairs_cap;
+    BarBuf ess;          // dimension k (used when essential != 0)
+    int64_t ess_cap;
+    int essential;
+    HomOut *out;
+};
+
+size_t hom_lds_bytes();
+hipError_t launch_hom_reduce(const HomJob &J, hipStream_t st);
+void launch_hom_vertices(int n, PivotHash piv, BarBuf ess, HomOut *o, hipStream_t st);
+void launch_hom_iota(int *a, int64_t n, hipStream_t st);
+void launch_hom_gather(BarBuf in, const int *perm, int64_t n, BarBuf out, hipStream_t st);
+
 constexpr int kRedThreads = 256;
 
 } // namespace rips

@@ -1,0 +1,77 @@
+"""The homology variant (rips_barcode_homology): boundary matrices reduced
+with clearing from the top dimension down. The pairs of a filtration and of
+its dual coincide (section "Cohomology"), so the bars must equal the
+oracle's bit for bit. The column counters must show what clearing does in
+homology: nothing in the top dimension (every (max_dim+1)-simplex is a
+column), and below it exactly the pivots of the boundary above; and they
+must show the asymmetry with cohomology, which reduces far fewer columns."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+INF = float("inf")
+
+
+def rips():
+    import paper_1908_02518_amd as r
+    return r
+
+
+CASES = [
+    ("rectangle-p3", lambda: workloads.rectangle(), 1, INF, 3),
+    ("hexagon", lambda: workloads.regular_polygon(6), 2, INF, 2),
+    ("lattice-ties", lambda: workloads.integer_lattice(27, 3, 5, side=3), 2, INF, 2),
+    ("cube-40-p5", lambda: workloads.uniform_cube(40, 3, 31), 2, INF, 5),
+    ("cube-30-p3-t", lambda: workloads.uniform_cube(30, 4, 7), 2, 0.9, 3),
+    ("sphere-100", lambda: workloads.config(1)["clouds"][0], 1, INF, 2),
+    ("so3-1000-d1", lambda: workloads.config(2)["clouds"][0], 1, 1.4, 2),
+]
+
+
+@pytest.mark.parametrize("name,make,max_dim,t,p", CASES, ids=[c[0] for c in CASES])
+def test_homology_bars_equal_oracle(name, make, max_dim, t, p):
+    r = rips()
+    x = make()
+    print(f"[case] homology {name}", flush=True)
+    ref = oracle.barcode(x, max_dim=max_dim, threshold=t, p=p)
+    got = r.barcode_homology(x, max_dim=max_dim, threshold=t, p=p)
+    for d in range(max_dim + 1):
+        for f in ("birth", "death", "birth_simplex", "death_simplex"):
+            assert np.array_equal(getattr(got.bars[d], f), getattr(ref.bars[d], f)), (name, d, f)
+    top = max_dim
+    for d in range(max_dim + 1):
+        s = got.stats[d]
+        assert s["candidates"] == ref.counts[d + 1], (name, d)
+        assert s["columns"] == s["candidates"] - s["cleared"], (name, d)
+        assert s["bars_nonzero"] + s["essential"] == len(got.bars[d].birth), (name, d)
+        if d == top:
+            assert s["cleared"] == 0, (name, d)
+        else:
+            # the cleared (d+1)-simplices are the pivots of the boundary above
+            assert s["cleared"] == got.stats[d + 1]["reduced"], (name, d)
+    # dimension 0: every vertex is a pivot of an edge column or essential
+    assert got.stats[0]["reduced"] + got.stats[0]["essential"] == got.n
+
+
+def test_homology_reduces_more_columns_than_cohomology():
+    r = rips()
+    c = workloads.config(2)
+    x = c["clouds"][0]
+    hom = r.barcode_homology(x, max_dim=1, threshold=1.4, p=2)
+    coh = r.barcode(x, max_dim=1, threshold=1.4, p=2)
+    # homology must reduce every triangle; cohomology reduces the edges
+    # clearing and the apparent pairs leave
+    assert hom.stats[1]["columns"] == hom.stats[1]["candidates"]
+    assert hom.stats[1]["columns"] > 100 * coh.stats[1]["columns"]
+    for f in ("birth", "death", "birth_simplex", "death_simplex"):
+        assert np.array_equal(getattr(hom.bars[1], f), getattr(coh.bars[1], f))
+
+
+def test_homology_rejects_dimension_3():
+    r = rips()
+    with pytest.raises(r.RipsError):
+        r.barcode_homology(workloads.regular_polygon(6), max_dim=3)
