@@ -27,6 +27,9 @@ per step. Also reported:
                     cloud: ms per barcode with clearing and no other
                     shortcut, clearing + emergent, all three (the default),
                     clearing + apparent; and cohomology without clearing
+  homology          the homology variant (boundary matrices with clearing,
+                    top dimension first) on the bench cloud in dims 0-1,
+                    against cohomology: seconds, columns and additions
   paper_scale       one barcode of a paper-scale workload (o3 shape, 1024
                     points, threshold 1.8, dims 0-3), against the CPU
                     implementation of the paper's algorithm
@@ -262,6 +265,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-shortcuts", action="store_true",
                     help="skip the shortcut ablation leg (Table 3 of the paper, on so3-1000)")
+    ap.add_argument("--no-homology", action="store_true",
+                    help="skip the homology-variant leg (so3-1000, dims 0-1, about 15 s)")
     ap.add_argument("--no-paper-scale", action="store_true",
                     help="skip the paper-scale o3-1024 (t = 1.8, dims 0-3) leg")
     ap.add_argument("--pmc-run", action="store_true",
@@ -475,6 +480,33 @@ def main() -> int:
         finally:
             rips.set_shortcuts()
 
+    homology = None
+    if not args.no_homology:
+        # the homology variant on the bench cloud, dims 0-1: boundary matrices
+        # with clearing from the top down, against cohomology with clearing
+        # (sections "Clearing inessential birth columns" and "Cohomology")
+        c0 = time.perf_counter()
+        hom = rips.barcode_homology(x, max_dim=1, threshold=t, p=p)
+        t_hom = time.perf_counter() - c0
+        rips.barcode(x, max_dim=1, threshold=t, p=p)  # warm-up
+        c0 = time.perf_counter()
+        coh = rips.barcode(x, max_dim=1, threshold=t, p=p)
+        t_coh = time.perf_counter() - c0
+        same = all(np.array_equal(getattr(hom.bars[d], f), getattr(coh.bars[d], f))
+                   for d in range(2) for f in ("birth", "death", "birth_simplex", "death_simplex"))
+        homology = {
+            "workload": "so3-1000, t = 1.4, dims 0-1, Z/2 (host input, one call each)",
+            "seconds_homology": round(t_hom, 3),
+            "seconds_cohomology": round(t_coh, 4),
+            "columns_homology": [hom.stats[d]["columns"] for d in range(2)],
+            "cleared_homology": [hom.stats[d]["cleared"] for d in range(2)],
+            "additions_homology": [hom.stats[d]["additions"] for d in range(2)],
+            "columns_cohomology": [coh.stats[d]["columns"] for d in range(2)],
+            "additions_cohomology": [coh.stats[d]["additions"] for d in range(2)],
+            "bars_equal": bool(same),
+        }
+        log(f"homology variant: {t_hom:.2f} s against {1e3 * t_coh:.1f} ms, bars equal {same}")
+
     paper_scale = None
     if not args.no_paper_scale:
         c6 = workloads.config(6)
@@ -577,6 +609,7 @@ def main() -> int:
         "eliminated": eliminated,
         "batched": batched,
         "shortcuts": shortcuts,
+        "homology": homology,
         "paper_scale": paper_scale,
         "cpu_baseline": cpu,
         "cpu_paper_algorithm": cpu_paper,
