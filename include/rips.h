@@ -304,6 +304,25 @@ rips_status rips_set_shortcuts(int32_t flags);
 rips_status rips_get_shortcuts(int32_t *flags);
 
 /*
+ * When the single-cloud path keeps a death column's reduced column R_j beside
+ * V_j (Table 3: implicit reduction storing, or discarding, the reduced
+ * matrix; section "Implicit matrix reduction"). An addition of column j
+ * later adds the stored R_j, or recomputes the coboundaries of V_j's
+ * simplices.
+ *   RIPS_R_AUTO (default): R_j is kept when it is cheaper to add than those
+ *     coboundaries are to recompute (and fits the working column's LDS part);
+ *   RIPS_R_DISCARD: never kept;
+ *   RIPS_R_STORE: kept whenever it fits the working column's LDS part.
+ * The bars are the same in every mode. Other values: RIPS_E_INVALID_ARG.
+ * The batched path always uses RIPS_R_AUTO.
+ */
+#define RIPS_R_AUTO 0
+#define RIPS_R_DISCARD 1
+#define RIPS_R_STORE 2
+rips_status rips_set_reduced_storage(int32_t mode);
+rips_status rips_get_reduced_storage(int32_t *mode);
+
+/*
  * The homology variant, for the ablation of the sections "Clearing
  * inessential birth columns" and "Cohomology": the filtration boundary
  * matrices are reduced with clearing (Algorithm 2 on boundary matrices),

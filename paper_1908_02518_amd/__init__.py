@@ -45,6 +45,8 @@ EXPORTS = (
     "rips_result_free",
     "rips_barcode_cocycles",
     "rips_barcode_homology",
+    "rips_set_reduced_storage",
+    "rips_get_reduced_storage",
     "rips_cocycles_free",
     "rips_status_string",
     "rips_last_error",
@@ -205,6 +207,10 @@ def _load():
     lib.rips_set_shortcuts.restype = ctypes.c_int
     lib.rips_get_shortcuts.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     lib.rips_get_shortcuts.restype = ctypes.c_int
+    lib.rips_set_reduced_storage.argtypes = [ctypes.c_int32]
+    lib.rips_set_reduced_storage.restype = ctypes.c_int
+    lib.rips_get_reduced_storage.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+    lib.rips_get_reduced_storage.restype = ctypes.c_int
     lib.rips_batched_set_config.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.rips_batched_set_config.restype = ctypes.c_int
     lib.rips_batched_get_config.argtypes = [ctypes.POINTER(ctypes.c_int32),
@@ -553,6 +559,24 @@ def set_shortcuts(flags: int = SHORTCUT_APPARENT | SHORTCUT_EMERGENT | SHORTCUT_
     gives no column to a pivot of the dimension below. The bars are the same
     with any of them off."""
     _check(_lib.rips_set_shortcuts(int(flags)))
+
+
+R_AUTO = 0
+R_DISCARD = 1
+R_STORE = 2
+
+
+def set_reduced_storage(mode: int = R_AUTO):
+    """When the single-cloud path keeps R_j beside V_j (Table 3's "storing R"
+    and "discarding R" rows): R_AUTO when cheaper to add, R_DISCARD never,
+    R_STORE whenever it fits. The bars are the same in every mode."""
+    _check(_lib.rips_set_reduced_storage(int(mode)))
+
+
+def get_reduced_storage() -> int:
+    a = ctypes.c_int32()
+    _check(_lib.rips_get_reduced_storage(ctypes.byref(a)))
+    return int(a.value)
 
 
 def get_shortcuts() -> int:

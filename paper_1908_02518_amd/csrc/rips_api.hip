@@ -215,6 +215,7 @@ struct DevCtx {
     int reduce_groups = 0; // workgroups of the single-cloud reduction: 0 = one per CU
     int shortcuts = kShortApparent | kShortEmergent | kShortClearing; // of the single-cloud path
     int cocycle_dim = -1; // dimension whose zero columns also store V_j (cocycle requests)
+    int rstore = kRStoreAuto; // when the single-cloud path stores R_j beside V_j
     hipStream_t capture_stream = nullptr;
     // cached graph of the batched launch and the arguments it was built for
     hipGraphExec_t batch_exec = nullptr;
@@ -901,6 +902,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             J.par = par;
             J.shortcuts = C.shortcuts;
             J.keep_essential_v = k == C.cocycle_dim ? 1 : 0;
+            J.rstore = C.rstore;
             J.prev_bits = W.bits;
             J.prev = ph_prev;
             J.cand_avg = P.sparse ? (float)(2.0 * (double)P.nedges / (double)std::max<int64_t>(n, 1))
@@ -1951,6 +1953,29 @@ rips_status rips_set_shortcuts(int32_t flags) {
     C->shortcuts = (flags & RIPS_SHORTCUT_APPARENT ? kShortApparent : 0) |
                    (flags & RIPS_SHORTCUT_EMERGENT ? kShortEmergent : 0) |
                    (flags & RIPS_SHORTCUT_CLEARING ? kShortClearing : 0);
+    return RIPS_OK;
+}
+
+rips_status rips_set_reduced_storage(int32_t mode) {
+    g_err.clear();
+    if (mode != RIPS_R_AUTO && mode != RIPS_R_DISCARD && mode != RIPS_R_STORE)
+        return fail(RIPS_E_INVALID_ARG, "unknown storage mode");
+    DevCtx *C;
+    rips_status rs = get_ctx(&C);
+    if (rs) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    C->rstore = mode == RIPS_R_DISCARD ? kRStoreNever : (mode == RIPS_R_STORE ? kRStoreAlways : kRStoreAuto);
+    return RIPS_OK;
+}
+
+rips_status rips_get_reduced_storage(int32_t *mode) {
+    g_err.clear();
+    if (!mode) return fail(RIPS_E_INVALID_ARG, "null mode");
+    DevCtx *C;
+    rips_status rs = get_ctx(&C);
+    if (rs) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    *mode = C->rstore == kRStoreNever ? RIPS_R_DISCARD : (C->rstore == kRStoreAlways ? RIPS_R_STORE : RIPS_R_AUTO);
     return RIPS_OK;
 }
 

@@ -488,6 +488,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         J.app = app;
         J.shortcuts = kShortApparent | kShortEmergent | kShortClearing;
         J.keep_essential_v = 0;
+        J.rstore = kRStoreAuto;
         J.prev_bits = nullptr;
         J.prev = PivotHash{nullptr, nullptr, 0};
         gsync();

@@ -146,6 +146,11 @@ constexpr int kShortEmergent = 2;
 // of the dimension below gets no column. Without it that column reduces to
 // zero and is not an essential class.
 constexpr int kShortClearing = 4;
+// When a death column's reduced column R_j is stored beside V_j (the
+// "storing R" and "discarding R" rows of Table 3): when it is cheaper to add
+// than V_j's coboundaries are to recompute, never, or whenever it has no far
+// part
+constexpr int kRStoreAuto = 0, kRStoreNever = 1, kRStoreAlways = 2;
 
 // Additions one column may take before the reduction reports an error: every
 // addition moves the pivot to a strictly younger row, so the loop ends; the
@@ -309,6 +314,7 @@ struct ReduceJob {
     ParState par;               // reduction spread over workgroups (cst null: one workgroup)
     int shortcuts;              // kShortApparent | kShortEmergent | kShortClearing: those in use
     int keep_essential_v;       // also store V_j of zero columns (their cocycles)
+    int rstore;                 // kRStoreAuto, kRStoreNever or kRStoreAlways: when R_j is kept
     // the pivots of the dimension below (read only without clearing): forest
     // edges of H0 as bits (k = 1), else that dimension's pivot table
     const u32 *prev_bits;
@@ -1927,7 +1933,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         RED_T0(t_st);
         int64_t roff = 0;
         int rn = -1;
-        if (S.fwn == 0 && S.mwn == 0) {
+        if (S.fwn == 0 && S.mwn == 0 && J.rstore != kRStoreNever) {
             if (S.len > 0 && *D.nslots > 0) {
                 result = base_merge<BT>(D, G, SC.SB, p, S);
                 if (result) break;
@@ -1936,7 +1942,9 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             const bool rb = S.len > 0;
             const int64_t live = rb ? count_live_base<BT>(SC.SB, p, S)
                                     : (int64_t)count_live<BT>(D, p, S);
-            if ((float)live <= 2.0f * (float)S.vest * J.cand_avg) {
+            const bool keep_r = J.rstore == kRStoreAlways ||
+                                (J.rstore == kRStoreAuto && (float)live <= 2.0f * (float)S.vest * J.cand_avg);
+            if (keep_r) {
                 rn = rb ? store_base<BT>(SC.SB, J.V, J.vcount, p, S, &roff)
                         : store_table<BT>(D, J.V, J.vcount, p, S, &roff);
                 if (rn < 0) {

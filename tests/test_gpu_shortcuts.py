@@ -83,3 +83,29 @@ def test_defaults_restored_and_all_shortcuts_used():
     assert got.stats[1]["apparent_col"] > 0
     assert got.stats[2]["emergent"] > 0
     assert got.stats[1]["cleared"] > 0 and got.stats[2]["cleared"] > 0
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+@pytest.mark.parametrize("name", ["cube-40-p5", "so3-1000", "torus4-2000"])
+def test_bars_unchanged_with_r_stored_or_discarded(mode, name):
+    """Table 3's storing / discarding of the reduced matrix R: the bars are
+    the oracle's in every mode, and the stored entries order as the modes do
+    (discarding keeps V only; storing keeps R whenever it fits)."""
+    r = rips()
+    print(f"[case] reduced storage {mode} {name}", flush=True)
+    x, ref = case(name)
+    _, _, max_dim, t, p = next(c for c in CASES if c[0] == name)
+    r.set_reduced_storage(mode)
+    try:
+        assert r.get_reduced_storage() == mode
+        got = r.barcode(x, max_dim=max_dim, threshold=t, p=p)
+    finally:
+        r.set_reduced_storage()
+    auto = r.barcode(x, max_dim=max_dim, threshold=t, p=p)
+    for d in range(max_dim + 1):
+        for f in ("birth", "death", "birth_simplex", "death_simplex"):
+            assert np.array_equal(getattr(got.bars[d], f), getattr(ref.bars[d], f)), (name, d, f)
+    for k in range(1, max_dim + 1):
+        a, g = auto.stats[k]["entries_stored"], got.stats[k]["entries_stored"]
+        assert (g <= a) if mode == r.R_DISCARD else (g >= a), (name, k, a, g)
+    assert r.get_reduced_storage() == r.R_AUTO
