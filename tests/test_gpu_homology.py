@@ -29,6 +29,9 @@ CASES = [
     ("cube-30-p3-t", lambda: workloads.uniform_cube(30, 4, 7), 2, 0.9, 3),
     ("sphere-100", lambda: workloads.config(1)["clouds"][0], 1, INF, 2),
     ("so3-1000-d1", lambda: workloads.config(2)["clouds"][0], 1, 1.4, 2),
+    ("one-point", lambda: np.zeros((1, 3), np.float32), 2, INF, 2),
+    ("no-edges", lambda: workloads.uniform_cube(12, 3, 5), 2, 0.0, 2),
+    ("duplicates-p3", lambda: np.repeat(workloads.uniform_cube(8, 2, 9), 2, axis=0), 2, INF, 3),
 ]
 
 
