@@ -40,6 +40,10 @@ def build(verbose: bool = False) -> str:
         obj = os.path.join(CSRC, os.path.basename(src) + ".o")
         # RIPS_PHASE_TIMERS=1 compiles the reduction's phase timers in (profiling only)
         extra = ["-DRIPS_PHASE_TIMERS=1"] if os.environ.get("RIPS_PHASE_TIMERS") == "1" else []
+        # RIPS_COLUMN_TRACE=1 records per-column clocks of the spread-out
+        # reduction into the file named by RIPS_COLUMN_TRACE_OUT (profiling only)
+        if os.environ.get("RIPS_COLUMN_TRACE") == "1":
+            extra.append("-DRIPS_COLUMN_TRACE=1")
         cmd = [HIPCC, *FLAGS, *extra, "-I", os.path.join(ROOT, "include"), "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         out = "\n".join(ln for ln in (r.stdout + r.stderr).splitlines()

@@ -839,6 +839,9 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             HIP_TRY(C.ensure(B_CBAR_DS, (size_t)S * 8, &q));
             cbars.ds = as<int64_t>(q);
         }
+#if RIPS_COLUMN_TRACE
+        unsigned long long *trace_buf = nullptr;
+#endif
         for (int attempt = 0;; ++attempt) {
             if (attempt > 12) return fail(RIPS_E_CAPACITY, "reduction scratch kept overflowing");
             HIP_TRY(C.ensure(B_V_IDX, (size_t)vcap * 8, &q));
@@ -901,6 +904,14 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             J.app = app;
             J.par = par;
             J.shortcuts = C.shortcuts;
+#if RIPS_COLUMN_TRACE
+            // profiling builds only: per-column clocks of the spread-out reduction
+            if (trace_buf) (void)hipFree(trace_buf);
+            trace_buf = nullptr;
+            if (getenv("RIPS_COLUMN_TRACE_OUT") && hipMalloc(&trace_buf, (size_t)S * 32 + 32) == hipSuccess)
+                (void)hipMemset(trace_buf, 0, (size_t)S * 32 + 32);
+            J.trace = trace_buf;
+#endif
             J.keep_essential_v = k == C.cocycle_dim ? 1 : 0;
             J.rstore = C.rstore;
             J.prev_bits = W.bits;
@@ -967,6 +978,19 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
                     (long long)groups);
         }
         o.count[k] = C.host_scal->nbars;
+#if RIPS_COLUMN_TRACE
+        if (trace_buf) {
+            std::vector<unsigned long long> tb((size_t)S * 4);
+            if (hipMemcpy(tb.data(), trace_buf, (size_t)S * 32, hipMemcpyDeviceToHost) == hipSuccess) {
+                const std::string path = std::string(getenv("RIPS_COLUMN_TRACE_OUT")) + "_d" + std::to_string(k) + ".bin";
+                if (FILE *fp = fopen(path.c_str(), "wb")) {
+                    fwrite(tb.data(), 8, tb.size(), fp);
+                    fclose(fp);
+                }
+            }
+            (void)hipFree(trace_buf);
+        }
+#endif
         o.stats[k].emergent = (int64_t)C.host_scal->stat[kStatEmergent];
         o.stats[k].reduced = (int64_t)C.host_scal->stat[kStatReduced];
         o.stats[k].additions = (int64_t)C.host_scal->stat[kStatAdditions];

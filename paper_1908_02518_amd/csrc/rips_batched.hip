@@ -489,6 +489,9 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         J.shortcuts = kShortApparent | kShortEmergent | kShortClearing;
         J.keep_essential_v = 0;
         J.rstore = kRStoreAuto;
+#if RIPS_COLUMN_TRACE
+        J.trace = nullptr;
+#endif
         J.prev_bits = nullptr;
         J.prev = PivotHash{nullptr, nullptr, 0};
         gsync();

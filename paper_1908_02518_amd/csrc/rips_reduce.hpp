@@ -315,6 +315,9 @@ struct ReduceJob {
     int shortcuts;              // kShortApparent | kShortEmergent | kShortClearing: those in use
     int keep_essential_v;       // also store V_j of zero columns (their cocycles)
     int rstore;                 // kRStoreAuto, kRStoreNever or kRStoreAlways: when R_j is kept
+#if RIPS_COLUMN_TRACE
+    unsigned long long *trace;  // per column: pick and commit clock, additions, clock spent waiting
+#endif
     // the pivots of the dimension below (read only without clearing): forest
     // edges of H0 as bits (k = 1), else that dimension's pivot table
     const u32 *prev_bits;
@@ -343,6 +346,9 @@ struct RedShared {
     int64_t tau;    // spread-out reduction: emergent candidate
     u32 tcoef, pub; // its coefficient; diameter bits published for this column
     int wbad, wopen, wstop;
+#if RIPS_COLUMN_TRACE
+    unsigned long long wacc;
+#endif
     int fa_n, fa_r; // apparent steps of wave 0: additions made, result
     u32 lo, bound;
     int shift;
@@ -1622,6 +1628,16 @@ __device__ int par_wait(const ReduceJob<Dist> &J, RedShared<BT> &S, int j, u32 d
     __syncthreads();
     int from = min(S.wbad, j);
     const unsigned long long t0 = tid == 0 ? wall_clock64() : 0ull;
+#if RIPS_COLUMN_TRACE
+    struct WaitClock {
+        RedShared<BT> &S;
+        unsigned long long t0;
+        int tid;
+        __device__ ~WaitClock() {
+            if (tid == 0) S.wacc += wall_clock64() - t0;
+        }
+    } wclock{S, t0, tid};
+#endif
     for (bool first = true;; first = false) {
         int bad = j, open = j;
         for (int o = from + tid; o < j; o += BT) {
@@ -2138,6 +2154,9 @@ __device__ __forceinline__ int reduce_columns_par(const ReduceJob<Dist> &J, cons
     }
     if (tid < 13) S.stat[tid] = 0;
     if (tid < kRedTimers) S.tm[tid] = 0;
+#if RIPS_COLUMN_TRACE
+    if (tid == 0) S.wacc = 0;
+#endif
     int status = 0;
     gsync();
     RED_T0(t_total);
@@ -2164,6 +2183,28 @@ __device__ __forceinline__ int reduce_columns_par(const ReduceJob<Dist> &J, cons
         const int emerg = S.m;
         __syncthreads();
         if (col >= J.ncols) break;
+#if RIPS_COLUMN_TRACE
+        unsigned long long tr0 = 0, tra = 0, trw = 0;
+        if (tid == 0) {
+            tr0 = wall_clock64();
+            tra = S.stat[2];
+            trw = S.wacc;
+        }
+        struct ColClock {
+            const ReduceJob<Dist> &J;
+            RedShared<BT> &S;
+            int col, tid;
+            unsigned long long t0, a0, w0;
+            __device__ ~ColClock() {
+                if (tid == 0 && J.trace) {
+                    J.trace[4 * col + 0] = t0;
+                    J.trace[4 * col + 1] = wall_clock64();
+                    J.trace[4 * col + 2] = S.stat[2] - a0;
+                    J.trace[4 * col + 3] = S.wacc - w0;
+                }
+            }
+        } cclock{J, S, col, tid, tr0, tra, trw};
+#endif
         if (emerg) {
             RED_T0(t_em);
             RED_T0(t_w);
