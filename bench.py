@@ -27,6 +27,8 @@ per step. Also reported:
                     cloud: ms per barcode with clearing and no other
                     shortcut, clearing + emergent, all three (the default),
                     clearing + apparent; and cohomology without clearing
+  cocycles          representative cocycles of dimension 1 on the bench
+                    cloud: ms per call against the plain barcode, entries
   homology          the homology variant (boundary matrices with clearing,
                     top dimension first) on the bench cloud in dims 0-1,
                     against cohomology: seconds, columns and additions
@@ -265,6 +267,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-shortcuts", action="store_true",
                     help="skip the shortcut ablation leg (Table 3 of the paper, on so3-1000)")
+    ap.add_argument("--no-cocycles", action="store_true",
+                    help="skip the representative-cocycle leg (so3-1000, dimension 1)")
     ap.add_argument("--no-homology", action="store_true",
                     help="skip the homology-variant leg (so3-1000, dims 0-1, about 15 s)")
     ap.add_argument("--no-paper-scale", action="store_true",
@@ -480,6 +484,31 @@ def main() -> int:
         finally:
             rips.set_shortcuts()
 
+    cocycles = None
+    if not args.no_cocycles:
+        # representative cocycles of dimension 1 on the bench cloud (V_j of
+        # every bar, essential columns included), against the plain barcode
+        # of the same dimensions; host input, median of three after a warm-up
+        rips.cocycles(x, dim=1, threshold=t, p=p)
+        tc, tb = [], []
+        for _ in range(3):
+            c0 = time.perf_counter()
+            cc = rips.cocycles(x, dim=1, threshold=t, p=p)
+            tc.append(time.perf_counter() - c0)
+            c0 = time.perf_counter()
+            rips.barcode(x, max_dim=1, threshold=t, p=p)
+            tb.append(time.perf_counter() - c0)
+        sizes = [len(sc) for sc, _ in cc.cocycles]
+        cocycles = {
+            "workload": "so3-1000, t = 1.4, cocycles of dimension 1, Z/2 (host input)",
+            "ms_cocycles": round(1e3 * sorted(tc)[1], 2),
+            "ms_barcode_dims_0_1": round(1e3 * sorted(tb)[1], 2),
+            "bars": len(sizes),
+            "entries": int(sum(sizes)),
+            "max_entries": int(max(sizes)) if sizes else 0,
+        }
+        log(f"cocycles: {cocycles['ms_cocycles']} ms for {len(sizes)} bars")
+
     homology = None
     if not args.no_homology:
         # the homology variant on the bench cloud, dims 0-1: boundary matrices
@@ -610,6 +639,7 @@ def main() -> int:
         "batched": batched,
         "shortcuts": shortcuts,
         "homology": homology,
+        "cocycles": cocycles,
         "paper_scale": paper_scale,
         "cpu_baseline": cpu,
         "cpu_paper_algorithm": cpu_paper,
