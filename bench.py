@@ -287,8 +287,8 @@ def main() -> int:
         return summarize_trace(args.summarize_trace)
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(batched clouds would shard by clouds across GPUs; see DESIGN.md).",
+        print("bench.py measures one GPU only: there is no multi-GPU path "
+              "(a batch of clouds would shard by clouds across GPUs).",
               file=sys.stderr)
         return 2
 
