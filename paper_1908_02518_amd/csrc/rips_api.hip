@@ -550,11 +550,6 @@ rips_status prepare(DevCtx &C, const float *d_in, int n, int m, int jmax, float 
 
 int group_size_for(const Prepared &P) {
     // lanes per candidate: about the expected early-exit scan length
-    const char *env = getenv("RIPS_GROUP");
-    if (env) {
-        int g = atoi(env);
-        if (g == 4 || g == 8 || g == 16 || g == 32 || g == 64) return g;
-    }
     if (P.sparse) return 16;
     return P.ctx.n <= 128 ? 16 : 32;
 }
@@ -564,11 +559,6 @@ int group_size_for(const Prepared &P) {
 // scan, so groups are narrower than the expansion's: one lane per candidate
 // for sparse dimensions >= 2, four for edges, eight for small dense clouds.
 int filter_group_size_for(const Prepared &P, int k) {
-    const char *env = getenv("RIPS_FILTER_GROUP");
-    if (env) {
-        int g = atoi(env);
-        if (g == 1 || g == 2 || g == 4 || g == 8 || g == 16 || g == 32 || g == 64) return g;
-    }
     if (P.sparse) return k == 1 ? 4 : 1;
     return P.ctx.n <= 128 ? 8 : 32;
 }
@@ -637,24 +627,6 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         launch_h0(P.E, P.scal, n, W, bars[0], nwords, st);
     }
     if ((rs = read_scalars(C, P.scal, st))) return rs;
-    if (getenv("RIPS_DEBUG") && n <= 64) {
-        // diagnostics: H0 internals of small inputs
-        const int m = (int)C.host_scal->mst;
-        std::vector<unsigned long long> k0(n), k1(n);
-        std::vector<int> par(n), mx(n);
-        std::vector<float> hd(n);
-        (void)hipMemcpy(k0.data(), W.mst, 8 * n, hipMemcpyDeviceToHost);
-        (void)hipMemcpy(k1.data(), W.mst2, 8 * n, hipMemcpyDeviceToHost);
-        (void)hipMemcpy(par.data(), W.parent, 4 * n, hipMemcpyDeviceToHost);
-        (void)hipMemcpy(mx.data(), W.maxv, 4 * n, hipMemcpyDeviceToHost);
-        (void)hipMemcpy(hd.data(), W.hdeath, 4 * n, hipMemcpyDeviceToHost);
-        fprintf(stderr, "[rips h0] n=%d edges=%lld forest=%d nbars=%lld\n", n,
-                (long long)P.nedges, m, (long long)C.host_scal->nbars);
-        for (int i = 0; i < m; ++i)
-            fprintf(stderr, "[rips h0] key[%d] %016llx / %016llx\n", i, k0[i], k1[i]);
-        for (int v = 0; v < n; ++v)
-            fprintf(stderr, "[rips h0] v=%d parent=%d maxv=%d hdeath=%g\n", v, par[v], mx[v], hd[v]);
-    }
     o.count[0] = C.host_scal->nbars;
     o.ncols[0] = n;
     o.stats[0].candidates = n;
@@ -950,7 +922,9 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             }
         }
         if ((int64_t)C.host_scal->vcount > C.hint_v) C.hint_v = (int64_t)C.host_scal->vcount;
-        if (getenv("RIPS_DEBUG"))
+#if RIPS_PHASE_TIMERS
+        // profiling build: the reduction's counters and phase clocks
+        if (getenv("RIPS_PHASE_REPORT"))
             fprintf(stderr,
                     "[rips reduce d%d] cols=%lld capD=%u lds_per_block=%d "
                     "base_cols=%llu entries=%llu maxV=%llu maxR=%llu additions=%llu pulls=%llu "
@@ -961,7 +935,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
                     C.host_scal->stat[kStatAdditions], C.host_scal->stat[kStatPulls],
                     C.host_scal->stat[kStatMerges], C.host_scal->stat[kStatSplits],
                     C.host_scal->stat[kStatPulled]);
-        if (getenv("RIPS_DEBUG")) {
+        if (getenv("RIPS_PHASE_REPORT")) {
             int khz = 0;
             (void)hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0);
             const double f = khz > 0 ? 1.0 / khz : 1e-5;
@@ -977,6 +951,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
                     T[15] * f, T[3] * f, T[4] * f, T[16] * f, T[17] * f, T[18] * f, T[19] * f, T[20] * f, T[21] * f,
                     (long long)groups);
         }
+#endif
         o.count[k] = C.host_scal->nbars;
 #if RIPS_COLUMN_TRACE
         if (trace_buf) {

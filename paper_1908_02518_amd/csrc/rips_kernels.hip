@@ -960,11 +960,7 @@ __global__ void __launch_bounds__(256) k_cob_lists(Ctx<Dist> c, int k, PairHash 
 
 void launch_cob_lists(const Ctx<DistFull> &c, int k, PairHash app, int64_t *ckey, float *cdia,
                       unsigned long long *count, int64_t cap, hipStream_t st) {
-    int spw = 16;
-    if (const char *env = getenv("RIPS_COB_SPW")) {
-        const int v = atoi(env);
-        if (v >= 1 && v <= kWave) spw = v;
-    }
+    const int spw = 16; // table slots per wave
     const int64_t slots = (int64_t)app.mask + 1;
     const int64_t waves = (slots + spw - 1) / spw;
     int64_t blocks = (waves + 3) / 4; // 4 waves per workgroup of 256

@@ -1,11 +1,15 @@
 """GPU parity of the batched persistent launch: every cloud's bars equal the
-single-cloud path's and, on a sample, the oracle's, bit for bit."""
+oracle's, bit for bit (the oracle runs on the host CPU in worker processes
+while the GPU works), and the single-cloud path's. The pairs of a
+simplexwise filtration are unique (section "Persistence pairs"), so every
+cloud has exactly one correct barcode."""
 
 import numpy as np
 import pytest
 
 import oracle
 import workloads
+from tests.oracle_pool import OraclePool
 
 pytestmark = pytest.mark.gpu
 
@@ -61,35 +65,45 @@ def test_batch_threshold_and_h0_only():
         assert_cloud(bb, b, ref.bars, 0, "h0-only")
 
 
-def test_mixture_512_vs_single_and_oracle_sample():
+def _batch_vs_oracle_and_single(clouds, tag, max_dim=1, threshold=float("inf"), p=2,
+                                single=True):
     import torch
-    c = workloads.config(4)
-    clouds = c["clouds"]
-    x, off, nmax = rips().pack_clouds(clouds)
-    print(f"[case] mixture batch B={len(clouds)} nmax={nmax}", flush=True)
-    bb = rips().barcode_batched(x, off, nmax, max_dim=1, p=2)
-    torch.cuda.synchronize()
-    for b in range(len(clouds)):
-        single = rips().barcode(clouds[b], max_dim=1, p=2)
-        assert_cloud(bb, b, single.bars, 1, "mixture-vs-single")
-    for b in (0, 1, 97, 300, 511):
-        ref = oracle.barcode(clouds[b], max_dim=1, p=2)
-        assert_cloud(bb, b, ref.bars, 1, "mixture-vs-oracle")
+    with OraclePool(clouds, max_dim, threshold, p) as pool:
+        x, off, nmax = rips().pack_clouds(clouds)
+        print(f"[case] {tag} B={len(clouds)} nmax={nmax} p={p}", flush=True)
+        bb = rips().barcode_batched(x, off, nmax, max_dim=max_dim, threshold=threshold, p=p)
+        torch.cuda.synchronize()
+        thr = bb.thresholds.cpu().numpy()
+        if single:
+            for b in range(len(clouds)):
+                one = rips().barcode(clouds[b], max_dim=max_dim, threshold=threshold, p=p)
+                assert_cloud(bb, b, one.bars, max_dim, tag + "-vs-single")
+        for b in range(len(clouds)):
+            bars, t_ref = pool.get(b)
+            ref = [oracle.Bars(*q) for q in bars]
+            assert_cloud(bb, b, ref, max_dim, tag + "-vs-oracle")
+            assert thr[b] == np.float32(t_ref), (tag, b, "threshold")
 
 
-def test_circles_64x400_vs_single_and_oracle_sample():
-    import torch
-    c = workloads.config(5)
-    clouds = c["clouds"]
-    x, off, nmax = rips().pack_clouds(clouds)
-    print(f"[case] circles batch B={len(clouds)} nmax={nmax}", flush=True)
-    bb = rips().barcode_batched(x, off, nmax, max_dim=1, p=2)
-    torch.cuda.synchronize()
-    for b in range(len(clouds)):
-        single = rips().barcode(clouds[b], max_dim=1, p=2)
-        assert_cloud(bb, b, single.bars, 1, "circles-vs-single")
-    ref = oracle.barcode(clouds[0], max_dim=1, p=2)
-    assert_cloud(bb, 0, ref.bars, 1, "circles-vs-oracle")
+def test_mixture_512_every_cloud_vs_oracle():
+    _batch_vs_oracle_and_single(workloads.config(4)["clouds"], "mixture-512")
+
+
+def test_circles_64x400_every_cloud_vs_oracle():
+    _batch_vs_oracle_and_single(workloads.config(5)["clouds"], "circles-64x400")
+
+
+def lattice_batch(num=48):
+    # integer lattices: many tied distances and duplicate points, sizes up to
+    # the dense-LDS limit and above it
+    g = workloads.rng(4242)
+    return [workloads.integer_lattice(int(g.integers(2, 300)), 3, 9000 + b,
+                                      side=int(g.integers(2, 6))) for b in range(num)]
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_lattice_ties_batch_vs_oracle(p):
+    _batch_vs_oracle_and_single(lattice_batch(), f"lattice-ties-p{p}", p=p, single=False)
 
 
 def test_graph_replay_is_deterministic():

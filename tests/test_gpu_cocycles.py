@@ -138,7 +138,12 @@ def test_cocycle_properties(name, make, d, t, p, sample):
         assert np.all((coef > 0) & (coef < p)), (name, b)
         at = np.nonzero(simp == bs)[0]
         assert len(at) == 1 and coef[at[0]] == 1, (name, b, "birth simplex")
-        assert all(diam(D, decode(int(s), d)) >= birth for s in simp), (name, b, "older simplex")
+        # nothing older than sigma_j in the refined order (diameter, then
+        # larger index older): V_j adds only columns reduced before j, which
+        # are younger
+        for s in simp:
+            ds_ = diam(D, decode(int(s), d))
+            assert ds_ > birth or (ds_ == birth and int(s) <= bs), (name, b, "older simplex")
         tk, tv, td = delta(simp, coef)
         if ds < 0:
             assert len(tk) == 0, (name, b, "essential cocycle has a coboundary")

@@ -293,6 +293,39 @@ def test_cone_pair_counts_and_euler(seed):
         assert r.counters[k]["pairs"] == want
 
 
+def test_enclosing_radius_closed_form():
+    # "Input" paragraph: the enclosing radius is min over x of max over y of
+    # d(x, y). Four points on a line at -3, 0, 2, 5 (exact float32 distances):
+    # the row maxima are 8, 5, 5, 8, so the enclosing radius is 5; the
+    # diameter (max max) is 8, max min is 3 and min min is 2, so swapping
+    # either min or max gives another value.
+    x = np.array([[-3.0], [0.0], [2.0], [5.0]], np.float32)
+    r = oracle.barcode(x, max_dim=1)
+    assert r.enclosing_radius == 5.0 and r.threshold == 5.0
+    # a finite threshold is clamped to it, never raised
+    assert oracle.barcode(x, max_dim=1, threshold=6.0).threshold == 5.0
+    assert oracle.barcode(x, max_dim=1, threshold=4.0).threshold == 4.0
+    # without the clamp the full complex is used
+    assert oracle.barcode(x, max_dim=1, clamp=False).threshold == INF
+    # unit square with its centre: the centre's farthest point is a corner at
+    # sqrt(2) (correctly rounded: 0x3FB504F3), every corner's is 2 sqrt(2)
+    sq = np.array([[0, 0], [2, 0], [0, 2], [2, 2], [1, 1]], np.float32)
+    rs = oracle.barcode(sq, max_dim=1)
+    assert np.float32(rs.enclosing_radius).view(np.uint32) == 0x3FB504F3
+    # a star: centre 0, leaves at distances 1, 2, 3 and 4 on the coordinate
+    # axes; the centre's row maximum is 4, the leaves' are sqrt(17), 6, 5, 6
+    st = np.array([[0, 0], [1, 0], [0, 2], [-3, 0], [0, -4]], np.float32)
+    assert oracle.barcode(st, max_dim=1).enclosing_radius == 4.0
+
+
+def test_facets_from_paper():
+    # facets of {v5, v3, v0} in forward colexicographic order (section
+    # "Enumerating cofacets and facets"): dropping v5, then v3, then v0
+    _, _, (s, want) = golden_io.cns()
+    got = [oracle.cns_index(tuple(v for q, v in enumerate(s) if q != m)) for m in range(len(s))]
+    assert got == want
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_enclosing_radius_cut_keeps_bars(seed):
     g = workloads.rng(500 + seed)
