@@ -184,6 +184,31 @@ rips_status rips_barcode_device(const float *d_data, int64_t n, int32_t dim, int
                                 void *hip_stream);
 
 /*
+ * rips_barcode_device_noalloc -- rips_barcode_device for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc). Same computation, arguments, outputs and
+ * error behaviour as rips_barcode_device; the call itself allocates nothing:
+ * no hipMalloc, hipFree, pinned host memory or library allocation. All its
+ * scratch memory is carved from one fixed device array of
+ * RIPS_NOALLOC_SCRATCH_MIB MiB that the library holds on every GPU it runs on
+ * until the process ends (its device address is taken at the first call on
+ * each device). Limits: n <= RIPS_NOALLOC_MAX_POINTS and
+ * max_dim <= RIPS_NOALLOC_MAX_DIM (else RIPS_E_INVALID_ARG); an input whose
+ * scratch does not fit the array returns RIPS_E_CAPACITY. The reduction runs
+ * in one workgroup. Every call on a GPU reuses that GPU's array, which keeps
+ * the last call's contents (everything that must start at zero is cleared by
+ * the call); calls are serialized per device by the library, and concurrent
+ * use of the array by other means would race. Kernel profiling
+ * (rips_profile_enable) does not time this entry point.
+ */
+#define RIPS_NOALLOC_SCRATCH_MIB 64
+#define RIPS_NOALLOC_MAX_POINTS 256
+#define RIPS_NOALLOC_MAX_DIM 1
+rips_status rips_barcode_device_noalloc(const float *d_data, int64_t n, int32_t dim, int32_t max_dim,
+                                        float threshold, uint32_t p, rips_device_out *out,
+                                        void *hip_stream);
+
+/*
  * rips_simplex_counts_device -- |K_d| for d = 0 .. top (top <= RIPS_MAX_DIM + 1)
  * at threshold min(threshold, enclosing radius), counted on the GPU without
  * storing the top dimension. Used for throughput accounting

@@ -51,6 +51,7 @@ EXPORTS = (
     "rips_status_string",
     "rips_last_error",
     "rips_barcode_device",
+    "rips_barcode_device_noalloc",
     "rips_simplex_counts_device",
     "rips_barcode_batched_device",
     "rips_backward_device",
@@ -185,6 +186,8 @@ def _load():
                                         ctypes.c_int32, ctypes.c_float, ctypes.c_uint32,
                                         ctypes.POINTER(rips_device_out), ctypes.c_void_p]
     lib.rips_barcode_device.restype = ctypes.c_int
+    lib.rips_barcode_device_noalloc.argtypes = lib.rips_barcode_device.argtypes
+    lib.rips_barcode_device_noalloc.restype = ctypes.c_int
     lib.rips_simplex_counts_device.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                                ctypes.c_int32, ctypes.c_float,
                                                ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]
@@ -387,12 +390,15 @@ def _stream_ptr(torch, device):
 
 
 def barcode_device(x, *, max_dim: int = 1, threshold: float = float("inf"), p: int = 2,
-                   is_distance: bool = False, cap: int | None = None):
+                   is_distance: bool = False, cap: int | None = None, noalloc: bool = False):
     """Barcode of a device-resident float32 tensor (points (n, m), or a full
     (n, n) distance matrix with is_distance=True). Returns (bars, info):
     bars[d] = (birth, death, birth_simplex, death_simplex) torch.cuda tensors;
-    info holds stats, simplex counts and the threshold used."""
+    info holds stats, simplex counts and the threshold used. noalloc=True
+    calls rips_barcode_device_noalloc (the library allocates nothing; the
+    output tensors are still allocated here, by the caller)."""
     import torch
+    entry = _lib.rips_barcode_device_noalloc if noalloc else _lib.rips_barcode_device
     if not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 2:
         raise ValueError("x must be a contiguous float32 CUDA tensor of rank 2")
     n = x.shape[0]
@@ -408,9 +414,8 @@ def barcode_device(x, *, max_dim: int = 1, threshold: float = float("inf"), p: i
         o.cap = cap
         o.birth, o.death = birth.data_ptr(), death.data_ptr()
         o.birth_simplex, o.death_simplex = bs.data_ptr(), ds.data_ptr()
-        st = _lib.rips_barcode_device(ctypes.c_void_p(x.data_ptr()), n, m, max_dim,
-                                      ctypes.c_float(threshold), p, ctypes.byref(o),
-                                      _stream_ptr(torch, dev))
+        st = entry(ctypes.c_void_p(x.data_ptr()), n, m, max_dim, ctypes.c_float(threshold), p,
+                   ctypes.byref(o), _stream_ptr(torch, dev))
         if st == -6 and o.needed_cap > cap:
             cap = int(o.needed_cap)
             continue

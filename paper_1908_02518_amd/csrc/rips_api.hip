@@ -227,8 +227,59 @@ struct DevCtx {
     u32 batch_capD = 0; // 0 = default delta size of the batched reduction
     int batch_wgpcu = 0; // 0 = default (1 persistent workgroup per CU)
 
+    // No-allocation mode (the context of rips_barcode_device_noalloc): every
+    // buffer is carved from one fixed device region instead of hipMalloc;
+    // reset_arena() at the start of each call forgets the carving.
+    unsigned char *arena = nullptr;
+    size_t arena_cap = 0, arena_used = 0;
+    int arena_last = -1;  // buffer carved last (it can grow in place)
+    bool arena_full = false;
+
+    void reset_arena() {
+        for (int i = 0; i < B_NUM; ++i) {
+            buf[i] = nullptr;
+            cap[i] = 0;
+        }
+        arena_used = 0;
+        arena_last = -1;
+        arena_full = false;
+    }
+
+    hipError_t carve(int id, size_t bytes, void **out) {
+        const size_t al = 256;
+        if (id == arena_last && buf[id]) {
+            // the last region grows in place
+            const size_t at = (size_t)((unsigned char *)buf[id] - arena);
+            if (at + bytes <= arena_cap) {
+                arena_used = (at + bytes + al - 1) / al * al;
+                cap[id] = bytes;
+                *out = buf[id];
+                return hipSuccess;
+            }
+        } else {
+            const size_t at = (arena_used + al - 1) / al * al;
+            if (at + bytes <= arena_cap) {
+                buf[id] = arena + at;
+                cap[id] = bytes;
+                arena_used = (at + bytes + al - 1) / al * al;
+                arena_last = id;
+                *out = buf[id];
+                return hipSuccess;
+            }
+        }
+        arena_full = true;
+        return hipErrorOutOfMemory;
+    }
+
     hipError_t ensure(int id, size_t bytes, void **out) {
         if (bytes == 0) bytes = 16;
+        if (arena) {
+            if (cap[id] >= bytes) {
+                *out = buf[id];
+                return hipSuccess;
+            }
+            return carve(id, bytes, out);
+        }
         if (cap[id] < bytes) {
             if (buf[id]) {
                 hipError_t e = hipFree(buf[id]);
@@ -267,6 +318,42 @@ rips_status get_ctx(DevCtx **out) {
         g_ctx[dev] = c;
     }
     *out = g_ctx[dev];
+    return RIPS_OK;
+}
+
+// Device memory of the no-allocation entry point (rips_barcode_device_noalloc):
+// one fixed region per GPU, held until the process ends. In host code the
+// symbol is only a stand-in; its device address comes from
+// hipGetSymbolAddress, once per device, and only that address is used.
+constexpr size_t kNoAllocBytes = (size_t)RIPS_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+DevCtx *g_ctx_na[64];
+Scalars g_na_scal[64]; // host copies of the scalars (pageable: nothing is allocated)
+
+// The context of the no-allocation entry point on the current device: set up
+// at its first call there (the device address of `scratch`, the device
+// attributes), with no allocation of device or pinned memory.
+rips_status get_ctx_noalloc(DevCtx **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(RIPS_E_HIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    if (!g_ctx_na[dev]) {
+        void *ptr = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) return fail(RIPS_E_HIP, "no device address for the no-allocation scratch");
+        static DevCtx ctx_store[64];
+        DevCtx *c = &ctx_store[dev];
+        c->arena = (unsigned char *)ptr;
+        c->arena_cap = kNoAllocBytes;
+        c->host_scal = &g_na_scal[dev];
+        HIP_TRY(hipDeviceGetAttribute(&c->lds_per_block, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                      dev));
+        HIP_TRY(hipDeviceGetAttribute(&c->num_cus, hipDeviceAttributeMultiprocessorCount, dev));
+        g_ctx_na[dev] = c;
+    }
+    *out = g_ctx_na[dev];
     return RIPS_OK;
 }
 
@@ -392,13 +479,16 @@ struct Profiler {
     }
 };
 Profiler g_prof;
+// set while the no-allocation entry point runs: its launches are not timed
+// (timing would create events and grow the profiler's lists)
+thread_local bool g_prof_quiet = false;
 
 struct ProfScope {
     hipStream_t st;
     int id;
     hipEvent_t a = nullptr, b = nullptr;
     ProfScope(int id_, hipStream_t st_) : st(st_), id(id_) {
-        if (!g_prof.on) return;
+        if (!g_prof.on || g_prof_quiet) return;
         a = g_prof.get();
         b = g_prof.get();
         if (a && b) (void)hipEventRecord(a, st);
@@ -412,7 +502,7 @@ struct ProfScope {
 
 // after a stream synchronize: fold the finished intervals into the totals
 void prof_resolve() {
-    if (!g_prof.on) return;
+    if (!g_prof.on || g_prof_quiet) return;
     for (auto &r : g_prof.pending) {
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
@@ -703,6 +793,9 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             // as many entries as rho has candidates (grown from the last call's need)
             const int64_t per = P.sparse ? std::min<int64_t>(std::max(P.maxdeg, 1), 64) : n;
             cobcap = std::max<int64_t>(C.hint_cob, std::min<int64_t>(ncand * per, 1ll << 25));
+            // no-allocation mode: a small list buffer (a slot whose list does
+            // not fit gets none; the reduction then enumerates it)
+            if (C.arena) cobcap = std::min<int64_t>(cobcap, 1ll << 18);
             HIP_TRY(C.ensure(B_COB_KEY, (size_t)cobcap * 8, &q));
             app.ckey = as<int64_t>(q);
             ckey_w = as<int64_t>(q);
@@ -781,7 +874,7 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         V.roff = as<int64_t>(q);
         HIP_TRY(C.ensure(B_V_RLEN, (size_t)S * 4, &q));
         V.rlen = as<int>(q);
-        int64_t vcap = std::max<int64_t>(C.hint_v, 64 * S + 65536);
+        int64_t vcap = std::max<int64_t>(C.hint_v, C.arena ? 16 * S + 16384 : 64 * S + 65536);
         if ((rs = ensure_bars(k, S))) return rs;
         const int bound = P.sparse ? P.maxdeg : n;
         // working column: the delta in LDS (as large as a workgroup's share
@@ -791,7 +884,8 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         while (capD > 256 && reduce_lds_bytes(capD) > lds_budget) capD >>= 1;
         // the columns spread over one workgroup per CU, each with its own
         // scratch (smaller first sizes, grown on overflow), or one workgroup
-        const int64_t want = C.reduce_groups > 0 ? C.reduce_groups : std::max(1, C.num_cus);
+        // (no-allocation mode: one workgroup, whose scratch is small)
+        const int64_t want = C.arena ? 1 : C.reduce_groups > 0 ? C.reduce_groups : std::max(1, C.num_cus);
         const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(want, S));
         const bool spread = groups > 1;
         int64_t fcap = spread ? std::max<int64_t>(C.hint_far, 1 << 16)
@@ -1424,19 +1518,12 @@ const char *rips_status_string(rips_status s) {
 
 const char *rips_last_error(void) { return g_err.c_str(); }
 
-rips_status rips_barcode_device(const float *d_data, int64_t n, int32_t dim, int32_t max_dim,
-                                float threshold, uint32_t p, rips_device_out *out,
-                                void *hip_stream) {
-    g_err.clear();
-    if (!d_data || !out) return fail(RIPS_E_INVALID_ARG, "null pointer");
-    rips_status rs = validate(n, dim, max_dim, threshold, p, 0);
-    if (rs) return rs;
-    DevCtx *C;
-    if ((rs = get_ctx(&C))) return rs;
-    std::lock_guard<std::mutex> lk(C->mu);
-    hipStream_t st = (hipStream_t)hip_stream;
+// One cloud from device memory into the caller's device buffers, with the
+// scratch of context C (the caller holds C's lock).
+rips_status device_barcode(DevCtx *C, const float *d_data, int64_t n, int32_t dim, int32_t max_dim,
+                           float threshold, uint32_t p, rips_device_out *out, hipStream_t st) {
     RunOut o;
-    rs = run_single(*C, d_data, (int)n, dim, max_dim, threshold, p, st, o);
+    rips_status rs = run_single(*C, d_data, (int)n, dim, max_dim, threshold, p, st, o);
     if (rs) return rs;
     int64_t need = 0;
     for (int d = 0; d <= max_dim; ++d) need = std::max(need, o.count[d]);
@@ -1463,6 +1550,45 @@ rips_status rips_barcode_device(const float *d_data, int64_t n, int32_t dim, int
     HIP_TRY(hipStreamSynchronize(st));
     prof_resolve();
     return RIPS_OK;
+}
+
+rips_status rips_barcode_device(const float *d_data, int64_t n, int32_t dim, int32_t max_dim,
+                                float threshold, uint32_t p, rips_device_out *out,
+                                void *hip_stream) {
+    g_err.clear();
+    if (!d_data || !out) return fail(RIPS_E_INVALID_ARG, "null pointer");
+    rips_status rs = validate(n, dim, max_dim, threshold, p, 0);
+    if (rs) return rs;
+    DevCtx *C;
+    if ((rs = get_ctx(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    return device_barcode(C, d_data, n, dim, max_dim, threshold, p, out, (hipStream_t)hip_stream);
+}
+
+rips_status rips_barcode_device_noalloc(const float *d_data, int64_t n, int32_t dim, int32_t max_dim,
+                                        float threshold, uint32_t p, rips_device_out *out,
+                                        void *hip_stream) {
+    g_err.clear();
+    if (!d_data || !out) return fail(RIPS_E_INVALID_ARG, "null pointer");
+    rips_status rs = validate(n, dim, max_dim, threshold, p, 0);
+    if (rs) return rs;
+    if (n > RIPS_NOALLOC_MAX_POINTS)
+        return fail(RIPS_E_INVALID_ARG, "no-allocation entry point: n must be <= " +
+                                            std::to_string(RIPS_NOALLOC_MAX_POINTS));
+    if (max_dim > RIPS_NOALLOC_MAX_DIM)
+        return fail(RIPS_E_INVALID_ARG, "no-allocation entry point: max_dim must be <= " +
+                                            std::to_string(RIPS_NOALLOC_MAX_DIM));
+    DevCtx *C;
+    if ((rs = get_ctx_noalloc(&C))) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    C->reset_arena();
+    g_prof_quiet = true;
+    rs = device_barcode(C, d_data, n, dim, max_dim, threshold, p, out, (hipStream_t)hip_stream);
+    g_prof_quiet = false;
+    if (rs != RIPS_OK && C->arena_full)
+        return fail(RIPS_E_CAPACITY, "no-allocation entry point: the input needs more than the " +
+                                         std::to_string(kNoAllocBytes >> 20) + " MiB of its scratch");
+    return rs;
 }
 
 rips_status rips_barcode(const float *data, int64_t n, int32_t dim, int32_t max_dim,
