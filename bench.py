@@ -1,45 +1,46 @@
 #!/usr/bin/env python3
 """Throughput of the Vietoris-Rips persistence hot path on one MI355X.
 
-One step = one full barcode (distances, threshold, H0, enumeration /
-apparent-pair filter, column sort and Z/p reduction in every dimension) of
-the so3-1000 workload: 1000 Haar-random rotations of R^3 flattened to R^9,
-float32, threshold 1.4, dimensions 0-2, Z/2 (the shape of the paper's o3
-data set). The input is resident in HBM before the timed region.
+One step = the barcodes of the circles-64x400 batch, the largest of the five
+workloads: 64 clouds of 400 points in R^2 (360 on the unit circle with
+Gaussian noise 0.1, 40 uniform outliers in [-2, 2]^2), float32, full Rips (the
+enclosing radius), dimensions 0-1, Z/2, all in one persistent launch replayed
+from a hipGraph (distances, threshold, H0, enumeration / apparent-pair
+filter, column sort and Z/p reduction for every cloud). The input is
+resident in HBM before the timed region.
 
-value = simplices/s = (|K_0| + |K_1| + |K_2| + |K_3|) at the threshold, the size
-of the explicit filtration the method avoids building, divided by the time
-per step. Also reported:
-  roofline          the dominant kernel's algorithmic bytes per launch over
-                    its mean launch time (HIP events on the library's
-                    stream), against the HBM peak; traffic = HBM bytes per
-                    launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters
-                    (committed summary under profiles/, scaled by a plain copy
-                    of known size), null when the kernel sources changed since
-  enumeration_pass  the same for the enumeration / apparent-pair filter
-  valu              (in both) the kernel's vector-ALU issue rate: VALU wave
-                    instructions per dispatch from a committed rocprofv3
-                    counter summary over the live launch time, against
-                    256 CUs x 2.4 GHz x one wave64 instruction per CU-cycle
-  batched           barcodes/s of the 512-cloud mixture batch in one
-                    persistent launch vs one cloud at a time
-  shortcuts         the shortcut ablation of the paper's Table 3 on the same
-                    cloud: ms per barcode with clearing and no other
-                    shortcut, clearing + emergent, all three (the default),
-                    clearing + apparent; and cohomology without clearing
-  cocycles          representative cocycles of dimension 1 on the bench
-                    cloud: ms per call against the plain barcode, entries
-  homology          the homology variant (boundary matrices with clearing,
-                    top dimension first) on the bench cloud in dims 0-1,
-                    against cohomology: seconds, columns and additions
-  paper_scale       one barcode of a paper-scale workload (o3 shape, 1024
-                    points, threshold 1.8, dims 0-3), against the CPU
-                    implementation of the paper's algorithm
-  cpu_baseline      the CPU oracle on this host (a bounded sample)
+value = simplices/s = the sum over the 64 clouds of |K_0| + |K_1| + |K_2| at
+each cloud's threshold (the size of the explicit filtrations the method
+avoids building) divided by the time per step. Also reported:
+  roofline          the dominant kernel (the batched launch): its algorithmic
+                    bytes per launch over its mean launch time (HIP events on
+                    the stream it runs on), against the HBM peak; traffic =
+                    HBM bytes per launch from rocprofv3 FETCH_SIZE /
+                    WRITE_SIZE counters (committed summary under profiles/,
+                    scaled by a plain copy of known size), null when the
+                    kernel sources changed since
+  configs           every workload: sphere-100, so3-1000 and torus4-2000 one
+                    cloud per call (simplices/s), mixture-512 in one launch
+                    (barcodes/s and simplices/s) against one cloud at a time,
+                    and the headline batch
+  enumeration_pass  the enumeration / apparent-pair filter of so3-1000
+                    (dimension 2): candidates, survivors and neighbour lists
+                    in bytes over its launch time, with the vector-ALU issue
+                    rate beside it
+  shortcuts         the shortcut ablation of the paper's Table 3 on so3-1000
+  cocycles          representative cocycles of dimension 1 on so3-1000
+  homology          the homology variant on so3-1000 in dims 0-1
+  paper_scale       one barcode of the o3 shape at 1024 points, t = 1.8,
+                    dims 0-3, against the CPU implementation of the paper's
+                    algorithm
+  cpu_baseline      the CPU oracle on this host (a bounded sample of the
+                    headline batch: its first clouds), single thread
   cpu_paper_algorithm  the single-threaded CPU implementation of the paper's
-                    algorithm (cpu_baseline/) on the same cloud, same host
+                    algorithm (cpu_baseline/) on all 64 clouds, and the same
+                    over one process per core
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --pmc-run            (counter runs under rocprofv3)
        python bench.py --summarize-pmc FETCH_DIR WRITE_DIR   (profiles helpers)
        python bench.py --summarize-trace TRACE_DIR
        python bench.py --summarize-valu PMC_DIR
@@ -53,6 +54,7 @@ import glob
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -62,6 +64,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_so3-1000.txt")
+PMC_SUMMARY_BATCH = os.path.join(ROOT, "profiles", "pmc_traffic_circles-64x400.txt")
 PMC_VALU_SUMMARY = os.path.join(ROOT, "profiles", "pmc_valu_so3-1000.txt")
 COPY_BYTES = 1 << 29   # plain copy used to calibrate the counters (512 MiB read + written)
 
@@ -77,45 +80,13 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def kernel_bytes(name: str, n: int, counts, stats, sparse: bool) -> float | None:
-    """Algorithmic HBM bytes of one launch of a kernel class: what the method
-    must move once. Records: simplex (index 8 B + diameter 4 B), column
-    (+ zero pivot cofacet 4 B + flag 1 B), apparent-pair table record (4 x
-    8 B), reduction entry (index 8 B + diameter 4 B + coefficient 4 B)."""
-    edges = counts[1] if len(counts) > 1 else 0
-    dmat = 4.0 * n * n
-    if name == "distances":
-        return dmat
-    if name == "edges":
-        return dmat + 12.0 * edges
-    if name.startswith("filter_d"):
-        # + one apparent-pair table record per zero apparent pair (tau key,
-        # rho value, rho's vertices, its neighbour-list span: 4 x 8 B)
-        k = int(name[-1])
-        return (12.0 * counts[k] + 17.0 * stats[k]["columns"] + 32.0 * stats[k]["apparent_col"]
-                + (8.0 * edges if sparse else dmat))
-    if name.startswith("expand_d"):
-        k = int(name[-1])
-        return 12.0 * counts[k - 1] + 12.0 * counts[k] + (8.0 * edges if sparse else dmat)
-    if name.startswith("sort_d"):
-        k = int(name[-1])
-        return 2.0 * 17.0 * stats[k]["columns"]
-    if name.startswith("reduce_d"):
-        k = int(name[-1])
-        s = stats[k]
-        return 17.0 * s["columns"] + 16.0 * (s["entries_added"] + s["entries_stored"])
-    if name == "h0":
-        return 12.0 * edges + 16.0 * n
-    return None
-
-
-def read_pmc_summary():
+def read_pmc_summary(path: str):
     """{class: (fetch_bytes, write_bytes) per launch} scaled by the copy
     calibration, or None when absent or stale."""
-    if not os.path.exists(PMC_SUMMARY):
+    if not os.path.exists(path):
         return None
     vals, rows = {}, {}
-    for ln in open(PMC_SUMMARY):
+    for ln in open(path):
         ln = ln.strip()
         if not ln or ln.startswith("#"):
             continue
@@ -160,6 +131,8 @@ def _classify(per):
             out.setdefault(f"filter_d{dim}", []).append(v)
         elif "k_reduce" in name:
             out.setdefault(f"reduce_d{dim}", []).append(v)
+        elif "k_batched" in name:
+            out.setdefault("batched", []).append(v)
         elif "copy" in name.lower() or "elementwise" in name.lower():
             copies.append(v)
     if copies:
@@ -179,7 +152,8 @@ def summarize_valu(d: str) -> int:
     """Print the profiles/ summary of a rocprofv3 --pmc run of
     `bench.py --pmc-run` with VALU_COUNTERS: mean per dispatch per class."""
     per = {c: _classify(_load_counter(d, c)) for c in VALU_COUNTERS}
-    print("# instruction counters per dispatch, rocprofv3 --pmc, so3-1000 barcode")
+    print("# instruction counters per dispatch, rocprofv3 --pmc: bench.py --pmc-run "
+          "(circles-64x400 batch and so3-1000 barcode)")
     print(f"source_sha256 {source_hash()}")
     kinds = sorted({k for v in per.values() for k in v if k != "copy"})
     for k in kinds:
@@ -203,13 +177,31 @@ def read_valu_summary():
     return out if sha == source_hash() else None
 
 
+def alu_rate(prof, name):
+    """Vector-ALU issue rate of a kernel class: VALU wave instructions per
+    dispatch (committed counter summary) over the live launch time, with its
+    LDS and vector-memory instructions; None when the summary is stale."""
+    valu = read_valu_summary()
+    row = valu.get(name) if valu else None
+    if not row or name not in prof:
+        return None
+    ms, calls = prof[name]
+    sec = ms / calls * 1e-3
+    ach = row["SQ_INSTS_VALU"] / sec / 1e9
+    return {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_GIPS,
+            "unit": "G wave64 VALU instructions/s", "frac": round(ach / VALU_PEAK_GIPS, 5),
+            "lds_instructions": row.get("SQ_INSTS_LDS"),
+            "vmem_read_instructions": row.get("SQ_INSTS_VMEM_RD")}
+
+
 def summarize_pmc(fetch_dir: str, write_dir: str) -> int:
     """Print the profiles/ summary from two rocprofv3 --pmc runs of
     `bench.py --pmc-run` (FETCH_SIZE, then WRITE_SIZE): mean KiB per
     dispatch for each kernel class, and the copy kernel's reading."""
     f = _classify(_load_counter(fetch_dir, "FETCH_SIZE"))
     w = _classify(_load_counter(write_dir, "WRITE_SIZE"))
-    print("# HBM traffic per dispatch, rocprofv3 counters (KiB), so3-1000 barcode")
+    print("# HBM traffic per dispatch, rocprofv3 counters (KiB): bench.py --pmc-run "
+          "(circles-64x400 batch and so3-1000 barcode)")
     print(f"source_sha256 {source_hash()}")
     print(f"copy_bytes {COPY_BYTES}")
     print(f"copy_fetch_kib {f.get('copy', 0.0):.1f}")
@@ -255,6 +247,47 @@ def summarize_trace(trace_dir: str) -> int:
     return 0
 
 
+def host_cpu() -> dict:
+    """CPU model and core counts of this host."""
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.startswith("Model name:"):
+                model = ln.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None and os.path.exists("/proc/cpuinfo"):
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cores": usable}
+
+
+def batched_bytes(clouds, counts, stats) -> float:
+    """Algorithmic HBM bytes of one batched launch: per cloud the distances
+    (points read once, 4 B per pair written), one read of them by the
+    threshold / H0 / enumeration passes (4 B per pair), the surviving columns
+    written (12 B each) and sorted (2 x 17 B), the reduction's columns
+    (17 B) and entries added or stored (16 B each), and the bars (24 B)."""
+    total = 0.0
+    for b, x in enumerate(clouds):
+        n, m = x.shape
+        pairs = n * (n - 1) / 2
+        s = stats[b]
+        cols = s[1]["columns"]
+        bars = s[0]["bars_nonzero"] + s[0]["essential"] + s[1]["bars_nonzero"] + s[1]["essential"]
+        total += (4.0 * n * m + 4.0 * pairs + 4.0 * pairs + 12.0 * cols + 34.0 * cols
+                  + 17.0 * cols + 16.0 * (s[1]["entries_added"] + s[1]["entries_stored"])
+                  + 24.0 * bars)
+    return total
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,8 +296,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="bound on the CPU-oracle sample (seconds)")
     ap.add_argument("--no-cpu-baseline", action="store_true",
-                    help="skip both CPU legs (oracle and the paper's algorithm)")
-    ap.add_argument("--no-batched", action="store_true")
+                    help="skip the CPU legs (oracle and the paper's algorithm)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the legs of the other four workloads")
     ap.add_argument("--no-shortcuts", action="store_true",
                     help="skip the shortcut ablation leg (Table 3 of the paper, on so3-1000)")
     ap.add_argument("--no-cocycles", action="store_true",
@@ -274,7 +308,8 @@ def main() -> int:
     ap.add_argument("--no-paper-scale", action="store_true",
                     help="skip the paper-scale o3-1024 (t = 1.8, dims 0-3) leg")
     ap.add_argument("--pmc-run", action="store_true",
-                    help="counter runs: a few steps plus one plain copy of known size")
+                    help="counter runs: a few steps of the headline batch and of so3-1000, "
+                         "plus one plain copy of known size")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     ap.add_argument("--summarize-trace", metavar="TRACE_DIR")
     ap.add_argument("--summarize-valu", metavar="PMC_DIR")
@@ -301,12 +336,15 @@ def main() -> int:
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
-    cfg = workloads.config(2)
-    x = cfg["clouds"][0]
-    n, m = x.shape
-    t, p, max_dim = cfg["threshold"], cfg["p"], cfg["max_dim"]
     dev = torch.device("cuda:0")
-    xt = torch.from_numpy(x).to(dev)
+    c5 = workloads.config(5)
+    clouds5 = c5["clouds"]
+    kw5 = dict(max_dim=c5["max_dim"], threshold=c5["threshold"], p=c5["p"])
+    xb5, off5, nmax5 = rips.pack_clouds(clouds5)
+    c2 = workloads.config(2)
+    x2 = c2["clouds"][0]
+    x2t = torch.from_numpy(x2).to(dev)
+    kw2 = dict(max_dim=c2["max_dim"], threshold=c2["threshold"], p=c2["p"])
     torch.cuda.synchronize()
 
     if args.pmc_run:
@@ -317,145 +355,172 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
         for i in range(args.steps):
-            rips.barcode_device(xt, max_dim=max_dim, threshold=t, p=p)
+            rips.barcode_batched(xb5, off5, nmax5, **kw5)
+            torch.cuda.synchronize()
+            rips.barcode_device(x2t, **kw2)
             torch.cuda.synchronize()
             log(f"pmc step {i + 1}/{args.steps}")
         return 0
 
-    # size of the explicit filtration (numerator), outside the timed region
-    counts = rips.simplex_counts(xt, max_dim + 1, threshold=t)
-    n_simplices = int(sum(counts))
-    log(f"workload {cfg['name']}: n={n}, |K_0..K_{max_dim + 1}| = {counts}")
+    def ev_pair():
+        return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    # ---- headline: the circles-64x400 batch in one launch
+    counts5 = [rips.simplex_counts(torch.from_numpy(x).to(dev), kw5["max_dim"] + 1,
+                                   threshold=kw5["threshold"]) for x in clouds5]
+    n_simplices = int(sum(sum(c) for c in counts5))
+    log(f"workload {c5['name']}: {len(clouds5)} clouds, {n_simplices} simplices of dims 0-2")
     for i in range(args.warmup):
         c0 = time.perf_counter()
-        bars, info = rips.barcode_device(xt, max_dim=max_dim, threshold=t, p=p)
+        bb = rips.barcode_batched(xb5, off5, nmax5, **kw5)
         torch.cuda.synchronize()
         log(f"warmup {i}: {1e3 * (time.perf_counter() - c0):.2f} ms")
-
     rips.profile_enable(True)
+    evs = [ev_pair() for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        bars, info = rips.barcode_device(xt, max_dim=max_dim, threshold=t, p=p)
+        evs[i][0].record()
+        bb = rips.barcode_batched(xb5, off5, nmax5, **kw5)
+        evs[i][1].record()
         if i % 5 == 4:
             log(f"step {i + 1}/{args.steps}")
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    log(f"timed: {1e3 * (t1 - t0) / args.steps:.2f} ms/step")
     rips.profile_enable(False)
-    prof = rips.profile_read()
-
+    prof5 = rips.profile_read()
+    step_ms = sorted(a.elapsed_time(b) for a, b in evs)
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = n_simplices / ((t1 - t0) / args.steps)
-    stats = info["stats"]
-    sparse = info["sparse"]
-    pmc = read_pmc_summary()
-    valu = read_valu_summary()
+    log(f"timed: {ms_per_step:.2f} ms/step (event median {step_ms[len(step_ms) // 2]:.2f} ms)")
+    stats5 = bb.stats.cpu().numpy()
+    fields = rips.STAT_FIELDS
+    st5 = [[{f: int(stats5[b, d, q]) for q, f in enumerate(fields)} for d in range(2)]
+           for b in range(len(clouds5))]
+    pmc = read_pmc_summary(PMC_SUMMARY_BATCH)
+    gms, gcalls = prof5["batched_graph"]
+    glaunch = gms / gcalls
+    gbytes = batched_bytes(clouds5, counts5, st5)
+    gach = gbytes / (glaunch * 1e-3) / 1e9
+    tr = pmc.get("batched") if pmc else None
+    roofline = {
+        "kernel": "k_batched (the batched launch: one hipGraph of the LPT order, the persistent "
+                  "kernel and the bar layout)",
+        "bound": "hbm",
+        "achieved": round(gach, 4),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(gach / HBM_PEAK_GBS, 7),
+        "traffic": round(tr[0] + tr[1], 1) if tr else None,
+        "bytes_per_launch": gbytes,
+        "avg_launch_us": round(glaunch * 1e3, 3),
+        "note": "latency-bound: each cloud's dimension-1 reduction is a chain of dependent "
+                "column additions in one workgroup; the HBM roof is far away",
+    }
+    elim5 = {}
+    for key in ("candidates", "cleared", "apparent_col", "columns", "emergent", "reduced",
+                "additions", "entries_added", "entries_stored"):
+        elim5[key] = int(sum(s[1][key] for s in st5))
+    elim5["fraction_eliminated"] = round(
+        (elim5["cleared"] + elim5["apparent_col"]) / max(1, elim5["candidates"]), 6)
 
-    def roof(name):
-        ms, calls = prof[name]
-        per_launch_ms = ms / calls
-        by = kernel_bytes(name, n, counts, stats, sparse)
-        ach = by / (per_launch_ms * 1e-3) / 1e9 if by else None
-        tr = pmc.get(name) if pmc else None
-        return {
-            "kernel": name,
-            "bound": "hbm",
-            "achieved": round(ach, 4) if ach is not None else None,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 7) if ach is not None else None,
-            "traffic": round(tr[0] + tr[1], 1) if tr else None,
-            "bytes_per_launch": by,
-            "avg_launch_us": round(per_launch_ms * 1e3, 3),
-        }
-
-    def alu(name):
-        """Vector-ALU issue rate of a kernel class: VALU wave instructions
-        per dispatch (committed counter summary) over the live launch time;
-        LDS instructions alongside. None when the summary is stale."""
-        row = valu.get(name) if valu else None
-        if not row:
-            return None
-        ms, calls = prof[name]
-        sec = ms / calls * 1e-3
-        ach = row["SQ_INSTS_VALU"] / sec / 1e9
-        return {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_GIPS,
-                "unit": "G wave64 VALU instructions/s", "frac": round(ach / VALU_PEAK_GIPS, 5),
-                "lds_instructions": row.get("SQ_INSTS_LDS"),
-                "vmem_read_instructions": row.get("SQ_INSTS_VMEM_RD")}
-
-    dname = max(prof.items(), key=lambda kv: kv[1][0])[0]
-    roofline = roof(dname)
-    roofline["valu"] = alu(dname)
-    if dname.startswith("reduce_d"):
-        k = int(dname[-1])
-        s = stats[k]
-        roofline["note"] = ("column reduction spread over one workgroup per CU, bound by the "
-                            "latency of the longest chain of dependent additions: "
-                            f"{s['columns']} columns, {s['additions']} additions, "
-                            f"{s['entries_added']} entries added, {s['entries_stored']} stored")
-        roofline["columns_per_s"] = round(s["columns"] / (roofline["avg_launch_us"] * 1e-6), 1)
-    fname = f"filter_d{max_dim}"
+    # ---- the other four workloads
+    configs = {"circles-64x400": {
+        "ms_per_batch": round(ms_per_step, 3), "simplices_per_s": round(value, 1),
+        "barcodes_per_s": round(len(clouds5) / (ms_per_step * 1e-3), 1),
+        "simplices": n_simplices, "eliminated_d1": elim5}}
     enum_pass = None
-    if fname in prof:
-        enum_pass = roof(fname)
-        fms, fc = prof[fname]
-        enum_pass["candidates_per_s"] = round(counts[max_dim] / (fms / fc * 1e-3), 1)
-        enum_pass["valu"] = alu(fname)
-
-    eliminated = {}
-    for k in range(1, max_dim + 1):
-        s = stats[k]
-        c = max(1, s["candidates"])
-        eliminated[f"d{k}"] = {
-            "candidates": s["candidates"],
-            "cleared": s["cleared"], "apparent_col": s["apparent_col"],
-            "apparent_pivot": s["apparent_pivot"],
-            "fraction_eliminated": round(
-                (s["cleared"] + s["apparent_col"] + s["apparent_pivot"]) / c, 6),
-            "columns": s["columns"], "emergent": s["emergent"], "reduced": s["reduced"],
-            "additions": s["additions"],
-        }
-
-    batched = None
-    if not args.no_batched:
+    prof2 = None
+    info2 = None
+    counts2 = rips.simplex_counts(x2t, kw2["max_dim"] + 1, threshold=kw2["threshold"])
+    if not args.no_configs:
+        for cid in (1, 2, 3):
+            c = workloads.config(cid)
+            xt = torch.from_numpy(c["clouds"][0]).to(dev)
+            kw = dict(max_dim=c["max_dim"], threshold=c["threshold"], p=c["p"])
+            cnt = rips.simplex_counts(xt, kw["max_dim"] + 1, threshold=kw["threshold"])
+            rips.barcode_device(xt, **kw)
+            torch.cuda.synchronize()
+            reps = 10
+            ev = [ev_pair() for _ in range(reps)]
+            if cid == 2:
+                rips.profile_enable(True)
+            torch.cuda.synchronize()
+            c0 = time.perf_counter()
+            for q in range(reps):
+                ev[q][0].record()
+                _, info = rips.barcode_device(xt, **kw)
+                ev[q][1].record()
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - c0) / reps
+            if cid == 2:
+                rips.profile_enable(False)
+                prof2 = rips.profile_read()
+                info2 = info
+            med = sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
+            configs[c["name"]] = {
+                "ms_per_barcode": round(wall * 1e3, 3), "event_median_ms": round(med, 3),
+                "simplices": cnt, "simplices_per_s": round(sum(cnt) / wall, 1),
+                "columns": [info["stats"][k]["columns"] for k in range(1, kw["max_dim"] + 1)],
+                "additions": [info["stats"][k]["additions"] for k in range(1, kw["max_dim"] + 1)]}
+            log(f"{c['name']}: {wall * 1e3:.2f} ms per barcode")
+        # mixture-512 in one launch against one cloud at a time
         c4 = workloads.config(4)
-        clouds = c4["clouds"]
-        xb, off, nmax = rips.pack_clouds(clouds)
-        rips.barcode_batched(xb, off, nmax, max_dim=c4["max_dim"], p=c4["p"])  # graph + scratch
+        clouds4 = c4["clouds"]
+        kw4 = dict(max_dim=c4["max_dim"], threshold=c4["threshold"], p=c4["p"])
+        xb4, off4, nmax4 = rips.pack_clouds(clouds4)
+        cnt4 = int(sum(sum(rips.simplex_counts(torch.from_numpy(x).to(dev), 2)) for x in clouds4))
+        rips.barcode_batched(xb4, off4, nmax4, **kw4)
         torch.cuda.synchronize()
-        reps = 5
+        reps = 10
         c0 = time.perf_counter()
         for _ in range(reps):
-            rips.barcode_batched(xb, off, nmax, max_dim=c4["max_dim"], p=c4["p"])
+            rips.barcode_batched(xb4, off4, nmax4, **kw4)
         torch.cuda.synchronize()
         tb = (time.perf_counter() - c0) / reps
-        log(f"batched mixture-512: {1e3 * tb:.1f} ms per batch")
-        xs = [torch.from_numpy(a).to(dev) for a in clouds]
+        xs = [torch.from_numpy(a).to(dev) for a in clouds4]
         torch.cuda.synchronize()
         c0 = time.perf_counter()
         for q, a in enumerate(xs):
-            rips.barcode_device(a, max_dim=c4["max_dim"], p=c4["p"])
-            if q % 128 == 127:
-                log(f"one at a time: {q + 1}/{len(xs)}")
+            rips.barcode_device(a, **kw4)
         torch.cuda.synchronize()
         ts = time.perf_counter() - c0
-        batched = {
-            "workload": "mixture-512: 512 clouds of 32-256 points in R^3 (1-3 noisy circles "
-                        "and blobs), full Rips, dims 0-1, Z/2",
-            "barcodes_per_s_batched": round(len(clouds) / tb, 1),
-            "barcodes_per_s_single": round(len(clouds) / ts, 1),
-            "ratio": round(ts / tb, 2),
-            "config": list(rips.batched_get_config()),
-        }
+        configs[c4["name"]] = {
+            "ms_per_batch": round(tb * 1e3, 3), "simplices": cnt4,
+            "simplices_per_s": round(cnt4 / tb, 1),
+            "barcodes_per_s_batched": round(len(clouds4) / tb, 1),
+            "barcodes_per_s_single": round(len(clouds4) / ts, 1),
+            "batched_over_single": round(ts / tb, 2),
+            "config": list(rips.batched_get_config())}
+        log(f"mixture-512: {tb * 1e3:.1f} ms per batch, {ts:.2f} s one at a time")
+
+    if prof2 is not None and "filter_d2" in prof2:
+        # the enumeration / apparent-pair pass of so3-1000, dimension 2: the
+        # candidates read (12 B), the survivors written (12 B) and the
+        # neighbour lists read (8 B per edge); the apparent-pair table the
+        # reduction reads afterwards is an implementation choice, reported
+        # apart
+        fms, fc = prof2["filter_d2"]
+        sec = fms / fc * 1e-3
+        s2 = info2["stats"][2]
+        by = 12.0 * counts2[2] + 12.0 * s2["columns"] + 8.0 * counts2[1]
+        ach = by / sec / 1e9
+        pmc2 = read_pmc_summary(PMC_SUMMARY)
+        tr2 = pmc2.get("filter_d2") if pmc2 else None
+        enum_pass = {
+            "kernel": "filter_d2 (so3-1000)", "bound": "hbm", "achieved": round(ach, 4),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 7),
+            "traffic": round(tr2[0] + tr2[1], 1) if tr2 else None,
+            "bytes_per_launch": by, "avg_launch_us": round(sec * 1e6, 3),
+            "table_bytes_per_launch": 32.0 * s2["apparent_col"],
+            "candidates_per_s": round(counts2[2] / sec, 1),
+            "valu": alu_rate(prof2, "filter_d2")}
 
     shortcuts = None
     if not args.no_shortcuts:
-        # the ablation of the paper's Table 3 on the bench cloud, every row
-        # with clearing: no other shortcut ("discarded"), the emergent
-        # shortcut, both ("apparent"); the apparent one alone; and all but
-        # clearing (cohomology without clearing)
+        # the ablation of the paper's Table 3 on so3-1000, every row with
+        # clearing: no other shortcut ("discarded"), the emergent shortcut,
+        # both ("apparent"); the apparent one alone; and all but clearing
         C, E, A = rips.SHORTCUT_CLEARING, rips.SHORTCUT_EMERGENT, rips.SHORTCUT_APPARENT
         names = {C: "clearing", C | E: "clearing + emergent",
                  C | E | A: "clearing + emergent + apparent (default)",
@@ -464,21 +529,21 @@ def main() -> int:
         try:
             for flags in names:
                 rips.set_shortcuts(flags)
-                rips.barcode_device(xt, max_dim=max_dim, threshold=t, p=p)  # warm-up
+                rips.barcode_device(x2t, **kw2)  # warm-up
                 torch.cuda.synchronize()
                 tt = []
                 for _ in range(3):
                     c0 = time.perf_counter()
-                    _, inf_s = rips.barcode_device(xt, max_dim=max_dim, threshold=t, p=p)
+                    _, inf_s = rips.barcode_device(x2t, **kw2)
                     torch.cuda.synchronize()
                     tt.append(time.perf_counter() - c0)
                 st_s = inf_s["stats"]
                 shortcuts.append({
                     "shortcuts": names[flags],
                     "ms_per_barcode": round(1e3 * sorted(tt)[1], 3),
-                    "columns": [st_s[k]["columns"] for k in range(1, max_dim + 1)],
-                    "emergent": [st_s[k]["emergent"] for k in range(1, max_dim + 1)],
-                    "additions": [st_s[k]["additions"] for k in range(1, max_dim + 1)],
+                    "columns": [st_s[k]["columns"] for k in range(1, 3)],
+                    "emergent": [st_s[k]["emergent"] for k in range(1, 3)],
+                    "additions": [st_s[k]["additions"] for k in range(1, 3)],
                 })
                 log(f"shortcuts {names[flags]}: {1e3 * sorted(tt)[1]:.1f} ms")
         finally:
@@ -486,47 +551,39 @@ def main() -> int:
 
     cocycles = None
     if not args.no_cocycles:
-        # representative cocycles of dimension 1 on the bench cloud (V_j of
-        # every bar, essential columns included), against the plain barcode
-        # of the same dimensions; host input, median of three after a warm-up
-        rips.cocycles(x, dim=1, threshold=t, p=p)
-        tc, tb = [], []
+        rips.cocycles(x2, dim=1, threshold=kw2["threshold"], p=kw2["p"])
+        tc, tbc = [], []
         for _ in range(3):
             c0 = time.perf_counter()
-            cc = rips.cocycles(x, dim=1, threshold=t, p=p)
+            cc = rips.cocycles(x2, dim=1, threshold=kw2["threshold"], p=kw2["p"])
             tc.append(time.perf_counter() - c0)
             c0 = time.perf_counter()
-            rips.barcode(x, max_dim=1, threshold=t, p=p)
-            tb.append(time.perf_counter() - c0)
+            rips.barcode(x2, max_dim=1, threshold=kw2["threshold"], p=kw2["p"])
+            tbc.append(time.perf_counter() - c0)
         sizes = [len(sc) for sc, _ in cc.cocycles]
         cocycles = {
             "workload": "so3-1000, t = 1.4, cocycles of dimension 1, Z/2 (host input)",
             "ms_cocycles": round(1e3 * sorted(tc)[1], 2),
-            "ms_barcode_dims_0_1": round(1e3 * sorted(tb)[1], 2),
-            "bars": len(sizes),
-            "entries": int(sum(sizes)),
+            "ms_barcode_dims_0_1": round(1e3 * sorted(tbc)[1], 2),
+            "bars": len(sizes), "entries": int(sum(sizes)),
             "max_entries": int(max(sizes)) if sizes else 0,
         }
         log(f"cocycles: {cocycles['ms_cocycles']} ms for {len(sizes)} bars")
 
     homology = None
     if not args.no_homology:
-        # the homology variant on the bench cloud, dims 0-1: boundary matrices
-        # with clearing from the top down, against cohomology with clearing
-        # (sections "Clearing inessential birth columns" and "Cohomology")
         c0 = time.perf_counter()
-        hom = rips.barcode_homology(x, max_dim=1, threshold=t, p=p)
+        hom = rips.barcode_homology(x2, max_dim=1, threshold=kw2["threshold"], p=kw2["p"])
         t_hom = time.perf_counter() - c0
-        rips.barcode(x, max_dim=1, threshold=t, p=p)  # warm-up
+        rips.barcode(x2, max_dim=1, threshold=kw2["threshold"], p=kw2["p"])  # warm-up
         c0 = time.perf_counter()
-        coh = rips.barcode(x, max_dim=1, threshold=t, p=p)
+        coh = rips.barcode(x2, max_dim=1, threshold=kw2["threshold"], p=kw2["p"])
         t_coh = time.perf_counter() - c0
         same = all(np.array_equal(getattr(hom.bars[d], f), getattr(coh.bars[d], f))
                    for d in range(2) for f in ("birth", "death", "birth_simplex", "death_simplex"))
         homology = {
             "workload": "so3-1000, t = 1.4, dims 0-1, Z/2 (host input, one call each)",
-            "seconds_homology": round(t_hom, 3),
-            "seconds_cohomology": round(t_coh, 4),
+            "seconds_homology": round(t_hom, 3), "seconds_cohomology": round(t_coh, 4),
             "columns_homology": [hom.stats[d]["columns"] for d in range(2)],
             "cleared_homology": [hom.stats[d]["cleared"] for d in range(2)],
             "additions_homology": [hom.stats[d]["additions"] for d in range(2)],
@@ -578,45 +635,55 @@ def main() -> int:
                 for f, g in zip(("birth", "death", "birth_simplex", "death_simplex"), bars6[d])))
 
     cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        oracle.build(force=False)
-        reps, el = 0, 0.0
-        while reps == 0 or el < args.cpu_seconds:
-            c0 = time.perf_counter()
-            oracle.barcode(x, max_dim=max_dim, threshold=t, p=p)
-            el += time.perf_counter() - c0
-            reps += 1
-            log(f"cpu oracle run {reps}: {el / reps:.2f} s")
-        cpu = {"value": round(n_simplices / (el / reps), 1), "unit": "simplices/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"the full so3-1000 cloud (same input), {reps} run(s), "
-                         f"{el / reps:.3f} s each, single thread"}
-
     cpu_paper = None
     if not args.no_cpu_baseline:
         import cpu_baseline
         import oracle
-        cpu_baseline.build(force=False)
-        dl = oracle.distances(x)  # the same float32 distances (not timed)
-        reps, el = 0, 0.0
-        while reps == 0 or el < 5.0:
+        hc = host_cpu()
+        oracle.build(force=False)
+        # the oracle on the first clouds of the headline batch, one thread,
+        # until the bound on CPU seconds is reached
+        el, done, simp = 0.0, 0, 0
+        while done < len(clouds5) and (done == 0 or el < args.cpu_seconds):
             c0 = time.perf_counter()
-            cb = cpu_baseline.barcode(dl, n, max_dim=max_dim, threshold=t, p=p)
+            oracle.barcode(clouds5[done], **kw5)
             el += time.perf_counter() - c0
-            reps += 1
-        log(f"cpu paper algorithm: {el / reps:.3f} s per barcode ({reps} runs)")
-        same = all(np.array_equal(getattr(cb.bars[d], f), g.cpu().numpy())
-                   for d in range(max_dim + 1)
-                   for f, g in zip(("birth", "death", "birth_simplex", "death_simplex"), bars[d]))
-        cpu_paper = {"value": round(n_simplices / (el / reps), 1), "unit": "simplices/s", "cores": 1,
+            simp += sum(counts5[done])
+            done += 1
+            log(f"cpu oracle cloud {done}: {el / done:.2f} s per cloud")
+        cpu = {"value": round(simp / el, 1), "unit": "simplices/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {done} clouds of the circles-64x400 batch (same inputs), "
+                         f"{el / done:.3f} s per cloud, single thread",
+               **hc}
+        # the paper's algorithm on every cloud of the batch, one thread; then
+        # one process per usable core (at most 16)
+        cpu_baseline.build(force=False)
+        dls = [oracle.distances(x) for x in clouds5]  # the same float32 distances (not timed)
+        c0 = time.perf_counter()
+        res = [cpu_baseline.barcode(dl, x.shape[0], **kw5) for dl, x in zip(dls, clouds5)]
+        tcpu = time.perf_counter() - c0
+        same = True
+        for b, r in enumerate(res):
+            for d in range(kw5["max_dim"] + 1):
+                seg = [t.cpu().numpy() for t in bb.segment(b, d)]
+                for f, g in zip(("birth", "death", "birth_simplex", "death_simplex"), seg):
+                    same = same and np.array_equal(getattr(r.bars[d], f), g)
+        workers = max(1, min(16, hc["usable_cores"] or 1))
+        tpar = cpu_baseline.timed_pool(dls, [x.shape[0] for x in clouds5], workers, **kw5)
+        log(f"cpu paper algorithm: {tcpu:.2f} s for the batch on one thread, {tpar:.2f} s on "
+            f"{workers} processes")
+        cpu_paper = {"value": round(n_simplices / tcpu, 1), "unit": "simplices/s", "cores": 1,
                      "kind": "paper algorithm, single thread (cpu_baseline/)",
-                     "sample": f"the full so3-1000 cloud, {reps} run(s), {el / reps:.3f} s each; "
-                               f"distances precomputed",
-                     "bars_equal_gpu": bool(same)}
+                     "sample": f"all {len(clouds5)} clouds of the circles-64x400 batch, "
+                               f"{tcpu:.3f} s; distances precomputed",
+                     "bars_equal_gpu": bool(same),
+                     "all_cores": {"value": round(n_simplices / tpar, 1), "cores": workers,
+                                   "seconds": round(tpar, 3),
+                                   "kind": "the same, one process per core over the clouds"},
+                     **hc}
 
     line = {
-        "metric": "simplices/s (one barcode of the so3-1000 workload per step)",
+        "metric": "simplices/s (the circles-64x400 batch of barcodes per step)",
         "value": round(value, 1),
         "unit": "simplices/s",
         "n_gpus": 1,
@@ -628,15 +695,19 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "so3-1000: 1000 Haar SO(3) rotations in R^9, float32, "
-                               "threshold 1.4, dims 0-2, Z/2",
-                   "n": n, "dims": max_dim, "threshold": t, "p": p,
-                   "simplex_counts": counts},
+        "config": {"workload": "circles-64x400: 64 clouds of 400 points in R^2 (360 on the unit "
+                               "circle, noise 0.1, 40 uniform outliers in [-2, 2]^2), float32, "
+                               "full Rips, dims 0-1, Z/2, one persistent launch",
+                   "clouds": len(clouds5), "n": 400, "dims": 1, "p": 2,
+                   "simplices": n_simplices},
+        "event_ms_per_step": {"median": round(step_ms[len(step_ms) // 2], 4),
+                              "min": round(step_ms[0], 4), "max": round(step_ms[-1], 4)},
+        "barcodes_per_s": round(len(clouds5) / (ms_per_step * 1e-3), 1),
         "roofline": roofline,
         "enumeration_pass": enum_pass,
-        "kernels_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in sorted(prof.items())},
-        "eliminated": eliminated,
-        "batched": batched,
+        "configs": configs,
+        "kernels_ms_per_barcode_so3_1000": (
+            {k: round(v[0] / v[1], 4) for k, v in sorted(prof2.items())} if prof2 else None),
         "shortcuts": shortcuts,
         "homology": homology,
         "cocycles": cocycles,

@@ -106,3 +106,26 @@ def barcode(dist_lower: np.ndarray, n: int, *, max_dim: int = 1,
         return Result(float(lib.pc_threshold(h)), bars, cols, adds)
     finally:
         lib.pc_free(h)
+
+
+def _pool_one(args):
+    dl, n, kw = args
+    barcode(dl, n, **kw)
+    return 0
+
+
+def timed_pool(dist_lowers, ns, workers: int, **kw) -> float:
+    """Wall seconds of barcode() over many clouds in `workers` processes (one
+    cloud per task, largest first), with the workers started and warmed up
+    before the clock starts. The processes are spawned, so none inherits a
+    process that uses the GPU."""
+    import multiprocessing as mp
+    import time
+    order = sorted(range(len(ns)), key=lambda b: -ns[b])
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        warm = np.zeros(3, np.float32) + 1.0
+        pool.map(_pool_one, [(warm, 3, dict(max_dim=1))] * workers)
+        t0 = time.perf_counter()
+        pool.map(_pool_one, [(dist_lowers[b], ns[b], kw) for b in order], chunksize=1)
+        return time.perf_counter() - t0
