@@ -348,6 +348,27 @@ rips_status rips_set_reduced_storage(int32_t mode);
 rips_status rips_get_reduced_storage(int32_t *mode);
 
 /*
+ * The working column of the dimension-1 reduction (per device, the current
+ * one; single-cloud and batched paths). Its rows are triangles, and over
+ * Z/2 with every shortcut on it can be held direct-mapped: one bit per
+ * (longest edge, third vertex), the edges <= t in order of length, so that
+ * an addition is one XOR per entry and the oldest entry is the highest bit
+ * of the first nonempty edge (the refined order of section "Lexicographic
+ * refinement"; the implicit columns of section "Implicit matrix
+ * reduction").
+ *   RIPS_WORKING_COLUMN_AUTO (default): direct-mapped where it applies and
+ *     fits (n <= 1984, at most 2^18 edges <= t, its bitmaps within 8 GiB),
+ *     else the general working column;
+ *   RIPS_WORKING_COLUMN_GENERAL: always the general one (LDS delta, sorted
+ *     base, far list).
+ * The bars are the same either way. Other values: RIPS_E_INVALID_ARG.
+ */
+#define RIPS_WORKING_COLUMN_AUTO 0
+#define RIPS_WORKING_COLUMN_GENERAL 1
+rips_status rips_set_working_column(int32_t mode);
+rips_status rips_get_working_column(int32_t *mode);
+
+/*
  * The homology variant, for the ablation of the sections "Clearing
  * inessential birth columns" and "Cohomology": the filtration boundary
  * matrices are reduced with clearing (Algorithm 2 on boundary matrices),

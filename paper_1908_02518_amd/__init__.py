@@ -45,6 +45,8 @@ EXPORTS = (
     "rips_result_free",
     "rips_barcode_cocycles",
     "rips_barcode_homology",
+    "rips_set_working_column",
+    "rips_get_working_column",
     "rips_set_reduced_storage",
     "rips_get_reduced_storage",
     "rips_cocycles_free",
@@ -210,6 +212,10 @@ def _load():
     lib.rips_set_shortcuts.restype = ctypes.c_int
     lib.rips_get_shortcuts.argtypes = [ctypes.POINTER(ctypes.c_int32)]
     lib.rips_get_shortcuts.restype = ctypes.c_int
+    lib.rips_set_working_column.argtypes = [ctypes.c_int32]
+    lib.rips_set_working_column.restype = ctypes.c_int
+    lib.rips_get_working_column.argtypes = [ctypes.POINTER(ctypes.c_int32)]
+    lib.rips_get_working_column.restype = ctypes.c_int
     lib.rips_set_reduced_storage.argtypes = [ctypes.c_int32]
     lib.rips_set_reduced_storage.restype = ctypes.c_int
     lib.rips_get_reduced_storage.argtypes = [ctypes.POINTER(ctypes.c_int32)]
@@ -576,6 +582,24 @@ def set_reduced_storage(mode: int = R_AUTO):
     and "discarding R" rows): R_AUTO when cheaper to add, R_DISCARD never,
     R_STORE whenever it fits. The bars are the same in every mode."""
     _check(_lib.rips_set_reduced_storage(int(mode)))
+
+
+WORKING_COLUMN_AUTO = 0
+WORKING_COLUMN_GENERAL = 1
+
+
+def set_working_column(mode: int = WORKING_COLUMN_AUTO):
+    """Working column of the dimension-1 reduction: WORKING_COLUMN_AUTO uses
+    the direct-mapped one (one bit per longest edge and third vertex) where
+    it applies (Z/2, every shortcut on) and fits; WORKING_COLUMN_GENERAL
+    always the general one. The bars are the same either way."""
+    _check(_lib.rips_set_working_column(int(mode)))
+
+
+def get_working_column() -> int:
+    a = ctypes.c_int32()
+    _check(_lib.rips_get_working_column(ctypes.byref(a)))
+    return int(a.value)
 
 
 def get_reduced_storage() -> int:

@@ -190,6 +190,22 @@ enum BufId {
     BB_SCAL,
     BB_BINOM,
     BB_INV,
+    // direct-mapped working column of dimension 1 (batched path)
+    BB_BM_POS,
+    BB_BM_VERTS,
+    BB_BM_LEN,
+    BB_BM_BITS,
+    // the same for the single-cloud path, and its edge sort
+    B_BM_POS,
+    B_BM_VERTS,
+    B_BM_LEN,
+    B_BM_BITS,
+    B_BM_SORT_LO0,
+    B_BM_SORT_LO1,
+    B_BM_SORT_HI0,
+    B_BM_SORT_HI1,
+    B_BM_SORT_V0,
+    B_BM_SORT_V1,
     // homology variant
     B_HOM_OUT,
     B_HOM_PERM,
@@ -226,6 +242,11 @@ struct DevCtx {
     int64_t batch_logstride = 0;
     u32 batch_capD = 0; // 0 = default delta size of the batched reduction
     int batch_wgpcu = 0; // 0 = default (1 persistent workgroup per CU)
+    int working_column = RIPS_WORKING_COLUMN_AUTO; // rips_set_working_column
+    // the bitmap buffers are zero between columns; these record what was
+    // zeroed after the last allocation (pointer and bytes) per path
+    void *bm_zero_ptr[2] = {nullptr, nullptr};
+    size_t bm_zero_bytes[2] = {0, 0};
 
     // No-allocation mode (the context of rips_barcode_device_noalloc): every
     // buffer is carved from one fixed device region instead of hipMalloc;
@@ -1401,6 +1422,24 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     int *order;
     ENS(BB_ORDER, (int64_t)B * 4, order, int);
     A.order = order;
+    // the direct-mapped working column of dimension 1, where it fits
+    const bool bm = C->working_column == RIPS_WORKING_COLUMN_AUTO &&
+                    batched_bm_fits(n_max, max_dim, p, G);
+    if (bm) {
+        const int64_t W = (n_max + 31) / 32;
+        ENS(BB_BM_POS, G * npairs * 4, A.bm_pos, int);
+        ENS(BB_BM_VERTS, G * npairs * 4, A.bm_verts, u32);
+        ENS(BB_BM_LEN, G * npairs * 4, A.bm_len, float);
+        A.bm_tab_stride = npairs;
+        ENS(BB_BM_BITS, G * npairs * W * 4, A.bm_bits, u32);
+        A.bm_stride = npairs * W;
+        const size_t need = (size_t)(G * npairs * W * 4);
+        if (C->bm_zero_ptr[1] != (void *)A.bm_bits || C->bm_zero_bytes[1] < need) {
+            HIP_TRY(hipMemsetAsync(A.bm_bits, 0, need, st));
+            C->bm_zero_ptr[1] = (void *)A.bm_bits;
+            C->bm_zero_bytes[1] = need;
+        }
+    }
     struct BatchScal {
         unsigned long long queue, ucount;
         int64_t total;
@@ -1412,7 +1451,7 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     A.ucount = &bs->ucount;
     A.status = &bs->status;
 #undef ENS
-    HIP_TRY(batched_prepare(lds_d, n_max, capD));
+    HIP_TRY(batched_prepare(lds_d, n_max, capD, bm));
     // the graph is keyed by every argument and buffer address it captures
     std::vector<unsigned char> key(sizeof(A) + sizeof(lpt) + 6 * sizeof(void *) + 16);
     {
@@ -2090,6 +2129,29 @@ rips_status rips_set_reduced_storage(int32_t mode) {
     if (rs) return rs;
     std::lock_guard<std::mutex> lk(C->mu);
     C->rstore = mode == RIPS_R_DISCARD ? kRStoreNever : (mode == RIPS_R_STORE ? kRStoreAlways : kRStoreAuto);
+    return RIPS_OK;
+}
+
+rips_status rips_set_working_column(int32_t mode) {
+    g_err.clear();
+    if (mode != RIPS_WORKING_COLUMN_AUTO && mode != RIPS_WORKING_COLUMN_GENERAL)
+        return fail(RIPS_E_INVALID_ARG, "unknown working-column mode");
+    DevCtx *C;
+    rips_status rs = get_ctx(&C);
+    if (rs) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    C->working_column = mode;
+    return RIPS_OK;
+}
+
+rips_status rips_get_working_column(int32_t *mode) {
+    g_err.clear();
+    if (!mode) return fail(RIPS_E_INVALID_ARG, "null mode");
+    DevCtx *C;
+    rips_status rs = get_ctx(&C);
+    if (rs) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    *mode = C->working_column;
     return RIPS_OK;
 }
 

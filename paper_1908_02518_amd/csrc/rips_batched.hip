@@ -66,9 +66,17 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
     constexpr bool kLds = std::is_same<Dist, DistPacked>::value;
     const int tid = threadIdx.x, lane = lane_id();
     const int wg = blockIdx.x;
+    // max_dim and the cloud index are uniform: held in scalar registers they
+    // are never copied between vector registers by the register allocator.
+    // (A copy of max_dim into an accumulation register, placed at the end of
+    // a divergent loop before the exec mask was restored, once left it
+    // undefined in the lanes outside that loop; those lanes then took the
+    // dimension-1 branch alone.)
+    const int max_dim = __builtin_amdgcn_readfirstlane(A.max_dim);
+    b = __builtin_amdgcn_readfirstlane(b);
+    const int D1 = max_dim + 1;
     const int64_t o0 = A.offsets[b];
     const int64_t nn = A.offsets[b + 1] - o0;
-    const int D1 = A.max_dim + 1;
     if (nn < 1 || nn > A.nmax) {
         // rejected by the order pass (status bit 16); publish empty segments
         if (threadIdx.x == 0)
@@ -79,7 +87,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         __syncthreads();
         return;
     }
-    const int n = (int)nn;
+    const int n = __builtin_amdgcn_readfirstlane((int)nn);
     const int m = A.m;
     const float *X = A.X + o0 * m;
     const int64_t npairs = (int64_t)n * (n - 1) / 2;
@@ -119,7 +127,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
     }
     __syncthreads();
     const float renc = n > 1 ? __uint_as_float((u32)Sh.flag) : 0.0f;
-    const float t = fminf(A.threshold, renc);
+    const float t = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(fminf(A.threshold, renc))));
     // ---- H0: Boruvka on the pairs <= t, union-find state in LDS
     const int nm = A.nmax;
     const int64_t npairs_max = (int64_t)nm * (nm - 1) / 2;
@@ -332,7 +340,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
     }
     __syncthreads();
     int nb1 = 0;
-    if (A.max_dim >= 1) {
+    if (max_dim >= 1) {
         // ---- dimension 1: enumeration / apparent-pair filter over the edges
         Ctx<Dist> c;
         c.d = dist;
@@ -433,6 +441,50 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
             cols.j[q] = surv.j[e];
             cols.tapp[q] = surv.tapp[e];
         }
+        // ---- the edges <= t in order of length, for the direct-mapped
+        // working column: each thread keeps a contiguous range of pair
+        // indices, so that the stable sort leaves equal lengths in index order
+        EdgeOrder eo{nullptr, nullptr, nullptr, 0, 0};
+#ifndef RIPS_AB_NO_EDGE_ORDER
+        if (A.bm_bits) {
+            const int64_t chunk = (npairs + kBT - 1) / kBT;
+            const int64_t e0 = (int64_t)tid * chunk, e1 = min(npairs, e0 + chunk);
+            int cnt = 0;
+            for (int64_t e = e0; e < e1; ++e) {
+                int a, cc;
+                pair_of(e, &a, &cc);
+                cnt += dist(a, cc) <= t ? 1 : 0;
+            }
+            int nE;
+            int at = block_scan_excl<kBT>(cnt, Sh.w, &nE);
+            for (int64_t e = e0; e < e1; ++e) {
+                int a, cc;
+                pair_of(e, &a, &cc);
+                const float d = dist(a, cc);
+                if (d <= t) {
+                    sb.lo[0][at] = 0;
+                    sb.hi[0][at] = __float_as_uint(d);
+                    sb.val[0][at] = (u32)e;
+                    ++at;
+                }
+            }
+            gsync();
+            const int ce = block_radix_sort<kBT>(sb, nE, 0, 4, SS);
+            int *bpos = A.bm_pos + (int64_t)wg * A.bm_tab_stride;
+            u32 *bv = A.bm_verts + (int64_t)wg * A.bm_tab_stride;
+            float *bl = A.bm_len + (int64_t)wg * A.bm_tab_stride;
+            for (int q = tid; q < nE; q += kBT) {
+                const u32 e = sb.val[ce][q];
+                int a, cc;
+                pair_of(e, &a, &cc);
+                bpos[e] = q;
+                bv[q] = ((u32)a << 16) | (u32)cc;
+                bl[q] = __uint_as_float(sb.hi[ce][q]);
+            }
+            gsync();
+            eo = EdgeOrder{bpos, bv, bl, nE, (n + 31) / 32};
+        }
+#endif
         // ---- the reduction reads D from global; LDS now holds its working column
         if (kLds)
             for (int64_t e = tid; e < npairs; e += kBT) Dgw[e] = Dl[e];
@@ -468,6 +520,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         Staging Gs;
         ReduceScratch SC;
         carve_reduce_lds(smem, A.capD, (LDS int *)&s_nsl, &Dw, &Gs, &SC.SB);
+        const BmLds L = carve_bm_lds(smem, reduce_lds_bytes(A.capD), A.bm_bits ? eo.E : 0);
         for (int h = 0; h < 2; ++h) {
             SC.F.idx[h] = A.f_idx[h] + (int64_t)wg * A.f_stride;
             SC.F.dia[h] = A.f_dia[h] + (int64_t)wg * A.f_stride;
@@ -494,8 +547,11 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
 #endif
         J.prev_bits = nullptr;
         J.prev = PivotHash{nullptr, nullptr, 0};
+        J.eo = eo;
+        J.bm_bits = A.bm_bits;
+        J.bm_stride = A.bm_stride;
         gsync();
-        const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, RS);
+        const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, L, RS);
         if (rstat && tid == 0) {
             const int bit = rstat == kRedBaseFull    ? 1
                             : rstat == kRedStoreFull ? 2
@@ -646,11 +702,22 @@ __global__ void k_batch_copy(const int64_t *seg_start, const int64_t *seg_count,
     }
 }
 
-size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD) {
+size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD, bool bm) {
     const size_t npairs = (size_t)nmax * (nmax - 1) / 2;
     const size_t dpart = lds_d ? (npairs * 4 + 15) / 16 * 16 : 0;
     const size_t uf = (size_t)nmax * (8 + 4 + 4) + (lds_d ? (npairs / 32 + 1) * 4 : 0);
-    return std::max(dpart + uf, reduce_lds_bytes(capD));
+    return std::max(dpart + uf, reduce_lds_bytes(capD) + (bm ? bm_lds_bytes((int64_t)npairs) : 0));
+}
+
+// The direct-mapped working column needs W = ceil(nmax / 32) <= 62 words per
+// edge (the pivot search reads one edge's bitmap with one wave), a summary of
+// C(nmax, 2) bits in LDS beside the general working column's, and
+// C(nmax, 2) * W words of bitmaps per workgroup (at most 8 GiB in all).
+bool batched_bm_fits(int nmax, int max_dim, u32 p, int64_t grid) {
+    const int64_t npairs = (int64_t)nmax * (nmax - 1) / 2;
+    const int64_t W = (nmax + 31) / 32;
+    return p == 2 && max_dim >= 1 && W <= 62 && npairs <= (1 << 18) &&
+           grid * npairs * W * 4 <= (8ll << 30);
 }
 
 // default delta: the largest (kMaxDelta slots, about 94 KB of LDS with its
@@ -661,8 +728,8 @@ u32 batched_default_capD(bool lds_d, int nmax) {
     return kMaxDelta;
 }
 
-hipError_t batched_prepare(bool lds_d, int nmax, u32 capD) {
-    const size_t lds = batched_lds_bytes(lds_d, nmax, capD);
+hipError_t batched_prepare(bool lds_d, int nmax, u32 capD, bool bm) {
+    const size_t lds = batched_lds_bytes(lds_d, nmax, capD, bm);
     return hipFuncSetAttribute(lds_d ? (const void *)k_batched<DistPacked>
                                      : (const void *)k_batched<DistFull>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -672,7 +739,7 @@ void launch_batched(const BatchArgs &A, bool lds_d, int grid, SortBufs lpt, hipS
     hipLaunchKernelGGL(k_batch_status_reset, dim3(1), dim3(1), 0, st, A.status);
     hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, st, A.offsets, A.B, lpt,
                        (int *)A.order, A.queue, A.ucount, A.status, A.nmax);
-    const size_t lds = batched_lds_bytes(lds_d, A.nmax, A.capD);
+    const size_t lds = batched_lds_bytes(lds_d, A.nmax, A.capD, A.bm_bits != nullptr);
     if (lds_d) hipLaunchKernelGGL(k_batched<DistPacked>, dim3(grid), dim3(kBT), lds, st, A);
     else hipLaunchKernelGGL(k_batched<DistFull>, dim3(grid), dim3(kBT), lds, st, A);
 }

@@ -74,13 +74,23 @@ struct BatchArgs {
     rips_dim_stats *stats;          // B * (max_dim + 1)
     float *t_used;                  // B
     int *status;
+    // direct-mapped working column of dimension 1 (Z/2), or bm_bits == null:
+    // per workgroup the edge order (C(nmax, 2) entries each) and the bitmaps
+    int *bm_pos;
+    u32 *bm_verts;
+    float *bm_len;
+    int64_t bm_tab_stride;          // C(nmax, 2)
+    u32 *bm_bits;                   // all zero between columns
+    int64_t bm_stride;              // C(nmax, 2) * ceil(nmax / 32) words
 };
 
 
-size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD);
+size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD, bool bm);
 u32 batched_default_capD(bool lds_d, int nmax);
-hipError_t batched_prepare(bool lds_d, int nmax, u32 capD);
+hipError_t batched_prepare(bool lds_d, int nmax, u32 capD, bool bm);
 void launch_batched(const BatchArgs &A, bool lds_d, int grid, SortBufs lpt, hipStream_t st);
+// whether the batched path can use the direct-mapped working column
+bool batched_bm_fits(int nmax, int max_dim, u32 p, int64_t grid);
 void launch_batch_finalize(const BatchArgs &A, int64_t *offsets_out, int64_t *total, int64_t cap,
                            float *ob, float *od, int64_t *obs, int64_t *ods, hipStream_t st);
 

@@ -768,8 +768,9 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 c
     Staging G;
     SortedBase SB;
     carve_reduce_lds(smem, capD, (LDS int *)&s_ns, &D, &G, &SB);
+    const BmLds L = carve_bm_lds(smem, reduce_lds_bytes(capD), J.bm_bits ? J.eo.E : 0);
     const ReduceScratch SC = make_scratch(RB, SB, (LDS int *)&S.vns);
-    const int status = reduce_columns<kRedThreads>(J, D, G, SC, S);
+    const int status = reduce_columns<kRedThreads>(J, D, G, SC, L, S);
     if (threadIdx.x == 0) {
         s->status = status;
         s->nbars = S.nbars;
@@ -818,7 +819,8 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce_par(ReduceJob<Dist> J, u
     R.lcoef += g * RB.lcap;
     R.ldia += g * RB.lcap;
     const ReduceScratch SC = make_scratch(R, SB, (LDS int *)&S.vns);
-    const int status = reduce_columns_par<kRedThreads>(J, D, G, SC, S);
+    const BmLds L = carve_bm_lds(smem, reduce_lds_bytes(capD), J.bm_bits ? J.eo.E : 0);
+    const int status = reduce_columns_par<kRedThreads>(J, D, G, SC, L, S);
     if (threadIdx.x == 0) {
         if (status && status != kRedAbort) atomicCAS(&s->status, 0, status);
         atomicAdd(&s->stat[kStatEmergent], S.stat[0]);
@@ -1199,7 +1201,7 @@ void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Colu
 
 hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceBuffers RB, Scalars *s,
                          hipStream_t st) {
-    const size_t lds = reduce_lds_bytes(capD);
+    const size_t lds = reduce_lds_bytes(capD) + (J.bm_bits ? bm_lds_bytes(J.eo.E) : 0);
     hipError_t e = hipFuncSetAttribute((const void *)k_reduce<DistFull>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
@@ -1209,7 +1211,7 @@ hipError_t launch_reduce(const ReduceJob<DistFull> &J, u32 capD, ReduceBuffers R
 
 hipError_t launch_reduce_par(const ReduceJob<DistFull> &J, u32 capD, ReduceBuffers RB, int groups,
                              BarBuf out, Scalars *s, hipStream_t st) {
-    const size_t lds = reduce_lds_bytes(capD);
+    const size_t lds = reduce_lds_bytes(capD) + (J.bm_bits ? bm_lds_bytes(J.eo.E) : 0);
     hipError_t e = hipFuncSetAttribute((const void *)k_reduce_par<DistFull>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

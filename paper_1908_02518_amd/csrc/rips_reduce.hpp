@@ -297,6 +297,42 @@ struct ParState {
               // committed; only raised), abort flag
 };
 
+// The edges <= t in order of length, for the direct-mapped working column of
+// dimension 1 (rips_reduce_bm.hpp): edge CNS index -> position, position ->
+// vertices (a << 16 | b, a > b) and length. E == 0: not in use.
+struct EdgeOrder {
+    const int *pos;
+    const u32 *verts;
+    const float *len;
+    int E;
+    int W; // 32-bit words of one edge's bitmap: ceil(n / 32)
+};
+
+// The summary of the direct-mapped working column in LDS: one bit per edge
+// position (l1, n1 words) and one per first-level word (l2, n2 words).
+struct BmLds {
+    LDS u32 *l1;
+    LDS u32 *l2;
+    int n1, n2, E;
+};
+
+__host__ __device__ constexpr size_t bm_lds_bytes(int64_t E) {
+    return E <= 0 ? 0 : (size_t)(((E + 31) / 32) + ((E + 1023) / 1024)) * 4;
+}
+
+// Carve the summary after `at` bytes of the block and clear it (all threads).
+__device__ __forceinline__ BmLds carve_bm_lds(unsigned char *smem, size_t at, int E) {
+    BmLds L;
+    L.E = E;
+    L.n1 = (E + 31) / 32;
+    L.n2 = (L.n1 + 31) / 32;
+    L.l1 = (LDS u32 *)((LDS unsigned char *)smem + at);
+    L.l2 = L.l1 + L.n1;
+    for (int i = threadIdx.x; i < L.n1 + L.n2; i += blockDim.x) L.l1[i] = 0u;
+    __syncthreads();
+    return L;
+}
+
 template <class Dist>
 struct ReduceJob {
     Ctx<Dist> c;
@@ -322,6 +358,11 @@ struct ReduceJob {
     // edges of H0 as bits (k = 1), else that dimension's pivot table
     const u32 *prev_bits;
     PivotHash prev;
+    // direct-mapped working column (dimension 1, Z/2, every shortcut on):
+    // bm_bits == null means the general working column is used
+    EdgeOrder eo = {nullptr, nullptr, nullptr, 0, 0};
+    u32 *bm_bits = nullptr; // eo.E * eo.W words per workgroup, all zero between columns
+    int64_t bm_stride = 0;  // words per workgroup (workgroup blockIdx.x uses its own)
 };
 
 constexpr int kRedTimers = 24;
@@ -350,6 +391,7 @@ struct RedShared {
     unsigned long long wacc;
 #endif
     int fa_n, fa_r; // apparent steps of wave 0: additions made, result
+    int bmf;        // direct-mapped working column: front position of the pivot search
     u32 lo, bound;
     int shift;
     unsigned long long vbase;
@@ -2041,9 +2083,15 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
 // global scratch. Returns a result code. Stats: S.stat = emergent, reduced,
 // additions, bars_nonzero, essential, columns that used the sorted base or
 // far list, largest stored V column, largest working column.
+} // namespace rips
+
+#include "rips_reduce_bm.hpp"
+
+namespace rips {
+
 template <int BT, class Dist>
 __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const LdsCol &D, const Staging &G,
-                              const ReduceScratch &SC, RedShared<BT> &S) {
+                              const ReduceScratch &SC, const BmLds &L, RedShared<BT> &S) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
     const u32 p = J.p;
@@ -2120,7 +2168,8 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
         RED_T1(S, 8, t_em);
         if (!S.full) continue;
         const int j = S.base;
-        status = reduce_one<BT, Dist, false>(J, D, G, SC, j, S);
+        status = J.bm_bits ? reduce_one_bm<BT, Dist, false>(J, D, SC, L, j, S)
+                           : reduce_one<BT, Dist, false>(J, D, G, SC, j, S);
         if (tid == 0) S.base = j + 1;
         gsync(); // V_j and the table entry are visible before the next column
     }
@@ -2138,7 +2187,7 @@ __device__ __forceinline__ int reduce_columns(const ReduceJob<Dist> &J, const Ld
 template <int BT, class Dist>
 __device__ __forceinline__ int reduce_columns_par(const ReduceJob<Dist> &J, const LdsCol &D,
                                                   const Staging &G, const ReduceScratch &SC,
-                                                  RedShared<BT> &S) {
+                                                  const BmLds &L, RedShared<BT> &S) {
     const Ctx<Dist> &c = J.c;
     const int k = J.k;
     const u32 p = J.p;
@@ -2237,7 +2286,8 @@ __device__ __forceinline__ int reduce_columns_par(const ReduceJob<Dist> &J, cons
             RED_T1(S, 8, t_em);
             if (free) continue;
         }
-        status = reduce_one<BT, Dist, true>(J, D, G, SC, col, S);
+        status = J.bm_bits ? reduce_one_bm<BT, Dist, true>(J, D, SC, L, col, S)
+                           : reduce_one<BT, Dist, true>(J, D, G, SC, col, S);
         if (status) break;
     }
     if (status && status != kRedAbort && tid == 0) st_dev(&J.par.ctl[kCtlAbort], 1u);

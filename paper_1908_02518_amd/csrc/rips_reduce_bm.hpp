@@ -1,0 +1,599 @@
+// rips_reduce_bm.hpp -- the reduction of the dimension-1 columns over Z/2
+// with a direct-mapped working column (included by rips_reduce.hpp).
+//
+// The rows of a dimension-1 coboundary column are triangles. A triangle's
+// diameter is the length of its longest edge, its "owner" (the first of the
+// edges xy, xz, yz of its decreasing vertices x > y > z whose length is the
+// diameter), and among the triangles of one owner edge {a, b} the CNS index
+// grows with the third vertex c. The working column R_j is therefore held
+// as one bit per (owner edge, third vertex): the edges <= t are put in order
+// of length once per dimension (position = rank), and bit c of edge
+// position e is set when the triangle {a_e, b_e, c} is in R_j (over Z/2 an
+// addition is an XOR). The oldest entry (smallest diameter, then largest
+// index) is the highest set bit of the first edge position with a set bit,
+// compared across the run of positions of exactly that length. A summary in
+// LDS marks the positions that may hold set bits (one bit per position, and
+// one bit per 32 of those); it is cleared lazily as the pivot search finds
+// positions empty. The pivot only moves to younger rows while a column is
+// reduced, so the search starts from a front that only moves forward.
+//
+// Compared with the general working column (delta, sorted base, far list)
+// there is no merge, no sorting and no spill: an addition costs one XOR per
+// entry, and the column's size does not matter. The memory is
+// (edges <= t) x ceil(n / 32) words per workgroup, so the engine is used when
+// that fits; the rest of the reduction (the pivot and apparent-pair tables,
+// the addition log, V_j, the commit of the spread-out reduction) is the
+// general one's.
+#pragma once
+
+namespace rips {
+
+// Triangle {a, b, c} (any order) -> CNS index: with x > y > z,
+// C(x, 3) + C(y, 2) + C(z, 1).
+__device__ __forceinline__ int64_t bm_tri_index(int a, int b, int c) {
+    int x = a, y = b, z = c, t;
+    if (x < y) { t = x; x = y; y = t; }
+    if (y < z) { t = y; y = z; z = t; }
+    if (x < y) { t = x; x = y; y = t; }
+    return (int64_t)x * (x - 1) * (x - 2) / 6 + (int64_t)y * (y - 1) / 2 + z;
+}
+
+// Owner edge and third vertex of the triangle {x, y, z}, x > y > z, with
+// edge lengths lxy, lxz, lyz and diameter dm (their maximum): the first of
+// xy, xz, yz whose length is dm.
+__device__ __forceinline__ void bm_owner(int x, int y, int z, float lxy, float lxz, float dm, int *a,
+                                         int *b, int *c) {
+    if (lxy == dm) {
+        *a = x;
+        *b = y;
+        *c = z;
+    } else if (lxz == dm) {
+        *a = x;
+        *b = z;
+        *c = y;
+    } else {
+        *a = y;
+        *b = z;
+        *c = x;
+    }
+}
+
+// Bitmap coordinate of the triangle sigma u {w} of the edge (u, v), u > v,
+// of length luv; -1 when the triangle is longer than t or w is u or v.
+template <class Dist>
+__device__ __forceinline__ int64_t bm_coord(const Ctx<Dist> &c, const EdgeOrder &eo, int u, int v,
+                                            float luv, int w) {
+    if (w == u || w == v) return -1;
+    const float luw = c.d(u, w), lvw = c.d(v, w);
+    const float dm = fmaxf(luv, fmaxf(luw, lvw));
+    if (!(dm <= c.t)) return -1;
+    // decreasing vertices x > y > z, with the lengths of xy and xz
+    int x, y, z;
+    float lxy, lxz;
+    if (w > u) {
+        x = w; y = u; z = v; lxy = luw; lxz = lvw;
+    } else if (w > v) {
+        x = u; y = w; z = v; lxy = luw; lxz = luv;
+    } else {
+        x = u; y = v; z = w; lxy = luv; lxz = luw;
+    }
+    int a, b, cc;
+    bm_owner(x, y, z, lxy, lxz, dm, &a, &b, &cc);
+    const int pos = eo.pos[(int64_t)a * (a - 1) / 2 + b];
+    return ((int64_t)pos << 16) | cc;
+}
+
+// XOR one entry into the working column and mark its position in the
+// summary (any thread; LDS and global atomics at workgroup scope).
+__device__ __forceinline__ void bm_flip(u32 *bits, const BmLds &L, int W, int64_t coord) {
+    const int pos = (int)(coord >> 16), cc = (int)(coord & 0xffff);
+    __hip_atomic_fetch_xor(&bits[(int64_t)pos * W + (cc >> 5)], 1u << (cc & 31), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_or(&L.l1[pos >> 5], 1u << (pos & 31), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_or(&L.l2[pos >> 10], 1u << ((pos >> 5) & 31), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// First position >= f whose summary bit is set, or -1 (wave 0; the result
+// in every lane). Stale second-level bits met on the way are cleared.
+__device__ __forceinline__ int bm_next(const BmLds &L, int f) {
+    const int lane = lane_id();
+    if (f >= L.E) return -1;
+    int w1 = f >> 5;
+    const u32 first = L.l1[w1] & (~0u << (f & 31));
+    if (first) return (w1 << 5) + __ffs((int)first) - 1;
+    int i = w1 + 1; // next first-level word to look at
+    while (i < L.n1) {
+        // second level from bit i: 64 words of it at a time
+        const int w2 = (i >> 5) + lane;
+        u32 x = w2 < L.n2 ? L.l2[w2] : 0u;
+        if (lane == 0) x &= ~0u << (i & 31);
+        const u64 nz = __ballot(x != 0);
+        if (!nz) {
+            i = ((i >> 5) + kWave) << 5;
+            continue;
+        }
+        const int ln = __ffsll((unsigned long long)nz) - 1;
+        const u32 xw = lane_bcast(x, ln);
+        const int j = (((i >> 5) + ln) << 5) + __ffs((int)xw) - 1; // first-level word
+        const u32 y = L.l1[j];
+        if (y) return (j << 5) + __ffs((int)y) - 1;
+        if (lane == 0)
+            __hip_atomic_fetch_and(&L.l2[j >> 5], ~(1u << (j & 31)), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        i = j + 1;
+    }
+    return -1;
+}
+
+// The oldest live entry of the working column (wave 0 calls it; the result
+// in every lane of wave 0): smallest diameter, then largest index. *front
+// moves past positions found empty (their summary bits are cleared) and
+// then to the first position of the pivot's run of equal lengths: an entry
+// younger than the pivot may still be added anywhere in that run, never
+// before it. The edge's bitmap takes lanes 0 .. W-1 (W <= 62); lanes 62 and
+// 63 read the lengths on either side in the same round trip.
+__device__ __forceinline__ PivotCand bm_pivot(const EdgeOrder &eo, const u32 *bits, const BmLds &L,
+                                              int *front) {
+    const int lane = lane_id();
+    const int W = eo.W;
+    PivotCand out;
+    out.idx = kEmpty;
+    out.diam = 0.0f;
+    out.coef = 1u;
+    int f = *front;
+    for (;;) {
+        const int pos = bm_next(L, f);
+        if (pos < 0) {
+            f = L.E;
+            break;
+        }
+        u32 w = 0;
+        float side = -1.0f;
+        if (lane < W) w = ld(&bits[(int64_t)pos * W + lane]);
+        else if (lane == kWave - 2 && pos > 0) side = eo.len[pos - 1];
+        else if (lane == kWave - 1 && pos + 1 < eo.E) side = eo.len[pos + 1];
+        const float dm = eo.len[pos];
+        const u64 nz = __ballot(w != 0);
+        if (!nz) {
+            if (lane == 0) {
+                const u32 bit = 1u << (pos & 31);
+                const u32 was = __hip_atomic_fetch_and(&L.l1[pos >> 5], ~bit, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                if ((was & ~bit) == 0)
+                    __hip_atomic_fetch_and(&L.l2[pos >> 10], ~(1u << ((pos >> 5) & 31)),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+            f = pos + 1;
+            continue;
+        }
+        const int hl = 63 - __clzll((long long)nz);
+        const u32 hw = lane_bcast(w, hl);
+        const int c = hl * 32 + 31 - __clz((int)hw);
+        const u32 ab = eo.verts[pos];
+        out.idx = bm_tri_index((int)(ab >> 16), (int)(ab & 0xffffu), c);
+        out.diam = dm;
+        // the run of equal lengths starts at or before pos
+        int rs = pos;
+        float prev_len = lane_bcast(side, kWave - 2);
+        while (rs > 0 && prev_len == dm) {
+            --rs;
+            prev_len = rs > 0 ? eo.len[rs - 1] : -1.0f;
+        }
+        f = rs;
+        // positions after pos of exactly the same length: their triangles tie
+        // on the diameter, and the largest index among them is the oldest
+        float next_len = lane_bcast(side, kWave - 1);
+        for (int q = pos + 1; q < eo.E && next_len == dm; ++q) {
+            if ((L.l1[q >> 5] >> (q & 31)) & 1u) {
+                u32 wq = 0;
+                if (lane < W) wq = ld(&bits[(int64_t)q * W + lane]);
+                const u64 nq = __ballot(wq != 0);
+                if (nq) {
+                    const int hq = 63 - __clzll((long long)nq);
+                    const u32 hwq = lane_bcast(wq, hq);
+                    const int cq = hq * 32 + 31 - __clz((int)hwq);
+                    const u32 abq = eo.verts[q];
+                    const int64_t iq = bm_tri_index((int)(abq >> 16), (int)(abq & 0xffffu), cq);
+                    if (iq > out.idx) out.idx = iq;
+                }
+            }
+            next_len = q + 1 < eo.E ? eo.len[q + 1] : -1.0f;
+        }
+        break;
+    }
+    *front = f;
+    return out;
+}
+
+// Add the coboundaries of the S.nit edges in S.it_v to the working column:
+// the (edge, candidate vertex) pairs are spread over the workgroup; dense
+// candidates are all vertices, sparse ones the neighbours of the edge's
+// vertex with the fewer neighbours (as in add_items).
+template <int BT, class Dist>
+__device__ __forceinline__ void bm_add_items(const ReduceJob<Dist> &J, RedShared<BT> &S, u32 *bits,
+                                             const BmLds &L) {
+    // values, not references into the job (which may live in scratch memory)
+    const Ctx<Dist> c = J.c;
+    const EdgeOrder eo = J.eo;
+    const int tid = threadIdx.x;
+    const int nit = S.nit;
+    int cnt = 0;
+    if (tid < nit) {
+        if (c.nb.off == nullptr) {
+            S.it_u[tid] = -1;
+            S.it_start[tid] = 0;
+            cnt = c.n;
+        } else {
+            const int u = S.it_v[tid][0], v = S.it_v[tid][1];
+            const int lu = c.nb.off[u], du = c.nb.off[u + 1] - lu;
+            const int lv = c.nb.off[v], dv = c.nb.off[v + 1] - lv;
+            S.it_u[tid] = dv < du ? v : u;
+            S.it_start[tid] = dv < du ? lv : lu;
+            cnt = dv < du ? dv : du;
+        }
+    }
+    int total;
+    if (nit == 1) {
+        if (tid == 0) {
+            S.it_off[0] = 0;
+            S.it_off[1] = cnt;
+        }
+        __syncthreads();
+        total = S.it_off[1];
+    } else {
+        const int off = block_scan_excl<BT>(cnt, S.w, &total);
+        if (tid < nit) S.it_off[tid] = off;
+        if (tid == 0) S.it_off[nit] = total;
+        __syncthreads();
+    }
+    unsigned long long added = 0;
+    for (int fl = tid; fl < total; fl += BT) {
+        int lo = 0, hi = nit - 1; // last item with it_off <= fl
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (S.it_off[mid] <= fl) lo = mid;
+            else hi = mid - 1;
+        }
+        const int q = fl - S.it_off[lo];
+        const int w = S.it_u[lo] < 0 ? q : c.nb.idx[S.it_start[lo] + q];
+        const int u = S.it_v[lo][0], v = S.it_v[lo][1];
+        const int64_t cd = bm_coord(c, eo, u, v, S.it_diam[lo], w);
+        if (cd >= 0) {
+            bm_flip(bits, L, eo.W, cd);
+            ++added;
+        }
+    }
+    if (added) atomicAdd(&S.stat[12], added);
+    __syncthreads(); // the flips are done, and the items read, before anyone goes on
+}
+
+// Add a stored reduced column R_o (entries in bitmap coordinates).
+template <int BT>
+__device__ __forceinline__ void bm_add_r(const VStore &V, int64_t off, int len, u32 *bits,
+                                         const BmLds &L, int W, RedShared<BT> &S) {
+    for (int e = threadIdx.x; e < len; e += BT) bm_flip(bits, L, W, V.idx[off + e]);
+    if (threadIdx.x == 0) S.stat[12] += (unsigned long long)len;
+    __syncthreads();
+}
+
+// Live entries of the working column from the front on (all threads).
+template <int BT>
+__device__ __forceinline__ int64_t bm_count(const u32 *bits, const BmLds &L, int W, int f,
+                                            RedShared<BT> &S) {
+    int cnt = 0;
+    for (int i = (f >> 5) + threadIdx.x; i < L.n1; i += BT) {
+        u32 m = L.l1[i];
+        while (m) {
+            const int pos = (i << 5) + __ffs((int)m) - 1;
+            m &= m - 1;
+            for (int q = 0; q < W; ++q) cnt += __popc(ld(&bits[(int64_t)pos * W + q]));
+        }
+    }
+    int tot;
+    (void)block_scan_excl<BT>(cnt, S.w, &tot);
+    return tot;
+}
+
+// Append the live entries (bitmap coordinates) to the column store; returns
+// the count, or -1 when the store is full (all threads).
+template <int BT>
+__device__ __forceinline__ int bm_store(const u32 *bits, const BmLds &L, int W, int f, const VStore &V,
+                                        unsigned long long *vcount, RedShared<BT> &S, int64_t *off_out) {
+    int cnt = 0;
+    for (int i = (f >> 5) + threadIdx.x; i < L.n1; i += BT) {
+        u32 m = L.l1[i];
+        while (m) {
+            const int pos = (i << 5) + __ffs((int)m) - 1;
+            m &= m - 1;
+            for (int q = 0; q < W; ++q) cnt += __popc(ld(&bits[(int64_t)pos * W + q]));
+        }
+    }
+    int tot;
+    int at = block_scan_excl<BT>(cnt, S.w, &tot);
+    if (threadIdx.x == 0) S.vbase = atomicAdd(vcount, (unsigned long long)tot);
+    __syncthreads();
+    const int64_t vb = (int64_t)S.vbase;
+    if (vb + tot > V.cap) return -1;
+    for (int i = (f >> 5) + threadIdx.x; i < L.n1; i += BT) {
+        u32 m = L.l1[i];
+        while (m) {
+            const int pos = (i << 5) + __ffs((int)m) - 1;
+            m &= m - 1;
+            for (int q = 0; q < W; ++q) {
+                u32 x = ld(&bits[(int64_t)pos * W + q]);
+                while (x) {
+                    const int cc = q * 32 + __ffs((int)x) - 1;
+                    x &= x - 1;
+                    V.idx[vb + at] = ((int64_t)pos << 16) | cc;
+                    V.diam[vb + at] = 0.0f;
+                    V.coef[vb + at] = 1u;
+                    ++at;
+                }
+            }
+        }
+    }
+    *off_out = vb;
+    return tot;
+}
+
+// Empty the working column: the bitmaps of every marked position, then the
+// summary (all threads). A position whose summary bit is clear has an empty
+// bitmap, so this clears everything.
+template <int BT>
+__device__ __forceinline__ void bm_clear(u32 *bits, const BmLds &L, int W) {
+    for (int i = threadIdx.x; i < L.n1; i += BT) {
+        u32 m = L.l1[i];
+        while (m) {
+            const int pos = (i << 5) + __ffs((int)m) - 1;
+            m &= m - 1;
+            for (int q = 0; q < W; ++q) st(&bits[(int64_t)pos * W + q], 0u);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < L.n1; i += BT) L.l1[i] = 0u;
+    for (int i = threadIdx.x; i < L.n2; i += BT) L.l2[i] = 0u;
+    __syncthreads();
+}
+
+// Full reduction of column j with the direct-mapped working column: the
+// steps of reduce_one (same pivot tests, additions, log, stores and commit),
+// for k = 1 over Z/2 with every shortcut on.
+template <int BT, class Dist, bool kPar>
+__device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const LdsCol &D,
+                                             const ReduceScratch &SC, const BmLds &L, int j,
+                                             RedShared<BT> &S) {
+    const Ctx<Dist> &c = J.c;
+    const int k = J.k;
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    const int W = J.eo.W;
+    u32 *bits = J.bm_bits + (int64_t)blockIdx.x * J.bm_stride;
+    const int64_t sidx = J.cols.idx[j];
+    const float sdm = J.cols.diam[j];
+    if (tid == 0) {
+        S.abort = 0;
+        S.bmf = 0;
+        S.nlog = 0;
+        S.vest = 1;
+        S.nit = 1;
+        S.it_coef[0] = 1u;
+        S.it_diam[0] = sdm;
+        decode(sidx, k, c.n, c.B, S.it_v[0]);
+        if (kPar) {
+            S.pub = __float_as_uint(sdm);
+            st_dev(&J.par.cst[j], S.pub);
+        }
+    }
+    __syncthreads();
+    bm_add_items<BT>(J, S, bits, L);
+    int result = kRedOk;
+    int nadd = 0;
+    for (;;) {
+        if (nadd > kMaxAdditions) {
+            result = kRedBound;
+            break;
+        }
+        if (w == 0) {
+            int f = S.bmf;
+            const EdgeOrder eo = J.eo;
+            const PivotCand pv = bm_pivot(eo, bits, L, &f);
+            if (lane == 0) {
+                S.bmf = f;
+                S.piv = pv;
+            }
+        }
+        __syncthreads();
+        const PivotCand piv = S.piv;
+        if (piv.idx == kEmpty) {
+            // zero column: an essential class born at sigma
+            int64_t voff = 0;
+            int vn = -1;
+            if (J.keep_essential_v) {
+                vn = store_v<BT>(J, D, SC, sidx, sdm, S, &voff);
+                if (vn < 0) {
+                    result = -vn;
+                    break;
+                }
+            }
+            if (kPar) {
+                if (tid == 0) {
+                    J.bars.birth[j] = sdm;
+                    J.bars.death[j] = INFINITY;
+                    J.bars.bs[j] = sidx;
+                    J.bars.ds[j] = -1;
+                    S.stat[4] += 1;
+                    if (J.keep_essential_v) {
+                        J.V.off[j] = voff;
+                        J.V.len[j] = vn;
+                    }
+                }
+                fence_release_dev();
+                __syncthreads();
+                if (tid == 0) st_dev(&J.par.cst[j], kColDone);
+            } else if (tid == 0) {
+                if (S.nbars < J.ncols) {
+                    J.bars.birth[S.nbars] = sdm;
+                    J.bars.death[S.nbars] = INFINITY;
+                    J.bars.bs[S.nbars] = sidx;
+                    J.bars.ds[S.nbars] = -1;
+                    S.nbars++;
+                }
+                S.stat[4] += 1;
+                if (J.keep_essential_v) {
+                    J.V.off[j] = voff;
+                    J.V.len[j] = vn;
+                }
+            }
+            break;
+        }
+        if (kPar && tid == 0 && __float_as_uint(piv.diam) > S.pub) {
+            S.pub = __float_as_uint(piv.diam);
+            st_dev(&J.par.cst[j], S.pub);
+        }
+        if (tid == 0) S.owner = ph_find(J.ph, piv.idx);
+        if (tid == kWave) S.appv = pair_find(J.app, piv.idx);
+        __syncthreads();
+        if (kPar && S.owner < 0 && S.appv < 0) {
+            result = par_wait<BT>(J, S, j, __float_as_uint(piv.diam));
+            if (result) break;
+            if (tid == 0) S.owner = ph_find_dev(J.ph, piv.idx);
+            __syncthreads();
+        }
+        const int64_t o = S.owner;
+        if (kPar && o >= j) {
+            result = kRedOrder;
+            break;
+        }
+        if (kPar && o >= 0) fence_acquire_dev();
+        if (o >= 0) {
+            // R_j += R_o (Z/2)
+            const int vlen = J.V.len[o];
+            const int rlen = J.V.rlen[o];
+            if (tid == 0 && !log_add(SC, S, -2 - o, 1u, 0.0f, vlen < 0 ? 1 : vlen)) S.abort = kRedLogFull;
+            if (rlen >= 0) {
+                bm_add_r<BT>(J.V, J.V.roff[o], rlen, bits, L, W, S);
+            } else if (vlen < 0) {
+                // emergent column: R_o is the coboundary of sigma_o
+                if (tid == 0) {
+                    S.nit = 1;
+                    S.it_coef[0] = 1u;
+                    S.it_diam[0] = J.cols.diam[o];
+                    decode(J.cols.idx[o], k, c.n, c.B, S.it_v[0]);
+                }
+                __syncthreads();
+                bm_add_items<BT>(J, S, bits, L);
+            } else {
+                const int64_t voff = J.V.off[o];
+                for (int c0 = 0; c0 < vlen; c0 += BT) {
+                    const int nit = min(BT, vlen - c0);
+                    if (tid < nit) {
+                        const int64_t e = voff + c0 + tid;
+                        decode(J.V.idx[e], k, c.n, c.B, S.it_v[tid]);
+                        S.it_diam[tid] = J.V.diam[e];
+                        S.it_coef[tid] = 1u;
+                    }
+                    if (tid == 0) S.nit = nit;
+                    __syncthreads();
+                    bm_add_items<BT>(J, S, bits, L);
+                }
+            }
+            if (S.abort) {
+                result = S.abort;
+                break;
+            }
+            ++nadd;
+            continue;
+        }
+        if (S.appv >= 0) {
+            // the pivot tau is in a zero apparent pair (rho, tau): add the
+            // coboundary of rho
+            if (tid == 0) {
+                const int64_t a = S.appv;
+                decode(a >> 3, k, c.n, c.B, S.it_v[0]);
+                S.nit = 1;
+                S.it_coef[0] = 1u;
+                S.it_diam[0] = piv.diam;
+                if (!log_add(SC, S, a >> 3, 1u, piv.diam, 1)) S.abort = kRedLogFull;
+            }
+            __syncthreads();
+            bm_add_items<BT>(J, S, bits, L);
+            if (S.abort) {
+                result = S.abort;
+                break;
+            }
+            ++nadd;
+            continue;
+        }
+        // free pivot: the pair (sigma_j, pivot). R_j is stored (in bitmap
+        // coordinates) when it is cheaper to add than V_j's coboundaries are
+        // to recompute; then V_j is summed from the log and stored.
+        int64_t roff = 0;
+        int rn = -1;
+        const int64_t live = bm_count<BT>(bits, L, W, S.bmf, S);
+        if ((float)live <= 2.0f * (float)S.vest * J.cand_avg) {
+            rn = bm_store<BT>(bits, L, W, S.bmf, J.V, J.vcount, S, &roff);
+            if (rn < 0) {
+                result = kRedStoreFull;
+                break;
+            }
+        }
+        __syncthreads();
+        int64_t voff = 0;
+        const int vn = store_v<BT>(J, D, SC, sidx, sdm, S, &voff);
+        if (vn < 0) {
+            result = -vn;
+            break;
+        }
+        if (kPar) {
+            if (tid == 0) {
+                if ((unsigned long long)vn > S.stat[6]) S.stat[6] = vn;
+                J.bars.birth[j] = sdm;
+                J.bars.death[j] = piv.diam;
+                J.bars.bs[j] = piv.diam > sdm ? sidx : -1;
+                J.bars.ds[j] = piv.idx;
+                if (piv.diam > sdm) S.stat[3] += 1;
+                J.V.pivcoef[j] = 1u;
+                J.V.off[j] = voff;
+                J.V.len[j] = vn;
+                J.V.roff[j] = roff;
+                J.V.rlen[j] = rn;
+            }
+            fence_release_dev();
+            __syncthreads();
+            if (tid == 0) {
+                ph_insert_dev(J.ph, piv.idx, j);
+                fence_release_dev();
+                st_dev(&J.par.cst[j], kColDone);
+            }
+        } else if (tid == 0) {
+            if ((unsigned long long)vn > S.stat[6]) S.stat[6] = vn;
+            if (piv.diam > sdm) {
+                if (S.nbars < J.ncols) {
+                    J.bars.birth[S.nbars] = sdm;
+                    J.bars.death[S.nbars] = piv.diam;
+                    J.bars.bs[S.nbars] = sidx;
+                    J.bars.ds[S.nbars] = piv.idx;
+                    S.nbars++;
+                }
+                S.stat[3] += 1;
+            }
+            ph_insert(J.ph, piv.idx, j);
+            J.V.pivcoef[j] = 1u;
+            J.V.off[j] = voff;
+            J.V.len[j] = vn;
+            J.V.roff[j] = roff;
+            J.V.rlen[j] = rn;
+        }
+        break;
+    }
+    if (tid == 0 && result == kRedOk) {
+        S.stat[1] += nadd > 0 ? 1 : 0;
+        S.stat[2] += nadd;
+    }
+    __syncthreads();
+    bm_clear<BT>(bits, L, W);
+    return result;
+}
+
+} // namespace rips

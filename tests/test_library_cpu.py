@@ -168,3 +168,57 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in (r.stdout + r.stderr)
+
+
+def _misplaced_copies(asm: str):
+    """Register copies of the allocator (moves to or from the accumulation
+    registers, spill stores and reloads) placed at the end of a divergent
+    region, just before its exec mask is restored: they run only in the
+    region's lanes, and a value the other lanes need afterwards is then
+    undefined in them."""
+    lines = asm.splitlines()
+    kinds = ("v_accvgpr_write_b32", "v_accvgpr_read_b32", "scratch_store", "scratch_load")
+    hits = []
+    for i, ln in enumerate(lines):
+        if not re.match(r"\s*s_or_b64 exec, exec, s\[\d+:\d+\]\s*$", ln):
+            continue
+        j = i - 1
+        while j >= 0:
+            t = lines[j].strip()
+            if lines[j].startswith((".LBB", "; %bb")) or t.endswith(":"):
+                break
+            if t.startswith(kinds) and "Folded" not in t:
+                hits.append((i + 1, t))
+            elif t and not t.startswith((";", "s_waitcnt", "s_nop")):
+                break
+            j -= 1
+    return hits
+
+
+@pytest.mark.skipif(not os.path.exists("/opt/rocm/bin/hipcc"), reason="needs hipcc")
+@pytest.mark.parametrize("src", ["rips_batched.hip", "rips_kernels.hip"])
+def test_no_register_copy_before_exec_restore(src, tmp_path):
+    # a compiler placement once put a copy of max_dim into an accumulation
+    # register at the end of a divergent loop; the lanes outside the loop then
+    # read an undefined max_dim and took the dimension-1 branch alone
+    csrc = os.path.join(ROOT, "paper_1908_02518_amd", "csrc")
+    out = str(tmp_path / "k.s")
+    r = subprocess.run(["/opt/rocm/bin/hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+                        "-ffp-contract=off", "-Xclang", "-target-feature", "-Xclang",
+                        "-packed-fp32-ops", "-I", os.path.join(ROOT, "include"),
+                        "--cuda-device-only", "-S", src, "-o", out],
+                       capture_output=True, text=True, cwd=csrc, timeout=600)
+    assert r.returncode == 0, r.stderr[-2000:]
+    hits = _misplaced_copies(open(out).read())
+    assert not hits, hits[:5]
+
+
+def test_misplaced_copy_scanner_finds_the_pattern():
+    # the shape the scanner looks for, as the compiler once emitted it, and a
+    # correct join block (the copy after the exec restore)
+    bad = "\n".join([".LBB8_104:", "\tv_accvgpr_write_b32 a4, v24",
+                     "\ts_or_b64 exec, exec, s[0:1]", "\ts_getpc_b64 s[2:3]"])
+    good = "\n".join([".LBB8_104:", "\ts_or_b64 exec, exec, s[0:1]",
+                      "\tv_accvgpr_write_b32 a4, v24", "\ts_getpc_b64 s[2:3]"])
+    assert _misplaced_copies(bad) == [(3, "v_accvgpr_write_b32 a4, v24")]
+    assert _misplaced_copies(good) == []
