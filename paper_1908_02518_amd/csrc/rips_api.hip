@@ -194,11 +194,13 @@ enum BufId {
     BB_BM_POS,
     BB_BM_VERTS,
     BB_BM_LEN,
+    BB_BM_RUN,
     BB_BM_BITS,
     // the same for the single-cloud path, and its edge sort
     B_BM_POS,
     B_BM_VERTS,
     B_BM_LEN,
+    B_BM_RUN,
     B_BM_BITS,
     B_BM_SORT_LO0,
     B_BM_SORT_LO1,
@@ -901,14 +903,64 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         // working column: the delta in LDS (as large as a workgroup's share
         // allows), the sorted base in global scratch (grown on overflow)
         const size_t lds_budget = C.lds_per_block > 16384 ? (size_t)C.lds_per_block - 12288 : 0;
-        uint32_t capD = kMaxDelta;
-        while (capD > 256 && reduce_lds_bytes(capD) > lds_budget) capD >>= 1;
         // the columns spread over one workgroup per CU, each with its own
         // scratch (smaller first sizes, grown on overflow), or one workgroup
         // (no-allocation mode: one workgroup, whose scratch is small)
         const int64_t want = C.arena ? 1 : C.reduce_groups > 0 ? C.reduce_groups : std::max(1, C.num_cus);
         const int64_t groups = std::max<int64_t>(1, std::min<int64_t>(want, S));
         const bool spread = groups > 1;
+        // the direct-mapped working column of dimension 1 (Z/2, every
+        // shortcut and the default storage), where its bitmaps and summary fit
+        const int64_t nE = P.nedges;
+        const int64_t bmW = (n + 31) / 32;
+        // (dense clouds: sparse ones keep the general column, whose apparent
+        // runs read the precomputed coboundary lists of the filter)
+        const bool bm = k == 1 && p == 2 && S > 0 && !C.arena && !P.sparse &&
+                        C.working_column == RIPS_WORKING_COLUMN_AUTO &&
+                        C.shortcuts == (kShortApparent | kShortEmergent | kShortClearing) &&
+                        C.rstore == kRStoreAuto && bmW <= 62 && nE > 0 && nE <= (1 << 18) &&
+                        groups * nE * bmW * 4 <= (8ll << 30) &&
+                        reduce_lds_bytes(256) + bm_lds_bytes(nE) <= lds_budget;
+        uint32_t capD = kMaxDelta;
+        while (capD > 256 && reduce_lds_bytes(capD) + (bm ? bm_lds_bytes(nE) : 0) > lds_budget) capD >>= 1;
+        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, 0, 0};
+        u32 *bm_bits = nullptr;
+        if (bm) {
+            HIP_TRY(C.ensure(B_BM_POS, (size_t)choose_i64(n, 2) * 4 + 16, &q));
+            int *bpos = as<int>(q);
+            HIP_TRY(C.ensure(B_BM_VERTS, (size_t)nE * 4, &q));
+            u32 *bverts = as<u32>(q);
+            HIP_TRY(C.ensure(B_BM_LEN, (size_t)nE * 4, &q));
+            float *blen = as<float>(q);
+            HIP_TRY(C.ensure(B_BM_RUN, (size_t)nE * 4, &q));
+            u32 *brun = as<u32>(q);
+            SortBufs eb;
+            HIP_TRY(C.ensure(B_BM_SORT_LO0, (size_t)nE * 8, &q));
+            eb.lo[0] = as<u64>(q);
+            HIP_TRY(C.ensure(B_BM_SORT_LO1, (size_t)nE * 8, &q));
+            eb.lo[1] = as<u64>(q);
+            HIP_TRY(C.ensure(B_BM_SORT_HI0, (size_t)nE * 4, &q));
+            eb.hi[0] = as<u32>(q);
+            HIP_TRY(C.ensure(B_BM_SORT_HI1, (size_t)nE * 4, &q));
+            eb.hi[1] = as<u32>(q);
+            HIP_TRY(C.ensure(B_BM_SORT_V0, (size_t)nE * 4, &q));
+            eb.val[0] = as<u32>(q);
+            HIP_TRY(C.ensure(B_BM_SORT_V1, (size_t)nE * 4, &q));
+            eb.val[1] = as<u32>(q);
+            const size_t need = (size_t)(groups * nE * bmW * 4);
+            HIP_TRY(C.ensure(B_BM_BITS, need, &q));
+            bm_bits = as<u32>(q);
+            if (C.bm_zero_ptr[0] != (void *)bm_bits || C.bm_zero_bytes[0] < need) {
+                HIP_TRY(hipMemsetAsync(bm_bits, 0, need, st));
+                C.bm_zero_ptr[0] = (void *)bm_bits;
+                C.bm_zero_bytes[0] = need;
+            }
+            {
+                PROF(P_SORT1);
+                launch_bm_edge_order(P.E, (int)nE, eb, bpos, bverts, blen, brun, st);
+            }
+            eo = EdgeOrder{bpos, bverts, blen, brun, (int)nE, (int)bmW};
+        }
         int64_t fcap = spread ? std::max<int64_t>(C.hint_far, 1 << 16)
                               : std::max<int64_t>(C.hint_far, std::max<int64_t>(1 << 18, 256ll * bound));
         int64_t vwcap = std::max<int64_t>(C.hint_vw, 1 << 14);
@@ -1005,6 +1057,11 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             J.prev = ph_prev;
             J.cand_avg = P.sparse ? (float)(2.0 * (double)P.nedges / (double)std::max<int64_t>(n, 1))
                                   : (float)n;
+            if (bm) {
+                J.eo = eo;
+                J.bm_bits = bm_bits;
+                J.bm_stride = nE * bmW;
+            }
             {
                 PROF(P_REDUCE1 + k - 1);
                 if (spread) HIP_TRY(launch_reduce_par(J, capD, RB, (int)groups, bars[k], P.scal, st));
@@ -1430,6 +1487,7 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
         ENS(BB_BM_POS, G * npairs * 4, A.bm_pos, int);
         ENS(BB_BM_VERTS, G * npairs * 4, A.bm_verts, u32);
         ENS(BB_BM_LEN, G * npairs * 4, A.bm_len, float);
+        ENS(BB_BM_RUN, G * npairs * 4, A.bm_run, u32);
         A.bm_tab_stride = npairs;
         ENS(BB_BM_BITS, G * npairs * W * 4, A.bm_bits, u32);
         A.bm_stride = npairs * W;

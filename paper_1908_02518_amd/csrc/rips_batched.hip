@@ -444,7 +444,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         // ---- the edges <= t in order of length, for the direct-mapped
         // working column: each thread keeps a contiguous range of pair
         // indices, so that the stable sort leaves equal lengths in index order
-        EdgeOrder eo{nullptr, nullptr, nullptr, 0, 0};
+        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, 0, 0};
 #ifndef RIPS_AB_NO_EDGE_ORDER
         if (A.bm_bits) {
             const int64_t chunk = (npairs + kBT - 1) / kBT;
@@ -473,6 +473,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
             int *bpos = A.bm_pos + (int64_t)wg * A.bm_tab_stride;
             u32 *bv = A.bm_verts + (int64_t)wg * A.bm_tab_stride;
             float *bl = A.bm_len + (int64_t)wg * A.bm_tab_stride;
+            u32 *br = A.bm_run + (int64_t)wg * A.bm_tab_stride;
             for (int q = tid; q < nE; q += kBT) {
                 const u32 e = sb.val[ce][q];
                 int a, cc;
@@ -482,7 +483,17 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
                 bl[q] = __uint_as_float(sb.hi[ce][q]);
             }
             gsync();
-            eo = EdgeOrder{bpos, bv, bl, nE, (n + 31) / 32};
+            // runs of equal lengths: first position, and whether the next
+            // position continues the run (keys are the length bits)
+            for (int q = tid; q < nE; q += kBT) {
+                const u32 key = sb.hi[ce][q];
+                int r = q;
+                while (r > 0 && sb.hi[ce][r - 1] == key) --r;
+                const bool tie = q + 1 < nE && sb.hi[ce][q + 1] == key;
+                br[q] = (u32)r | (tie ? kRunTie : 0u);
+            }
+            gsync();
+            eo = EdgeOrder{bpos, bv, bl, br, nE, (n + 31) / 32};
         }
 #endif
         // ---- the reduction reads D from global; LDS now holds its working column

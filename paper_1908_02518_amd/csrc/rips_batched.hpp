@@ -79,6 +79,7 @@ struct BatchArgs {
     int *bm_pos;
     u32 *bm_verts;
     float *bm_len;
+    u32 *bm_run;
     int64_t bm_tab_stride;          // C(nmax, 2)
     u32 *bm_bits;                   // all zero between columns
     int64_t bm_stride;              // C(nmax, 2) * ceil(nmax / 32) words

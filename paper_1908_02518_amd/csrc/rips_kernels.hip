@@ -1193,6 +1193,42 @@ void launch_fill_u32(u32 *a, int64_t n, u32 v, hipStream_t st) {
 }
 
 
+// The edges <= t in order of length for the direct-mapped working column of
+// dimension 1 (one workgroup): a sort on the length bits, then position ->
+// vertices, length and run word, and edge index -> position.
+__global__ void __launch_bounds__(1024) k_bm_edge_order(EdgeList E, int nE, SortBufs sb, int *pos,
+                                                        u32 *verts, float *len, u32 *run) {
+    __shared__ SortShared<1024> S;
+    for (int q = threadIdx.x; q < nE; q += 1024) {
+        sb.lo[0][q] = (u64)E.idx[q];
+        sb.hi[0][q] = __float_as_uint(E.diam[q]);
+        sb.val[0][q] = (u32)q;
+    }
+    gsync();
+    // equal lengths may come in any order (the pivot search scans a run of
+    // them whole), so the length bits alone are the key
+    const int cur = block_radix_sort<1024>(sb, nE, 0, 4, S);
+    for (int q = threadIdx.x; q < nE; q += 1024) {
+        const u32 e = sb.val[cur][q];
+        pos[E.idx[e]] = q;
+        verts[q] = ((u32)E.a[e] << 16) | (u32)E.b[e];
+        len[q] = E.diam[e];
+    }
+    gsync();
+    for (int q = threadIdx.x; q < nE; q += 1024) {
+        const u32 key = sb.hi[cur][q];
+        int r = q;
+        while (r > 0 && sb.hi[cur][r - 1] == key) --r;
+        const bool tie = q + 1 < nE && sb.hi[cur][q + 1] == key;
+        run[q] = (u32)r | (tie ? kRunTie : 0u);
+    }
+}
+
+void launch_bm_edge_order(EdgeList E, int nE, SortBufs sb, int *pos, u32 *verts, float *len, u32 *run,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_bm_edge_order, dim3(1), dim3(1024), 0, st, E, nE, sb, pos, verts, len, run);
+}
+
 void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Columns out,
                          hipStream_t st) {
     hipLaunchKernelGGL(k_sort_columns, dim3(1), dim3(kSortThreads), 0, st, in, s, sb, lo_bytes,

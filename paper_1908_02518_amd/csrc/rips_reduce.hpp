@@ -304,9 +304,12 @@ struct EdgeOrder {
     const int *pos;
     const u32 *verts;
     const float *len;
+    const u32 *run; // position -> first position of its run of equal lengths,
+                    // with kRunTie set when the next position has the same length
     int E;
     int W; // 32-bit words of one edge's bitmap: ceil(n / 32)
 };
+constexpr u32 kRunTie = 0x80000000u;
 
 // The summary of the direct-mapped working column in LDS: one bit per edge
 // position (l1, n1 words) and one per first-level word (l2, n2 words).
@@ -360,7 +363,7 @@ struct ReduceJob {
     PivotHash prev;
     // direct-mapped working column (dimension 1, Z/2, every shortcut on):
     // bm_bits == null means the general working column is used
-    EdgeOrder eo = {nullptr, nullptr, nullptr, 0, 0};
+    EdgeOrder eo = {nullptr, nullptr, nullptr, nullptr, 0, 0};
     u32 *bm_bits = nullptr; // eo.E * eo.W words per workgroup, all zero between columns
     int64_t bm_stride = 0;  // words per workgroup (workgroup blockIdx.x uses its own)
 };

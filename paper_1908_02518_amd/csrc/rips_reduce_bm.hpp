@@ -95,6 +95,12 @@ __device__ __forceinline__ void bm_flip(u32 *bits, const BmLds &L, int W, int64_
                           __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Wait until every memory operation the wave issued has completed, the
+// XORs of bm_flip included (s_waitcnt vmcnt(0) expcnt(0) lgkmcnt(0)); the
+// words they changed are read next, by this wave or, after a barrier, by
+// the others.
+__device__ __forceinline__ void bm_wait_flips() { __builtin_amdgcn_s_waitcnt(0); }
+
 // First position >= f whose summary bit is set, or -1 (wave 0; the result
 // in every lane). Stale second-level bits met on the way are cleared.
 __device__ __forceinline__ int bm_next(const BmLds &L, int f) {
@@ -128,78 +134,122 @@ __device__ __forceinline__ int bm_next(const BmLds &L, int f) {
 }
 
 // The oldest live entry of the working column (wave 0 calls it; the result
-// in every lane of wave 0): smallest diameter, then largest index. *front
-// moves past positions found empty (their summary bits are cleared) and
-// then to the first position of the pivot's run of equal lengths: an entry
-// younger than the pivot may still be added anywhere in that run, never
-// before it. The edge's bitmap takes lanes 0 .. W-1 (W <= 62); lanes 62 and
-// 63 read the lengths on either side in the same round trip.
+// in every lane of wave 0): smallest diameter, then largest index. The
+// marked positions from *front on are checked a few at a time: one round
+// trip reads the bitmaps of up to kBmSlots of them (W lanes each) with each
+// one's length and run word (two more lanes). Empty ones are unmarked and
+// passed; *front then stays at the first position of the pivot's run of
+// equal lengths, where an entry younger than the pivot may still be added
+// (never before it).
+constexpr int kBmSlots = 6;
+
+__device__ __forceinline__ int64_t bm_top_index(const EdgeOrder &eo, int pos, u32 w, u64 nz, int base) {
+    // the highest set bit of the position's bitmap (lanes base .. base+W-1)
+    const int hl = 63 - __clzll((long long)nz);
+    const u32 hw = lane_bcast(w, hl);
+    const int c = (hl - base) * 32 + 31 - __clz((int)hw);
+    const u32 ab = eo.verts[pos];
+    return bm_tri_index((int)(ab >> 16), (int)(ab & 0xffffu), c);
+}
+
 __device__ __forceinline__ PivotCand bm_pivot(const EdgeOrder &eo, const u32 *bits, const BmLds &L,
                                               int *front) {
     const int lane = lane_id();
     const int W = eo.W;
+    const int SL = W + 2;
+    const int P = min(kBmSlots, kWave / SL);
     PivotCand out;
     out.idx = kEmpty;
     out.diam = 0.0f;
     out.coef = 1u;
     int f = *front;
     for (;;) {
-        const int pos = bm_next(L, f);
-        if (pos < 0) {
+        // up to P marked positions from f (LDS only)
+        int ps[kBmSlots];
+        int np = 0, g = f;
+#pragma unroll
+        for (int q = 0; q < kBmSlots; ++q) {
+            ps[q] = -1;
+            if (q < P && g >= 0) {
+                const int pp = bm_next(L, g);
+                ps[q] = pp;
+                np += pp >= 0 ? 1 : 0;
+                g = pp >= 0 ? pp + 1 : -1;
+            }
+        }
+        if (np == 0) {
             f = L.E;
             break;
         }
-        u32 w = 0;
-        float side = -1.0f;
-        if (lane < W) w = ld(&bits[(int64_t)pos * W + lane]);
-        else if (lane == kWave - 2 && pos > 0) side = eo.len[pos - 1];
-        else if (lane == kWave - 1 && pos + 1 < eo.E) side = eo.len[pos + 1];
-        const float dm = eo.len[pos];
+        // one round trip: slot q = lanes [q*SL, q*SL + W) bitmap words,
+        // lane q*SL + W its length, lane q*SL + W + 1 its run word
+        const int q = lane / SL, r = lane - q * SL;
+        int mypos = -1;
+#pragma unroll
+        for (int qq = 0; qq < kBmSlots; ++qq) mypos = qq == q ? ps[qq] : mypos;
+        u32 w = 0, rw = 0;
+        float ln = 0.0f;
+        if (q < np && mypos >= 0) {
+            if (r < W) w = ld(&bits[(int64_t)mypos * W + r]);
+            else if (r == W) ln = eo.len[mypos];
+            else rw = eo.run[mypos];
+        }
         const u64 nz = __ballot(w != 0);
-        if (!nz) {
-            if (lane == 0) {
-                const u32 bit = 1u << (pos & 31);
-                const u32 was = __hip_atomic_fetch_and(&L.l1[pos >> 5], ~bit, __ATOMIC_RELAXED,
+        // first slot with a set bit
+        int live = -1;
+        for (int qq = 0; qq < np; ++qq) {
+            const u64 m = qq * SL + W >= 64 ? ~0ull << (qq * SL) : (((1ull << W) - 1) << (qq * SL));
+            if (nz & m) {
+                live = qq;
+                break;
+            }
+        }
+        // unmark the empty slots before it
+        const int nempty = live < 0 ? np : live;
+        if (lane == 0)
+            for (int qq = 0; qq < nempty; ++qq) {
+                int pp = -1;
+#pragma unroll
+                for (int z = 0; z < kBmSlots; ++z) pp = z == qq ? ps[z] : pp;
+                const u32 bit = 1u << (pp & 31);
+                const u32 was = __hip_atomic_fetch_and(&L.l1[pp >> 5], ~bit, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                 if ((was & ~bit) == 0)
-                    __hip_atomic_fetch_and(&L.l2[pos >> 10], ~(1u << ((pos >> 5) & 31)),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_and(&L.l2[pp >> 10], ~(1u << ((pp >> 5) & 31)), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
             }
-            f = pos + 1;
+        if (live < 0) {
+            int last = -1;
+#pragma unroll
+            for (int z = 0; z < kBmSlots; ++z) last = z == np - 1 ? ps[z] : last;
+            f = last + 1;
             continue;
         }
-        const int hl = 63 - __clzll((long long)nz);
-        const u32 hw = lane_bcast(w, hl);
-        const int c = hl * 32 + 31 - __clz((int)hw);
-        const u32 ab = eo.verts[pos];
-        out.idx = bm_tri_index((int)(ab >> 16), (int)(ab & 0xffffu), c);
+        int pos = -1;
+#pragma unroll
+        for (int z = 0; z < kBmSlots; ++z) pos = z == live ? ps[z] : pos;
+        const int base = live * SL;
+        const u64 mlive = (((W >= 64) ? ~0ull : ((1ull << W) - 1)) << base) & nz;
+        out.idx = bm_top_index(eo, pos, w, mlive, base);
+        const float dm = lane_bcast(ln, base + W);
+        const u32 run = lane_bcast(rw, base + W + 1);
         out.diam = dm;
-        // the run of equal lengths starts at or before pos
-        int rs = pos;
-        float prev_len = lane_bcast(side, kWave - 2);
-        while (rs > 0 && prev_len == dm) {
-            --rs;
-            prev_len = rs > 0 ? eo.len[rs - 1] : -1.0f;
-        }
-        f = rs;
+        f = (int)(run & ~kRunTie);
         // positions after pos of exactly the same length: their triangles tie
         // on the diameter, and the largest index among them is the oldest
-        float next_len = lane_bcast(side, kWave - 1);
-        for (int q = pos + 1; q < eo.E && next_len == dm; ++q) {
-            if ((L.l1[q >> 5] >> (q & 31)) & 1u) {
+        bool tie = (run & kRunTie) != 0;
+        for (int qp = pos + 1; tie && qp < eo.E; ++qp) {
+            const u32 rq = eo.run[qp];
+            if ((L.l1[qp >> 5] >> (qp & 31)) & 1u) {
                 u32 wq = 0;
-                if (lane < W) wq = ld(&bits[(int64_t)q * W + lane]);
+                if (lane < W) wq = ld(&bits[(int64_t)qp * W + lane]);
                 const u64 nq = __ballot(wq != 0);
                 if (nq) {
-                    const int hq = 63 - __clzll((long long)nq);
-                    const u32 hwq = lane_bcast(wq, hq);
-                    const int cq = hq * 32 + 31 - __clz((int)hwq);
-                    const u32 abq = eo.verts[q];
-                    const int64_t iq = bm_tri_index((int)(abq >> 16), (int)(abq & 0xffffu), cq);
+                    const int64_t iq = bm_top_index(eo, qp, wq, nq, 0);
                     if (iq > out.idx) out.idx = iq;
                 }
             }
-            next_len = q + 1 < eo.E ? eo.len[q + 1] : -1.0f;
+            tie = (rq & kRunTie) != 0;
         }
         break;
     }
@@ -266,6 +316,7 @@ __device__ __forceinline__ void bm_add_items(const ReduceJob<Dist> &J, RedShared
         }
     }
     if (added) atomicAdd(&S.stat[12], added);
+    bm_wait_flips();
     __syncthreads(); // the flips are done, and the items read, before anyone goes on
 }
 
@@ -275,6 +326,7 @@ __device__ __forceinline__ void bm_add_r(const VStore &V, int64_t off, int len, 
                                          const BmLds &L, int W, RedShared<BT> &S) {
     for (int e = threadIdx.x; e < len; e += BT) bm_flip(bits, L, W, V.idx[off + e]);
     if (threadIdx.x == 0) S.stat[12] += (unsigned long long)len;
+    bm_wait_flips();
     __syncthreads();
 }
 
@@ -351,6 +403,7 @@ __device__ __forceinline__ void bm_clear(u32 *bits, const BmLds &L, int W) {
             for (int q = 0; q < W; ++q) st(&bits[(int64_t)pos * W + q], 0u);
         }
     }
+    bm_wait_flips();
     __syncthreads();
     for (int i = threadIdx.x; i < L.n1; i += BT) L.l1[i] = 0u;
     for (int i = threadIdx.x; i < L.n2; i += BT) L.l2[i] = 0u;
@@ -394,13 +447,26 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
             result = kRedBound;
             break;
         }
+        // the pivot and both table lookups, by wave 0 (one barrier)
         if (w == 0) {
             int f = S.bmf;
             const EdgeOrder eo = J.eo;
             const PivotCand pv = bm_pivot(eo, bits, L, &f);
+            int64_t own = -1;
+            PairHit hit{-1, kNoVerts, 0, kNoList};
+            if (pv.idx != kEmpty) {
+                if (lane == 0) own = ph_find(J.ph, pv.idx);
+                if (lane == 32) hit = pair_find_all(J.app, pv.idx);
+            }
+            own = lane_bcast(own, 0);
+            const int64_t av = lane_bcast(hit.val, 32);
+            const u64 avw = lane_bcast(hit.verts, 32);
             if (lane == 0) {
                 S.bmf = f;
                 S.piv = pv;
+                S.owner = own;
+                S.appv = av;
+                S.vbase = avw; // rho's vertices, when the pivot is apparent
             }
         }
         __syncthreads();
@@ -451,9 +517,6 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
             S.pub = __float_as_uint(piv.diam);
             st_dev(&J.par.cst[j], S.pub);
         }
-        if (tid == 0) S.owner = ph_find(J.ph, piv.idx);
-        if (tid == kWave) S.appv = pair_find(J.app, piv.idx);
-        __syncthreads();
         if (kPar && S.owner < 0 && S.appv < 0) {
             result = par_wait<BT>(J, S, j, __float_as_uint(piv.diam));
             if (result) break;
@@ -507,10 +570,16 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
         }
         if (S.appv >= 0) {
             // the pivot tau is in a zero apparent pair (rho, tau): add the
-            // coboundary of rho
+            // coboundary of rho (its vertices come with the table entry)
             if (tid == 0) {
                 const int64_t a = S.appv;
-                decode(a >> 3, k, c.n, c.B, S.it_v[0]);
+                const u64 vw = (u64)S.vbase;
+                if (vw != kNoVerts) {
+                    S.it_v[0][0] = (int)(vw & 0xffffu);
+                    S.it_v[0][1] = (int)((vw >> 16) & 0xffffu);
+                } else {
+                    decode(a >> 3, k, c.n, c.B, S.it_v[0]);
+                }
                 S.nit = 1;
                 S.it_coef[0] = 1u;
                 S.it_diam[0] = piv.diam;
