@@ -337,13 +337,24 @@ rips_status rips_get_shortcuts(int32_t *flags);
  *   RIPS_R_AUTO (default): R_j is kept when it is cheaper to add than those
  *     coboundaries are to recompute (and fits the working column's LDS part);
  *   RIPS_R_DISCARD: never kept;
- *   RIPS_R_STORE: kept whenever it fits the working column's LDS part.
+ *   RIPS_R_STORE: kept whenever it fits the working column's LDS part;
+ *   RIPS_R_EXPLICIT: explicit matrix reduction (the "explicit" column of
+ *     Table 3): before each dimension is reduced, the coboundary columns of
+ *     all its columns (after clearing) are built in device memory, and every
+ *     reduced column is stored and used for the additions. The apparent and
+ *     emergent shortcuts do not apply (rips_set_shortcuts' clearing bit
+ *     does). A coboundary column of more than 4096 cofacets <= threshold
+ *     returns RIPS_E_CAPACITY. stats: emergent, apparent_col and
+ *     apparent_pivot are 0; entries_stored counts the entries of the
+ *     coboundary matrix and of the stored reduced columns.
+ *     rips_barcode_cocycles keeps the implicit reduction in this mode.
  * The bars are the same in every mode. Other values: RIPS_E_INVALID_ARG.
  * The batched path always uses RIPS_R_AUTO.
  */
 #define RIPS_R_AUTO 0
 #define RIPS_R_DISCARD 1
 #define RIPS_R_STORE 2
+#define RIPS_R_EXPLICIT 3
 rips_status rips_set_reduced_storage(int32_t mode);
 rips_status rips_get_reduced_storage(int32_t *mode);
 

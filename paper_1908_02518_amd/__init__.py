@@ -575,12 +575,16 @@ def set_shortcuts(flags: int = SHORTCUT_APPARENT | SHORTCUT_EMERGENT | SHORTCUT_
 R_AUTO = 0
 R_DISCARD = 1
 R_STORE = 2
+R_EXPLICIT = 3
 
 
 def set_reduced_storage(mode: int = R_AUTO):
     """When the single-cloud path keeps R_j beside V_j (Table 3's "storing R"
     and "discarding R" rows): R_AUTO when cheaper to add, R_DISCARD never,
-    R_STORE whenever it fits. The bars are the same in every mode."""
+    R_STORE whenever it fits; R_EXPLICIT: explicit matrix reduction (the
+    "explicit" column: every coboundary column built before the reduction,
+    every reduced column stored and added). The bars are the same in every
+    mode."""
     _check(_lib.rips_set_reduced_storage(int(mode)))
 
 

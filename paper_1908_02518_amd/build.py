@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librips.so")
-SOURCES = ["rips_kernels.hip", "rips_batched.hip", "rips_homology.hip", "rips_api.hip"]
+SOURCES = ["rips_kernels.hip", "rips_batched.hip", "rips_homology.hip", "rips_explicit.hip", "rips_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

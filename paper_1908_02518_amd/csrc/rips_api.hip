@@ -213,6 +213,19 @@ enum BufId {
     B_HOM_PERM,
     B_HOM_PERM2,
     B_HOM_TAPP,
+    // explicit matrix reduction
+    B_EXP_CNT,
+    B_EXP_OFF,
+    B_EXP_OUT,
+    B_EXP_IDX,
+    B_EXP_DIA,
+    B_EXP_COEF,
+    B_EXP_WI0,
+    B_EXP_WI1,
+    B_EXP_WD0,
+    B_EXP_WD1,
+    B_EXP_WC0,
+    B_EXP_WC1,
     B_NUM
 };
 
@@ -228,6 +241,7 @@ struct DevCtx {
     int64_t hint_vw = 0;
     int64_t hint_log = 0;
     int64_t hint_cob = 0;
+    int64_t hint_exp_w = 0;
     int lds_per_block = 0;
     int num_cus = 0;
     int reduce_groups = 0; // workgroups of the single-cloud reduction: 0 = one per CU
@@ -450,7 +464,8 @@ enum ProfId {
     P_SORT1 = P_FILTER1 + kMaxDim,
     P_REDUCE1 = P_SORT1 + kMaxDim,
     P_COB1 = P_REDUCE1 + kMaxDim,
-    P_EMIT = P_COB1 + kMaxDim,
+    P_EXP_BUILD1 = P_COB1 + kMaxDim, // explicit coboundary matrix of dimension k
+    P_EMIT = P_EXP_BUILD1 + kMaxDim,
     P_BATCHED,
     P_NUM
 };
@@ -472,6 +487,7 @@ const char *prof_name(int i) {
             snprintf(names[P_SORT1 + k - 1], 32, "sort_d%d", k);
             snprintf(names[P_REDUCE1 + k - 1], 32, "reduce_d%d", k);
             snprintf(names[P_COB1 + k - 1], 32, "cob_lists_d%d", k);
+            snprintf(names[P_EXP_BUILD1 + k - 1], 32, "explicit_build_d%d", k);
         }
         snprintf(names[P_EMIT], 32, "emit");
         snprintf(names[P_BATCHED], 32, "batched_graph");
@@ -676,6 +692,114 @@ int filter_group_size_for(const Prepared &P, int k) {
     return P.ctx.n <= 128 ? 8 : 32;
 }
 
+// Explicit matrix reduction of dimension k (the first column of Table 3):
+// the coboundary matrix of the S columns is built in HBM, then reduced by
+// adding stored reduced columns. Fills bars (column order), o.count[k] and
+// o.stats[k]; ph receives the pivots (clearing of dimension k+1).
+rips_status reduce_explicit(DevCtx &C, const Prepared &P, int k, uint32_t p, const Columns &cols, int64_t S,
+                            PivotHash ph, uint32_t phcap, const u32 *prev_bits, PivotHash prev, BarBuf bars,
+                            hipStream_t st, RunOut &o) {
+    void *q;
+    HIP_TRY(C.ensure(B_EXP_CNT, (size_t)(S + 1) * 8, &q));
+    int64_t *cnt = as<int64_t>(q);
+    HIP_TRY(C.ensure(B_EXP_OFF, (size_t)(S + 1) * 8, &q));
+    int64_t *off = as<int64_t>(q);
+    HIP_TRY(C.ensure(B_EXP_OUT, sizeof(ExpOut), &q));
+    ExpOut *hout = as<ExpOut>(q);
+    HIP_TRY(hipMemsetAsync(hout, 0, sizeof(ExpOut), st));
+    int64_t nnz = 0;
+    ExpOut h{};
+    {
+        PROF(P_EXP_BUILD1 + k - 1);
+        launch_exp_count(P.ctx, k, cols.idx, cols.diam, S, cnt, &hout->longest, st);
+        launch_exp_offsets(cnt, S, off, st);
+        HIP_TRY(hipMemcpyAsync(&nnz, off + S, 8, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&h, hout, sizeof(h), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (h.longest > (unsigned long long)kExpBuildCap)
+        return fail(RIPS_E_CAPACITY, "a column of the explicit coboundary matrix exceeds " +
+                                         std::to_string(kExpBuildCap) + " entries");
+    ExpJob J{};
+    J.k = k;
+    J.p = p;
+    J.inv = P.inv;
+    J.cidx = cols.idx;
+    J.cdia = cols.diam;
+    J.ncols = S;
+    HIP_TRY(C.ensure(B_EXP_IDX, (size_t)std::max<int64_t>(nnz, 1) * 8, &q));
+    J.D.idx = as<int64_t>(q);
+    HIP_TRY(C.ensure(B_EXP_DIA, (size_t)std::max<int64_t>(nnz, 1) * 4, &q));
+    J.D.diam = as<float>(q);
+    HIP_TRY(C.ensure(B_EXP_COEF, (size_t)std::max<int64_t>(nnz, 1) * 4, &q));
+    J.D.coef = as<u32>(q);
+    J.D.off = off;
+    {
+        PROF(P_EXP_BUILD1 + k - 1);
+        launch_exp_fill(P.ctx, k, p, cols.idx, cols.diam, S, off, J.D, st);
+    }
+    J.piv = ph;
+    J.prev = prev;
+    J.prev_bits = prev_bits;
+    J.clearing = (C.shortcuts & kShortClearing) ? 1 : 0;
+    HIP_TRY(C.ensure(B_V_ROFF, (size_t)std::max<int64_t>(S, 1) * 8, &q));
+    J.roff = as<int64_t>(q);
+    HIP_TRY(C.ensure(B_V_RLEN, (size_t)std::max<int64_t>(S, 1) * 4, &q));
+    J.rlen = as<int>(q);
+    J.bars = bars;
+    J.out = hout;
+    int64_t pcap = std::max<int64_t>(C.hint_v, nnz + 4096);
+    int64_t wcap = std::max<int64_t>(C.hint_exp_w, 4 * (int64_t)h.longest + 4096);
+    for (int attempt = 0;; ++attempt) {
+        if (attempt > 12) return fail(RIPS_E_CAPACITY, "explicit reduction scratch kept overflowing");
+        HIP_TRY(C.ensure(B_V_IDX, (size_t)pcap * 8, &q));
+        J.pidx = as<int64_t>(q);
+        HIP_TRY(C.ensure(B_V_DIAM, (size_t)pcap * 4, &q));
+        J.pdia = as<float>(q);
+        HIP_TRY(C.ensure(B_V_COEF, (size_t)pcap * 4, &q));
+        J.pcoef = as<u32>(q);
+        J.pcap = pcap;
+        for (int b = 0; b < 2; ++b) {
+            HIP_TRY(C.ensure(B_EXP_WI0 + b, (size_t)wcap * 8, &q));
+            J.wi[b] = as<int64_t>(q);
+            HIP_TRY(C.ensure(B_EXP_WD0 + b, (size_t)wcap * 4, &q));
+            J.wd[b] = as<float>(q);
+            HIP_TRY(C.ensure(B_EXP_WC0 + b, (size_t)wcap * 4, &q));
+            J.wc[b] = as<u32>(q);
+        }
+        J.wcap = (int)wcap;
+        launch_fill_i64(ph.keys, phcap, kEmpty, st);
+        {
+            PROF(P_REDUCE1 + k - 1);
+            launch_exp_reduce(J, st);
+        }
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(&h, hout, sizeof(h), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (h.status == kExpPool) {
+            pcap *= 4;
+        } else if (h.status == kExpFull && wcap < (1ll << 28)) {
+            wcap = std::min<int64_t>(wcap * 4, 1ll << 28);
+        } else {
+            break;
+        }
+    }
+    if (h.status == kExpFull) return fail(RIPS_E_CAPACITY, "a working column of the explicit reduction exceeded 2^28 entries");
+    if (h.status == kExpBound) return fail(RIPS_E_CAPACITY, "reduction: a column exceeded the bound of 2^24 additions");
+    if (h.status != kExpOk) return fail(RIPS_E_HIP, "explicit reduction: internal consistency check failed");
+    if (h.stored > C.hint_v) C.hint_v = h.stored;
+    if (wcap > C.hint_exp_w) C.hint_exp_w = wcap;
+    o.count[k] = h.bars;
+    o.stats[k].emergent = 0;
+    o.stats[k].reduced = h.reduced;
+    o.stats[k].additions = h.additions;
+    o.stats[k].bars_nonzero = h.bars - h.essential;
+    o.stats[k].essential = h.essential;
+    o.stats[k].entries_added = h.added;
+    o.stats[k].entries_stored = nnz + h.stored;
+    return RIPS_OK;
+}
+
 rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, float t, uint32_t p,
                        hipStream_t st, RunOut &o) {
     memset(&o, 0, sizeof(o));
@@ -792,7 +916,10 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         // zero apparent pairs (rho, tau) found by the filter, for the
         // reduction's pivot test; twice the candidates, so inserts never fail
         // (none without the apparent shortcut: those pairs are columns then)
-        const bool apparent = (C.shortcuts & kShortApparent) != 0;
+        // (the explicit matrix has no use for them: its columns are all built)
+        // (cocycle requests keep the implicit reduction, which stores V_j)
+        const bool explicit_matrix = C.rstore == kRStoreExplicit && C.cocycle_dim < 0;
+        const bool apparent = (C.shortcuts & kShortApparent) != 0 && !explicit_matrix;
         PairHash app{};
         int64_t *ckey_w = nullptr;
         float *cdia_w = nullptr;
@@ -886,6 +1013,15 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         HIP_TRY(C.ensure(B_PH_VALS0 + slot, (size_t)phcap * 4, &q));
         ph.vals = as<int32_t>(q);
         ph.mask = phcap - 1;
+        if (explicit_matrix) {
+            if ((rs = ensure_bars(k, S))) return rs;
+            if ((rs = reduce_explicit(C, P, k, p, cols, S, ph, phcap, W.bits, ph_prev, bars[k], st, o)))
+                return rs;
+            ph_prev = ph;
+            prev_list = cand;
+            prev_count = ncand;
+            continue;
+        }
         VStore V;
         HIP_TRY(C.ensure(B_V_OFF, (size_t)S * 8, &q));
         V.off = as<int64_t>(q);
@@ -2180,13 +2316,16 @@ rips_status rips_set_shortcuts(int32_t flags) {
 
 rips_status rips_set_reduced_storage(int32_t mode) {
     g_err.clear();
-    if (mode != RIPS_R_AUTO && mode != RIPS_R_DISCARD && mode != RIPS_R_STORE)
+    if (mode != RIPS_R_AUTO && mode != RIPS_R_DISCARD && mode != RIPS_R_STORE && mode != RIPS_R_EXPLICIT)
         return fail(RIPS_E_INVALID_ARG, "unknown storage mode");
     DevCtx *C;
     rips_status rs = get_ctx(&C);
     if (rs) return rs;
     std::lock_guard<std::mutex> lk(C->mu);
-    C->rstore = mode == RIPS_R_DISCARD ? kRStoreNever : (mode == RIPS_R_STORE ? kRStoreAlways : kRStoreAuto);
+    C->rstore = mode == RIPS_R_DISCARD    ? kRStoreNever
+                : mode == RIPS_R_STORE    ? kRStoreAlways
+                : mode == RIPS_R_EXPLICIT ? kRStoreExplicit
+                                          : kRStoreAuto;
     return RIPS_OK;
 }
 
@@ -2220,7 +2359,10 @@ rips_status rips_get_reduced_storage(int32_t *mode) {
     rips_status rs = get_ctx(&C);
     if (rs) return rs;
     std::lock_guard<std::mutex> lk(C->mu);
-    *mode = C->rstore == kRStoreNever ? RIPS_R_DISCARD : (C->rstore == kRStoreAlways ? RIPS_R_STORE : RIPS_R_AUTO);
+    *mode = C->rstore == kRStoreNever      ? RIPS_R_DISCARD
+            : C->rstore == kRStoreAlways   ? RIPS_R_STORE
+            : C->rstore == kRStoreExplicit ? RIPS_R_EXPLICIT
+                                           : RIPS_R_AUTO;
     return RIPS_OK;
 }
 

@@ -184,6 +184,67 @@ void launch_hom_vertices(int n, PivotHash piv, BarBuf ess, HomOut *o, hipStream_
 void launch_hom_iota(int *a, int64_t n, hipStream_t st);
 void launch_hom_gather(BarBuf in, const int *perm, int64_t n, BarBuf out, hipStream_t st);
 
+// ---- explicit matrix reduction (rips_explicit.hip)
+constexpr int kExpThreads = 256;
+constexpr int kExpBuildCap = 4096;        // cofacets <= t of one column
+constexpr int64_t kExpMaxAdds = 1 << 24;  // additions per column
+constexpr int kExpOk = 0, kExpFull = 1, kExpPool = 2, kExpTable = 3, kExpBound = 4;
+
+// The coboundary matrix of one dimension's columns: column c holds entries
+// [off[c], off[c+1]), oldest first.
+struct ExpMatrix {
+    const int64_t *off;
+    int64_t *idx;
+    float *diam;
+    u32 *coef;
+};
+
+struct ExpOut {
+    int status; // kExpOk, or what stopped the reduction
+    int pad;
+    long long bars;      // bars of dimension k (finite and essential)
+    long long nonzero;   // columns left nonzero
+    long long essential; // essential bars
+    long long reduced;   // columns with at least one addition
+    long long additions; // column additions
+    long long added;     // entries of the added columns
+    long long stored;    // entries of the stored reduced columns
+    unsigned long long longest; // longest coboundary column (build)
+};
+
+struct ExpJob {
+    int k;               // columns are k-simplices
+    u32 p;
+    const u32 *inv;
+    const int64_t *cidx; // the columns, younger first
+    const float *cdia;
+    int64_t ncols;
+    ExpMatrix D;
+    PivotHash piv;       // pivot -> column position (final)
+    PivotHash prev;      // pivots of dimension k-1 (k >= 2)
+    const u32 *prev_bits; // forest edges (k = 1)
+    int clearing;        // columns that are pivots below were removed
+    int64_t *roff;       // per column: its stored R in the pool
+    int *rlen;
+    int64_t *pidx;       // the pool, oldest first within a column
+    float *pdia;
+    u32 *pcoef;
+    int64_t pcap;
+    int64_t *wi[2];      // working column and merge target (global)
+    float *wd[2];
+    u32 *wc[2];
+    int wcap;
+    BarBuf bars;
+    ExpOut *out;
+};
+
+void launch_exp_count(const Ctx<DistFull> &c, int k, const int64_t *cidx, const float *cdia, int64_t S,
+                      int64_t *cnt, unsigned long long *longest, hipStream_t st);
+void launch_exp_offsets(const int64_t *cnt, int64_t S, int64_t *off, hipStream_t st);
+void launch_exp_fill(const Ctx<DistFull> &c, int k, u32 p, const int64_t *cidx, const float *cdia, int64_t S,
+                     const int64_t *off, ExpMatrix D, hipStream_t st);
+void launch_exp_reduce(const ExpJob &J, hipStream_t st);
+
 constexpr int kRedThreads = 256;
 
 } // namespace rips

@@ -151,6 +151,8 @@ constexpr int kShortClearing = 4;
 // than V_j's coboundaries are to recompute, never, or whenever it has no far
 // part
 constexpr int kRStoreAuto = 0, kRStoreNever = 1, kRStoreAlways = 2;
+// (the single-cloud path's explicit matrix reduction: no implicit reduction runs)
+constexpr int kRStoreExplicit = 3;
 
 // Additions one column may take before the reduction reports an error: every
 // addition moves the pivot to a strictly younger row, so the loop ends; the
