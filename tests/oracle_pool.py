@@ -37,11 +37,15 @@ class OraclePool:
     that the long ones do not come last) and hands the results out by
     cloud number; use as a context manager."""
 
-    def __init__(self, clouds, max_dim: int, threshold: float = float("inf"), p: int = 2):
-        self._pool = mp.get_context("spawn").Pool(workers())
-        order = sorted(range(len(clouds)), key=lambda b: -int(np.asarray(clouds[b]).shape[0]))
-        self._async = {b: self._pool.apply_async(_oracle_bars, ((clouds[b], max_dim, threshold, p),))
-                       for b in order}
+    def __init__(self, clouds, max_dim: int = 1, threshold: float = float("inf"), p: int = 2,
+                 jobs=None):
+        """clouds with one (max_dim, threshold, p) for all, or jobs: a list of
+        (points, max_dim, threshold, p), one per result."""
+        if jobs is None:
+            jobs = [(c, max_dim, threshold, p) for c in clouds]
+        self._pool = mp.get_context("spawn").Pool(min(workers(), max(1, len(jobs))))
+        order = sorted(range(len(jobs)), key=lambda b: -int(np.asarray(jobs[b][0]).shape[0]))
+        self._async = {b: self._pool.apply_async(_oracle_bars, (jobs[b],)) for b in order}
 
     def get(self, b: int, timeout: float = 900.0):
         return self._async[b].get(timeout)

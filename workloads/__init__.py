@@ -26,6 +26,7 @@ __all__ = [
     "rng",
     "sphere",
     "so3",
+    "orthogonal",
     "clifford_torus",
     "mixture_cloud",
     "mixture_batch",
@@ -79,6 +80,17 @@ def so3(n: int, seed: int) -> np.ndarray:
     q = g.standard_normal((n, 4))
     q /= np.linalg.norm(q, axis=1, keepdims=True)
     return _f32(_quat_to_rot(q).reshape(n, 9))
+
+
+def orthogonal(n: int, seed: int) -> np.ndarray:
+    """n Haar-random orthogonal 3x3 matrices (the group O(3): a Haar rotation
+    times an independent sign, so half have determinant -1), each flattened
+    row-major to R^9. The two components lie at Frobenius distance >= 2."""
+    g = rng(seed)
+    q = g.standard_normal((n, 4))
+    q /= np.linalg.norm(q, axis=1, keepdims=True)
+    sign = np.where(g.random(n) < 0.5, -1.0, 1.0)
+    return _f32((_quat_to_rot(q) * sign[:, None, None]).reshape(n, 9))
 
 
 def clifford_torus(n: int, sigma: float, seed: int) -> np.ndarray:
@@ -175,11 +187,13 @@ def integer_lattice(n: int, m: int, seed: int, side: int = 4) -> np.ndarray:
 
 # name -> (generator thunk, max_dim, threshold (inf = none), p)
 def config(cfg_id: int):
-    """The five benchmark workloads (1-5), and two at paper scale: 6, the shape
+    """The five benchmark workloads (1-5), and four at paper scale: 6, the shape
     of the paper's o3 run on 1024 orthogonal matrices (threshold 1.8, homology
-    up to dimension 3), and 7, a 10,000-point Clifford torus (threshold 0.25,
-    up to dimension 2) on the way to the paper's 50,000-point torus. Returns a
-    dict describing one of them."""
+    up to dimension 3); 7, a 10,000-point Clifford torus (threshold 0.25, up
+    to dimension 2); 8, the o3 run at the paper's full size, 4096 matrices
+    (threshold 1.4, up to dimension 3); 9, the paper's torus4 run, 50,000
+    points on the Clifford torus (threshold 0.15, up to dimension 2).
+    Returns a dict describing one of them."""
     inf = float("inf")
     if cfg_id == 1:
         return dict(name="sphere-100", clouds=[sphere(100, SEED_BASE + 1)], max_dim=1,
@@ -197,13 +211,19 @@ def config(cfg_id: int):
         return dict(name="circles-64x400", clouds=circle_batch(64, 5), max_dim=1,
                     threshold=inf, p=2)
     if cfg_id == 6:
-        return dict(name="o3-1024-t1.8", clouds=[so3(1024, SEED_BASE + 6)], max_dim=3,
+        return dict(name="o3-1024-t1.8", clouds=[orthogonal(1024, SEED_BASE + 6)], max_dim=3,
                     threshold=1.8, p=2)
     if cfg_id == 7:
         return dict(name="torus4-10000-t0.25", clouds=[clifford_torus(10000, 0.02, SEED_BASE + 7)],
                     max_dim=2, threshold=0.25, p=2)
+    if cfg_id == 8:
+        return dict(name="o3-4096-t1.4", clouds=[orthogonal(4096, SEED_BASE + 8)], max_dim=3,
+                    threshold=1.4, p=2)
+    if cfg_id == 9:
+        return dict(name="torus4-50000-t0.15", clouds=[clifford_torus(50000, 0.0, SEED_BASE + 9)],
+                    max_dim=2, threshold=0.15, p=2)
     raise ValueError(cfg_id)
 
 
 CONFIGS = (1, 2, 3, 4, 5)
-PAPER_SCALE = (6, 7)
+PAPER_SCALE = (6, 7, 8, 9)
