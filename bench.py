@@ -27,12 +27,15 @@ avoids building) divided by the time per step. Also reported:
                     (dimension 2): candidates, survivors and neighbour lists
                     in bytes over its launch time, with the vector-ALU issue
                     rate beside it
-  shortcuts         the shortcut ablation of the paper's Table 3 on so3-1000
+  shortcuts         the ablation of the paper's Table 3 on so3-1000: explicit
+                    matrix, implicit storing / discarding R, emergent and
+                    apparent shortcuts, with time and entries held
   cocycles          representative cocycles of dimension 1 on so3-1000
   homology          the homology variant on so3-1000 in dims 0-1
-  paper_scale       one barcode of the o3 shape at 1024 points, t = 1.8,
-                    dims 0-3, against the CPU implementation of the paper's
-                    algorithm
+  paper_scale       the paper's o3 runs (1024 matrices, t = 1.8, and 4096,
+                    t = 1.4, dims 0-3) and its torus4 run (50,000 points,
+                    t = 0.15, dims 0-2), one barcode each; the 1024 one also
+                    on the CPU implementation of the paper's algorithm
   cpu_baseline      the CPU oracle on this host (a bounded sample of the
                     headline batch: its first clouds), single thread
   cpu_paper_algorithm  the single-threaded CPU implementation of the paper's
@@ -300,13 +303,13 @@ def main() -> int:
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the legs of the other four workloads")
     ap.add_argument("--no-shortcuts", action="store_true",
-                    help="skip the shortcut ablation leg (Table 3 of the paper, on so3-1000)")
+                    help="skip the ablation leg (Table 3 of the paper, on so3-1000)")
     ap.add_argument("--no-cocycles", action="store_true",
                     help="skip the representative-cocycle leg (so3-1000, dimension 1)")
     ap.add_argument("--no-homology", action="store_true",
                     help="skip the homology-variant leg (so3-1000, dims 0-1, about 15 s)")
     ap.add_argument("--no-paper-scale", action="store_true",
-                    help="skip the paper-scale o3-1024 (t = 1.8, dims 0-3) leg")
+                    help="skip the paper-scale legs (o3 1024 and 4096, torus4 50,000)")
     ap.add_argument("--pmc-run", action="store_true",
                     help="counter runs: a few steps of the headline batch and of so3-1000, "
                          "plus one plain copy of known size")
@@ -518,16 +521,23 @@ def main() -> int:
 
     shortcuts = None
     if not args.no_shortcuts:
-        # the ablation of the paper's Table 3 on so3-1000, every row with
-        # clearing: no other shortcut ("discarded"), the emergent shortcut,
-        # both ("apparent"); the apparent one alone; and all but clearing
+        # the ablation of the paper's Table 3 on so3-1000, its five columns in
+        # order (every one with clearing and cohomology): explicit matrix
+        # reduction, implicit reduction storing R, discarding R, the emergent
+        # shortcut, the apparent one; then this library's default (R kept
+        # where cheaper to add) and all shortcuts but clearing. "memory" is
+        # the entries the reduction holds (coboundary matrix and stored
+        # columns), 16 bytes each.
         C, E, A = rips.SHORTCUT_CLEARING, rips.SHORTCUT_EMERGENT, rips.SHORTCUT_APPARENT
-        names = {C: "clearing", C | E: "clearing + emergent",
-                 C | E | A: "clearing + emergent + apparent (default)",
-                 C | A: "clearing + apparent", E | A: "emergent + apparent, no clearing"}
+        rows = [("explicit", rips.R_EXPLICIT, C), ("implicit, storing R", rips.R_STORE, C),
+                ("discarding R", rips.R_DISCARD, C), ("emergent", rips.R_DISCARD, C | E),
+                ("apparent", rips.R_DISCARD, C | E | A),
+                ("default (R kept where cheaper)", rips.R_AUTO, C | E | A),
+                ("no clearing", rips.R_AUTO, E | A)]
         shortcuts = []
         try:
-            for flags in names:
+            for name, mode, flags in rows:
+                rips.set_reduced_storage(mode)
                 rips.set_shortcuts(flags)
                 rips.barcode_device(x2t, **kw2)  # warm-up
                 torch.cuda.synchronize()
@@ -538,16 +548,20 @@ def main() -> int:
                     torch.cuda.synchronize()
                     tt.append(time.perf_counter() - c0)
                 st_s = inf_s["stats"]
+                stored = sum(st_s[k]["entries_stored"] for k in range(1, 3))
                 shortcuts.append({
-                    "shortcuts": names[flags],
+                    "column": name,
                     "ms_per_barcode": round(1e3 * sorted(tt)[1], 3),
                     "columns": [st_s[k]["columns"] for k in range(1, 3)],
                     "emergent": [st_s[k]["emergent"] for k in range(1, 3)],
                     "additions": [st_s[k]["additions"] for k in range(1, 3)],
+                    "entries_held": [st_s[k]["entries_stored"] for k in range(1, 3)],
+                    "memory_mb": round(16 * stored / 1e6, 2),
                 })
-                log(f"shortcuts {names[flags]}: {1e3 * sorted(tt)[1]:.1f} ms")
+                log(f"table 3 {name}: {1e3 * sorted(tt)[1]:.1f} ms, {16 * stored / 1e6:.1f} MB")
         finally:
             rips.set_shortcuts()
+            rips.set_reduced_storage()
 
     cocycles = None
     if not args.no_cocycles:
@@ -595,41 +609,58 @@ def main() -> int:
 
     paper_scale = None
     if not args.no_paper_scale:
-        c6 = workloads.config(6)
-        x6 = c6["clouds"][0]
-        x6t = torch.from_numpy(x6).to(dev)
-        k6 = dict(max_dim=c6["max_dim"], threshold=c6["threshold"], p=c6["p"])
-        counts6 = rips.simplex_counts(x6t, c6["max_dim"] + 1, threshold=c6["threshold"])
-        bars6, _ = rips.barcode_device(x6t, **k6)  # warm-up: scratch sizes
-        torch.cuda.synchronize()
-        ts6 = []
-        for _ in range(3):
-            c0 = time.perf_counter()
-            bars6, _ = rips.barcode_device(x6t, **k6)
+        # the paper's o3 and torus4 runs (Tables 1 and 2): o3 on 1024 and on
+        # 4096 orthogonal matrices, torus4 on 50,000 points; one barcode per
+        # call, input resident in HBM, median of 3 after a warm-up call
+        ripser_s = {6: 2.1, 8: 43.1, 9: 117.0}
+        paper_scale = {}
+        bars6 = None
+        for cfg in (6, 8, 9):
+            cp = workloads.config(cfg)
+            xp = cp["clouds"][0]
+            xpt = torch.from_numpy(xp).to(dev)
+            kp = dict(max_dim=cp["max_dim"], threshold=cp["threshold"], p=cp["p"])
+            counts_p = rips.simplex_counts(xpt, cp["max_dim"] + 1, threshold=cp["threshold"])
+            bars_p, info_p = rips.barcode_device(xpt, **kp)  # warm-up: scratch sizes
             torch.cuda.synchronize()
-            ts6.append(time.perf_counter() - c0)
-        t6 = sorted(ts6)[1]
-        log(f"paper scale {c6['name']}: {t6:.3f} s per barcode (median of 3)")
-        paper_scale = {
-            "workload": "o3-1024-t1.8: 1024 Haar SO(3) rotations in R^9, float32, threshold 1.8, "
-                        "dims 0-3, Z/2 (the shape of the paper's o3 1024 run)",
-            "simplex_counts": counts6,
-            "seconds_per_barcode": round(t6, 4),
-            "simplices_per_s": round(sum(counts6) / t6, 1),
-            "context": "the paper reports 2.1 s for Ripser on its own o3 1024 data (t = 1.8, "
-                       "4 GHz Core i7): other data, other machine, not a target",
-        }
+            tsp = []
+            for _ in range(3):
+                c0 = time.perf_counter()
+                bars_p, info_p = rips.barcode_device(xpt, **kp)
+                torch.cuda.synchronize()
+                tsp.append(time.perf_counter() - c0)
+            tp = sorted(tsp)[1]
+            if cfg == 6:
+                bars6 = bars_p
+            log(f"paper scale {cp['name']}: {tp:.3f} s per barcode (median of 3)")
+            paper_scale[cp["name"]] = {
+                "points": int(xp.shape[0]),
+                "threshold": cp["threshold"],
+                "dims": f"0-{cp['max_dim']}",
+                "simplex_counts": counts_p,
+                "seconds_per_barcode": round(tp, 4),
+                "simplices_per_s": round(sum(counts_p) / tp, 1),
+                "bars": [int(bars_p[d][0].shape[0]) for d in range(cp["max_dim"] + 1)],
+                "context": f"the paper reports {ripser_s[cfg]} s for Ripser on its own data of "
+                           "this shape (4 GHz Core i7): other data, other machine, not a target",
+            }
+            del xpt
+            torch.cuda.empty_cache()
         if not args.no_cpu_baseline:
             import cpu_baseline
             import oracle
+            c6 = workloads.config(6)
+            x6 = c6["clouds"][0]
+            k6 = dict(max_dim=c6["max_dim"], threshold=c6["threshold"], p=c6["p"])
             cpu_baseline.build(force=False)
             dl6 = oracle.distances(x6)  # not timed
             c0 = time.perf_counter()
             cb6 = cpu_baseline.barcode(dl6, x6.shape[0], **k6)
             tc6 = time.perf_counter() - c0
             log(f"paper scale, cpu paper algorithm: {tc6:.2f} s")
-            paper_scale["cpu_paper_algorithm_seconds"] = round(tc6, 3)
-            paper_scale["bars_equal_cpu_paper_algorithm"] = bool(all(
+            e6 = paper_scale[c6["name"]]
+            e6["cpu_paper_algorithm_seconds"] = round(tc6, 3)
+            e6["bars_equal_cpu_paper_algorithm"] = bool(all(
                 np.array_equal(getattr(cb6.bars[d], f), g.cpu().numpy())
                 for d in range(c6["max_dim"] + 1)
                 for f, g in zip(("birth", "death", "birth_simplex", "death_simplex"), bars6[d])))

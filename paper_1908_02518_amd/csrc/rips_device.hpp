@@ -268,6 +268,21 @@ __device__ __forceinline__ void st(LDS T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Hand-over point between the lanes of one wave, for code that one wave
+// runs alone (no workgroup barrier): values that other lanes stored to
+// shared or global memory before it are read after it. Without it the
+// compiler, reasoning about each lane on its own, may serve a later load
+// from a value loaded earlier (a lane that did not store sees no reason to
+// load again) or move the access across the other lanes' stores. A
+// wavefront-scope fence is such a point for the compiler and costs no
+// instruction (a wave's memory accesses execute in order); the wave barrier
+// keeps the scheduler from moving work across it.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Lanes of this lane's group of G in a wave-wide mask.
 template <int G>
 __device__ __forceinline__ u64 group_mask() {
     if (G >= 64) return ~0ull;
@@ -275,86 +290,8 @@ __device__ __forceinline__ u64 group_mask() {
     return ((1ull << (G & 63)) - 1) << base;
 }
 
-// Largest candidate vertex j > jmin, j not in v[0..k], with d(j, v_m) <= bound
-// for every vertex v_m; -1 if none. Candidates are scanned in decreasing
-// order, G at a time, which is decreasing CNS order of the cofacets
-// sigma u {j}; the scan stops at the first chunk holding a hit (the
-// early exit of the apparent-pair shortcut). Dense: all vertices; sparse:
-// the neighbour list of the vertex of v with the fewest neighbours.
-// Kept out of line: it ends lane groups early from inside a loop with a
-// group ballot, and the filter built with it inlined returned wrong columns.
-template <int G, class Dist>
-__device__ __attribute__((noinline)) int group_find_max(const Ctx<Dist> &c, const int *v, int k, float bound, int jmin) {
-    const int lg = lane_id() & (G - 1);
-    const u64 gm = group_mask<G>();
-    if (c.nb.off == nullptr) {
-        for (int top = c.n - 1; top > jmin; top -= G) {
-            const int j = top - lg;
-            bool ok = j > jmin;
-            if (ok)
-                for (int m = 0; m <= k; ++m) ok = ok && (j != v[m]);
-            if (ok)
-                for (int m = 0; m <= k; ++m) ok = ok && (c.d(v[m], j) <= bound);
-            const u64 mask = __ballot(ok) & gm;
-            if (mask) return __shfl(j, __ffsll((unsigned long long)mask) - 1, kWave);
-        }
-        return -1;
-    }
-    int u = v[0];
-    int du = c.nb.off[u + 1] - c.nb.off[u];
-    for (int m = 1; m <= k; ++m) {
-        const int dm = c.nb.off[v[m] + 1] - c.nb.off[v[m]];
-        if (dm < du) {
-            du = dm;
-            u = v[m];
-        }
-    }
-    const int *L = c.nb.idx + c.nb.off[u];
-    for (int top = du - 1; top >= 0; top -= G) {
-        if (L[top] <= jmin) break; // the rest of the list is smaller still
-        const int q = top - lg;
-        const int j = q >= 0 ? L[q] : -1;
-        bool ok = j > jmin;
-        if (ok)
-            for (int m = 0; m <= k; ++m) ok = ok && (j != v[m]);
-        if (ok)
-            for (int m = 0; m <= k; ++m) ok = ok && (c.d(v[m], j) <= bound);
-        const u64 mask = __ballot(ok) & gm;
-        if (mask) return __shfl(j, __ffsll((unsigned long long)mask) - 1, kWave);
-    }
-    return -1;
-}
-
-// (sigma, sigma u {j}) is a zero apparent pair iff sigma u {j} is the
-// lexicographically largest same-diameter cofacet of sigma (j = the result of
-// group_find_max with bound = diam sigma) and sigma is its lexicographically
-// smallest same-diameter facet (Proposition on zero apparent pairs).
-template <class Dist>
-__device__ __forceinline__ bool is_zero_apparent_cofacet(const Ctx<Dist> &c, const int *v, int k,
-                                                        float dm, int j) {
-    int tv[kMaxVerts];
-    const int pos = insert_vertex(v, k, j, tv);
-    return zero_pivot_facet(c, tv, k + 1, dm) == pos;
-}
-
-// Does the k-simplex v (diameter dm) lie in a zero apparent pair (rho, v)
-// with rho a facet? rho is v's zero pivot facet; the pair is apparent iff no
-// vertex j above the removed vertex w extends rho at the same diameter, i.e.
-// v is rho's lexicographically largest same-diameter cofacet. Returns the
-// position of w in v, or -1.
-template <int G, class Dist>
-__device__ __attribute__((noinline)) int zero_apparent_facet(const Ctx<Dist> &c, const int *v, int k, float dm) {
-    if (k == 0) return -1;
-    const int m = zero_pivot_facet(c, v, k, dm);
-    if (m < 0) return -1;
-    int rv[kMaxVerts];
-    remove_vertex(v, k, m, rv);
-    const int j = group_find_max<G>(c, rv, k - 1, dm, v[m]);
-    return j < 0 ? m : -1;
-}
-
 // ---------------------------------------------------------------------------
-// The same tests with the dimension K fixed at compile time, for the
+// The zero apparent pair tests with the dimension K fixed at compile time, for the
 // enumeration / apparent-pair pass: every tuple is indexed by constants, so
 // it stays in registers. The scans are called by every lane of the wave at
 // once; their loops run until every group of the wave is done, so no lane
@@ -418,9 +355,12 @@ __device__ __forceinline__ int zero_pivot_facet_k(const Ctx<Dist> &c, const int 
 }
 
 // Largest vertex j > jmin, j not in the K-simplex v, with d(j, v_m) <= bound
-// for every m; -1 if none, or if the group is not active. The candidates of
-// group_find_max, in the same decreasing order and G at a time; all lanes of
-// a group get the same result.
+// for every m; -1 if none, or if the group is not active. Candidates are
+// scanned in decreasing order (decreasing CNS order of the cofacets
+// v u {j}), G at a time, and the scan of a group stops at its first chunk
+// with a hit (the early exit of the apparent-pair test); dense: all
+// vertices, sparse: the neighbour list of the vertex of v with the fewest
+// neighbours. All lanes of a group get the same result.
 template <int G, int K, class Dist>
 __device__ __forceinline__ int scan_max_k(const Ctx<Dist> &c, const int (&v)[K + 1], float bound,
                                           int jmin, bool active) {

@@ -758,6 +758,22 @@ __global__ void __launch_bounds__(kSortThreads) k_sort_columns(Columns in, Scala
 // with the working column's delta in LDS and its sorted base in global
 // scratch.
 // ---------------------------------------------------------------------------
+// The job record of a reduction kernel, copied once into LDS and read from
+// there. Read straight from the kernel arguments, its fields become
+// wave-uniform scalar values, and that build of the reduction loses zero
+// apparent pairs (the pivot lookups in the pair table miss, the columns end
+// early, the bars are wrong; the same with SGPR spills to memory, without
+// the VGPR live-range pass and at -O1); copied to LDS (or, as before, to
+// scratch memory) the same source gives the oracle's bars, at the same
+// speed. The cause is not found.
+template <class Dist>
+__device__ __forceinline__ const ReduceJob<Dist> &job_to_lds(const ReduceJob<Dist> &J) {
+    __shared__ __align__(16) unsigned char jbuf[sizeof(ReduceJob<Dist>)];
+    if (threadIdx.x == 0) __builtin_memcpy(jbuf, &J, sizeof(ReduceJob<Dist>));
+    __syncthreads();
+    return *reinterpret_cast<const ReduceJob<Dist> *>(jbuf);
+}
+
 template <class Dist>
 __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 capD,
                                                        ReduceBuffers RB, Scalars *s) {
@@ -770,7 +786,8 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce(ReduceJob<Dist> J, u32 c
     carve_reduce_lds(smem, capD, (LDS int *)&s_ns, &D, &G, &SB);
     const BmLds L = carve_bm_lds(smem, reduce_lds_bytes(capD), J.bm_bits ? J.eo.E : 0);
     const ReduceScratch SC = make_scratch(RB, SB, (LDS int *)&S.vns);
-    const int status = reduce_columns<kRedThreads>(J, D, G, SC, L, S);
+    const ReduceJob<Dist> &Jl = job_to_lds(J);
+    const int status = reduce_columns<kRedThreads>(Jl, D, G, SC, L, S);
     if (threadIdx.x == 0) {
         s->status = status;
         s->nbars = S.nbars;
@@ -820,7 +837,8 @@ __global__ void __launch_bounds__(kRedThreads) k_reduce_par(ReduceJob<Dist> J, u
     R.ldia += g * RB.lcap;
     const ReduceScratch SC = make_scratch(R, SB, (LDS int *)&S.vns);
     const BmLds L = carve_bm_lds(smem, reduce_lds_bytes(capD), J.bm_bits ? J.eo.E : 0);
-    const int status = reduce_columns_par<kRedThreads>(J, D, G, SC, L, S);
+    const ReduceJob<Dist> &Jl = job_to_lds(J);
+    const int status = reduce_columns_par<kRedThreads>(Jl, D, G, SC, L, S);
     if (threadIdx.x == 0) {
         if (status && status != kRedAbort) atomicCAS(&s->status, 0, status);
         atomicAdd(&s->stat[kStatEmergent], S.stat[0]);

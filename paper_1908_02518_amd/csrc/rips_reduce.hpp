@@ -174,6 +174,7 @@ enum : int {
     kRedNoPull = 9,    // a pull of the far part moved nothing (cannot happen)
     kRedOrder = 10,    // a column after j owns a pivot j looks up (cannot happen)
     kRedRefill = 11,   // the middle level came out of a refill empty (cannot happen)
+    kRedNoTable = 12,  // apparent shortcut without the filter's pair table (cannot happen)
 };
 
 // Bound of one wait in the spread-out reduction, in wall-clock ticks
@@ -604,6 +605,7 @@ __device__ __forceinline__ PivotCand base_advance(const ReduceJob<Dist> &J, cons
     out.diam = 0.0f;
     out.coef = 0;
     if (threadIdx.x >= kWave) return out;
+    wave_sync(); // S.f: lane 0 may have moved it, in this wave's own run
     const int lane = lane_id();
     int64_t f = S.f;
     const int64_t len = S.len;
@@ -1496,6 +1498,8 @@ __device__ __forceinline__ int apparent_run(const ReduceJob<Dist> &J, const LdsC
     int nadd = 0;
     *res = kRedOk;
     while (nadd < budget) {
+        // the last step's additions (other lanes' slots, diameters, counts)
+        wave_sync();
         const int ns0 = min(*D.nslots, capD);
         if (ns0 > capD / 8) break; // maintenance due
         RED_T0(t_r0);
@@ -1667,10 +1671,13 @@ __device__ __forceinline__ void block_min2(int &a, int &b, RedShared<BT> &S) {
 // pivot of diameter bits <= dbits, i.e. each one is committed or its current
 // pivot is past that diameter (a column's published bound only grows).
 // Returns 0, or kRedAbort / kRedWait (all threads get the same answer).
-template <int BT, class Dist>
-__device__ int par_wait(const ReduceJob<Dist> &J, RedShared<BT> &S, int j, u32 dbits) {
+// (The column words come by value: a job struct whose address reached this
+// out-of-line call would be copied to scratch memory, and every read of it
+// in the caller would become a scratch load.)
+template <int BT>
+__device__ int par_wait(const ParState par, RedShared<BT> &S, int j, u32 dbits) {
     const int tid = threadIdx.x;
-    u32 *ctl = J.par.ctl;
+    u32 *ctl = par.ctl;
     if (tid == 0) S.wbad = (int)ld_dev(&ctl[kCtlFront]);
     __syncthreads();
     int from = min(S.wbad, j);
@@ -1688,7 +1695,7 @@ __device__ int par_wait(const ReduceJob<Dist> &J, RedShared<BT> &S, int j, u32 d
     for (bool first = true;; first = false) {
         int bad = j, open = j;
         for (int o = from + tid; o < j; o += BT) {
-            const u32 st = ld_dev(&J.par.cst[o]);
+            const u32 st = ld_dev(&par.cst[o]);
             if (st != kColDone) open = min(open, o);
             if (st <= dbits) bad = min(bad, o);
         }
@@ -1890,7 +1897,7 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
         if (kPar && S.owner < 0 && S.appv < 0) {
             // free pivot: final once no column before can still take it
             RED_T0(t_w);
-            result = par_wait<BT>(J, S, j, __float_as_uint(piv.diam));
+            result = par_wait<BT>(J.par, S, j, __float_as_uint(piv.diam));
             RED_T1(S, 17, t_w);
             if (result) break;
             if (tid == 0) S.owner = ph_find_dev(J.ph, piv.idx);
@@ -1955,26 +1962,10 @@ __device__ __forceinline__ int reduce_one(const ReduceJob<Dist> &J, const LdsCol
             }
         } else if (!(J.shortcuts & kShortApparent)) {
             if (tid == 0) S.m = -1; // no apparent shortcut: the pivot is free
-        } else if (w == 0) {
-            int tv[kMaxVerts];
-            decode(piv.idx, k + 1, c.n, c.B, tv);
-            const int m = zero_apparent_facet<kWave>(c, tv, k + 1, piv.diam);
-            if (lane == 0) {
-                S.m = m;
-                if (m >= 0) {
-                    int rv[kMaxVerts];
-                    remove_vertex(tv, k + 1, m, rv);
-                    // tau = rho u {tau[m]}; vertices of rho below tau[m]: k + 1 - m
-                    const u32 crho = coeff_sign(k + 1 - m, p);
-                    const u32 lam = (u32)((u64)piv.coef * J.inv[crho] % p);
-                    for (int q = 0; q <= k; ++q) S.it_v[0][q] = rv[q];
-                    S.nit = 1;
-                    S.it_coef[0] = (p - lam) % p;
-                    S.it_diam[0] = piv.diam;
-                    if (!log_add(SC, S, simplex_index(rv, k, c.B), (p - lam) % p, piv.diam, 1))
-                        S.abort = kRedLogFull;
-                }
-            }
+        } else if (tid == 0) {
+            // every caller that keeps the shortcut passes the filter's table
+            S.m = -1;
+            S.abort = kRedNoTable;
         }
         __syncthreads();
         RED_T1(S, 7, t_app);
@@ -2262,7 +2253,7 @@ __device__ __forceinline__ int reduce_columns_par(const ReduceJob<Dist> &J, cons
         if (emerg) {
             RED_T0(t_em);
             RED_T0(t_w);
-            status = par_wait<BT>(J, S, col, __float_as_uint(J.cols.diam[col]));
+            status = par_wait<BT>(J.par, S, col, __float_as_uint(J.cols.diam[col]));
             RED_T1(S, 17, t_w);
             if (status) break;
             if (tid == 0) S.owner = ph_find_dev(J.ph, S.tau);

@@ -106,6 +106,7 @@ __device__ __forceinline__ void bm_wait_flips() { __builtin_amdgcn_s_waitcnt(0);
 __device__ __forceinline__ int bm_next(const BmLds &L, int f) {
     const int lane = lane_id();
     if (f >= L.E) return -1;
+    wave_sync(); // summary bits lane 0 cleared in this wave's last look
     int w1 = f >> 5;
     const u32 first = L.l1[w1] & (~0u << (f & 31));
     if (first) return (w1 << 5) + __ffs((int)first) - 1;
@@ -128,6 +129,7 @@ __device__ __forceinline__ int bm_next(const BmLds &L, int f) {
         if (lane == 0)
             __hip_atomic_fetch_and(&L.l2[j >> 5], ~(1u << (j & 31)), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_WORKGROUP);
+        wave_sync();
         i = j + 1;
     }
     return -1;
@@ -518,7 +520,7 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
             st_dev(&J.par.cst[j], S.pub);
         }
         if (kPar && S.owner < 0 && S.appv < 0) {
-            result = par_wait<BT>(J, S, j, __float_as_uint(piv.diam));
+            result = par_wait<BT>(J.par, S, j, __float_as_uint(piv.diam));
             if (result) break;
             if (tid == 0) S.owner = ph_find_dev(J.ph, piv.idx);
             __syncthreads();

@@ -107,7 +107,7 @@ def test_batched_config_validation():
     assert lib.rips_set_reduce_workgroups(-1) == -1
     assert lib.rips_set_shortcuts(-1) == -1
     assert lib.rips_set_shortcuts(8) == -1
-    assert lib.rips_set_reduced_storage(3) == -1
+    assert lib.rips_set_reduced_storage(4) == -1
     assert lib.rips_set_reduced_storage(-1) == -1
     assert lib.rips_batched_autotune(None, None, 1, 2, 8, 1, ctypes.c_float(1.0), 2, None, None,
                                      0, None, None, None) == -1
