@@ -373,6 +373,10 @@ def main() -> int:
                                    threshold=kw5["threshold"]) for x in clouds5]
     n_simplices = int(sum(sum(c) for c in counts5))
     log(f"workload {c5['name']}: {len(clouds5)} clouds, {n_simplices} simplices of dims 0-2")
+    # the launch configuration the autotuner picks on this batch (every
+    # configuration's bars agree; it keeps the fastest for the timed steps)
+    tuned = rips.batched_autotune(xb5, off5, nmax5, reps=2, **kw5)
+    log(f"autotune: delta slots {tuned[0]}, workgroups per CU {tuned[1]}, {tuned[2]:.2f} ms")
     for i in range(args.warmup):
         c0 = time.perf_counter()
         bb = rips.barcode_batched(xb5, off5, nmax5, **kw5)
@@ -730,7 +734,10 @@ def main() -> int:
                                "circle, noise 0.1, 40 uniform outliers in [-2, 2]^2), float32, "
                                "full Rips, dims 0-1, Z/2, one persistent launch",
                    "clouds": len(clouds5), "n": 400, "dims": 1, "p": 2,
-                   "simplices": n_simplices},
+                   "simplices": n_simplices,
+                   "launch": {"delta_slots": tuned[0], "workgroups_per_cu": tuned[1],
+                              "chosen_by": "rips_batched_autotune on this batch",
+                              "autotune_ms": round(tuned[2], 3)}},
         "event_ms_per_step": {"median": round(step_ms[len(step_ms) // 2], 4),
                               "min": round(step_ms[0], 4), "max": round(step_ms[-1], 4)},
         "barcodes_per_s": round(len(clouds5) / (ms_per_step * 1e-3), 1),
