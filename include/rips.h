@@ -414,6 +414,18 @@ rips_status rips_batched_set_config(int32_t delta_slots, int32_t workgroups_per_
 rips_status rips_batched_get_config(int32_t *delta_slots, int32_t *workgroups_per_cu);
 
 /*
+ * Workgroups per cloud of the batched path (per device, the current one).
+ * mode 0 (default): a batch of B clouds with at least two compute units per
+ * cloud spreads each cloud over min(8, CUs / B) workgroups: one of them runs
+ * the cloud's distances, H0, enumeration filter, column sort and edge order,
+ * and all of them reduce its columns together (the spread-out reduction of
+ * rips_set_reduce_workgroups); larger batches keep one workgroup per cloud.
+ * mode 1: always one workgroup per cloud. The bars are the same either way.
+ * Other values: RIPS_E_INVALID_ARG.
+ */
+rips_status rips_batched_set_spread(int32_t mode);
+
+/*
  * rips_batched_autotune -- time the batched launch on the caller's batch
  * (same arguments as rips_barcode_batched_device) for every configuration
  * of delta_slots in {512, 1024, 2048} x workgroups_per_cu in {1, 2, 4},

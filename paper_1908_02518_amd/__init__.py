@@ -62,6 +62,7 @@ EXPORTS = (
     "rips_set_shortcuts",
     "rips_get_shortcuts",
     "rips_batched_set_config",
+    "rips_batched_set_spread",
     "rips_batched_get_config",
     "rips_batched_autotune",
     "rips_profile_enable",
@@ -222,6 +223,8 @@ def _load():
     lib.rips_get_reduced_storage.restype = ctypes.c_int
     lib.rips_batched_set_config.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.rips_batched_set_config.restype = ctypes.c_int
+    lib.rips_batched_set_spread.argtypes = [ctypes.c_int32]
+    lib.rips_batched_set_spread.restype = ctypes.c_int
     lib.rips_batched_get_config.argtypes = [ctypes.POINTER(ctypes.c_int32),
                                             ctypes.POINTER(ctypes.c_int32)]
     lib.rips_batched_get_config.restype = ctypes.c_int
@@ -621,6 +624,13 @@ def get_shortcuts() -> int:
 def batched_set_config(delta_slots: int = 0, workgroups_per_cu: int = 0):
     """Launch configuration of the batched path (0 = defaults)."""
     _check(_lib.rips_batched_set_config(int(delta_slots), int(workgroups_per_cu)))
+
+
+def batched_set_spread(mode: int = 0):
+    """Workgroups per cloud of the batched path: 0 (auto) spreads each cloud
+    of a batch smaller than the chip over several workgroups, 1 keeps one
+    workgroup per cloud. The bars are the same either way."""
+    _check(_lib.rips_batched_set_spread(int(mode)))
 
 
 def batched_get_config():

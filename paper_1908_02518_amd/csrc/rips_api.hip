@@ -196,6 +196,11 @@ enum BufId {
     BB_BM_LEN,
     BB_BM_RUN,
     BB_BM_BITS,
+    // workgroups that share one cloud (spread-out batched reduction)
+    BB_SYNC,
+    BB_PAR_CST,
+    BB_PAR_CTL,
+    BB_PAR_STAT,
     // the same for the single-cloud path, and its edge sort
     B_BM_POS,
     B_BM_VERTS,
@@ -258,6 +263,7 @@ struct DevCtx {
     int64_t batch_logstride = 0;
     u32 batch_capD = 0; // 0 = default delta size of the batched reduction
     int batch_wgpcu = 0; // 0 = default (1 persistent workgroup per CU)
+    int batch_spread_off = 0; // 1 = one workgroup per cloud even for a small batch
     int working_column = RIPS_WORKING_COLUMN_AUTO; // rips_set_working_column
     // the bitmap buffers are zero between columns; these record what was
     // zeroed after the last allocation (pointer and bytes) per path
@@ -1500,8 +1506,12 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     hipStream_t st = (hipStream_t)hip_stream;
     const int D1 = max_dim + 1;
     const bool lds_d = n_max <= kBatchLdsN;
-    int grid = std::max(1, C->num_cus) * std::max(1, C->batch_wgpcu);
-    if (grid > B) grid = B;
+    // a batch smaller than the chip spreads each cloud over several
+    // workgroups, at most one per CU in all (they wait for each other, so all
+    // of them must be resident at once)
+    const int slots = std::max(1, C->num_cus) * std::max(1, C->batch_wgpcu);
+    const int spread = C->batch_spread_off ? 1 : batched_spread(B, std::max(1, C->num_cus), max_dim);
+    int grid = spread > 1 ? B * spread : std::min(slots, B);
     const int64_t npairs = (int64_t)n_max * (n_max - 1) / 2;
     const int64_t col_stride = npairs + n_max + 16;
     int64_t ph_stride = 64;
@@ -1615,6 +1625,13 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
     int *order;
     ENS(BB_ORDER, (int64_t)B * 4, order, int);
     A.order = order;
+    A.spread = spread;
+    if (spread > 1) {
+        ENS(BB_SYNC, G * kSyncWords * 4, A.sync, int);
+        ENS(BB_PAR_CST, G * col_stride * 4, A.par_cst, u32);
+        ENS(BB_PAR_CTL, G * kCtlWords * 4, A.par_ctl, u32);
+        ENS(BB_PAR_STAT, G * kSyncStats * 8, A.par_stat, unsigned long long);
+    }
     // the direct-mapped working column of dimension 1, where it fits
     const bool bm = C->working_column == RIPS_WORKING_COLUMN_AUTO &&
                     batched_bm_fits(n_max, max_dim, p, G);
@@ -2391,6 +2408,17 @@ rips_status rips_batched_set_config(int32_t delta_slots, int32_t workgroups_per_
     std::lock_guard<std::mutex> lk(C->mu);
     C->batch_capD = (u32)delta_slots;
     C->batch_wgpcu = workgroups_per_cu;
+    return RIPS_OK;
+}
+
+rips_status rips_batched_set_spread(int32_t mode) {
+    g_err.clear();
+    if (mode != 0 && mode != 1) return fail(RIPS_E_INVALID_ARG, "spread mode is 0 (auto) or 1 (off)");
+    DevCtx *C;
+    rips_status rs = get_ctx(&C);
+    if (rs) return rs;
+    std::lock_guard<std::mutex> lk(C->mu);
+    C->batch_spread_off = mode;
     return RIPS_OK;
 }
 

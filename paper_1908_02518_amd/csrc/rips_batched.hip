@@ -58,6 +58,173 @@ struct CloudDist<DistFull> {
     static __device__ DistFull make(float *, float *g, int n) { return DistFull{g, n}; }
 };
 
+// The reduction job of the cloud whose data-parallel passes workgroup wgL
+// ran: its columns, pivot table, apparent-pair table, column store, edge
+// order and staged bars live in wgL's slices. The distances are read from
+// wgL's global slice (the packed variant copies its LDS triangle there).
+template <class Dist>
+__device__ __forceinline__ ReduceJob<Dist> batch_job(const BatchArgs &A, int wgL, int n, float t, int S,
+                                                    int nE) {
+    const int64_t npairs = (int64_t)n * (n - 1) / 2;
+    float *Dgw = A.Dg + (int64_t)wgL * A.d_stride;
+    ReduceJob<Dist> J;
+    J.c.d = CloudDist<Dist>::make(Dgw, Dgw, n);
+    J.c.B = A.binom;
+    J.c.nb.off = nullptr;
+    J.c.nb.idx = nullptr;
+    J.c.n = n;
+    J.c.t = t;
+    J.k = 1;
+    J.p = A.p;
+    J.inv = A.inv;
+    const int64_t co = (int64_t)wgL * A.col_stride;
+    J.cols = Columns{A.c_idx1 + co, A.c_dm1 + co, A.c_j1 + co, A.c_t1 + co};
+    J.ncols = S;
+    u32 phcap = 64;
+    while (phcap < 2u * (u32)S + 64u && (int64_t)phcap < A.ph_stride) phcap <<= 1;
+    J.ph = PivotHash{A.ph_keys + (int64_t)wgL * A.ph_stride, A.ph_vals + (int64_t)wgL * A.ph_stride,
+                     phcap - 1};
+    J.V.off = A.v_off + co;
+    J.V.len = A.v_len + co;
+    J.V.pivcoef = A.v_piv + co;
+    J.V.roff = A.v_roff + co;
+    J.V.rlen = A.v_rlen + co;
+    J.V.idx = A.v_idx + (int64_t)wgL * A.v_stride;
+    J.V.diam = A.v_diam + (int64_t)wgL * A.v_stride;
+    J.V.coef = A.v_coef + (int64_t)wgL * A.v_stride;
+    J.V.cap = A.v_stride;
+    J.vcount = &A.v_count[wgL];
+    const int64_t so = (int64_t)wgL * A.st_stride + n;
+    J.bars = BarBuf{A.st_b + so, A.st_d + so, A.st_bs + so, A.st_ds + so};
+    J.cand_avg = (float)n;
+    u32 appcap = 64;
+    while (appcap < 2u * (u32)npairs + 64u && (int64_t)appcap < A.ph_stride) appcap <<= 1;
+    J.app = PairHash{A.app_keys + (int64_t)wgL * A.ph_stride, A.app_vals + (int64_t)wgL * A.ph_stride,
+                     A.app_verts + (int64_t)wgL * A.ph_stride, nullptr, nullptr, nullptr, nullptr,
+                     appcap - 1};
+    J.par = A.spread > 1 ? ParState{A.par_cst + co, A.par_ctl + (int64_t)wgL * kCtlWords}
+                         : ParState{nullptr, nullptr};
+    J.shortcuts = kShortApparent | kShortEmergent | kShortClearing;
+    J.keep_essential_v = 0;
+    J.rstore = kRStoreAuto;
+#if RIPS_COLUMN_TRACE
+    J.trace = nullptr;
+#endif
+    J.prev_bits = nullptr;
+    J.prev = PivotHash{nullptr, nullptr, 0};
+    const int64_t to = (int64_t)wgL * A.bm_tab_stride;
+    J.eo = A.bm_bits ? EdgeOrder{A.bm_pos + to, A.bm_verts + to, A.bm_len + to, A.bm_run + to, nE,
+                                 (n + 31) / 32}
+                     : EdgeOrder{nullptr, nullptr, nullptr, nullptr, 0, 0};
+    J.bm_bits = A.bm_bits;
+    J.bm_stride = A.bm_stride;
+    return J;
+}
+
+// This workgroup's own reduction scratch (blockIdx.x's slices) and the LDS
+// of its working column.
+__device__ __forceinline__ void batch_scratch(const BatchArgs &A, unsigned char *smem, LDS int *nsl,
+                                              RedShared<kBT> &RS, int nE, LdsCol *Dw, Staging *Gs,
+                                              ReduceScratch *SC, BmLds *L) {
+    const int64_t wg = blockIdx.x;
+    carve_reduce_lds(smem, A.capD, nsl, Dw, Gs, &SC->SB);
+    *L = carve_bm_lds(smem, reduce_lds_bytes(A.capD), A.bm_bits ? nE : 0);
+    for (int h = 0; h < 2; ++h) {
+        SC->F.idx[h] = A.f_idx[h] + wg * A.f_stride;
+        SC->F.dia[h] = A.f_dia[h] + wg * A.f_stride;
+        SC->F.coef[h] = A.f_coef[h] + wg * A.f_stride;
+    }
+    SC->F.cap = A.f_stride;
+    SC->Vw.keys = A.vw_keys + wg * A.vw_stride;
+    SC->Vw.coef = A.vw_coef + wg * A.vw_stride;
+    SC->Vw.diam = A.vw_diam + wg * A.vw_stride;
+    SC->Vw.slots = A.vw_slots + wg * A.vw_stride;
+    SC->Vw.nslots = (LDS int *)&RS.vns;
+    SC->Vw.mask = (u32)A.vw_stride - 1;
+    SC->lkey = A.log_key + wg * A.log_stride;
+    SC->lcoef = A.log_coef + wg * A.log_stride;
+    SC->ldia = A.log_dia + wg * A.log_stride;
+    SC->lcap = A.log_stride;
+}
+
+// A reduction's status as a status bit of the batch (the host grows the
+// buffer behind it and runs again).
+__device__ __forceinline__ void batch_red_status(const BatchArgs &A, int rstat) {
+    if (!rstat || rstat == kRedAbort || threadIdx.x != 0) return;
+    const int bit = rstat == kRedBaseFull    ? 1
+                    : rstat == kRedStoreFull ? 2
+                    : rstat == kRedFarFull   ? 32
+                    : rstat == kRedVFull     ? 64
+                    : rstat == kRedLogFull   ? 128
+                                             : 8;
+    atomicOr(A.status, bit);
+}
+
+// Bounded wait of thread 0 until *w >= want (agent scope); false after
+// kWaitTicks, with the batch status marked.
+__device__ __forceinline__ bool batch_wait(const BatchArgs &A, const int *w, int want) {
+    const unsigned long long t0 = wall_clock64();
+    while (ld_dev(w) < want) {
+        if (wall_clock64() - t0 > kWaitTicks) {
+            atomicOr(A.status, 8);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+    return true;
+}
+
+// The counters of one workgroup's share of a spread-out reduction, summed
+// into its cloud's (the leader's) counters.
+__device__ __forceinline__ void batch_par_stats(const BatchArgs &A, int wgL, const RedShared<kBT> &RS) {
+    if (threadIdx.x != 0) return;
+    unsigned long long *ps = A.par_stat + (int64_t)wgL * kSyncStats;
+    atomicAdd(&ps[0], RS.stat[0]);   // emergent
+    atomicAdd(&ps[1], RS.stat[1]);   // reduced
+    atomicAdd(&ps[2], RS.stat[2]);   // additions
+    atomicAdd(&ps[3], RS.stat[3]);   // bars of nonzero persistence
+    atomicAdd(&ps[4], RS.stat[4]);   // essential
+    atomicAdd(&ps[12], RS.stat[12]); // entries added
+}
+
+// A workgroup that helps its cloud's leader reduce (spread > 1): waits for
+// the leader's passes, reduces columns from the shared cursor with its own
+// scratch, adds its counters and reports done.
+template <class Dist>
+__device__ void batch_follow(const BatchArgs &A, int wgL, unsigned char *smem, RedShared<kBT> &RS) {
+    const int tid = threadIdx.x;
+    if (A.max_dim < 1) return; // no reduction: the leader waits for nobody
+    int *sw = A.sync + (int64_t)wgL * kSyncWords;
+    __shared__ int s_go;
+    if (tid == 0) s_go = batch_wait(A, &sw[kSyncReady], 1) ? 1 : 0;
+    __syncthreads();
+    if (s_go) {
+        fence_acquire_dev(); // the leader's columns, tables and words
+        const int skip = __builtin_amdgcn_readfirstlane(ld_dev(&sw[kSyncSkip]));
+        if (!skip) {
+            const int n = __builtin_amdgcn_readfirstlane(ld_dev(&sw[kSyncN]));
+            const float t = __int_as_float(__builtin_amdgcn_readfirstlane(ld_dev(&sw[kSyncT])));
+            const int S = __builtin_amdgcn_readfirstlane(ld_dev(&sw[kSyncS]));
+            const int nE = __builtin_amdgcn_readfirstlane(ld_dev(&sw[kSyncE]));
+            const ReduceJob<Dist> J = batch_job<Dist>(A, wgL, n, t, S, nE);
+            __shared__ int s_nsl;
+            LdsCol Dw;
+            Staging Gs;
+            ReduceScratch SC;
+            BmLds L;
+            batch_scratch(A, smem, (LDS int *)&s_nsl, RS, nE, &Dw, &Gs, &SC, &L);
+            gsync();
+            const int rstat = reduce_columns_par<kBT>(J, Dw, Gs, SC, L, RS);
+            batch_red_status(A, rstat);
+            batch_par_stats(A, wgL, RS);
+        }
+    }
+    // the column slots and the column store written here, then done
+    fence_release_dev();
+    __syncthreads();
+    if (tid == 0) atomicAdd(&sw[kSyncDone], 1);
+}
+
 // One cloud by one workgroup. kLdsD: distances in LDS (packed) for the
 // enumeration and H0 phases, then copied to global for the reduction.
 template <class Dist>
@@ -79,11 +246,18 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
     const int64_t nn = A.offsets[b + 1] - o0;
     if (nn < 1 || nn > A.nmax) {
         // rejected by the order pass (status bit 16); publish empty segments
-        if (threadIdx.x == 0)
+        if (threadIdx.x == 0) {
             for (int d = 0; d < D1; ++d) {
                 A.seg_start[(int64_t)b * D1 + d] = 0;
                 A.seg_count[(int64_t)b * D1 + d] = 0;
             }
+            if (A.spread > 1) {
+                int *sw = A.sync + (int64_t)wg * kSyncWords;
+                st_dev(&sw[kSyncSkip], 1);
+                fence_release_dev();
+                st_dev(&sw[kSyncReady], 1);
+            }
+        }
         __syncthreads();
         return;
     }
@@ -445,7 +619,6 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         // working column: each thread keeps a contiguous range of pair
         // indices, so that the stable sort leaves equal lengths in index order
         EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, 0, 0};
-#ifndef RIPS_AB_NO_EDGE_ORDER
         if (A.bm_bits) {
             const int64_t chunk = (npairs + kBT - 1) / kBT;
             const int64_t e0 = (int64_t)tid * chunk, e1 = min(npairs, e0 + chunk);
@@ -495,84 +668,93 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
             gsync();
             eo = EdgeOrder{bpos, bv, bl, br, nE, (n + 31) / 32};
         }
-#endif
         // ---- the reduction reads D from global; LDS now holds its working column
         if (kLds)
             for (int64_t e = tid; e < npairs; e += kBT) Dgw[e] = Dl[e];
-        u32 phcap = 64;
-        while (phcap < 2u * (u32)S + 64u && (int64_t)phcap < A.ph_stride) phcap <<= 1;
-        PivotHash ph{A.ph_keys + (int64_t)wg * A.ph_stride, A.ph_vals + (int64_t)wg * A.ph_stride,
-                     phcap - 1};
-        for (u32 q = tid; q < phcap; q += kBT) st(&ph.keys[q], kEmpty);
+        const int spread = A.spread;
+        const ReduceJob<Dist> J = batch_job<Dist>(A, wg, n, t, S, eo.E);
+        for (u32 q = tid; q <= J.ph.mask; q += kBT) {
+            st(&J.ph.keys[q], kEmpty);
+            if (spread > 1) st(&J.ph.vals[q], -1); // spread out: -1 = no value yet
+        }
         if (tid == 0) A.v_count[wg] = 0;
-        gsync();
-        ReduceJob<Dist> J;
-        J.c = c;
-        J.c.d = CloudDist<Dist>::make(Dgw, Dgw, n);
-        J.k = 1;
-        J.p = A.p;
-        J.inv = A.inv;
-        J.cols = cols;
-        J.ncols = S;
-        J.ph = ph;
-        J.V.off = A.v_off + (int64_t)wg * A.col_stride;
-        J.V.len = A.v_len + (int64_t)wg * A.col_stride;
-        J.V.pivcoef = A.v_piv + (int64_t)wg * A.col_stride;
-        J.V.roff = A.v_roff + (int64_t)wg * A.col_stride;
-        J.V.rlen = A.v_rlen + (int64_t)wg * A.col_stride;
-        J.V.idx = A.v_idx + (int64_t)wg * A.v_stride;
-        J.V.diam = A.v_diam + (int64_t)wg * A.v_stride;
-        J.V.coef = A.v_coef + (int64_t)wg * A.v_stride;
-        J.V.cap = A.v_stride;
-        J.vcount = &A.v_count[wg];
-        J.bars = BarBuf{sb_b + n, sb_d + n, sb_bs + n, sb_ds + n};
+        int *sw = A.sync + (int64_t)wg * kSyncWords;
+        if (spread > 1) {
+            // column states, control words and counters of the shared
+            // reduction, then the words the other workgroups build their job
+            // from, then the ready flag
+            for (int q = tid; q < S; q += kBT) J.par.cst[q] = 0u;
+            if (tid < kCtlWords) J.par.ctl[tid] = 0u;
+            if (tid < kSyncStats) A.par_stat[(int64_t)wg * kSyncStats + tid] = 0ull;
+            if (tid == 0) {
+                sw[kSyncN] = n;
+                sw[kSyncT] = __float_as_int(t);
+                sw[kSyncS] = S;
+                sw[kSyncE] = eo.E;
+            }
+            fence_release_dev();
+            gsync();
+            if (tid == 0) st_dev(&sw[kSyncReady], 1);
+        }
         __shared__ int s_nsl;
         LdsCol Dw;
         Staging Gs;
         ReduceScratch SC;
-        carve_reduce_lds(smem, A.capD, (LDS int *)&s_nsl, &Dw, &Gs, &SC.SB);
-        const BmLds L = carve_bm_lds(smem, reduce_lds_bytes(A.capD), A.bm_bits ? eo.E : 0);
-        for (int h = 0; h < 2; ++h) {
-            SC.F.idx[h] = A.f_idx[h] + (int64_t)wg * A.f_stride;
-            SC.F.dia[h] = A.f_dia[h] + (int64_t)wg * A.f_stride;
-            SC.F.coef[h] = A.f_coef[h] + (int64_t)wg * A.f_stride;
-        }
-        SC.F.cap = A.f_stride;
-        SC.Vw.keys = A.vw_keys + (int64_t)wg * A.vw_stride;
-        SC.Vw.coef = A.vw_coef + (int64_t)wg * A.vw_stride;
-        SC.Vw.diam = A.vw_diam + (int64_t)wg * A.vw_stride;
-        SC.Vw.slots = A.vw_slots + (int64_t)wg * A.vw_stride;
-        SC.Vw.nslots = (LDS int *)&RS.vns;
-        SC.Vw.mask = (u32)A.vw_stride - 1;
-        SC.lkey = A.log_key + (int64_t)wg * A.log_stride;
-        SC.lcoef = A.log_coef + (int64_t)wg * A.log_stride;
-        SC.ldia = A.log_dia + (int64_t)wg * A.log_stride;
-        SC.lcap = A.log_stride;
-        J.cand_avg = (float)n;
-        J.app = app;
-        J.shortcuts = kShortApparent | kShortEmergent | kShortClearing;
-        J.keep_essential_v = 0;
-        J.rstore = kRStoreAuto;
-#if RIPS_COLUMN_TRACE
-        J.trace = nullptr;
-#endif
-        J.prev_bits = nullptr;
-        J.prev = PivotHash{nullptr, nullptr, 0};
-        J.eo = eo;
-        J.bm_bits = A.bm_bits;
-        J.bm_stride = A.bm_stride;
+        BmLds L;
+        batch_scratch(A, smem, (LDS int *)&s_nsl, RS, eo.E, &Dw, &Gs, &SC, &L);
         gsync();
-        const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, L, RS);
-        if (rstat && tid == 0) {
-            const int bit = rstat == kRedBaseFull    ? 1
-                            : rstat == kRedStoreFull ? 2
-                            : rstat == kRedFarFull   ? 32
-                            : rstat == kRedVFull     ? 64
-                            : rstat == kRedLogFull   ? 128
-                                                     : 8;
-            atomicOr(A.status, bit);
+        unsigned long long st5[6];
+        if (spread > 1) {
+            const int rstat = reduce_columns_par<kBT>(J, Dw, Gs, SC, L, RS);
+            batch_red_status(A, rstat);
+            batch_par_stats(A, wg, RS);
+            // the other workgroups' column slots, then the bars compacted in
+            // column order (each slot has birth simplex -1 when it gives none)
+            if (tid == 0) (void)batch_wait(A, &sw[kSyncDone], spread - 1);
+            __syncthreads();
+            fence_acquire_dev();
+            int base = 0;
+            for (int c0 = 0; c0 < S; c0 += kBT) {
+                const int q = c0 + tid;
+                float bb = 0.0f, bd = 0.0f;
+                int64_t bbs = -1, bds = -1;
+                if (q < S) {
+                    bb = J.bars.birth[q];
+                    bd = J.bars.death[q];
+                    bbs = J.bars.bs[q];
+                    bds = J.bars.ds[q];
+                }
+                const bool keep = q < S && bbs >= 0;
+                int tot;
+                const int at = block_scan_excl<kBT>(keep ? 1 : 0, Sh.w, &tot);
+                if (keep) {
+                    J.bars.birth[base + at] = bb;
+                    J.bars.death[base + at] = bd;
+                    J.bars.bs[base + at] = bbs;
+                    J.bars.ds[base + at] = bds;
+                }
+                base += tot;
+                gsync();
+            }
+            nb1 = base;
+            const unsigned long long *ps = A.par_stat + (int64_t)wg * kSyncStats;
+            st5[0] = ld_dev(&ps[0]);
+            st5[1] = ld_dev(&ps[1]);
+            st5[2] = ld_dev(&ps[2]);
+            st5[3] = ld_dev(&ps[3]);
+            st5[4] = ld_dev(&ps[4]);
+            st5[5] = ld_dev(&ps[12]);
+        } else {
+            const int rstat = reduce_columns<kBT>(J, Dw, Gs, SC, L, RS);
+            batch_red_status(A, rstat);
+            nb1 = RS.nbars;
+            st5[0] = RS.stat[0];
+            st5[1] = RS.stat[1];
+            st5[2] = RS.stat[2];
+            st5[3] = RS.stat[3];
+            st5[4] = RS.stat[4];
+            st5[5] = RS.stat[12];
         }
-        nb1 = RS.nbars;
         if (tid == 0) {
             rips_dim_stats &s1 = A.stats[(int64_t)b * D1 + 1];
             s1.candidates = (int64_t)Sh.cnt[0];
@@ -580,13 +762,13 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
             s1.apparent_col = (int64_t)Sh.cnt[2];
             s1.apparent_pivot = 0;
             s1.columns = S;
-            s1.emergent = (int64_t)RS.stat[0];
-            s1.reduced = (int64_t)RS.stat[1];
-            s1.additions = (int64_t)RS.stat[2];
-            s1.bars_nonzero = (int64_t)RS.stat[3];
-            s1.entries_added = (int64_t)RS.stat[12];
-            s1.entries_stored = (int64_t)ld(&A.v_count[wg]);
-            s1.essential = (int64_t)RS.stat[4];
+            s1.emergent = (int64_t)st5[0];
+            s1.reduced = (int64_t)st5[1];
+            s1.additions = (int64_t)st5[2];
+            s1.bars_nonzero = (int64_t)st5[3];
+            s1.entries_added = (int64_t)st5[5];
+            s1.entries_stored = (int64_t)ld_dev(&A.v_count[wg]);
+            s1.essential = (int64_t)st5[4];
         }
     }
     // ---- publish: one segment per dimension in the unordered buffer
@@ -627,6 +809,16 @@ __global__ void __launch_bounds__(kBT) k_batched(BatchArgs A) {
     __shared__ BatchShared Sh;
     __shared__ RedShared<kBT> RS;
     __shared__ SortShared<kBT> SS;
+    if (A.spread > 1) {
+        // a fixed workgroup set per cloud, all resident together (the grid
+        // is at most the resident workgroups of the chip)
+        const int w = blockIdx.x;
+        const int slot = w / A.spread, role = w - slot * A.spread;
+        if (slot >= A.B) return;
+        if (role == 0) batch_cloud<Dist>(A, A.order[slot], smem, Sh, RS, SS);
+        else batch_follow<Dist>(A, w - role, smem, RS);
+        return;
+    }
     for (;;) {
         if (threadIdx.x == 0) Sh.cloud = (int)atomicAdd(A.queue, 1ull);
         __syncthreads();
@@ -660,6 +852,18 @@ __global__ void __launch_bounds__(1024) k_lpt_order(const int64_t *offsets, int 
 }
 
 __global__ void k_batch_status_reset(int *status) { *status = 0; }
+
+__global__ void k_batch_zero_words(int *w, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        w[i] = 0;
+}
+
+int batched_spread(int B, int slots, int max_dim) {
+    if (max_dim < 1 || B < 1) return 1;
+    const int s = slots / B;
+    return s < 2 ? 1 : (s > 8 ? 8 : s);
+}
 
 // canonical layout: segments in (cloud, dimension) order
 __global__ void __launch_bounds__(1024) k_batch_offsets(const int64_t *seg_count, int nseg,
@@ -748,6 +952,9 @@ hipError_t batched_prepare(bool lds_d, int nmax, u32 capD, bool bm) {
 
 void launch_batched(const BatchArgs &A, bool lds_d, int grid, SortBufs lpt, hipStream_t st) {
     hipLaunchKernelGGL(k_batch_status_reset, dim3(1), dim3(1), 0, st, A.status);
+    if (A.spread > 1)
+        hipLaunchKernelGGL(k_batch_zero_words, dim3(((int64_t)grid * kSyncWords + 255) / 256), dim3(256), 0,
+                           st, A.sync, (int64_t)grid * kSyncWords);
     hipLaunchKernelGGL(k_lpt_order, dim3(1), dim3(1024), 0, st, A.offsets, A.B, lpt,
                        (int *)A.order, A.queue, A.ucount, A.status, A.nmax);
     const size_t lds = batched_lds_bytes(lds_d, A.nmax, A.capD, A.bm_bits != nullptr);

@@ -83,13 +83,31 @@ struct BatchArgs {
     int64_t bm_tab_stride;          // C(nmax, 2)
     u32 *bm_bits;                   // all zero between columns
     int64_t bm_stride;              // C(nmax, 2) * ceil(nmax / 32) words
+    // workgroups per cloud: 1 = one workgroup per cloud, clouds from the
+    // queue; s > 1 (a batch smaller than the chip) = workgroup w works on
+    // cloud order[w / s]: w % s == 0 leads it (distances to edge order) and
+    // all s reduce its columns together (the spread-out reduction)
+    int spread;
+    int *sync;                      // kSyncWords per workgroup (its cloud's leader's are used)
+    u32 *par_cst;                   // per workgroup col_stride words: column states
+    u32 *par_ctl;                   // per workgroup kCtlWords words: cursor, frontier, abort
+    unsigned long long *par_stat;   // per workgroup kSyncStats counters of the reduction
 };
+
+// The words a cloud's leader shares with the other workgroups of its cloud
+// (spread > 1), zeroed before every launch: ready flag, n, t (bits), columns,
+// edges of the edge order, skip (the cloud has no reduction), reductions done.
+enum : int { kSyncReady = 0, kSyncN = 1, kSyncT = 2, kSyncS = 3, kSyncE = 4, kSyncSkip = 5,
+             kSyncDone = 6, kSyncWords = 8 };
+constexpr int kSyncStats = 16;
 
 
 size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD, bool bm);
 u32 batched_default_capD(bool lds_d, int nmax);
 hipError_t batched_prepare(bool lds_d, int nmax, u32 capD, bool bm);
 void launch_batched(const BatchArgs &A, bool lds_d, int grid, SortBufs lpt, hipStream_t st);
+// workgroups per cloud for a batch of B clouds on `slots` resident workgroups
+int batched_spread(int B, int slots, int max_dim);
 // whether the batched path can use the direct-mapped working column
 bool batched_bm_fits(int nmax, int max_dim, u32 p, int64_t grid);
 void launch_batch_finalize(const BatchArgs &A, int64_t *offsets_out, int64_t *total, int64_t cap,

@@ -130,3 +130,34 @@ def test_cloud_above_n_max_is_rejected():
         rips().barcode_batched(x, off, 20, max_dim=1)
     assert e.value.status == -1
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_spread_out_clouds_match_one_workgroup_per_cloud(p):
+    """A batch smaller than the chip spreads each cloud over several
+    workgroups (one leads, all reduce); the bars must equal those of one
+    workgroup per cloud, bit for bit."""
+    import torch
+    r = rips()
+    clouds = small_batch() + lattice_batch(12)
+    x, off, nmax = r.pack_clouds(clouds)
+    print(f"[case] spread vs one workgroup per cloud B={len(clouds)} p={p}", flush=True)
+    r.batched_set_spread(1)
+    try:
+        one = r.barcode_batched(x, off, nmax, max_dim=1, p=p)
+        torch.cuda.synchronize()
+        one = [t.clone() for t in (one.birth, one.death, one.birth_simplex, one.death_simplex,
+                                   one.offsets, one.stats)]
+    finally:
+        r.batched_set_spread(0)
+    spread = r.barcode_batched(x, off, nmax, max_dim=1, p=p)
+    torch.cuda.synchronize()
+    n = int(spread.offsets[-1])
+    assert torch.equal(one[4], spread.offsets)
+    for a, b in zip(one[:4], (spread.birth, spread.death, spread.birth_simplex, spread.death_simplex)):
+        assert torch.equal(a[:n], b[:n])
+    # the counters that do not depend on the order of the reduction agree
+    fields = r.STAT_FIELDS
+    for f in ("candidates", "cleared", "apparent_col", "columns", "bars_nonzero", "essential"):
+        q = fields.index(f)
+        assert torch.equal(one[5][:, :, q], spread.stats[:, :, q]), f
