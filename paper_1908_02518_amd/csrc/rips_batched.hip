@@ -187,15 +187,138 @@ __device__ __forceinline__ void batch_par_stats(const BatchArgs &A, int wgL, con
     atomicAdd(&ps[12], RS.stat[12]); // entries added
 }
 
-// A workgroup that helps its cloud's leader reduce (spread > 1): waits for
-// the leader's passes, reduces columns from the shared cursor with its own
-// scratch, adds its counters and reports done.
+// The dimension-1 enumeration / apparent-pair filter over share `part` of
+// `nparts` of the edges (interleaved by wave): survivors appended through
+// *nsurv, zero apparent pairs inserted into app, the counts of candidates,
+// cleared and apparent columns added to cnt[0..2]. Every thread calls it.
 template <class Dist>
-__device__ void batch_follow(const BatchArgs &A, int wgL, unsigned char *smem, RedShared<kBT> &RS) {
+__device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist> &c, float t, int64_t npairs,
+                                             const u32 *bits, const Columns &surv, const PairHash &app,
+                                             int part, int nparts, int *nsurv, unsigned long long *cnt) {
+    const int tid = threadIdx.x, lane = lane_id();
+    const Dist dist = c.d;
+    const bool leader = (lane & (kBatchFilterG - 1)) == 0;
+    unsigned long long n_clear = 0, n_acol = 0, n_cand = 0;
+    // one edge per group of kBatchFilterG lanes; the loop is uniform in
+    // the wave and the tests are predicates (the scans need every lane)
+    constexpr int kGroups = kWave / kBatchFilterG;
+    const int64_t step = (int64_t)nparts * (kBT / kWave) * kGroups;
+    for (int64_t e0 = ((int64_t)part * (kBT / kWave) + tid / kWave) * kGroups; e0 < npairs; e0 += step) {
+        const int64_t e = e0 + lane / kBatchFilterG;
+        bool live = e < npairs;
+        int v[2] = {0, 0};
+        float dm = 0.0f;
+        if (live) {
+            pair_of(e, &v[0], &v[1]);
+            dm = dist(v[0], v[1]);
+            live = dm <= t;
+        }
+        if (live) {
+            n_cand += leader;
+            if ((bits[e >> 5] >> (e & 31)) & 1u) {
+                n_clear += leader;
+                live = false;
+            }
+        }
+        const int j = scan_max_k<kBatchFilterG, 1>(c, v, dm, -1, live);
+        int tv[3];
+        int pos = 0;
+        insert_k<1>(v, j, tv, pos);
+        if (live && j >= 0 && zero_pivot_facet_k<2>(c, tv, dm) == pos) {
+            n_acol += leader;
+            live = false;
+            // capacity is at least twice the pairs: the insert cannot fail
+            if (leader)
+                (void)pair_insert(app, simplex_index(tv, 2, c.B), (e << 3) | pos,
+                                  (u64)(u32)v[0] | ((u64)(u32)v[1] << 16), 0);
+        }
+        // is the zero pivot cofacet itself in a zero apparent pair (for
+        // the emergent shortcut)?
+        const bool tj = live && j >= 0;
+        const int mt = tj ? zero_pivot_facet_k<2>(c, tv, dm) : -1;
+        int rt[2];
+        remove_k<2>(tv, mt < 0 ? 0 : mt, rt);
+        const bool ttest = tj && mt >= 0;
+        const int jt = scan_max_k<kBatchFilterG, 1>(c, rt, dm, pick_vertex(tv, mt), ttest);
+        if (live && leader) {
+            const int slot = atomicAdd(nsurv, 1);
+            if (slot < A.col_stride) {
+                surv.idx[slot] = e;
+                surv.diam[slot] = dm;
+                surv.j[slot] = j;
+                surv.tapp[slot] = (ttest && jt < 0) ? 1 : 0;
+            }
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        n_clear += __shfl_xor(n_clear, off, kWave);
+        n_acol += __shfl_xor(n_acol, off, kWave);
+        n_cand += __shfl_xor(n_cand, off, kWave);
+    }
+    if (lane == 0) {
+        atomicAdd(&cnt[0], n_cand);
+        atomicAdd(&cnt[1], n_clear);
+        atomicAdd(&cnt[2], n_acol);
+    }
+}
+
+// A workgroup that helps its cloud's leader (spread > 1). With the
+// distances in global memory it first filters its share of the edges (after
+// the leader's distances and H0); then it waits for the leader's sorted
+// columns, reduces columns from the shared cursor with its own scratch, adds
+// its counters and reports done.
+template <class Dist>
+__device__ void batch_follow(const BatchArgs &A, int wgL, int role, unsigned char *smem,
+                             RedShared<kBT> &RS) {
+    constexpr bool kLds = std::is_same<Dist, DistPacked>::value;
     const int tid = threadIdx.x;
     if (A.max_dim < 1) return; // no reduction: the leader waits for nobody
     int *sw = A.sync + (int64_t)wgL * kSyncWords;
     __shared__ int s_go;
+    if (!kLds) {
+        if (tid == 0) {
+            // the front flag, or the skip flag of a rejected cloud
+            const unsigned long long t0 = wall_clock64();
+            int go = 1;
+            while (ld_dev(&sw[kSyncFront]) == 0 && ld_dev(&sw[kSyncSkip]) == 0) {
+                if (wall_clock64() - t0 > kWaitTicks) {
+                    atomicOr(A.status, 8);
+                    go = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+            s_go = go && ld_dev(&sw[kSyncSkip]) == 0;
+        }
+        __syncthreads();
+        if (s_go) {
+            fence_acquire_dev(); // the leader's distances, forest edges and table
+            const int n = __builtin_amdgcn_readfirstlane(ld_dev(&sw[kSyncN]));
+            const float t = __int_as_float(__builtin_amdgcn_readfirstlane(ld_dev(&sw[kSyncT])));
+            const int64_t npairs = (int64_t)n * (n - 1) / 2;
+            float *Dgw = A.Dg + (int64_t)wgL * A.d_stride;
+            Ctx<Dist> c;
+            c.d = CloudDist<Dist>::make(Dgw, Dgw, n);
+            c.B = A.binom;
+            c.nb.off = nullptr;
+            c.nb.idx = nullptr;
+            c.n = n;
+            c.t = t;
+            const int64_t co = (int64_t)wgL * A.col_stride;
+            const Columns surv{A.c_idx0 + co, A.c_dm0 + co, A.c_j0 + co, A.c_t0 + co};
+            u32 appcap = 64;
+            while (appcap < 2u * (u32)npairs + 64u && (int64_t)appcap < A.ph_stride) appcap <<= 1;
+            const PairHash app{A.app_keys + (int64_t)wgL * A.ph_stride, A.app_vals + (int64_t)wgL * A.ph_stride,
+                               A.app_verts + (int64_t)wgL * A.ph_stride, nullptr, nullptr, nullptr, nullptr,
+                               appcap - 1};
+            batch_filter<Dist>(A, c, t, npairs, A.bits_g + (int64_t)wgL * A.bits_stride, surv, app, role,
+                               A.spread, &sw[kSyncSurv], A.par_stat + (int64_t)wgL * kSyncStats + 8);
+        }
+        // its survivors and table entries, then done
+        fence_release_dev();
+        __syncthreads();
+        if (tid == 0) atomicAdd(&sw[kSyncFiltered], 1);
+    }
     if (tid == 0) s_go = batch_wait(A, &sw[kSyncReady], 1) ? 1 : 0;
     __syncthreads();
     if (s_go) {
@@ -525,7 +648,6 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         c.t = t;
         Columns surv{A.c_idx0 + (int64_t)wg * A.col_stride, A.c_dm0 + (int64_t)wg * A.col_stride,
                      A.c_j0 + (int64_t)wg * A.col_stride, A.c_t0 + (int64_t)wg * A.col_stride};
-        const bool leader = (lane & (kBatchFilterG - 1)) == 0;
         // the zero apparent pairs (rho, tau) found here serve the reduction's
         // pivot tests (one lookup instead of facet and cofacet scans)
         u32 appcap = 64;
@@ -535,66 +657,35 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
                            appcap - 1};
         for (u32 q = tid; q < appcap; q += kBT) app.keys[q] = kEmpty;
         gsync();
-        unsigned long long n_clear = 0, n_acol = 0, n_cand = 0;
-        // one edge per group of kBatchFilterG lanes; the loop is uniform in
-        // the wave and the tests are predicates (the scans need every lane)
-        constexpr int kGroups = kWave / kBatchFilterG;
-        for (int64_t e0 = (int64_t)(tid / kWave) * kGroups; e0 < npairs; e0 += (kBT / kWave) * kGroups) {
-            const int64_t e = e0 + lane / kBatchFilterG;
-            bool live = e < npairs;
-            int v[2] = {0, 0};
-            float dm = 0.0f;
-            if (live) {
-                pair_of(e, &v[0], &v[1]);
-                dm = dist(v[0], v[1]);
-                live = dm <= t;
+        // with the distances in global memory the cloud's other workgroups
+        // filter their shares of the edges too (spread out)
+        const bool share = A.spread > 1 && !kLds;
+        int *sw0 = A.sync + (int64_t)wg * kSyncWords;
+        unsigned long long *fcnt = A.par_stat + (int64_t)wg * kSyncStats + 8;
+        if (share) {
+            if (tid < 3) fcnt[tid] = 0ull;
+            if (tid == 0) {
+                sw0[kSyncN] = n;
+                sw0[kSyncT] = __float_as_int(t);
             }
-            if (live) {
-                n_cand += leader;
-                if ((bits[e >> 5] >> (e & 31)) & 1u) {
-                    n_clear += leader;
-                    live = false;
-                }
-            }
-            const int j = scan_max_k<kBatchFilterG, 1>(c, v, dm, -1, live);
-            int tv[3];
-            int pos = 0;
-            insert_k<1>(v, j, tv, pos);
-            if (live && j >= 0 && zero_pivot_facet_k<2>(c, tv, dm) == pos) {
-                n_acol += leader;
-                live = false;
-                // capacity is at least twice the pairs: the insert cannot fail
-                if (leader)
-                    (void)pair_insert(app, simplex_index(tv, 2, c.B), (e << 3) | pos,
-                                      (u64)(u32)v[0] | ((u64)(u32)v[1] << 16), 0);
-            }
-            // is the zero pivot cofacet itself in a zero apparent pair (for
-            // the emergent shortcut)?
-            const bool tj = live && j >= 0;
-            const int mt = tj ? zero_pivot_facet_k<2>(c, tv, dm) : -1;
-            int rt[2];
-            remove_k<2>(tv, mt < 0 ? 0 : mt, rt);
-            const bool ttest = tj && mt >= 0;
-            const int jt = scan_max_k<kBatchFilterG, 1>(c, rt, dm, pick_vertex(tv, mt), ttest);
-            if (live && leader) {
-                const int slot = atomicAdd(&Sh.nsurv, 1);
-                if (slot < A.col_stride) {
-                    surv.idx[slot] = e;
-                    surv.diam[slot] = dm;
-                    surv.j[slot] = j;
-                    surv.tapp[slot] = (ttest && jt < 0) ? 1 : 0;
-                }
-            }
+            fence_release_dev();
+            gsync();
+            if (tid == 0) st_dev(&sw0[kSyncFront], 1);
         }
-        for (int off = 32; off >= 1; off >>= 1) {
-            n_clear += __shfl_xor(n_clear, off, kWave);
-            n_acol += __shfl_xor(n_acol, off, kWave);
-            n_cand += __shfl_xor(n_cand, off, kWave);
-        }
-        if (lane == 0) {
-            atomicAdd(&Sh.cnt[0], n_cand);
-            atomicAdd(&Sh.cnt[1], n_clear);
-            atomicAdd(&Sh.cnt[2], n_acol);
+        batch_filter<Dist>(A, c, t, npairs, bits, surv, app, 0, share ? A.spread : 1,
+                           share ? &sw0[kSyncSurv] : &Sh.nsurv, share ? fcnt : Sh.cnt);
+        if (share) {
+            fence_release_dev();
+            __syncthreads();
+            if (tid == 0) (void)batch_wait(A, &sw0[kSyncFiltered], A.spread - 1);
+            __syncthreads();
+            fence_acquire_dev();
+            if (tid == 0) {
+                Sh.nsurv = ld_dev(&sw0[kSyncSurv]);
+                Sh.cnt[0] = ld_dev(&fcnt[0]);
+                Sh.cnt[1] = ld_dev(&fcnt[1]);
+                Sh.cnt[2] = ld_dev(&fcnt[2]);
+            }
         }
         gsync();
         const int S = min(Sh.nsurv, (int)A.col_stride);
@@ -816,7 +907,7 @@ __global__ void __launch_bounds__(kBT) k_batched(BatchArgs A) {
         const int slot = w / A.spread, role = w - slot * A.spread;
         if (slot >= A.B) return;
         if (role == 0) batch_cloud<Dist>(A, A.order[slot], smem, Sh, RS, SS);
-        else batch_follow<Dist>(A, w - role, smem, RS);
+        else batch_follow<Dist>(A, w - role, role, smem, RS);
         return;
     }
     for (;;) {

@@ -95,10 +95,13 @@ struct BatchArgs {
 };
 
 // The words a cloud's leader shares with the other workgroups of its cloud
-// (spread > 1), zeroed before every launch: ready flag, n, t (bits), columns,
-// edges of the edge order, skip (the cloud has no reduction), reductions done.
+// (spread > 1), zeroed before every launch: ready flag (columns sorted, the
+// reduction may start), n, t (bits), columns, edges of the edge order, skip
+// (the cloud has no reduction), reductions done; with the distances in
+// global memory also: front flag (distances and H0 done, the filter may
+// start), survivors appended, filter shares done.
 enum : int { kSyncReady = 0, kSyncN = 1, kSyncT = 2, kSyncS = 3, kSyncE = 4, kSyncSkip = 5,
-             kSyncDone = 6, kSyncWords = 8 };
+             kSyncDone = 6, kSyncFront = 7, kSyncSurv = 8, kSyncFiltered = 9, kSyncWords = 16 };
 constexpr int kSyncStats = 16;
 
 
