@@ -262,16 +262,78 @@ __device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist>
     }
 }
 
+// The edges <= t in order of length, for the direct-mapped working column,
+// into workgroup wgT's tables (edge index -> position, position -> vertices,
+// length and run word); sb are the calling workgroup's sort buffers. Each
+// thread keeps a contiguous range of pair indices, so that the stable sort
+// leaves equal lengths in index order. Every thread calls it; returns the
+// number of edges.
+template <class Dist>
+__device__ __forceinline__ int batch_edge_order(const BatchArgs &A, const Dist &dist, float t, int64_t npairs,
+                                                SortBufs sb, SortShared<kBT> &SS, int *scan_w, int wgT) {
+    const int tid = threadIdx.x;
+    const int64_t chunk = (npairs + kBT - 1) / kBT;
+    const int64_t e0 = (int64_t)tid * chunk, e1 = min(npairs, e0 + chunk);
+    int cnt = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+        int a, cc;
+        pair_of(e, &a, &cc);
+        cnt += dist(a, cc) <= t ? 1 : 0;
+    }
+    int nE;
+    int at = block_scan_excl<kBT>(cnt, scan_w, &nE);
+    for (int64_t e = e0; e < e1; ++e) {
+        int a, cc;
+        pair_of(e, &a, &cc);
+        const float d = dist(a, cc);
+        if (d <= t) {
+            sb.lo[0][at] = 0;
+            sb.hi[0][at] = __float_as_uint(d);
+            sb.val[0][at] = (u32)e;
+            ++at;
+        }
+    }
+    gsync();
+    const int ce = block_radix_sort<kBT>(sb, nE, 0, 4, SS);
+    int *bpos = A.bm_pos + (int64_t)wgT * A.bm_tab_stride;
+    u32 *bv = A.bm_verts + (int64_t)wgT * A.bm_tab_stride;
+    float *bl = A.bm_len + (int64_t)wgT * A.bm_tab_stride;
+    u32 *br = A.bm_run + (int64_t)wgT * A.bm_tab_stride;
+    for (int q = tid; q < nE; q += kBT) {
+        const u32 e = sb.val[ce][q];
+        int a, cc;
+        pair_of(e, &a, &cc);
+        bpos[e] = q;
+        bv[q] = ((u32)a << 16) | (u32)cc;
+        bl[q] = __uint_as_float(sb.hi[ce][q]);
+    }
+    gsync();
+    // runs of equal lengths: first position, and whether the next
+    // position continues the run (keys are the length bits)
+    for (int q = tid; q < nE; q += kBT) {
+        const u32 key = sb.hi[ce][q];
+        int r = q;
+        while (r > 0 && sb.hi[ce][r - 1] == key) --r;
+        const bool tie = q + 1 < nE && sb.hi[ce][q + 1] == key;
+        br[q] = (u32)r | (tie ? kRunTie : 0u);
+    }
+    gsync();
+    return nE;
+}
+
 // A workgroup that helps its cloud's leader (spread > 1). With the
 // distances in global memory it first filters its share of the edges (after
 // the leader's distances and H0); then it waits for the leader's sorted
 // columns, reduces columns from the shared cursor with its own scratch, adds
 // its counters and reports done.
 template <class Dist>
-__device__ void batch_follow(const BatchArgs &A, int wgL, int role, unsigned char *smem,
-                             RedShared<kBT> &RS) {
+__device__ void batch_follow(const BatchArgs &A, int wgL, int role, unsigned char *smem, BatchShared &Sh,
+                             RedShared<kBT> &RS, SortShared<kBT> &SS) {
     constexpr bool kLds = std::is_same<Dist, DistPacked>::value;
     const int tid = threadIdx.x;
+    // with three or more workgroups the second builds the edge order
+    const bool ordering = A.spread >= 3 && A.bm_bits != nullptr;
+    const bool order_role = ordering && role == 1;
     if (A.max_dim < 1) return; // no reduction: the leader waits for nobody
     int *sw = A.sync + (int64_t)wgL * kSyncWords;
     __shared__ int s_go;
@@ -311,13 +373,29 @@ __device__ void batch_follow(const BatchArgs &A, int wgL, int role, unsigned cha
             const PairHash app{A.app_keys + (int64_t)wgL * A.ph_stride, A.app_vals + (int64_t)wgL * A.ph_stride,
                                A.app_verts + (int64_t)wgL * A.ph_stride, nullptr, nullptr, nullptr, nullptr,
                                appcap - 1};
-            batch_filter<Dist>(A, c, t, npairs, A.bits_g + (int64_t)wgL * A.bits_stride, surv, app, role,
-                               A.spread, &sw[kSyncSurv], A.par_stat + (int64_t)wgL * kSyncStats + 8);
+            if (order_role) {
+                // the edge order, into the leader's tables, with this
+                // workgroup's sort buffers
+                const int64_t wo = (int64_t)blockIdx.x * A.col_stride;
+                SortBufs sb;
+                sb.lo[0] = A.s_lo0 + wo;
+                sb.lo[1] = A.s_lo1 + wo;
+                sb.hi[0] = A.s_hi0 + wo;
+                sb.hi[1] = A.s_hi1 + wo;
+                sb.val[0] = A.s_v0 + wo;
+                sb.val[1] = A.s_v1 + wo;
+                const int nE = batch_edge_order<Dist>(A, c.d, t, npairs, sb, SS, Sh.w, wgL);
+                if (tid == 0) sw[kSyncE] = nE;
+            } else {
+                batch_filter<Dist>(A, c, t, npairs, A.bits_g + (int64_t)wgL * A.bits_stride, surv, app,
+                                   ordering ? role - 1 : role, ordering ? A.spread - 1 : A.spread,
+                                   &sw[kSyncSurv], A.par_stat + (int64_t)wgL * kSyncStats + 8);
+            }
         }
-        // its survivors and table entries, then done
+        // its survivors and table entries (or the edge order), then done
         fence_release_dev();
         __syncthreads();
-        if (tid == 0) atomicAdd(&sw[kSyncFiltered], 1);
+        if (tid == 0) atomicAdd(&sw[order_role ? kSyncOrdered : kSyncFiltered], 1);
     }
     if (tid == 0) s_go = batch_wait(A, &sw[kSyncReady], 1) ? 1 : 0;
     __syncthreads();
@@ -672,12 +750,15 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
             gsync();
             if (tid == 0) st_dev(&sw0[kSyncFront], 1);
         }
-        batch_filter<Dist>(A, c, t, npairs, bits, surv, app, 0, share ? A.spread : 1,
+        // (with three or more workgroups the second one builds the edge
+        // order meanwhile and filters nothing)
+        const int fparts = share ? (A.spread >= 3 && A.bm_bits ? A.spread - 1 : A.spread) : 1;
+        batch_filter<Dist>(A, c, t, npairs, bits, surv, app, 0, fparts,
                            share ? &sw0[kSyncSurv] : &Sh.nsurv, share ? fcnt : Sh.cnt);
         if (share) {
             fence_release_dev();
             __syncthreads();
-            if (tid == 0) (void)batch_wait(A, &sw0[kSyncFiltered], A.spread - 1);
+            if (tid == 0) (void)batch_wait(A, &sw0[kSyncFiltered], fparts - 1);
             __syncthreads();
             fence_acquire_dev();
             if (tid == 0) {
@@ -707,57 +788,22 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
             cols.tapp[q] = surv.tapp[e];
         }
         // ---- the edges <= t in order of length, for the direct-mapped
-        // working column: each thread keeps a contiguous range of pair
-        // indices, so that the stable sort leaves equal lengths in index order
+        // working column (by the cloud's second workgroup, during the
+        // filter, when the cloud has three or more)
+        const bool offload = share && A.spread >= 3 && A.bm_bits;
         EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, 0, 0};
         if (A.bm_bits) {
-            const int64_t chunk = (npairs + kBT - 1) / kBT;
-            const int64_t e0 = (int64_t)tid * chunk, e1 = min(npairs, e0 + chunk);
-            int cnt = 0;
-            for (int64_t e = e0; e < e1; ++e) {
-                int a, cc;
-                pair_of(e, &a, &cc);
-                cnt += dist(a, cc) <= t ? 1 : 0;
-            }
             int nE;
-            int at = block_scan_excl<kBT>(cnt, Sh.w, &nE);
-            for (int64_t e = e0; e < e1; ++e) {
-                int a, cc;
-                pair_of(e, &a, &cc);
-                const float d = dist(a, cc);
-                if (d <= t) {
-                    sb.lo[0][at] = 0;
-                    sb.hi[0][at] = __float_as_uint(d);
-                    sb.val[0][at] = (u32)e;
-                    ++at;
-                }
+            if (offload) {
+                if (tid == 0) (void)batch_wait(A, &sw0[kSyncOrdered], 1);
+                __syncthreads();
+                fence_acquire_dev();
+                nE = __builtin_amdgcn_readfirstlane(ld_dev(&sw0[kSyncE]));
+            } else {
+                nE = batch_edge_order<Dist>(A, dist, t, npairs, sb, SS, Sh.w, wg);
             }
-            gsync();
-            const int ce = block_radix_sort<kBT>(sb, nE, 0, 4, SS);
-            int *bpos = A.bm_pos + (int64_t)wg * A.bm_tab_stride;
-            u32 *bv = A.bm_verts + (int64_t)wg * A.bm_tab_stride;
-            float *bl = A.bm_len + (int64_t)wg * A.bm_tab_stride;
-            u32 *br = A.bm_run + (int64_t)wg * A.bm_tab_stride;
-            for (int q = tid; q < nE; q += kBT) {
-                const u32 e = sb.val[ce][q];
-                int a, cc;
-                pair_of(e, &a, &cc);
-                bpos[e] = q;
-                bv[q] = ((u32)a << 16) | (u32)cc;
-                bl[q] = __uint_as_float(sb.hi[ce][q]);
-            }
-            gsync();
-            // runs of equal lengths: first position, and whether the next
-            // position continues the run (keys are the length bits)
-            for (int q = tid; q < nE; q += kBT) {
-                const u32 key = sb.hi[ce][q];
-                int r = q;
-                while (r > 0 && sb.hi[ce][r - 1] == key) --r;
-                const bool tie = q + 1 < nE && sb.hi[ce][q + 1] == key;
-                br[q] = (u32)r | (tie ? kRunTie : 0u);
-            }
-            gsync();
-            eo = EdgeOrder{bpos, bv, bl, br, nE, (n + 31) / 32};
+            const int64_t to = (int64_t)wg * A.bm_tab_stride;
+            eo = EdgeOrder{A.bm_pos + to, A.bm_verts + to, A.bm_len + to, A.bm_run + to, nE, (n + 31) / 32};
         }
         // ---- the reduction reads D from global; LDS now holds its working column
         if (kLds)
@@ -907,7 +953,7 @@ __global__ void __launch_bounds__(kBT) k_batched(BatchArgs A) {
         const int slot = w / A.spread, role = w - slot * A.spread;
         if (slot >= A.B) return;
         if (role == 0) batch_cloud<Dist>(A, A.order[slot], smem, Sh, RS, SS);
-        else batch_follow<Dist>(A, w - role, role, smem, RS);
+        else batch_follow<Dist>(A, w - role, role, smem, Sh, RS, SS);
         return;
     }
     for (;;) {

@@ -99,9 +99,10 @@ struct BatchArgs {
 // reduction may start), n, t (bits), columns, edges of the edge order, skip
 // (the cloud has no reduction), reductions done; with the distances in
 // global memory also: front flag (distances and H0 done, the filter may
-// start), survivors appended, filter shares done.
+// start), survivors appended, filter shares done, edge order done.
 enum : int { kSyncReady = 0, kSyncN = 1, kSyncT = 2, kSyncS = 3, kSyncE = 4, kSyncSkip = 5,
-             kSyncDone = 6, kSyncFront = 7, kSyncSurv = 8, kSyncFiltered = 9, kSyncWords = 16 };
+             kSyncDone = 6, kSyncFront = 7, kSyncSurv = 8, kSyncFiltered = 9, kSyncOrdered = 10,
+             kSyncWords = 16 };
 constexpr int kSyncStats = 16;
 
 
