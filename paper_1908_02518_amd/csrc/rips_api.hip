@@ -195,6 +195,8 @@ enum BufId {
     BB_BM_VERTS,
     BB_BM_LEN,
     BB_BM_RUN,
+    BB_BM_APP,
+    BB_BM_APPE,
     BB_BM_BITS,
     // workgroups that share one cloud (spread-out batched reduction)
     BB_SYNC,
@@ -206,6 +208,7 @@ enum BufId {
     B_BM_VERTS,
     B_BM_LEN,
     B_BM_RUN,
+    B_BM_APP,
     B_BM_BITS,
     B_BM_SORT_LO0,
     B_BM_SORT_LO1,
@@ -1060,12 +1063,12 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
         const bool bm = k == 1 && p == 2 && S > 0 && !C.arena && !P.sparse &&
                         C.working_column == RIPS_WORKING_COLUMN_AUTO &&
                         C.shortcuts == (kShortApparent | kShortEmergent | kShortClearing) &&
-                        C.rstore == kRStoreAuto && bmW <= 62 && nE > 0 && nE <= (1 << 18) &&
+                        C.rstore == kRStoreAuto && bmW <= 60 && nE > 0 && nE <= (1 << 18) &&
                         groups * nE * bmW * 4 <= (8ll << 30) &&
                         reduce_lds_bytes(256) + bm_lds_bytes(nE) <= lds_budget;
         uint32_t capD = kMaxDelta;
         while (capD > 256 && reduce_lds_bytes(capD) + (bm ? bm_lds_bytes(nE) : 0) > lds_budget) capD >>= 1;
-        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, 0, 0};
+        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
         u32 *bm_bits = nullptr;
         if (bm) {
             HIP_TRY(C.ensure(B_BM_POS, (size_t)choose_i64(n, 2) * 4 + 16, &q));
@@ -1076,6 +1079,8 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             float *blen = as<float>(q);
             HIP_TRY(C.ensure(B_BM_RUN, (size_t)nE * 4, &q));
             u32 *brun = as<u32>(q);
+            HIP_TRY(C.ensure(B_BM_APP, (size_t)nE * 4, &q));
+            int *bapp = as<int>(q);
             SortBufs eb;
             HIP_TRY(C.ensure(B_BM_SORT_LO0, (size_t)nE * 8, &q));
             eb.lo[0] = as<u64>(q);
@@ -1099,9 +1104,9 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             }
             {
                 PROF(P_SORT1);
-                launch_bm_edge_order(P.E, (int)nE, eb, bpos, bverts, blen, brun, st);
+                launch_bm_edge_order(P.E, (int)nE, choose_i64(n, 2), eb, bpos, bverts, blen, brun, app, bapp, st);
             }
-            eo = EdgeOrder{bpos, bverts, blen, brun, (int)nE, (int)bmW};
+            eo = EdgeOrder{bpos, bverts, blen, brun, bapp, (int)nE, (int)bmW};
         }
         int64_t fcap = spread ? std::max<int64_t>(C.hint_far, 1 << 16)
                               : std::max<int64_t>(C.hint_far, std::max<int64_t>(1 << 18, 256ll * bound));
@@ -1641,6 +1646,8 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
         ENS(BB_BM_VERTS, G * npairs * 4, A.bm_verts, u32);
         ENS(BB_BM_LEN, G * npairs * 4, A.bm_len, float);
         ENS(BB_BM_RUN, G * npairs * 4, A.bm_run, u32);
+        ENS(BB_BM_APP, G * npairs * 4, A.bm_app, int);
+        ENS(BB_BM_APPE, G * npairs * 4, A.bm_appe, int);
         A.bm_tab_stride = npairs;
         ENS(BB_BM_BITS, G * npairs * W * 4, A.bm_bits, u32);
         A.bm_stride = npairs * W;

@@ -113,9 +113,9 @@ __device__ __forceinline__ ReduceJob<Dist> batch_job(const BatchArgs &A, int wgL
     J.prev_bits = nullptr;
     J.prev = PivotHash{nullptr, nullptr, 0};
     const int64_t to = (int64_t)wgL * A.bm_tab_stride;
-    J.eo = A.bm_bits ? EdgeOrder{A.bm_pos + to, A.bm_verts + to, A.bm_len + to, A.bm_run + to, nE,
-                                 (n + 31) / 32}
-                     : EdgeOrder{nullptr, nullptr, nullptr, nullptr, 0, 0};
+    J.eo = A.bm_bits ? EdgeOrder{A.bm_pos + to, A.bm_verts + to, A.bm_len + to, A.bm_run + to,
+                                 A.bm_app + to, nE, (n + 31) / 32}
+                     : EdgeOrder{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
     J.bm_bits = A.bm_bits;
     J.bm_stride = A.bm_stride;
     return J;
@@ -190,11 +190,14 @@ __device__ __forceinline__ void batch_par_stats(const BatchArgs &A, int wgL, con
 // The dimension-1 enumeration / apparent-pair filter over share `part` of
 // `nparts` of the edges (interleaved by wave): survivors appended through
 // *nsurv, zero apparent pairs inserted into app, the counts of candidates,
-// cleared and apparent columns added to cnt[0..2]. Every thread calls it.
+// cleared and apparent columns added to cnt[0..2]; with appe (the
+// direct-mapped column), appe[e] = the third vertex of edge e's zero
+// apparent cofacet, or -1, for every edge of the share. Every thread calls it.
 template <class Dist>
 __device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist> &c, float t, int64_t npairs,
                                              const u32 *bits, const Columns &surv, const PairHash &app,
-                                             int part, int nparts, int *nsurv, unsigned long long *cnt) {
+                                             int *appe, int part, int nparts, int *nsurv,
+                                             unsigned long long *cnt) {
     const int tid = threadIdx.x, lane = lane_id();
     const Dist dist = c.d;
     const bool leader = (lane & (kBatchFilterG - 1)) == 0;
@@ -224,7 +227,8 @@ __device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist>
         int tv[3];
         int pos = 0;
         insert_k<1>(v, j, tv, pos);
-        if (live && j >= 0 && zero_pivot_facet_k<2>(c, tv, dm) == pos) {
+        const bool zap = live && j >= 0 && zero_pivot_facet_k<2>(c, tv, dm) == pos;
+        if (zap) {
             n_acol += leader;
             live = false;
             // capacity is at least twice the pairs: the insert cannot fail
@@ -232,6 +236,7 @@ __device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist>
                 (void)pair_insert(app, simplex_index(tv, 2, c.B), (e << 3) | pos,
                                   (u64)(u32)v[0] | ((u64)(u32)v[1] << 16), 0);
         }
+        if (appe != nullptr && leader && e < npairs) appe[e] = zap ? j : -1;
         // is the zero pivot cofacet itself in a zero apparent pair (for
         // the emergent shortcut)?
         const bool tj = live && j >= 0;
@@ -262,15 +267,28 @@ __device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist>
     }
 }
 
+// Per position of workgroup wgT's edge order, the third vertex of the
+// edge's zero apparent cofacet, from the filter's per-edge values (the edge
+// of position q is sb.val[ce][q]); after the whole filter. Every thread
+// calls it.
+__device__ __forceinline__ void batch_map_app(const BatchArgs &A, SortBufs sb, int ce, int nE, int wgT) {
+    const int *appe = A.bm_appe + (int64_t)wgT * A.bm_tab_stride;
+    int *app = A.bm_app + (int64_t)wgT * A.bm_tab_stride;
+    for (int q = threadIdx.x; q < nE; q += kBT) app[q] = appe[sb.val[ce][q]];
+    gsync();
+}
+
 // The edges <= t in order of length, for the direct-mapped working column,
-// into workgroup wgT's tables (edge index -> position, position -> vertices,
-// length and run word); sb are the calling workgroup's sort buffers. Each
-// thread keeps a contiguous range of pair indices, so that the stable sort
-// leaves equal lengths in index order. Every thread calls it; returns the
-// number of edges.
+// into workgroup wgT's tables (edge index -> position, -1 for an edge longer
+// than t; position -> vertices, length and run word); sb are the calling
+// workgroup's sort buffers, *ce the one that holds the order. Each thread
+// keeps a contiguous range of pair indices, so that the stable sort leaves
+// equal lengths in index order. Every thread calls it; returns the number
+// of edges.
 template <class Dist>
 __device__ __forceinline__ int batch_edge_order(const BatchArgs &A, const Dist &dist, float t, int64_t npairs,
-                                                SortBufs sb, SortShared<kBT> &SS, int *scan_w, int wgT) {
+                                                SortBufs sb, SortShared<kBT> &SS, int *scan_w, int wgT,
+                                                int *ce_out) {
     const int tid = threadIdx.x;
     const int64_t chunk = (npairs + kBT - 1) / kBT;
     const int64_t e0 = (int64_t)tid * chunk, e1 = min(npairs, e0 + chunk);
@@ -282,6 +300,7 @@ __device__ __forceinline__ int batch_edge_order(const BatchArgs &A, const Dist &
     }
     int nE;
     int at = block_scan_excl<kBT>(cnt, scan_w, &nE);
+    int *bpos = A.bm_pos + (int64_t)wgT * A.bm_tab_stride;
     for (int64_t e = e0; e < e1; ++e) {
         int a, cc;
         pair_of(e, &a, &cc);
@@ -291,11 +310,13 @@ __device__ __forceinline__ int batch_edge_order(const BatchArgs &A, const Dist &
             sb.hi[0][at] = __float_as_uint(d);
             sb.val[0][at] = (u32)e;
             ++at;
+        } else {
+            bpos[e] = -1;
         }
     }
     gsync();
     const int ce = block_radix_sort<kBT>(sb, nE, 0, 4, SS);
-    int *bpos = A.bm_pos + (int64_t)wgT * A.bm_tab_stride;
+    *ce_out = ce;
     u32 *bv = A.bm_verts + (int64_t)wgT * A.bm_tab_stride;
     float *bl = A.bm_len + (int64_t)wgT * A.bm_tab_stride;
     u32 *br = A.bm_run + (int64_t)wgT * A.bm_tab_stride;
@@ -384,10 +405,18 @@ __device__ void batch_follow(const BatchArgs &A, int wgL, int role, unsigned cha
                 sb.hi[1] = A.s_hi1 + wo;
                 sb.val[0] = A.s_v0 + wo;
                 sb.val[1] = A.s_v1 + wo;
-                const int nE = batch_edge_order<Dist>(A, c.d, t, npairs, sb, SS, Sh.w, wgL);
+                int ce;
+                const int nE = batch_edge_order<Dist>(A, c.d, t, npairs, sb, SS, Sh.w, wgL, &ce);
+                // the apparent vertices by position, once every share of
+                // the filter (the leader's too) is done
+                if (tid == 0) (void)batch_wait(A, &sw[kSyncFiltered], A.spread - 1);
+                __syncthreads();
+                fence_acquire_dev();
+                batch_map_app(A, sb, ce, nE, wgL);
                 if (tid == 0) sw[kSyncE] = nE;
             } else {
-                batch_filter<Dist>(A, c, t, npairs, A.bits_g + (int64_t)wgL * A.bits_stride, surv, app,
+                int *appe = A.bm_bits ? A.bm_appe + (int64_t)wgL * A.bm_tab_stride : nullptr;
+                batch_filter<Dist>(A, c, t, npairs, A.bits_g + (int64_t)wgL * A.bits_stride, surv, app, appe,
                                    ordering ? role - 1 : role, ordering ? A.spread - 1 : A.spread,
                                    &sw[kSyncSurv], A.par_stat + (int64_t)wgL * kSyncStats + 8);
             }
@@ -753,12 +782,18 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         // (with three or more workgroups the second one builds the edge
         // order meanwhile and filters nothing)
         const int fparts = share ? (A.spread >= 3 && A.bm_bits ? A.spread - 1 : A.spread) : 1;
-        batch_filter<Dist>(A, c, t, npairs, bits, surv, app, 0, fparts,
+        int *appe = A.bm_bits ? A.bm_appe + (int64_t)wg * A.bm_tab_stride : nullptr;
+        batch_filter<Dist>(A, c, t, npairs, bits, surv, app, appe, 0, fparts,
                            share ? &sw0[kSyncSurv] : &Sh.nsurv, share ? fcnt : Sh.cnt);
         if (share) {
+            // this share done (the edge-order workgroup waits for every
+            // share), then the others'
             fence_release_dev();
             __syncthreads();
-            if (tid == 0) (void)batch_wait(A, &sw0[kSyncFiltered], fparts - 1);
+            if (tid == 0) {
+                atomicAdd(&sw0[kSyncFiltered], 1);
+                (void)batch_wait(A, &sw0[kSyncFiltered], fparts);
+            }
             __syncthreads();
             fence_acquire_dev();
             if (tid == 0) {
@@ -791,7 +826,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         // working column (by the cloud's second workgroup, during the
         // filter, when the cloud has three or more)
         const bool offload = share && A.spread >= 3 && A.bm_bits;
-        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, 0, 0};
+        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
         if (A.bm_bits) {
             int nE;
             if (offload) {
@@ -800,10 +835,13 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
                 fence_acquire_dev();
                 nE = __builtin_amdgcn_readfirstlane(ld_dev(&sw0[kSyncE]));
             } else {
-                nE = batch_edge_order<Dist>(A, dist, t, npairs, sb, SS, Sh.w, wg);
+                int ce;
+                nE = batch_edge_order<Dist>(A, dist, t, npairs, sb, SS, Sh.w, wg, &ce);
+                batch_map_app(A, sb, ce, nE, wg);
             }
             const int64_t to = (int64_t)wg * A.bm_tab_stride;
-            eo = EdgeOrder{A.bm_pos + to, A.bm_verts + to, A.bm_len + to, A.bm_run + to, nE, (n + 31) / 32};
+            eo = EdgeOrder{A.bm_pos + to, A.bm_verts + to, A.bm_len + to, A.bm_run + to, A.bm_app + to, nE,
+                           (n + 31) / 32};
         }
         // ---- the reduction reads D from global; LDS now holds its working column
         if (kLds)
@@ -1068,7 +1106,7 @@ size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD, bool bm) {
 bool batched_bm_fits(int nmax, int max_dim, u32 p, int64_t grid) {
     const int64_t npairs = (int64_t)nmax * (nmax - 1) / 2;
     const int64_t W = (nmax + 31) / 32;
-    return p == 2 && max_dim >= 1 && W <= 62 && npairs <= (1 << 18) &&
+    return p == 2 && max_dim >= 1 && W <= 60 && npairs <= (1 << 18) &&
            grid * npairs * W * 4 <= (8ll << 30);
 }
 

@@ -80,6 +80,8 @@ struct BatchArgs {
     u32 *bm_verts;
     float *bm_len;
     u32 *bm_run;
+    int *bm_app;                    // position -> third vertex of its zero apparent cofacet, or -1
+    int *bm_appe;                   // the same by edge index, written by the filter
     int64_t bm_tab_stride;          // C(nmax, 2)
     u32 *bm_bits;                   // all zero between columns
     int64_t bm_stride;              // C(nmax, 2) * ceil(nmax / 32) words

@@ -268,6 +268,35 @@ __device__ __forceinline__ void st(LDS T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Pointers into global memory carry the global address space where it
+// matters. A pointer read from memory (the reduction's job record is copied
+// to LDS) is generic, and a generic access compiles to a flat instruction,
+// which counts on the LDS counter as well as on the vector-memory counter:
+// every later LDS wait of the wave then also waits for that global access
+// (an atomic to a line in HBM, say). gp() casts a pointer that is known to
+// point to global memory.
+#define GLB __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ GLB T *gp(T *p) {
+    return (GLB T *)p;
+}
+
+template <class T>
+__device__ __forceinline__ const GLB T *gp(const T *p) {
+    return (const GLB T *)p;
+}
+
+template <class T>
+__device__ __forceinline__ T ld(const GLB T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <class T>
+__device__ __forceinline__ void st(GLB T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Hand-over point between the lanes of one wave, for code that one wave
 // runs alone (no workgroup barrier): values that other lanes stored to
 // shared or global memory before it are read after it. Without it the
@@ -442,8 +471,8 @@ struct PivotHash {
 __device__ __forceinline__ int32_t ph_find(const PivotHash &h, int64_t key) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
-        const int64_t cur = ld(&h.keys[s]);
-        if (cur == key) return ld(&h.vals[s]);
+        const int64_t cur = ld(gp(&h.keys[s]));
+        if (cur == key) return ld(gp(&h.vals[s]));
         if (cur == kEmpty) return -1;
         s = (s + 1) & h.mask;
     }
@@ -529,11 +558,11 @@ __device__ __forceinline__ PairHit pair_find_all(const PairHash &h, int64_t key)
     PairHit r{-1, kNoVerts, 0, kNoList};
     for (u32 probe = 0; probe <= h.mask; ++probe) {
         // the slot's words are loaded together: one round trip per probe
-        const int64_t cur = h.keys[s];
-        const int64_t v = h.vals[s];
-        const u64 w = h.verts ? h.verts[s] : kNoVerts;
-        const u64 nb = h.nbr ? h.nbr[s] : 0;
-        const u64 cb = h.cob ? h.cob[s] : kNoList;
+        const int64_t cur = gp(h.keys)[s];
+        const int64_t v = gp(h.vals)[s];
+        const u64 w = h.verts ? gp(h.verts)[s] : kNoVerts;
+        const u64 nb = h.nbr ? gp(h.nbr)[s] : 0;
+        const u64 cb = h.cob ? gp(h.cob)[s] : kNoList;
         if (cur == key) {
             r.val = v;
             r.verts = w;
@@ -553,8 +582,8 @@ __device__ __forceinline__ PairHit pair_find_all(const PairHash &h, int64_t key)
 __device__ __forceinline__ int64_t pair_find(const PairHash &h, int64_t key) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
-        const int64_t cur = h.keys[s];
-        const int64_t v = h.vals[s];
+        const int64_t cur = gp(h.keys)[s];
+        const int64_t v = gp(h.vals)[s];
         if (cur == key) return v;
         if (cur == kEmpty) return -1;
         s = (s + 1) & h.mask;

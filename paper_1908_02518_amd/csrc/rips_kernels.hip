@@ -1260,9 +1260,39 @@ __global__ void __launch_bounds__(1024) k_bm_edge_order(EdgeList E, int nE, Sort
     }
 }
 
-void launch_bm_edge_order(EdgeList E, int nE, SortBufs sb, int *pos, u32 *verts, float *len, u32 *run,
-                          hipStream_t st) {
+// Per edge position, the third vertex of the edge's zero apparent cofacet:
+// for every pair (rho, tau) of the table, app[pos(rho)] = the vertex of tau
+// off rho (app holds -1 elsewhere).
+__global__ void k_bm_app(PairHash tab, const int *pos, int *app) {
+    const u32 cap = tab.mask + 1;
+    for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
+        const int64_t tau = tab.keys[q];
+        if (tau == kEmpty) continue;
+        const int64_t rho = tab.vals[q] >> 3;
+        int a, b;
+        edge_vertices((u32)rho, &a, &b);
+        // tau = C(x, 3) + C(y, 2) + z with x > y > z
+        int x = (int)cbrt(6.0 * (double)tau) + 1;
+        while ((int64_t)x * (x - 1) * (x - 2) / 6 > tau) --x;
+        while ((int64_t)(x + 1) * x * (x - 1) / 6 <= tau) ++x;
+        int y, z;
+        edge_vertices((u32)(tau - (int64_t)x * (x - 1) * (x - 2) / 6), &y, &z);
+        const int c = (x != a && x != b) ? x : (y != a && y != b) ? y : z;
+        const int p = pos[rho];
+        if (p >= 0) app[p] = c;
+    }
+}
+
+void launch_bm_edge_order(EdgeList E, int nE, int64_t npairs, SortBufs sb, int *pos, u32 *verts, float *len,
+                          u32 *run, PairHash app_tab, int *app, hipStream_t st) {
+    launch_fill_u32((u32 *)pos, npairs, 0xffffffffu, st);
+    launch_fill_u32((u32 *)app, nE, 0xffffffffu, st);
     hipLaunchKernelGGL(k_bm_edge_order, dim3(1), dim3(1024), 0, st, E, nE, sb, pos, verts, len, run);
+    if (app_tab.keys) {
+        const int64_t cap = (int64_t)app_tab.mask + 1;
+        const unsigned blocks = (unsigned)std::min<int64_t>(1024, (cap + 255) / 256);
+        hipLaunchKernelGGL(k_bm_app, dim3(blocks), dim3(256), 0, st, app_tab, (const int *)pos, app);
+    }
 }
 
 void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Columns out,

@@ -301,14 +301,17 @@ struct ParState {
 };
 
 // The edges <= t in order of length, for the direct-mapped working column of
-// dimension 1 (rips_reduce_bm.hpp): edge CNS index -> position, position ->
-// vertices (a << 16 | b, a > b) and length. E == 0: not in use.
+// dimension 1 (rips_reduce_bm.hpp): edge CNS index -> position (-1 for an
+// edge longer than t), position -> vertices (a << 16 | b, a > b) and length.
+// E == 0: not in use.
 struct EdgeOrder {
     const int *pos;
     const u32 *verts;
     const float *len;
     const u32 *run; // position -> first position of its run of equal lengths,
                     // with kRunTie set when the next position has the same length
+    const int *app; // position -> the third vertex c of the edge's zero apparent
+                    // cofacet (the edge and {a, b, c} are a zero apparent pair), or -1
     int E;
     int W; // 32-bit words of one edge's bitmap: ceil(n / 32)
 };
@@ -366,7 +369,7 @@ struct ReduceJob {
     PivotHash prev;
     // direct-mapped working column (dimension 1, Z/2, every shortcut on):
     // bm_bits == null means the general working column is used
-    EdgeOrder eo = {nullptr, nullptr, nullptr, nullptr, 0, 0};
+    EdgeOrder eo = {nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
     u32 *bm_bits = nullptr; // eo.E * eo.W words per workgroup, all zero between columns
     int64_t bm_stride = 0;  // words per workgroup (workgroup blockIdx.x uses its own)
 };
@@ -431,7 +434,18 @@ struct RedShared {
     do {                                                                                           \
         if (threadIdx.x == 0) (S).tm[i] += wall_clock64() - v;                                     \
     } while (0)
+// the same for any thread (cond), accumulated atomically
+#define RED_TW0(v, cond) const unsigned long long v = (cond) ? wall_clock64() : 0ull
+#define RED_TW1(S, i, v, cond)                                                                     \
+    do {                                                                                           \
+        if (cond) atomicAdd(&(S).tm[i], wall_clock64() - v);                                       \
+    } while (0)
 #else
+#define RED_TW0(v, cond) const unsigned long long v = 0ull
+#define RED_TW1(S, i, v, cond)                                                                     \
+    do {                                                                                           \
+        (void)(v);                                                                                 \
+    } while (0)
 #define RED_T0(v) const unsigned long long v = 0ull
 #define RED_T1(S, i, v)                                                                            \
     do {                                                                                           \
@@ -1425,9 +1439,9 @@ template <int BT>
 __device__ __forceinline__ bool log_add(const ReduceScratch &SC, RedShared<BT> &S, int64_t key,
                                         u32 coef, float dm, int64_t vlen) {
     if ((int64_t)S.nlog >= SC.lcap) return false;
-    SC.lkey[S.nlog] = key;
-    SC.lcoef[S.nlog] = coef;
-    SC.ldia[S.nlog] = dm;
+    gp(SC.lkey)[S.nlog] = key;
+    gp(SC.lcoef)[S.nlog] = coef;
+    gp(SC.ldia)[S.nlog] = dm;
     S.nlog += 1;
     S.vest += vlen;
     return true;

@@ -1,21 +1,30 @@
 // rips_reduce_bm.hpp -- the reduction of the dimension-1 columns over Z/2
 // with a direct-mapped working column (included by rips_reduce.hpp).
 //
-// The rows of a dimension-1 coboundary column are triangles. A triangle's
-// diameter is the length of its longest edge, its "owner" (the first of the
-// edges xy, xz, yz of its decreasing vertices x > y > z whose length is the
-// diameter), and among the triangles of one owner edge {a, b} the CNS index
-// grows with the third vertex c. The working column R_j is therefore held
-// as one bit per (owner edge, third vertex): the edges <= t are put in order
-// of length once per dimension (position = rank), and bit c of edge
-// position e is set when the triangle {a_e, b_e, c} is in R_j (over Z/2 an
-// addition is an XOR). The oldest entry (smallest diameter, then largest
+// The rows of a dimension-1 coboundary column are triangles. The edges <= t
+// are put in order of length once per dimension (position = rank; equal
+// lengths in any order). A triangle's "owner" is its edge of the latest
+// position, so the triangle's diameter (the length of its longest edge) is
+// the owner's length, and among the triangles of one edge {a, b} the CNS
+// index grows with the third vertex c. The working column R_j is therefore
+// held as one bit per (owner position, third vertex): bit c of position e is
+// set when the triangle {a_e, b_e, c} is in R_j (over Z/2 an addition is an
+// XOR), and a triangle's coordinate needs the positions of its three edges
+// only, no distances. The oldest entry (smallest diameter, then largest
 // index) is the highest set bit of the first edge position with a set bit,
 // compared across the run of positions of exactly that length. A summary in
 // LDS marks the positions that may hold set bits (one bit per position, and
 // one bit per 32 of those); it is cleared lazily as the pivot search finds
 // positions empty. The pivot only moves to younger rows while a column is
 // reduced, so the search starts from a front that only moves forward.
+//
+// Zero apparent pairs (section "Apparent pairs"): when no other edge has the
+// owner's length, a triangle's only facet of its own diameter is its owner,
+// so the triangle is in a zero apparent pair exactly when it is the owner's
+// zero apparent cofacet. The third vertex of that cofacet is kept per
+// position (EdgeOrder::app) and read in the same round trip as the bitmap
+// words, so such a pivot needs no table lookup; in runs of equal lengths the
+// pair table is asked as before.
 //
 // Compared with the general working column (delta, sorted base, far list)
 // there is no merge, no sorting and no spill: an addition costs one XOR per
@@ -38,56 +47,37 @@ __device__ __forceinline__ int64_t bm_tri_index(int a, int b, int c) {
     return (int64_t)x * (x - 1) * (x - 2) / 6 + (int64_t)y * (y - 1) / 2 + z;
 }
 
-// Owner edge and third vertex of the triangle {x, y, z}, x > y > z, with
-// edge lengths lxy, lxz, lyz and diameter dm (their maximum): the first of
-// xy, xz, yz whose length is dm.
-__device__ __forceinline__ void bm_owner(int x, int y, int z, float lxy, float lxz, float dm, int *a,
-                                         int *b, int *c) {
-    if (lxy == dm) {
-        *a = x;
-        *b = y;
-        *c = z;
-    } else if (lxz == dm) {
-        *a = x;
-        *b = z;
-        *c = y;
-    } else {
-        *a = y;
-        *b = z;
-        *c = x;
-    }
+__device__ __forceinline__ int64_t bm_edge_index(int a, int b) {
+    const int x = max(a, b), y = min(a, b);
+    return (int64_t)x * (x - 1) / 2 + y;
 }
 
-// Bitmap coordinate of the triangle sigma u {w} of the edge (u, v), u > v,
-// of length luv; -1 when the triangle is longer than t or w is u or v.
-template <class Dist>
-__device__ __forceinline__ int64_t bm_coord(const Ctx<Dist> &c, const EdgeOrder &eo, int u, int v,
-                                            float luv, int w) {
+// Bitmap coordinate of the triangle {u, v, w}, puv the position of the edge
+// uv: the owner is the edge of the latest position, the coordinate its
+// position and the vertex off it; -1 when w is u or v, or when an edge is
+// longer than t (no position).
+__device__ __forceinline__ int64_t bm_coord(const EdgeOrder &eo, int u, int v, int puv, int w) {
     if (w == u || w == v) return -1;
-    const float luw = c.d(u, w), lvw = c.d(v, w);
-    const float dm = fmaxf(luv, fmaxf(luw, lvw));
-    if (!(dm <= c.t)) return -1;
-    // decreasing vertices x > y > z, with the lengths of xy and xz
-    int x, y, z;
-    float lxy, lxz;
-    if (w > u) {
-        x = w; y = u; z = v; lxy = luw; lxz = lvw;
-    } else if (w > v) {
-        x = u; y = w; z = v; lxy = luw; lxz = luv;
-    } else {
-        x = u; y = v; z = w; lxy = luv; lxz = luw;
+    const int puw = gp(eo.pos)[bm_edge_index(u, w)];
+    const int pvw = gp(eo.pos)[bm_edge_index(v, w)];
+    if (puw < 0 || pvw < 0) return -1;
+    int po = puv, cc = w;
+    if (puw > po) {
+        po = puw;
+        cc = v;
     }
-    int a, b, cc;
-    bm_owner(x, y, z, lxy, lxz, dm, &a, &b, &cc);
-    const int pos = eo.pos[(int64_t)a * (a - 1) / 2 + b];
-    return ((int64_t)pos << 16) | cc;
+    if (pvw > po) {
+        po = pvw;
+        cc = u;
+    }
+    return ((int64_t)po << 16) | cc;
 }
 
 // XOR one entry into the working column and mark its position in the
 // summary (any thread; LDS and global atomics at workgroup scope).
 __device__ __forceinline__ void bm_flip(u32 *bits, const BmLds &L, int W, int64_t coord) {
     const int pos = (int)(coord >> 16), cc = (int)(coord & 0xffff);
-    __hip_atomic_fetch_xor(&bits[(int64_t)pos * W + (cc >> 5)], 1u << (cc & 31), __ATOMIC_RELAXED,
+    __hip_atomic_fetch_xor(gp(&bits[(int64_t)pos * W + (cc >> 5)]), 1u << (cc & 31), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_WORKGROUP);
     __hip_atomic_fetch_or(&L.l1[pos >> 5], 1u << (pos & 31), __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -139,31 +129,35 @@ __device__ __forceinline__ int bm_next(const BmLds &L, int f) {
 // in every lane of wave 0): smallest diameter, then largest index. The
 // marked positions from *front on are checked a few at a time: one round
 // trip reads the bitmaps of up to kBmSlots of them (W lanes each) with each
-// one's length and run word (two more lanes). Empty ones are unmarked and
-// passed; *front then stays at the first position of the pivot's run of
-// equal lengths, where an entry younger than the pivot may still be added
-// (never before it).
+// one's length, run word, vertices and apparent vertex (four more lanes).
+// Empty ones are unmarked and passed; *front then stays at the first
+// position of the pivot's run of equal lengths, where an entry younger than
+// the pivot may still be added (never before it).
 constexpr int kBmSlots = 6;
+constexpr u32 kNoRho = 0xffffffffu;
 
-__device__ __forceinline__ int64_t bm_top_index(const EdgeOrder &eo, int pos, u32 w, u64 nz, int base) {
-    // the highest set bit of the position's bitmap (lanes base .. base+W-1)
+// The highest set bit of a position's bitmap (lanes base .. base+W-1 hold
+// its words, nz their nonzero mask): the third vertex of its oldest entry.
+__device__ __forceinline__ int bm_top_vertex(u32 w, u64 nz, int base) {
     const int hl = 63 - __clzll((long long)nz);
     const u32 hw = lane_bcast(w, hl);
-    const int c = (hl - base) * 32 + 31 - __clz((int)hw);
-    const u32 ab = eo.verts[pos];
-    return bm_tri_index((int)(ab >> 16), (int)(ab & 0xffffu), c);
+    return (hl - base) * 32 + 31 - __clz((int)hw);
 }
 
+// *rho: when the pivot is in a zero apparent pair found through
+// EdgeOrder::app, the vertices (a << 16 | b) of its partner edge; else kNoRho.
 __device__ __forceinline__ PivotCand bm_pivot(const EdgeOrder &eo, const u32 *bits, const BmLds &L,
-                                              int *front) {
+                                              int *front, u32 *rho) {
     const int lane = lane_id();
     const int W = eo.W;
-    const int SL = W + 2;
+    // a slot: W bitmap words, then length, run word, vertices, apparent vertex
+    const int SL = W + 4;
     const int P = min(kBmSlots, kWave / SL);
     PivotCand out;
     out.idx = kEmpty;
     out.diam = 0.0f;
     out.coef = 1u;
+    *rho = kNoRho;
     int f = *front;
     for (;;) {
         // up to P marked positions from f (LDS only)
@@ -184,23 +178,25 @@ __device__ __forceinline__ PivotCand bm_pivot(const EdgeOrder &eo, const u32 *bi
             break;
         }
         // one round trip: slot q = lanes [q*SL, q*SL + W) bitmap words,
-        // lane q*SL + W its length, lane q*SL + W + 1 its run word
+        // then (lanes q*SL + W ..) its length, run word, vertices and the
+        // third vertex of its zero apparent cofacet
         const int q = lane / SL, r = lane - q * SL;
         int mypos = -1;
 #pragma unroll
         for (int qq = 0; qq < kBmSlots; ++qq) mypos = qq == q ? ps[qq] : mypos;
-        u32 w = 0, rw = 0;
-        float ln = 0.0f;
+        u32 w = 0, mw = 0;
         if (q < np && mypos >= 0) {
-            if (r < W) w = ld(&bits[(int64_t)mypos * W + r]);
-            else if (r == W) ln = eo.len[mypos];
-            else rw = eo.run[mypos];
+            if (r < W) w = ld(gp(&bits[(int64_t)mypos * W + r]));
+            else if (r == W) mw = __float_as_uint(gp(eo.len)[mypos]);
+            else if (r == W + 1) mw = gp(eo.run)[mypos];
+            else if (r == W + 2) mw = gp(eo.verts)[mypos];
+            else mw = (u32)gp(eo.app)[mypos];
         }
         const u64 nz = __ballot(w != 0);
         // first slot with a set bit
         int live = -1;
         for (int qq = 0; qq < np; ++qq) {
-            const u64 m = qq * SL + W >= 64 ? ~0ull << (qq * SL) : (((1ull << W) - 1) << (qq * SL));
+            const u64 m = ((1ull << W) - 1) << (qq * SL);
             if (nz & m) {
                 live = qq;
                 break;
@@ -231,23 +227,31 @@ __device__ __forceinline__ PivotCand bm_pivot(const EdgeOrder &eo, const u32 *bi
 #pragma unroll
         for (int z = 0; z < kBmSlots; ++z) pos = z == live ? ps[z] : pos;
         const int base = live * SL;
-        const u64 mlive = (((W >= 64) ? ~0ull : ((1ull << W) - 1)) << base) & nz;
-        out.idx = bm_top_index(eo, pos, w, mlive, base);
-        const float dm = lane_bcast(ln, base + W);
-        const u32 run = lane_bcast(rw, base + W + 1);
+        const u64 mlive = (((1ull << W) - 1) << base) & nz;
+        const int cc = bm_top_vertex(w, mlive, base);
+        const float dm = __uint_as_float(lane_bcast(mw, base + W));
+        const u32 run = lane_bcast(mw, base + W + 1);
+        const u32 ab = lane_bcast(mw, base + W + 2);
+        const int app = (int)lane_bcast(mw, base + W + 3);
+        out.idx = bm_tri_index((int)(ab >> 16), (int)(ab & 0xffffu), cc);
         out.diam = dm;
         f = (int)(run & ~kRunTie);
+        // alone in its run: the pivot's only facet of its diameter is the
+        // owner edge, and EdgeOrder::app decides the zero apparent pair
+        if ((run & kRunTie) == 0 && f == pos && app == cc) *rho = ab;
         // positions after pos of exactly the same length: their triangles tie
         // on the diameter, and the largest index among them is the oldest
         bool tie = (run & kRunTie) != 0;
         for (int qp = pos + 1; tie && qp < eo.E; ++qp) {
-            const u32 rq = eo.run[qp];
+            const u32 rq = gp(eo.run)[qp];
             if ((L.l1[qp >> 5] >> (qp & 31)) & 1u) {
                 u32 wq = 0;
-                if (lane < W) wq = ld(&bits[(int64_t)qp * W + lane]);
+                if (lane < W) wq = ld(gp(&bits[(int64_t)qp * W + lane]));
                 const u64 nq = __ballot(wq != 0);
                 if (nq) {
-                    const int64_t iq = bm_top_index(eo, qp, wq, nq, 0);
+                    const u32 abq = gp(eo.verts)[qp];
+                    const int64_t iq =
+                        bm_tri_index((int)(abq >> 16), (int)(abq & 0xffffu), bm_top_vertex(wq, nq, 0));
                     if (iq > out.idx) out.idx = iq;
                 }
             }
@@ -271,6 +275,35 @@ __device__ __forceinline__ void bm_add_items(const ReduceJob<Dist> &J, RedShared
     const EdgeOrder eo = J.eo;
     const int tid = threadIdx.x;
     const int nit = S.nit;
+    // one edge, every vertex a candidate: each thread loads the edge
+    // positions of up to kRounds candidates at once, then flips (no barrier
+    // before: the item was written before the caller's barrier)
+    constexpr int kRounds = 8;
+    if (nit == 1 && c.nb.off == nullptr && c.n <= kRounds * BT) {
+        RED_TW0(t_fl, tid == 0);
+        const int u = S.it_v[0][0], v = S.it_v[0][1];
+        const int puv = gp(eo.pos)[bm_edge_index(u, v)];
+        const int rounds = (c.n + BT - 1) / BT;
+        int64_t cd[kRounds];
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            const int w = r * BT + tid;
+            cd[r] = (r < rounds && w < c.n) ? bm_coord(eo, u, v, puv, w) : -1;
+        }
+        unsigned long long added = 0;
+#pragma unroll
+        for (int r = 0; r < kRounds; ++r) {
+            if (cd[r] >= 0) {
+                bm_flip(bits, L, eo.W, cd[r]);
+                ++added;
+            }
+        }
+        if (added) atomicAdd(&S.stat[12], added);
+        bm_wait_flips();
+        RED_TW1(S, 21, t_fl, tid == 0);
+        __syncthreads(); // the flips are done, and the item read, before anyone goes on
+        return;
+    }
     int cnt = 0;
     if (tid < nit) {
         if (c.nb.off == nullptr) {
@@ -287,19 +320,10 @@ __device__ __forceinline__ void bm_add_items(const ReduceJob<Dist> &J, RedShared
         }
     }
     int total;
-    if (nit == 1) {
-        if (tid == 0) {
-            S.it_off[0] = 0;
-            S.it_off[1] = cnt;
-        }
-        __syncthreads();
-        total = S.it_off[1];
-    } else {
-        const int off = block_scan_excl<BT>(cnt, S.w, &total);
-        if (tid < nit) S.it_off[tid] = off;
-        if (tid == 0) S.it_off[nit] = total;
-        __syncthreads();
-    }
+    const int off = block_scan_excl<BT>(cnt, S.w, &total);
+    if (tid < nit) S.it_off[tid] = off;
+    if (tid == 0) S.it_off[nit] = total;
+    __syncthreads();
     unsigned long long added = 0;
     for (int fl = tid; fl < total; fl += BT) {
         int lo = 0, hi = nit - 1; // last item with it_off <= fl
@@ -311,7 +335,7 @@ __device__ __forceinline__ void bm_add_items(const ReduceJob<Dist> &J, RedShared
         const int q = fl - S.it_off[lo];
         const int w = S.it_u[lo] < 0 ? q : c.nb.idx[S.it_start[lo] + q];
         const int u = S.it_v[lo][0], v = S.it_v[lo][1];
-        const int64_t cd = bm_coord(c, eo, u, v, S.it_diam[lo], w);
+        const int64_t cd = bm_coord(eo, u, v, gp(eo.pos)[bm_edge_index(u, v)], w);
         if (cd >= 0) {
             bm_flip(bits, L, eo.W, cd);
             ++added;
@@ -326,7 +350,7 @@ __device__ __forceinline__ void bm_add_items(const ReduceJob<Dist> &J, RedShared
 template <int BT>
 __device__ __forceinline__ void bm_add_r(const VStore &V, int64_t off, int len, u32 *bits,
                                          const BmLds &L, int W, RedShared<BT> &S) {
-    for (int e = threadIdx.x; e < len; e += BT) bm_flip(bits, L, W, V.idx[off + e]);
+    for (int e = threadIdx.x; e < len; e += BT) bm_flip(bits, L, W, gp(V.idx)[off + e]);
     if (threadIdx.x == 0) S.stat[12] += (unsigned long long)len;
     bm_wait_flips();
     __syncthreads();
@@ -342,7 +366,7 @@ __device__ __forceinline__ int64_t bm_count(const u32 *bits, const BmLds &L, int
         while (m) {
             const int pos = (i << 5) + __ffs((int)m) - 1;
             m &= m - 1;
-            for (int q = 0; q < W; ++q) cnt += __popc(ld(&bits[(int64_t)pos * W + q]));
+            for (int q = 0; q < W; ++q) cnt += __popc(ld(gp(&bits[(int64_t)pos * W + q])));
         }
     }
     int tot;
@@ -361,7 +385,7 @@ __device__ __forceinline__ int bm_store(const u32 *bits, const BmLds &L, int W, 
         while (m) {
             const int pos = (i << 5) + __ffs((int)m) - 1;
             m &= m - 1;
-            for (int q = 0; q < W; ++q) cnt += __popc(ld(&bits[(int64_t)pos * W + q]));
+            for (int q = 0; q < W; ++q) cnt += __popc(ld(gp(&bits[(int64_t)pos * W + q])));
         }
     }
     int tot;
@@ -376,13 +400,13 @@ __device__ __forceinline__ int bm_store(const u32 *bits, const BmLds &L, int W, 
             const int pos = (i << 5) + __ffs((int)m) - 1;
             m &= m - 1;
             for (int q = 0; q < W; ++q) {
-                u32 x = ld(&bits[(int64_t)pos * W + q]);
+                u32 x = ld(gp(&bits[(int64_t)pos * W + q]));
                 while (x) {
                     const int cc = q * 32 + __ffs((int)x) - 1;
                     x &= x - 1;
-                    V.idx[vb + at] = ((int64_t)pos << 16) | cc;
-                    V.diam[vb + at] = 0.0f;
-                    V.coef[vb + at] = 1u;
+                    gp(V.idx)[vb + at] = ((int64_t)pos << 16) | cc;
+                    gp(V.diam)[vb + at] = 0.0f;
+                    gp(V.coef)[vb + at] = 1u;
                     ++at;
                 }
             }
@@ -402,7 +426,7 @@ __device__ __forceinline__ void bm_clear(u32 *bits, const BmLds &L, int W) {
         while (m) {
             const int pos = (i << 5) + __ffs((int)m) - 1;
             m &= m - 1;
-            for (int q = 0; q < W; ++q) st(&bits[(int64_t)pos * W + q], 0u);
+            for (int q = 0; q < W; ++q) st(gp(&bits[(int64_t)pos * W + q]), 0u);
         }
     }
     bm_wait_flips();
@@ -450,28 +474,50 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
             break;
         }
         // the pivot and both table lookups, by wave 0 (one barrier)
+        RED_T0(t_piv);
         if (w == 0) {
             int f = S.bmf;
             const EdgeOrder eo = J.eo;
-            const PivotCand pv = bm_pivot(eo, bits, L, &f);
+            u32 rho;
+            RED_TW0(t_bp, lane == 0);
+            const PivotCand pv = bm_pivot(eo, bits, L, &f, &rho);
+            RED_TW1(S, 19, t_bp, lane == 0);
             int64_t own = -1;
             PairHit hit{-1, kNoVerts, 0, kNoList};
-            if (pv.idx != kEmpty) {
+            if (pv.idx != kEmpty && rho == kNoRho) {
                 if (lane == 0) own = ph_find(J.ph, pv.idx);
                 if (lane == 32) hit = pair_find_all(J.app, pv.idx);
             }
             own = lane_bcast(own, 0);
-            const int64_t av = lane_bcast(hit.val, 32);
-            const u64 avw = lane_bcast(hit.verts, 32);
+            int64_t av = lane_bcast(hit.val, 32);
+            u64 avw = lane_bcast(hit.verts, 32);
+            if (rho != kNoRho) {
+                // a zero apparent pair (rho, pivot) read with the pivot (a
+                // pivot of a zero apparent pair is never in the pivot table)
+                av = bm_edge_index((int)(rho >> 16), (int)(rho & 0xffffu)) << 3;
+                avw = (u64)(rho >> 16) | ((u64)(rho & 0xffffu) << 16);
+            }
             if (lane == 0) {
                 S.bmf = f;
                 S.piv = pv;
                 S.owner = own;
                 S.appv = av;
-                S.vbase = avw; // rho's vertices, when the pivot is apparent
+                if (pv.idx != kEmpty && own < 0 && av >= 0) {
+                    // the addition of delta(rho): its item, set up here
+                    if (avw != kNoVerts) {
+                        S.it_v[0][0] = (int)(avw & 0xffffu);
+                        S.it_v[0][1] = (int)((avw >> 16) & 0xffffu);
+                    } else {
+                        decode(av >> 3, k, c.n, c.B, S.it_v[0]);
+                    }
+                    S.nit = 1;
+                    S.it_coef[0] = 1u;
+                    S.it_diam[0] = pv.diam;
+                }
             }
         }
         __syncthreads();
+        RED_T1(S, 0, t_piv);
         const PivotCand piv = S.piv;
         if (piv.idx == kEmpty) {
             // zero column: an essential class born at sigma
@@ -520,10 +566,12 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
             st_dev(&J.par.cst[j], S.pub);
         }
         if (kPar && S.owner < 0 && S.appv < 0) {
+            RED_T0(t_w);
             result = par_wait<BT>(J.par, S, j, __float_as_uint(piv.diam));
             if (result) break;
             if (tid == 0) S.owner = ph_find_dev(J.ph, piv.idx);
             __syncthreads();
+            RED_T1(S, 17, t_w);
         }
         const int64_t o = S.owner;
         if (kPar && o >= j) {
@@ -533,6 +581,7 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
         if (kPar && o >= 0) fence_acquire_dev();
         if (o >= 0) {
             // R_j += R_o (Z/2)
+            RED_T0(t_add);
             const int vlen = J.V.len[o];
             const int rlen = J.V.rlen[o];
             if (tid == 0 && !log_add(SC, S, -2 - o, 1u, 0.0f, vlen < 0 ? 1 : vlen)) S.abort = kRedLogFull;
@@ -563,6 +612,7 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
                     bm_add_items<BT>(J, S, bits, L);
                 }
             }
+            RED_T1(S, 1, t_add);
             if (S.abort) {
                 result = S.abort;
                 break;
@@ -571,24 +621,14 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
             continue;
         }
         if (S.appv >= 0) {
+            RED_T0(t_app);
             // the pivot tau is in a zero apparent pair (rho, tau): add the
-            // coboundary of rho (its vertices come with the table entry)
-            if (tid == 0) {
-                const int64_t a = S.appv;
-                const u64 vw = (u64)S.vbase;
-                if (vw != kNoVerts) {
-                    S.it_v[0][0] = (int)(vw & 0xffffu);
-                    S.it_v[0][1] = (int)((vw >> 16) & 0xffffu);
-                } else {
-                    decode(a >> 3, k, c.n, c.B, S.it_v[0]);
-                }
-                S.nit = 1;
-                S.it_coef[0] = 1u;
-                S.it_diam[0] = piv.diam;
-                if (!log_add(SC, S, a >> 3, 1u, piv.diam, 1)) S.abort = kRedLogFull;
-            }
-            __syncthreads();
+            // coboundary of rho (its item was set up with the pivot); the
+            // last wave writes the log entry, so that wave 0 has no store
+            // outstanding when it loads
+            if (tid == BT - kWave && !log_add(SC, S, S.appv >> 3, 1u, piv.diam, 1)) S.abort = kRedLogFull;
             bm_add_items<BT>(J, S, bits, L);
+            RED_T1(S, 16, t_app);
             if (S.abort) {
                 result = S.abort;
                 break;
@@ -599,6 +639,7 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
         // free pivot: the pair (sigma_j, pivot). R_j is stored (in bitmap
         // coordinates) when it is cheaper to add than V_j's coboundaries are
         // to recompute; then V_j is summed from the log and stored.
+        RED_T0(t_st);
         int64_t roff = 0;
         int rn = -1;
         const int64_t live = bm_count<BT>(bits, L, W, S.bmf, S);
@@ -656,6 +697,7 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
             J.V.roff[j] = roff;
             J.V.rlen[j] = rn;
         }
+        RED_T1(S, 5, t_st);
         break;
     }
     if (tid == 0 && result == kRedOk) {
@@ -663,7 +705,9 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
         S.stat[2] += nadd;
     }
     __syncthreads();
+    RED_T0(t_clr);
     bm_clear<BT>(bits, L, W);
+    RED_T1(S, 9, t_clr);
     return result;
 }
 
