@@ -471,8 +471,8 @@ struct PivotHash {
 __device__ __forceinline__ int32_t ph_find(const PivotHash &h, int64_t key) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
-        const int64_t cur = ld(gp(&h.keys[s]));
-        if (cur == key) return ld(gp(&h.vals[s]));
+        const int64_t cur = ld(&h.keys[s]);
+        if (cur == key) return ld(&h.vals[s]);
         if (cur == kEmpty) return -1;
         s = (s + 1) & h.mask;
     }
@@ -558,11 +558,11 @@ __device__ __forceinline__ PairHit pair_find_all(const PairHash &h, int64_t key)
     PairHit r{-1, kNoVerts, 0, kNoList};
     for (u32 probe = 0; probe <= h.mask; ++probe) {
         // the slot's words are loaded together: one round trip per probe
-        const int64_t cur = gp(h.keys)[s];
-        const int64_t v = gp(h.vals)[s];
-        const u64 w = h.verts ? gp(h.verts)[s] : kNoVerts;
-        const u64 nb = h.nbr ? gp(h.nbr)[s] : 0;
-        const u64 cb = h.cob ? gp(h.cob)[s] : kNoList;
+        const int64_t cur = h.keys[s];
+        const int64_t v = h.vals[s];
+        const u64 w = h.verts ? h.verts[s] : kNoVerts;
+        const u64 nb = h.nbr ? h.nbr[s] : 0;
+        const u64 cb = h.cob ? h.cob[s] : kNoList;
         if (cur == key) {
             r.val = v;
             r.verts = w;
@@ -582,8 +582,8 @@ __device__ __forceinline__ PairHit pair_find_all(const PairHash &h, int64_t key)
 __device__ __forceinline__ int64_t pair_find(const PairHash &h, int64_t key) {
     u32 s = mix64((u64)key) & h.mask;
     for (u32 probe = 0; probe <= h.mask; ++probe) {
-        const int64_t cur = gp(h.keys)[s];
-        const int64_t v = gp(h.vals)[s];
+        const int64_t cur = h.keys[s];
+        const int64_t v = h.vals[s];
         if (cur == key) return v;
         if (cur == kEmpty) return -1;
         s = (s + 1) & h.mask;

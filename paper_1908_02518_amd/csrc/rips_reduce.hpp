@@ -1439,9 +1439,9 @@ template <int BT>
 __device__ __forceinline__ bool log_add(const ReduceScratch &SC, RedShared<BT> &S, int64_t key,
                                         u32 coef, float dm, int64_t vlen) {
     if ((int64_t)S.nlog >= SC.lcap) return false;
-    gp(SC.lkey)[S.nlog] = key;
-    gp(SC.lcoef)[S.nlog] = coef;
-    gp(SC.ldia)[S.nlog] = dm;
+    SC.lkey[S.nlog] = key;
+    SC.lcoef[S.nlog] = coef;
+    SC.ldia[S.nlog] = dm;
     S.nlog += 1;
     S.vest += vlen;
     return true;
