@@ -72,14 +72,40 @@ PMC_VALU_SUMMARY = os.path.join(ROOT, "profiles", "pmc_valu_so3-1000.txt")
 COPY_BYTES = 1 << 29   # plain copy used to calibrate the counters (512 MiB read + written)
 
 
+def _code_only(text: str) -> str:
+    """The source without comments and whitespace (string and character
+    literals kept), so that a comment edit leaves the hash alone."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            if not c.isspace():
+                out.append(c)
+            i += 1
+    return "".join(out)
+
+
 def source_hash() -> str:
-    """Hash of the HIP sources: counter summaries are valid for these only."""
+    """Hash of the code of the HIP sources (comments and whitespace left out):
+    counter summaries are valid for this code only."""
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_1908_02518_amd", "csrc", "*"))):
         if f.endswith((".hip", ".hpp")):
             h.update(os.path.basename(f).encode())
-            with open(f, "rb") as fh:
-                h.update(fh.read())
+            with open(f, encoding="utf-8") as fh:
+                h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

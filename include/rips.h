@@ -368,7 +368,7 @@ rips_status rips_get_reduced_storage(int32_t *mode);
  * refinement"; the implicit columns of section "Implicit matrix
  * reduction").
  *   RIPS_WORKING_COLUMN_AUTO (default): direct-mapped where it applies and
- *     fits (n <= 1984, at most 2^18 edges <= t, its bitmaps within 8 GiB),
+ *     fits (n <= 1920, at most 2^18 edges <= t, its bitmaps within 8 GiB),
  *     else the general working column;
  *   RIPS_WORKING_COLUMN_GENERAL: always the general one (LDS delta, sorted
  *     base, far list).

@@ -1099,8 +1099,9 @@ size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD, bool bm) {
     return std::max(dpart + uf, reduce_lds_bytes(capD) + (bm ? bm_lds_bytes((int64_t)npairs) : 0));
 }
 
-// The direct-mapped working column needs W = ceil(nmax / 32) <= 62 words per
-// edge (the pivot search reads one edge's bitmap with one wave), a summary of
+// The direct-mapped working column needs W = ceil(nmax / 32) <= 60 words per
+// edge (the pivot search reads one edge's bitmap words and four more words
+// of the edge with one wave), a summary of
 // C(nmax, 2) bits in LDS beside the general working column's, and
 // C(nmax, 2) * W words of bitmaps per workgroup (at most 8 GiB in all).
 bool batched_bm_fits(int nmax, int max_dim, u32 p, int64_t grid) {

@@ -49,3 +49,18 @@ def test_prefix_restriction_is_the_cut_filtration(name, x, max_dim, t, r):
             assert np.array_equal(g_, w_), (name, d)
     # the cut is not trivial: some bar dies after r, or is born after it
     assert any(np.any(full.bars[d].death > np.float32(r)) for d in range(max_dim + 1))
+
+
+def test_counter_summary_hash_ignores_comments_only():
+    """The hash that ties a counter summary to the kernels it measured: a
+    comment or whitespace edit leaves it, a code edit (even inside what
+    looks like a comment marker in a string) changes it."""
+    import bench
+    base = 'int f(int x) {\n    return x + 1; // one more\n}\nconst char *s = "a // b";\n'
+    same = '/* header */\nint f(int x) {   return x + 1; }\nconst char *s = "a // b"; // note\n'
+    other = 'int f(int x) {\n    return x + 2; // one more\n}\nconst char *s = "a // b";\n'
+    lit = 'int f(int x) {\n    return x + 1; // one more\n}\nconst char *s = "a // c";\n'
+    code = bench._code_only
+    assert code(base) == code(same)
+    assert code(base) != code(other)
+    assert code(base) != code(lit)
