@@ -187,17 +187,23 @@ __device__ __forceinline__ void batch_par_stats(const BatchArgs &A, int wgL, con
     atomicAdd(&ps[12], RS.stat[12]); // entries added
 }
 
-// The dimension-1 enumeration / apparent-pair filter over share `part` of
-// `nparts` of the edges (interleaved by wave): survivors appended through
-// *nsurv, zero apparent pairs inserted into app, the counts of candidates,
-// cleared and apparent columns added to cnt[0..2]; with appe (the
+// The dimension-1 enumeration / apparent-pair filter: survivors appended
+// through *nsurv, zero apparent pairs inserted into app, the counts of
+// candidates, cleared and apparent columns added to cnt[0..2]; with appe (the
 // direct-mapped column), appe[e] = the third vertex of edge e's zero
-// apparent cofacet, or -1, for every edge of the share. Every thread calls it.
+// apparent cofacet, or -1, for every edge it looks at. The edges: with
+// chunk == null, this workgroup's whole pass over all of them; otherwise
+// runs of kFilterChunk edges handed out through *chunk (an agent-scope
+// counter the cloud's workgroups share). bits (the forest edges of H0, which
+// clearing skips) or null: then a forest edge comes out as a survivor (it is
+// in no zero apparent pair, being paired in dimension 0), and the caller
+// drops it. Every thread calls it.
+constexpr int kFilterChunk = 128;
+
 template <class Dist>
 __device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist> &c, float t, int64_t npairs,
                                              const u32 *bits, const Columns &surv, const PairHash &app,
-                                             int *appe, int part, int nparts, int *nsurv,
-                                             unsigned long long *cnt) {
+                                             int *appe, int *chunk, int *nsurv, unsigned long long *cnt) {
     const int tid = threadIdx.x, lane = lane_id();
     const Dist dist = c.d;
     const bool leader = (lane & (kBatchFilterG - 1)) == 0;
@@ -205,10 +211,27 @@ __device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist>
     // one edge per group of kBatchFilterG lanes; the loop is uniform in
     // the wave and the tests are predicates (the scans need every lane)
     constexpr int kGroups = kWave / kBatchFilterG;
-    const int64_t step = (int64_t)nparts * (kBT / kWave) * kGroups;
-    for (int64_t e0 = ((int64_t)part * (kBT / kWave) + tid / kWave) * kGroups; e0 < npairs; e0 += step) {
+    int64_t e0 = (int64_t)(tid / kWave) * kGroups, cend = npairs;
+    if (chunk) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(chunk, kFilterChunk);
+        base = __shfl(base, 0, kWave);
+        e0 = base;
+        cend = min<int64_t>(npairs, (int64_t)base + kFilterChunk);
+    }
+    for (;;) {
+        if (e0 >= cend) {
+            if (!chunk || cend >= npairs) break;
+            int base = 0;
+            if (lane == 0) base = atomicAdd(chunk, kFilterChunk);
+            base = __shfl(base, 0, kWave);
+            e0 = base;
+            cend = min<int64_t>(npairs, (int64_t)base + kFilterChunk);
+            if (e0 >= cend) break;
+        }
         const int64_t e = e0 + lane / kBatchFilterG;
-        bool live = e < npairs;
+        e0 += chunk ? kGroups : (int64_t)(kBT / kWave) * kGroups;
+        bool live = e < cend;
         int v[2] = {0, 0};
         float dm = 0.0f;
         if (live) {
@@ -218,7 +241,7 @@ __device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist>
         }
         if (live) {
             n_cand += leader;
-            if ((bits[e >> 5] >> (e & 31)) & 1u) {
+            if (bits && ((bits[e >> 5] >> (e & 31)) & 1u)) {
                 n_clear += leader;
                 live = false;
             }
@@ -236,7 +259,7 @@ __device__ __forceinline__ void batch_filter(const BatchArgs &A, const Ctx<Dist>
                 (void)pair_insert(app, simplex_index(tv, 2, c.B), (e << 3) | pos,
                                   (u64)(u32)v[0] | ((u64)(u32)v[1] << 16), 0);
         }
-        if (appe != nullptr && leader && e < npairs) appe[e] = zap ? j : -1;
+        if (appe != nullptr && leader && e < cend) appe[e] = zap ? j : -1;
         // is the zero pivot cofacet itself in a zero apparent pair (for
         // the emergent shortcut)?
         const bool tj = live && j >= 0;
@@ -394,37 +417,42 @@ __device__ void batch_follow(const BatchArgs &A, int wgL, int role, unsigned cha
             const PairHash app{A.app_keys + (int64_t)wgL * A.ph_stride, A.app_vals + (int64_t)wgL * A.ph_stride,
                                A.app_verts + (int64_t)wgL * A.ph_stride, nullptr, nullptr, nullptr, nullptr,
                                appcap - 1};
+            SortBufs sb_o;
+            int ce_o = 0, nE_o = 0;
             if (order_role) {
-                // the edge order, into the leader's tables, with this
+                // first the edge order, into the leader's tables, with this
                 // workgroup's sort buffers
                 const int64_t wo = (int64_t)blockIdx.x * A.col_stride;
-                SortBufs sb;
-                sb.lo[0] = A.s_lo0 + wo;
-                sb.lo[1] = A.s_lo1 + wo;
-                sb.hi[0] = A.s_hi0 + wo;
-                sb.hi[1] = A.s_hi1 + wo;
-                sb.val[0] = A.s_v0 + wo;
-                sb.val[1] = A.s_v1 + wo;
-                int ce;
-                const int nE = batch_edge_order<Dist>(A, c.d, t, npairs, sb, SS, Sh.w, wgL, &ce);
-                // the apparent vertices by position, once every share of
-                // the filter (the leader's too) is done
-                if (tid == 0) (void)batch_wait(A, &sw[kSyncFiltered], A.spread - 1);
+                sb_o.lo[0] = A.s_lo0 + wo;
+                sb_o.lo[1] = A.s_lo1 + wo;
+                sb_o.hi[0] = A.s_hi0 + wo;
+                sb_o.hi[1] = A.s_hi1 + wo;
+                sb_o.val[0] = A.s_v0 + wo;
+                sb_o.val[1] = A.s_v1 + wo;
+                nE_o = batch_edge_order<Dist>(A, c.d, t, npairs, sb_o, SS, Sh.w, wgL, &ce_o);
+            }
+            // runs of edges from the shared counter until none is left (no
+            // clearing: the leader drops the forest edges); then done
+            int *appe = A.bm_bits ? A.bm_appe + (int64_t)wgL * A.bm_tab_stride : nullptr;
+            batch_filter<Dist>(A, c, t, npairs, nullptr, surv, app, appe, &sw[kSyncChunk], &sw[kSyncSurv],
+                               A.par_stat + (int64_t)wgL * kSyncStats + 8);
+            fence_release_dev();
+            __syncthreads();
+            if (tid == 0) atomicAdd(&sw[kSyncFiltered], 1);
+            if (order_role) {
+                // the apparent vertices by position, once every workgroup
+                // of the cloud is done filtering
+                if (tid == 0) (void)batch_wait(A, &sw[kSyncFiltered], A.spread);
                 __syncthreads();
                 fence_acquire_dev();
-                batch_map_app(A, sb, ce, nE, wgL);
-                if (tid == 0) sw[kSyncE] = nE;
-            } else {
-                int *appe = A.bm_bits ? A.bm_appe + (int64_t)wgL * A.bm_tab_stride : nullptr;
-                batch_filter<Dist>(A, c, t, npairs, A.bits_g + (int64_t)wgL * A.bits_stride, surv, app, appe,
-                                   ordering ? role - 1 : role, ordering ? A.spread - 1 : A.spread,
-                                   &sw[kSyncSurv], A.par_stat + (int64_t)wgL * kSyncStats + 8);
+                batch_map_app(A, sb_o, ce_o, nE_o, wgL);
+                if (tid == 0) sw[kSyncE] = nE_o;
             }
         }
-        // its survivors and table entries (or the edge order), then done
+        // the edge order, then done
         fence_release_dev();
         __syncthreads();
-        if (tid == 0) atomicAdd(&sw[order_role ? kSyncOrdered : kSyncFiltered], 1);
+        if (order_role && tid == 0) atomicAdd(&sw[kSyncOrdered], 1);
     }
     if (tid == 0) s_go = batch_wait(A, &sw[kSyncReady], 1) ? 1 : 0;
     __syncthreads();
@@ -532,6 +560,28 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
     __syncthreads();
     const float renc = n > 1 ? __uint_as_float((u32)Sh.flag) : 0.0f;
     const float t = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(fminf(A.threshold, renc))));
+    // with the distances in global memory the cloud's other workgroups start
+    // the dimension-1 filter now, while this one computes H0: its apparent-
+    // pair table is emptied first, then n, t and the front flag are published
+    const bool share = A.spread > 1 && !kLds && max_dim >= 1;
+    u32 appcap = 64;
+    while (appcap < 2u * (u32)npairs + 64u && (int64_t)appcap < A.ph_stride) appcap <<= 1;
+    int *sw0 = A.sync + (int64_t)wg * kSyncWords;
+    unsigned long long *fcnt = A.par_stat + (int64_t)wg * kSyncStats + 8;
+    if (max_dim >= 1) {
+        int64_t *akeys = A.app_keys + (int64_t)wg * A.ph_stride;
+        for (u32 q = tid; q < appcap; q += kBT) akeys[q] = kEmpty;
+    }
+    if (share) {
+        if (tid < 3) fcnt[tid] = 0ull;
+        if (tid == 0) {
+            sw0[kSyncN] = n;
+            sw0[kSyncT] = __float_as_int(t);
+        }
+        fence_release_dev();
+        gsync();
+        if (tid == 0) st_dev(&sw0[kSyncFront], 1);
+    }
     // ---- H0: Boruvka on the pairs <= t, union-find state in LDS
     const int nm = A.nmax;
     const int64_t npairs_max = (int64_t)nm * (nm - 1) / 2;
@@ -756,43 +806,26 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         Columns surv{A.c_idx0 + (int64_t)wg * A.col_stride, A.c_dm0 + (int64_t)wg * A.col_stride,
                      A.c_j0 + (int64_t)wg * A.col_stride, A.c_t0 + (int64_t)wg * A.col_stride};
         // the zero apparent pairs (rho, tau) found here serve the reduction's
-        // pivot tests (one lookup instead of facet and cofacet scans)
-        u32 appcap = 64;
-        while (appcap < 2u * (u32)npairs + 64u && (int64_t)appcap < A.ph_stride) appcap <<= 1;
+        // pivot tests (one lookup instead of facet and cofacet scans); the
+        // table was emptied before H0
         const PairHash app{A.app_keys + (int64_t)wg * A.ph_stride, A.app_vals + (int64_t)wg * A.ph_stride,
                            A.app_verts + (int64_t)wg * A.ph_stride, nullptr, nullptr, nullptr, nullptr,
                            appcap - 1};
-        for (u32 q = tid; q < appcap; q += kBT) app.keys[q] = kEmpty;
         gsync();
-        // with the distances in global memory the cloud's other workgroups
-        // filter their shares of the edges too (spread out)
-        const bool share = A.spread > 1 && !kLds;
-        int *sw0 = A.sync + (int64_t)wg * kSyncWords;
-        unsigned long long *fcnt = A.par_stat + (int64_t)wg * kSyncStats + 8;
-        if (share) {
-            if (tid < 3) fcnt[tid] = 0ull;
-            if (tid == 0) {
-                sw0[kSyncN] = n;
-                sw0[kSyncT] = __float_as_int(t);
-            }
-            fence_release_dev();
-            gsync();
-            if (tid == 0) st_dev(&sw0[kSyncFront], 1);
-        }
-        // (with three or more workgroups the second one builds the edge
-        // order meanwhile and filters nothing)
-        const int fparts = share ? (A.spread >= 3 && A.bm_bits ? A.spread - 1 : A.spread) : 1;
+        // spread out, every workgroup of the cloud takes runs of edges from
+        // the shared counter (the edge-order workgroup once its order is
+        // built), with no clearing: the forest edges are dropped below
         int *appe = A.bm_bits ? A.bm_appe + (int64_t)wg * A.bm_tab_stride : nullptr;
-        batch_filter<Dist>(A, c, t, npairs, bits, surv, app, appe, 0, fparts,
-                           share ? &sw0[kSyncSurv] : &Sh.nsurv, share ? fcnt : Sh.cnt);
+        batch_filter<Dist>(A, c, t, npairs, share ? nullptr : bits, surv, app, appe,
+                           share ? &sw0[kSyncChunk] : nullptr, share ? &sw0[kSyncSurv] : &Sh.nsurv,
+                           share ? fcnt : Sh.cnt);
         if (share) {
-            // this share done (the edge-order workgroup waits for every
-            // share), then the others'
+            // this workgroup done filtering, then every other
             fence_release_dev();
             __syncthreads();
             if (tid == 0) {
                 atomicAdd(&sw0[kSyncFiltered], 1);
-                (void)batch_wait(A, &sw0[kSyncFiltered], fparts);
+                (void)batch_wait(A, &sw0[kSyncFiltered], A.spread);
             }
             __syncthreads();
             fence_acquire_dev();
@@ -804,18 +837,29 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
             }
         }
         gsync();
-        const int S = min(Sh.nsurv, (int)A.col_stride);
-        // ---- sort: diameter descending, then index ascending
-        for (int e = tid; e < S; e += kBT) {
-            sb.lo[0][e] = (u64)surv.idx[e];
-            sb.hi[0][e] = ~__float_as_uint(surv.diam[e]);
+        const int S0 = min(Sh.nsurv, (int)A.col_stride);
+        // ---- sort: diameter descending, then index ascending (a forest edge,
+        // when the filter did not clear it, after every column: bit 31 of its
+        // key; the count of those is the cleared count)
+        if (share && tid == 0) Sh.cnt[3] = 0;
+        gsync();
+        int nforest = 0;
+        for (int e = tid; e < S0; e += kBT) {
+            const int64_t ix = surv.idx[e];
+            const bool forest = share && ((bits[ix >> 5] >> (ix & 31)) & 1u);
+            nforest += forest ? 1 : 0;
+            sb.lo[0][e] = (u64)ix | (forest ? (1ull << 31) : 0ull);
+            sb.hi[0][e] = forest ? ~0u : ~__float_as_uint(surv.diam[e]);
             sb.val[0][e] = (u32)e;
         }
+        if (nforest) atomicAdd(&Sh.cnt[3], (unsigned long long)nforest);
         gsync();
-        const int cs = block_radix_sort<kBT>(sb, S, 4, 4, SS);
+        if (share && tid == 0) Sh.cnt[1] = Sh.cnt[3];
+        const int S = S0 - (share ? (int)Sh.cnt[3] : 0);
+        const int cs = block_radix_sort<kBT>(sb, S0, 4, 4, SS);
         Columns cols{A.c_idx1 + (int64_t)wg * A.col_stride, A.c_dm1 + (int64_t)wg * A.col_stride,
                      A.c_j1 + (int64_t)wg * A.col_stride, A.c_t1 + (int64_t)wg * A.col_stride};
-        for (int q = tid; q < S; q += kBT) {
+        for (int q = tid; q < S0; q += kBT) {
             const u32 e = sb.val[cs][q];
             cols.idx[q] = surv.idx[e];
             cols.diam[q] = surv.diam[e];

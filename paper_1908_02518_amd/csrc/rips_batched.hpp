@@ -100,11 +100,12 @@ struct BatchArgs {
 // (spread > 1), zeroed before every launch: ready flag (columns sorted, the
 // reduction may start), n, t (bits), columns, edges of the edge order, skip
 // (the cloud has no reduction), reductions done; with the distances in
-// global memory also: front flag (distances and H0 done, the filter may
-// start), survivors appended, filter shares done, edge order done.
+// global memory also: front flag (distances and threshold done, the filter
+// may start), survivors appended, workgroups done filtering, edge order
+// done, edges handed out to the filter.
 enum : int { kSyncReady = 0, kSyncN = 1, kSyncT = 2, kSyncS = 3, kSyncE = 4, kSyncSkip = 5,
              kSyncDone = 6, kSyncFront = 7, kSyncSurv = 8, kSyncFiltered = 9, kSyncOrdered = 10,
-             kSyncWords = 16 };
+             kSyncChunk = 11, kSyncWords = 16 };
 constexpr int kSyncStats = 16;
 
 
