@@ -1068,10 +1068,10 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
                         reduce_lds_bytes(256) + bm_lds_bytes(nE) <= lds_budget;
         uint32_t capD = kMaxDelta;
         while (capD > 256 && reduce_lds_bytes(capD) + (bm ? bm_lds_bytes(nE) : 0) > lds_budget) capD >>= 1;
-        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
+        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
         u32 *bm_bits = nullptr;
         if (bm) {
-            HIP_TRY(C.ensure(B_BM_POS, (size_t)choose_i64(n, 2) * 4 + 16, &q));
+            HIP_TRY(C.ensure(B_BM_POS, (size_t)n * n * 4 + 16, &q));
             int *bpos = as<int>(q);
             HIP_TRY(C.ensure(B_BM_VERTS, (size_t)nE * 4, &q));
             u32 *bverts = as<u32>(q);
@@ -1104,9 +1104,9 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             }
             {
                 PROF(P_SORT1);
-                launch_bm_edge_order(P.E, (int)nE, choose_i64(n, 2), eb, bpos, bverts, blen, brun, app, bapp, st);
+                launch_bm_edge_order(P.E, (int)nE, n, eb, bpos, bverts, blen, brun, app, bapp, st);
             }
-            eo = EdgeOrder{bpos, bverts, blen, brun, bapp, (int)nE, (int)bmW};
+            eo = EdgeOrder{bpos, bverts, blen, brun, bapp, (int)nE, (int)bmW, n};
         }
         int64_t fcap = spread ? std::max<int64_t>(C.hint_far, 1 << 16)
                               : std::max<int64_t>(C.hint_far, std::max<int64_t>(1 << 18, 256ll * bound));
@@ -1642,7 +1642,8 @@ rips_status batched_once(DevCtx &Cref, const float *d_points, const int64_t *d_o
                     batched_bm_fits(n_max, max_dim, p, G);
     if (bm) {
         const int64_t W = (n_max + 31) / 32;
-        ENS(BB_BM_POS, G * npairs * 4, A.bm_pos, int);
+        ENS(BB_BM_POS, G * (int64_t)n_max * n_max * 4, A.bm_pos, int);
+        A.bm_pos_stride = (int64_t)n_max * n_max;
         ENS(BB_BM_VERTS, G * npairs * 4, A.bm_verts, u32);
         ENS(BB_BM_LEN, G * npairs * 4, A.bm_len, float);
         ENS(BB_BM_RUN, G * npairs * 4, A.bm_run, u32);

@@ -113,9 +113,9 @@ __device__ __forceinline__ ReduceJob<Dist> batch_job(const BatchArgs &A, int wgL
     J.prev_bits = nullptr;
     J.prev = PivotHash{nullptr, nullptr, 0};
     const int64_t to = (int64_t)wgL * A.bm_tab_stride;
-    J.eo = A.bm_bits ? EdgeOrder{A.bm_pos + to, A.bm_verts + to, A.bm_len + to, A.bm_run + to,
-                                 A.bm_app + to, nE, (n + 31) / 32}
-                     : EdgeOrder{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
+    J.eo = A.bm_bits ? EdgeOrder{A.bm_pos + (int64_t)wgL * A.bm_pos_stride, A.bm_verts + to, A.bm_len + to,
+                                 A.bm_run + to, A.bm_app + to, nE, (n + 31) / 32, n}
+                     : EdgeOrder{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
     J.bm_bits = A.bm_bits;
     J.bm_stride = A.bm_stride;
     return J;
@@ -309,7 +309,7 @@ __device__ __forceinline__ void batch_map_app(const BatchArgs &A, SortBufs sb, i
 // equal lengths in index order. Every thread calls it; returns the number
 // of edges.
 template <class Dist>
-__device__ __forceinline__ int batch_edge_order(const BatchArgs &A, const Dist &dist, float t, int64_t npairs,
+__device__ __forceinline__ int batch_edge_order(const BatchArgs &A, const Dist &dist, float t, int n, int64_t npairs,
                                                 SortBufs sb, SortShared<kBT> &SS, int *scan_w, int wgT,
                                                 int *ce_out) {
     const int tid = threadIdx.x;
@@ -323,7 +323,7 @@ __device__ __forceinline__ int batch_edge_order(const BatchArgs &A, const Dist &
     }
     int nE;
     int at = block_scan_excl<kBT>(cnt, scan_w, &nE);
-    int *bpos = A.bm_pos + (int64_t)wgT * A.bm_tab_stride;
+    int *bpos = A.bm_pos + (int64_t)wgT * A.bm_pos_stride;
     for (int64_t e = e0; e < e1; ++e) {
         int a, cc;
         pair_of(e, &a, &cc);
@@ -334,7 +334,8 @@ __device__ __forceinline__ int batch_edge_order(const BatchArgs &A, const Dist &
             sb.val[0][at] = (u32)e;
             ++at;
         } else {
-            bpos[e] = -1;
+            bpos[(int64_t)a * n + cc] = -1;
+            bpos[(int64_t)cc * n + a] = -1;
         }
     }
     gsync();
@@ -347,7 +348,8 @@ __device__ __forceinline__ int batch_edge_order(const BatchArgs &A, const Dist &
         const u32 e = sb.val[ce][q];
         int a, cc;
         pair_of(e, &a, &cc);
-        bpos[e] = q;
+        bpos[(int64_t)a * n + cc] = q;
+        bpos[(int64_t)cc * n + a] = q;
         bv[q] = ((u32)a << 16) | (u32)cc;
         bl[q] = __uint_as_float(sb.hi[ce][q]);
     }
@@ -429,7 +431,7 @@ __device__ void batch_follow(const BatchArgs &A, int wgL, int role, unsigned cha
                 sb_o.hi[1] = A.s_hi1 + wo;
                 sb_o.val[0] = A.s_v0 + wo;
                 sb_o.val[1] = A.s_v1 + wo;
-                nE_o = batch_edge_order<Dist>(A, c.d, t, npairs, sb_o, SS, Sh.w, wgL, &ce_o);
+                nE_o = batch_edge_order<Dist>(A, c.d, t, n, npairs, sb_o, SS, Sh.w, wgL, &ce_o);
             }
             // runs of edges from the shared counter until none is left (no
             // clearing: the leader drops the forest edges); then done
@@ -870,7 +872,7 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
         // working column (by the cloud's second workgroup, during the
         // filter, when the cloud has three or more)
         const bool offload = share && A.spread >= 3 && A.bm_bits;
-        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
+        EdgeOrder eo{nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
         if (A.bm_bits) {
             int nE;
             if (offload) {
@@ -880,12 +882,12 @@ __device__ void batch_cloud(const BatchArgs &A, int b, unsigned char *smem, Batc
                 nE = __builtin_amdgcn_readfirstlane(ld_dev(&sw0[kSyncE]));
             } else {
                 int ce;
-                nE = batch_edge_order<Dist>(A, dist, t, npairs, sb, SS, Sh.w, wg, &ce);
+                nE = batch_edge_order<Dist>(A, dist, t, n, npairs, sb, SS, Sh.w, wg, &ce);
                 batch_map_app(A, sb, ce, nE, wg);
             }
             const int64_t to = (int64_t)wg * A.bm_tab_stride;
-            eo = EdgeOrder{A.bm_pos + to, A.bm_verts + to, A.bm_len + to, A.bm_run + to, A.bm_app + to, nE,
-                           (n + 31) / 32};
+            eo = EdgeOrder{A.bm_pos + (int64_t)wg * A.bm_pos_stride, A.bm_verts + to, A.bm_len + to,
+                           A.bm_run + to, A.bm_app + to, nE, (n + 31) / 32, n};
         }
         // ---- the reduction reads D from global; LDS now holds its working column
         if (kLds)
@@ -1147,12 +1149,13 @@ size_t batched_lds_bytes(bool lds_d, int nmax, u32 capD, bool bm) {
 // edge (the pivot search reads one edge's bitmap words and four more words
 // of the edge with one wave), a summary of
 // C(nmax, 2) bits in LDS beside the general working column's, and
-// C(nmax, 2) * W words of bitmaps per workgroup (at most 8 GiB in all).
+// C(nmax, 2) * W words of bitmaps and an nmax x nmax position table per
+// workgroup (at most 8 GiB in all).
 bool batched_bm_fits(int nmax, int max_dim, u32 p, int64_t grid) {
     const int64_t npairs = (int64_t)nmax * (nmax - 1) / 2;
     const int64_t W = (nmax + 31) / 32;
     return p == 2 && max_dim >= 1 && W <= 60 && npairs <= (1 << 18) &&
-           grid * npairs * W * 4 <= (8ll << 30);
+           grid * (npairs * W + (int64_t)nmax * nmax) * 4 <= (8ll << 30);
 }
 
 // default delta: the largest (kMaxDelta slots, about 94 KB of LDS with its

@@ -80,6 +80,7 @@ struct BatchArgs {
     u32 *bm_verts;
     float *bm_len;
     u32 *bm_run;
+    int64_t bm_pos_stride;          // nmax * nmax: the n x n position table of each workgroup
     int *bm_app;                    // position -> third vertex of its zero apparent cofacet, or -1
     int *bm_appe;                   // the same by edge index, written by the filter
     int64_t bm_tab_stride;          // C(nmax, 2)

@@ -1231,8 +1231,8 @@ void launch_fill_u32(u32 *a, int64_t n, u32 v, hipStream_t st) {
 
 // The edges <= t in order of length for the direct-mapped working column of
 // dimension 1 (one workgroup): a sort on the length bits, then position ->
-// vertices, length and run word, and edge index -> position.
-__global__ void __launch_bounds__(1024) k_bm_edge_order(EdgeList E, int nE, SortBufs sb, int *pos,
+// vertices, length and run word, and (a, b) -> position in the n x n table.
+__global__ void __launch_bounds__(1024) k_bm_edge_order(EdgeList E, int nE, int n, SortBufs sb, int *pos,
                                                         u32 *verts, float *len, u32 *run) {
     __shared__ SortShared<1024> S;
     for (int q = threadIdx.x; q < nE; q += 1024) {
@@ -1246,7 +1246,8 @@ __global__ void __launch_bounds__(1024) k_bm_edge_order(EdgeList E, int nE, Sort
     const int cur = block_radix_sort<1024>(sb, nE, 0, 4, S);
     for (int q = threadIdx.x; q < nE; q += 1024) {
         const u32 e = sb.val[cur][q];
-        pos[E.idx[e]] = q;
+        pos[(int64_t)E.a[e] * n + E.b[e]] = q;
+        pos[(int64_t)E.b[e] * n + E.a[e]] = q;
         verts[q] = ((u32)E.a[e] << 16) | (u32)E.b[e];
         len[q] = E.diam[e];
     }
@@ -1263,7 +1264,7 @@ __global__ void __launch_bounds__(1024) k_bm_edge_order(EdgeList E, int nE, Sort
 // Per edge position, the third vertex of the edge's zero apparent cofacet:
 // for every pair (rho, tau) of the table, app[pos(rho)] = the vertex of tau
 // off rho (app holds -1 elsewhere).
-__global__ void k_bm_app(PairHash tab, const int *pos, int *app) {
+__global__ void k_bm_app(PairHash tab, const int *pos, int n, int *app) {
     const u32 cap = tab.mask + 1;
     for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q < cap; q += gridDim.x * blockDim.x) {
         const int64_t tau = tab.keys[q];
@@ -1278,20 +1279,20 @@ __global__ void k_bm_app(PairHash tab, const int *pos, int *app) {
         int y, z;
         edge_vertices((u32)(tau - (int64_t)x * (x - 1) * (x - 2) / 6), &y, &z);
         const int c = (x != a && x != b) ? x : (y != a && y != b) ? y : z;
-        const int p = pos[rho];
+        const int p = pos[(int64_t)a * n + b];
         if (p >= 0) app[p] = c;
     }
 }
 
-void launch_bm_edge_order(EdgeList E, int nE, int64_t npairs, SortBufs sb, int *pos, u32 *verts, float *len,
-                          u32 *run, PairHash app_tab, int *app, hipStream_t st) {
-    launch_fill_u32((u32 *)pos, npairs, 0xffffffffu, st);
+void launch_bm_edge_order(EdgeList E, int nE, int n, SortBufs sb, int *pos, u32 *verts, float *len, u32 *run,
+                          PairHash app_tab, int *app, hipStream_t st) {
+    launch_fill_u32((u32 *)pos, (int64_t)n * n, 0xffffffffu, st);
     launch_fill_u32((u32 *)app, nE, 0xffffffffu, st);
-    hipLaunchKernelGGL(k_bm_edge_order, dim3(1), dim3(1024), 0, st, E, nE, sb, pos, verts, len, run);
+    hipLaunchKernelGGL(k_bm_edge_order, dim3(1), dim3(1024), 0, st, E, nE, n, sb, pos, verts, len, run);
     if (app_tab.keys) {
         const int64_t cap = (int64_t)app_tab.mask + 1;
         const unsigned blocks = (unsigned)std::min<int64_t>(1024, (cap + 255) / 256);
-        hipLaunchKernelGGL(k_bm_app, dim3(blocks), dim3(256), 0, st, app_tab, (const int *)pos, app);
+        hipLaunchKernelGGL(k_bm_app, dim3(blocks), dim3(256), 0, st, app_tab, (const int *)pos, n, app);
     }
 }
 

@@ -129,8 +129,8 @@ void launch_filter(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t
                    hipStream_t st);
 void launch_expand(int G, const Ctx<DistFull> &c, int k, SimplexList in, int64_t count, Scalars *s,
                    SimplexList out, int64_t cap, bool count_only, hipStream_t st);
-void launch_bm_edge_order(EdgeList E, int nE, int64_t npairs, SortBufs sb, int *pos, u32 *verts, float *len,
-                          u32 *run, PairHash app_tab, int *app, hipStream_t st);
+void launch_bm_edge_order(EdgeList E, int nE, int n, SortBufs sb, int *pos, u32 *verts, float *len, u32 *run,
+                          PairHash app_tab, int *app, hipStream_t st);
 void launch_sort_columns(Columns in, Scalars *s, SortBufs sb, int lo_bytes, Columns out,
                          hipStream_t st);
 void launch_emit(BarBuf in, Scalars *s, int reverse, BarBuf out, hipStream_t st);

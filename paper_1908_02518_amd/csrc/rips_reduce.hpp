@@ -301,8 +301,10 @@ struct ParState {
 };
 
 // The edges <= t in order of length, for the direct-mapped working column of
-// dimension 1 (rips_reduce_bm.hpp): edge CNS index -> position (-1 for an
-// edge longer than t), position -> vertices (a << 16 | b, a > b) and length.
+// dimension 1 (rips_reduce_bm.hpp): pos[a * n + b] = pos[b * n + a] = the
+// position of the edge {a, b} (-1 for an edge longer than t; a row is
+// contiguous in its second vertex, so the positions of the edges {a, w} of
+// all w load together), position -> vertices (a << 16 | b, a > b) and length.
 // E == 0: not in use.
 struct EdgeOrder {
     const int *pos;
@@ -314,6 +316,7 @@ struct EdgeOrder {
                     // cofacet (the edge and {a, b, c} are a zero apparent pair), or -1
     int E;
     int W; // 32-bit words of one edge's bitmap: ceil(n / 32)
+    int n; // points: the row length of pos
 };
 constexpr u32 kRunTie = 0x80000000u;
 
@@ -369,7 +372,7 @@ struct ReduceJob {
     PivotHash prev;
     // direct-mapped working column (dimension 1, Z/2, every shortcut on):
     // bm_bits == null means the general working column is used
-    EdgeOrder eo = {nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0};
+    EdgeOrder eo = {nullptr, nullptr, nullptr, nullptr, nullptr, 0, 0, 0};
     u32 *bm_bits = nullptr; // eo.E * eo.W words per workgroup, all zero between columns
     int64_t bm_stride = 0;  // words per workgroup (workgroup blockIdx.x uses its own)
 };

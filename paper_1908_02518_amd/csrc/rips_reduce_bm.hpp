@@ -58,8 +58,8 @@ __device__ __forceinline__ int64_t bm_edge_index(int a, int b) {
 // longer than t (no position).
 __device__ __forceinline__ int64_t bm_coord(const EdgeOrder &eo, int u, int v, int puv, int w) {
     if (w == u || w == v) return -1;
-    const int puw = gp(eo.pos)[bm_edge_index(u, w)];
-    const int pvw = gp(eo.pos)[bm_edge_index(v, w)];
+    const int puw = gp(eo.pos)[(int64_t)u * eo.n + w];
+    const int pvw = gp(eo.pos)[(int64_t)v * eo.n + w];
     if (puw < 0 || pvw < 0) return -1;
     int po = puv, cc = w;
     if (puw > po) {
@@ -282,7 +282,7 @@ __device__ __forceinline__ void bm_add_items(const ReduceJob<Dist> &J, RedShared
     if (nit == 1 && c.nb.off == nullptr && c.n <= kRounds * BT) {
         RED_TW0(t_fl, tid == 0);
         const int u = S.it_v[0][0], v = S.it_v[0][1];
-        const int puv = gp(eo.pos)[bm_edge_index(u, v)];
+        const int puv = gp(eo.pos)[(int64_t)u * eo.n + v];
         const int rounds = (c.n + BT - 1) / BT;
         int64_t cd[kRounds];
 #pragma unroll
@@ -335,7 +335,7 @@ __device__ __forceinline__ void bm_add_items(const ReduceJob<Dist> &J, RedShared
         const int q = fl - S.it_off[lo];
         const int w = S.it_u[lo] < 0 ? q : c.nb.idx[S.it_start[lo] + q];
         const int u = S.it_v[lo][0], v = S.it_v[lo][1];
-        const int64_t cd = bm_coord(eo, u, v, gp(eo.pos)[bm_edge_index(u, v)], w);
+        const int64_t cd = bm_coord(eo, u, v, gp(eo.pos)[(int64_t)u * eo.n + v], w);
         if (cd >= 0) {
             bm_flip(bits, L, eo.W, cd);
             ++added;
