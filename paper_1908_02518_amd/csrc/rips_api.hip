@@ -969,10 +969,27 @@ rips_status run_single(DevCtx &C, const float *d_in, int n, int m, int max_dim, 
             launch_filter(filter_group_size_for(P, k), P.ctx, k, cand, ncand, W.bits, ph_prev, P.scal, surv,
                           app, (apparent ? kShortApparent : 0) | (C.shortcuts & kShortClearing), st);
         }
-        if (apparent) {
+        // the coboundary lists serve the general working column's apparent
+        // runs; a dimension that the direct-mapped column will reduce (the
+        // same conditions as below, with every workgroup counted) has no use
+        // for them
+        const int64_t bm_w = (n + 31) / 32;
+        const int64_t bm_groups = C.reduce_groups > 0 ? C.reduce_groups : std::max(1, C.num_cus);
+        const size_t bm_budget = C.lds_per_block > 16384 ? (size_t)C.lds_per_block - 12288 : 0;
+        const bool bm_ahead = k == 1 && p == 2 && !C.arena && !P.sparse &&
+                              C.working_column == RIPS_WORKING_COLUMN_AUTO &&
+                              C.shortcuts == (kShortApparent | kShortEmergent | kShortClearing) &&
+                              C.rstore == kRStoreAuto && bm_w <= 60 && P.nedges > 0 && P.nedges <= (1 << 18) &&
+                              bm_groups * P.nedges * bm_w * 4 <= (8ll << 30) &&
+                              reduce_lds_bytes(256) + bm_lds_bytes(P.nedges) <= bm_budget;
+        if (apparent && !bm_ahead) {
             PROF(P_COB1 + k - 1);
             hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, st, &P.scal->cob, 0ull);
             launch_cob_lists(P.ctx, k, app, ckey_w, cdia_w, &P.scal->cob, cobcap, st);
+        } else if (apparent) {
+            app.cob = nullptr;
+            app.ckey = nullptr;
+            app.cdia = nullptr;
         }
         if ((rs = read_scalars(C, P.scal, st))) return rs;
         if ((int64_t)C.host_scal->cob > C.hint_cob)
