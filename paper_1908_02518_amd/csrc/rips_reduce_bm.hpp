@@ -23,14 +23,14 @@
 // so the triangle is in a zero apparent pair exactly when it is the owner's
 // zero apparent cofacet. The third vertex of that cofacet is kept per
 // position (EdgeOrder::app) and read in the same round trip as the bitmap
-// words, so such a pivot needs no table lookup; in runs of equal lengths the
-// pair table is asked as before.
+// words, so such a pivot needs no table lookup; a pivot in a run of equal
+// lengths, or not paired so, is looked up in the pair and pivot tables.
 //
 // Compared with the general working column (delta, sorted base, far list)
 // there is no merge, no sorting and no spill: an addition costs one XOR per
 // entry, and the column's size does not matter. The memory is
-// (edges <= t) x ceil(n / 32) words per workgroup, so the engine is used when
-// that fits; the rest of the reduction (the pivot and apparent-pair tables,
+// (edges <= t) x ceil(n / 32) words per workgroup and an n x n table of edge
+// positions, so the engine is used when that fits; the rest of the reduction (the pivot and apparent-pair tables,
 // the addition log, V_j, the commit of the spread-out reduction) is the
 // general one's.
 #pragma once
