@@ -135,6 +135,7 @@ __device__ __forceinline__ int bm_next(const BmLds &L, int f) {
 // the pivot may still be added (never before it).
 constexpr int kBmSlots = 6;
 constexpr u32 kNoRho = 0xffffffffu;
+constexpr int kBmStoreAdds = 256; // longest column whose R_j is stored (V_j always is)
 
 // The highest set bit of a position's bitmap (lanes base .. base+W-1 hold
 // its words, nz their nonzero mask): the third vertex of its oldest entry.
@@ -642,7 +643,12 @@ __device__ __forceinline__ int reduce_one_bm(const ReduceJob<Dist> &J, const Lds
         RED_T0(t_st);
         int64_t roff = 0;
         int rn = -1;
-        const int64_t live = bm_count<BT>(bits, L, W, S.bmf, S);
+        // a column of more than kBmStoreAdds additions stores V_j only: its
+        // summary marks nearly every position after the front (an entry
+        // stays marked after it cancels), so counting and storing R_j would
+        // scan the whole bitmap at the end of the longest chain of additions,
+        // and a later addition of it recomputes it from V_j
+        const int64_t live = nadd > kBmStoreAdds ? INT64_MAX : bm_count<BT>(bits, L, W, S.bmf, S);
         if ((float)live <= 2.0f * (float)S.vest * J.cand_avg) {
             rn = bm_store<BT>(bits, L, W, S.bmf, J.V, J.vcount, S, &roff);
             if (rn < 0) {
